@@ -1,0 +1,217 @@
+"""DBL oracle — TEST INFRASTRUCTURE ONLY.
+
+A plain CPU implementation of the DBL reachability index (arXiv 2101.09441), written from the
+paper's definitions and Algorithms 1-3 in ``dbl_oracle.c`` and wrapped here with ctypes. Only the
+test suite, the smoke check and the benchmark's CPU-baseline leg may use it; the GPU library never
+imports or links it, and the two share no code.
+
+Class codes of ``query_dbl`` (``out = answer | class << 1``):
+0 self, 1 DL hit (Lemma 1), 2 BL miss (Lemma 2), 3 Theorem 1, 4 Theorem 2, 5 BFS true,
+6 BFS false.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "dbl_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+CLASS_SELF, CLASS_R1, CLASS_R2, CLASS_R3, CLASS_R4, CLASS_BFS_TRUE, CLASS_BFS_FALSE = range(7)
+CLASS_NAMES = ["self", "R1_dl_hit", "R2_bl_miss", "R3_thm1", "R4_thm2", "bfs_true", "bfs_false"]
+
+
+def build() -> str:
+    """Compile the oracle with gcc (always recompiles)."""
+    tmp = _LIB + ".tmp"
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-pthread", "-o", tmp,
+                           _SRC])
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        build()
+    lib = ctypes.CDLL(_LIB)
+    P = ctypes.c_void_p
+    u32, u64, i32 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+    lib.orc_new.restype = P
+    lib.orc_new.argtypes = [u32, u64, P, P]
+    lib.orc_free.argtypes = [P]
+    lib.orc_free.restype = None
+    lib.orc_build.argtypes = [P, u32, u32, P, P, P, u32]
+    lib.orc_build.restype = i32
+    lib.orc_select_landmarks.argtypes = [P, u32, P]
+    lib.orc_select_landmarks.restype = u32
+    lib.orc_hash.argtypes = [u32, u32]
+    lib.orc_hash.restype = u32
+    for name in ("orc_query_dbl", "orc_query_truth"):
+        f = getattr(lib, name)
+        f.argtypes = [P, u64, P, P, P, u32]
+        f.restype = i32
+    lib.orc_query_label_class.argtypes = [P, u64, P, P, P]
+    lib.orc_query_label_class.restype = i32
+    lib.orc_insert.argtypes = [P, u64, P, P]
+    lib.orc_insert.restype = i32
+    lib.orc_read_labels.argtypes = [P, P, P, P, P]
+    lib.orc_read_labels.restype = None
+    lib.orc_landmarks.argtypes = [P, P]
+    lib.orc_landmarks.restype = u32
+    lib.orc_leaves.argtypes = [P, P, P, P]
+    lib.orc_leaves.restype = None
+    lib.orc_num_edges.argtypes = [P]
+    lib.orc_num_edges.restype = u64
+    lib.orc_closure.argtypes = [P, P]
+    lib.orc_closure.restype = i32
+    lib.orc_in_degree.argtypes = [P, u32]
+    lib.orc_in_degree.restype = u32
+    lib.orc_out_degree.argtypes = [P, u32]
+    lib.orc_out_degree.restype = u32
+    _lib = lib
+    return lib
+
+
+def _u32(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.uint32)
+
+
+def fib_hash(x: int, kp: int) -> int:
+    """The oracle's leaf hash h(x) (Fibonacci hashing into kp buckets)."""
+    return int(_load().orc_hash(x, kp))
+
+
+class OracleIndex:
+    """Graph + DBL labels held by the oracle."""
+
+    def __init__(self, n: int, src, dst):
+        lib = _load()
+        src, dst = _u32(src), _u32(dst)
+        if len(src) != len(dst):
+            raise ValueError("src/dst length mismatch")
+        self.n = int(n)
+        self._keep = (src, dst)
+        self._h = lib.orc_new(self.n, len(src), src.ctypes.data, dst.ctypes.data)
+        if not self._h:
+            raise ValueError("orc_new failed (vertex id out of range or out of memory)")
+        self.k = 0
+        self.kp = 0
+
+    def close(self):
+        if self._h:
+            _load().orc_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- construction (Algorithm 1)
+    def build(self, k: int = 64, kp: int = 64, landmarks=None, bucket_table=None,
+              leaf_flags=None, threads: int = 1) -> "OracleIndex":
+        """Algorithm 1. ``leaf_flags``: optional uint8[n], bit 0 = in S_in, bit 1 = in S_out."""
+        lib = _load()
+        lm = None if landmarks is None else _u32(landmarks)
+        if lm is not None and len(lm) < min(k, self.n):
+            raise ValueError("need k landmarks")
+        bt = None if bucket_table is None else np.ascontiguousarray(bucket_table, dtype=np.uint8)
+        lf = None if leaf_flags is None else np.ascontiguousarray(leaf_flags, dtype=np.uint8)
+        rc = lib.orc_build(self._h, k, kp, None if lm is None else lm.ctypes.data,
+                           None if bt is None else bt.ctypes.data,
+                           None if lf is None else lf.ctypes.data, threads)
+        if rc:
+            raise ValueError("orc_build failed")
+        self.k = min(k, self.n)
+        self.kp = kp
+        return self
+
+    def select_landmarks(self, k: int) -> np.ndarray:
+        out = np.zeros(max(k, 1), dtype=np.uint32)
+        got = _load().orc_select_landmarks(self._h, k, out.ctypes.data)
+        return out[:got].copy()
+
+    def landmarks(self) -> np.ndarray:
+        out = np.zeros(64, dtype=np.uint32)
+        got = _load().orc_landmarks(self._h, out.ctypes.data)
+        return out[:got].copy()
+
+    def leaves(self):
+        a = np.zeros(self.n, np.uint8)
+        b = np.zeros(self.n, np.uint8)
+        c = np.zeros(self.n, np.uint8)
+        _load().orc_leaves(self._h, a.ctypes.data, b.ctypes.data, c.ctypes.data)
+        return a.astype(bool), b.astype(bool), c
+
+    def labels(self):
+        """(DL_in, DL_out, BL_in, BL_out), each uint64[n]."""
+        arrs = [np.zeros(self.n, dtype=np.uint64) for _ in range(4)]
+        _load().orc_read_labels(self._h, *[a.ctypes.data for a in arrs])
+        return tuple(arrs)
+
+    # -- queries (Algorithm 2)
+    def _q(self, fn, u, v, threads):
+        u, v = _u32(u), _u32(v)
+        out = np.zeros(max(len(u), 1), dtype=np.uint8)
+        rc = fn(self._h, len(u), u.ctypes.data, v.ctypes.data, out.ctypes.data, threads)
+        if rc:
+            raise ValueError("query failed (vertex id out of range?)")
+        return out[:len(u)].copy()
+
+    def query_dbl(self, u, v, threads: int = 1) -> np.ndarray:
+        """Algorithm 2: answer | class << 1 per pair."""
+        return self._q(_load().orc_query_dbl, u, v, threads)
+
+    def query_truth(self, u, v, threads: int = 1) -> np.ndarray:
+        """Plain BFS reachability (no labels): 1 if u reaches v."""
+        return self._q(_load().orc_query_truth, u, v, threads)
+
+    def label_class(self, u, v) -> np.ndarray:
+        u, v = _u32(u), _u32(v)
+        out = np.zeros(max(len(u), 1), dtype=np.uint8)
+        rc = _load().orc_query_label_class(self._h, len(u), u.ctypes.data, v.ctypes.data,
+                                           out.ctypes.data)
+        if rc:
+            raise ValueError("label_class failed")
+        return out[:len(u)].copy()
+
+    # -- insertion (Algorithm 3)
+    def insert(self, src, dst) -> "OracleIndex":
+        src, dst = _u32(src), _u32(dst)
+        rc = _load().orc_insert(self._h, len(src), src.ctypes.data, dst.ctypes.data)
+        if rc:
+            raise ValueError("orc_insert failed (vertex id out of range?)")
+        return self
+
+    def num_edges(self) -> int:
+        return int(_load().orc_num_edges(self._h))
+
+    def degrees(self):
+        lib = _load()
+        indeg = np.array([lib.orc_in_degree(self._h, x) for x in range(self.n)], dtype=np.uint32)
+        outdeg = np.array([lib.orc_out_degree(self._h, x) for x in range(self.n)], dtype=np.uint32)
+        return indeg, outdeg
+
+    def closure(self) -> np.ndarray:
+        """Boolean n x n reachability matrix by bitset Warshall (small n only)."""
+        if self.n > 4096:
+            raise ValueError("closure is for small graphs")
+        words = (self.n + 63) // 64
+        rows = np.zeros(self.n * words, dtype=np.uint64)
+        _load().orc_closure(self._h, rows.ctypes.data)
+        bits = np.unpackbits(rows.view(np.uint8).reshape(self.n, words * 8), axis=1,
+                             bitorder="little")
+        return bits[:, :self.n].astype(bool)
+
+
+def build_index(n, src, dst, **kw) -> OracleIndex:
+    return OracleIndex(n, src, dst).build(**kw)

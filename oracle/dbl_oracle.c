@@ -1,0 +1,629 @@
+/*
+ * DBL oracle: TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, sequential, deliberately unoptimised CPU implementation of the DBL reachability
+ * index (Lyu, Li, He, Gong, "DBL: Efficient Reachability Queries on Dynamic Graphs",
+ * arXiv 2101.09441). It exists to check the GPU library against, and only the test suite, the
+ * smoke check and the benchmark's CPU-baseline leg may load it. It shares no code, header,
+ * table or helper with the GPU library.
+ *
+ * What it computes (section numbers are the paper's):
+ *   - Graph model, Section 2 / Table 1: G and its reverse G'; Des(u) and Anc(u) include u.
+ *   - DL label, Definition 1: DL_in(v) = landmarks that reach v, DL_out(v) = landmarks v reaches.
+ *     Landmarks: top-k vertices by M(u) = |Pre(u)| * |Suc(u)| (Section 3.1).
+ *   - BL label, Definition 2: BL_in(v) = hashed zero-in-degree vertices reaching v, BL_out(v) =
+ *     hashed zero-out-degree vertices reached by v; leaves exclude landmarks (Section 1); a hash h
+ *     maps each leaf to one of k' bits (Section 3.1, the paragraph on hash sets).
+ *   - Construction, Algorithm 1: one BFS per landmark (forward for DL_in, on G' for DL_out); BL
+ *     replaces the landmark by all leaves hashed to bucket i.
+ *   - Query, Algorithm 2 with Theorems 1 and 2: label rules, then a pruned BFS.
+ *   - Insertion, Algorithm 3 and Section 4: pruned BFS from v over Suc adding DL_in(u); the
+ *     symmetric DL_out update over Pre from u adding DL_out(v); BL likewise.
+ *
+ * Readings where the paper is silent or its listings are incomplete (each one is listed in the
+ * design notes of the repository):
+ *   R1  Algorithm 1 keeps no visited set and does not label the landmark itself. Here each BFS
+ *       keeps a visited set and the source receives its own bit (Des/Anc include the vertex;
+ *       the Figure 1 labels give v8 its own bit although v8 is on no cycle).
+ *   R2  Algorithm 3 starts from Suc(v) and never updates v. Here v is seeded first: if DL_in(u) is
+ *       not contained in DL_in(v), DL_in(v) gains it and v is enqueued (the worked example of
+ *       Section 4 copies DL_in(v9) into DL_in(v2)).
+ *   R3  Algorithm 2's BFS keeps a visited set (marked when a vertex is enqueued).
+ *   R4  q(u,u) is true (Des(u) includes u) and is decided before the label rules, class SELF.
+ *   R5  Landmark order: M descending, then vertex id ascending; M is computed in 64 bits; exactly
+ *       min(k, n) landmarks are taken; bit i of a DL label stands for the i-th landmark.
+ *   R6  The leaf sets and h are fixed when the index is built; later insertions never add or
+ *       remove BL sources.
+ *   R7  Leaves are the zero-in-degree (S_in) / zero-out-degree (S_out) vertices that are not
+ *       landmarks; an isolated vertex is in both. Self-loops and duplicate edges are dropped when
+ *       the graph is ingested, so degrees count distinct neighbours other than the vertex itself.
+ *   R8  h(x) = (x * 0x9E3779B97F4A7C15 mod 2^64) >> (64 - log2 k') (Fibonacci hashing), unless
+ *       the caller supplies a bucket table (the worked example of the paper gives one).
+ *   R9  Algorithm 3's skip test (Lemma 1: u already reaches v) skips all four label updates.
+ *   R10 Inserted self-loops are no-ops; inserted duplicates change no label.
+ */
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_NONE 0xFFFFFFFFu
+
+enum {
+  ORC_CLASS_SELF = 0,
+  ORC_CLASS_R1_DL_HIT = 1,   /* Lemma 1 */
+  ORC_CLASS_R2_BL_MISS = 2,  /* Lemma 2 */
+  ORC_CLASS_R3_THM1 = 3,     /* Theorem 1 */
+  ORC_CLASS_R4_THM2 = 4,     /* Theorem 2 */
+  ORC_CLASS_BFS_TRUE = 5,
+  ORC_CLASS_BFS_FALSE = 6
+};
+
+/* growable per-vertex neighbour list */
+typedef struct {
+  uint32_t *v;
+  uint32_t len, cap;
+} orc_list;
+
+typedef struct {
+  uint32_t n;
+  orc_list *suc; /* Suc(x) */
+  orc_list *pre; /* Pre(x) */
+  uint32_t k, kp;
+  uint32_t landmark[64];
+  uint8_t *in_leaf, *out_leaf; /* membership in S_in / S_out, fixed at build */
+  uint8_t *bucket;             /* h(x) for every x */
+  uint64_t *dl_in, *dl_out, *bl_in, *bl_out;
+} orc_index;
+
+static int list_push(orc_list *l, uint32_t x) {
+  if (l->len == l->cap) {
+    uint32_t nc = l->cap ? 2 * l->cap : 4;
+    uint32_t *nv = (uint32_t *)realloc(l->v, sizeof(uint32_t) * nc);
+    if (!nv) return -1;
+    l->v = nv;
+    l->cap = nc;
+  }
+  l->v[l->len++] = x;
+  return 0;
+}
+
+static int list_has(const orc_list *l, uint32_t x) {
+  for (uint32_t i = 0; i < l->len; i++)
+    if (l->v[i] == x) return 1;
+  return 0;
+}
+
+static int cmp_u32(const void *a, const void *b) {
+  uint32_t x = *(const uint32_t *)a, y = *(const uint32_t *)b;
+  return (x > y) - (x < y);
+}
+
+/* sort and drop repeated neighbours */
+static void list_unique(orc_list *l) {
+  if (l->len < 2) return;
+  qsort(l->v, l->len, sizeof(uint32_t), cmp_u32);
+  uint32_t w = 1;
+  for (uint32_t i = 1; i < l->len; i++)
+    if (l->v[i] != l->v[w - 1]) l->v[w++] = l->v[i];
+  l->len = w;
+}
+
+void orc_free(orc_index *ix) {
+  if (!ix) return;
+  if (ix->suc)
+    for (uint32_t x = 0; x < ix->n; x++) free(ix->suc[x].v);
+  if (ix->pre)
+    for (uint32_t x = 0; x < ix->n; x++) free(ix->pre[x].v);
+  free(ix->suc); free(ix->pre);
+  free(ix->in_leaf); free(ix->out_leaf); free(ix->bucket);
+  free(ix->dl_in); free(ix->dl_out); free(ix->bl_in); free(ix->bl_out);
+  free(ix);
+}
+
+/* Graph model: ingest edges (self-loops and duplicates dropped). */
+orc_index *orc_new(uint32_t n, uint64_t m, const uint32_t *src, const uint32_t *dst) {
+  orc_index *ix = (orc_index *)calloc(1, sizeof(orc_index));
+  if (!ix) return NULL;
+  ix->n = n;
+  size_t nn = n ? n : 1;
+  ix->suc = (orc_list *)calloc(nn, sizeof(orc_list));
+  ix->pre = (orc_list *)calloc(nn, sizeof(orc_list));
+  ix->in_leaf = (uint8_t *)calloc(nn, 1);
+  ix->out_leaf = (uint8_t *)calloc(nn, 1);
+  ix->bucket = (uint8_t *)calloc(nn, 1);
+  ix->dl_in = (uint64_t *)calloc(nn, 8);
+  ix->dl_out = (uint64_t *)calloc(nn, 8);
+  ix->bl_in = (uint64_t *)calloc(nn, 8);
+  ix->bl_out = (uint64_t *)calloc(nn, 8);
+  if (!ix->suc || !ix->pre || !ix->in_leaf || !ix->out_leaf || !ix->bucket || !ix->dl_in ||
+      !ix->dl_out || !ix->bl_in || !ix->bl_out) {
+    orc_free(ix);
+    return NULL;
+  }
+  for (uint64_t e = 0; e < m; e++) {
+    uint32_t a = src[e], b = dst[e];
+    if (a >= n || b >= n) { orc_free(ix); return NULL; }
+    if (a == b) continue;
+    if (list_push(&ix->suc[a], b) || list_push(&ix->pre[b], a)) { orc_free(ix); return NULL; }
+  }
+  for (uint32_t x = 0; x < n; x++) {
+    list_unique(&ix->suc[x]);
+    list_unique(&ix->pre[x]);
+  }
+  return ix;
+}
+
+uint32_t orc_out_degree(const orc_index *ix, uint32_t x) { return ix->suc[x].len; }
+uint32_t orc_in_degree(const orc_index *ix, uint32_t x) { return ix->pre[x].len; }
+
+/* Landmark selection (Section 3.1): top-k by M(u) = |Pre(u)| * |Suc(u)|; ties by smaller id. */
+static int ranks_before(const orc_index *ix, uint32_t a, uint32_t b) {
+  uint64_t ma = (uint64_t)ix->pre[a].len * ix->suc[a].len;
+  uint64_t mb = (uint64_t)ix->pre[b].len * ix->suc[b].len;
+  if (ma != mb) return ma > mb;
+  return a < b;
+}
+
+uint32_t orc_select_landmarks(const orc_index *ix, uint32_t k, uint32_t *out) {
+  /* keep the best k seen so far in `out`, ordered best first (insertion into a sorted list) */
+  uint32_t have = 0;
+  for (uint32_t x = 0; x < ix->n; x++) {
+    if (have < k) {
+      uint32_t p = have++;
+      while (p > 0 && ranks_before(ix, x, out[p - 1])) { out[p] = out[p - 1]; p--; }
+      out[p] = x;
+    } else if (k > 0 && ranks_before(ix, x, out[k - 1])) {
+      uint32_t p = k - 1;
+      while (p > 0 && ranks_before(ix, x, out[p - 1])) { out[p] = out[p - 1]; p--; }
+      out[p] = x;
+    }
+  }
+  return have;
+}
+
+/* Fibonacci hashing of a vertex id into [0, kp), kp a power of two in [1, 64]. */
+uint32_t orc_hash(uint32_t x, uint32_t kp) {
+  if (kp <= 1) return 0;
+  uint32_t bits = 0;
+  while ((1u << bits) < kp) bits++;
+  return (uint32_t)(((uint64_t)x * 0x9E3779B97F4A7C15ULL) >> (64 - bits));
+}
+
+/* ---------------------------------------------------------------- construction (Algorithm 1) */
+
+typedef struct {
+  uint32_t *queue;
+  uint32_t *seen; /* seen[x] == stamp means visited in the current BFS */
+  uint32_t stamp;
+} orc_bfs_ws;
+
+static int ws_init(orc_bfs_ws *w, uint32_t n) {
+  size_t nn = n ? n : 1;
+  w->queue = (uint32_t *)malloc(sizeof(uint32_t) * nn);
+  w->seen = (uint32_t *)calloc(nn, sizeof(uint32_t));
+  w->stamp = 0;
+  return (w->queue && w->seen) ? 0 : -1;
+}
+
+static void ws_free(orc_bfs_ws *w) { free(w->queue); free(w->seen); }
+
+static void ws_next_stamp(orc_bfs_ws *w, uint32_t n) {
+  if (++w->stamp == 0) {
+    memset(w->seen, 0, sizeof(uint32_t) * (n ? n : 1));
+    w->stamp = 1;
+  }
+}
+
+/*
+ * One BFS of Algorithm 1 from a set of sources, over Suc (forward) or Pre (backward), setting
+ * `bit` in `label` of every vertex reached, sources included (reading R1).
+ */
+static void bfs_set_bit(const orc_index *ix, orc_bfs_ws *w, const uint32_t *sources, uint32_t ns,
+                        int forward, uint64_t *label, uint32_t bit, int atomic) {
+  const orc_list *adj = forward ? ix->suc : ix->pre;
+  const uint64_t mask = 1ULL << bit;
+  ws_next_stamp(w, ix->n);
+  uint64_t head = 0, tail = 0;
+  for (uint32_t i = 0; i < ns; i++) {
+    uint32_t s = sources[i];
+    if (w->seen[s] == w->stamp) continue;
+    w->seen[s] = w->stamp;
+    w->queue[tail++] = s;
+  }
+  while (head < tail) {
+    uint32_t p = w->queue[head++];
+    if (atomic) __atomic_fetch_or(&label[p], mask, __ATOMIC_RELAXED);
+    else label[p] |= mask;
+    for (uint32_t j = 0; j < adj[p].len; j++) {
+      uint32_t x = adj[p].v[j];
+      if (w->seen[x] == w->stamp) continue;
+      w->seen[x] = w->stamp;
+      w->queue[tail++] = x;
+    }
+  }
+}
+
+/* One unit of construction work: a (label, bit) pair and its source set. */
+typedef struct {
+  int forward;
+  uint64_t *label;
+  uint32_t bit;
+  uint32_t *sources;
+  uint32_t ns;
+} orc_task;
+
+typedef struct {
+  const orc_index *ix;
+  orc_task *tasks;
+  uint32_t ntasks;
+  uint32_t next; /* shared task counter */
+  int atomic;
+  int failed;
+} orc_pool;
+
+static void *pool_worker(void *arg) {
+  orc_pool *p = (orc_pool *)arg;
+  orc_bfs_ws w;
+  if (ws_init(&w, p->ix->n)) {
+    __atomic_store_n(&p->failed, 1, __ATOMIC_RELAXED);
+    ws_free(&w);
+    return NULL;
+  }
+  for (;;) {
+    uint32_t t = __atomic_fetch_add(&p->next, 1, __ATOMIC_RELAXED);
+    if (t >= p->ntasks) break;
+    orc_task *tk = &p->tasks[t];
+    bfs_set_bit(p->ix, &w, tk->sources, tk->ns, tk->forward, tk->label, tk->bit, p->atomic);
+  }
+  ws_free(&w);
+  return NULL;
+}
+
+/*
+ * Build all four labels. landmarks: explicit ordered list (NULL = select top-k by M).
+ * bucket_table: explicit h(x) for every x (NULL = Fibonacci hashing). leaf_flags: explicit leaf
+ * sets, bit 0 = x in S_in, bit 1 = x in S_out (NULL = from the degrees, reading R7); it lets a
+ * rebuild use the leaf sets fixed by an earlier build (reading R6). k in [0,64], kp a power of
+ * two in [1,64]. threads <= 1 runs sequentially. Returns 0 on success.
+ */
+int orc_build(orc_index *ix, uint32_t k, uint32_t kp, const uint32_t *landmarks,
+              const uint8_t *bucket_table, const uint8_t *leaf_flags, uint32_t threads) {
+  if (k > 64 || kp == 0 || kp > 64 || (kp & (kp - 1))) return -1;
+  uint32_t n = ix->n;
+  if (k > n) k = n;
+  ix->k = k;
+  ix->kp = kp;
+  if (landmarks) {
+    for (uint32_t i = 0; i < k; i++) {
+      if (landmarks[i] >= n) return -1;
+      ix->landmark[i] = landmarks[i];
+    }
+  } else {
+    orc_select_landmarks(ix, k, ix->landmark);
+  }
+  uint8_t *is_landmark = (uint8_t *)calloc(n ? n : 1, 1);
+  if (!is_landmark) return -1;
+  for (uint32_t i = 0; i < k; i++) is_landmark[ix->landmark[i]] = 1;
+  for (uint32_t x = 0; x < n; x++) {
+    if (leaf_flags) {
+      ix->in_leaf[x] = leaf_flags[x] & 1;
+      ix->out_leaf[x] = (leaf_flags[x] >> 1) & 1;
+    } else {
+      ix->in_leaf[x] = !is_landmark[x] && ix->pre[x].len == 0;
+      ix->out_leaf[x] = !is_landmark[x] && ix->suc[x].len == 0;
+    }
+    ix->bucket[x] = (uint8_t)(bucket_table ? bucket_table[x] : orc_hash(x, kp));
+    if (ix->bucket[x] >= kp) { free(is_landmark); return -1; }
+  }
+  free(is_landmark);
+  memset(ix->dl_in, 0, 8 * (size_t)(n ? n : 1));
+  memset(ix->dl_out, 0, 8 * (size_t)(n ? n : 1));
+  memset(ix->bl_in, 0, 8 * (size_t)(n ? n : 1));
+  memset(ix->bl_out, 0, 8 * (size_t)(n ? n : 1));
+
+  /* task list: DL forward/backward per landmark, BL forward/backward per bucket */
+  uint32_t ntasks = 2 * k + 2 * kp;
+  orc_task *tasks = (orc_task *)calloc(ntasks ? ntasks : 1, sizeof(orc_task));
+  uint32_t *src_in = (uint32_t *)malloc(sizeof(uint32_t) * (n ? n : 1));
+  uint32_t *src_out = (uint32_t *)malloc(sizeof(uint32_t) * (n ? n : 1));
+  uint32_t *cnt_in = (uint32_t *)calloc(kp + 1, sizeof(uint32_t));
+  uint32_t *cnt_out = (uint32_t *)calloc(kp + 1, sizeof(uint32_t));
+  if (!tasks || !src_in || !src_out || !cnt_in || !cnt_out) {
+    free(tasks); free(src_in); free(src_out); free(cnt_in); free(cnt_out);
+    return -1;
+  }
+  /* group leaves by bucket (counting sort) so each bucket's sources are contiguous */
+  for (uint32_t x = 0; x < n; x++) {
+    if (ix->in_leaf[x]) cnt_in[ix->bucket[x] + 1]++;
+    if (ix->out_leaf[x]) cnt_out[ix->bucket[x] + 1]++;
+  }
+  for (uint32_t j = 0; j < kp; j++) { cnt_in[j + 1] += cnt_in[j]; cnt_out[j + 1] += cnt_out[j]; }
+  {
+    uint32_t *fi = (uint32_t *)malloc(sizeof(uint32_t) * (kp + 1));
+    uint32_t *fo = (uint32_t *)malloc(sizeof(uint32_t) * (kp + 1));
+    if (!fi || !fo) {
+      free(fi); free(fo); free(tasks); free(src_in); free(src_out); free(cnt_in); free(cnt_out);
+      return -1;
+    }
+    memcpy(fi, cnt_in, sizeof(uint32_t) * (kp + 1));
+    memcpy(fo, cnt_out, sizeof(uint32_t) * (kp + 1));
+    for (uint32_t x = 0; x < n; x++) {
+      if (ix->in_leaf[x]) src_in[fi[ix->bucket[x]]++] = x;
+      if (ix->out_leaf[x]) src_out[fo[ix->bucket[x]]++] = x;
+    }
+    free(fi); free(fo);
+  }
+  uint32_t t = 0;
+  for (uint32_t i = 0; i < k; i++) {
+    tasks[t++] = (orc_task){1, ix->dl_in, i, &ix->landmark[i], 1};
+    tasks[t++] = (orc_task){0, ix->dl_out, i, &ix->landmark[i], 1};
+  }
+  for (uint32_t j = 0; j < kp; j++) {
+    tasks[t++] = (orc_task){1, ix->bl_in, j, src_in + cnt_in[j], cnt_in[j + 1] - cnt_in[j]};
+    tasks[t++] = (orc_task){0, ix->bl_out, j, src_out + cnt_out[j], cnt_out[j + 1] - cnt_out[j]};
+  }
+  orc_pool pool = {ix, tasks, ntasks, 0, threads > 1, 0};
+  if (threads <= 1) {
+    pool_worker(&pool);
+  } else {
+    pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * threads);
+    uint32_t started = 0;
+    if (th)
+      for (; started < threads; started++)
+        if (pthread_create(&th[started], NULL, pool_worker, &pool)) break;
+    if (started == 0) pool_worker(&pool);
+    for (uint32_t i = 0; i < started; i++) pthread_join(th[i], NULL);
+    free(th);
+  }
+  free(tasks); free(src_in); free(src_out); free(cnt_in); free(cnt_out);
+  return pool.failed ? -1 : 0;
+}
+
+/* ---------------------------------------------------------------- queries (Algorithm 2) */
+
+/* DL_Intersec(x, y) of Algorithm 2: DL_out(x) and DL_in(y) share a landmark. */
+static int dl_intersec(const orc_index *ix, uint32_t x, uint32_t y) {
+  return (ix->dl_out[x] & ix->dl_in[y]) != 0;
+}
+
+/* BL_Contain(x, y) of Algorithm 2: BL_in(x) within BL_in(y) and BL_out(y) within BL_out(x). */
+static int bl_contain(const orc_index *ix, uint32_t x, uint32_t y) {
+  return (ix->bl_in[x] & ~ix->bl_in[y]) == 0 && (ix->bl_out[y] & ~ix->bl_out[x]) == 0;
+}
+
+/* The label-only part of Algorithm 2; returns a class, or -1 if the labels cannot decide. */
+static int label_rules(const orc_index *ix, uint32_t u, uint32_t v) {
+  if (u == v) return ORC_CLASS_SELF;
+  if (dl_intersec(ix, u, v)) return ORC_CLASS_R1_DL_HIT;
+  if (!bl_contain(ix, u, v)) return ORC_CLASS_R2_BL_MISS;
+  if (dl_intersec(ix, v, u)) return ORC_CLASS_R3_THM1;
+  if (dl_intersec(ix, u, u) || dl_intersec(ix, v, v)) return ORC_CLASS_R4_THM2;
+  return -1;
+}
+
+/* Algorithm 2's pruned BFS from u looking for v (reading R3: visited marks on enqueue). */
+static int pruned_bfs(const orc_index *ix, orc_bfs_ws *w, uint32_t u, uint32_t v) {
+  ws_next_stamp(w, ix->n);
+  uint64_t head = 0, tail = 0;
+  w->seen[u] = w->stamp;
+  w->queue[tail++] = u;
+  while (head < tail) {
+    uint32_t p = w->queue[head++];
+    const orc_list *s = &ix->suc[p];
+    for (uint32_t j = 0; j < s->len; j++) {
+      uint32_t x = s->v[j];
+      if (x == v) return 1;
+      if (dl_intersec(ix, u, x)) continue; /* a landmark of u reaches x */
+      if (!bl_contain(ix, x, v)) continue; /* x cannot reach v */
+      if (w->seen[x] == w->stamp) continue;
+      w->seen[x] = w->stamp;
+      w->queue[tail++] = x;
+    }
+  }
+  return 0;
+}
+
+/* Plain BFS reachability with no labels at all (the truth the index must reproduce). */
+static int plain_reach(const orc_index *ix, orc_bfs_ws *w, uint32_t u, uint32_t v) {
+  if (u == v) return 1;
+  ws_next_stamp(w, ix->n);
+  uint64_t head = 0, tail = 0;
+  w->seen[u] = w->stamp;
+  w->queue[tail++] = u;
+  while (head < tail) {
+    uint32_t p = w->queue[head++];
+    const orc_list *s = &ix->suc[p];
+    for (uint32_t j = 0; j < s->len; j++) {
+      uint32_t x = s->v[j];
+      if (x == v) return 1;
+      if (w->seen[x] == w->stamp) continue;
+      w->seen[x] = w->stamp;
+      w->queue[tail++] = x;
+    }
+  }
+  return 0;
+}
+
+typedef struct {
+  const orc_index *ix;
+  const uint32_t *u, *v;
+  uint8_t *out;
+  uint64_t count;
+  uint64_t next;
+  int mode; /* 0 = Algorithm 2 (answer | class << 1), 1 = plain BFS truth (answer only) */
+  int failed;
+} orc_qpool;
+
+#define ORC_QCHUNK 256
+
+static void *query_worker(void *arg) {
+  orc_qpool *p = (orc_qpool *)arg;
+  orc_bfs_ws w;
+  if (ws_init(&w, p->ix->n)) {
+    __atomic_store_n(&p->failed, 1, __ATOMIC_RELAXED);
+    ws_free(&w);
+    return NULL;
+  }
+  for (;;) {
+    uint64_t b = __atomic_fetch_add(&p->next, ORC_QCHUNK, __ATOMIC_RELAXED);
+    if (b >= p->count) break;
+    uint64_t e = b + ORC_QCHUNK < p->count ? b + ORC_QCHUNK : p->count;
+    for (uint64_t i = b; i < e; i++) {
+      uint32_t u = p->u[i], v = p->v[i];
+      if (p->mode == 1) {
+        p->out[i] = (uint8_t)plain_reach(p->ix, &w, u, v);
+        continue;
+      }
+      int c = label_rules(p->ix, u, v);
+      int ans;
+      if (c < 0) {
+        ans = pruned_bfs(p->ix, &w, u, v);
+        c = ans ? ORC_CLASS_BFS_TRUE : ORC_CLASS_BFS_FALSE;
+      } else {
+        ans = (c == ORC_CLASS_SELF || c == ORC_CLASS_R1_DL_HIT);
+      }
+      p->out[i] = (uint8_t)(ans | (c << 1));
+    }
+  }
+  ws_free(&w);
+  return NULL;
+}
+
+static int run_queries(const orc_index *ix, uint64_t count, const uint32_t *u, const uint32_t *v,
+                       uint8_t *out, int mode, uint32_t threads) {
+  for (uint64_t i = 0; i < count; i++)
+    if (u[i] >= ix->n || v[i] >= ix->n) return -1;
+  orc_qpool pool = {ix, u, v, out, count, 0, mode, 0};
+  if (threads <= 1) {
+    query_worker(&pool);
+  } else {
+    pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * threads);
+    uint32_t started = 0;
+    if (th)
+      for (; started < threads; started++)
+        if (pthread_create(&th[started], NULL, query_worker, &pool)) break;
+    if (started == 0) query_worker(&pool);
+    for (uint32_t i = 0; i < started; i++) pthread_join(th[i], NULL);
+    free(th);
+  }
+  return pool.failed ? -1 : 0;
+}
+
+/* Algorithm 2 per pair: out[i] = answer | (class << 1). */
+int orc_query_dbl(const orc_index *ix, uint64_t count, const uint32_t *u, const uint32_t *v,
+                  uint8_t *out, uint32_t threads) {
+  return run_queries(ix, count, u, v, out, 0, threads);
+}
+
+/* Plain BFS reachability per pair: out[i] = 1 if u reaches v (u reaches u). */
+int orc_query_truth(const orc_index *ix, uint64_t count, const uint32_t *u, const uint32_t *v,
+                    uint8_t *out, uint32_t threads) {
+  return run_queries(ix, count, u, v, out, 1, threads);
+}
+
+/* Label-only part of Algorithm 2: out[i] = class of the first deciding rule, or 0xFF. */
+int orc_query_label_class(const orc_index *ix, uint64_t count, const uint32_t *u,
+                          const uint32_t *v, uint8_t *out) {
+  for (uint64_t i = 0; i < count; i++) {
+    if (u[i] >= ix->n || v[i] >= ix->n) return -1;
+    int c = label_rules(ix, u[i], v[i]);
+    out[i] = (uint8_t)(c < 0 ? 0xFF : c);
+  }
+  return 0;
+}
+
+/* ---------------------------------------------------------------- insertion (Algorithm 3) */
+
+/*
+ * Algorithm 3 for one label: add `add` (the inserted edge's endpoint label, read before the
+ * update) to every vertex of Des(start) (forward) or Anc(start) (backward), pruning a vertex as
+ * soon as it already contains `add`. Reading R2: start itself is checked and updated first.
+ */
+static void alg3_propagate(const orc_index *ix, orc_bfs_ws *w, uint64_t *label, uint64_t add,
+                           uint32_t start, int forward) {
+  const orc_list *adj = forward ? ix->suc : ix->pre;
+  if ((add & ~label[start]) == 0) return;
+  label[start] |= add;
+  uint64_t head = 0, tail = 0;
+  w->queue[tail++] = start;
+  while (head < tail) {
+    uint32_t p = w->queue[head++];
+    for (uint32_t j = 0; j < adj[p].len; j++) {
+      uint32_t x = adj[p].v[j];
+      if ((add & ~label[x]) != 0) {
+        label[x] |= add;
+        w->queue[tail++] = x; /* each vertex is enqueued at most once: it now contains `add` */
+      }
+    }
+  }
+}
+
+/* Insert edges one at a time in the given order, each by Algorithm 3 on all four labels. */
+int orc_insert(orc_index *ix, uint64_t count, const uint32_t *src, const uint32_t *dst) {
+  for (uint64_t e = 0; e < count; e++)
+    if (src[e] >= ix->n || dst[e] >= ix->n) return -1;
+  orc_bfs_ws w;
+  if (ws_init(&w, ix->n)) { ws_free(&w); return -1; }
+  for (uint64_t e = 0; e < count; e++) {
+    uint32_t u = src[e], v = dst[e];
+    if (u == v) continue;                 /* reading R10 */
+    if (list_has(&ix->suc[u], v)) continue; /* duplicate: reachability unchanged */
+    if (list_push(&ix->suc[u], v) || list_push(&ix->pre[v], u)) { ws_free(&w); return -1; }
+    if (dl_intersec(ix, u, v)) continue;  /* reading R9: u already reaches v (Lemma 1) */
+    uint64_t dl_in_u = ix->dl_in[u], bl_in_u = ix->bl_in[u];
+    uint64_t dl_out_v = ix->dl_out[v], bl_out_v = ix->bl_out[v];
+    alg3_propagate(ix, &w, ix->dl_in, dl_in_u, v, 1);
+    alg3_propagate(ix, &w, ix->bl_in, bl_in_u, v, 1);
+    alg3_propagate(ix, &w, ix->dl_out, dl_out_v, u, 0);
+    alg3_propagate(ix, &w, ix->bl_out, bl_out_v, u, 0);
+  }
+  ws_free(&w);
+  return 0;
+}
+
+/* ---------------------------------------------------------------- accessors */
+
+void orc_read_labels(const orc_index *ix, uint64_t *dl_in, uint64_t *dl_out, uint64_t *bl_in,
+                     uint64_t *bl_out) {
+  size_t b = 8 * (size_t)ix->n;
+  memcpy(dl_in, ix->dl_in, b);
+  memcpy(dl_out, ix->dl_out, b);
+  memcpy(bl_in, ix->bl_in, b);
+  memcpy(bl_out, ix->bl_out, b);
+}
+
+uint32_t orc_landmarks(const orc_index *ix, uint32_t *out) {
+  memcpy(out, ix->landmark, sizeof(uint32_t) * ix->k);
+  return ix->k;
+}
+
+void orc_leaves(const orc_index *ix, uint8_t *in_leaf, uint8_t *out_leaf, uint8_t *bucket) {
+  memcpy(in_leaf, ix->in_leaf, ix->n);
+  memcpy(out_leaf, ix->out_leaf, ix->n);
+  memcpy(bucket, ix->bucket, ix->n);
+}
+
+uint64_t orc_num_edges(const orc_index *ix) {
+  uint64_t m = 0;
+  for (uint32_t x = 0; x < ix->n; x++) m += ix->suc[x].len;
+  return m;
+}
+
+/* Bitset transitive closure for small n (Warshall): row u holds every v that u reaches. */
+int orc_closure(const orc_index *ix, uint64_t *rows) {
+  uint32_t n = ix->n, words = (n + 63) / 64;
+  memset(rows, 0, 8 * (size_t)n * words);
+  for (uint32_t u = 0; u < n; u++) {
+    rows[(size_t)u * words + u / 64] |= 1ULL << (u % 64);
+    for (uint32_t j = 0; j < ix->suc[u].len; j++) {
+      uint32_t v = ix->suc[u].v[j];
+      rows[(size_t)u * words + v / 64] |= 1ULL << (v % 64);
+    }
+  }
+  for (uint32_t k = 0; k < n; k++)
+    for (uint32_t i = 0; i < n; i++)
+      if (rows[(size_t)i * words + k / 64] >> (k % 64) & 1)
+        for (uint32_t w = 0; w < words; w++) rows[(size_t)i * words + w] |= rows[(size_t)k * words + w];
+  return 0;
+}
