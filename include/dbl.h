@@ -1,0 +1,161 @@
+/*
+ * dbl.h — C ABI of the DBL reachability index on one MI355X (gfx950).
+ *
+ * DBL (Lyu, Li, He, Gong, arXiv 2101.09441) answers reachability queries q(u,v) on a directed
+ * graph that only grows by edge insertion. Every vertex carries four 64-bit labels:
+ *   DL_in(v)  - the landmarks that reach v           (Definition 1)
+ *   DL_out(v) - the landmarks v reaches              (Definition 1)
+ *   BL_in(v)  - hashed zero-in-degree leaves reaching v   (Definition 2, hashed into k' bits)
+ *   BL_out(v) - hashed zero-out-degree leaves v reaches   (Definition 2, hashed into k' bits)
+ * Reachability includes the vertex itself (Table 1: Des(u) and Anc(u) contain u).
+ *
+ * Conventions for every entry point:
+ *   - Array arguments named d_* are DEVICE pointers (for example the data pointer of a torch
+ *     tensor on the same GPU); arguments named h_* or documented as host arrays are host memory.
+ *   - `stream` is a hipStream_t (NULL = the default stream). Work is ordered on that stream; the
+ *     call returns after its own work has finished (each call synchronises the stream once at
+ *     its end to report its status), unless stated otherwise.
+ *   - The caller owns every array it passes; the index owns all device memory it allocates.
+ *   - Vertex ids are uint32 in [0, n). No exception crosses this boundary; every call returns a
+ *     dbl_status. An index is used by one host thread at a time.
+ *   - The index lives on the device that is current when dbl_build is called; later calls make
+ *     that device current themselves.
+ */
+#ifndef DBL_H
+#define DBL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dbl_index dbl_index;
+
+typedef enum {
+  DBL_OK = 0,
+  DBL_ERR_INVALID_ARG = 1,   /* null pointer, bad size, bad option */
+  DBL_ERR_VERTEX_RANGE = 2,  /* some vertex id >= n; nothing was changed */
+  DBL_ERR_OUT_OF_MEMORY = 3, /* a device allocation failed */
+  DBL_ERR_DEVICE = 4         /* a HIP runtime error */
+} dbl_status;
+
+/* Decision class of a query, stored in bits 1-3 of each output byte of dbl_query_batch. */
+typedef enum {
+  DBL_CLASS_SELF = 0,      /* u == v: true (Table 1, Des(u) contains u) */
+  DBL_CLASS_DL_HIT = 1,    /* DL_out(u) & DL_in(v) != 0: true (Lemma 1) */
+  DBL_CLASS_BL_MISS = 2,   /* BL containment fails: false (Lemma 2) */
+  DBL_CLASS_THM1 = 3,      /* DL_out(v) & DL_in(u) != 0: false (Theorem 1) */
+  DBL_CLASS_THM2 = 4,      /* u or v shares an SCC with a landmark: false (Theorem 2) */
+  DBL_CLASS_BFS_TRUE = 5,  /* label-pruned BFS of Algorithm 2 found v */
+  DBL_CLASS_BFS_FALSE = 6  /* label-pruned BFS of Algorithm 2 did not find v */
+} dbl_class;
+
+typedef struct {
+  /* k: number of landmarks, 0..64 (default 64). Landmarks are the top-k vertices by
+     M(u) = |Pre(u)| * |Suc(u)| (Section 3.1), ties broken by smaller id; DL bit i stands for
+     the i-th landmark. Bits >= k stay zero. */
+  uint32_t num_landmarks;
+  /* k': number of BL hash buckets, a power of two in 1..64 (default 64). */
+  uint32_t bl_bits;
+  /* Optional HOST array [num_landmarks]: explicit ordered landmark list (distinct ids < n). */
+  const uint32_t *landmarks;
+  /* Optional HOST array [n]: the leaf hash h(x) for every vertex, each < bl_bits. Default:
+     h(x) = (x * 0x9E3779B97F4A7C15 mod 2^64) >> (64 - log2 k') (Fibonacci hashing). */
+  const uint8_t *leaf_bucket;
+  /* Optional HOST array [n]: explicit leaf sets, bit 0 = x in S_in, bit 1 = x in S_out.
+     Default: S_in / S_out = vertices of zero in- / out-degree that are not landmarks. */
+  const uint8_t *leaf_flags;
+  /* Per-vertex spare adjacency capacity: cap = deg + max(ceil(slack_fraction*deg), slack_min),
+     in both the forward and the reverse CSR. Defaults 0.25 and 4. */
+  float slack_fraction;
+  uint32_t slack_min;
+  /* Concurrent BFS slots (one wavefront each) for queries the labels cannot decide; 0 = auto. */
+  uint32_t bfs_slots;
+  /* Queue entries per BFS slot (0 = auto: min(n, 2^18)). A query whose pruned BFS needs more
+     runs on the whole device instead; the answer is the same. */
+  uint32_t bfs_queue_cap;
+  /* Nonzero: the build edges are known to hold no duplicate (the hash de-duplication pass is
+     skipped). Self-loops are always dropped. */
+  uint32_t edges_unique;
+} dbl_options;
+
+typedef struct {
+  uint64_t num_edges;         /* stored forward adjacency entries (build edges + insertions) */
+  uint64_t build_rounds;      /* propagation rounds of the last build */
+  uint64_t insert_calls;      /* dbl_insert_edges calls that changed the graph */
+  uint64_t insert_rounds;     /* propagation rounds over all insertion calls */
+  uint64_t vertices_expanded; /* frontier entries expanded (build + insertions) */
+  uint64_t edges_relaxed;     /* adjacency entries scanned by propagation */
+  uint64_t csr_regrows;       /* times the CSR was rebuilt because a row ran out of slack */
+  uint64_t queries;           /* pairs answered */
+  uint64_t query_class[7];    /* pairs per dbl_class */
+  uint64_t bfs_vertices;      /* vertices dequeued by query BFS */
+  uint64_t bfs_edges;         /* adjacency entries scanned by query BFS */
+  uint64_t bfs_heavy;         /* BFS that outgrew a slot and ran on the whole device */
+} dbl_stats;
+
+/* Fill *opt with the defaults listed above. */
+void dbl_default_options(dbl_options *opt);
+
+/*
+ * Build the index for G = (V = [0,n), E = {(d_src[i], d_dst[i])}) (Algorithm 1 and the
+ * construction paragraph of Section 3.1).
+ *   n: vertex count, 1 <= n < 2^31.  m: edge count (0 allowed).
+ *   d_src, d_dst: device arrays [m]. Self-loops are dropped; duplicate edges are dropped.
+ *   opt: NULL = defaults.  *out receives the new index (NULL on error).
+ * Errors: INVALID_ARG (bad options or sizes), VERTEX_RANGE (an id >= n), OUT_OF_MEMORY,
+ * DEVICE. On error no index is returned and nothing is leaked.
+ */
+dbl_status dbl_build(uint32_t n, uint64_t m, const uint32_t *d_src, const uint32_t *d_dst,
+                     const dbl_options *opt, void *stream, dbl_index **out);
+
+/*
+ * Insert edges (d_src[i], d_dst[i]), i < count, and bring all four labels to the values they
+ * have on the grown graph (Algorithm 3 and Section 4, for DL_in / DL_out / BL_in / BL_out).
+ * The landmarks, the leaf sets and h stay those fixed at build time. A batch is a set: the
+ * result equals inserting its edges one at a time in any order. Self-loops are ignored;
+ * duplicates are accepted and change no label.
+ *   d_src, d_dst: device arrays [count]; count == 0 is a no-op.
+ * Errors: VERTEX_RANGE if any id >= n — then the index is left exactly as it was.
+ */
+dbl_status dbl_insert_edges(dbl_index *ix, uint64_t count, const uint32_t *d_src,
+                            const uint32_t *d_dst, void *stream);
+
+/*
+ * Answer q(d_u[i], d_v[i]) for i < count (Algorithm 2 with Theorems 1 and 2).
+ *   d_out: device array [count]; d_out[i] = answer | (dbl_class << 1), answer 1 = u reaches v.
+ * Answers are exact reachability on the current graph. Errors: VERTEX_RANGE if any id >= n
+ * (d_out is then unspecified); the index is never modified by a query.
+ */
+dbl_status dbl_query_batch(dbl_index *ix, uint64_t count, const uint32_t *d_u,
+                           const uint32_t *d_v, uint8_t *d_out, void *stream);
+
+/* Copy the labels out: each argument is a device array [n] of uint64 (any may be NULL). */
+dbl_status dbl_read_labels(const dbl_index *ix, uint64_t *d_dl_in, uint64_t *d_dl_out,
+                           uint64_t *d_bl_in, uint64_t *d_bl_out, void *stream);
+
+/* Copy the ordered landmark list to HOST array h_out [64]; *k receives the landmark count. */
+dbl_status dbl_get_landmarks(const dbl_index *ix, uint32_t *h_out, uint32_t *k);
+
+/* Copy the leaf sets fixed at build time to HOST array h_flags [n] (bit 0 S_in, bit 1 S_out)
+   and the leaf hash table to HOST array h_bucket [n]; either may be NULL. */
+dbl_status dbl_get_leaves(const dbl_index *ix, uint8_t *h_flags, uint8_t *h_bucket);
+
+/* Counters since build (host struct). */
+dbl_status dbl_get_stats(const dbl_index *ix, dbl_stats *out);
+
+/* Vertex count of the index. */
+uint32_t dbl_num_vertices(const dbl_index *ix);
+
+/* Release every device buffer of the index (NULL is ignored). */
+void dbl_destroy(dbl_index *ix);
+
+/* Static text for a status code. */
+const char *dbl_status_str(dbl_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DBL_H */

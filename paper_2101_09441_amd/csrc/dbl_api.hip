@@ -1,0 +1,623 @@
+// C ABI of the DBL index (declared in include/dbl.h): device memory, call orchestration and
+// status reporting. Every step of the method runs in the kernels of dbl_kernels.hip; this file
+// only allocates, launches and reads back the small control block.
+#include <stddef.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "dbl.h"
+#include "dbl_internal.hpp"
+
+using dbl::Csr;
+using dbl::Ctl;
+using dbl::Ovf;
+using u64 = unsigned long long;
+
+struct dbl_index {
+  int device = 0;
+  uint32_t n = 0, k = 0, kp = 0, kp_bits = 0;
+  float slack_frac = 0.25f;
+  uint32_t slack_min = 4;
+  Csr f{}, r{};
+  uint64_t f_total = 0, r_total = 0;  // entries reserved in f.col / r.col
+  u64 *lab = nullptr;
+  uint32_t *fq[3] = {nullptr, nullptr, nullptr};
+  uint32_t *inq = nullptr;
+  u64 *heavy_list = nullptr;
+  uint64_t heavy_cap = 0;
+  Ctl *ctl = nullptr;
+  Ctl *h_ctl = nullptr;  // pinned host copy
+  Ovf *ovf = nullptr;
+  uint64_t ovf_cap = 0;
+  uint32_t *landmarks_d = nullptr;
+  uint32_t landmarks_h[64] = {};
+  uint8_t *leaf_flags = nullptr, *bucket = nullptr;
+  u64 *scan_tmp = nullptr, *scan_total = nullptr;
+  uint64_t scan_tmp_words = 0;
+  // query scratch
+  uint32_t *und = nullptr, *heavy_q = nullptr;
+  uint64_t und_cap = 0;
+  u64 *vis = nullptr;
+  uint64_t vis_words = 0;
+  uint32_t *bfs_queue = nullptr;
+  uint32_t slots = 0, qcap = 0, slots_opt = 0, qcap_opt = 0;
+  u64 *gvis = nullptr;
+  // statistics kept on the host
+  uint64_t build_rounds = 0, insert_calls = 0, insert_rounds = 0, regrows = 0, bfs_heavy = 0;
+};
+
+namespace {
+
+dbl_status from_hip(hipError_t e) {
+  if (e == hipSuccess) return DBL_OK;
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return DBL_ERR_OUT_OF_MEMORY;
+  return DBL_ERR_DEVICE;
+}
+
+#define CK(expr)                                   \
+  do {                                             \
+    hipError_t e_ = (expr);                        \
+    if (e_ != hipSuccess) return from_hip(e_);     \
+  } while (0)
+
+#define CKS(expr)                                  \
+  do {                                             \
+    dbl_status s_ = (expr);                        \
+    if (s_ != DBL_OK) return s_;                   \
+  } while (0)
+
+template <typename T>
+dbl_status dalloc(T **p, uint64_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc((void **)p, sizeof(T) * count);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return DBL_ERR_OUT_OF_MEMORY;
+  }
+  return DBL_OK;
+}
+
+template <typename T>
+void dfree(T *&p) {
+  if (p) (void)hipFree((void *)p);
+  p = nullptr;
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+dbl::PropArgs prop_args(const dbl_index *ix) {
+  dbl::PropArgs a;
+  a.L.lab = ix->lab;
+  a.f = ix->f;
+  a.r = ix->r;
+  for (int i = 0; i < 3; i++) a.fq[i] = ix->fq[i];
+  a.inq = ix->inq;
+  a.heavy_list = ix->heavy_list;
+  a.heavy_cap = ix->heavy_cap;
+  a.ctl = ix->ctl;
+  return a;
+}
+
+// Copy the control block to the host and wait for the stream.
+dbl_status sync_ctl(dbl_index *ix, hipStream_t s) {
+  CK(hipMemcpyAsync(ix->h_ctl, ix->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+  CK(hipStreamSynchronize(s));
+  return DBL_OK;
+}
+
+// Write one 32-bit field of the device control block (host value, stream ordered).
+dbl_status set_ctl_u32(dbl_index *ix, size_t offset, uint32_t value, hipStream_t s) {
+  CK(dbl::launch_fill_u32((uint32_t *)((char *)ix->ctl + offset), value, 1, s));
+  return DBL_OK;
+}
+
+dbl_status ensure_heavy_cap(dbl_index *ix) {
+  const uint64_t need = (ix->f_total + ix->r_total) / 2048 + 1024;
+  if (need <= ix->heavy_cap) return DBL_OK;
+  dfree(ix->heavy_list);
+  CKS(dalloc(&ix->heavy_list, need));
+  ix->heavy_cap = need;
+  return DBL_OK;
+}
+
+// Grid rounds until the pending frontier is empty. `group` rounds are enqueued between reads of
+// the control block; a round that finds an empty frontier does nothing.
+dbl_status grid_propagate(dbl_index *ix, hipStream_t s, uint32_t group, uint64_t *rounds) {
+  for (;;) {
+    CKS(sync_ctl(ix, s));
+    const uint32_t cur = ix->h_ctl->cur;
+    const uint32_t fsz = ix->h_ctl->fsize[cur];
+    if (fsz == 0) return DBL_OK;
+    uint32_t stamp = ix->h_ctl->stamp;
+    if (stamp > 0xF0000000u) {
+      // restart the stamp sequence before it wraps; the pending frontier is already closed, so
+      // only later frontiers use the cleared marks
+      CK(dbl::launch_fill_u32(ix->inq, 0u, 2ull * ix->n, s));
+      CKS(set_ctl_u32(ix, offsetof(Ctl, stamp), 1u, s));
+      stamp = 1;
+    }
+    dbl::PropArgs a = prop_args(ix);
+    uint32_t ring = cur;
+    uint32_t grid = (uint32_t)std::min<uint64_t>(2048, std::max<uint64_t>(64, (fsz + 255) / 256));
+    for (uint32_t g = 0; g < group; g++) {
+      CK(dbl::launch_round(a, ring, stamp, grid, s));
+      ring = ring == 2 ? 0 : ring + 1;
+      stamp++;
+      grid = 2048;
+    }
+    *rounds += group;
+  }
+}
+
+dbl_status regrow(dbl_index *ix, uint32_t dir, uint32_t novf, hipStream_t s) {
+  Csr &g = dir ? ix->r : ix->f;
+  uint64_t &total_ref = dir ? ix->r_total : ix->f_total;
+  Csr ng{};
+  ng.deg = g.deg;
+  CKS(dalloc(&ng.cap, ix->n));
+  dbl_status st = dalloc(&ng.off, ix->n);
+  if (st != DBL_OK) { dfree(ng.cap); return st; }
+  CK(dbl::launch_slack_cap(g.deg, ng.cap, ix->n, ix->slack_frac, ix->slack_min, s));
+  CK(dbl::scan_exclusive(ng.cap, ng.off, ix->n, ix->scan_tmp, ix->scan_total, s));
+  u64 total = 0;
+  CK(hipMemcpyAsync(&total, ix->scan_total, sizeof(u64), hipMemcpyDeviceToHost, s));
+  CK(hipStreamSynchronize(s));
+  st = dalloc(&ng.col, total);
+  if (st != DBL_OK) { dfree(ng.cap); dfree(ng.off); return st; }
+  CK(dbl::launch_regrow_copy(g, ng, ix->n, s));
+  CK(dbl::launch_place_overflow(ix->ovf, novf, dir, ng, s));
+  CK(hipStreamSynchronize(s));
+  dfree(g.col);
+  dfree(g.cap);
+  dfree(g.off);
+  g.col = ng.col;
+  g.cap = ng.cap;
+  g.off = ng.off;
+  total_ref = total;
+  ix->regrows++;
+  return ensure_heavy_cap(ix);
+}
+
+// After appends: regrow rows that ran out of slack, then finish propagation.
+dbl_status finish_insert(dbl_index *ix, hipStream_t s, uint64_t *rounds) {
+  CKS(sync_ctl(ix, s));
+  uint32_t novf = ix->h_ctl->ovf_count;
+  if (novf) {
+    if (novf > ix->ovf_cap) return DBL_ERR_DEVICE;  // cannot happen: capacity is 2 per edge
+    // which directions overflowed
+    std::vector<Ovf> rec(novf);
+    CK(hipMemcpyAsync(rec.data(), ix->ovf, sizeof(Ovf) * novf, hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    bool any_f = false, any_r = false;
+    for (const Ovf &o : rec) ((o.x >> 31) ? any_r : any_f) = true;
+    if (any_f) CKS(regrow(ix, 0, novf, s));
+    if (any_r) CKS(regrow(ix, 1, novf, s));
+    dbl::PropArgs a = prop_args(ix);
+    CK(dbl::launch_push_overflow(a, ix->ovf, novf, s));
+    CKS(set_ctl_u32(ix, offsetof(Ctl, ovf_count), 0u, s));
+    CK(dbl::launch_local_rounds(a, s));
+  }
+  return grid_propagate(ix, s, 2, rounds);
+}
+
+uint32_t bits_of(uint32_t kp) {
+  uint32_t b = 0;
+  while ((1u << b) < kp) b++;
+  return b;
+}
+
+dbl_status ensure_query_scratch(dbl_index *ix, uint64_t count) {
+  if (count > ix->und_cap) {
+    dfree(ix->und);
+    dfree(ix->heavy_q);
+    uint64_t cap = std::max<uint64_t>(count, 1024);
+    CKS(dalloc(&ix->und, cap));
+    CKS(dalloc(&ix->heavy_q, cap));
+    ix->und_cap = cap;
+  }
+  if (!ix->vis) {
+    uint32_t slots = ix->slots_opt ? ix->slots_opt : 1024;
+    slots = std::max<uint32_t>(4, (slots + 3) / 4 * 4);
+    const uint64_t words = (ix->n + 63) / 64;
+    const uint32_t qcap = ix->qcap_opt ? std::min<uint32_t>(ix->qcap_opt, ix->n)
+                                       : (uint32_t)std::min<uint64_t>(ix->n, 1u << 18);
+    CKS(dalloc(&ix->vis, words * slots));
+    CKS(dalloc(&ix->bfs_queue, (uint64_t)qcap * slots));
+    hipStream_t s0 = nullptr;
+    CK(dbl::launch_fill_u64(ix->vis, 0ull, words * slots, s0));
+    CK(hipStreamSynchronize(s0));
+    ix->slots = slots;
+    ix->vis_words = words;
+    ix->qcap = qcap;
+  }
+  return DBL_OK;
+}
+
+dbl_status do_build(dbl_index *ix, uint64_t m, const uint32_t *src, const uint32_t *dst,
+                    const dbl_options &o, hipStream_t s) {
+  const uint32_t n = ix->n;
+  CKS(dalloc(&ix->ctl, 1));
+  CK(hipHostMalloc((void **)&ix->h_ctl, sizeof(Ctl), hipHostMallocDefault));
+  {
+    Ctl init;
+    memset(&init, 0, sizeof(init));
+    init.cur = 0;
+    init.stamp = 1;
+    CK(hipMemcpyAsync(ix->ctl, &init, sizeof(Ctl), hipMemcpyHostToDevice, s));
+    CK(hipStreamSynchronize(s));
+  }
+  // ---- a1: validate, de-duplicate, count degrees, reserve slack, scatter into both CSRs
+  CK(dbl::launch_validate_pairs(src, dst, m, n, ix->ctl, s));
+  CKS(sync_ctl(ix, s));
+  if (ix->h_ctl->err) return DBL_ERR_VERTEX_RANGE;
+  uint8_t *keep = nullptr;
+  u64 *table = nullptr;
+  CKS(dalloc(&keep, m));
+  uint64_t mask = 0;
+  if (!o.edges_unique && m) {
+    uint64_t cap = 1024;
+    while (cap < 2 * m) cap <<= 1;
+    dbl_status st = dalloc(&table, cap);
+    if (st != DBL_OK) { dfree(keep); return st; }
+    CK(dbl::launch_fill_u64(table, ~0ull, cap, s));
+    mask = cap - 1;
+  }
+  CK(dbl::launch_dedup_mark(src, dst, m, table, mask, keep, o.edges_unique ? 1 : 0, s));
+  CKS(dalloc(&ix->f.deg, n));
+  CKS(dalloc(&ix->r.deg, n));
+  CKS(dalloc(&ix->f.cap, n));
+  CKS(dalloc(&ix->r.cap, n));
+  CKS(dalloc(&ix->f.off, n));
+  CKS(dalloc(&ix->r.off, n));
+  CK(dbl::launch_fill_u32(ix->f.deg, 0u, n, s));
+  CK(dbl::launch_fill_u32(ix->r.deg, 0u, n, s));
+  CK(dbl::launch_degree_count(src, dst, keep, m, ix->f.deg, ix->r.deg, s));
+  CK(dbl::launch_slack_cap(ix->f.deg, ix->f.cap, n, ix->slack_frac, ix->slack_min, s));
+  CK(dbl::launch_slack_cap(ix->r.deg, ix->r.cap, n, ix->slack_frac, ix->slack_min, s));
+  ix->scan_tmp_words = dbl::scan_tmp_words(n);
+  CKS(dalloc(&ix->scan_tmp, ix->scan_tmp_words));
+  CKS(dalloc(&ix->scan_total, 2));
+  CK(dbl::scan_exclusive(ix->f.cap, ix->f.off, n, ix->scan_tmp, ix->scan_total, s));
+  CK(dbl::scan_exclusive(ix->r.cap, ix->r.off, n, ix->scan_tmp, ix->scan_total + 1, s));
+  u64 totals[2] = {0, 0};
+  CK(hipMemcpyAsync(totals, ix->scan_total, sizeof(totals), hipMemcpyDeviceToHost, s));
+  CK(hipStreamSynchronize(s));
+  ix->f_total = totals[0];
+  ix->r_total = totals[1];
+  CKS(dalloc(&ix->f.col, ix->f_total));
+  CKS(dalloc(&ix->r.col, ix->r_total));
+  // in/out degrees are needed by selection and seeding before the scatter recounts them
+  uint32_t *indeg = nullptr, *outdeg = nullptr;
+  CKS(dalloc(&indeg, n));
+  CKS(dalloc(&outdeg, n));
+  CK(hipMemcpyAsync(indeg, ix->r.deg, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s));
+  CK(hipMemcpyAsync(outdeg, ix->f.deg, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s));
+  CK(dbl::launch_fill_u32(ix->f.deg, 0u, n, s));
+  CK(dbl::launch_fill_u32(ix->r.deg, 0u, n, s));
+  CK(dbl::launch_scatter(src, dst, keep, m, ix->f, ix->r, s));
+  CK(hipStreamSynchronize(s));
+  dfree(table);
+  dfree(keep);
+
+  // ---- a2: landmarks (top-k by |Pre|*|Suc|), leaves and their hash buckets
+  CKS(dalloc(&ix->landmarks_d, 64));
+  if (ix->k) {
+    if (o.landmarks) {
+      CK(hipMemcpyAsync(ix->landmarks_d, o.landmarks, sizeof(uint32_t) * ix->k,
+                        hipMemcpyHostToDevice, s));
+    } else {
+      const uint64_t te = dbl::topk_tmp_entries(n);
+      u64 *tm = nullptr;
+      uint32_t *tid = nullptr;
+      CKS(dalloc(&tm, te));
+      dbl_status st = dalloc(&tid, te);
+      if (st != DBL_OK) { dfree(tm); return st; }
+      CK(dbl::select_topk(indeg, outdeg, n, ix->k, tm, tid, ix->landmarks_d, s));
+      CK(hipStreamSynchronize(s));
+      dfree(tm);
+      dfree(tid);
+    }
+    CK(hipMemcpyAsync(ix->landmarks_h, ix->landmarks_d, sizeof(uint32_t) * ix->k,
+                      hipMemcpyDeviceToHost, s));
+  }
+  CKS(dalloc(&ix->lab, 4ull * n));
+  CK(dbl::launch_fill_u64(ix->lab, 0ull, 4ull * n, s));
+  uint8_t *is_lm = nullptr, *flags_in = nullptr, *bucket_in = nullptr;
+  CKS(dalloc(&is_lm, n));
+  CK(hipMemsetAsync(is_lm, 0, n, s));
+  if (o.leaf_flags) {
+    CKS(dalloc(&flags_in, n));
+    CK(hipMemcpyAsync(flags_in, o.leaf_flags, n, hipMemcpyHostToDevice, s));
+  }
+  if (o.leaf_bucket) {
+    CKS(dalloc(&bucket_in, n));
+    CK(hipMemcpyAsync(bucket_in, o.leaf_bucket, n, hipMemcpyHostToDevice, s));
+  }
+  CKS(dalloc(&ix->leaf_flags, n));
+  CKS(dalloc(&ix->bucket, n));
+  CK(dbl::launch_seed({ix->lab}, n, ix->landmarks_d, ix->k, indeg, outdeg, flags_in, bucket_in,
+                      ix->kp_bits, ix->leaf_flags, ix->bucket, is_lm, s));
+  CK(hipStreamSynchronize(s));
+  dfree(is_lm);
+  dfree(flags_in);
+  dfree(bucket_in);
+  dfree(indeg);
+  dfree(outdeg);
+
+  // ---- a3: bit-parallel propagation of the seeds to the least fixpoint
+  for (int i = 0; i < 3; i++) CKS(dalloc(&ix->fq[i], 2ull * n));
+  CKS(dalloc(&ix->inq, 2ull * n));
+  CK(dbl::launch_fill_u32(ix->inq, 0u, 2ull * n, s));
+  CKS(ensure_heavy_cap(ix));
+  CK(dbl::launch_init_frontier({ix->lab}, n, ix->f, ix->r, ix->fq[0], ix->ctl, ix->inq, 1u, s));
+  uint64_t rounds = 0;
+  CKS(grid_propagate(ix, s, 4, &rounds));
+  ix->build_rounds = rounds;
+  return DBL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void dbl_default_options(dbl_options *opt) {
+  if (!opt) return;
+  memset(opt, 0, sizeof(*opt));
+  opt->num_landmarks = 64;
+  opt->bl_bits = 64;
+  opt->slack_fraction = 0.25f;
+  opt->slack_min = 4;
+}
+
+const char *dbl_status_str(dbl_status s) {
+  switch (s) {
+    case DBL_OK: return "ok";
+    case DBL_ERR_INVALID_ARG: return "invalid argument";
+    case DBL_ERR_VERTEX_RANGE: return "vertex id out of range";
+    case DBL_ERR_OUT_OF_MEMORY: return "out of device memory";
+    case DBL_ERR_DEVICE: return "HIP device error";
+  }
+  return "unknown status";
+}
+
+dbl_status dbl_build(uint32_t n, uint64_t m, const uint32_t *d_src, const uint32_t *d_dst,
+                     const dbl_options *opt, void *stream, dbl_index **out) {
+  if (!out) return DBL_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (n == 0 || n > 0x7FFFFFFFu) return DBL_ERR_INVALID_ARG;
+  if (m && (!d_src || !d_dst)) return DBL_ERR_INVALID_ARG;
+  dbl_options o;
+  if (opt) o = *opt; else dbl_default_options(&o);
+  if (o.num_landmarks > 64) return DBL_ERR_INVALID_ARG;
+  if (o.bl_bits == 0 || o.bl_bits > 64 || (o.bl_bits & (o.bl_bits - 1))) return DBL_ERR_INVALID_ARG;
+  if (!(o.slack_fraction >= 0.0f) || o.slack_fraction > 16.0f) return DBL_ERR_INVALID_ARG;
+  const uint32_t k = std::min<uint32_t>(o.num_landmarks, n);
+  if (o.landmarks) {
+    std::vector<uint32_t> seen(o.landmarks, o.landmarks + k);
+    for (uint32_t x : seen)
+      if (x >= n) return DBL_ERR_INVALID_ARG;
+    std::sort(seen.begin(), seen.end());
+    if (std::adjacent_find(seen.begin(), seen.end()) != seen.end()) return DBL_ERR_INVALID_ARG;
+  }
+  if (o.leaf_bucket)
+    for (uint32_t x = 0; x < n; x++)
+      if (o.leaf_bucket[x] >= o.bl_bits) return DBL_ERR_INVALID_ARG;
+  dbl_index *ix = new (std::nothrow) dbl_index();
+  if (!ix) return DBL_ERR_OUT_OF_MEMORY;
+  if (hipGetDevice(&ix->device) != hipSuccess) {
+    delete ix;
+    return DBL_ERR_DEVICE;
+  }
+  ix->n = n;
+  ix->k = k;
+  ix->kp = o.bl_bits;
+  ix->kp_bits = bits_of(o.bl_bits);
+  ix->slack_frac = o.slack_fraction;
+  ix->slack_min = o.slack_min;
+  ix->slots_opt = o.bfs_slots;
+  ix->qcap_opt = o.bfs_queue_cap;
+  hipStream_t s = (hipStream_t)stream;
+  dbl_status st = do_build(ix, m, d_src, d_dst, o, s);
+  if (st != DBL_OK) {
+    (void)hipStreamSynchronize(s);
+    dbl_destroy(ix);
+    return st;
+  }
+  *out = ix;
+  return DBL_OK;
+}
+
+dbl_status dbl_insert_edges(dbl_index *ix, uint64_t count, const uint32_t *d_src,
+                            const uint32_t *d_dst, void *stream) {
+  if (!ix) return DBL_ERR_INVALID_ARG;
+  if (count == 0) return DBL_OK;
+  if (!d_src || !d_dst || count > 0xFFFFFFFFull / 2) return DBL_ERR_INVALID_ARG;
+  DeviceGuard dg(ix->device);
+  hipStream_t s = (hipStream_t)stream;
+  if (2 * count > ix->ovf_cap) {
+    dfree(ix->ovf);
+    const uint64_t cap = std::max<uint64_t>(2 * count, 1024);
+    CKS(dalloc(&ix->ovf, cap));
+    ix->ovf_cap = cap;
+  }
+  dbl::PropArgs a = prop_args(ix);
+  if (count <= dbl::kSmallBatch) {
+    CK(dbl::launch_insert_small(a, d_src, d_dst, (uint32_t)count, ix->n, ix->ovf, ix->ovf_cap, s));
+  } else {
+    CK(dbl::launch_validate_pairs(d_src, d_dst, count, ix->n, ix->ctl, s));
+    CK(dbl::launch_insert_apply(a, d_src, d_dst, count, ix->ovf, ix->ovf_cap, s));
+    CK(dbl::launch_local_rounds(a, s));
+  }
+  CKS(sync_ctl(ix, s));
+  if (ix->h_ctl->err) {
+    CKS(set_ctl_u32(ix, offsetof(Ctl, err), 0u, s));
+    CK(hipStreamSynchronize(s));
+    return DBL_ERR_VERTEX_RANGE;
+  }
+  uint64_t rounds = 0;
+  dbl_status st = finish_insert(ix, s, &rounds);
+  ix->insert_calls++;
+  ix->insert_rounds += rounds;
+  return st;
+}
+
+dbl_status dbl_query_batch(dbl_index *ix, uint64_t count, const uint32_t *d_u,
+                           const uint32_t *d_v, uint8_t *d_out, void *stream) {
+  if (!ix) return DBL_ERR_INVALID_ARG;
+  if (count == 0) return DBL_OK;
+  if (!d_u || !d_v || !d_out || count > 0xFFFFFFFFull) return DBL_ERR_INVALID_ARG;
+  DeviceGuard dg(ix->device);
+  hipStream_t s = (hipStream_t)stream;
+  CKS(ensure_query_scratch(ix, count));
+  CK(dbl::launch_ctl_reset_query(ix->ctl, s));
+  CK(dbl::launch_query_label({ix->lab}, d_u, d_v, count, ix->n, d_out, ix->und, ix->ctl, s));
+  dbl::BfsArgs b;
+  b.L.lab = ix->lab;
+  b.f = ix->f;
+  b.u = d_u;
+  b.v = d_v;
+  b.und = ix->und;
+  b.out = d_out;
+  b.vis = ix->vis;
+  b.vis_words = ix->vis_words;
+  b.queue = ix->bfs_queue;
+  b.qcap = ix->qcap;
+  b.heavy_q = ix->heavy_q;
+  b.ctl = ix->ctl;
+  CK(dbl::launch_query_bfs(b, ix->slots, s));
+  CKS(sync_ctl(ix, s));
+  if (ix->h_ctl->err) {
+    CKS(set_ctl_u32(ix, offsetof(Ctl, err), 0u, s));
+    CK(hipStreamSynchronize(s));
+    return DBL_ERR_VERTEX_RANGE;
+  }
+  const uint32_t nheavy = ix->h_ctl->bfs_heavy;
+  if (nheavy) {
+    std::vector<uint32_t> hq(nheavy), hu(nheavy), hv(nheavy);
+    CK(hipMemcpyAsync(hq.data(), ix->heavy_q, sizeof(uint32_t) * nheavy, hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    if (!ix->gvis) CKS(dalloc(&ix->gvis, ix->vis_words));
+    dbl::PropArgs a = prop_args(ix);
+    for (uint32_t i = 0; i < nheavy; i++) {
+      uint32_t u = 0, v = 0;
+      CK(hipMemcpyAsync(&u, d_u + hq[i], sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+      CK(hipMemcpyAsync(&v, d_v + hq[i], sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+      CK(hipStreamSynchronize(s));
+      CK(dbl::launch_gbfs_start(a, ix->gvis, ix->vis_words, u, s));
+      uint32_t ring = 0;
+      for (;;) {
+        CK(dbl::launch_gbfs_round(a, ix->gvis, u, v, ring, s));
+        ring = ring == 2 ? 0 : ring + 1;
+        CKS(sync_ctl(ix, s));
+        if (ix->h_ctl->found || ix->h_ctl->fsize[ring] == 0) break;
+      }
+      CK(dbl::launch_gbfs_finish(a, hq[i], d_out, s));
+    }
+    // the propagation frontier was borrowed: it is empty again, keep its ring position
+    CK(hipStreamSynchronize(s));
+    ix->bfs_heavy += nheavy;
+  }
+  return DBL_OK;
+}
+
+dbl_status dbl_read_labels(const dbl_index *ix, uint64_t *d_dl_in, uint64_t *d_dl_out,
+                           uint64_t *d_bl_in, uint64_t *d_bl_out, void *stream) {
+  if (!ix) return DBL_ERR_INVALID_ARG;
+  DeviceGuard dg(ix->device);
+  hipStream_t s = (hipStream_t)stream;
+  CK(dbl::launch_unpack_labels({ix->lab}, ix->n, (u64 *)d_dl_in, (u64 *)d_dl_out, (u64 *)d_bl_in,
+                               (u64 *)d_bl_out, s));
+  CK(hipStreamSynchronize(s));
+  return DBL_OK;
+}
+
+dbl_status dbl_get_landmarks(const dbl_index *ix, uint32_t *h_out, uint32_t *k) {
+  if (!ix || !h_out || !k) return DBL_ERR_INVALID_ARG;
+  memcpy(h_out, ix->landmarks_h, sizeof(uint32_t) * ix->k);
+  *k = ix->k;
+  return DBL_OK;
+}
+
+dbl_status dbl_get_leaves(const dbl_index *ix, uint8_t *h_flags, uint8_t *h_bucket) {
+  if (!ix) return DBL_ERR_INVALID_ARG;
+  DeviceGuard dg(ix->device);
+  if (h_flags) CK(hipMemcpy(h_flags, ix->leaf_flags, ix->n, hipMemcpyDeviceToHost));
+  if (h_bucket) CK(hipMemcpy(h_bucket, ix->bucket, ix->n, hipMemcpyDeviceToHost));
+  return DBL_OK;
+}
+
+dbl_status dbl_get_stats(const dbl_index *ix, dbl_stats *out) {
+  if (!ix || !out) return DBL_ERR_INVALID_ARG;
+  DeviceGuard dg(ix->device);
+  Ctl c;
+  CK(hipMemcpy(&c, ix->ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+  uint64_t stored = 0;
+  {
+    std::vector<uint32_t> deg(ix->n);
+    CK(hipMemcpy(deg.data(), ix->f.deg, sizeof(uint32_t) * ix->n, hipMemcpyDeviceToHost));
+    for (uint32_t d : deg) stored += d;
+  }
+  memset(out, 0, sizeof(*out));
+  out->num_edges = stored;
+  out->build_rounds = ix->build_rounds;
+  out->insert_calls = ix->insert_calls;
+  out->insert_rounds = ix->insert_rounds + c.local_rounds;
+  out->vertices_expanded = c.ctr[dbl::kCtrExpanded];
+  out->edges_relaxed = c.ctr[dbl::kCtrRelaxed];
+  out->csr_regrows = ix->regrows;
+  uint64_t q = 0;
+  for (int i = 0; i < 7; i++) {
+    out->query_class[i] = c.ctr[dbl::kCtrClass0 + i];
+    q += out->query_class[i];
+  }
+  out->queries = q;
+  out->bfs_vertices = c.ctr[dbl::kCtrBfsVert];
+  out->bfs_edges = c.ctr[dbl::kCtrBfsEdge];
+  out->bfs_heavy = ix->bfs_heavy;
+  return DBL_OK;
+}
+
+uint32_t dbl_num_vertices(const dbl_index *ix) { return ix ? ix->n : 0; }
+
+void dbl_destroy(dbl_index *ix) {
+  if (!ix) return;
+  DeviceGuard dg(ix->device);
+  dfree(ix->f.off); dfree(ix->f.deg); dfree(ix->f.cap); dfree(ix->f.col);
+  dfree(ix->r.off); dfree(ix->r.deg); dfree(ix->r.cap); dfree(ix->r.col);
+  dfree(ix->lab);
+  for (int i = 0; i < 3; i++) dfree(ix->fq[i]);
+  dfree(ix->inq);
+  dfree(ix->heavy_list);
+  dfree(ix->ctl);
+  if (ix->h_ctl) (void)hipHostFree(ix->h_ctl);
+  dfree(ix->ovf);
+  dfree(ix->landmarks_d);
+  dfree(ix->leaf_flags);
+  dfree(ix->bucket);
+  dfree(ix->scan_tmp);
+  dfree(ix->scan_total);
+  dfree(ix->und);
+  dfree(ix->heavy_q);
+  dfree(ix->vis);
+  dfree(ix->bfs_queue);
+  dfree(ix->gvis);
+  delete ix;
+}
+
+}  // extern "C"

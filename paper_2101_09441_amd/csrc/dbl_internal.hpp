@@ -1,0 +1,174 @@
+// Internal types and launch wrappers shared by the two translation units of libdbl
+// (dbl_kernels.hip: device code + launch wrappers; dbl_api.cpp: the C ABI and orchestration).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dbl {
+
+// A frontier entry is a vertex id with the propagation direction in bit 31: forward entries
+// carry (DL_in, BL_in) along Suc, backward entries carry (DL_out, BL_out) along Pre.
+constexpr uint32_t kDirBit = 0x80000000u;
+constexpr uint32_t kIdMask = 0x7FFFFFFFu;
+
+// Frontier vertices whose row is longer than kHeavyDeg are split into chunks of kChunk entries
+// and expanded by a separate kernel so that one hub does not serialise a whole round.
+constexpr uint32_t kHeavyDeg = 4096;
+constexpr uint32_t kChunk = 4096;
+
+// Single-workgroup propagation handles a round itself while the frontier and the edges it
+// would scan stay below these bounds; above them it hands the frontier to grid rounds.
+constexpr uint32_t kLocalMaxFrontier = 8192;
+constexpr uint32_t kLocalMaxEdges = 1u << 16;
+constexpr uint32_t kLocalThreads = 1024;
+
+// Insert batches up to this size are validated, applied and propagated by one workgroup.
+constexpr uint32_t kSmallBatch = 256;
+
+constexpr uint32_t kErrRange = 1u;
+
+// One direction of the adjacency: row x holds entries col[off[x] .. off[x] + min(deg, cap)).
+// deg may exceed cap after an append found the row full; the overflowing entries wait in the
+// overflow list until the CSR is regrown.
+struct Csr {
+  unsigned long long *off;
+  uint32_t *deg;
+  uint32_t *cap;
+  uint32_t *col;
+};
+
+enum CtrIdx : uint32_t {
+  kCtrExpanded = 0,
+  kCtrRelaxed = 1,
+  kCtrBfsVert = 2,
+  kCtrBfsEdge = 3,
+  kCtrClass0 = 4,  // 4..10: query classes
+  kCtrQueries = 11,
+  kCtrCount = 16
+};
+
+// Device-side control block; the host reads it back in one transfer at each synchronisation.
+struct Ctl {
+  uint32_t err;
+  uint32_t cur;         // ring index (0..2) of the pending frontier
+  uint32_t stamp;       // stamp of the pending frontier's entries
+  uint32_t fsize[3];    // frontier sizes (ring of three)
+  uint32_t heavy[2];    // chunk counts of high-degree frontier vertices (ring of two)
+  uint32_t ovf_count;   // adjacency appends that found their row full
+  uint32_t und_count;   // queries the labels left undecided
+  uint32_t bfs_next;    // work counter of the BFS kernel
+  uint32_t bfs_heavy;   // queries whose BFS outgrew a slot
+  uint32_t found;       // grid BFS: target reached
+  uint32_t local_rounds;
+  uint32_t pad[2];
+  unsigned long long ctr[kCtrCount];
+};
+
+// Overflowing append: row `x` (bit 31 = reverse CSR) wanted entry `y` at position `pos`.
+struct Ovf {
+  uint32_t x, pos, y, pad;
+};
+
+struct LabelsView {
+  unsigned long long *lab;  // [4n]: per vertex {DL_in, BL_in, DL_out, BL_out}
+};
+
+// ---------------------------------------------------------------- launch wrappers
+// Every wrapper enqueues on `s` and returns the launch status.
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t value, uint64_t count, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long *p, unsigned long long value, uint64_t count,
+                           hipStream_t s);
+hipError_t launch_ctl_reset_query(Ctl *ctl, hipStream_t s);
+
+// build: ingest
+hipError_t launch_validate_pairs(const uint32_t *a, const uint32_t *b, uint64_t count, uint32_t n,
+                                 Ctl *ctl, hipStream_t s);
+hipError_t launch_dedup_mark(const uint32_t *src, const uint32_t *dst, uint64_t m,
+                             unsigned long long *table, uint64_t mask, uint8_t *keep,
+                             int assume_unique, hipStream_t s);
+hipError_t launch_degree_count(const uint32_t *src, const uint32_t *dst, const uint8_t *keep,
+                               uint64_t m, uint32_t *fdeg, uint32_t *rdeg, hipStream_t s);
+hipError_t launch_slack_cap(const uint32_t *deg, uint32_t *cap, uint32_t n, float frac,
+                            uint32_t smin, hipStream_t s);
+// exclusive scan of cap[n] into off[n]; *total receives the sum. tmp: scan_tmp_words(n) words.
+uint64_t scan_tmp_words(uint32_t n);
+hipError_t scan_exclusive(const uint32_t *in, unsigned long long *out, uint32_t n, unsigned long long *tmp,
+                          unsigned long long *total, hipStream_t s);
+hipError_t launch_scatter(const uint32_t *src, const uint32_t *dst, const uint8_t *keep,
+                          uint64_t m, Csr f, Csr r, hipStream_t s);
+
+// build: landmark selection. Writes the top-k vertex ids by (M desc, id asc) into out[k].
+// tmp_m / tmp_id: topk_tmp_entries(n) entries each.
+uint64_t topk_tmp_entries(uint32_t n);
+hipError_t select_topk(const uint32_t *indeg, const uint32_t *outdeg, uint32_t n, uint32_t k,
+                       unsigned long long *tmp_m, uint32_t *tmp_id, uint32_t *out,
+                       hipStream_t s);
+
+// build: seeds
+hipError_t launch_seed(LabelsView L, uint32_t n, const uint32_t *landmarks, uint32_t k,
+                       const uint32_t *indeg, const uint32_t *outdeg,
+                       const uint8_t *leaf_flags_in, const uint8_t *bucket_in, uint32_t kp_bits,
+                       uint8_t *leaf_flags_out, uint8_t *bucket_out, uint8_t *is_landmark,
+                       hipStream_t s);
+hipError_t launch_init_frontier(LabelsView L, uint32_t n, Csr f, Csr r, uint32_t *frontier,
+                                Ctl *ctl, uint32_t *inq, uint32_t stamp, hipStream_t s);
+
+// propagation
+struct PropArgs {
+  LabelsView L;
+  Csr f, r;
+  uint32_t *fq[3];  // frontier ring
+  uint32_t *inq;    // [2n] stamp of the frontier each (vertex, direction) is queued in
+  unsigned long long *heavy_list;
+  uint64_t heavy_cap;
+  Ctl *ctl;
+};
+// one grid round: expand the frontier at ring `ring` (entries stamped `stamp`)
+hipError_t launch_round(const PropArgs &a, uint32_t ring, uint32_t stamp, uint32_t grid,
+                        hipStream_t s);
+// single-workgroup rounds starting from ctl->cur / ctl->stamp
+hipError_t launch_local_rounds(const PropArgs &a, hipStream_t s);
+
+// insertion
+hipError_t launch_insert_small(const PropArgs &a, const uint32_t *src, const uint32_t *dst,
+                               uint32_t count, uint32_t n, Ovf *ovf, uint64_t ovf_cap,
+                               hipStream_t s);
+hipError_t launch_insert_apply(const PropArgs &a, const uint32_t *src, const uint32_t *dst,
+                               uint64_t count, Ovf *ovf, uint64_t ovf_cap, hipStream_t s);
+hipError_t launch_regrow_copy(Csr old_g, Csr new_g, uint32_t n, hipStream_t s);
+hipError_t launch_place_overflow(const Ovf *ovf, uint32_t count, uint32_t dir, Csr new_g,
+                                 hipStream_t s);
+hipError_t launch_push_overflow(const PropArgs &a, const Ovf *ovf, uint32_t count,
+                                hipStream_t s);
+
+// queries
+hipError_t launch_query_label(LabelsView L, const uint32_t *u, const uint32_t *v, uint64_t count,
+                              uint32_t n, uint8_t *out, uint32_t *und, Ctl *ctl, hipStream_t s);
+struct BfsArgs {
+  LabelsView L;
+  Csr f;
+  const uint32_t *u, *v;
+  const uint32_t *und;
+  uint8_t *out;
+  unsigned long long *vis;  // [slots * vis_words]
+  uint64_t vis_words;
+  uint32_t *queue;          // [slots * qcap]
+  uint32_t qcap;
+  uint32_t *heavy_q;        // queries handed to the grid BFS
+  Ctl *ctl;
+};
+hipError_t launch_query_bfs(const BfsArgs &a, uint32_t slots, hipStream_t s);
+// grid BFS for one query (u, v) whose slot overflowed
+hipError_t launch_gbfs_start(const PropArgs &a, unsigned long long *vis, uint64_t vis_words,
+                             uint32_t u, hipStream_t s);
+hipError_t launch_gbfs_round(const PropArgs &a, unsigned long long *vis, uint32_t u, uint32_t v,
+                             uint32_t ring, hipStream_t s);
+hipError_t launch_gbfs_finish(const PropArgs &a, uint32_t qi, uint8_t *out, hipStream_t s);
+
+hipError_t launch_unpack_labels(LabelsView L, uint32_t n, unsigned long long *dl_in,
+                                unsigned long long *dl_out, unsigned long long *bl_in,
+                                unsigned long long *bl_out, hipStream_t s);
+
+}  // namespace dbl

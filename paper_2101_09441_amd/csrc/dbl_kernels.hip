@@ -1,0 +1,1147 @@
+// HIP kernels of the DBL index for gfx950 (wave64) and their launch wrappers.
+//
+// Label record: every vertex owns 32 bytes {DL_in, BL_in, DL_out, BL_out} (Definitions 1 and
+// 2, 64 bits each). Forward propagation reads and ORs the first 16 bytes along Suc; backward
+// propagation the last 16 bytes along Pre, so one 16-byte access carries both labels of a
+// direction and a query reads two 32-byte records.
+//
+// Propagation is the bit-parallel form of Algorithms 1 and 3: instead of one BFS per landmark
+// or leaf bucket, every frontier vertex ORs its whole 128-bit direction label into each
+// neighbour, and a neighbour whose label grew joins the next frontier. The labels reach the
+// least fixpoint of "label(x) contains label(p) for every edge (p, x)" over the seeds, which is
+// exactly what one BFS per bit computes; Algorithm 3's pruning (stop at a vertex that already
+// holds the added bits) is the "did the OR change anything" test.
+#include "dbl_internal.hpp"
+
+namespace dbl {
+
+using u64 = unsigned long long;
+
+// ---------------------------------------------------------------- wave / block helpers
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+  const uint32_t lane = __lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= (uint32_t)o) x += y;
+  }
+  return x;
+}
+
+__device__ __forceinline__ u64 wave_incl_scan64(u64 x) {
+  const uint32_t lane = __lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    u64 y = __shfl_up(x, o, 64);
+    if (lane >= (uint32_t)o) x += y;
+  }
+  return x;
+}
+
+__device__ __forceinline__ uint32_t lanemask_lt_popc(u64 mask) {
+  const uint32_t lane = __lane_id();
+  return (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+}
+
+// Append `val` for every active lane with `pred` to q, reserving space with one atomic per wave.
+__device__ __forceinline__ void wave_push(uint32_t *q, uint32_t *cnt, bool pred, uint32_t val) {
+  const u64 mask = __ballot(pred);
+  if (mask == 0) return;
+  const uint32_t leader = (uint32_t)__builtin_ctzll(mask);
+  uint32_t base = 0;
+  if (__lane_id() == leader) base = atomicAdd(cnt, (uint32_t)__popcll(mask));
+  base = __shfl(base, (int)leader, 64);
+  if (pred) q[base + lanemask_lt_popc(mask)] = val;
+}
+
+// Exclusive scan over a block of NT threads; *total receives the block sum.
+template <int NT>
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t *s_wsum,
+                                                    uint32_t &total) {
+  const uint32_t incl = wave_incl_scan(x);
+  const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+  if (lane == 63u) s_wsum[w] = incl;
+  __syncthreads();
+  uint32_t off = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < NT / 64; i++) {
+    const uint32_t t = s_wsum[i];
+    if ((uint32_t)i < w) off += t;
+    tot += t;
+  }
+  __syncthreads();
+  total = tot;
+  return off + incl - x;
+}
+
+__device__ __forceinline__ u64 ld_agent(const u64 *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t ld_agent32(const uint32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent32(uint32_t *p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// OR (a, b) into the two label words at w. Returns true if the call added a bit. The plain
+// pre-read only avoids atomics on targets that already hold the bits; a stale pre-read costs
+// an extra atomic, never a missed change, because the decision uses the atomic's old value.
+__device__ __forceinline__ bool relax(u64 *__restrict__ w, u64 a, u64 b) {
+  const ulonglong2 cur = *reinterpret_cast<const ulonglong2 *>(w);
+  bool changed = false;
+  if (a & ~cur.x) changed |= (a & ~atomicOr(w, a)) != 0ull;
+  if (b & ~cur.y) changed |= (b & ~atomicOr(w + 1, b)) != 0ull;
+  return changed;
+}
+
+// Claim the right to queue (vertex, direction) in the frontier stamped `stamp`. Stamps only
+// grow, so a stale read can never equal `stamp` by accident.
+__device__ __forceinline__ bool claim(uint32_t *slot, uint32_t stamp) {
+  if (*slot == stamp) return false;
+  return atomicExch(slot, stamp) != stamp;
+}
+
+__device__ __forceinline__ uint32_t fib_bucket(uint32_t x, uint32_t bits) {
+  return bits == 0 ? 0u : (uint32_t)(((u64)x * 0x9E3779B97F4A7C15ull) >> (64u - bits));
+}
+
+// ---------------------------------------------------------------- small utility kernels
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, uint64_t count) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < count;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_fill_u64(u64 *p, u64 v, uint64_t count) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < count;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+static uint32_t grid_for(uint64_t items, uint32_t per_block, uint32_t cap) {
+  uint64_t g = (items + per_block - 1) / per_block;
+  if (g == 0) g = 1;
+  if (g > cap) g = cap;
+  return (uint32_t)g;
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t value, uint64_t count, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(count, 256, 8192)), dim3(256), 0, s, p, value,
+                     count);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(u64 *p, u64 value, uint64_t count, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(count, 256, 8192)), dim3(256), 0, s, p, value,
+                     count);
+  return hipGetLastError();
+}
+
+__global__ void k_ctl_reset_query(Ctl *ctl) {
+  ctl->und_count = 0;
+  ctl->bfs_next = 0;
+  ctl->bfs_heavy = 0;
+}
+
+hipError_t launch_ctl_reset_query(Ctl *ctl, hipStream_t s) {
+  hipLaunchKernelGGL(k_ctl_reset_query, dim3(1), dim3(1), 0, s, ctl);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- ingest
+
+__global__ void k_validate(const uint32_t *a, const uint32_t *b, uint64_t count, uint32_t n,
+                           Ctl *ctl) {
+  bool bad = false;
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < count;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    bad |= (a[i] >= n) | (b[i] >= n);
+  if (__ballot(bad) && __lane_id() == 0) atomicOr(&ctl->err, kErrRange);
+}
+
+hipError_t launch_validate_pairs(const uint32_t *a, const uint32_t *b, uint64_t count, uint32_t n,
+                                 Ctl *ctl, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_validate, dim3(grid_for(count, 256, 4096)), dim3(256), 0, s, a, b, count,
+                     n, ctl);
+  return hipGetLastError();
+}
+
+__device__ __forceinline__ u64 mix64(u64 z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// keep[e] = 1 for the first copy of each distinct non-loop edge (open-addressing hash set).
+__global__ void k_dedup_mark(const uint32_t *src, const uint32_t *dst, uint64_t m, u64 *table,
+                             uint64_t mask, uint8_t *keep, int assume_unique) {
+  for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < m;
+       e += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t a = src[e], b = dst[e];
+    uint8_t k = 0;
+    if (a != b) {
+      if (assume_unique) {
+        k = 1;
+      } else {
+        const u64 key = ((u64)a << 32) | b;
+        uint64_t h = mix64(key) & mask;
+        for (;;) {
+          const u64 prev = atomicCAS(&table[h], ~0ull, key);
+          if (prev == ~0ull) { k = 1; break; }
+          if (prev == key) break;
+          h = (h + 1) & mask;
+        }
+      }
+    }
+    keep[e] = k;
+  }
+}
+
+hipError_t launch_dedup_mark(const uint32_t *src, const uint32_t *dst, uint64_t m, u64 *table,
+                             uint64_t mask, uint8_t *keep, int assume_unique, hipStream_t s) {
+  if (m == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_dedup_mark, dim3(grid_for(m, 256, 16384)), dim3(256), 0, s, src, dst, m,
+                     table, mask, keep, assume_unique);
+  return hipGetLastError();
+}
+
+__global__ void k_degree_count(const uint32_t *src, const uint32_t *dst, const uint8_t *keep,
+                               uint64_t m, uint32_t *fdeg, uint32_t *rdeg) {
+  for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < m;
+       e += (uint64_t)gridDim.x * blockDim.x) {
+    if (!keep[e]) continue;
+    atomicAdd(&fdeg[src[e]], 1u);
+    atomicAdd(&rdeg[dst[e]], 1u);
+  }
+}
+
+hipError_t launch_degree_count(const uint32_t *src, const uint32_t *dst, const uint8_t *keep,
+                               uint64_t m, uint32_t *fdeg, uint32_t *rdeg, hipStream_t s) {
+  if (m == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_degree_count, dim3(grid_for(m, 256, 16384)), dim3(256), 0, s, src, dst,
+                     keep, m, fdeg, rdeg);
+  return hipGetLastError();
+}
+
+__global__ void k_slack_cap(const uint32_t *deg, uint32_t *cap, uint32_t n, float frac,
+                            uint32_t smin) {
+  for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < n; x += gridDim.x * blockDim.x) {
+    const uint32_t d = deg[x];
+    uint32_t sl = (uint32_t)ceilf(frac * (float)d);
+    if (sl < smin) sl = smin;
+    cap[x] = d + sl;
+  }
+}
+
+hipError_t launch_slack_cap(const uint32_t *deg, uint32_t *cap, uint32_t n, float frac,
+                            uint32_t smin, hipStream_t s) {
+  hipLaunchKernelGGL(k_slack_cap, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, deg, cap, n,
+                     frac, smin);
+  return hipGetLastError();
+}
+
+// ---- exclusive scan (uint32 -> uint64), three phases
+constexpr uint32_t kScanNT = 256, kScanIT = 8, kScanTile = kScanNT * kScanIT;
+
+uint64_t scan_tmp_words(uint32_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
+
+__global__ __launch_bounds__(kScanNT) void k_scan_local(const uint32_t *in, u64 *out, uint32_t n,
+                                                        u64 *block_sums) {
+  __shared__ u64 s_w[kScanNT / 64];
+  const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanIT;
+  uint32_t v[kScanIT];
+  u64 sum = 0;
+#pragma unroll
+  for (uint32_t j = 0; j < kScanIT; j++) {
+    v[j] = (base + j < n) ? in[base + j] : 0u;
+    sum += v[j];
+  }
+  const u64 incl = wave_incl_scan64(sum);
+  const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+  if (lane == 63u) s_w[w] = incl;
+  __syncthreads();
+  u64 off = 0, tot = 0;
+#pragma unroll
+  for (uint32_t i = 0; i < kScanNT / 64; i++) {
+    if (i < w) off += s_w[i];
+    tot += s_w[i];
+  }
+  u64 run = off + incl - sum;
+#pragma unroll
+  for (uint32_t j = 0; j < kScanIT; j++) {
+    if (base + j < n) out[base + j] = run;
+    run += v[j];
+  }
+  if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_sums(u64 *sums, uint32_t nb, u64 *total) {
+  __shared__ u64 s_w[16];
+  __shared__ u64 s_carry;
+  if (threadIdx.x == 0) s_carry = 0;
+  __syncthreads();
+  for (uint32_t base = 0; base < nb; base += 1024) {
+    const uint32_t i = base + threadIdx.x;
+    const u64 x = i < nb ? sums[i] : 0ull;
+    const u64 incl = wave_incl_scan64(x);
+    const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+    if (lane == 63u) s_w[w] = incl;
+    __syncthreads();
+    u64 off = 0, tot = 0;
+    for (uint32_t j = 0; j < 16; j++) {
+      if (j < w) off += s_w[j];
+      tot += s_w[j];
+    }
+    const u64 carry = s_carry;
+    if (i < nb) sums[i] = carry + off + incl - x;
+    __syncthreads();
+    if (threadIdx.x == 0) s_carry = carry + tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *total = s_carry;
+}
+
+__global__ __launch_bounds__(kScanNT) void k_scan_add(u64 *out, uint32_t n, const u64 *sums) {
+  const u64 add = sums[blockIdx.x];
+  const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+  for (uint32_t j = threadIdx.x; j < kScanTile; j += kScanNT)
+    if (base + j < n) out[base + j] += add;
+}
+
+hipError_t scan_exclusive(const uint32_t *in, u64 *out, uint32_t n, u64 *tmp, u64 *total,
+                          hipStream_t s) {
+  const uint32_t nb = (n + kScanTile - 1) / kScanTile;
+  if (nb > 0) {
+    hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(kScanNT), 0, s, in, out, n, tmp);
+  }
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, s, tmp, nb, total);
+  if (nb > 0) {
+    hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(kScanNT), 0, s, out, n, tmp);
+  }
+  return hipGetLastError();
+}
+
+__global__ void k_scatter(const uint32_t *src, const uint32_t *dst, const uint8_t *keep,
+                          uint64_t m, Csr f, Csr r) {
+  for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < m;
+       e += (uint64_t)gridDim.x * blockDim.x) {
+    if (!keep[e]) continue;
+    const uint32_t a = src[e], b = dst[e];
+    const uint32_t p = atomicAdd(&f.deg[a], 1u);
+    f.col[f.off[a] + p] = b;
+    const uint32_t q = atomicAdd(&r.deg[b], 1u);
+    r.col[r.off[b] + q] = a;
+  }
+}
+
+hipError_t launch_scatter(const uint32_t *src, const uint32_t *dst, const uint8_t *keep,
+                          uint64_t m, Csr f, Csr r, hipStream_t s) {
+  if (m == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scatter, dim3(grid_for(m, 256, 16384)), dim3(256), 0, s, src, dst, keep,
+                     m, f, r);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- landmark selection
+// Tiles of 2048 candidates are bitonic-sorted in LDS by (M descending, id ascending); the best
+// 64 of each tile survive to the next pass until one tile remains.
+constexpr uint32_t kTkTile = 2048, kTkNT = 256, kTkKeep = 64;
+
+uint64_t topk_tmp_entries(uint32_t n) {
+  const uint64_t tiles = ((uint64_t)n + kTkTile - 1) / kTkTile;
+  return 2 * (tiles * kTkKeep + kTkKeep);
+}
+
+__global__ __launch_bounds__(kTkNT) void k_topk(const uint32_t *indeg, const uint32_t *outdeg,
+                                                const u64 *in_m, const uint32_t *in_id,
+                                                uint64_t count, u64 *out_m, uint32_t *out_id) {
+  __shared__ u64 sm[kTkTile];
+  __shared__ uint32_t sid[kTkTile];
+  const uint64_t base = (uint64_t)blockIdx.x * kTkTile;
+  for (uint32_t j = threadIdx.x; j < kTkTile; j += kTkNT) {
+    const uint64_t idx = base + j;
+    u64 m = 0;
+    uint32_t id = 0xFFFFFFFFu;
+    if (idx < count) {
+      if (in_m) {
+        m = in_m[idx];
+        id = in_id[idx];
+      } else {
+        m = (u64)indeg[idx] * (u64)outdeg[idx];
+        id = (uint32_t)idx;
+      }
+    }
+    sm[j] = m;
+    sid[j] = id;
+  }
+  for (uint32_t size = 2; size <= kTkTile; size <<= 1) {
+    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+      __syncthreads();
+      for (uint32_t p = threadIdx.x; p < kTkTile / 2; p += kTkNT) {
+        const uint32_t i = 2 * p - (p & (stride - 1));
+        const uint32_t j = i + stride;
+        const bool best_first = (i & size) == 0;
+        const u64 mi = sm[i], mj = sm[j];
+        const uint32_t ii = sid[i], ij = sid[j];
+        const bool j_before_i = (mj > mi) || (mj == mi && ij < ii);
+        if (j_before_i == best_first) {
+          sm[i] = mj; sm[j] = mi;
+          sid[i] = ij; sid[j] = ii;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (uint32_t j = threadIdx.x; j < kTkKeep; j += kTkNT) {
+    out_m[(uint64_t)blockIdx.x * kTkKeep + j] = sm[j];
+    out_id[(uint64_t)blockIdx.x * kTkKeep + j] = sid[j];
+  }
+}
+
+hipError_t select_topk(const uint32_t *indeg, const uint32_t *outdeg, uint32_t n, uint32_t k,
+                       u64 *tmp_m, uint32_t *tmp_id, uint32_t *out, hipStream_t s) {
+  if (k == 0) return hipSuccess;
+  const uint64_t half = topk_tmp_entries(n) / 2;
+  uint64_t count = n;
+  const u64 *in_m = nullptr;
+  const uint32_t *in_id = nullptr;
+  int side = 0;
+  for (;;) {
+    const uint64_t tiles = (count + kTkTile - 1) / kTkTile;
+    u64 *om = tmp_m + side * half;
+    uint32_t *oi = tmp_id + side * half;
+    hipLaunchKernelGGL(k_topk, dim3((uint32_t)tiles), dim3(kTkNT), 0, s, indeg, outdeg, in_m,
+                       in_id, count, om, oi);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (tiles == 1) return hipMemcpyAsync(out, oi, sizeof(uint32_t) * k, hipMemcpyDeviceToDevice, s);
+    in_m = om;
+    in_id = oi;
+    count = tiles * kTkKeep;
+    side ^= 1;
+  }
+}
+
+// ---------------------------------------------------------------- seeds
+
+__global__ void k_mark_landmarks(u64 *lab, const uint32_t *landmarks, uint32_t k,
+                                 uint8_t *is_landmark) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= k) return;
+  const uint32_t x = landmarks[i];
+  is_landmark[x] = 1;
+  atomicOr(&lab[4ull * x + 0], 1ull << i);  // DL_in: the landmark reaches itself
+  atomicOr(&lab[4ull * x + 2], 1ull << i);  // DL_out
+}
+
+__global__ void k_seed_leaves(u64 *lab, uint32_t n, const uint32_t *indeg, const uint32_t *outdeg,
+                              const uint8_t *is_landmark, const uint8_t *flags_in,
+                              const uint8_t *bucket_in, uint32_t kp_bits, uint8_t *flags_out,
+                              uint8_t *bucket_out) {
+  for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < n; x += gridDim.x * blockDim.x) {
+    uint32_t fl;
+    if (flags_in) {
+      fl = flags_in[x] & 3u;
+    } else {
+      const bool lm = is_landmark[x] != 0;
+      fl = (uint32_t)(!lm && indeg[x] == 0) | ((uint32_t)(!lm && outdeg[x] == 0) << 1);
+    }
+    const uint32_t b = bucket_in ? bucket_in[x] : fib_bucket(x, kp_bits);
+    if (fl & 1u) lab[4ull * x + 1] |= 1ull << b;  // BL_in: the leaf reaches itself
+    if (fl & 2u) lab[4ull * x + 3] |= 1ull << b;  // BL_out
+    flags_out[x] = (uint8_t)fl;
+    bucket_out[x] = (uint8_t)b;
+  }
+}
+
+hipError_t launch_seed(LabelsView L, uint32_t n, const uint32_t *landmarks, uint32_t k,
+                       const uint32_t *indeg, const uint32_t *outdeg,
+                       const uint8_t *leaf_flags_in, const uint8_t *bucket_in, uint32_t kp_bits,
+                       uint8_t *leaf_flags_out, uint8_t *bucket_out, uint8_t *is_landmark,
+                       hipStream_t s) {
+  if (k) {
+    hipLaunchKernelGGL(k_mark_landmarks, dim3(1), dim3(64), 0, s, L.lab, landmarks, k,
+                       is_landmark);
+  }
+  hipLaunchKernelGGL(k_seed_leaves, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, L.lab, n,
+                     indeg, outdeg, is_landmark, leaf_flags_in, bucket_in, kp_bits,
+                     leaf_flags_out, bucket_out);
+  return hipGetLastError();
+}
+
+__global__ void k_init_frontier(const u64 *lab, uint32_t n, Csr f, Csr r, uint32_t *frontier,
+                                Ctl *ctl, uint32_t ring, uint32_t *inq, uint32_t stamp) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctl->heavy[0] = 0;
+    ctl->heavy[1] = 0;
+  }
+  for (uint32_t x0 = blockIdx.x * blockDim.x; x0 < n; x0 += gridDim.x * blockDim.x) {
+    const uint32_t x = x0 + threadIdx.x;
+    bool pf = false, pb = false;
+    if (x < n) {
+      const ulonglong2 a = *reinterpret_cast<const ulonglong2 *>(lab + 4ull * x);
+      const ulonglong2 b = *reinterpret_cast<const ulonglong2 *>(lab + 4ull * x + 2);
+      pf = ((a.x | a.y) != 0ull) && min(f.deg[x], f.cap[x]) > 0u;
+      pb = ((b.x | b.y) != 0ull) && min(r.deg[x], r.cap[x]) > 0u;
+      if (pf) inq[2ull * x] = stamp;
+      if (pb) inq[2ull * x + 1] = stamp;
+    }
+    wave_push(frontier, &ctl->fsize[ring], pf, x);
+    wave_push(frontier, &ctl->fsize[ring], pb, x | kDirBit);
+  }
+}
+
+hipError_t launch_init_frontier(LabelsView L, uint32_t n, Csr f, Csr r, uint32_t *frontier,
+                                Ctl *ctl, uint32_t *inq, uint32_t stamp, hipStream_t s) {
+  // the pending frontier is ring 0 at build time
+  hipLaunchKernelGGL(k_init_frontier, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, L.lab, n,
+                     f, r, frontier, ctl, 0u, inq, stamp);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- propagation
+
+// Expand frontier entries [beg, end) (at most NT, one per thread): every edge of every entry
+// relaxes its target; targets whose label grew are queued in nq with stamp nstamp. With a heavy
+// list, rows longer than kHeavyDeg are split into chunks for k_heavy instead.
+// `coherent` reads the frontier vertices' labels past the L1 cache (needed when earlier rounds
+// of the same kernel changed them).
+template <int NT>
+__device__ __forceinline__ void expand_tile(const PropArgs &a, const uint32_t *fq, uint32_t beg,
+                                            uint32_t end, uint32_t *nq, uint32_t *ncnt,
+                                            uint32_t nstamp, u64 *heavy_list,
+                                            uint32_t *heavy_cnt, bool coherent,
+                                            uint32_t *s_start, u64 *s_off, ulonglong2 *s_lab,
+                                            uint32_t *s_ent, uint32_t *s_wsum, u64 &relaxed) {
+  const uint32_t t = threadIdx.x;
+  const uint32_t i = beg + t;
+  uint32_t d = 0;
+  if (i < end) {
+    const uint32_t ent = fq[i];
+    const uint32_t dir = ent >> 31, x = ent & kIdMask;
+    const u64 *offp = dir ? a.r.off : a.f.off;
+    const uint32_t* degp = dir ? a.r.deg : a.f.deg;
+    const uint32_t* capp = dir ? a.r.cap : a.f.cap;
+    uint32_t dg = min(degp[x], capp[x]);
+    const u64 *lp = a.L.lab + 4ull * x + 2u * dir;
+    ulonglong2 lv;
+    if (coherent) {
+      lv.x = ld_agent(lp);
+      lv.y = ld_agent(lp + 1);
+    } else {
+      lv = *reinterpret_cast<const ulonglong2 *>(lp);
+    }
+    if (heavy_list && dg > kHeavyDeg) {
+      const uint32_t nch = (dg + kChunk - 1) / kChunk;
+      const uint32_t hb = atomicAdd(heavy_cnt, nch);
+      for (uint32_t c = 0; c < nch; c++)
+        if (hb + c < a.heavy_cap) heavy_list[hb + c] = ((u64)ent << 32) | c;
+      dg = 0;
+    }
+    s_ent[t] = ent;
+    s_off[t] = offp[x];
+    s_lab[t] = lv;
+    d = dg;
+  }
+  uint32_t total;
+  const uint32_t ex = block_excl_scan<NT>(d, s_wsum, total);
+  s_start[t] = ex;
+  __syncthreads();
+  const uint32_t last = min((uint32_t)NT, end - beg) - 1u;
+  for (uint32_t e = t; e < total; e += NT) {
+    uint32_t lo = 0, hi = last;
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi + 1) >> 1;
+      if (s_start[mid] <= e) lo = mid; else hi = mid - 1;
+    }
+    const uint32_t ent = s_ent[lo];
+    const uint32_t dir = ent >> 31;
+    const uint32_t *col = dir ? a.r.col : a.f.col;
+    const uint32_t y = col[s_off[lo] + (e - s_start[lo])];
+    const ulonglong2 lv = s_lab[lo];
+    const bool ch = relax(a.L.lab + 4ull * y + 2u * dir, lv.x, lv.y);
+    const bool push = ch && claim(&a.inq[2ull * y + dir], nstamp);
+    wave_push(nq, ncnt, push, y | (ent & kDirBit));
+  }
+  if (t == 0) relaxed += total;
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_round(PropArgs a, uint32_t ring, uint32_t stamp) {
+  __shared__ uint32_t s_start[256];
+  __shared__ u64 s_off[256];
+  __shared__ ulonglong2 s_lab[256];
+  __shared__ uint32_t s_ent[256];
+  __shared__ uint32_t s_wsum[4];
+  Ctl *ctl = a.ctl;
+  const uint32_t nring = ring == 2u ? 0u : ring + 1u;
+  const uint32_t fsz = ctl->fsize[ring];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctl->fsize[nring == 2u ? 0u : nring + 1u] = 0;
+    ctl->heavy[(stamp + 1u) & 1u] = 0;
+    ctl->cur = nring;
+    ctl->stamp = stamp + 1u;
+  }
+  u64 relaxed = 0, expanded = 0;
+  for (uint32_t beg = blockIdx.x * 256u; beg < fsz; beg += gridDim.x * 256u) {
+    const uint32_t end = min(beg + 256u, fsz);
+    expanded += end - beg;
+    expand_tile<256>(a, a.fq[ring], beg, end, a.fq[nring], &ctl->fsize[nring], stamp + 1u,
+                     a.heavy_list, &ctl->heavy[stamp & 1u], false, s_start, s_off, s_lab, s_ent,
+                     s_wsum, relaxed);
+  }
+  if (threadIdx.x == 0 && expanded) {
+    atomicAdd(&ctl->ctr[kCtrExpanded], expanded);
+    atomicAdd(&ctl->ctr[kCtrRelaxed], relaxed);
+  }
+}
+
+// Chunks of high-degree frontier rows: one block per chunk of kChunk entries.
+__global__ __launch_bounds__(256) void k_heavy(PropArgs a, uint32_t hidx, uint32_t nring,
+                                               uint32_t nstamp) {
+  Ctl *ctl = a.ctl;
+  uint32_t cnt = ctl->heavy[hidx];
+  if (cnt > a.heavy_cap) cnt = (uint32_t)a.heavy_cap;
+  u64 relaxed = 0;
+  for (uint32_t item = blockIdx.x; item < cnt; item += gridDim.x) {
+    const u64 h = a.heavy_list[item];
+    const uint32_t ent = (uint32_t)(h >> 32), c = (uint32_t)h;
+    const uint32_t dir = ent >> 31, x = ent & kIdMask;
+    const Csr g = dir ? a.r : a.f;
+    const uint32_t dg = min(g.deg[x], g.cap[x]);
+    const uint32_t b = c * kChunk, e_end = min(dg, b + kChunk);
+    const ulonglong2 lv = *reinterpret_cast<const ulonglong2 *>(a.L.lab + 4ull * x + 2u * dir);
+    const u64 o = g.off[x];
+    for (uint32_t e0 = b; e0 < e_end; e0 += 256u) {
+      const uint32_t e = e0 + threadIdx.x;
+      bool push = false;
+      uint32_t y = 0;
+      if (e < e_end) {
+        y = g.col[o + e];
+        push = relax(a.L.lab + 4ull * y + 2u * dir, lv.x, lv.y) &&
+               claim(&a.inq[2ull * y + dir], nstamp);
+      }
+      wave_push(a.fq[nring], &ctl->fsize[nring], push, y | (ent & kDirBit));
+    }
+    relaxed += e_end > b ? e_end - b : 0;
+  }
+  if (threadIdx.x == 0 && relaxed) atomicAdd(&ctl->ctr[kCtrRelaxed], relaxed);
+}
+
+hipError_t launch_round(const PropArgs &a, uint32_t ring, uint32_t stamp, uint32_t grid,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_round, dim3(grid), dim3(256), 0, s, a, ring, stamp);
+  const uint32_t nring = ring == 2u ? 0u : ring + 1u;
+  hipLaunchKernelGGL(k_heavy, dim3(1024), dim3(256), 0, s, a, stamp & 1u, nring, stamp + 1u);
+  return hipGetLastError();
+}
+
+// Rounds inside one workgroup while the frontier is small (no kernel launch per round). Reads
+// the pending frontier from ctl->cur / ctl->stamp and writes back where it stopped: either the
+// frontier is empty, or it outgrew the local bounds and grid rounds take over.
+__device__ void local_rounds_body(const PropArgs &a) {
+  __shared__ uint32_t s_start[kLocalThreads];
+  __shared__ u64 s_off[kLocalThreads];
+  __shared__ ulonglong2 s_lab[kLocalThreads];
+  __shared__ uint32_t s_ent[kLocalThreads];
+  __shared__ uint32_t s_wsum[kLocalThreads / 64];
+  __shared__ uint32_t s_edges;
+  Ctl *ctl = a.ctl;
+  const uint32_t t = threadIdx.x;
+  uint32_t ring = ctl->cur, stamp = ctl->stamp;
+  u64 relaxed = 0, expanded = 0;
+  uint32_t rounds = 0;
+  for (;;) {
+    const uint32_t fsz = ld_agent32(&ctl->fsize[ring]);
+    if (fsz == 0 || fsz > kLocalMaxFrontier) break;
+    uint32_t my = 0;
+    const uint32_t *fq = a.fq[ring];
+    for (uint32_t i = t; i < fsz; i += kLocalThreads) {
+      const uint32_t ent = fq[i];
+      const uint32_t x = ent & kIdMask;
+      my += (ent >> 31) ? min(a.r.deg[x], a.r.cap[x]) : min(a.f.deg[x], a.f.cap[x]);
+    }
+    if (t == 0) s_edges = 0;
+    __syncthreads();
+    if (my) atomicAdd(&s_edges, my);
+    __syncthreads();
+    const uint32_t edges = s_edges;
+    __syncthreads();
+    if (edges > kLocalMaxEdges) break;
+    const uint32_t nring = ring == 2u ? 0u : ring + 1u;
+    if (t == 0) st_agent32(&ctl->fsize[nring], 0u);
+    __syncthreads();
+    for (uint32_t beg = 0; beg < fsz; beg += kLocalThreads) {
+      const uint32_t end = min(beg + kLocalThreads, fsz);
+      expand_tile<kLocalThreads>(a, fq, beg, end, a.fq[nring], &ctl->fsize[nring], stamp + 1u,
+                                 nullptr, nullptr, true, s_start, s_off, s_lab, s_ent, s_wsum,
+                                 relaxed);
+    }
+    expanded += fsz;
+    __syncthreads();
+    ring = nring;
+    stamp++;
+    rounds++;
+  }
+  __syncthreads();
+  if (t == 0) {
+    const uint32_t nring = ring == 2u ? 0u : ring + 1u;
+    st_agent32(&ctl->fsize[nring], 0u);
+    ctl->cur = ring;
+    ctl->stamp = stamp;
+    ctl->local_rounds += rounds;
+    if (expanded) {
+      atomicAdd(&ctl->ctr[kCtrExpanded], expanded);
+      atomicAdd(&ctl->ctr[kCtrRelaxed], relaxed);
+    }
+  }
+}
+
+__global__ __launch_bounds__(kLocalThreads) void k_local_rounds(PropArgs a) {
+  local_rounds_body(a);
+}
+
+hipError_t launch_local_rounds(const PropArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_local_rounds, dim3(1), dim3(kLocalThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- insertion
+
+__device__ __forceinline__ void append_edge(const Csr &g, uint32_t x, uint32_t y,
+                                            uint32_t dirbit, Ovf *ovf, uint64_t ovf_cap,
+                                            Ctl *ctl) {
+  const uint32_t pos = atomicAdd(&g.deg[x], 1u);
+  if (pos < g.cap[x]) {
+    g.col[g.off[x] + pos] = y;
+  } else {
+    const uint32_t k = atomicAdd(&ctl->ovf_count, 1u);
+    if (k < ovf_cap) {
+      Ovf o;
+      o.x = x | dirbit;
+      o.pos = pos;
+      o.y = y;
+      o.pad = 0;
+      ovf[k] = o;
+    }
+  }
+}
+
+// Append (u,v) to both CSRs and seed both directions (Algorithm 3 starts from v with DL_in(u)
+// and, symmetrically, from u with DL_out(v)); changed endpoints join the pending frontier.
+__device__ __forceinline__ void apply_edge(const PropArgs &a, uint32_t u, uint32_t v,
+                                           uint32_t ring, uint32_t stamp, Ovf *ovf,
+                                           uint64_t ovf_cap, bool active) {
+  bool pv = false, pu = false;
+  if (active && u != v) {
+    append_edge(a.f, u, v, 0u, ovf, ovf_cap, a.ctl);
+    append_edge(a.r, v, u, kDirBit, ovf, ovf_cap, a.ctl);
+    const ulonglong2 fu = *reinterpret_cast<const ulonglong2 *>(a.L.lab + 4ull * u);
+    const ulonglong2 bv = *reinterpret_cast<const ulonglong2 *>(a.L.lab + 4ull * v + 2);
+    pv = relax(a.L.lab + 4ull * v, fu.x, fu.y) && claim(&a.inq[2ull * v], stamp);
+    pu = relax(a.L.lab + 4ull * u + 2, bv.x, bv.y) && claim(&a.inq[2ull * u + 1], stamp);
+  }
+  wave_push(a.fq[ring], &a.ctl->fsize[ring], pv, v);
+  wave_push(a.fq[ring], &a.ctl->fsize[ring], pu, u | kDirBit);
+}
+
+__global__ __launch_bounds__(kLocalThreads) void k_insert_small(PropArgs a, const uint32_t *src,
+                                                                const uint32_t *dst,
+                                                                uint32_t count, uint32_t n,
+                                                                Ovf *ovf, uint64_t ovf_cap) {
+  __shared__ uint32_t s_bad;
+  Ctl *ctl = a.ctl;
+  const uint32_t t = threadIdx.x;
+  if (t == 0) s_bad = 0;
+  __syncthreads();
+  for (uint32_t i = t; i < count; i += kLocalThreads)
+    if (src[i] >= n || dst[i] >= n) s_bad = 1;
+  __syncthreads();
+  if (s_bad) {
+    if (t == 0) atomicOr(&ctl->err, kErrRange);
+    return;
+  }
+  const uint32_t ring = ctl->cur, stamp = ctl->stamp;
+  if (t == 0) {
+    ctl->heavy[0] = 0;
+    ctl->heavy[1] = 0;
+  }
+  for (uint32_t i0 = 0; i0 < count; i0 += kLocalThreads) {
+    const uint32_t i = i0 + t;
+    const bool act = i < count;
+    apply_edge(a, act ? src[i] : 0u, act ? dst[i] : 0u, ring, stamp, ovf, ovf_cap, act);
+  }
+  __syncthreads();
+  local_rounds_body(a);
+}
+
+hipError_t launch_insert_small(const PropArgs &a, const uint32_t *src, const uint32_t *dst,
+                               uint32_t count, uint32_t n, Ovf *ovf, uint64_t ovf_cap,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_insert_small, dim3(1), dim3(kLocalThreads), 0, s, a, src, dst, count, n,
+                     ovf, ovf_cap);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_insert_apply(PropArgs a, const uint32_t *src,
+                                                      const uint32_t *dst, uint64_t count,
+                                                      Ovf *ovf, uint64_t ovf_cap) {
+  Ctl *ctl = a.ctl;
+  if (ctl->err) return;  // validation failed: leave the index untouched
+  const uint32_t ring = ctl->cur, stamp = ctl->stamp;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctl->heavy[0] = 0;
+    ctl->heavy[1] = 0;
+  }
+  for (uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x; i0 < count;
+       i0 += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t i = i0 + threadIdx.x;
+    const bool act = i < count;
+    apply_edge(a, act ? src[i] : 0u, act ? dst[i] : 0u, ring, stamp, ovf, ovf_cap, act);
+  }
+}
+
+hipError_t launch_insert_apply(const PropArgs &a, const uint32_t *src, const uint32_t *dst,
+                               uint64_t count, Ovf *ovf, uint64_t ovf_cap, hipStream_t s) {
+  hipLaunchKernelGGL(k_insert_apply, dim3(grid_for(count, 256, 4096)), dim3(256), 0, s, a, src,
+                     dst, count, ovf, ovf_cap);
+  return hipGetLastError();
+}
+
+// Copy every row of old_g into new_g (same deg array; new offsets and capacities).
+__global__ __launch_bounds__(256) void k_regrow_copy(Csr old_g, Csr new_g, uint32_t n) {
+  const uint32_t lane = __lane_id();
+  const uint32_t waves = gridDim.x * (blockDim.x / 64u);
+  for (uint32_t x = blockIdx.x * (blockDim.x / 64u) + (threadIdx.x >> 6); x < n; x += waves) {
+    const uint32_t d = min(old_g.deg[x], old_g.cap[x]);
+    const u64 so = old_g.off[x], dof = new_g.off[x];
+    for (uint32_t j = lane; j < d; j += 64u) new_g.col[dof + j] = old_g.col[so + j];
+  }
+}
+
+hipError_t launch_regrow_copy(Csr old_g, Csr new_g, uint32_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_regrow_copy, dim3(grid_for(n, 4, 8192)), dim3(256), 0, s, old_g, new_g, n);
+  return hipGetLastError();
+}
+
+__global__ void k_place_overflow(const Ovf *ovf, uint32_t count, uint32_t dir, Csr g) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+    const Ovf o = ovf[i];
+    if ((o.x >> 31) != dir) continue;
+    const uint32_t x = o.x & kIdMask;
+    g.col[g.off[x] + o.pos] = o.y;
+  }
+}
+
+hipError_t launch_place_overflow(const Ovf *ovf, uint32_t count, uint32_t dir, Csr new_g,
+                                 hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_place_overflow, dim3(grid_for(count, 256, 4096)), dim3(256), 0, s, ovf,
+                     count, dir, new_g);
+  return hipGetLastError();
+}
+
+// After a regrow, the tail of each overflowed edge re-enters the pending frontier so that its
+// label flows over the edge that was missing from the CSR during the first propagation.
+__global__ void k_push_overflow(PropArgs a, const Ovf *ovf, uint32_t count) {
+  Ctl *ctl = a.ctl;
+  const uint32_t ring = ctl->cur, stamp = ctl->stamp;
+  for (uint32_t i0 = blockIdx.x * blockDim.x; i0 < count; i0 += gridDim.x * blockDim.x) {
+    const uint32_t i = i0 + threadIdx.x;
+    bool p = false;
+    uint32_t ent = 0;
+    if (i < count) {
+      ent = ovf[i].x;
+      const uint32_t x = ent & kIdMask, dir = ent >> 31;
+      p = claim(&a.inq[2ull * x + dir], stamp);
+    }
+    wave_push(a.fq[ring], &ctl->fsize[ring], p, ent);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctl->heavy[0] = 0;
+    ctl->heavy[1] = 0;
+  }
+}
+
+hipError_t launch_push_overflow(const PropArgs &a, const Ovf *ovf, uint32_t count, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  // one block: the pending frontier's ring and stamp are read once per thread from ctl
+  hipLaunchKernelGGL(k_push_overflow, dim3(1), dim3(256), 0, s, a, ovf, count);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- queries
+
+// Label phase of Algorithm 2: one lane per pair. Decided pairs get their answer byte now;
+// the rest are compacted into `und` for the BFS kernel.
+__global__ __launch_bounds__(256) void k_query_label(const u64 *lab, const uint32_t *qu,
+                                                     const uint32_t *qv, uint64_t count,
+                                                     uint32_t n, uint8_t *out, uint32_t *und,
+                                                     Ctl *ctl) {
+  uint32_t cls_cnt[5] = {0, 0, 0, 0, 0};
+  bool bad_any = false;
+  for (uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x; i0 < count;
+       i0 += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t i = i0 + threadIdx.x;
+    const bool act = i < count;
+    int cls = -1;
+    bool undecided = false;
+    if (act) {
+      const uint32_t u = qu[i], v = qv[i];
+      if (u >= n || v >= n) {
+        bad_any = true;
+        out[i] = 0xFF;
+      } else if (u == v) {
+        cls = 0;
+      } else {
+        const ulonglong2 fu = *reinterpret_cast<const ulonglong2 *>(lab + 4ull * u);
+        const ulonglong2 bu = *reinterpret_cast<const ulonglong2 *>(lab + 4ull * u + 2);
+        const ulonglong2 fv = *reinterpret_cast<const ulonglong2 *>(lab + 4ull * v);
+        const ulonglong2 bv = *reinterpret_cast<const ulonglong2 *>(lab + 4ull * v + 2);
+        // fu = {DL_in(u), BL_in(u)}, bu = {DL_out(u), BL_out(u)}
+        if (bu.x & fv.x) cls = 1;                                      // Lemma 1
+        else if ((fu.y & ~fv.y) | (bv.y & ~bu.y)) cls = 2;             // Lemma 2
+        else if (bv.x & fu.x) cls = 3;                                 // Theorem 1
+        else if ((bu.x & fu.x) | (bv.x & fv.x)) cls = 4;               // Theorem 2
+        else undecided = true;
+      }
+      if (cls >= 0) out[i] = (uint8_t)((cls <= 1 ? 1u : 0u) | ((uint32_t)cls << 1));
+    }
+#pragma unroll
+    for (int c = 0; c < 5; c++) cls_cnt[c] += (uint32_t)__popcll(__ballot(cls == c));
+    wave_push(und, &ctl->und_count, undecided, (uint32_t)i);
+  }
+  if (__ballot(bad_any) && __lane_id() == 0) atomicOr(&ctl->err, kErrRange);
+  if (__lane_id() == 0) {
+#pragma unroll
+    for (int c = 0; c < 5; c++)
+      if (cls_cnt[c]) atomicAdd(&ctl->ctr[kCtrClass0 + c], (u64)cls_cnt[c]);
+  }
+}
+
+hipError_t launch_query_label(LabelsView L, const uint32_t *u, const uint32_t *v, uint64_t count,
+                              uint32_t n, uint8_t *out, uint32_t *und, Ctl *ctl, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_query_label, dim3(grid_for(count, 256, 8192)), dim3(256), 0, s, L.lab, u, v,
+                     count, n, out, und, ctl);
+  return hipGetLastError();
+}
+
+// Pruned BFS of Algorithm 2, one wavefront per undecided pair, pairs pulled from a counter.
+// Each wave owns a visited bitmap and a queue. The queue is processed 64 entries at a time:
+// their rows are laid end to end and every lane takes one edge (a prefix sum over the lanes'
+// degrees maps edge slots to rows), so short and long rows both keep the lanes busy.
+// Prunes: a target x is skipped when a landmark of u reaches it (DL_out(u) & DL_in(x)) or when
+// it cannot reach v (BL_Contain(x, v) fails). The visited bits are cleared by replaying the
+// queue, so a bitmap is clean again for the wave's next pair.
+constexpr uint32_t kBfsNT = 256;
+
+__global__ __launch_bounds__(kBfsNT) void k_query_bfs(BfsArgs a) {
+  Ctl *ctl = a.ctl;
+  const uint32_t lane = __lane_id();
+  const uint32_t slot = blockIdx.x * (kBfsNT / 64u) + (threadIdx.x >> 6);
+  u64 *vis = a.vis + (uint64_t)slot * a.vis_words;
+  uint32_t *q = a.queue + (uint64_t)slot * a.qcap;
+  const uint32_t nund = ctl->und_count;
+  const u64 *lab = a.L.lab;
+  u64 n_vert = 0, n_edge = 0, cls_t = 0, cls_f = 0;
+  for (;;) {
+    uint32_t item = 0;
+    if (lane == 0) item = atomicAdd(&ctl->bfs_next, 1u);
+    item = __shfl(item, 0, 64);
+    if (item >= nund) break;
+    const uint32_t qi = a.und[item];
+    const uint32_t u = a.u[qi], v = a.v[qi];
+    const u64 dlo_u = lab[4ull * u + 2];
+    const u64 bli_v = lab[4ull * v + 1];
+    const u64 blo_v = lab[4ull * v + 3];
+    if (lane == 0) {
+      atomicOr(&vis[u >> 6], 1ull << (u & 63u));
+      q[0] = u;
+    }
+    uint32_t head = 0, tail = 1;
+    bool found = false, overflow = false;
+    while (head < tail) {
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      const uint32_t chunk = min(64u, tail - head);
+      uint32_t d = 0;
+      u64 o = 0;
+      if (lane < chunk) {
+        const uint32_t w = q[head + lane];
+        d = min(a.f.deg[w], a.f.cap[w]);
+        o = a.f.off[w];
+      }
+      const uint32_t incl = wave_incl_scan(d);
+      const uint32_t ex = incl - d;
+      const uint32_t total = __shfl(incl, 63, 64);
+      n_vert += chunk;
+      n_edge += total;
+      for (uint32_t base = 0; base < total; base += 64u) {
+        const uint32_t e = base + lane;
+        // owner row of edge slot e: the last lane whose exclusive prefix is <= e
+        uint32_t lo = 0;
+#pragma unroll
+        for (uint32_t step = 32; step > 0; step >>= 1) {
+          const uint32_t cand = lo + step;
+          const uint32_t st = __shfl(ex, (int)cand, 64);
+          if (cand < 64u && st <= e) lo = cand;
+        }
+        const u64 ow_off = __shfl(o, (int)lo, 64);
+        const uint32_t ow_ex = __shfl(ex, (int)lo, 64);
+        const bool act = e < total;
+        uint32_t x = 0;
+        if (act) x = a.f.col[ow_off + (e - ow_ex)];
+        if (__ballot(act && x == v)) {
+          found = true;
+          break;
+        }
+        bool keep = false;
+        u64 bit = 0;
+        if (act) {
+          const ulonglong2 fx = *reinterpret_cast<const ulonglong2 *>(lab + 4ull * x);
+          const u64 blo_x = lab[4ull * x + 3];
+          keep = !(dlo_u & fx.x) && !(fx.y & ~bli_v) && !(blo_v & ~blo_x);
+          if (keep) {
+            bit = 1ull << (x & 63u);
+            keep = !(atomicOr(&vis[x >> 6], bit) & bit);
+          }
+        }
+        const u64 km = __ballot(keep);
+        const uint32_t cnt = (uint32_t)__popcll(km);
+        if (tail + cnt > a.qcap) {
+          if (keep) atomicAnd(&vis[x >> 6], ~bit);  // every set bit stays listed in the queue
+          overflow = true;
+          break;
+        }
+        if (keep) q[tail + lanemask_lt_popc(km)] = x;
+        tail += cnt;
+      }
+      if (found || overflow) break;
+      head += chunk;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    for (uint32_t i = lane; i < tail; i += 64u) atomicExch(&vis[q[i] >> 6], 0ull);
+    if (lane == 0) {
+      if (overflow) {
+        const uint32_t h = atomicAdd(&ctl->bfs_heavy, 1u);
+        a.heavy_q[h] = qi;
+      } else {
+        a.out[qi] = found ? (uint8_t)(1u | (5u << 1)) : (uint8_t)(6u << 1);
+        if (found) cls_t++; else cls_f++;
+      }
+    }
+  }
+  if (lane == 0) {
+    if (n_vert) atomicAdd(&ctl->ctr[kCtrBfsVert], n_vert);
+    if (n_edge) atomicAdd(&ctl->ctr[kCtrBfsEdge], n_edge);
+    if (cls_t) atomicAdd(&ctl->ctr[kCtrClass0 + 5], cls_t);
+    if (cls_f) atomicAdd(&ctl->ctr[kCtrClass0 + 6], cls_f);
+  }
+}
+
+hipError_t launch_query_bfs(const BfsArgs &a, uint32_t slots, hipStream_t s) {
+  hipLaunchKernelGGL(k_query_bfs, dim3(slots / (kBfsNT / 64u)), dim3(kBfsNT), 0, s, a);
+  return hipGetLastError();
+}
+
+// ---- whole-device BFS for one pair whose slot queue overflowed (rare)
+
+__global__ void k_gbfs_start(PropArgs a, u64 *vis, uint32_t u) {
+  Ctl *ctl = a.ctl;
+  vis[u >> 6] |= 1ull << (u & 63u);
+  a.fq[0][0] = u;
+  ctl->fsize[0] = 1;
+  ctl->fsize[1] = 0;
+  ctl->fsize[2] = 0;
+  ctl->found = 0;
+}
+
+hipError_t launch_gbfs_start(const PropArgs &a, u64 *vis, uint64_t vis_words, uint32_t u,
+                             hipStream_t s) {
+  hipError_t e = launch_fill_u64(vis, 0ull, vis_words, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_gbfs_start, dim3(1), dim3(1), 0, s, a, vis, u);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_gbfs_round(PropArgs a, u64 *vis, uint32_t u, uint32_t v,
+                                                    uint32_t ring) {
+  Ctl *ctl = a.ctl;
+  const uint32_t nring = ring == 2u ? 0u : ring + 1u;
+  const uint32_t fsz = ctl->fsize[ring];
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctl->fsize[nring == 2u ? 0u : nring + 1u] = 0;
+  const u64 *lab = a.L.lab;
+  const u64 dlo_u = lab[4ull * u + 2], bli_v = lab[4ull * v + 1], blo_v = lab[4ull * v + 3];
+  for (uint32_t i0 = blockIdx.x * blockDim.x; i0 < fsz; i0 += gridDim.x * blockDim.x) {
+    const uint32_t i = i0 + threadIdx.x;
+    if (i >= fsz) continue;
+    const uint32_t w = a.fq[ring][i];
+    const uint32_t d = min(a.f.deg[w], a.f.cap[w]);
+    const u64 o = a.f.off[w];
+    for (uint32_t j = 0; j < d; j++) {
+      const uint32_t x = a.f.col[o + j];
+      if (x == v) {
+        ctl->found = 1;
+        continue;
+      }
+      const ulonglong2 fx = *reinterpret_cast<const ulonglong2 *>(lab + 4ull * x);
+      const u64 blo_x = lab[4ull * x + 3];
+      if ((dlo_u & fx.x) || (fx.y & ~bli_v) || (blo_v & ~blo_x)) continue;
+      const u64 bit = 1ull << (x & 63u);
+      if (atomicOr(&vis[x >> 6], bit) & bit) continue;
+      const uint32_t p = atomicAdd(&ctl->fsize[nring], 1u);
+      a.fq[nring][p] = x;
+    }
+  }
+}
+
+hipError_t launch_gbfs_round(const PropArgs &a, u64 *vis, uint32_t u, uint32_t v, uint32_t ring,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_gbfs_round, dim3(2048), dim3(256), 0, s, a, vis, u, v, ring);
+  return hipGetLastError();
+}
+
+__global__ void k_gbfs_finish(PropArgs a, uint32_t qi, uint8_t *out) {
+  Ctl *ctl = a.ctl;
+  const bool found = ctl->found != 0;
+  out[qi] = found ? (uint8_t)(1u | (5u << 1)) : (uint8_t)(6u << 1);
+  atomicAdd(&ctl->ctr[kCtrClass0 + (found ? 5 : 6)], 1ull);
+  ctl->fsize[0] = 0;
+  ctl->fsize[1] = 0;
+  ctl->fsize[2] = 0;
+  ctl->found = 0;
+}
+
+hipError_t launch_gbfs_finish(const PropArgs &a, uint32_t qi, uint8_t *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_gbfs_finish, dim3(1), dim3(1), 0, s, a, qi, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- label read-out
+
+__global__ void k_unpack_labels(const u64 *lab, uint32_t n, u64 *dl_in, u64 *dl_out, u64 *bl_in,
+                                u64 *bl_out) {
+  for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < n; x += gridDim.x * blockDim.x) {
+    const ulonglong2 f = *reinterpret_cast<const ulonglong2 *>(lab + 4ull * x);
+    const ulonglong2 b = *reinterpret_cast<const ulonglong2 *>(lab + 4ull * x + 2);
+    if (dl_in) dl_in[x] = f.x;
+    if (bl_in) bl_in[x] = f.y;
+    if (dl_out) dl_out[x] = b.x;
+    if (bl_out) bl_out[x] = b.y;
+  }
+}
+
+hipError_t launch_unpack_labels(LabelsView L, uint32_t n, u64 *dl_in, u64 *dl_out, u64 *bl_in,
+                                u64 *bl_out, hipStream_t s) {
+  hipLaunchKernelGGL(k_unpack_labels, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, L.lab, n,
+                     dl_in, dl_out, bl_in, bl_out);
+  return hipGetLastError();
+}
+
+}  // namespace dbl

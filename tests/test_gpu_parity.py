@@ -1,0 +1,314 @@
+"""GPU parity: labels and answers of libdbl (through the C ABI) against the oracle, bit for bit.
+
+Every expected value comes from the CPU oracle on the same seeded inputs. Labels are compared
+word for word; answers and decision classes byte for byte (the class is a function of the exact
+labels, so it is unique too).
+"""
+import numpy as np
+import pytest
+import torch
+
+import dblgen
+import oracle
+from golden_io import fig1_graph, fig1_labels, fig3_insert
+from test_oracle_brute import FAMILIES, random_bucket
+
+pytestmark = pytest.mark.gpu
+
+dbl = pytest.importorskip("paper_2101_09441_amd")
+
+
+def dev(a):
+    return dbl.to_device_ids(a)
+
+
+def gpu_index(n, src, dst, **kw):
+    return dbl.Index.build(n, dev(src), dev(dst), **kw)
+
+
+def assert_labels_equal(gix, oix, what=""):
+    g = gix.labels_numpy()
+    o = oix.labels()
+    for name, a, b in zip(("DL_in", "DL_out", "BL_in", "BL_out"), g, o):
+        if not np.array_equal(a, b):
+            bad = np.flatnonzero(a != b)
+            raise AssertionError(f"{what} {name} differs at {len(bad)} vertices, first {bad[:5]}: "
+                                 f"gpu {a[bad[:5]]} oracle {b[bad[:5]]}")
+
+
+def all_pairs(n):
+    return (np.repeat(np.arange(n), n).astype(np.uint32),
+            np.tile(np.arange(n), n).astype(np.uint32))
+
+
+def assert_queries_equal(gix, oix, u, v, threads=8):
+    got = gix.query(dev(u), dev(v)).cpu().numpy()
+    want = oix.query_dbl(u, v, threads=threads)
+    if not np.array_equal(got, want):
+        bad = np.flatnonzero(got != want)
+        raise AssertionError(f"{len(bad)} answers differ, first pairs "
+                             f"{list(zip(u[bad[:5]], v[bad[:5]]))}: gpu {got[bad[:5]]} "
+                             f"oracle {want[bad[:5]]}")
+    return got
+
+
+# ------------------------------------------------------------------ the paper's running example
+
+def test_fig1_labels_queries_and_fig3_insert():
+    n, src, dst = fig1_graph()
+    landmarks, bucket, _ = fig1_labels()
+    g = gpu_index(n, src, dst, num_landmarks=2, bl_bits=2, landmarks=landmarks, leaf_bucket=bucket)
+    o = oracle.OracleIndex(n, src, dst).build(k=2, kp=2, landmarks=landmarks, bucket_table=bucket)
+    assert_labels_equal(g, o, "Figure 1")
+    u, v = all_pairs(n)
+    assert_queries_equal(g, o, u, v)
+    (a, b), _ = fig3_insert()
+    g.insert_edges(dev([a]), dev([b]))
+    o.insert([a], [b])
+    assert_labels_equal(g, o, "Figure 3")
+    assert_queries_equal(g, o, u, v)
+
+
+def test_fig1_selection_on_gpu():
+    n, src, dst = fig1_graph()
+    landmarks, _, _ = fig1_labels()
+    g = gpu_index(n, src, dst, num_landmarks=2, bl_bits=2)
+    assert list(g.landmarks()) == landmarks
+    flags, _ = g.leaves()
+    assert set(np.flatnonzero(flags & 1) + 1) == {1, 2, 3}
+    assert set(np.flatnonzero(flags & 2) + 1) == {10, 11}
+
+
+# ------------------------------------------------------------------ small graph families
+
+@pytest.mark.parametrize("name,gr", FAMILIES, ids=[f[0] for f in FAMILIES])
+@pytest.mark.parametrize("k,kp", [(64, 64), (3, 4), (0, 2)])
+def test_families_build_and_all_pairs(name, gr, k, kp):
+    n, src, dst = gr
+    bucket = random_bucket(n, kp, n + k + kp)
+    g = gpu_index(n, src, dst, num_landmarks=k, bl_bits=kp, leaf_bucket=bucket)
+    o = oracle.OracleIndex(n, src, dst).build(k=k, kp=kp, bucket_table=bucket)
+    assert list(g.landmarks()) == list(o.landmarks())
+    flags, bk = g.leaves()
+    oi, oo, ob = o.leaves()
+    assert np.array_equal(flags & 1, oi.astype(np.uint8))
+    assert np.array_equal((flags >> 1) & 1, oo.astype(np.uint8))
+    assert np.array_equal(bk, ob)
+    assert_labels_equal(g, o, name)
+    u, v = all_pairs(n)
+    assert_queries_equal(g, o, u, v)
+
+
+@pytest.mark.parametrize("name,gr", FAMILIES[3:], ids=[f[0] for f in FAMILIES[3:]])
+def test_families_insert_batches(name, gr):
+    n, src, dst = gr
+    rng = np.random.default_rng(7)
+    iu = rng.integers(0, n, 60).astype(np.uint32)
+    iv = rng.integers(0, n, 60).astype(np.uint32)
+    g = gpu_index(n, src, dst, num_landmarks=6, bl_bits=8)
+    o = oracle.OracleIndex(n, src, dst).build(k=6, kp=8)
+    for lo, hi in [(0, 1), (1, 8), (8, 60)]:
+        g.insert_edges(dev(iu[lo:hi]), dev(iv[lo:hi]))
+        o.insert(iu[lo:hi], iv[lo:hi])
+        assert_labels_equal(g, o, f"{name} after {hi}")
+    u, v = all_pairs(n)
+    assert_queries_equal(g, o, u, v)
+
+
+def test_default_hash_matches_oracle():
+    w = dblgen.make_rmat_workload("h", 10, 5, draws=8 << 10)
+    g = gpu_index(w.n, w.src, w.dst)
+    o = oracle.OracleIndex(w.n, w.src, w.dst).build()
+    _, bk = g.leaves()
+    _, _, ob = o.leaves()
+    assert np.array_equal(bk, ob)
+    assert_labels_equal(g, o, "default hash")
+
+
+# ------------------------------------------------------------------ the 2^14-vertex workload
+
+@pytest.fixture(scope="module")
+def tiny():
+    return dblgen.tiny_workload(1)
+
+
+def test_tiny_build_labels(tiny):
+    w = tiny
+    g = gpu_index(w.n, w.src, w.dst)
+    o = oracle.OracleIndex(w.n, w.src, w.dst).build(threads=8)
+    assert list(g.landmarks()) == list(o.landmarks())
+    assert_labels_equal(g, o, "tiny build")
+
+
+def test_tiny_single_insertions_then_queries(tiny):
+    """1,000 uniform new edges inserted one at a time; labels checked after every insertion."""
+    w = tiny
+    g = gpu_index(w.n, w.src, w.dst)
+    o = oracle.OracleIndex(w.n, w.src, w.dst).build(threads=8)
+    su, sv = dev(w.ins_src), dev(w.ins_dst)
+    for i in range(len(w.ins_src)):
+        g.insert_edges(su[i:i + 1], sv[i:i + 1])
+        o.insert(w.ins_src[i:i + 1], w.ins_dst[i:i + 1])
+        if i % 50 == 49 or i < 20:
+            assert_labels_equal(g, o, f"after insertion {i}")
+    assert_labels_equal(g, o, "after all insertions")
+    got = assert_queries_equal(g, o, w.q_u, w.q_v)
+    truth = o.query_truth(w.q_u, w.q_v, threads=8)
+    assert np.array_equal(got & 1, truth)
+
+
+@pytest.mark.parametrize("batch", [1000, 333, 7])
+def test_tiny_batched_insertions_equal_sequential(tiny, batch):
+    w = tiny
+    g = gpu_index(w.n, w.src, w.dst)
+    o = oracle.OracleIndex(w.n, w.src, w.dst).build(threads=8)
+    o.insert(w.ins_src, w.ins_dst)
+    for lo in range(0, len(w.ins_src), batch):
+        g.insert_edges(dev(w.ins_src[lo:lo + batch]), dev(w.ins_dst[lo:lo + batch]))
+    assert_labels_equal(g, o, f"batch {batch}")
+    assert_queries_equal(g, o, w.q_u, w.q_v)
+
+
+def test_tiny_no_slack_forces_regrow(tiny):
+    """Zero per-vertex slack: every insertion overflows its row and the CSR is regrown."""
+    w = tiny
+    g = gpu_index(w.n, w.src, w.dst, slack_fraction=0.0, slack_min=0)
+    o = oracle.OracleIndex(w.n, w.src, w.dst).build(threads=8)
+    for lo, hi in [(0, 1), (1, 2), (2, 300), (300, 1000)]:
+        g.insert_edges(dev(w.ins_src[lo:hi]), dev(w.ins_dst[lo:hi]))
+        o.insert(w.ins_src[lo:hi], w.ins_dst[lo:hi])
+        assert_labels_equal(g, o, f"no slack after {hi}")
+    assert g.stats()["csr_regrows"] > 0
+    assert_queries_equal(g, o, w.q_u, w.q_v)
+
+
+def test_small_bfs_slots_overflow_to_device_bfs(tiny):
+    """Four BFS slots with 8-entry queues: long BFS overflow their slot and run on the device."""
+    n = 3000
+    src = np.arange(n - 1, dtype=np.uint32)
+    dst = src + 1
+    # no landmarks and one BL bucket: the labels decide nothing, every pair needs the BFS
+    g = gpu_index(n, src, dst, num_landmarks=0, bl_bits=1, bfs_slots=4, bfs_queue_cap=8)
+    o = oracle.OracleIndex(n, src, dst).build(k=0, kp=1)
+    rng = np.random.default_rng(4)
+    u = rng.integers(0, n, 40).astype(np.uint32)
+    v = rng.integers(0, n, 40).astype(np.uint32)
+    u[:5] = [0, 10, 2000, 5, 2999]
+    v[:5] = [n - 1, 12, 1000, 5, 0]
+    got = assert_queries_equal(g, o, u, v)
+    assert np.array_equal(got & 1, (u <= v).astype(np.uint8))
+    assert g.stats()["bfs_heavy"] > 0
+    w = tiny
+    g = gpu_index(w.n, w.src, w.dst, bfs_slots=4, bfs_queue_cap=8)
+    o = oracle.OracleIndex(w.n, w.src, w.dst).build(threads=8)
+    assert_queries_equal(g, o, w.q_u, w.q_v)
+
+
+# ------------------------------------------------------------------ edge cases
+
+def test_out_of_range_ids_leave_index_unchanged(tiny):
+    w = tiny
+    g = gpu_index(w.n, w.src, w.dst)
+    before = g.labels_numpy()
+    edges_before = g.stats()["num_edges"]
+    for src, dst in ([[0], [w.n]], [[w.n + 5], [1]], [list(range(300)), [w.n] * 300],
+                     [[1, 2, 3], [4, 5, 0xFFFFFFFF]]):
+        with pytest.raises(dbl.DblError) as e:
+            g.insert_edges(dev(src), dev(dst))
+        assert e.value.status == dbl.DBL_ERR_VERTEX_RANGE
+    after = g.labels_numpy()
+    for a, b in zip(before, after):
+        assert np.array_equal(a, b)
+    assert g.stats()["num_edges"] == edges_before
+    with pytest.raises(dbl.DblError) as e:
+        g.query(dev([0, w.n]), dev([1, 2]))
+    assert e.value.status == dbl.DBL_ERR_VERTEX_RANGE
+    # the index still works
+    o = oracle.OracleIndex(w.n, w.src, w.dst).build(threads=8)
+    assert_queries_equal(g, o, w.q_u[:500], w.q_v[:500])
+    with pytest.raises(dbl.DblError):
+        dbl.Index.build(10, dev([0, 10]), dev([1, 2]))
+
+
+def test_empty_loops_duplicates_and_degenerate_graphs():
+    # single vertex, no edges
+    g = gpu_index(1, [], [])
+    assert g.query(dev([0]), dev([0])).cpu().numpy()[0] == 1
+    g.insert_edges(dev([]), dev([]))
+    assert g.query(dev([]), dev([])).numel() == 0
+    # no edges at all: every vertex is both leaves; k > n
+    n = 50
+    g = gpu_index(n, [], [], num_landmarks=64)
+    o = oracle.OracleIndex(n, [], []).build(k=64)
+    assert_labels_equal(g, o, "edgeless")
+    u, v = all_pairs(n)
+    assert_queries_equal(g, o, u, v)
+    # self-loops and duplicates in the build and in insertions
+    src = [0, 0, 1, 1, 2, 3, 3, 4]
+    dst = [0, 1, 2, 2, 3, 3, 1, 4]
+    g = gpu_index(6, src, dst, num_landmarks=2, bl_bits=4)
+    o = oracle.OracleIndex(6, src, dst).build(k=2, kp=4)
+    assert_labels_equal(g, o, "loops/dups build")
+    g.insert_edges(dev([5, 5, 2, 2]), dev([5, 0, 3, 3]))
+    o.insert([5, 5, 2, 2], [5, 0, 3, 3])
+    assert_labels_equal(g, o, "loops/dups insert")
+    u, v = all_pairs(6)
+    assert_queries_equal(g, o, u, v)
+
+
+def test_long_chain_many_rounds():
+    """A 20,000-vertex path: propagation needs one round per hop, grid and local forms both."""
+    n = 20000
+    src = np.arange(n - 1, dtype=np.uint32)
+    dst = src + 1
+    g = gpu_index(n, src, dst, num_landmarks=4, bl_bits=4)
+    o = oracle.OracleIndex(n, src, dst).build(k=4, kp=4)
+    assert_labels_equal(g, o, "chain")
+    # closing the cycle changes every label
+    g.insert_edges(dev([n - 1]), dev([0]))
+    o.insert([n - 1], [0])
+    assert_labels_equal(g, o, "chain closed")
+    rng = np.random.default_rng(3)
+    u = rng.integers(0, n, 3000).astype(np.uint32)
+    v = rng.integers(0, n, 3000).astype(np.uint32)
+    assert_queries_equal(g, o, u, v)
+
+
+def test_star_hub_heavy_rows():
+    """A hub with 200,000 out-edges and 100,000 in-edges exercises the chunked heavy rows."""
+    n = 300001
+    leaves_out = np.arange(1, 200001, dtype=np.uint32)
+    leaves_in = np.arange(200001, n, dtype=np.uint32)
+    src = np.concatenate([np.zeros(200000, np.uint32), leaves_in])
+    dst = np.concatenate([leaves_out, np.zeros(100000, np.uint32)])
+    g = gpu_index(n, src, dst, num_landmarks=8, bl_bits=64)
+    o = oracle.OracleIndex(n, src, dst).build(k=8, kp=64, threads=8)
+    assert_labels_equal(g, o, "star")
+    rng = np.random.default_rng(9)
+    u = rng.integers(0, n, 5000).astype(np.uint32)
+    v = rng.integers(0, n, 5000).astype(np.uint32)
+    assert_queries_equal(g, o, u, v)
+    g.insert_edges(dev([5, 250000]), dev([250001, 7]))
+    o.insert([5, 250000], [250001, 7])
+    assert_labels_equal(g, o, "star insert")
+
+
+# ------------------------------------------------------------------ several tiles, heavy rows
+
+def test_rmat18_build_insert_query():
+    w = dblgen.make_rmat_workload("r18", 18, 11, draws=8 << 18, n_insert=20000,
+                                  insert_kind="rmat", n_query=100000, query_kind="mixed")
+    g = gpu_index(w.n, w.src, w.dst)
+    o = oracle.OracleIndex(w.n, w.src, w.dst).build(threads=8)
+    assert list(g.landmarks()) == list(o.landmarks())
+    assert_labels_equal(g, o, "rmat18 build")
+    assert_queries_equal(g, o, w.q_u, w.q_v)
+    o.insert(w.ins_src, w.ins_dst)
+    for lo in range(0, 20000, 5000):
+        g.insert_edges(dev(w.ins_src[lo:lo + 5000]), dev(w.ins_dst[lo:lo + 5000]))
+    assert_labels_equal(g, o, "rmat18 after inserts")
+    got = assert_queries_equal(g, o, w.q_u, w.q_v)
+    st = g.stats()
+    assert st["queries"] == 200000
+    assert sum(st["query_class"].values()) == 200000
+    assert np.bincount(got >> 1, minlength=7)[5:].sum() > 0  # some BFS ran
