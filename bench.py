@@ -1,0 +1,280 @@
+#!/usr/bin/env python3
+"""Benchmark of the DBL hot path on one MI355X (prints one JSON line).
+
+One step is one pass of the whole path over the LiveJournal-shaped synthetic workload
+(R-MAT, 2^22 vertices, 68,993,773 unique edges; the inputs are already resident in HBM when the
+timed region starts):
+
+  1. build: ingest into forward/reverse CSR, select 64 landmarks, hash the leaves, propagate
+     DL and BL labels to the fixpoint;
+  2. insert 100,000 R-MAT edges, one edge per request (validate, append, seed, propagate);
+  3. answer 1,000,000 queries (about half reachable) in one batch: label rules, then the
+     label-pruned BFS for the pairs the labels leave open.
+
+`value` = (inserted edges + answered queries) per second of whole steps. The line also carries
+the per-phase rates, the p50/p99 latency of single insertions, the roofline of the dominant
+kernel (its launches timed with HIP events inside the timed region) and the CPU oracle timed on
+a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "inserted edges/s (label update) + reachability queries/s; p99 latency; HBM GB/s"
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic bytes per unit of work (the bytes the method must move, not what caches move).
+# Query decided by labels: the pair (8 B), the 32-byte label records of u and v, the answer byte.
+QUERY_LABEL_BYTES = 8 + 32 + 32 + 1
+# Propagation: per relaxed edge the 4-byte neighbour id and a 16-byte read-modify-write of the
+# neighbour's direction label; per expanded frontier entry its id (4 B), row offset and degree
+# (12 B) and its own 16-byte label.
+RELAX_BYTES = 4 + 16
+EXPAND_BYTES = 4 + 12 + 16
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    p = os.path.join(ROOT, "paper_2101_09441_amd", "csrc", "dbl_kernels.hip")
+    with open(p, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def committed_traffic(kernel):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on the
+    kernel source as it is now (else None)."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        with open(p) as f:
+            d = json.load(f)
+        e = d.get(kernel)
+        if not e or e.get("kernel_source_sha256_16") != kernel_source_hash():
+            return None
+        return e.get("bytes_per_launch")
+    except (OSError, ValueError):
+        return None
+
+
+def cpu_baseline(w, n_ins_sample, n_q_sample):
+    """Time the oracle on the host: full build, a prefix of the insertions, a prefix of the
+    queries; scale each phase to the step's counts."""
+    import oracle
+
+    threads = max(1, min(16, os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    o = oracle.OracleIndex(w.n, w.src, w.dst)
+    o.build(k=64, kp=64, threads=threads)
+    t_build = time.perf_counter() - t0
+    log(f"cpu oracle build {t_build:.1f}s ({threads} threads)")
+    t0 = time.perf_counter()
+    o.insert(w.ins_src[:n_ins_sample], w.ins_dst[:n_ins_sample])
+    t_ins = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    o.query_dbl(w.q_u[:n_q_sample], w.q_v[:n_q_sample], threads=threads)
+    t_q = time.perf_counter() - t0
+    o.close()
+    n_ins, n_q = len(w.ins_src), len(w.q_u)
+    t_step = t_build + t_ins * n_ins / n_ins_sample + t_q * n_q / n_q_sample
+    return {
+        "value": (n_ins + n_q) / t_step,
+        "unit": "ops/s (inserted edges + answered queries)",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": (f"oracle build of the full graph ({t_build:.1f} s, {threads} threads), first "
+                   f"{n_ins_sample} insertions one at a time ({t_ins * 1e3:.1f} ms, 1 thread), "
+                   f"first {n_q_sample} queries ({t_q * 1e3:.1f} ms, {threads} threads); each phase "
+                   f"scaled to the step's {n_ins} insertions and {n_q} queries"),
+        "step_s_extrapolated": t_step,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=["lj", "tiny"], default="lj")
+    ap.add_argument("--cpu-baseline", choices=["on", "off"], default="on")
+    ap.add_argument("--time-kernels", default="insert_small,query_label,query_bfs,round:8",
+                    help="kernel kinds timed with HIP events during the timed steps "
+                         "(':N' times one launch in N)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this path "
+              "runs on a single MI355X)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import dblgen
+    import paper_2101_09441_amd as dbl
+
+    torch.cuda.init()
+    dev = torch.device("cuda:0")
+    if args.workload == "lj":
+        w = dblgen.cached("rmat22-lj-s1", dblgen.lj_workload)
+        desc = ("R-MAT (a,b,c,d)=(0.57,0.19,0.19,0.05), 2^22 vertices, 68,993,773 unique edges, "
+                "100,000 R-MAT insertions one per request, 1,000,000 queries (35% random-walk "
+                "endpoints, 65% uniform) in one batch, 64 DL + 64 BL bits")
+    else:
+        w = dblgen.cached("rmat14-tiny-s1", dblgen.tiny_workload)
+        desc = ("R-MAT 2^14 vertices, 8n draws, 1,000 uniform insertions one per request, "
+                "10,000 uniform queries, 64 DL + 64 BL bits")
+    log(f"workload {w.name}: n={w.n} m={w.m} insertions={len(w.ins_src)} queries={len(w.q_u)}")
+    src, dst = dbl.to_device_ids(w.src), dbl.to_device_ids(w.dst)
+    isrc, idst = dbl.to_device_ids(w.ins_src), dbl.to_device_ids(w.ins_dst)
+    qu, qv = dbl.to_device_ids(w.q_u), dbl.to_device_ids(w.q_v)
+    out = torch.empty(len(w.q_u), dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+
+    def step(timed):
+        r = {}
+        t0 = time.perf_counter()
+        ix = dbl.Index.build(w.n, src, dst, edges_unique=True)
+        t1 = time.perf_counter()
+        if timed and args.time_kernels:
+            ix.time_kernels(args.time_kernels)
+        lat = ix.insert_edges_each(isrc, idst, latencies=True)
+        t2 = time.perf_counter()
+        ix.query(qu, qv, out=out)
+        t3 = time.perf_counter()
+        r.update(build_s=t1 - t0, insert_s=t2 - t1, query_s=t3 - t2, lat=lat)
+        if timed:
+            r["ktimes"] = ix.kernel_times()
+        ix.close()
+        return r
+
+    def diagnostics():
+        """Untimed pass over the same inputs: counters after each phase."""
+        ix = dbl.Index.build(w.n, src, dst, edges_unique=True)
+        s_build = ix.stats()
+        ix.insert_edges_each(isrc, idst)
+        s_ins = ix.stats()
+        ix.query(qu, qv, out=out)
+        s_q = ix.stats()
+        ix.close()
+        return s_build, s_ins, s_q
+
+    for i in range(args.warmup):
+        r = step(False)
+        log(f"warmup {i}: build {r['build_s']*1e3:.1f} ms, inserts {r['insert_s']:.2f} s, "
+            f"queries {r['query_s']*1e3:.1f} ms")
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    results = []
+    for i in range(args.steps):
+        r = step(True)
+        results.append(r)
+        log(f"step {i}: build {r['build_s']*1e3:.1f} ms, inserts {r['insert_s']:.2f} s, "
+            f"queries {r['query_s']*1e3:.1f} ms")
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    ms_per_step = t_total / args.steps * 1e3
+    n_ins, n_q = len(w.ins_src), len(w.q_u)
+    value = (n_ins + n_q) / (ms_per_step / 1e3)
+
+    lat = np.concatenate([r["lat"] for r in results])
+    build_s = float(np.mean([r["build_s"] for r in results]))
+    insert_s = float(np.mean([r["insert_s"] for r in results]))
+    query_s = float(np.mean([r["query_s"] for r in results]))
+    s_build, s_ins, s_q = diagnostics()
+    ins_expanded = s_ins["vertices_expanded"] - s_build["vertices_expanded"]
+    ins_relaxed = s_ins["edges_relaxed"] - s_build["edges_relaxed"]
+    answers = out.cpu().numpy()
+    classes = np.bincount(answers >> 1, minlength=7)
+
+    # kernel times accumulated over all timed steps
+    kt = {}
+    for r in results:
+        for k, v in r["ktimes"].items():
+            a = kt.setdefault(k, {"launches": 0, "total_ms": 0.0})
+            a["launches"] += v["launches"]
+            a["total_ms"] += v["total_ms"]
+    dominant = max(kt, key=lambda k: kt[k]["total_ms"]) if kt else None
+
+    roofline = None
+    if dominant:
+        d = kt[dominant]
+        avg_s = d["total_ms"] / d["launches"] / 1e3
+        if dominant == "query_label":
+            per_launch = QUERY_LABEL_BYTES * n_q
+        elif dominant == "insert_small":
+            # one edge per launch: the two appends and two seeds (ids 8 B, two degree RMWs 8 B,
+            # two row offsets and capacities 24 B, two column writes 8 B, labels read 32 B and
+            # OR-ed 32 B), plus the propagation the insertions triggered, averaged per launch
+            prop = ins_expanded * EXPAND_BYTES + ins_relaxed * RELAX_BYTES
+            per_launch = 8 + 8 + 24 + 8 + 32 + 32 + prop / n_ins
+        elif dominant == "round":
+            prop = (s_build["vertices_expanded"] * EXPAND_BYTES
+                    + s_build["edges_relaxed"] * RELAX_BYTES)
+            per_launch = prop / max(s_build["build_rounds"], 1)
+        else:  # query_bfs: per scanned edge 4 B id + 24 B of labels + the visited word
+            per_launch = (s_q["bfs_edges"] - s_ins["bfs_edges"]) * (4 + 24 + 8) + \
+                (s_q["bfs_vertices"] - s_ins["bfs_vertices"]) * 16
+        achieved = per_launch / avg_s / 1e9
+        traffic = committed_traffic(dominant)
+        roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dominant,
+                    "avg_launch_us": avg_s * 1e6, "launches": d["launches"],
+                    "algorithmic_bytes_per_launch": per_launch}
+
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "ops/s (inserted edges + answered queries)",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": desc, "n": w.n, "m": w.m, "insertions": n_ins,
+                   "insertion_form": "one edge per request", "queries": n_q,
+                   "query_batch": n_q, "landmarks": 64, "bl_bits": 64},
+        "build_ms": build_s * 1e3,
+        "insert_edges_per_s": n_ins / insert_s,
+        "insert_latency_us": {"p50": float(np.percentile(lat, 50)),
+                              "p99": float(np.percentile(lat, 99)),
+                              "max": float(lat.max())},
+        "queries_per_s": n_q / query_s,
+        "query_batch_ms": query_s * 1e3,
+        "label_decided_frac": float(classes[:5].sum() / max(n_q, 1)),
+        "reachable_frac": float((answers & 1).mean()),
+        "class_histogram": {dbl.CLASS_NAMES[i]: int(classes[i]) for i in range(7)},
+        "kernel_times_ms": {k: {"launches": v["launches"], "avg_us": v["total_ms"] / v["launches"]
+                                * 1e3} for k, v in kt.items()},
+        "propagation": {"build_rounds": s_build["build_rounds"],
+                        "build_edges_relaxed": s_build["edges_relaxed"],
+                        "build_vertices_expanded": s_build["vertices_expanded"],
+                        "insert_edges_relaxed": ins_relaxed,
+                        "insert_vertices_expanded": ins_expanded,
+                        "csr_regrows": s_ins["csr_regrows"],
+                        "bfs_edges": s_q["bfs_edges"], "bfs_vertices": s_q["bfs_vertices"]},
+        "roofline": roofline,
+        "cpu_baseline": None,
+    }
+    if args.cpu_baseline == "on":
+        n_ins_s = min(n_ins, 10000)
+        n_q_s = min(n_q, 100000)
+        line["cpu_baseline"] = cpu_baseline(w, n_ins_s, n_q_s)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -211,6 +211,29 @@ def make_rmat_workload(name: str, scale: int, seed: int, *, draws: int = 0, m_ta
     return Workload(name, n, src, dst, isrc, idst, qu, qv, n_draws)
 
 
+def cached(name: str, make, cache_dir: str = None) -> Workload:
+    """Return make() through an on-disk cache (uncompressed .npz keyed by `name`)."""
+    cache_dir = cache_dir or os.environ.get("DBLGEN_CACHE", "/tmp/dblgen_cache")
+    path = os.path.join(cache_dir, name + ".npz")
+    if os.path.exists(path):
+        try:
+            z = np.load(path, allow_pickle=False)
+            return Workload(str(z["name"]), int(z["n"]), z["src"], z["dst"], z["ins_src"],
+                            z["ins_dst"], z["q_u"], z["q_v"], int(z["draws"]))
+        except Exception:
+            pass
+    w = make()
+    try:
+        os.makedirs(cache_dir, exist_ok=True)
+        tmp = path + f".tmp{os.getpid()}.npz"
+        np.savez(tmp, name=w.name, n=w.n, src=w.src, dst=w.dst, ins_src=w.ins_src,
+                 ins_dst=w.ins_dst, q_u=w.q_u, q_v=w.q_v, draws=w.draws)
+        os.replace(tmp, path)
+    except OSError:
+        pass
+    return w
+
+
 def tiny_workload(seed: int = 1) -> Workload:
     """2^14 vertices, 8n draws, 1,000 uniform new edges, 10,000 uniform queries."""
     return make_rmat_workload("rmat14-tiny", 14, seed, draws=8 << 14, n_insert=1000,

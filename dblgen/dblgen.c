@@ -75,10 +75,17 @@ static uint64_t mix64(uint64_t z) {
   return z ^ (z >> 31);
 }
 
+/* zeroed table, touched up front (pages are faulted in once, in order, not at random) */
+static uint64_t *table_alloc(uint64_t cap) {
+  uint64_t *p = (uint64_t *)malloc((size_t)cap * sizeof(uint64_t));
+  if (p) memset(p, 0, (size_t)cap * sizeof(uint64_t));
+  return p;
+}
+
 static int set_init(edge_set *s, uint64_t expected) {
   uint64_t cap = 1024;
-  while (cap < 2 * expected + 16) cap <<= 1;
-  s->slot = (uint64_t *)calloc(cap, sizeof(uint64_t));
+  while (cap < expected + expected / 3 + 16) cap <<= 1; /* load factor at most 3/4 */
+  s->slot = table_alloc(cap);
   s->mask = cap - 1;
   s->count = 0;
   return s->slot ? 0 : -1;
@@ -86,7 +93,7 @@ static int set_init(edge_set *s, uint64_t expected) {
 
 static int set_grow(edge_set *s) {
   uint64_t old_cap = s->mask + 1, cap = old_cap * 2;
-  uint64_t *ns = (uint64_t *)calloc(cap, sizeof(uint64_t));
+  uint64_t *ns = table_alloc(cap);
   if (!ns) return -1;
   for (uint64_t i = 0; i < old_cap; i++) {
     uint64_t k = s->slot[i];
@@ -103,7 +110,7 @@ static int set_grow(edge_set *s) {
 
 /* returns 1 if inserted (new), 0 if present, -1 on allocation failure */
 static int set_insert(edge_set *s, uint64_t key) {
-  if (2 * (s->count + 1) > s->mask + 1 && set_grow(s)) return -1;
+  if (4 * (s->count + 1) > 3 * (s->mask + 1) && set_grow(s)) return -1;
   uint64_t k = key + 1;
   uint64_t h = mix64(k) & s->mask;
   while (s->slot[h]) {
@@ -130,6 +137,7 @@ typedef struct {
   uint32_t scale, n;
   double a, b, c;
   xoshiro256 rng;
+  xoshiro256 rng_mark; /* generator state at the start of the current batch of draws */
   uint32_t *perm; /* raw id -> output id */
   edge_set set;   /* keys over output ids: (src << 32) | dst */
   uint64_t draws;
@@ -144,6 +152,7 @@ dblgen_rmat *dblgen_rmat_new(uint32_t scale, uint64_t seed, double a, double b, 
   g->n = 1u << scale;
   g->a = a; g->b = b; g->c = c;
   xo_seed(&g->rng, seed);
+  g->rng_mark = g->rng;
   g->perm = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)g->n);
   if (!g->perm || set_init(&g->set, expected_edges)) {
     free(g->perm); free(g->set.slot); free(g);
@@ -196,20 +205,41 @@ static void rmat_draw_raw(dblgen_rmat *g, uint32_t *src, uint32_t *dst) {
  */
 int64_t dblgen_rmat_next(dblgen_rmat *g, uint64_t max_unique, uint64_t max_draws, uint32_t *src,
                          uint32_t *dst) {
+  /* Draws are made in small batches so that the hash-set slots of a batch can be prefetched
+     before the keys are inserted one by one, in stream order. */
+  enum { B = 64 };
   uint64_t got = 0, drawn = 0;
+  uint64_t key[B];
   while (got < max_unique && (max_draws == 0 || drawn < max_draws)) {
-    uint32_t s, d;
-    rmat_draw_raw(g, &s, &d);
-    drawn++;
-    if (s == d) continue;
-    s = g->perm[s];
-    d = g->perm[d];
-    int r = set_insert(&g->set, ((uint64_t)s << 32) | d);
-    if (r < 0) return -1;
-    if (r == 0) continue;
-    src[got] = s;
-    dst[got] = d;
-    got++;
+    uint64_t nb = B;
+    if (max_draws && max_draws - drawn < nb) nb = max_draws - drawn;
+    for (uint64_t i = 0; i < nb; i++) {
+      uint32_t s, d;
+      rmat_draw_raw(g, &s, &d);
+      key[i] = s == d ? UINT64_MAX : (((uint64_t)g->perm[s] << 32) | g->perm[d]);
+      if (key[i] != UINT64_MAX) __builtin_prefetch(&g->set.slot[mix64(key[i] + 1) & g->set.mask]);
+    }
+    uint64_t i = 0;
+    for (; i < nb && got < max_unique; i++) {
+      if (key[i] == UINT64_MAX) continue;
+      int r = set_insert(&g->set, key[i]);
+      if (r < 0) return -1;
+      if (r == 0) continue;
+      src[got] = (uint32_t)(key[i] >> 32);
+      dst[got] = (uint32_t)key[i];
+      got++;
+    }
+    drawn += i;
+    if (i < nb) {
+      /* the unique target was reached inside the batch: rewind the stream so that the draws
+         after the last one consumed are drawn again by the next call */
+      g->rng = g->rng_mark;
+      g->draws += drawn;
+      for (uint64_t j = 0; j < i; j++) { uint32_t s, d; rmat_draw_raw(g, &s, &d); }
+      g->rng_mark = g->rng;
+      return (int64_t)got;
+    }
+    g->rng_mark = g->rng;
   }
   g->draws += drawn;
   return (int64_t)got;

@@ -123,6 +123,16 @@ dbl_status dbl_insert_edges(dbl_index *ix, uint64_t count, const uint32_t *d_src
                             const uint32_t *d_dst, void *stream);
 
 /*
+ * The one-request-at-a-time form of dbl_insert_edges: edge i is inserted as its own request
+ * (validate, append, seed, propagate to the fixpoint, report), in order, exactly as `count`
+ * calls of dbl_insert_edges with one edge each. h_latency_us: optional HOST array [count] that
+ * receives each request's wall time in microseconds. Stops at the first failing request and
+ * returns its status (earlier requests stay applied).
+ */
+dbl_status dbl_insert_edges_each(dbl_index *ix, uint64_t count, const uint32_t *d_src,
+                                 const uint32_t *d_dst, float *h_latency_us, void *stream);
+
+/*
  * Answer q(d_u[i], d_v[i]) for i < count (Algorithm 2 with Theorems 1 and 2).
  *   d_out: device array [count]; d_out[i] = answer | (dbl_class << 1), answer 1 = u reaches v.
  * Answers are exact reachability on the current graph. Errors: VERTEX_RANGE if any id >= n
@@ -144,6 +154,26 @@ dbl_status dbl_get_leaves(const dbl_index *ix, uint8_t *h_flags, uint8_t *h_buck
 
 /* Counters since build (host struct). */
 dbl_status dbl_get_stats(const dbl_index *ix, dbl_stats *out);
+
+/* Launch timing of the library's own kernels, measured with HIP events recorded on the
+   caller's stream around each launch of the selected kinds (for roofline measurements). */
+typedef struct {
+  char name[32];      /* kernel kind, e.g. "query_label", "query_bfs", "insert_small" */
+  uint64_t launches;  /* timed launches since timing was enabled */
+  double total_ms;    /* summed event-to-event time */
+  double max_ms;
+} dbl_kernel_time;
+
+/* Enable timing for a comma-separated list of kernel kinds ("all" = every kind; NULL or "" =
+   off), optionally followed by ":N" to time one launch in every N of each kind (the first, the
+   N+1-th, ...). Enabling clears the accumulated times. Kinds: insert_small, insert_apply, local_rounds,
+   round (one grid propagation round), query_label, query_bfs. */
+dbl_status dbl_time_kernels(dbl_index *ix, const char *kinds);
+
+/* Copy up to `cap` per-kind records (kinds with at least one launch) to HOST array h_out;
+   *count receives the number written. Waits for outstanding timed launches. */
+dbl_status dbl_read_kernel_times(dbl_index *ix, dbl_kernel_time *h_out, uint32_t cap,
+                                 uint32_t *count);
 
 /* Vertex count of the index. */
 uint32_t dbl_num_vertices(const dbl_index *ix);

@@ -20,9 +20,11 @@ CLASS_NAMES = ["self", "dl_hit", "bl_miss", "thm1", "thm2", "bfs_true", "bfs_fal
 
 # every symbol declared in include/dbl.h
 EXPORTS = [
-    "dbl_default_options", "dbl_build", "dbl_insert_edges", "dbl_query_batch",
+    "dbl_default_options", "dbl_build", "dbl_insert_edges", "dbl_insert_edges_each",
+    "dbl_query_batch",
     "dbl_read_labels", "dbl_get_landmarks", "dbl_get_leaves", "dbl_get_stats",
-    "dbl_num_vertices", "dbl_destroy", "dbl_status_str",
+    "dbl_time_kernels", "dbl_read_kernel_times", "dbl_num_vertices", "dbl_destroy",
+    "dbl_status_str",
 ]
 
 
@@ -58,6 +60,15 @@ class DblStats(ctypes.Structure):
     ]
 
 
+class DblKernelTime(ctypes.Structure):
+    _fields_ = [
+        ("name", ctypes.c_char * 32),
+        ("launches", ctypes.c_uint64),
+        ("total_ms", ctypes.c_double),
+        ("max_ms", ctypes.c_double),
+    ]
+
+
 class DblError(RuntimeError):
     def __init__(self, status: int, what: str):
         self.status = status
@@ -84,6 +95,8 @@ def load_library():
     lib.dbl_build.restype = i32
     lib.dbl_insert_edges.argtypes = [P, u64, P, P, P]
     lib.dbl_insert_edges.restype = i32
+    lib.dbl_insert_edges_each.argtypes = [P, u64, P, P, P, P]
+    lib.dbl_insert_edges_each.restype = i32
     lib.dbl_query_batch.argtypes = [P, u64, P, P, P, P]
     lib.dbl_query_batch.restype = i32
     lib.dbl_read_labels.argtypes = [P, P, P, P, P, P]
@@ -94,6 +107,11 @@ def load_library():
     lib.dbl_get_leaves.restype = i32
     lib.dbl_get_stats.argtypes = [P, ctypes.POINTER(DblStats)]
     lib.dbl_get_stats.restype = i32
+    lib.dbl_time_kernels.argtypes = [P, ctypes.c_char_p]
+    lib.dbl_time_kernels.restype = i32
+    lib.dbl_read_kernel_times.argtypes = [P, ctypes.POINTER(DblKernelTime), u32,
+                                          ctypes.POINTER(u32)]
+    lib.dbl_read_kernel_times.restype = i32
     lib.dbl_num_vertices.argtypes = [P]
     lib.dbl_num_vertices.restype = u32
     lib.dbl_destroy.argtypes = [P]
@@ -219,6 +237,20 @@ class Index:
                                                  dst.data_ptr(), _stream_ptr(stream))
         _check(st, "dbl_insert_edges")
 
+    def insert_edges_each(self, src: torch.Tensor, dst: torch.Tensor, latencies: bool = False,
+                          stream=None):
+        """Insert the edges one request at a time; optionally return per-request wall times (us)."""
+        src, dst = _ids(src, "src"), _ids(dst, "dst")
+        if src.numel() != dst.numel():
+            raise ValueError("src and dst differ in length")
+        lat = np.zeros(max(src.numel(), 1), dtype=np.float32) if latencies else None
+        with torch.cuda.device(self.device):
+            st = load_library().dbl_insert_edges_each(
+                self._handle(), src.numel(), src.data_ptr(), dst.data_ptr(),
+                None if lat is None else lat.ctypes.data, _stream_ptr(stream))
+        _check(st, "dbl_insert_edges_each")
+        return None if lat is None else lat[:src.numel()]
+
     def query(self, u: torch.Tensor, v: torch.Tensor, out: Optional[torch.Tensor] = None,
               stream=None) -> torch.Tensor:
         """Answer bytes: bit 0 = u reaches v, bits 1-3 = decision class."""
@@ -262,6 +294,25 @@ class Index:
             _check(load_library().dbl_get_leaves(self._handle(), flags.ctypes.data,
                                                  bucket.ctypes.data), "dbl_get_leaves")
         return flags, bucket
+
+    def time_kernels(self, kinds: Optional[str]) -> None:
+        """Time launches of the given kernel kinds with HIP events ("all", a comma list, None)."""
+        _check(load_library().dbl_time_kernels(self._handle(), kinds.encode() if kinds else None),
+               "dbl_time_kernels")
+
+    def kernel_times(self) -> dict:
+        """{kind: {"launches", "total_ms", "avg_ms", "max_ms"}} for timed kinds."""
+        buf = (DblKernelTime * 16)()
+        cnt = ctypes.c_uint32()
+        with torch.cuda.device(self.device):
+            _check(load_library().dbl_read_kernel_times(self._handle(), buf, 16, ctypes.byref(cnt)),
+                   "dbl_read_kernel_times")
+        out = {}
+        for i in range(cnt.value):
+            r = buf[i]
+            out[r.name.decode()] = {"launches": int(r.launches), "total_ms": r.total_ms,
+                                    "avg_ms": r.total_ms / max(r.launches, 1), "max_ms": r.max_ms}
+        return out
 
     def stats(self) -> dict:
         s = DblStats()

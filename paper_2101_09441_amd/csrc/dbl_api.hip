@@ -6,7 +6,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "dbl.h"
@@ -30,7 +32,12 @@ struct dbl_index {
   u64 *heavy_list = nullptr;
   uint64_t heavy_cap = 0;
   Ctl *ctl = nullptr;
-  Ctl *h_ctl = nullptr;  // pinned host copy
+  dbl::Mirror *mirror = nullptr;  // pinned, device-mapped host memory written by the device
+  dbl::Mirror hs{};               // host copy of the last published status
+  uint32_t seq = 0;
+  u64 *pcnt = nullptr;     // per-block propagation counters
+  u64 *qcls = nullptr;     // per-block query class counters
+  u64 *bfs_cnt = nullptr;  // per-slot BFS counters
   Ovf *ovf = nullptr;
   uint64_t ovf_cap = 0;
   uint32_t *landmarks_d = nullptr;
@@ -48,9 +55,86 @@ struct dbl_index {
   u64 *gvis = nullptr;
   // statistics kept on the host
   uint64_t build_rounds = 0, insert_calls = 0, insert_rounds = 0, regrows = 0, bfs_heavy = 0;
+  // kernel timing (HIP events around selected launches)
+  uint32_t time_mask = 0;
+  struct Pending {
+    uint32_t kind;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> spare;
+  uint32_t time_period = 1;  // time one launch in every `time_period` of a selected kind
+  uint64_t t_seen[16] = {};
+  uint64_t t_launches[16] = {};
+  double t_total[16] = {}, t_max[16] = {};
 };
 
 namespace {
+
+enum TimedKind : uint32_t {
+  kTInsertSmall = 0,
+  kTInsertApply,
+  kTLocalRounds,
+  kTRound,
+  kTQueryLabel,
+  kTQueryBfs,
+  kTKinds
+};
+const char *const kKindNames[kTKinds] = {"insert_small", "insert_apply", "local_rounds", "round",
+                                         "query_label", "query_bfs"};
+
+hipEvent_t take_event(dbl_index *ix) {
+  if (!ix->spare.empty()) {
+    hipEvent_t e = ix->spare.back();
+    ix->spare.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets one launch with events when its kind is selected; otherwise does nothing.
+struct Timed {
+  dbl_index *ix;
+  uint32_t kind;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  Timed(dbl_index *ix_, uint32_t kind_, hipStream_t s_) : ix(ix_), kind(kind_), s(s_) {
+    if (!(ix->time_mask & (1u << kind))) return;
+    if (ix->t_seen[kind]++ % ix->time_period) return;
+    a = take_event(ix);
+    if (a && hipEventRecord(a, s) != hipSuccess) {
+      ix->spare.push_back(a);
+      a = nullptr;
+    }
+  }
+  ~Timed() {
+    if (!a) return;
+    hipEvent_t b = take_event(ix);
+    if (b && hipEventRecord(b, s) == hipSuccess) {
+      ix->pending.push_back({kind, a, b});
+    } else {
+      ix->spare.push_back(a);
+      if (b) ix->spare.push_back(b);
+    }
+  }
+};
+
+// Fold finished timed launches into the per-kind totals (the stream has been synchronised).
+void resolve_times(dbl_index *ix) {
+  for (const auto &p : ix->pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      ix->t_launches[p.kind]++;
+      ix->t_total[p.kind] += ms;
+      ix->t_max[p.kind] = std::max<double>(ix->t_max[p.kind], ms);
+    }
+    ix->spare.push_back(p.a);
+    ix->spare.push_back(p.b);
+  }
+  ix->pending.clear();
+}
 
 dbl_status from_hip(hipError_t e) {
   if (e == hipSuccess) return DBL_OK;
@@ -110,15 +194,46 @@ dbl::PropArgs prop_args(const dbl_index *ix) {
   a.inq = ix->inq;
   a.heavy_list = ix->heavy_list;
   a.heavy_cap = ix->heavy_cap;
+  a.pcnt = ix->pcnt;
   a.ctl = ix->ctl;
   return a;
 }
 
-// Copy the control block to the host and wait for the stream.
-dbl_status sync_ctl(dbl_index *ix, hipStream_t s) {
-  CK(hipMemcpyAsync(ix->h_ctl, ix->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
-  CK(hipStreamSynchronize(s));
+// Wait until the device has published status `seq` into the host mirror. The host spins on
+// the mirror; every few thousand polls it asks the stream whether it failed or went idle
+// without publishing, so a fault can never leave the host spinning.
+dbl_status wait_status(dbl_index *ix, hipStream_t s, uint32_t seq) {
+  volatile dbl::Mirror *m = ix->mirror;
+  for (uint64_t spin = 1;; spin++) {
+    if (__atomic_load_n(&ix->mirror->seq, __ATOMIC_ACQUIRE) == seq) break;
+    if ((spin & 4095) == 0) {
+      const hipError_t q = hipStreamQuery(s);
+      if (q == hipSuccess) {
+        if (__atomic_load_n(&ix->mirror->seq, __ATOMIC_ACQUIRE) == seq) break;
+        return DBL_ERR_DEVICE;  // the stream drained without publishing
+      }
+      if (q != hipErrorNotReady) return from_hip(q);
+    }
+  }
+  dbl::Mirror &h = ix->hs;
+  h.seq = seq;
+  h.err = m->err;
+  h.cur = m->cur;
+  h.stamp = m->stamp;
+  for (int i = 0; i < 3; i++) h.fsize[i] = m->fsize[i];
+  h.ovf_count = m->ovf_count;
+  h.und_count = m->und_count;
+  h.bfs_heavy = m->bfs_heavy;
+  h.found = m->found;
+  if (!ix->pending.empty()) resolve_times(ix);
   return DBL_OK;
+}
+
+// Publish the control block after the work queued so far and wait for it.
+dbl_status sync_ctl(dbl_index *ix, hipStream_t s) {
+  const uint32_t seq = ++ix->seq;
+  CK(dbl::launch_publish(ix->ctl, ix->mirror, seq, s));
+  return wait_status(ix, s, seq);
 }
 
 // Write one 32-bit field of the device control block (host value, stream ordered).
@@ -138,13 +253,16 @@ dbl_status ensure_heavy_cap(dbl_index *ix) {
 
 // Grid rounds until the pending frontier is empty. `group` rounds are enqueued between reads of
 // the control block; a round that finds an empty frontier does nothing.
-dbl_status grid_propagate(dbl_index *ix, hipStream_t s, uint32_t group, uint64_t *rounds) {
+// `fresh`: ix->hs already holds the status after the last queued work.
+dbl_status grid_propagate(dbl_index *ix, hipStream_t s, uint32_t group, uint64_t *rounds,
+                          bool fresh) {
   for (;;) {
-    CKS(sync_ctl(ix, s));
-    const uint32_t cur = ix->h_ctl->cur;
-    const uint32_t fsz = ix->h_ctl->fsize[cur];
+    if (!fresh) CKS(sync_ctl(ix, s));
+    fresh = false;
+    const uint32_t cur = ix->hs.cur;
+    const uint32_t fsz = ix->hs.fsize[cur];
     if (fsz == 0) return DBL_OK;
-    uint32_t stamp = ix->h_ctl->stamp;
+    uint32_t stamp = ix->hs.stamp;
     if (stamp > 0xF0000000u) {
       // restart the stamp sequence before it wraps; the pending frontier is already closed, so
       // only later frontiers use the cleared marks
@@ -156,6 +274,7 @@ dbl_status grid_propagate(dbl_index *ix, hipStream_t s, uint32_t group, uint64_t
     uint32_t ring = cur;
     uint32_t grid = (uint32_t)std::min<uint64_t>(2048, std::max<uint64_t>(64, (fsz + 255) / 256));
     for (uint32_t g = 0; g < group; g++) {
+      Timed tm(ix, kTRound, s);
       CK(dbl::launch_round(a, ring, stamp, grid, s));
       ring = ring == 2 ? 0 : ring + 1;
       stamp++;
@@ -194,10 +313,10 @@ dbl_status regrow(dbl_index *ix, uint32_t dir, uint32_t novf, hipStream_t s) {
   return ensure_heavy_cap(ix);
 }
 
-// After appends: regrow rows that ran out of slack, then finish propagation.
+// After the appends (ix->hs holds the status they published): regrow rows that ran out of
+// slack, then finish propagation.
 dbl_status finish_insert(dbl_index *ix, hipStream_t s, uint64_t *rounds) {
-  CKS(sync_ctl(ix, s));
-  uint32_t novf = ix->h_ctl->ovf_count;
+  const uint32_t novf = ix->hs.ovf_count;
   if (novf) {
     if (novf > ix->ovf_cap) return DBL_ERR_DEVICE;  // cannot happen: capacity is 2 per edge
     // which directions overflowed
@@ -211,9 +330,11 @@ dbl_status finish_insert(dbl_index *ix, hipStream_t s, uint64_t *rounds) {
     dbl::PropArgs a = prop_args(ix);
     CK(dbl::launch_push_overflow(a, ix->ovf, novf, s));
     CKS(set_ctl_u32(ix, offsetof(Ctl, ovf_count), 0u, s));
-    CK(dbl::launch_local_rounds(a, s));
+    const uint32_t seq = ++ix->seq;
+    CK(dbl::launch_local_rounds(a, ix->mirror, seq, s));
+    CKS(wait_status(ix, s, seq));
   }
-  return grid_propagate(ix, s, 2, rounds);
+  return grid_propagate(ix, s, 2, rounds, true);
 }
 
 uint32_t bits_of(uint32_t kp) {
@@ -239,8 +360,10 @@ dbl_status ensure_query_scratch(dbl_index *ix, uint64_t count) {
                                        : (uint32_t)std::min<uint64_t>(ix->n, 1u << 18);
     CKS(dalloc(&ix->vis, words * slots));
     CKS(dalloc(&ix->bfs_queue, (uint64_t)qcap * slots));
+    CKS(dalloc(&ix->bfs_cnt, (uint64_t)slots * dbl::kBfsCtrStride));
     hipStream_t s0 = nullptr;
     CK(dbl::launch_fill_u64(ix->vis, 0ull, words * slots, s0));
+    CK(dbl::launch_fill_u64(ix->bfs_cnt, 0ull, (uint64_t)slots * dbl::kBfsCtrStride, s0));
     CK(hipStreamSynchronize(s0));
     ix->slots = slots;
     ix->vis_words = words;
@@ -253,7 +376,13 @@ dbl_status do_build(dbl_index *ix, uint64_t m, const uint32_t *src, const uint32
                     const dbl_options &o, hipStream_t s) {
   const uint32_t n = ix->n;
   CKS(dalloc(&ix->ctl, 1));
-  CK(hipHostMalloc((void **)&ix->h_ctl, sizeof(Ctl), hipHostMallocDefault));
+  CK(hipHostMalloc((void **)&ix->mirror, sizeof(dbl::Mirror),
+                   hipHostMallocMapped | hipHostMallocCoherent));
+  memset((void *)ix->mirror, 0, sizeof(dbl::Mirror));
+  CKS(dalloc(&ix->pcnt, 2ull * dbl::kPropCtrSlots));
+  CKS(dalloc(&ix->qcls, (uint64_t)dbl::kQueryGrid * dbl::kQClsStride));
+  CK(dbl::launch_fill_u64(ix->pcnt, 0ull, 2ull * dbl::kPropCtrSlots, s));
+  CK(dbl::launch_fill_u64(ix->qcls, 0ull, (uint64_t)dbl::kQueryGrid * dbl::kQClsStride, s));
   {
     Ctl init;
     memset(&init, 0, sizeof(init));
@@ -265,7 +394,7 @@ dbl_status do_build(dbl_index *ix, uint64_t m, const uint32_t *src, const uint32
   // ---- a1: validate, de-duplicate, count degrees, reserve slack, scatter into both CSRs
   CK(dbl::launch_validate_pairs(src, dst, m, n, ix->ctl, s));
   CKS(sync_ctl(ix, s));
-  if (ix->h_ctl->err) return DBL_ERR_VERTEX_RANGE;
+  if (ix->hs.err) return DBL_ERR_VERTEX_RANGE;
   uint8_t *keep = nullptr;
   u64 *table = nullptr;
   CKS(dalloc(&keep, m));
@@ -367,7 +496,7 @@ dbl_status do_build(dbl_index *ix, uint64_t m, const uint32_t *src, const uint32
   CKS(ensure_heavy_cap(ix));
   CK(dbl::launch_init_frontier({ix->lab}, n, ix->f, ix->r, ix->fq[0], ix->ctl, ix->inq, 1u, s));
   uint64_t rounds = 0;
-  CKS(grid_propagate(ix, s, 4, &rounds));
+  CKS(grid_propagate(ix, s, 4, &rounds, false));
   ix->build_rounds = rounds;
   return DBL_OK;
 }
@@ -457,15 +586,22 @@ dbl_status dbl_insert_edges(dbl_index *ix, uint64_t count, const uint32_t *d_src
     ix->ovf_cap = cap;
   }
   dbl::PropArgs a = prop_args(ix);
+  const uint32_t seq = ++ix->seq;
   if (count <= dbl::kSmallBatch) {
-    CK(dbl::launch_insert_small(a, d_src, d_dst, (uint32_t)count, ix->n, ix->ovf, ix->ovf_cap, s));
+    Timed tm(ix, kTInsertSmall, s);
+    CK(dbl::launch_insert_small(a, d_src, d_dst, (uint32_t)count, ix->n, ix->ovf, ix->ovf_cap,
+                                ix->mirror, seq, s));
   } else {
     CK(dbl::launch_validate_pairs(d_src, d_dst, count, ix->n, ix->ctl, s));
-    CK(dbl::launch_insert_apply(a, d_src, d_dst, count, ix->ovf, ix->ovf_cap, s));
-    CK(dbl::launch_local_rounds(a, s));
+    {
+      Timed tm(ix, kTInsertApply, s);
+      CK(dbl::launch_insert_apply(a, d_src, d_dst, count, ix->ovf, ix->ovf_cap, s));
+    }
+    Timed tm(ix, kTLocalRounds, s);
+    CK(dbl::launch_local_rounds(a, ix->mirror, seq, s));
   }
-  CKS(sync_ctl(ix, s));
-  if (ix->h_ctl->err) {
+  CKS(wait_status(ix, s, seq));
+  if (ix->hs.err) {
     CKS(set_ctl_u32(ix, offsetof(Ctl, err), 0u, s));
     CK(hipStreamSynchronize(s));
     return DBL_ERR_VERTEX_RANGE;
@@ -477,6 +613,22 @@ dbl_status dbl_insert_edges(dbl_index *ix, uint64_t count, const uint32_t *d_src
   return st;
 }
 
+dbl_status dbl_insert_edges_each(dbl_index *ix, uint64_t count, const uint32_t *d_src,
+                                 const uint32_t *d_dst, float *h_latency_us, void *stream) {
+  if (!ix) return DBL_ERR_INVALID_ARG;
+  if (count == 0) return DBL_OK;
+  if (!d_src || !d_dst) return DBL_ERR_INVALID_ARG;
+  for (uint64_t i = 0; i < count; i++) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const dbl_status st = dbl_insert_edges(ix, 1, d_src + i, d_dst + i, stream);
+    if (h_latency_us)
+      h_latency_us[i] = std::chrono::duration<float, std::micro>(
+                            std::chrono::steady_clock::now() - t0).count();
+    if (st != DBL_OK) return st;
+  }
+  return DBL_OK;
+}
+
 dbl_status dbl_query_batch(dbl_index *ix, uint64_t count, const uint32_t *d_u,
                            const uint32_t *d_v, uint8_t *d_out, void *stream) {
   if (!ix) return DBL_ERR_INVALID_ARG;
@@ -486,7 +638,11 @@ dbl_status dbl_query_batch(dbl_index *ix, uint64_t count, const uint32_t *d_u,
   hipStream_t s = (hipStream_t)stream;
   CKS(ensure_query_scratch(ix, count));
   CK(dbl::launch_ctl_reset_query(ix->ctl, s));
-  CK(dbl::launch_query_label({ix->lab}, d_u, d_v, count, ix->n, d_out, ix->und, ix->ctl, s));
+  {
+    Timed tm(ix, kTQueryLabel, s);
+    CK(dbl::launch_query_label({ix->lab}, d_u, d_v, count, ix->n, d_out, ix->und, ix->ctl,
+                               ix->qcls, s));
+  }
   dbl::BfsArgs b;
   b.L.lab = ix->lab;
   b.f = ix->f;
@@ -499,15 +655,19 @@ dbl_status dbl_query_batch(dbl_index *ix, uint64_t count, const uint32_t *d_u,
   b.queue = ix->bfs_queue;
   b.qcap = ix->qcap;
   b.heavy_q = ix->heavy_q;
+  b.cnt = ix->bfs_cnt;
   b.ctl = ix->ctl;
-  CK(dbl::launch_query_bfs(b, ix->slots, s));
+  {
+    Timed tm(ix, kTQueryBfs, s);
+    CK(dbl::launch_query_bfs(b, ix->slots, s));
+  }
   CKS(sync_ctl(ix, s));
-  if (ix->h_ctl->err) {
+  if (ix->hs.err) {
     CKS(set_ctl_u32(ix, offsetof(Ctl, err), 0u, s));
     CK(hipStreamSynchronize(s));
     return DBL_ERR_VERTEX_RANGE;
   }
-  const uint32_t nheavy = ix->h_ctl->bfs_heavy;
+  const uint32_t nheavy = ix->hs.bfs_heavy;
   if (nheavy) {
     std::vector<uint32_t> hq(nheavy), hu(nheavy), hv(nheavy);
     CK(hipMemcpyAsync(hq.data(), ix->heavy_q, sizeof(uint32_t) * nheavy, hipMemcpyDeviceToHost, s));
@@ -525,9 +685,9 @@ dbl_status dbl_query_batch(dbl_index *ix, uint64_t count, const uint32_t *d_u,
         CK(dbl::launch_gbfs_round(a, ix->gvis, u, v, ring, s));
         ring = ring == 2 ? 0 : ring + 1;
         CKS(sync_ctl(ix, s));
-        if (ix->h_ctl->found || ix->h_ctl->fsize[ring] == 0) break;
+        if (ix->hs.found || ix->hs.fsize[ring] == 0) break;
       }
-      CK(dbl::launch_gbfs_finish(a, hq[i], d_out, s));
+      CK(dbl::launch_gbfs_finish(a, hq[i], d_out, ix->qcls, s));
     }
     // the propagation frontier was borrowed: it is empty again, keep its ring position
     CK(hipStreamSynchronize(s));
@@ -565,8 +725,14 @@ dbl_status dbl_get_leaves(const dbl_index *ix, uint8_t *h_flags, uint8_t *h_buck
 dbl_status dbl_get_stats(const dbl_index *ix, dbl_stats *out) {
   if (!ix || !out) return DBL_ERR_INVALID_ARG;
   DeviceGuard dg(ix->device);
-  Ctl c;
-  CK(hipMemcpy(&c, ix->ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+  std::vector<u64> pc(2ull * dbl::kPropCtrSlots), qc((uint64_t)dbl::kQueryGrid * dbl::kQClsStride);
+  CK(hipMemcpy(pc.data(), ix->pcnt, sizeof(u64) * pc.size(), hipMemcpyDeviceToHost));
+  CK(hipMemcpy(qc.data(), ix->qcls, sizeof(u64) * qc.size(), hipMemcpyDeviceToHost));
+  std::vector<u64> bc;
+  if (ix->bfs_cnt) {
+    bc.resize((uint64_t)ix->slots * dbl::kBfsCtrStride);
+    CK(hipMemcpy(bc.data(), ix->bfs_cnt, sizeof(u64) * bc.size(), hipMemcpyDeviceToHost));
+  }
   uint64_t stored = 0;
   {
     std::vector<uint32_t> deg(ix->n);
@@ -577,19 +743,82 @@ dbl_status dbl_get_stats(const dbl_index *ix, dbl_stats *out) {
   out->num_edges = stored;
   out->build_rounds = ix->build_rounds;
   out->insert_calls = ix->insert_calls;
-  out->insert_rounds = ix->insert_rounds + c.local_rounds;
-  out->vertices_expanded = c.ctr[dbl::kCtrExpanded];
-  out->edges_relaxed = c.ctr[dbl::kCtrRelaxed];
-  out->csr_regrows = ix->regrows;
-  uint64_t q = 0;
-  for (int i = 0; i < 7; i++) {
-    out->query_class[i] = c.ctr[dbl::kCtrClass0 + i];
-    q += out->query_class[i];
+  out->insert_rounds = ix->insert_rounds;
+  for (uint32_t b = 0; b < dbl::kPropCtrSlots; b++) {
+    out->vertices_expanded += pc[2 * b];
+    out->edges_relaxed += pc[2 * b + 1];
   }
-  out->queries = q;
-  out->bfs_vertices = c.ctr[dbl::kCtrBfsVert];
-  out->bfs_edges = c.ctr[dbl::kCtrBfsEdge];
+  out->csr_regrows = ix->regrows;
+  for (uint32_t b = 0; b < dbl::kQueryGrid; b++)
+    for (uint32_t c = 0; c < 7; c++) out->query_class[c] += qc[b * dbl::kQClsStride + c];
+  for (uint32_t sl = 0; sl < ix->slots; sl++) {
+    out->bfs_vertices += bc[sl * dbl::kBfsCtrStride + 0];
+    out->bfs_edges += bc[sl * dbl::kBfsCtrStride + 1];
+    out->query_class[5] += bc[sl * dbl::kBfsCtrStride + 2];
+    out->query_class[6] += bc[sl * dbl::kBfsCtrStride + 3];
+  }
+  for (uint32_t c = 0; c < 7; c++) out->queries += out->query_class[c];
   out->bfs_heavy = ix->bfs_heavy;
+  return DBL_OK;
+}
+
+dbl_status dbl_time_kernels(dbl_index *ix, const char *kinds) {
+  if (!ix) return DBL_ERR_INVALID_ARG;
+  uint32_t mask = 0, period = 1;
+  if (kinds && *kinds) {
+    std::string all(kinds);
+    const size_t colon = all.find(':');
+    if (colon != std::string::npos) {
+      const long p = strtol(all.c_str() + colon + 1, nullptr, 10);
+      if (p < 1 || p > 1000000) return DBL_ERR_INVALID_ARG;
+      period = (uint32_t)p;
+      all.resize(colon);
+    }
+    size_t pos = 0;
+    while (pos <= all.size()) {
+      size_t end = all.find(',', pos);
+      if (end == std::string::npos) end = all.size();
+      const std::string tok = all.substr(pos, end - pos);
+      if (tok == "all") {
+        mask = (1u << kTKinds) - 1u;
+      } else if (!tok.empty()) {
+        uint32_t k = 0;
+        while (k < kTKinds && tok != kKindNames[k]) k++;
+        if (k == kTKinds) return DBL_ERR_INVALID_ARG;
+        mask |= 1u << k;
+      }
+      pos = end + 1;
+    }
+  }
+  DeviceGuard dg(ix->device);
+  resolve_times(ix);
+  ix->time_mask = mask;
+  ix->time_period = period;
+  for (uint32_t k = 0; k < kTKinds; k++) {
+    ix->t_seen[k] = 0;
+    ix->t_launches[k] = 0;
+    ix->t_total[k] = 0.0;
+    ix->t_max[k] = 0.0;
+  }
+  return DBL_OK;
+}
+
+dbl_status dbl_read_kernel_times(dbl_index *ix, dbl_kernel_time *h_out, uint32_t cap,
+                                 uint32_t *count) {
+  if (!ix || !count || (cap && !h_out)) return DBL_ERR_INVALID_ARG;
+  DeviceGuard dg(ix->device);
+  resolve_times(ix);
+  uint32_t w = 0;
+  for (uint32_t k = 0; k < kTKinds && w < cap; k++) {
+    if (!ix->t_launches[k]) continue;
+    dbl_kernel_time &o = h_out[w++];
+    memset(&o, 0, sizeof(o));
+    strncpy(o.name, kKindNames[k], sizeof(o.name) - 1);
+    o.launches = ix->t_launches[k];
+    o.total_ms = ix->t_total[k];
+    o.max_ms = ix->t_max[k];
+  }
+  *count = w;
   return DBL_OK;
 }
 
@@ -605,7 +834,10 @@ void dbl_destroy(dbl_index *ix) {
   dfree(ix->inq);
   dfree(ix->heavy_list);
   dfree(ix->ctl);
-  if (ix->h_ctl) (void)hipHostFree(ix->h_ctl);
+  if (ix->mirror) (void)hipHostFree((void *)ix->mirror);
+  dfree(ix->pcnt);
+  dfree(ix->qcls);
+  dfree(ix->bfs_cnt);
   dfree(ix->ovf);
   dfree(ix->landmarks_d);
   dfree(ix->leaf_flags);
@@ -617,6 +849,11 @@ void dbl_destroy(dbl_index *ix) {
   dfree(ix->vis);
   dfree(ix->bfs_queue);
   dfree(ix->gvis);
+  for (const auto &p : ix->pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  for (hipEvent_t e : ix->spare) (void)hipEventDestroy(e);
   delete ix;
 }
 

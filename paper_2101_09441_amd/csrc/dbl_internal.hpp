@@ -65,6 +65,26 @@ struct Ctl {
   unsigned long long ctr[kCtrCount];
 };
 
+// Status published by the device into pinned, device-mapped host memory at the end of a call's
+// work; the host waits for `seq` to change instead of copying the control block and
+// synchronising the stream.
+struct Mirror {
+  uint32_t seq;
+  uint32_t err, cur, stamp;
+  uint32_t fsize[3];
+  uint32_t ovf_count, und_count, bfs_heavy, found;
+  uint32_t pad[5];
+};
+
+// Per-block / per-slot statistics (plain read-modify-write by the owning block, no atomics).
+constexpr uint32_t kQueryGrid = 1024;  // blocks of the label kernel (grid-stride)
+constexpr uint32_t kQClsStride = 8;    // class counters per label-kernel block
+constexpr uint32_t kBfsCtrStride = 4;  // vertices, edges, true, false per BFS slot
+// propagation counters: grid rounds use slots [0, 2048), heavy chunks [2048, 3072), the
+// single-workgroup rounds slot 3072
+constexpr uint32_t kRoundGridMax = 2048, kHeavyGrid = 1024;
+constexpr uint32_t kPropCtrSlots = kRoundGridMax + kHeavyGrid + 1;
+
 // Overflowing append: row `x` (bit 31 = reverse CSR) wanted entry `y` at position `pos`.
 struct Ovf {
   uint32_t x, pos, y, pad;
@@ -81,6 +101,7 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t value, uint64_t count, hipStrea
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long value, uint64_t count,
                            hipStream_t s);
 hipError_t launch_ctl_reset_query(Ctl *ctl, hipStream_t s);
+hipError_t launch_publish(Ctl *ctl, Mirror *m, uint32_t seq, hipStream_t s);
 
 // build: ingest
 hipError_t launch_validate_pairs(const uint32_t *a, const uint32_t *b, uint64_t count, uint32_t n,
@@ -123,18 +144,20 @@ struct PropArgs {
   uint32_t *inq;    // [2n] stamp of the frontier each (vertex, direction) is queued in
   unsigned long long *heavy_list;
   uint64_t heavy_cap;
+  unsigned long long *pcnt;  // [kPropCtrSlots * 2] per-block (expanded, relaxed) counters
   Ctl *ctl;
 };
 // one grid round: expand the frontier at ring `ring` (entries stamped `stamp`)
 hipError_t launch_round(const PropArgs &a, uint32_t ring, uint32_t stamp, uint32_t grid,
                         hipStream_t s);
-// single-workgroup rounds starting from ctl->cur / ctl->stamp
-hipError_t launch_local_rounds(const PropArgs &a, hipStream_t s);
+// single-workgroup rounds starting from ctl->cur / ctl->stamp; publishes the status to m (if
+// not null) with sequence number seq when done
+hipError_t launch_local_rounds(const PropArgs &a, Mirror *m, uint32_t seq, hipStream_t s);
 
 // insertion
 hipError_t launch_insert_small(const PropArgs &a, const uint32_t *src, const uint32_t *dst,
-                               uint32_t count, uint32_t n, Ovf *ovf, uint64_t ovf_cap,
-                               hipStream_t s);
+                               uint32_t count, uint32_t n, Ovf *ovf, uint64_t ovf_cap, Mirror *m,
+                               uint32_t seq, hipStream_t s);
 hipError_t launch_insert_apply(const PropArgs &a, const uint32_t *src, const uint32_t *dst,
                                uint64_t count, Ovf *ovf, uint64_t ovf_cap, hipStream_t s);
 hipError_t launch_regrow_copy(Csr old_g, Csr new_g, uint32_t n, hipStream_t s);
@@ -145,7 +168,8 @@ hipError_t launch_push_overflow(const PropArgs &a, const Ovf *ovf, uint32_t coun
 
 // queries
 hipError_t launch_query_label(LabelsView L, const uint32_t *u, const uint32_t *v, uint64_t count,
-                              uint32_t n, uint8_t *out, uint32_t *und, Ctl *ctl, hipStream_t s);
+                              uint32_t n, uint8_t *out, uint32_t *und, Ctl *ctl,
+                              unsigned long long *qcls, hipStream_t s);
 struct BfsArgs {
   LabelsView L;
   Csr f;
@@ -157,6 +181,7 @@ struct BfsArgs {
   uint32_t *queue;          // [slots * qcap]
   uint32_t qcap;
   uint32_t *heavy_q;        // queries handed to the grid BFS
+  unsigned long long *cnt;  // [slots * kBfsCtrStride]
   Ctl *ctl;
 };
 hipError_t launch_query_bfs(const BfsArgs &a, uint32_t slots, hipStream_t s);
@@ -165,7 +190,8 @@ hipError_t launch_gbfs_start(const PropArgs &a, unsigned long long *vis, uint64_
                              uint32_t u, hipStream_t s);
 hipError_t launch_gbfs_round(const PropArgs &a, unsigned long long *vis, uint32_t u, uint32_t v,
                              uint32_t ring, hipStream_t s);
-hipError_t launch_gbfs_finish(const PropArgs &a, uint32_t qi, uint8_t *out, hipStream_t s);
+hipError_t launch_gbfs_finish(const PropArgs &a, uint32_t qi, uint8_t *out,
+                              unsigned long long *qcls, hipStream_t s);
 
 hipError_t launch_unpack_labels(LabelsView L, uint32_t n, unsigned long long *dl_in,
                                 unsigned long long *dl_out, unsigned long long *bl_in,

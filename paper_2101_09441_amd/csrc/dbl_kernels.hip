@@ -153,6 +153,30 @@ hipError_t launch_ctl_reset_query(Ctl *ctl, hipStream_t s) {
   return hipGetLastError();
 }
 
+__device__ __forceinline__ void st_sys32(uint32_t *p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// One thread copies the fields the host needs into the host mirror, then releases `seq`.
+__device__ void publish_status(Ctl *ctl, Mirror *m, uint32_t seq) {
+  st_sys32(&m->err, ld_agent32(&ctl->err));
+  st_sys32(&m->cur, ld_agent32(&ctl->cur));
+  st_sys32(&m->stamp, ld_agent32(&ctl->stamp));
+  for (int i = 0; i < 3; i++) st_sys32(&m->fsize[i], ld_agent32(&ctl->fsize[i]));
+  st_sys32(&m->ovf_count, ld_agent32(&ctl->ovf_count));
+  st_sys32(&m->und_count, ld_agent32(&ctl->und_count));
+  st_sys32(&m->bfs_heavy, ld_agent32(&ctl->bfs_heavy));
+  st_sys32(&m->found, ld_agent32(&ctl->found));
+  __hip_atomic_store(&m->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+__global__ void k_publish(Ctl *ctl, Mirror *m, uint32_t seq) { publish_status(ctl, m, seq); }
+
+hipError_t launch_publish(Ctl *ctl, Mirror *m, uint32_t seq, hipStream_t s) {
+  hipLaunchKernelGGL(k_publish, dim3(1), dim3(1), 0, s, ctl, m, seq);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- ingest
 
 __global__ void k_validate(const uint32_t *a, const uint32_t *b, uint64_t count, uint32_t n,
@@ -597,8 +621,8 @@ __global__ __launch_bounds__(256) void k_round(PropArgs a, uint32_t ring, uint32
                      s_wsum, relaxed);
   }
   if (threadIdx.x == 0 && expanded) {
-    atomicAdd(&ctl->ctr[kCtrExpanded], expanded);
-    atomicAdd(&ctl->ctr[kCtrRelaxed], relaxed);
+    a.pcnt[2 * blockIdx.x] += expanded;
+    a.pcnt[2 * blockIdx.x + 1] += relaxed;
   }
 }
 
@@ -631,14 +655,16 @@ __global__ __launch_bounds__(256) void k_heavy(PropArgs a, uint32_t hidx, uint32
     }
     relaxed += e_end > b ? e_end - b : 0;
   }
-  if (threadIdx.x == 0 && relaxed) atomicAdd(&ctl->ctr[kCtrRelaxed], relaxed);
+  if (threadIdx.x == 0 && relaxed) a.pcnt[2 * (kRoundGridMax + blockIdx.x) + 1] += relaxed;
 }
 
 hipError_t launch_round(const PropArgs &a, uint32_t ring, uint32_t stamp, uint32_t grid,
                         hipStream_t s) {
+  if (grid > kRoundGridMax) grid = kRoundGridMax;
   hipLaunchKernelGGL(k_round, dim3(grid), dim3(256), 0, s, a, ring, stamp);
   const uint32_t nring = ring == 2u ? 0u : ring + 1u;
-  hipLaunchKernelGGL(k_heavy, dim3(1024), dim3(256), 0, s, a, stamp & 1u, nring, stamp + 1u);
+  hipLaunchKernelGGL(k_heavy, dim3(kHeavyGrid), dim3(256), 0, s, a, stamp & 1u, nring,
+                     stamp + 1u);
   return hipGetLastError();
 }
 
@@ -697,18 +723,20 @@ __device__ void local_rounds_body(const PropArgs &a) {
     ctl->stamp = stamp;
     ctl->local_rounds += rounds;
     if (expanded) {
-      atomicAdd(&ctl->ctr[kCtrExpanded], expanded);
-      atomicAdd(&ctl->ctr[kCtrRelaxed], relaxed);
+      a.pcnt[2 * (kRoundGridMax + kHeavyGrid)] += expanded;
+      a.pcnt[2 * (kRoundGridMax + kHeavyGrid) + 1] += relaxed;
     }
   }
 }
 
-__global__ __launch_bounds__(kLocalThreads) void k_local_rounds(PropArgs a) {
+__global__ __launch_bounds__(kLocalThreads) void k_local_rounds(PropArgs a, Mirror *m,
+                                                                uint32_t seq) {
   local_rounds_body(a);
+  if (m && threadIdx.x == 0) publish_status(a.ctl, m, seq);
 }
 
-hipError_t launch_local_rounds(const PropArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(k_local_rounds, dim3(1), dim3(kLocalThreads), 0, s, a);
+hipError_t launch_local_rounds(const PropArgs &a, Mirror *m, uint32_t seq, hipStream_t s) {
+  hipLaunchKernelGGL(k_local_rounds, dim3(1), dim3(kLocalThreads), 0, s, a, m, seq);
   return hipGetLastError();
 }
 
@@ -733,38 +761,56 @@ __device__ __forceinline__ void append_edge(const Csr &g, uint32_t x, uint32_t y
   }
 }
 
-// Append (u,v) to both CSRs and seed both directions (Algorithm 3 starts from v with DL_in(u)
-// and, symmetrically, from u with DL_out(v)); changed endpoints join the pending frontier.
+// Half of an insertion (u,v) for one direction. Forward: append v to Suc(u) and OR
+// (DL_in(u), BL_in(u)) into v (Algorithm 3 starts from v). Backward: append u to Pre(v) and OR
+// (DL_out(v), BL_out(v)) into u. A changed endpoint joins the pending frontier. Returns whether
+// it was queued.
+__device__ __forceinline__ bool apply_half(const PropArgs &a, uint32_t u, uint32_t v, uint32_t dir,
+                                           uint32_t ring, uint32_t stamp, Ovf *ovf,
+                                           uint64_t ovf_cap, bool active) {
+  bool p = false;
+  const uint32_t tail = dir ? v : u, head = dir ? u : v;
+  if (active && u != v) {
+    append_edge(dir ? a.r : a.f, tail, head, dir ? kDirBit : 0u, ovf, ovf_cap, a.ctl);
+    const ulonglong2 lt = *reinterpret_cast<const ulonglong2 *>(a.L.lab + 4ull * tail + 2u * dir);
+    p = relax(a.L.lab + 4ull * head + 2u * dir, lt.x, lt.y) &&
+        claim(&a.inq[2ull * head + dir], stamp);
+  }
+  wave_push(a.fq[ring], &a.ctl->fsize[ring], p, head | (dir ? kDirBit : 0u));
+  return p;
+}
+
+// Both halves of insertion (u,v) by one thread (used by the grid kernel).
 __device__ __forceinline__ void apply_edge(const PropArgs &a, uint32_t u, uint32_t v,
                                            uint32_t ring, uint32_t stamp, Ovf *ovf,
                                            uint64_t ovf_cap, bool active) {
-  bool pv = false, pu = false;
-  if (active && u != v) {
-    append_edge(a.f, u, v, 0u, ovf, ovf_cap, a.ctl);
-    append_edge(a.r, v, u, kDirBit, ovf, ovf_cap, a.ctl);
-    const ulonglong2 fu = *reinterpret_cast<const ulonglong2 *>(a.L.lab + 4ull * u);
-    const ulonglong2 bv = *reinterpret_cast<const ulonglong2 *>(a.L.lab + 4ull * v + 2);
-    pv = relax(a.L.lab + 4ull * v, fu.x, fu.y) && claim(&a.inq[2ull * v], stamp);
-    pu = relax(a.L.lab + 4ull * u + 2, bv.x, bv.y) && claim(&a.inq[2ull * u + 1], stamp);
-  }
-  wave_push(a.fq[ring], &a.ctl->fsize[ring], pv, v);
-  wave_push(a.fq[ring], &a.ctl->fsize[ring], pu, u | kDirBit);
+  apply_half(a, u, v, 0u, ring, stamp, ovf, ovf_cap, active);
+  apply_half(a, u, v, 1u, ring, stamp, ovf, ovf_cap, active);
 }
 
+// A small batch in one workgroup: validate every id, then (only if all are valid) apply both
+// halves of each edge on two threads, then run the propagation rounds here, then publish.
 __global__ __launch_bounds__(kLocalThreads) void k_insert_small(PropArgs a, const uint32_t *src,
                                                                 const uint32_t *dst,
                                                                 uint32_t count, uint32_t n,
-                                                                Ovf *ovf, uint64_t ovf_cap) {
-  __shared__ uint32_t s_bad;
+                                                                Ovf *ovf, uint64_t ovf_cap,
+                                                                Mirror *m, uint32_t seq) {
+  __shared__ uint32_t s_bad, s_pushed;
   Ctl *ctl = a.ctl;
   const uint32_t t = threadIdx.x;
-  if (t == 0) s_bad = 0;
+  if (t == 0) {
+    s_bad = 0;
+    s_pushed = 0;
+  }
   __syncthreads();
   for (uint32_t i = t; i < count; i += kLocalThreads)
     if (src[i] >= n || dst[i] >= n) s_bad = 1;
   __syncthreads();
   if (s_bad) {
-    if (t == 0) atomicOr(&ctl->err, kErrRange);
+    if (t == 0) {
+      atomicOr(&ctl->err, kErrRange);
+      publish_status(ctl, m, seq);
+    }
     return;
   }
   const uint32_t ring = ctl->cur, stamp = ctl->stamp;
@@ -772,20 +818,26 @@ __global__ __launch_bounds__(kLocalThreads) void k_insert_small(PropArgs a, cons
     ctl->heavy[0] = 0;
     ctl->heavy[1] = 0;
   }
-  for (uint32_t i0 = 0; i0 < count; i0 += kLocalThreads) {
-    const uint32_t i = i0 + t;
-    const bool act = i < count;
-    apply_edge(a, act ? src[i] : 0u, act ? dst[i] : 0u, ring, stamp, ovf, ovf_cap, act);
+  for (uint32_t j0 = 0; j0 < 2 * count; j0 += kLocalThreads) {
+    const uint32_t j = j0 + t;
+    const bool act = j < 2 * count;
+    const uint32_t i = j >> 1;
+    const bool p = apply_half(a, act ? src[i] : 0u, act ? dst[i] : 0u, j & 1u, ring, stamp, ovf,
+                              ovf_cap, act);
+    if (p) s_pushed = 1;
   }
   __syncthreads();
-  local_rounds_body(a);
+  // nothing changed: the pending frontier is still empty and no round is needed
+  if (s_pushed) local_rounds_body(a);
+  __syncthreads();
+  if (t == 0) publish_status(ctl, m, seq);
 }
 
 hipError_t launch_insert_small(const PropArgs &a, const uint32_t *src, const uint32_t *dst,
-                               uint32_t count, uint32_t n, Ovf *ovf, uint64_t ovf_cap,
-                               hipStream_t s) {
+                               uint32_t count, uint32_t n, Ovf *ovf, uint64_t ovf_cap, Mirror *m,
+                               uint32_t seq, hipStream_t s) {
   hipLaunchKernelGGL(k_insert_small, dim3(1), dim3(kLocalThreads), 0, s, a, src, dst, count, n,
-                     ovf, ovf_cap);
+                     ovf, ovf_cap, m, seq);
   return hipGetLastError();
 }
 
@@ -879,11 +931,13 @@ hipError_t launch_push_overflow(const PropArgs &a, const Ovf *ovf, uint32_t coun
 // ---------------------------------------------------------------- queries
 
 // Label phase of Algorithm 2: one lane per pair. Decided pairs get their answer byte now;
-// the rest are compacted into `und` for the BFS kernel.
+// the rest are compacted into `und` for the BFS kernel. Class counts are summed per block and
+// added to the block's own counters (no atomics shared across blocks).
 __global__ __launch_bounds__(256) void k_query_label(const u64 *lab, const uint32_t *qu,
                                                      const uint32_t *qv, uint64_t count,
                                                      uint32_t n, uint8_t *out, uint32_t *und,
-                                                     Ctl *ctl) {
+                                                     Ctl *ctl, u64 *qcls) {
+  __shared__ uint32_t s_cls[4][5];
   uint32_t cls_cnt[5] = {0, 0, 0, 0, 0};
   bool bad_any = false;
   for (uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x; i0 < count;
@@ -918,18 +972,23 @@ __global__ __launch_bounds__(256) void k_query_label(const u64 *lab, const uint3
     wave_push(und, &ctl->und_count, undecided, (uint32_t)i);
   }
   if (__ballot(bad_any) && __lane_id() == 0) atomicOr(&ctl->err, kErrRange);
-  if (__lane_id() == 0) {
-#pragma unroll
-    for (int c = 0; c < 5; c++)
-      if (cls_cnt[c]) atomicAdd(&ctl->ctr[kCtrClass0 + c], (u64)cls_cnt[c]);
+  const uint32_t w = threadIdx.x >> 6;
+  if (__lane_id() == 0)
+    for (int c = 0; c < 5; c++) s_cls[w][c] = cls_cnt[c];
+  __syncthreads();
+  if (threadIdx.x < 5) {
+    const uint32_t c = threadIdx.x;
+    const uint32_t tot = s_cls[0][c] + s_cls[1][c] + s_cls[2][c] + s_cls[3][c];
+    if (tot) qcls[blockIdx.x * kQClsStride + c] += tot;
   }
 }
 
 hipError_t launch_query_label(LabelsView L, const uint32_t *u, const uint32_t *v, uint64_t count,
-                              uint32_t n, uint8_t *out, uint32_t *und, Ctl *ctl, hipStream_t s) {
+                              uint32_t n, uint8_t *out, uint32_t *und, Ctl *ctl, u64 *qcls,
+                              hipStream_t s) {
   if (count == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_query_label, dim3(grid_for(count, 256, 8192)), dim3(256), 0, s, L.lab, u, v,
-                     count, n, out, und, ctl);
+  hipLaunchKernelGGL(k_query_label, dim3(grid_for(count, 256, kQueryGrid)), dim3(256), 0, s,
+                     L.lab, u, v, count, n, out, und, ctl, qcls);
   return hipGetLastError();
 }
 
@@ -1037,11 +1096,12 @@ __global__ __launch_bounds__(kBfsNT) void k_query_bfs(BfsArgs a) {
       }
     }
   }
-  if (lane == 0) {
-    if (n_vert) atomicAdd(&ctl->ctr[kCtrBfsVert], n_vert);
-    if (n_edge) atomicAdd(&ctl->ctr[kCtrBfsEdge], n_edge);
-    if (cls_t) atomicAdd(&ctl->ctr[kCtrClass0 + 5], cls_t);
-    if (cls_f) atomicAdd(&ctl->ctr[kCtrClass0 + 6], cls_f);
+  if (lane == 0 && (n_vert | cls_t | cls_f)) {
+    u64 *c = a.cnt + (uint64_t)slot * kBfsCtrStride;  // this wave's own counters
+    c[0] += n_vert;
+    c[1] += n_edge;
+    c[2] += cls_t;
+    c[3] += cls_f;
   }
 }
 
@@ -1107,19 +1167,20 @@ hipError_t launch_gbfs_round(const PropArgs &a, u64 *vis, uint32_t u, uint32_t v
   return hipGetLastError();
 }
 
-__global__ void k_gbfs_finish(PropArgs a, uint32_t qi, uint8_t *out) {
+__global__ void k_gbfs_finish(PropArgs a, uint32_t qi, uint8_t *out, u64 *qcls) {
   Ctl *ctl = a.ctl;
   const bool found = ctl->found != 0;
   out[qi] = found ? (uint8_t)(1u | (5u << 1)) : (uint8_t)(6u << 1);
-  atomicAdd(&ctl->ctr[kCtrClass0 + (found ? 5 : 6)], 1ull);
+  qcls[found ? 5 : 6] += 1ull;  // block 0's class slots; this kernel runs alone
   ctl->fsize[0] = 0;
   ctl->fsize[1] = 0;
   ctl->fsize[2] = 0;
   ctl->found = 0;
 }
 
-hipError_t launch_gbfs_finish(const PropArgs &a, uint32_t qi, uint8_t *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_gbfs_finish, dim3(1), dim3(1), 0, s, a, qi, out);
+hipError_t launch_gbfs_finish(const PropArgs &a, uint32_t qi, uint8_t *out, u64 *qcls,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_gbfs_finish, dim3(1), dim3(1), 0, s, a, qi, out, qcls);
   return hipGetLastError();
 }
 

@@ -157,6 +157,19 @@ def test_tiny_single_insertions_then_queries(tiny):
     assert np.array_equal(got & 1, truth)
 
 
+def test_tiny_insert_each_equals_single_calls(tiny):
+    w = tiny
+    g = gpu_index(w.n, w.src, w.dst)
+    o = oracle.OracleIndex(w.n, w.src, w.dst).build(threads=8)
+    lat = g.insert_edges_each(dev(w.ins_src), dev(w.ins_dst), latencies=True)
+    o.insert(w.ins_src, w.ins_dst)
+    assert lat.shape == (len(w.ins_src),) and np.all(lat > 0)
+    assert_labels_equal(g, o, "insert_each")
+    assert g.stats()["insert_calls"] == len(w.ins_src)
+    with pytest.raises(dbl.DblError):
+        g.insert_edges_each(dev([1, 2, w.n]), dev([3, 4, 5]))
+
+
 @pytest.mark.parametrize("batch", [1000, 333, 7])
 def test_tiny_batched_insertions_equal_sequential(tiny, batch):
     w = tiny
