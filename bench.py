@@ -107,6 +107,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", choices=["lj", "tiny"], default="lj")
     ap.add_argument("--cpu-baseline", choices=["on", "off"], default="on")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first copy one 1 GiB device buffer (reads 1 GiB, writes 1 GiB), the "
+                         "reference for scaling memory counters")
     ap.add_argument("--time-kernels", default="insert_small,query_label,query_bfs,round:8",
                     help="kernel kinds timed with HIP events during the timed steps "
                          "(':N' times one launch in N)")
@@ -138,6 +141,14 @@ def main():
     isrc, idst = dbl.to_device_ids(w.ins_src), dbl.to_device_ids(w.ins_dst)
     qu, qv = dbl.to_device_ids(w.q_u), dbl.to_device_ids(w.q_v)
     out = torch.empty(len(w.q_u), dtype=torch.uint8, device=dev)
+    if args.calibrate_copy:
+        a = torch.ones(1 << 28, dtype=torch.int32, device=dev)
+        c = torch.empty_like(a)
+        torch.cuda.synchronize()
+        c.copy_(a)
+        torch.cuda.synchronize()
+        del a, c
+        log("calibration copy: 1 GiB read, 1 GiB written")
     torch.cuda.synchronize()
 
     def step(timed):
@@ -158,15 +169,58 @@ def main():
         return r
 
     def diagnostics():
-        """Untimed pass over the same inputs: counters after each phase."""
+        """Untimed pass over the same inputs: counters after each phase, final labels."""
         ix = dbl.Index.build(w.n, src, dst, edges_unique=True)
         s_build = ix.stats()
         ix.insert_edges_each(isrc, idst)
         s_ins = ix.stats()
         ix.query(qu, qv, out=out)
         s_q = ix.stats()
+        labels = ix.labels()
         ix.close()
-        return s_build, s_ins, s_q
+        return s_build, s_ins, s_q, labels
+
+    def batched(plain_labels, plain_answers):
+        """The batched form on the same inputs: insertion batches of 1k/10k/100k edges and query
+        batches of 65,536 pairs; labels and answers must equal the plain form's."""
+        res = {}
+        qb = 65536
+        for bsz in (1000, 10000, 100000):
+            if bsz > n_ins:
+                continue
+            ix = dbl.Index.build(w.n, src, dst, edges_unique=True)
+            torch.cuda.synchronize()
+            times = []
+            t0 = time.perf_counter()
+            for lo in range(0, n_ins, bsz):
+                tb = time.perf_counter()
+                ix.insert_edges(isrc[lo:lo + bsz], idst[lo:lo + bsz])
+                times.append(time.perf_counter() - tb)
+            t_ins = time.perf_counter() - t0
+            same = all(torch.equal(a, b) for a, b in zip(ix.labels(), plain_labels))
+            entry = {"edges_per_s": n_ins / t_ins, "batches": len(times),
+                     "batch_ms_p50": float(np.percentile(times, 50) * 1e3),
+                     "batch_ms_p99": float(np.percentile(times, 99) * 1e3),
+                     "speedup_vs_plain": (n_ins / t_ins) / (n_ins / insert_s),
+                     "labels_equal_plain": bool(same)}
+            if bsz == 1000:
+                qout = torch.empty_like(out)
+                qt = []
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for lo in range(0, n_q, qb):
+                    tb = time.perf_counter()
+                    ix.query(qu[lo:lo + qb], qv[lo:lo + qb], out=qout[lo:lo + qb])
+                    qt.append(time.perf_counter() - tb)
+                t_q = time.perf_counter() - t0
+                res["query_batches_65536"] = {
+                    "queries_per_s": n_q / t_q, "batches": len(qt),
+                    "batch_ms_p50": float(np.percentile(qt, 50) * 1e3),
+                    "batch_ms_p99": float(np.percentile(qt, 99) * 1e3),
+                    "answers_equal_plain": bool(torch.equal(qout, plain_answers))}
+            res[f"insert_batch_{bsz}"] = entry
+            ix.close()
+        return res
 
     for i in range(args.warmup):
         r = step(False)
@@ -190,7 +244,8 @@ def main():
     build_s = float(np.mean([r["build_s"] for r in results]))
     insert_s = float(np.mean([r["insert_s"] for r in results]))
     query_s = float(np.mean([r["query_s"] for r in results]))
-    s_build, s_ins, s_q = diagnostics()
+    s_build, s_ins, s_q, plain_labels = diagnostics()
+    batched_res = batched(plain_labels, out.clone())
     ins_expanded = s_ins["vertices_expanded"] - s_build["vertices_expanded"]
     ins_relaxed = s_ins["edges_relaxed"] - s_build["edges_relaxed"]
     answers = out.cpu().numpy()
@@ -266,6 +321,7 @@ def main():
                         "insert_vertices_expanded": ins_expanded,
                         "csr_regrows": s_ins["csr_regrows"],
                         "bfs_edges": s_q["bfs_edges"], "bfs_vertices": s_q["bfs_vertices"]},
+        "batched": batched_res,
         "roofline": roofline,
         "cpu_baseline": None,
     }

@@ -229,6 +229,11 @@ dbl_status wait_status(dbl_index *ix, hipStream_t s, uint32_t seq) {
   return DBL_OK;
 }
 
+// Wait for the fast status word of a small insertion. With no flag set the call is complete and
+// nothing else needs reading; otherwise the whole status is published and read.
+dbl_status wait_fast(dbl_index *ix, hipStream_t s, uint32_t seq, uint32_t *flags);
+dbl_status sync_ctl(dbl_index *ix, hipStream_t s);
+
 // Publish the control block after the work queued so far and wait for it.
 dbl_status sync_ctl(dbl_index *ix, hipStream_t s) {
   const uint32_t seq = ++ix->seq;
@@ -239,6 +244,35 @@ dbl_status sync_ctl(dbl_index *ix, hipStream_t s) {
 // Write one 32-bit field of the device control block (host value, stream ordered).
 dbl_status set_ctl_u32(dbl_index *ix, size_t offset, uint32_t value, hipStream_t s) {
   CK(dbl::launch_fill_u32((uint32_t *)((char *)ix->ctl + offset), value, 1, s));
+  return DBL_OK;
+}
+
+dbl_status wait_fast(dbl_index *ix, hipStream_t s, uint32_t seq, uint32_t *flags) {
+  for (uint64_t spin = 1;; spin++) {
+    const u64 w = __atomic_load_n(&ix->mirror->fast, __ATOMIC_ACQUIRE);
+    if ((uint32_t)w == seq) {
+      *flags = (uint32_t)(w >> 32);
+      break;
+    }
+    if ((spin & 4095) == 0) {
+      const hipError_t q = hipStreamQuery(s);
+      if (q == hipSuccess) {
+        const u64 w2 = __atomic_load_n(&ix->mirror->fast, __ATOMIC_ACQUIRE);
+        if ((uint32_t)w2 == seq) {
+          *flags = (uint32_t)(w2 >> 32);
+          break;
+        }
+        return DBL_ERR_DEVICE;
+      }
+      if (q != hipErrorNotReady) return from_hip(q);
+    }
+  }
+  if (!ix->pending.empty()) resolve_times(ix);
+  if (*flags) return sync_ctl(ix, s);
+  // fast path: the pending frontier is empty and nothing overflowed
+  ix->hs.err = 0;
+  ix->hs.ovf_count = 0;
+  ix->hs.fsize[ix->hs.cur] = 0;
   return DBL_OK;
 }
 
@@ -588,19 +622,25 @@ dbl_status dbl_insert_edges(dbl_index *ix, uint64_t count, const uint32_t *d_src
   dbl::PropArgs a = prop_args(ix);
   const uint32_t seq = ++ix->seq;
   if (count <= dbl::kSmallBatch) {
-    Timed tm(ix, kTInsertSmall, s);
-    CK(dbl::launch_insert_small(a, d_src, d_dst, (uint32_t)count, ix->n, ix->ovf, ix->ovf_cap,
-                                ix->mirror, seq, s));
+    {
+      Timed tm(ix, kTInsertSmall, s);
+      CK(dbl::launch_insert_small(a, d_src, d_dst, (uint32_t)count, ix->n, ix->ovf, ix->ovf_cap,
+                                  ix->mirror, seq, s));
+    }
+    uint32_t flags = 0;
+    CKS(wait_fast(ix, s, seq, &flags));
   } else {
     CK(dbl::launch_validate_pairs(d_src, d_dst, count, ix->n, ix->ctl, s));
     {
       Timed tm(ix, kTInsertApply, s);
       CK(dbl::launch_insert_apply(a, d_src, d_dst, count, ix->ovf, ix->ovf_cap, s));
     }
-    Timed tm(ix, kTLocalRounds, s);
-    CK(dbl::launch_local_rounds(a, ix->mirror, seq, s));
+    {
+      Timed tm(ix, kTLocalRounds, s);
+      CK(dbl::launch_local_rounds(a, ix->mirror, seq, s));
+    }
+    CKS(wait_status(ix, s, seq));
   }
-  CKS(wait_status(ix, s, seq));
   if (ix->hs.err) {
     CKS(set_ctl_u32(ix, offsetof(Ctl, err), 0u, s));
     CK(hipStreamSynchronize(s));

@@ -74,7 +74,11 @@ struct Mirror {
   uint32_t fsize[3];
   uint32_t ovf_count, und_count, bfs_heavy, found;
   uint32_t pad[5];
+  // Fast path of one small insertion: sequence number (low 32 bits) and flags (high 32 bits)
+  // in one store; the host reads the other fields only when a flag is set.
+  unsigned long long fast;
 };
+constexpr uint32_t kFastErr = 1u, kFastOvf = 2u, kFastPending = 4u;
 
 // Per-block / per-slot statistics (plain read-modify-write by the owning block, no atomics).
 constexpr uint32_t kQueryGrid = 1024;  // blocks of the label kernel (grid-stride)

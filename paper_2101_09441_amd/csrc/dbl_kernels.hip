@@ -742,23 +742,25 @@ hipError_t launch_local_rounds(const PropArgs &a, Mirror *m, uint32_t seq, hipSt
 
 // ---------------------------------------------------------------- insertion
 
-__device__ __forceinline__ void append_edge(const Csr &g, uint32_t x, uint32_t y,
+// Append y to row x; returns false when the row is full and the entry went to the overflow list.
+__device__ __forceinline__ bool append_edge(const Csr &g, uint32_t x, uint32_t y,
                                             uint32_t dirbit, Ovf *ovf, uint64_t ovf_cap,
                                             Ctl *ctl) {
   const uint32_t pos = atomicAdd(&g.deg[x], 1u);
   if (pos < g.cap[x]) {
     g.col[g.off[x] + pos] = y;
-  } else {
-    const uint32_t k = atomicAdd(&ctl->ovf_count, 1u);
-    if (k < ovf_cap) {
-      Ovf o;
-      o.x = x | dirbit;
-      o.pos = pos;
-      o.y = y;
-      o.pad = 0;
-      ovf[k] = o;
-    }
+    return true;
   }
+  const uint32_t k = atomicAdd(&ctl->ovf_count, 1u);
+  if (k < ovf_cap) {
+    Ovf o;
+    o.x = x | dirbit;
+    o.pos = pos;
+    o.y = y;
+    o.pad = 0;
+    ovf[k] = o;
+  }
+  return false;
 }
 
 // Half of an insertion (u,v) for one direction. Forward: append v to Suc(u) and OR
@@ -767,14 +769,20 @@ __device__ __forceinline__ void append_edge(const Csr &g, uint32_t x, uint32_t y
 // it was queued.
 __device__ __forceinline__ bool apply_half(const PropArgs &a, uint32_t u, uint32_t v, uint32_t dir,
                                            uint32_t ring, uint32_t stamp, Ovf *ovf,
-                                           uint64_t ovf_cap, bool active) {
+                                           uint64_t ovf_cap, bool active, bool *overflowed) {
   bool p = false;
   const uint32_t tail = dir ? v : u, head = dir ? u : v;
   if (active && u != v) {
-    append_edge(dir ? a.r : a.f, tail, head, dir ? kDirBit : 0u, ovf, ovf_cap, a.ctl);
+    // the label reads do not depend on the append: issue them first
     const ulonglong2 lt = *reinterpret_cast<const ulonglong2 *>(a.L.lab + 4ull * tail + 2u * dir);
-    p = relax(a.L.lab + 4ull * head + 2u * dir, lt.x, lt.y) &&
-        claim(&a.inq[2ull * head + dir], stamp);
+    u64 *wh = a.L.lab + 4ull * head + 2u * dir;
+    const ulonglong2 lh = *reinterpret_cast<const ulonglong2 *>(wh);
+    if (!append_edge(dir ? a.r : a.f, tail, head, dir ? kDirBit : 0u, ovf, ovf_cap, a.ctl))
+      *overflowed = true;
+    bool changed = false;
+    if (lt.x & ~lh.x) changed |= (lt.x & ~atomicOr(wh, lt.x)) != 0ull;
+    if (lt.y & ~lh.y) changed |= (lt.y & ~atomicOr(wh + 1, lt.y)) != 0ull;
+    p = changed && claim(&a.inq[2ull * head + dir], stamp);
   }
   wave_push(a.fq[ring], &a.ctl->fsize[ring], p, head | (dir ? kDirBit : 0u));
   return p;
@@ -784,32 +792,38 @@ __device__ __forceinline__ bool apply_half(const PropArgs &a, uint32_t u, uint32
 __device__ __forceinline__ void apply_edge(const PropArgs &a, uint32_t u, uint32_t v,
                                            uint32_t ring, uint32_t stamp, Ovf *ovf,
                                            uint64_t ovf_cap, bool active) {
-  apply_half(a, u, v, 0u, ring, stamp, ovf, ovf_cap, active);
-  apply_half(a, u, v, 1u, ring, stamp, ovf, ovf_cap, active);
+  bool ovfl = false;
+  apply_half(a, u, v, 0u, ring, stamp, ovf, ovf_cap, active, &ovfl);
+  apply_half(a, u, v, 1u, ring, stamp, ovf, ovf_cap, active, &ovfl);
 }
 
-// A small batch in one workgroup: validate every id, then (only if all are valid) apply both
-// halves of each edge on two threads, then run the propagation rounds here, then publish.
+// A small batch in one workgroup: thread 2i handles the forward half of edge i and thread
+// 2i+1 the backward half. Every id is checked before anything changes (a block-wide vote);
+// then the halves are applied, the propagation rounds run here when something changed, and one
+// 64-bit word {seq, flags} is written to the host mirror.
 __global__ __launch_bounds__(kLocalThreads) void k_insert_small(PropArgs a, const uint32_t *src,
                                                                 const uint32_t *dst,
                                                                 uint32_t count, uint32_t n,
                                                                 Ovf *ovf, uint64_t ovf_cap,
                                                                 Mirror *m, uint32_t seq) {
-  __shared__ uint32_t s_bad, s_pushed;
+  __shared__ uint32_t s_pushed, s_ovf;
   Ctl *ctl = a.ctl;
   const uint32_t t = threadIdx.x;
-  if (t == 0) {
-    s_bad = 0;
-    s_pushed = 0;
+  const bool act = t < 2 * count;  // 2 * count <= kLocalThreads
+  uint32_t u = 0, v = 0;
+  if (act) {
+    u = src[t >> 1];
+    v = dst[t >> 1];
   }
-  __syncthreads();
-  for (uint32_t i = t; i < count; i += kLocalThreads)
-    if (src[i] >= n || dst[i] >= n) s_bad = 1;
-  __syncthreads();
-  if (s_bad) {
+  if (t == 0) {
+    s_pushed = 0;
+    s_ovf = 0;
+  }
+  if (__syncthreads_or(act && (u >= n || v >= n))) {
     if (t == 0) {
       atomicOr(&ctl->err, kErrRange);
-      publish_status(ctl, m, seq);
+      __hip_atomic_store(&m->fast, ((u64)kFastErr << 32) | seq, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_SYSTEM);
     }
     return;
   }
@@ -818,19 +832,20 @@ __global__ __launch_bounds__(kLocalThreads) void k_insert_small(PropArgs a, cons
     ctl->heavy[0] = 0;
     ctl->heavy[1] = 0;
   }
-  for (uint32_t j0 = 0; j0 < 2 * count; j0 += kLocalThreads) {
-    const uint32_t j = j0 + t;
-    const bool act = j < 2 * count;
-    const uint32_t i = j >> 1;
-    const bool p = apply_half(a, act ? src[i] : 0u, act ? dst[i] : 0u, j & 1u, ring, stamp, ovf,
-                              ovf_cap, act);
-    if (p) s_pushed = 1;
-  }
+  bool ovfl = false;
+  if (apply_half(a, u, v, t & 1u, ring, stamp, ovf, ovf_cap, act, &ovfl)) s_pushed = 1;
+  if (ovfl) s_ovf = 1;
   __syncthreads();
   // nothing changed: the pending frontier is still empty and no round is needed
   if (s_pushed) local_rounds_body(a);
   __syncthreads();
-  if (t == 0) publish_status(ctl, m, seq);
+  if (t == 0) {
+    uint32_t flags = 0;
+    if (s_ovf) flags |= kFastOvf;
+    if (s_pushed && ld_agent32(&ctl->fsize[ld_agent32(&ctl->cur)])) flags |= kFastPending;
+    __hip_atomic_store(&m->fast, ((u64)flags << 32) | seq, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_SYSTEM);
+  }
 }
 
 hipError_t launch_insert_small(const PropArgs &a, const uint32_t *src, const uint32_t *dst,
