@@ -107,6 +107,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", choices=["lj", "tiny"], default="lj")
     ap.add_argument("--cpu-baseline", choices=["on", "off"], default="on")
+    ap.add_argument("--serving", choices=["on", "off"], default="on")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy one 1 GiB device buffer (reads 1 GiB, writes 1 GiB), the "
                          "reference for scaling memory counters")
@@ -180,6 +181,41 @@ def main():
         ix.close()
         return s_build, s_ins, s_q, labels
 
+    def serving():
+        """Continuous-batching server on the resident graph: a Poisson stream of query batches
+        (1..100k pairs) and insertion batches (1k..10k edges) at 80:20, swept over arrival
+        rates; next to it the same trace replayed one request at a time (batched form, no
+        overlap, no coalescing)."""
+        from paper_2101_09441_amd.serve import Request, latency_summary, serve
+        res = {}
+        n_req = 300
+        for rate in (500.0, 2000.0, 8000.0):
+            spec = dblgen.serving_trace(w.q_u, w.q_v, w.ins_src, w.ins_dst, n_req, rate, seed=5)
+            trace = [Request(s_, k, a, b, t) for s_, k, a, b, t in spec]
+            ix = dbl.Index.build(w.n, src, dst, edges_unique=True)
+            summ = serve(ix, trace, workers=4, max_batch=1 << 17, bfs_slots=256)
+            ix.close()
+            # the same trace, each request alone in sequence order
+            ix = dbl.Index.build(w.n, src, dst, edges_unique=True)
+            seq = [Request(s_, k, a, b, t) for s_, k, a, b, t in spec]
+            same = True
+            t0 = time.perf_counter()
+            for r, m in zip(seq, trace):
+                tb = time.perf_counter()
+                if r.kind == "query":
+                    r.answers = ix.query(dbl.to_device_ids(r.a), dbl.to_device_ids(r.b)).cpu().numpy()
+                    same &= bool(np.array_equal(r.answers, m.answers))
+                else:
+                    ix.insert_edges(dbl.to_device_ids(r.a), dbl.to_device_ids(r.b))
+                r.arrival, r.done = tb - t0, time.perf_counter() - t0
+            seq_summ = latency_summary(seq, time.perf_counter() - t0)
+            ix.close()
+            res[f"rate_{int(rate)}_per_s"] = {"serving": summ, "one_at_a_time": seq_summ,
+                                              "answers_equal_alone": same}
+            log(f"serving rate {rate}: queries/s {summ['query']['per_s']:.3g}, "
+                f"query p99 {summ['query']['latency_ms_p99']:.2f} ms, equal {same}")
+        return res
+
     def batched(plain_labels, plain_answers):
         """The batched form on the same inputs: insertion batches of 1k/10k/100k edges and query
         batches of 65,536 pairs; labels and answers must equal the plain form's."""
@@ -246,6 +282,7 @@ def main():
     query_s = float(np.mean([r["query_s"] for r in results]))
     s_build, s_ins, s_q, plain_labels = diagnostics()
     batched_res = batched(plain_labels, out.clone())
+    serving_res = serving() if args.workload == "lj" and args.serving == "on" else None
     ins_expanded = s_ins["vertices_expanded"] - s_build["vertices_expanded"]
     ins_relaxed = s_ins["edges_relaxed"] - s_build["edges_relaxed"]
     answers = out.cpu().numpy()
@@ -322,6 +359,7 @@ def main():
                         "csr_regrows": s_ins["csr_regrows"],
                         "bfs_edges": s_q["bfs_edges"], "bfs_vertices": s_q["bfs_vertices"]},
         "batched": batched_res,
+        "serving": serving_res,
         "roofline": roofline,
         "cpu_baseline": None,
     }

@@ -211,6 +211,38 @@ def make_rmat_workload(name: str, scale: int, seed: int, *, draws: int = 0, m_ta
     return Workload(name, n, src, dst, isrc, idst, qu, qv, n_draws)
 
 
+def serving_trace(q_u, q_v, ins_src, ins_dst, n_requests: int, rate: float, p_query: float = 0.8,
+                  q_size=(1, 100_000), i_size=(1_000, 10_000), seed: int = 7):
+    """A Poisson arrival stream of query and insertion requests.
+
+    Inter-arrival times are exponential with mean 1/rate; a request is a query batch with
+    probability p_query, else an insertion batch; sizes are log-uniform integers in the given
+    ranges. Query pairs are taken in order from (q_u, q_v) (wrapping around); insertion edges in
+    order from (ins_src, ins_dst) (once they run out, further requests are queries).
+    Returns a list of (seq, kind, a, b, arrival_seconds).
+    """
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, size=n_requests))
+    out, qi, ii = [], 0, 0
+    nq, ni = len(q_u), len(ins_src)
+
+    def logu(lo, hi):
+        return int(np.exp(rng.uniform(np.log(lo), np.log(hi + 1))))
+
+    for s in range(n_requests):
+        want_q = rng.random() < p_query
+        if not want_q and ii < ni:
+            k = min(logu(*i_size), ni - ii)
+            out.append((s, "insert", ins_src[ii:ii + k].copy(), ins_dst[ii:ii + k].copy(), float(t[s])))
+            ii += k
+        else:
+            k = max(1, min(logu(*q_size), nq))
+            idx = (qi + np.arange(k)) % nq
+            out.append((s, "query", q_u[idx].copy(), q_v[idx].copy(), float(t[s])))
+            qi = (qi + k) % nq
+    return out
+
+
 def cached(name: str, make, cache_dir: str = None) -> Workload:
     """Return make() through an on-disk cache (uncompressed .npz keyed by `name`)."""
     cache_dir = cache_dir or os.environ.get("DBLGEN_CACHE", "/tmp/dblgen_cache")

@@ -31,6 +31,7 @@ extern "C" {
 #endif
 
 typedef struct dbl_index dbl_index;
+typedef struct dbl_query_ctx dbl_query_ctx;
 
 typedef enum {
   DBL_OK = 0,
@@ -140,6 +141,28 @@ dbl_status dbl_insert_edges_each(dbl_index *ix, uint64_t count, const uint32_t *
  */
 dbl_status dbl_query_batch(dbl_index *ix, uint64_t count, const uint32_t *d_u,
                            const uint32_t *d_v, uint8_t *d_out, void *stream);
+
+/*
+ * Query contexts: the scratch of one in-flight query batch (control block, status word, BFS
+ * slots, undecided-pair list). dbl_query_batch uses a context owned by the index; a caller that
+ * wants several query batches in flight at once (on different streams, from different host
+ * threads) gives each its own context. Queries never modify the index, so batches on different
+ * contexts may overlap each other; they must not overlap an insertion on the same index.
+ *   bfs_slots, queue_cap: as in dbl_options (0 = the index's setting).
+ *   dbl_query_ctx_bytes: device memory a context needs for batches of `batch` pairs (for
+ *   admission decisions).
+ * A context belongs to one index, is used by one host thread at a time, and is released by
+ * dbl_query_ctx_destroy (or with its index). Its counters stay in the index's statistics.
+ */
+uint64_t dbl_query_ctx_bytes(const dbl_index *ix, uint32_t bfs_slots, uint32_t queue_cap,
+                             uint64_t batch);
+dbl_status dbl_query_ctx_create(dbl_index *ix, uint32_t bfs_slots, uint32_t queue_cap,
+                                dbl_query_ctx **out);
+/* dbl_query_batch with the scratch of `ctx`; same semantics and errors. */
+dbl_status dbl_query_batch_ctx(dbl_index *ix, dbl_query_ctx *ctx, uint64_t count,
+                               const uint32_t *d_u, const uint32_t *d_v, uint8_t *d_out,
+                               void *stream);
+void dbl_query_ctx_destroy(dbl_query_ctx *ctx);
 
 /* Copy the labels out: each argument is a device array [n] of uint64 (any may be NULL). */
 dbl_status dbl_read_labels(const dbl_index *ix, uint64_t *d_dl_in, uint64_t *d_dl_out,

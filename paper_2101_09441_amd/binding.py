@@ -21,7 +21,8 @@ CLASS_NAMES = ["self", "dl_hit", "bl_miss", "thm1", "thm2", "bfs_true", "bfs_fal
 # every symbol declared in include/dbl.h
 EXPORTS = [
     "dbl_default_options", "dbl_build", "dbl_insert_edges", "dbl_insert_edges_each",
-    "dbl_query_batch",
+    "dbl_query_batch", "dbl_query_ctx_bytes", "dbl_query_ctx_create", "dbl_query_batch_ctx",
+    "dbl_query_ctx_destroy",
     "dbl_read_labels", "dbl_get_landmarks", "dbl_get_leaves", "dbl_get_stats",
     "dbl_time_kernels", "dbl_read_kernel_times", "dbl_num_vertices", "dbl_destroy",
     "dbl_status_str",
@@ -99,6 +100,14 @@ def load_library():
     lib.dbl_insert_edges_each.restype = i32
     lib.dbl_query_batch.argtypes = [P, u64, P, P, P, P]
     lib.dbl_query_batch.restype = i32
+    lib.dbl_query_ctx_bytes.argtypes = [P, u32, u32, u64]
+    lib.dbl_query_ctx_bytes.restype = u64
+    lib.dbl_query_ctx_create.argtypes = [P, u32, u32, ctypes.POINTER(P)]
+    lib.dbl_query_ctx_create.restype = i32
+    lib.dbl_query_batch_ctx.argtypes = [P, P, u64, P, P, P, P]
+    lib.dbl_query_batch_ctx.restype = i32
+    lib.dbl_query_ctx_destroy.argtypes = [P]
+    lib.dbl_query_ctx_destroy.restype = None
     lib.dbl_read_labels.argtypes = [P, P, P, P, P, P]
     lib.dbl_read_labels.restype = i32
     lib.dbl_get_landmarks.argtypes = [P, P, ctypes.POINTER(u32)]
@@ -154,6 +163,44 @@ def to_device_ids(a, device="cuda") -> torch.Tensor:
     """numpy/sequence of ids -> int32 device tensor (bit pattern of uint32)."""
     arr = np.ascontiguousarray(np.asarray(a, dtype=np.uint32)).view(np.int32)
     return torch.from_numpy(arr.copy()).to(device)
+
+
+class QueryContext:
+    """Scratch for one in-flight query batch; several contexts let batches overlap on the device
+    (each on its own stream, driven from its own host thread)."""
+
+    def __init__(self, index: "Index", bfs_slots: int = 0, queue_cap: int = 0):
+        self.index = index
+        h = ctypes.c_void_p()
+        with torch.cuda.device(index.device):
+            _check(load_library().dbl_query_ctx_create(index._handle(), bfs_slots, queue_cap,
+                                                       ctypes.byref(h)), "dbl_query_ctx_create")
+        self._h = h
+
+    def query(self, u: torch.Tensor, v: torch.Tensor, out: Optional[torch.Tensor] = None,
+              stream=None) -> torch.Tensor:
+        u, v = _ids(u, "u"), _ids(v, "v")
+        if u.numel() != v.numel():
+            raise ValueError("u and v differ in length")
+        if out is None:
+            out = torch.empty(u.numel(), dtype=torch.uint8, device=u.device)
+        elif out.dtype != torch.uint8 or out.numel() < u.numel() or not out.is_contiguous():
+            raise ValueError("out must be a contiguous uint8 tensor with room for every pair")
+        if self._h is None or not self._h.value:
+            raise RuntimeError("query context is closed")
+        with torch.cuda.device(self.index.device):
+            st = load_library().dbl_query_batch_ctx(self.index._handle(), self._h, u.numel(),
+                                                    u.data_ptr(), v.data_ptr(), out.data_ptr(),
+                                                    _stream_ptr(stream))
+        _check(st, "dbl_query_batch_ctx")
+        return out
+
+    def close(self):
+        if self._h is not None and self._h.value and self.index._h is not None \
+                and self.index._h.value:
+            with torch.cuda.device(self.index.device):
+                load_library().dbl_query_ctx_destroy(self._h)
+        self._h = None
 
 
 class Index:
@@ -266,6 +313,12 @@ class Index:
                                                 v.data_ptr(), out.data_ptr(), _stream_ptr(stream))
         _check(st, "dbl_query_batch")
         return out
+
+    def query_context(self, bfs_slots: int = 0, queue_cap: int = 0) -> QueryContext:
+        return QueryContext(self, bfs_slots, queue_cap)
+
+    def query_context_bytes(self, bfs_slots: int = 0, queue_cap: int = 0, batch: int = 0) -> int:
+        return int(load_library().dbl_query_ctx_bytes(self._handle(), bfs_slots, queue_cap, batch))
 
     def labels(self, stream=None):
         """(DL_in, DL_out, BL_in, BL_out) as int64 device tensors holding the 64-bit patterns."""

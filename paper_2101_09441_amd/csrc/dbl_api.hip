@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -18,6 +19,28 @@ using dbl::Csr;
 using dbl::Ctl;
 using dbl::Ovf;
 using u64 = unsigned long long;
+
+// Scratch of one in-flight query batch. The index owns a default one (used by dbl_query_batch);
+// callers create more to run query batches concurrently on several streams.
+struct dbl_query_ctx {
+  dbl_index *ix = nullptr;
+  bool is_default = false;
+  Ctl *ctl = nullptr;
+  dbl::Mirror *mirror = nullptr;
+  dbl::Mirror hs{};
+  uint32_t seq = 0;
+  uint32_t *und = nullptr, *heavy_q = nullptr;
+  uint64_t und_cap = 0;
+  u64 *vis = nullptr;
+  uint64_t vis_words = 0;
+  uint32_t *bfs_queue = nullptr;
+  uint32_t slots = 0, qcap = 0;
+  u64 *bfs_cnt = nullptr;  // per-slot BFS counters
+  u64 *qcls = nullptr;     // per-block query class counters
+  u64 *gvis = nullptr;     // whole-device BFS: visited bitmap and frontier ring
+  uint32_t *gfq[3] = {nullptr, nullptr, nullptr};
+  uint64_t bfs_heavy = 0;
+};
 
 struct dbl_index {
   int device = 0;
@@ -35,9 +58,7 @@ struct dbl_index {
   dbl::Mirror *mirror = nullptr;  // pinned, device-mapped host memory written by the device
   dbl::Mirror hs{};               // host copy of the last published status
   uint32_t seq = 0;
-  u64 *pcnt = nullptr;     // per-block propagation counters
-  u64 *qcls = nullptr;     // per-block query class counters
-  u64 *bfs_cnt = nullptr;  // per-slot BFS counters
+  u64 *pcnt = nullptr;  // per-block propagation counters
   Ovf *ovf = nullptr;
   uint64_t ovf_cap = 0;
   uint32_t *landmarks_d = nullptr;
@@ -45,16 +66,14 @@ struct dbl_index {
   uint8_t *leaf_flags = nullptr, *bucket = nullptr;
   u64 *scan_tmp = nullptr, *scan_total = nullptr;
   uint64_t scan_tmp_words = 0;
-  // query scratch
-  uint32_t *und = nullptr, *heavy_q = nullptr;
-  uint64_t und_cap = 0;
-  u64 *vis = nullptr;
-  uint64_t vis_words = 0;
-  uint32_t *bfs_queue = nullptr;
-  uint32_t slots = 0, qcap = 0, slots_opt = 0, qcap_opt = 0;
-  u64 *gvis = nullptr;
+  // query contexts: the default one and those created by callers (guarded by ctx_mu)
+  uint32_t slots_opt = 0, qcap_opt = 0;
+  dbl_query_ctx *qctx = nullptr;
+  std::vector<dbl_query_ctx *> ctxs;
+  std::mutex ctx_mu;
+  uint64_t retired_class[7] = {}, retired_bfs_v = 0, retired_bfs_e = 0, retired_heavy = 0;
   // statistics kept on the host
-  uint64_t build_rounds = 0, insert_calls = 0, insert_rounds = 0, regrows = 0, bfs_heavy = 0;
+  uint64_t build_rounds = 0, insert_calls = 0, insert_rounds = 0, regrows = 0;
   // kernel timing (HIP events around selected launches)
   uint32_t time_mask = 0;
   struct Pending {
@@ -101,7 +120,7 @@ struct Timed {
   hipStream_t s;
   hipEvent_t a = nullptr;
   Timed(dbl_index *ix_, uint32_t kind_, hipStream_t s_) : ix(ix_), kind(kind_), s(s_) {
-    if (!(ix->time_mask & (1u << kind))) return;
+    if (kind >= kTKinds || !(ix->time_mask & (1u << kind))) return;
     if (ix->t_seen[kind]++ % ix->time_period) return;
     a = take_event(ix);
     if (a && hipEventRecord(a, s) != hipSuccess) {
@@ -199,32 +218,43 @@ dbl::PropArgs prop_args(const dbl_index *ix) {
   return a;
 }
 
-// Wait until the device has published status `seq` into the host mirror. The host spins on
-// the mirror; every few thousand polls it asks the stream whether it failed or went idle
-// without publishing, so a fault can never leave the host spinning.
-dbl_status wait_status(dbl_index *ix, hipStream_t s, uint32_t seq) {
-  volatile dbl::Mirror *m = ix->mirror;
+// Wait until the device has published status `seq` into the host mirror `m` and copy it to
+// `h`. The host spins on the mirror; every few thousand polls it asks the stream whether it
+// failed or went idle without publishing, so a fault can never leave the host spinning.
+dbl_status wait_mirror(dbl::Mirror *m, dbl::Mirror &h, hipStream_t s, uint32_t seq) {
   for (uint64_t spin = 1;; spin++) {
-    if (__atomic_load_n(&ix->mirror->seq, __ATOMIC_ACQUIRE) == seq) break;
+    if (__atomic_load_n(&m->seq, __ATOMIC_ACQUIRE) == seq) break;
     if ((spin & 4095) == 0) {
       const hipError_t q = hipStreamQuery(s);
       if (q == hipSuccess) {
-        if (__atomic_load_n(&ix->mirror->seq, __ATOMIC_ACQUIRE) == seq) break;
+        if (__atomic_load_n(&m->seq, __ATOMIC_ACQUIRE) == seq) break;
         return DBL_ERR_DEVICE;  // the stream drained without publishing
       }
       if (q != hipErrorNotReady) return from_hip(q);
     }
   }
-  dbl::Mirror &h = ix->hs;
+  volatile dbl::Mirror *vm = m;
   h.seq = seq;
-  h.err = m->err;
-  h.cur = m->cur;
-  h.stamp = m->stamp;
-  for (int i = 0; i < 3; i++) h.fsize[i] = m->fsize[i];
-  h.ovf_count = m->ovf_count;
-  h.und_count = m->und_count;
-  h.bfs_heavy = m->bfs_heavy;
-  h.found = m->found;
+  h.err = vm->err;
+  h.cur = vm->cur;
+  h.stamp = vm->stamp;
+  for (int i = 0; i < 3; i++) h.fsize[i] = vm->fsize[i];
+  h.ovf_count = vm->ovf_count;
+  h.und_count = vm->und_count;
+  h.bfs_heavy = vm->bfs_heavy;
+  h.found = vm->found;
+  return DBL_OK;
+}
+
+// Publish a control block after the work queued so far and wait for it.
+dbl_status sync_chan(Ctl *ctl, dbl::Mirror *m, dbl::Mirror &h, uint32_t &seq, hipStream_t s) {
+  const uint32_t sq = ++seq;
+  CK(dbl::launch_publish(ctl, m, sq, s));
+  return wait_mirror(m, h, s, sq);
+}
+
+dbl_status wait_status(dbl_index *ix, hipStream_t s, uint32_t seq) {
+  CKS(wait_mirror(ix->mirror, ix->hs, s, seq));
   if (!ix->pending.empty()) resolve_times(ix);
   return DBL_OK;
 }
@@ -232,13 +262,11 @@ dbl_status wait_status(dbl_index *ix, hipStream_t s, uint32_t seq) {
 // Wait for the fast status word of a small insertion. With no flag set the call is complete and
 // nothing else needs reading; otherwise the whole status is published and read.
 dbl_status wait_fast(dbl_index *ix, hipStream_t s, uint32_t seq, uint32_t *flags);
-dbl_status sync_ctl(dbl_index *ix, hipStream_t s);
 
-// Publish the control block after the work queued so far and wait for it.
 dbl_status sync_ctl(dbl_index *ix, hipStream_t s) {
-  const uint32_t seq = ++ix->seq;
-  CK(dbl::launch_publish(ix->ctl, ix->mirror, seq, s));
-  return wait_status(ix, s, seq);
+  CKS(sync_chan(ix->ctl, ix->mirror, ix->hs, ix->seq, s));
+  if (!ix->pending.empty()) resolve_times(ix);
+  return DBL_OK;
 }
 
 // Write one 32-bit field of the device control block (host value, stream ordered).
@@ -377,31 +405,152 @@ uint32_t bits_of(uint32_t kp) {
   return b;
 }
 
-dbl_status ensure_query_scratch(dbl_index *ix, uint64_t count) {
-  if (count > ix->und_cap) {
-    dfree(ix->und);
-    dfree(ix->heavy_q);
-    uint64_t cap = std::max<uint64_t>(count, 1024);
-    CKS(dalloc(&ix->und, cap));
-    CKS(dalloc(&ix->heavy_q, cap));
-    ix->und_cap = cap;
+uint64_t ctx_bytes(const dbl_index *ix, uint32_t slots, uint32_t qcap, uint64_t batch) {
+  const uint64_t words = (ix->n + 63) / 64;
+  return sizeof(Ctl) + words * 8 * slots + (uint64_t)qcap * 4 * slots +
+         (uint64_t)slots * dbl::kBfsCtrStride * 8 + (uint64_t)dbl::kQueryGrid * dbl::kQClsStride * 8 +
+         batch * 8;
+}
+
+void ctx_free(dbl_query_ctx *c) {
+  dfree(c->ctl);
+  if (c->mirror) (void)hipHostFree((void *)c->mirror);
+  c->mirror = nullptr;
+  dfree(c->und);
+  dfree(c->heavy_q);
+  dfree(c->vis);
+  dfree(c->bfs_queue);
+  dfree(c->bfs_cnt);
+  dfree(c->qcls);
+  dfree(c->gvis);
+  for (int i = 0; i < 3; i++) dfree(c->gfq[i]);
+}
+
+// Allocate a context's fixed scratch: control block, mirror, counters, BFS slots.
+dbl_status ctx_init(dbl_index *ix, dbl_query_ctx *c, uint32_t slots, uint32_t qcap) {
+  c->ix = ix;
+  slots = slots ? slots : (ix->slots_opt ? ix->slots_opt : 1024);
+  slots = std::max<uint32_t>(4, (slots + 3) / 4 * 4);
+  qcap = qcap ? std::min<uint32_t>(qcap, ix->n)
+              : (ix->qcap_opt ? std::min<uint32_t>(ix->qcap_opt, ix->n)
+                              : (uint32_t)std::min<uint64_t>(ix->n, 1u << 18));
+  const uint64_t words = (ix->n + 63) / 64;
+  hipStream_t s0 = nullptr;
+  CKS(dalloc(&c->ctl, 1));
+  CK(hipHostMalloc((void **)&c->mirror, sizeof(dbl::Mirror),
+                   hipHostMallocMapped | hipHostMallocCoherent));
+  memset((void *)c->mirror, 0, sizeof(dbl::Mirror));
+  {
+    Ctl init;
+    memset(&init, 0, sizeof(init));
+    CK(hipMemcpy(c->ctl, &init, sizeof(Ctl), hipMemcpyHostToDevice));
   }
-  if (!ix->vis) {
-    uint32_t slots = ix->slots_opt ? ix->slots_opt : 1024;
-    slots = std::max<uint32_t>(4, (slots + 3) / 4 * 4);
-    const uint64_t words = (ix->n + 63) / 64;
-    const uint32_t qcap = ix->qcap_opt ? std::min<uint32_t>(ix->qcap_opt, ix->n)
-                                       : (uint32_t)std::min<uint64_t>(ix->n, 1u << 18);
-    CKS(dalloc(&ix->vis, words * slots));
-    CKS(dalloc(&ix->bfs_queue, (uint64_t)qcap * slots));
-    CKS(dalloc(&ix->bfs_cnt, (uint64_t)slots * dbl::kBfsCtrStride));
-    hipStream_t s0 = nullptr;
-    CK(dbl::launch_fill_u64(ix->vis, 0ull, words * slots, s0));
-    CK(dbl::launch_fill_u64(ix->bfs_cnt, 0ull, (uint64_t)slots * dbl::kBfsCtrStride, s0));
-    CK(hipStreamSynchronize(s0));
-    ix->slots = slots;
-    ix->vis_words = words;
-    ix->qcap = qcap;
+  CKS(dalloc(&c->vis, words * slots));
+  CKS(dalloc(&c->bfs_queue, (uint64_t)qcap * slots));
+  CKS(dalloc(&c->bfs_cnt, (uint64_t)slots * dbl::kBfsCtrStride));
+  CKS(dalloc(&c->qcls, (uint64_t)dbl::kQueryGrid * dbl::kQClsStride));
+  CK(dbl::launch_fill_u64(c->vis, 0ull, words * slots, s0));
+  CK(dbl::launch_fill_u64(c->bfs_cnt, 0ull, (uint64_t)slots * dbl::kBfsCtrStride, s0));
+  CK(dbl::launch_fill_u64(c->qcls, 0ull, (uint64_t)dbl::kQueryGrid * dbl::kQClsStride, s0));
+  CK(hipStreamSynchronize(s0));
+  c->slots = slots;
+  c->vis_words = words;
+  c->qcap = qcap;
+  return DBL_OK;
+}
+
+dbl_status ctx_reserve(dbl_query_ctx *c, uint64_t count) {
+  if (count <= c->und_cap) return DBL_OK;
+  dfree(c->und);
+  dfree(c->heavy_q);
+  const uint64_t cap = std::max<uint64_t>(count, 1024);
+  CKS(dalloc(&c->und, cap));
+  CKS(dalloc(&c->heavy_q, cap));
+  c->und_cap = cap;
+  return DBL_OK;
+}
+
+// Host copy of a context's counters, added into `out`.
+dbl_status ctx_add_counts(const dbl_query_ctx *c, uint64_t cls[7], uint64_t *bv, uint64_t *be) {
+  std::vector<u64> qc((uint64_t)dbl::kQueryGrid * dbl::kQClsStride), bc((uint64_t)c->slots * dbl::kBfsCtrStride);
+  CK(hipMemcpy(qc.data(), c->qcls, sizeof(u64) * qc.size(), hipMemcpyDeviceToHost));
+  CK(hipMemcpy(bc.data(), c->bfs_cnt, sizeof(u64) * bc.size(), hipMemcpyDeviceToHost));
+  for (uint32_t b = 0; b < dbl::kQueryGrid; b++)
+    for (uint32_t k = 0; k < 7; k++) cls[k] += qc[b * dbl::kQClsStride + k];
+  for (uint32_t sl = 0; sl < c->slots; sl++) {
+    *bv += bc[sl * dbl::kBfsCtrStride + 0];
+    *be += bc[sl * dbl::kBfsCtrStride + 1];
+    cls[5] += bc[sl * dbl::kBfsCtrStride + 2];
+    cls[6] += bc[sl * dbl::kBfsCtrStride + 3];
+  }
+  return DBL_OK;
+}
+
+// Algorithm 2 over a batch with the scratch of context c (see dbl_query_batch).
+dbl_status run_queries(dbl_index *ix, dbl_query_ctx *c, uint64_t count, const uint32_t *d_u,
+                       const uint32_t *d_v, uint8_t *d_out, hipStream_t s) {
+  CKS(ctx_reserve(c, count));
+  CK(dbl::launch_ctl_reset_query(c->ctl, s));
+  {
+    Timed tm(ix, c->is_default ? (uint32_t)kTQueryLabel : (uint32_t)kTKinds, s);
+    CK(dbl::launch_query_label({ix->lab}, d_u, d_v, count, ix->n, d_out, c->und, c->ctl, c->qcls,
+                               s));
+  }
+  dbl::BfsArgs b;
+  b.L.lab = ix->lab;
+  b.f = ix->f;
+  b.u = d_u;
+  b.v = d_v;
+  b.und = c->und;
+  b.out = d_out;
+  b.vis = c->vis;
+  b.vis_words = c->vis_words;
+  b.queue = c->bfs_queue;
+  b.qcap = c->qcap;
+  b.heavy_q = c->heavy_q;
+  b.cnt = c->bfs_cnt;
+  b.ctl = c->ctl;
+  {
+    Timed tm(ix, c->is_default ? (uint32_t)kTQueryBfs : (uint32_t)kTKinds, s);
+    CK(dbl::launch_query_bfs(b, c->slots, s));
+  }
+  CKS(sync_chan(c->ctl, c->mirror, c->hs, c->seq, s));
+  if (c->is_default && !ix->pending.empty()) resolve_times(ix);
+  if (c->hs.err) {
+    CK(dbl::launch_fill_u32((uint32_t *)((char *)c->ctl + offsetof(Ctl, err)), 0u, 1, s));
+    CK(hipStreamSynchronize(s));
+    return DBL_ERR_VERTEX_RANGE;
+  }
+  const uint32_t nheavy = c->hs.bfs_heavy;
+  if (nheavy) {
+    // pairs whose pruned BFS outgrew a slot: one whole-device BFS each (rare)
+    std::vector<uint32_t> hq(nheavy);
+    CK(hipMemcpyAsync(hq.data(), c->heavy_q, sizeof(uint32_t) * nheavy, hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    if (!c->gvis) {
+      CKS(dalloc(&c->gvis, c->vis_words));
+      for (int i = 0; i < 3; i++) CKS(dalloc(&c->gfq[i], ix->n));
+    }
+    dbl::PropArgs a = prop_args(ix);
+    for (int i = 0; i < 3; i++) a.fq[i] = c->gfq[i];
+    a.ctl = c->ctl;
+    for (uint32_t i = 0; i < nheavy; i++) {
+      uint32_t u = 0, v = 0;
+      CK(hipMemcpyAsync(&u, d_u + hq[i], sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+      CK(hipMemcpyAsync(&v, d_v + hq[i], sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+      CK(hipStreamSynchronize(s));
+      CK(dbl::launch_gbfs_start(a, c->gvis, c->vis_words, u, s));
+      uint32_t ring = 0;
+      for (;;) {
+        CK(dbl::launch_gbfs_round(a, c->gvis, u, v, ring, s));
+        ring = ring == 2 ? 0 : ring + 1;
+        CKS(sync_chan(c->ctl, c->mirror, c->hs, c->seq, s));
+        if (c->hs.found || c->hs.fsize[ring] == 0) break;
+      }
+      CK(dbl::launch_gbfs_finish(a, hq[i], d_out, c->qcls, s));
+    }
+    CK(hipStreamSynchronize(s));
+    c->bfs_heavy += nheavy;
   }
   return DBL_OK;
 }
@@ -414,9 +563,7 @@ dbl_status do_build(dbl_index *ix, uint64_t m, const uint32_t *src, const uint32
                    hipHostMallocMapped | hipHostMallocCoherent));
   memset((void *)ix->mirror, 0, sizeof(dbl::Mirror));
   CKS(dalloc(&ix->pcnt, 2ull * dbl::kPropCtrSlots));
-  CKS(dalloc(&ix->qcls, (uint64_t)dbl::kQueryGrid * dbl::kQClsStride));
   CK(dbl::launch_fill_u64(ix->pcnt, 0ull, 2ull * dbl::kPropCtrSlots, s));
-  CK(dbl::launch_fill_u64(ix->qcls, 0ull, (uint64_t)dbl::kQueryGrid * dbl::kQClsStride, s));
   {
     Ctl init;
     memset(&init, 0, sizeof(init));
@@ -676,64 +823,77 @@ dbl_status dbl_query_batch(dbl_index *ix, uint64_t count, const uint32_t *d_u,
   if (!d_u || !d_v || !d_out || count > 0xFFFFFFFFull) return DBL_ERR_INVALID_ARG;
   DeviceGuard dg(ix->device);
   hipStream_t s = (hipStream_t)stream;
-  CKS(ensure_query_scratch(ix, count));
-  CK(dbl::launch_ctl_reset_query(ix->ctl, s));
-  {
-    Timed tm(ix, kTQueryLabel, s);
-    CK(dbl::launch_query_label({ix->lab}, d_u, d_v, count, ix->n, d_out, ix->und, ix->ctl,
-                               ix->qcls, s));
-  }
-  dbl::BfsArgs b;
-  b.L.lab = ix->lab;
-  b.f = ix->f;
-  b.u = d_u;
-  b.v = d_v;
-  b.und = ix->und;
-  b.out = d_out;
-  b.vis = ix->vis;
-  b.vis_words = ix->vis_words;
-  b.queue = ix->bfs_queue;
-  b.qcap = ix->qcap;
-  b.heavy_q = ix->heavy_q;
-  b.cnt = ix->bfs_cnt;
-  b.ctl = ix->ctl;
-  {
-    Timed tm(ix, kTQueryBfs, s);
-    CK(dbl::launch_query_bfs(b, ix->slots, s));
-  }
-  CKS(sync_ctl(ix, s));
-  if (ix->hs.err) {
-    CKS(set_ctl_u32(ix, offsetof(Ctl, err), 0u, s));
-    CK(hipStreamSynchronize(s));
-    return DBL_ERR_VERTEX_RANGE;
-  }
-  const uint32_t nheavy = ix->hs.bfs_heavy;
-  if (nheavy) {
-    std::vector<uint32_t> hq(nheavy), hu(nheavy), hv(nheavy);
-    CK(hipMemcpyAsync(hq.data(), ix->heavy_q, sizeof(uint32_t) * nheavy, hipMemcpyDeviceToHost, s));
-    CK(hipStreamSynchronize(s));
-    if (!ix->gvis) CKS(dalloc(&ix->gvis, ix->vis_words));
-    dbl::PropArgs a = prop_args(ix);
-    for (uint32_t i = 0; i < nheavy; i++) {
-      uint32_t u = 0, v = 0;
-      CK(hipMemcpyAsync(&u, d_u + hq[i], sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-      CK(hipMemcpyAsync(&v, d_v + hq[i], sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-      CK(hipStreamSynchronize(s));
-      CK(dbl::launch_gbfs_start(a, ix->gvis, ix->vis_words, u, s));
-      uint32_t ring = 0;
-      for (;;) {
-        CK(dbl::launch_gbfs_round(a, ix->gvis, u, v, ring, s));
-        ring = ring == 2 ? 0 : ring + 1;
-        CKS(sync_ctl(ix, s));
-        if (ix->hs.found || ix->hs.fsize[ring] == 0) break;
-      }
-      CK(dbl::launch_gbfs_finish(a, hq[i], d_out, ix->qcls, s));
+  if (!ix->qctx) {
+    dbl_query_ctx *c = new (std::nothrow) dbl_query_ctx();
+    if (!c) return DBL_ERR_OUT_OF_MEMORY;
+    c->is_default = true;
+    const dbl_status st = ctx_init(ix, c, 0, 0);
+    if (st != DBL_OK) {
+      ctx_free(c);
+      delete c;
+      return st;
     }
-    // the propagation frontier was borrowed: it is empty again, keep its ring position
-    CK(hipStreamSynchronize(s));
-    ix->bfs_heavy += nheavy;
+    ix->qctx = c;
   }
+  return run_queries(ix, ix->qctx, count, d_u, d_v, d_out, s);
+}
+
+uint64_t dbl_query_ctx_bytes(const dbl_index *ix, uint32_t bfs_slots, uint32_t queue_cap,
+                             uint64_t batch) {
+  if (!ix) return 0;
+  uint32_t slots = bfs_slots ? bfs_slots : (ix->slots_opt ? ix->slots_opt : 1024);
+  slots = std::max<uint32_t>(4, (slots + 3) / 4 * 4);
+  const uint32_t qcap = queue_cap ? std::min<uint32_t>(queue_cap, ix->n)
+                                  : (uint32_t)std::min<uint64_t>(ix->n, 1u << 18);
+  return ctx_bytes(ix, slots, qcap, batch);
+}
+
+dbl_status dbl_query_ctx_create(dbl_index *ix, uint32_t bfs_slots, uint32_t queue_cap,
+                                dbl_query_ctx **out) {
+  if (!ix || !out) return DBL_ERR_INVALID_ARG;
+  *out = nullptr;
+  DeviceGuard dg(ix->device);
+  dbl_query_ctx *c = new (std::nothrow) dbl_query_ctx();
+  if (!c) return DBL_ERR_OUT_OF_MEMORY;
+  const dbl_status st = ctx_init(ix, c, bfs_slots, queue_cap);
+  if (st != DBL_OK) {
+    ctx_free(c);
+    delete c;
+    return st;
+  }
+  std::lock_guard<std::mutex> lk(ix->ctx_mu);
+  ix->ctxs.push_back(c);
+  *out = c;
   return DBL_OK;
+}
+
+dbl_status dbl_query_batch_ctx(dbl_index *ix, dbl_query_ctx *ctx, uint64_t count,
+                               const uint32_t *d_u, const uint32_t *d_v, uint8_t *d_out,
+                               void *stream) {
+  if (!ix || !ctx || ctx->ix != ix) return DBL_ERR_INVALID_ARG;
+  if (count == 0) return DBL_OK;
+  if (!d_u || !d_v || !d_out || count > 0xFFFFFFFFull) return DBL_ERR_INVALID_ARG;
+  DeviceGuard dg(ix->device);
+  return run_queries(ix, ctx, count, d_u, d_v, d_out, (hipStream_t)stream);
+}
+
+void dbl_query_ctx_destroy(dbl_query_ctx *ctx) {
+  if (!ctx) return;
+  dbl_index *ix = ctx->ix;
+  DeviceGuard dg(ix->device);
+  {
+    std::lock_guard<std::mutex> lk(ix->ctx_mu);
+    uint64_t cls[7] = {}, bv = 0, be = 0;
+    if (ctx_add_counts(ctx, cls, &bv, &be) == DBL_OK) {
+      for (int k = 0; k < 7; k++) ix->retired_class[k] += cls[k];
+      ix->retired_bfs_v += bv;
+      ix->retired_bfs_e += be;
+    }
+    ix->retired_heavy += ctx->bfs_heavy;
+    ix->ctxs.erase(std::remove(ix->ctxs.begin(), ix->ctxs.end(), ctx), ix->ctxs.end());
+  }
+  ctx_free(ctx);
+  delete ctx;
 }
 
 dbl_status dbl_read_labels(const dbl_index *ix, uint64_t *d_dl_in, uint64_t *d_dl_out,
@@ -762,17 +922,12 @@ dbl_status dbl_get_leaves(const dbl_index *ix, uint8_t *h_flags, uint8_t *h_buck
   return DBL_OK;
 }
 
-dbl_status dbl_get_stats(const dbl_index *ix, dbl_stats *out) {
-  if (!ix || !out) return DBL_ERR_INVALID_ARG;
+dbl_status dbl_get_stats(const dbl_index *ix_c, dbl_stats *out) {
+  if (!ix_c || !out) return DBL_ERR_INVALID_ARG;
+  dbl_index *ix = const_cast<dbl_index *>(ix_c);
   DeviceGuard dg(ix->device);
-  std::vector<u64> pc(2ull * dbl::kPropCtrSlots), qc((uint64_t)dbl::kQueryGrid * dbl::kQClsStride);
+  std::vector<u64> pc(2ull * dbl::kPropCtrSlots);
   CK(hipMemcpy(pc.data(), ix->pcnt, sizeof(u64) * pc.size(), hipMemcpyDeviceToHost));
-  CK(hipMemcpy(qc.data(), ix->qcls, sizeof(u64) * qc.size(), hipMemcpyDeviceToHost));
-  std::vector<u64> bc;
-  if (ix->bfs_cnt) {
-    bc.resize((uint64_t)ix->slots * dbl::kBfsCtrStride);
-    CK(hipMemcpy(bc.data(), ix->bfs_cnt, sizeof(u64) * bc.size(), hipMemcpyDeviceToHost));
-  }
   uint64_t stored = 0;
   {
     std::vector<uint32_t> deg(ix->n);
@@ -789,16 +944,23 @@ dbl_status dbl_get_stats(const dbl_index *ix, dbl_stats *out) {
     out->edges_relaxed += pc[2 * b + 1];
   }
   out->csr_regrows = ix->regrows;
-  for (uint32_t b = 0; b < dbl::kQueryGrid; b++)
-    for (uint32_t c = 0; c < 7; c++) out->query_class[c] += qc[b * dbl::kQClsStride + c];
-  for (uint32_t sl = 0; sl < ix->slots; sl++) {
-    out->bfs_vertices += bc[sl * dbl::kBfsCtrStride + 0];
-    out->bfs_edges += bc[sl * dbl::kBfsCtrStride + 1];
-    out->query_class[5] += bc[sl * dbl::kBfsCtrStride + 2];
-    out->query_class[6] += bc[sl * dbl::kBfsCtrStride + 3];
+  std::lock_guard<std::mutex> lk(ix->ctx_mu);
+  uint64_t cls[7] = {}, bv = ix->retired_bfs_v, be = ix->retired_bfs_e;
+  for (int k = 0; k < 7; k++) cls[k] = ix->retired_class[k];
+  uint64_t heavy = ix->retired_heavy;
+  std::vector<dbl_query_ctx *> all(ix->ctxs);
+  if (ix->qctx) all.push_back(ix->qctx);
+  for (dbl_query_ctx *c : all) {
+    CKS(ctx_add_counts(c, cls, &bv, &be));
+    heavy += c->bfs_heavy;
   }
-  for (uint32_t c = 0; c < 7; c++) out->queries += out->query_class[c];
-  out->bfs_heavy = ix->bfs_heavy;
+  for (int k = 0; k < 7; k++) {
+    out->query_class[k] = cls[k];
+    out->queries += cls[k];
+  }
+  out->bfs_vertices = bv;
+  out->bfs_edges = be;
+  out->bfs_heavy = heavy;
   return DBL_OK;
 }
 
@@ -876,19 +1038,21 @@ void dbl_destroy(dbl_index *ix) {
   dfree(ix->ctl);
   if (ix->mirror) (void)hipHostFree((void *)ix->mirror);
   dfree(ix->pcnt);
-  dfree(ix->qcls);
-  dfree(ix->bfs_cnt);
   dfree(ix->ovf);
   dfree(ix->landmarks_d);
   dfree(ix->leaf_flags);
   dfree(ix->bucket);
   dfree(ix->scan_tmp);
   dfree(ix->scan_total);
-  dfree(ix->und);
-  dfree(ix->heavy_q);
-  dfree(ix->vis);
-  dfree(ix->bfs_queue);
-  dfree(ix->gvis);
+  for (dbl_query_ctx *c : ix->ctxs) {
+    ctx_free(c);
+    delete c;
+  }
+  ix->ctxs.clear();
+  if (ix->qctx) {
+    ctx_free(ix->qctx);
+    delete ix->qctx;
+  }
   for (const auto &p : ix->pending) {
     (void)hipEventDestroy(p.a);
     (void)hipEventDestroy(p.b);
