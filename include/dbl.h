@@ -79,7 +79,17 @@ typedef struct {
   /* Nonzero: the build edges are known to hold no duplicate (the hash de-duplication pass is
      skipped). Self-loops are always dropped. */
   uint32_t edges_unique;
+  /* Landmark ranking (Table 3): 0 = |Pre|*|Suc| (the paper's choice, default), 1 = max,
+     2 = min, 3 = sum of |Pre| and |Suc|. Ties go to the smaller id. */
+  uint32_t landmark_rank;
+  /* Leaf threshold r (the leaf-selection paragraph of the experiments): 0 = leaves are the
+     zero-in / zero-out-degree vertices (default); r > 0 = every non-landmark vertex with
+     |Pre|*|Suc| <= r is a source of both BL labels. */
+  uint64_t leaf_threshold;
 } dbl_options;
+
+/* Which labels a query may use (the ablations of Table 4). */
+enum { DBL_RULES_DL = 1, DBL_RULES_BL = 2, DBL_RULES_ALL = 3 };
 
 typedef struct {
   uint64_t num_edges;         /* stored forward adjacency entries (build edges + insertions) */
@@ -163,6 +173,14 @@ dbl_status dbl_query_batch_ctx(dbl_index *ix, dbl_query_ctx *ctx, uint64_t count
                                const uint32_t *d_u, const uint32_t *d_v, uint8_t *d_out,
                                void *stream);
 void dbl_query_ctx_destroy(dbl_query_ctx *ctx);
+
+/* dbl_query_batch using only the labels in `rules` (DBL_RULES_*): without DL the rules of
+   Lemma 1 and Theorems 1-2 and the BFS's DL prune are skipped; without BL the rule of Lemma 2
+   and the BL prune. Answers stay exact; only the decision classes and the BFS work change.
+   ctx may be NULL (the index's own context). */
+dbl_status dbl_query_batch_rules(dbl_index *ix, dbl_query_ctx *ctx, uint64_t count,
+                                 const uint32_t *d_u, const uint32_t *d_v, uint8_t *d_out,
+                                 uint32_t rules, void *stream);
 
 /* Copy the labels out: each argument is a device array [n] of uint64 (any may be NULL). */
 dbl_status dbl_read_labels(const dbl_index *ix, uint64_t *d_dl_in, uint64_t *d_dl_out,

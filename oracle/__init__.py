@@ -24,6 +24,8 @@ _lib = None
 
 CLASS_SELF, CLASS_R1, CLASS_R2, CLASS_R3, CLASS_R4, CLASS_BFS_TRUE, CLASS_BFS_FALSE = range(7)
 CLASS_NAMES = ["self", "R1_dl_hit", "R2_bl_miss", "R3_thm1", "R4_thm2", "bfs_true", "bfs_false"]
+RULES_DL, RULES_BL = 1, 2
+RANK_PRODUCT, RANK_MAX, RANK_MIN, RANK_SUM = range(4)
 
 
 def build() -> str:
@@ -58,6 +60,10 @@ def _load():
         f = getattr(lib, name)
         f.argtypes = [P, u64, P, P, P, u32]
         f.restype = i32
+    lib.orc_query_dbl_rules.argtypes = [P, u64, P, P, P, u32, u32]
+    lib.orc_query_dbl_rules.restype = i32
+    lib.orc_set_selection.argtypes = [P, u32, u64]
+    lib.orc_set_selection.restype = None
     lib.orc_query_label_class.argtypes = [P, u64, P, P, P]
     lib.orc_query_label_class.restype = i32
     lib.orc_insert.argtypes = [P, u64, P, P]
@@ -118,9 +124,13 @@ class OracleIndex:
 
     # -- construction (Algorithm 1)
     def build(self, k: int = 64, kp: int = 64, landmarks=None, bucket_table=None,
-              leaf_flags=None, threads: int = 1) -> "OracleIndex":
-        """Algorithm 1. ``leaf_flags``: optional uint8[n], bit 0 = in S_in, bit 1 = in S_out."""
+              leaf_flags=None, threads: int = 1, rank: int = RANK_PRODUCT,
+              leaf_threshold: int = 0) -> "OracleIndex":
+        """Algorithm 1. ``leaf_flags``: optional uint8[n], bit 0 = in S_in, bit 1 = in S_out.
+        ``rank``: landmark ranking (product, max, min, sum of |Pre| and |Suc|);
+        ``leaf_threshold``: r of the generalised leaf rule (0 = zero in/out degree)."""
         lib = _load()
+        lib.orc_set_selection(self._h, rank, leaf_threshold)
         lm = None if landmarks is None else _u32(landmarks)
         if lm is not None and len(lm) < min(k, self.n):
             raise ValueError("need k landmarks")
@@ -170,6 +180,16 @@ class OracleIndex:
     def query_dbl(self, u, v, threads: int = 1) -> np.ndarray:
         """Algorithm 2: answer | class << 1 per pair."""
         return self._q(_load().orc_query_dbl, u, v, threads)
+
+    def query_rules(self, u, v, rules: int, threads: int = 1) -> np.ndarray:
+        """Algorithm 2 using only the labels in ``rules`` (RULES_DL | RULES_BL)."""
+        u, v = _u32(u), _u32(v)
+        out = np.zeros(max(len(u), 1), dtype=np.uint8)
+        rc = _load().orc_query_dbl_rules(self._h, len(u), u.ctypes.data, v.ctypes.data,
+                                         out.ctypes.data, rules, threads)
+        if rc:
+            raise ValueError("query failed (vertex id out of range?)")
+        return out[:len(u)].copy()
 
     def query_truth(self, u, v, threads: int = 1) -> np.ndarray:
         """Plain BFS reachability (no labels): 1 if u reaches v."""

@@ -41,6 +41,13 @@
  *       the caller supplies a bucket table (the worked example of the paper gives one).
  *   R9  Algorithm 3's skip test (Lemma 1: u already reaches v) skips all four label updates.
  *   R10 Inserted self-loops are no-ops; inserted duplicates change no label.
+ *   R11 The ablations of Table 4 ("the other label disabled"): with DL disabled the rules of
+ *       Lemma 1 and Theorems 1-2 and the DL prune of the BFS are skipped; with BL disabled the
+ *       rule of Lemma 2 and the BL prune are skipped. Answers stay exact.
+ *   R12 Selection variants of Table 3: the landmark rank may be max, min or sum of |Pre| and
+ *       |Suc| instead of their product (ties by smaller id). Leaf threshold r (the leaf-
+ *       selection paragraph of the experiments): r = 0 is the main body's rule (R7); r > 0
+ *       makes every non-landmark vertex with |Pre|*|Suc| <= r a source of both BL labels.
  */
 #include <pthread.h>
 #include <stdint.h>
@@ -70,6 +77,8 @@ typedef struct {
   orc_list *suc; /* Suc(x) */
   orc_list *pre; /* Pre(x) */
   uint32_t k, kp;
+  uint32_t rank_mode;       /* 0 product, 1 max, 2 min, 3 sum */
+  uint64_t leaf_threshold;  /* r */
   uint32_t landmark[64];
   uint8_t *in_leaf, *out_leaf; /* membership in S_in / S_out, fixed at build */
   uint8_t *bucket;             /* h(x) for every x */
@@ -157,12 +166,27 @@ orc_index *orc_new(uint32_t n, uint64_t m, const uint32_t *src, const uint32_t *
 uint32_t orc_out_degree(const orc_index *ix, uint32_t x) { return ix->suc[x].len; }
 uint32_t orc_in_degree(const orc_index *ix, uint32_t x) { return ix->pre[x].len; }
 
-/* Landmark selection (Section 3.1): top-k by M(u) = |Pre(u)| * |Suc(u)|; ties by smaller id. */
+/* Landmark rank (Section 3.1: M(u) = |Pre(u)| * |Suc(u)|; Table 3's variants: max, min, sum). */
+static uint64_t rank_of(const orc_index *ix, uint32_t x) {
+  uint64_t p = ix->pre[x].len, s = ix->suc[x].len;
+  switch (ix->rank_mode) {
+    case 1: return p > s ? p : s;
+    case 2: return p < s ? p : s;
+    case 3: return p + s;
+    default: return p * s;
+  }
+}
+
+/* Landmark selection: top-k by rank; ties by smaller id. */
 static int ranks_before(const orc_index *ix, uint32_t a, uint32_t b) {
-  uint64_t ma = (uint64_t)ix->pre[a].len * ix->suc[a].len;
-  uint64_t mb = (uint64_t)ix->pre[b].len * ix->suc[b].len;
+  uint64_t ma = rank_of(ix, a), mb = rank_of(ix, b);
   if (ma != mb) return ma > mb;
   return a < b;
+}
+
+void orc_set_selection(orc_index *ix, uint32_t rank_mode, uint64_t leaf_threshold) {
+  ix->rank_mode = rank_mode;
+  ix->leaf_threshold = leaf_threshold;
 }
 
 uint32_t orc_select_landmarks(const orc_index *ix, uint32_t k, uint32_t *out) {
@@ -309,6 +333,9 @@ int orc_build(orc_index *ix, uint32_t k, uint32_t kp, const uint32_t *landmarks,
     if (leaf_flags) {
       ix->in_leaf[x] = leaf_flags[x] & 1;
       ix->out_leaf[x] = (leaf_flags[x] >> 1) & 1;
+    } else if (ix->leaf_threshold) {
+      const uint64_t m = (uint64_t)ix->pre[x].len * ix->suc[x].len;
+      ix->in_leaf[x] = ix->out_leaf[x] = !is_landmark[x] && m <= ix->leaf_threshold;
     } else {
       ix->in_leaf[x] = !is_landmark[x] && ix->pre[x].len == 0;
       ix->out_leaf[x] = !is_landmark[x] && ix->suc[x].len == 0;
@@ -392,18 +419,23 @@ static int bl_contain(const orc_index *ix, uint32_t x, uint32_t y) {
   return (ix->bl_in[x] & ~ix->bl_in[y]) == 0 && (ix->bl_out[y] & ~ix->bl_out[x]) == 0;
 }
 
-/* The label-only part of Algorithm 2; returns a class, or -1 if the labels cannot decide. */
-static int label_rules(const orc_index *ix, uint32_t u, uint32_t v) {
+#define ORC_RULES_DL 1u
+#define ORC_RULES_BL 2u
+
+/* The label-only part of Algorithm 2; returns a class, or -1 if the labels cannot decide.
+   rules: which labels may be used (reading R11). */
+static int label_rules(const orc_index *ix, uint32_t u, uint32_t v, uint32_t rules) {
+  const int dl = (rules & ORC_RULES_DL) != 0, bl = (rules & ORC_RULES_BL) != 0;
   if (u == v) return ORC_CLASS_SELF;
-  if (dl_intersec(ix, u, v)) return ORC_CLASS_R1_DL_HIT;
-  if (!bl_contain(ix, u, v)) return ORC_CLASS_R2_BL_MISS;
-  if (dl_intersec(ix, v, u)) return ORC_CLASS_R3_THM1;
-  if (dl_intersec(ix, u, u) || dl_intersec(ix, v, v)) return ORC_CLASS_R4_THM2;
+  if (dl && dl_intersec(ix, u, v)) return ORC_CLASS_R1_DL_HIT;
+  if (bl && !bl_contain(ix, u, v)) return ORC_CLASS_R2_BL_MISS;
+  if (dl && dl_intersec(ix, v, u)) return ORC_CLASS_R3_THM1;
+  if (dl && (dl_intersec(ix, u, u) || dl_intersec(ix, v, v))) return ORC_CLASS_R4_THM2;
   return -1;
 }
 
 /* Algorithm 2's pruned BFS from u looking for v (reading R3: visited marks on enqueue). */
-static int pruned_bfs(const orc_index *ix, orc_bfs_ws *w, uint32_t u, uint32_t v) {
+static int pruned_bfs(const orc_index *ix, orc_bfs_ws *w, uint32_t u, uint32_t v, uint32_t rules) {
   ws_next_stamp(w, ix->n);
   uint64_t head = 0, tail = 0;
   w->seen[u] = w->stamp;
@@ -414,8 +446,8 @@ static int pruned_bfs(const orc_index *ix, orc_bfs_ws *w, uint32_t u, uint32_t v
     for (uint32_t j = 0; j < s->len; j++) {
       uint32_t x = s->v[j];
       if (x == v) return 1;
-      if (dl_intersec(ix, u, x)) continue; /* a landmark of u reaches x */
-      if (!bl_contain(ix, x, v)) continue; /* x cannot reach v */
+      if ((rules & ORC_RULES_DL) && dl_intersec(ix, u, x)) continue; /* a landmark of u reaches x */
+      if ((rules & ORC_RULES_BL) && !bl_contain(ix, x, v)) continue; /* x cannot reach v */
       if (w->seen[x] == w->stamp) continue;
       w->seen[x] = w->stamp;
       w->queue[tail++] = x;
@@ -452,6 +484,7 @@ typedef struct {
   uint64_t count;
   uint64_t next;
   int mode; /* 0 = Algorithm 2 (answer | class << 1), 1 = plain BFS truth (answer only) */
+  uint32_t rules;
   int failed;
 } orc_qpool;
 
@@ -475,10 +508,10 @@ static void *query_worker(void *arg) {
         p->out[i] = (uint8_t)plain_reach(p->ix, &w, u, v);
         continue;
       }
-      int c = label_rules(p->ix, u, v);
+      int c = label_rules(p->ix, u, v, p->rules);
       int ans;
       if (c < 0) {
-        ans = pruned_bfs(p->ix, &w, u, v);
+        ans = pruned_bfs(p->ix, &w, u, v, p->rules);
         c = ans ? ORC_CLASS_BFS_TRUE : ORC_CLASS_BFS_FALSE;
       } else {
         ans = (c == ORC_CLASS_SELF || c == ORC_CLASS_R1_DL_HIT);
@@ -491,10 +524,10 @@ static void *query_worker(void *arg) {
 }
 
 static int run_queries(const orc_index *ix, uint64_t count, const uint32_t *u, const uint32_t *v,
-                       uint8_t *out, int mode, uint32_t threads) {
+                       uint8_t *out, int mode, uint32_t rules, uint32_t threads) {
   for (uint64_t i = 0; i < count; i++)
     if (u[i] >= ix->n || v[i] >= ix->n) return -1;
-  orc_qpool pool = {ix, u, v, out, count, 0, mode, 0};
+  orc_qpool pool = {ix, u, v, out, count, 0, mode, rules, 0};
   if (threads <= 1) {
     query_worker(&pool);
   } else {
@@ -513,13 +546,19 @@ static int run_queries(const orc_index *ix, uint64_t count, const uint32_t *u, c
 /* Algorithm 2 per pair: out[i] = answer | (class << 1). */
 int orc_query_dbl(const orc_index *ix, uint64_t count, const uint32_t *u, const uint32_t *v,
                   uint8_t *out, uint32_t threads) {
-  return run_queries(ix, count, u, v, out, 0, threads);
+  return run_queries(ix, count, u, v, out, 0, ORC_RULES_DL | ORC_RULES_BL, threads);
+}
+
+/* Algorithm 2 with only some labels (reading R11): rules bit 0 = DL, bit 1 = BL. */
+int orc_query_dbl_rules(const orc_index *ix, uint64_t count, const uint32_t *u, const uint32_t *v,
+                        uint8_t *out, uint32_t rules, uint32_t threads) {
+  return run_queries(ix, count, u, v, out, 0, rules, threads);
 }
 
 /* Plain BFS reachability per pair: out[i] = 1 if u reaches v (u reaches u). */
 int orc_query_truth(const orc_index *ix, uint64_t count, const uint32_t *u, const uint32_t *v,
                     uint8_t *out, uint32_t threads) {
-  return run_queries(ix, count, u, v, out, 1, threads);
+  return run_queries(ix, count, u, v, out, 1, 0, threads);
 }
 
 /* Label-only part of Algorithm 2: out[i] = class of the first deciding rule, or 0xFF. */
@@ -527,7 +566,7 @@ int orc_query_label_class(const orc_index *ix, uint64_t count, const uint32_t *u
                           const uint32_t *v, uint8_t *out) {
   for (uint64_t i = 0; i < count; i++) {
     if (u[i] >= ix->n || v[i] >= ix->n) return -1;
-    int c = label_rules(ix, u[i], v[i]);
+    int c = label_rules(ix, u[i], v[i], ORC_RULES_DL | ORC_RULES_BL);
     out[i] = (uint8_t)(c < 0 ? 0xFF : c);
   }
   return 0;

@@ -22,7 +22,7 @@ CLASS_NAMES = ["self", "dl_hit", "bl_miss", "thm1", "thm2", "bfs_true", "bfs_fal
 EXPORTS = [
     "dbl_default_options", "dbl_build", "dbl_insert_edges", "dbl_insert_edges_each",
     "dbl_query_batch", "dbl_query_ctx_bytes", "dbl_query_ctx_create", "dbl_query_batch_ctx",
-    "dbl_query_ctx_destroy",
+    "dbl_query_ctx_destroy", "dbl_query_batch_rules",
     "dbl_read_labels", "dbl_get_landmarks", "dbl_get_leaves", "dbl_get_stats",
     "dbl_time_kernels", "dbl_read_kernel_times", "dbl_num_vertices", "dbl_destroy",
     "dbl_status_str",
@@ -41,6 +41,8 @@ class DblOptions(ctypes.Structure):
         ("bfs_slots", ctypes.c_uint32),
         ("bfs_queue_cap", ctypes.c_uint32),
         ("edges_unique", ctypes.c_uint32),
+        ("landmark_rank", ctypes.c_uint32),
+        ("leaf_threshold", ctypes.c_uint64),
     ]
 
 
@@ -106,6 +108,8 @@ def load_library():
     lib.dbl_query_ctx_create.restype = i32
     lib.dbl_query_batch_ctx.argtypes = [P, P, u64, P, P, P, P]
     lib.dbl_query_batch_ctx.restype = i32
+    lib.dbl_query_batch_rules.argtypes = [P, P, u64, P, P, P, u32, P]
+    lib.dbl_query_batch_rules.restype = i32
     lib.dbl_query_ctx_destroy.argtypes = [P]
     lib.dbl_query_ctx_destroy.restype = None
     lib.dbl_read_labels.argtypes = [P, P, P, P, P, P]
@@ -215,7 +219,8 @@ class Index:
     def build(cls, n: int, src: torch.Tensor, dst: torch.Tensor, *, num_landmarks: int = 64,
               bl_bits: int = 64, landmarks=None, leaf_bucket=None, leaf_flags=None,
               slack_fraction: float = 0.25, slack_min: int = 4, bfs_slots: int = 0,
-              bfs_queue_cap: int = 0, edges_unique: bool = False, stream=None) -> "Index":
+              bfs_queue_cap: int = 0, edges_unique: bool = False, landmark_rank: int = 0,
+              leaf_threshold: int = 0, stream=None) -> "Index":
         lib = load_library()
         src, dst = _ids(src, "src"), _ids(dst, "dst")
         if src.numel() != dst.numel():
@@ -246,6 +251,8 @@ class Index:
         opt.bfs_slots = bfs_slots
         opt.bfs_queue_cap = bfs_queue_cap
         opt.edges_unique = 1 if edges_unique else 0
+        opt.landmark_rank = landmark_rank
+        opt.leaf_threshold = leaf_threshold
         out = ctypes.c_void_p()
         with torch.cuda.device(src.device):
             st = lib.dbl_build(n, src.numel(), src.data_ptr(), dst.data_ptr(), ctypes.byref(opt),
@@ -312,6 +319,21 @@ class Index:
             st = load_library().dbl_query_batch(self._handle(), u.numel(), u.data_ptr(),
                                                 v.data_ptr(), out.data_ptr(), _stream_ptr(stream))
         _check(st, "dbl_query_batch")
+        return out
+
+    def query_rules(self, u: torch.Tensor, v: torch.Tensor, rules: int,
+                    out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """Queries using only the labels in `rules` (1 = DL, 2 = BL, 3 = both)."""
+        u, v = _ids(u, "u"), _ids(v, "v")
+        if u.numel() != v.numel():
+            raise ValueError("u and v differ in length")
+        if out is None:
+            out = torch.empty(u.numel(), dtype=torch.uint8, device=u.device)
+        with torch.cuda.device(self.device):
+            st = load_library().dbl_query_batch_rules(self._handle(), None, u.numel(),
+                                                      u.data_ptr(), v.data_ptr(), out.data_ptr(),
+                                                      rules, _stream_ptr(stream))
+        _check(st, "dbl_query_batch_rules")
         return out
 
     def query_context(self, bfs_slots: int = 0, queue_cap: int = 0) -> QueryContext:

@@ -29,7 +29,7 @@ struct dbl_query_ctx {
   dbl::Mirror *mirror = nullptr;
   dbl::Mirror hs{};
   uint32_t seq = 0;
-  uint32_t *und = nullptr, *heavy_q = nullptr;
+  uint32_t *und = nullptr, *heavy_q = nullptr, *seg = nullptr;
   uint64_t und_cap = 0;
   u64 *vis = nullptr;
   uint64_t vis_words = 0;
@@ -418,6 +418,7 @@ void ctx_free(dbl_query_ctx *c) {
   c->mirror = nullptr;
   dfree(c->und);
   dfree(c->heavy_q);
+  dfree(c->seg);
   dfree(c->vis);
   dfree(c->bfs_queue);
   dfree(c->bfs_cnt);
@@ -463,9 +464,12 @@ dbl_status ctx_reserve(dbl_query_ctx *c, uint64_t count) {
   if (count <= c->und_cap) return DBL_OK;
   dfree(c->und);
   dfree(c->heavy_q);
-  const uint64_t cap = std::max<uint64_t>(count, 1024);
+  dfree(c->seg);
+  const uint64_t blocks = (std::max<uint64_t>(count, 1024) + dbl::kQueryNT - 1) / dbl::kQueryNT;
+  const uint64_t cap = blocks * dbl::kQueryNT;
   CKS(dalloc(&c->und, cap));
   CKS(dalloc(&c->heavy_q, cap));
+  CKS(dalloc(&c->seg, blocks));
   c->und_cap = cap;
   return DBL_OK;
 }
@@ -486,15 +490,32 @@ dbl_status ctx_add_counts(const dbl_query_ctx *c, uint64_t cls[7], uint64_t *bv,
   return DBL_OK;
 }
 
+// The index's own query context, created on first use.
+dbl_status ensure_default_ctx(dbl_index *ix) {
+  if (ix->qctx) return DBL_OK;
+  dbl_query_ctx *c = new (std::nothrow) dbl_query_ctx();
+  if (!c) return DBL_ERR_OUT_OF_MEMORY;
+  c->is_default = true;
+  const dbl_status st = ctx_init(ix, c, 0, 0);
+  if (st != DBL_OK) {
+    ctx_free(c);
+    delete c;
+    return st;
+  }
+  ix->qctx = c;
+  return DBL_OK;
+}
+
 // Algorithm 2 over a batch with the scratch of context c (see dbl_query_batch).
 dbl_status run_queries(dbl_index *ix, dbl_query_ctx *c, uint64_t count, const uint32_t *d_u,
-                       const uint32_t *d_v, uint8_t *d_out, hipStream_t s) {
+                       const uint32_t *d_v, uint8_t *d_out, hipStream_t s,
+                       uint32_t rules = DBL_RULES_ALL) {
   CKS(ctx_reserve(c, count));
   CK(dbl::launch_ctl_reset_query(c->ctl, s));
   {
     Timed tm(ix, c->is_default ? (uint32_t)kTQueryLabel : (uint32_t)kTKinds, s);
-    CK(dbl::launch_query_label({ix->lab}, d_u, d_v, count, ix->n, d_out, c->und, c->ctl, c->qcls,
-                               s));
+    CK(dbl::launch_query_label({ix->lab}, d_u, d_v, count, ix->n, ix->f.deg, d_out, c->und,
+                               c->seg, c->ctl, c->qcls, rules, s));
   }
   dbl::BfsArgs b;
   b.L.lab = ix->lab;
@@ -502,6 +523,8 @@ dbl_status run_queries(dbl_index *ix, dbl_query_ctx *c, uint64_t count, const ui
   b.u = d_u;
   b.v = d_v;
   b.und = c->und;
+  b.seg = c->seg;
+  b.nseg = (uint32_t)((count + dbl::kQueryNT - 1) / dbl::kQueryNT);
   b.out = d_out;
   b.vis = c->vis;
   b.vis_words = c->vis_words;
@@ -509,6 +532,7 @@ dbl_status run_queries(dbl_index *ix, dbl_query_ctx *c, uint64_t count, const ui
   b.qcap = c->qcap;
   b.heavy_q = c->heavy_q;
   b.cnt = c->bfs_cnt;
+  b.rules = rules;
   b.ctl = c->ctl;
   {
     Timed tm(ix, c->is_default ? (uint32_t)kTQueryBfs : (uint32_t)kTKinds, s);
@@ -542,7 +566,7 @@ dbl_status run_queries(dbl_index *ix, dbl_query_ctx *c, uint64_t count, const ui
       CK(dbl::launch_gbfs_start(a, c->gvis, c->vis_words, u, s));
       uint32_t ring = 0;
       for (;;) {
-        CK(dbl::launch_gbfs_round(a, c->gvis, u, v, ring, s));
+        CK(dbl::launch_gbfs_round(a, c->gvis, u, v, ring, rules, s));
         ring = ring == 2 ? 0 : ring + 1;
         CKS(sync_chan(c->ctl, c->mirror, c->hs, c->seq, s));
         if (c->hs.found || c->hs.fsize[ring] == 0) break;
@@ -638,7 +662,7 @@ dbl_status do_build(dbl_index *ix, uint64_t m, const uint32_t *src, const uint32
       CKS(dalloc(&tm, te));
       dbl_status st = dalloc(&tid, te);
       if (st != DBL_OK) { dfree(tm); return st; }
-      CK(dbl::select_topk(indeg, outdeg, n, ix->k, tm, tid, ix->landmarks_d, s));
+      CK(dbl::select_topk(indeg, outdeg, n, ix->k, o.landmark_rank, tm, tid, ix->landmarks_d, s));
       CK(hipStreamSynchronize(s));
       dfree(tm);
       dfree(tid);
@@ -662,7 +686,7 @@ dbl_status do_build(dbl_index *ix, uint64_t m, const uint32_t *src, const uint32
   CKS(dalloc(&ix->leaf_flags, n));
   CKS(dalloc(&ix->bucket, n));
   CK(dbl::launch_seed({ix->lab}, n, ix->landmarks_d, ix->k, indeg, outdeg, flags_in, bucket_in,
-                      ix->kp_bits, ix->leaf_flags, ix->bucket, is_lm, s));
+                      ix->kp_bits, o.leaf_threshold, ix->leaf_flags, ix->bucket, is_lm, s));
   CK(hipStreamSynchronize(s));
   dfree(is_lm);
   dfree(flags_in);
@@ -717,6 +741,7 @@ dbl_status dbl_build(uint32_t n, uint64_t m, const uint32_t *d_src, const uint32
   if (o.num_landmarks > 64) return DBL_ERR_INVALID_ARG;
   if (o.bl_bits == 0 || o.bl_bits > 64 || (o.bl_bits & (o.bl_bits - 1))) return DBL_ERR_INVALID_ARG;
   if (!(o.slack_fraction >= 0.0f) || o.slack_fraction > 16.0f) return DBL_ERR_INVALID_ARG;
+  if (o.landmark_rank > 3) return DBL_ERR_INVALID_ARG;
   const uint32_t k = std::min<uint32_t>(o.num_landmarks, n);
   if (o.landmarks) {
     std::vector<uint32_t> seen(o.landmarks, o.landmarks + k);
@@ -822,20 +847,8 @@ dbl_status dbl_query_batch(dbl_index *ix, uint64_t count, const uint32_t *d_u,
   if (count == 0) return DBL_OK;
   if (!d_u || !d_v || !d_out || count > 0xFFFFFFFFull) return DBL_ERR_INVALID_ARG;
   DeviceGuard dg(ix->device);
-  hipStream_t s = (hipStream_t)stream;
-  if (!ix->qctx) {
-    dbl_query_ctx *c = new (std::nothrow) dbl_query_ctx();
-    if (!c) return DBL_ERR_OUT_OF_MEMORY;
-    c->is_default = true;
-    const dbl_status st = ctx_init(ix, c, 0, 0);
-    if (st != DBL_OK) {
-      ctx_free(c);
-      delete c;
-      return st;
-    }
-    ix->qctx = c;
-  }
-  return run_queries(ix, ix->qctx, count, d_u, d_v, d_out, s);
+  CKS(ensure_default_ctx(ix));
+  return run_queries(ix, ix->qctx, count, d_u, d_v, d_out, (hipStream_t)stream);
 }
 
 uint64_t dbl_query_ctx_bytes(const dbl_index *ix, uint32_t bfs_slots, uint32_t queue_cap,
@@ -875,6 +888,20 @@ dbl_status dbl_query_batch_ctx(dbl_index *ix, dbl_query_ctx *ctx, uint64_t count
   if (!d_u || !d_v || !d_out || count > 0xFFFFFFFFull) return DBL_ERR_INVALID_ARG;
   DeviceGuard dg(ix->device);
   return run_queries(ix, ctx, count, d_u, d_v, d_out, (hipStream_t)stream);
+}
+
+dbl_status dbl_query_batch_rules(dbl_index *ix, dbl_query_ctx *ctx, uint64_t count,
+                                 const uint32_t *d_u, const uint32_t *d_v, uint8_t *d_out,
+                                 uint32_t rules, void *stream) {
+  if (!ix || (ctx && ctx->ix != ix) || rules > DBL_RULES_ALL) return DBL_ERR_INVALID_ARG;
+  if (count == 0) return DBL_OK;
+  if (!d_u || !d_v || !d_out || count > 0xFFFFFFFFull) return DBL_ERR_INVALID_ARG;
+  DeviceGuard dg(ix->device);
+  if (!ctx) {
+    CKS(ensure_default_ctx(ix));
+    ctx = ix->qctx;
+  }
+  return run_queries(ix, ctx, count, d_u, d_v, d_out, (hipStream_t)stream, rules);
 }
 
 void dbl_query_ctx_destroy(dbl_query_ctx *ctx) {

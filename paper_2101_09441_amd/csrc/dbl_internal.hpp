@@ -81,8 +81,9 @@ struct Mirror {
 constexpr uint32_t kFastErr = 1u, kFastOvf = 2u, kFastPending = 4u;
 
 // Per-block / per-slot statistics (plain read-modify-write by the owning block, no atomics).
-constexpr uint32_t kQueryGrid = 1024;  // blocks of the label kernel (grid-stride)
-constexpr uint32_t kQClsStride = 8;    // class counters per label-kernel block
+constexpr uint32_t kQueryGrid = 64;    // class-counter stripes (label-kernel block % 64)
+constexpr uint32_t kQClsStride = 8;    // class counters per stripe
+constexpr uint32_t kQueryNT = 256;     // pairs per label-kernel block (one per thread)
 constexpr uint32_t kBfsCtrStride = 4;  // vertices, edges, true, false per BFS slot
 // propagation counters: grid rounds use slots [0, 2048), heavy chunks [2048, 3072), the
 // single-workgroup rounds slot 3072
@@ -127,16 +128,17 @@ hipError_t launch_scatter(const uint32_t *src, const uint32_t *dst, const uint8_
 // build: landmark selection. Writes the top-k vertex ids by (M desc, id asc) into out[k].
 // tmp_m / tmp_id: topk_tmp_entries(n) entries each.
 uint64_t topk_tmp_entries(uint32_t n);
+// rank: 0 product, 1 max, 2 min, 3 sum of in- and out-degree
 hipError_t select_topk(const uint32_t *indeg, const uint32_t *outdeg, uint32_t n, uint32_t k,
-                       unsigned long long *tmp_m, uint32_t *tmp_id, uint32_t *out,
+                       uint32_t rank, unsigned long long *tmp_m, uint32_t *tmp_id, uint32_t *out,
                        hipStream_t s);
 
 // build: seeds
 hipError_t launch_seed(LabelsView L, uint32_t n, const uint32_t *landmarks, uint32_t k,
                        const uint32_t *indeg, const uint32_t *outdeg,
                        const uint8_t *leaf_flags_in, const uint8_t *bucket_in, uint32_t kp_bits,
-                       uint8_t *leaf_flags_out, uint8_t *bucket_out, uint8_t *is_landmark,
-                       hipStream_t s);
+                       unsigned long long leaf_threshold, uint8_t *leaf_flags_out,
+                       uint8_t *bucket_out, uint8_t *is_landmark, hipStream_t s);
 hipError_t launch_init_frontier(LabelsView L, uint32_t n, Csr f, Csr r, uint32_t *frontier,
                                 Ctl *ctl, uint32_t *inq, uint32_t stamp, hipStream_t s);
 
@@ -171,14 +173,18 @@ hipError_t launch_push_overflow(const PropArgs &a, const Ovf *ovf, uint32_t coun
                                 hipStream_t s);
 
 // queries
+// Undecided pairs of label-kernel block b go to und[b * kQueryNT ...], their number to seg[b].
 hipError_t launch_query_label(LabelsView L, const uint32_t *u, const uint32_t *v, uint64_t count,
-                              uint32_t n, uint8_t *out, uint32_t *und, Ctl *ctl,
-                              unsigned long long *qcls, hipStream_t s);
+                              uint32_t n, const uint32_t *fdeg, uint8_t *out, uint32_t *und,
+                              uint32_t *seg, Ctl *ctl, unsigned long long *qcls, uint32_t rules,
+                              hipStream_t s);
 struct BfsArgs {
   LabelsView L;
   Csr f;
   const uint32_t *u, *v;
   const uint32_t *und;
+  const uint32_t *seg;      // undecided count per label-kernel block
+  uint32_t nseg;            // label-kernel blocks
   uint8_t *out;
   unsigned long long *vis;  // [slots * vis_words]
   uint64_t vis_words;
@@ -186,6 +192,7 @@ struct BfsArgs {
   uint32_t qcap;
   uint32_t *heavy_q;        // queries handed to the grid BFS
   unsigned long long *cnt;  // [slots * kBfsCtrStride]
+  uint32_t rules;           // bit 0: DL prune, bit 1: BL prune
   Ctl *ctl;
 };
 hipError_t launch_query_bfs(const BfsArgs &a, uint32_t slots, hipStream_t s);
@@ -193,7 +200,7 @@ hipError_t launch_query_bfs(const BfsArgs &a, uint32_t slots, hipStream_t s);
 hipError_t launch_gbfs_start(const PropArgs &a, unsigned long long *vis, uint64_t vis_words,
                              uint32_t u, hipStream_t s);
 hipError_t launch_gbfs_round(const PropArgs &a, unsigned long long *vis, uint32_t u, uint32_t v,
-                             uint32_t ring, hipStream_t s);
+                             uint32_t ring, uint32_t rules, hipStream_t s);
 hipError_t launch_gbfs_finish(const PropArgs &a, uint32_t qi, uint8_t *out,
                               unsigned long long *qcls, hipStream_t s);
 

@@ -384,7 +384,8 @@ uint64_t topk_tmp_entries(uint32_t n) {
 
 __global__ __launch_bounds__(kTkNT) void k_topk(const uint32_t *indeg, const uint32_t *outdeg,
                                                 const u64 *in_m, const uint32_t *in_id,
-                                                uint64_t count, u64 *out_m, uint32_t *out_id) {
+                                                uint64_t count, uint32_t rank, u64 *out_m,
+                                                uint32_t *out_id) {
   __shared__ u64 sm[kTkTile];
   __shared__ uint32_t sid[kTkTile];
   const uint64_t base = (uint64_t)blockIdx.x * kTkTile;
@@ -397,7 +398,8 @@ __global__ __launch_bounds__(kTkNT) void k_topk(const uint32_t *indeg, const uin
         m = in_m[idx];
         id = in_id[idx];
       } else {
-        m = (u64)indeg[idx] * (u64)outdeg[idx];
+        const u64 p = indeg[idx], q = outdeg[idx];
+        m = rank == 1 ? (p > q ? p : q) : rank == 2 ? (p < q ? p : q) : rank == 3 ? p + q : p * q;
         id = (uint32_t)idx;
       }
     }
@@ -429,7 +431,8 @@ __global__ __launch_bounds__(kTkNT) void k_topk(const uint32_t *indeg, const uin
 }
 
 hipError_t select_topk(const uint32_t *indeg, const uint32_t *outdeg, uint32_t n, uint32_t k,
-                       u64 *tmp_m, uint32_t *tmp_id, uint32_t *out, hipStream_t s) {
+                       uint32_t rank, u64 *tmp_m, uint32_t *tmp_id, uint32_t *out,
+                       hipStream_t s) {
   if (k == 0) return hipSuccess;
   const uint64_t half = topk_tmp_entries(n) / 2;
   uint64_t count = n;
@@ -441,7 +444,7 @@ hipError_t select_topk(const uint32_t *indeg, const uint32_t *outdeg, uint32_t n
     u64 *om = tmp_m + side * half;
     uint32_t *oi = tmp_id + side * half;
     hipLaunchKernelGGL(k_topk, dim3((uint32_t)tiles), dim3(kTkNT), 0, s, indeg, outdeg, in_m,
-                       in_id, count, om, oi);
+                       in_id, count, rank, om, oi);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (tiles == 1) return hipMemcpyAsync(out, oi, sizeof(uint32_t) * k, hipMemcpyDeviceToDevice, s);
@@ -466,12 +469,15 @@ __global__ void k_mark_landmarks(u64 *lab, const uint32_t *landmarks, uint32_t k
 
 __global__ void k_seed_leaves(u64 *lab, uint32_t n, const uint32_t *indeg, const uint32_t *outdeg,
                               const uint8_t *is_landmark, const uint8_t *flags_in,
-                              const uint8_t *bucket_in, uint32_t kp_bits, uint8_t *flags_out,
-                              uint8_t *bucket_out) {
+                              const uint8_t *bucket_in, uint32_t kp_bits, u64 leaf_threshold,
+                              uint8_t *flags_out, uint8_t *bucket_out) {
   for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < n; x += gridDim.x * blockDim.x) {
     uint32_t fl;
     if (flags_in) {
       fl = flags_in[x] & 3u;
+    } else if (leaf_threshold) {
+      const bool lm = is_landmark[x] != 0;
+      fl = (!lm && (u64)indeg[x] * (u64)outdeg[x] <= leaf_threshold) ? 3u : 0u;
     } else {
       const bool lm = is_landmark[x] != 0;
       fl = (uint32_t)(!lm && indeg[x] == 0) | ((uint32_t)(!lm && outdeg[x] == 0) << 1);
@@ -487,15 +493,15 @@ __global__ void k_seed_leaves(u64 *lab, uint32_t n, const uint32_t *indeg, const
 hipError_t launch_seed(LabelsView L, uint32_t n, const uint32_t *landmarks, uint32_t k,
                        const uint32_t *indeg, const uint32_t *outdeg,
                        const uint8_t *leaf_flags_in, const uint8_t *bucket_in, uint32_t kp_bits,
-                       uint8_t *leaf_flags_out, uint8_t *bucket_out, uint8_t *is_landmark,
-                       hipStream_t s) {
+                       u64 leaf_threshold, uint8_t *leaf_flags_out, uint8_t *bucket_out,
+                       uint8_t *is_landmark, hipStream_t s) {
   if (k) {
     hipLaunchKernelGGL(k_mark_landmarks, dim3(1), dim3(64), 0, s, L.lab, landmarks, k,
                        is_landmark);
   }
   hipLaunchKernelGGL(k_seed_leaves, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, L.lab, n,
                      indeg, outdeg, is_landmark, leaf_flags_in, bucket_in, kp_bits,
-                     leaf_flags_out, bucket_out);
+                     leaf_threshold, leaf_flags_out, bucket_out);
   return hipGetLastError();
 }
 
@@ -945,65 +951,79 @@ hipError_t launch_push_overflow(const PropArgs &a, const Ovf *ovf, uint32_t coun
 
 // ---------------------------------------------------------------- queries
 
-// Label phase of Algorithm 2: one lane per pair. Decided pairs get their answer byte now;
-// the rest are compacted into `und` for the BFS kernel. Class counts are summed per block and
-// added to the block's own counters (no atomics shared across blocks).
-__global__ __launch_bounds__(256) void k_query_label(const u64 *lab, const uint32_t *qu,
-                                                     const uint32_t *qv, uint64_t count,
-                                                     uint32_t n, uint8_t *out, uint32_t *und,
-                                                     Ctl *ctl, u64 *qcls) {
-  __shared__ uint32_t s_cls[4][5];
-  uint32_t cls_cnt[5] = {0, 0, 0, 0, 0};
-  bool bad_any = false;
-  for (uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x; i0 < count;
-       i0 += (uint64_t)gridDim.x * blockDim.x) {
-    const uint64_t i = i0 + threadIdx.x;
-    const bool act = i < count;
-    int cls = -1;
-    bool undecided = false;
-    if (act) {
-      const uint32_t u = qu[i], v = qv[i];
-      if (u >= n || v >= n) {
-        bad_any = true;
-        out[i] = 0xFF;
-      } else if (u == v) {
-        cls = 0;
-      } else {
-        const ulonglong2 fu = *reinterpret_cast<const ulonglong2 *>(lab + 4ull * u);
-        const ulonglong2 bu = *reinterpret_cast<const ulonglong2 *>(lab + 4ull * u + 2);
-        const ulonglong2 fv = *reinterpret_cast<const ulonglong2 *>(lab + 4ull * v);
-        const ulonglong2 bv = *reinterpret_cast<const ulonglong2 *>(lab + 4ull * v + 2);
-        // fu = {DL_in(u), BL_in(u)}, bu = {DL_out(u), BL_out(u)}
-        if (bu.x & fv.x) cls = 1;                                      // Lemma 1
-        else if ((fu.y & ~fv.y) | (bv.y & ~bu.y)) cls = 2;             // Lemma 2
-        else if (bv.x & fu.x) cls = 3;                                 // Theorem 1
-        else if ((bu.x & fu.x) | (bv.x & fv.x)) cls = 4;               // Theorem 2
-        else undecided = true;
-      }
-      if (cls >= 0) out[i] = (uint8_t)((cls <= 1 ? 1u : 0u) | ((uint32_t)cls << 1));
+// Label phase of Algorithm 2: one lane per pair. Decided pairs get their answer byte now.
+// A pair the rules leave open whose source has no out-edge is answered here too: the BFS from u
+// would scan nothing, so the answer is "BFS false". The remaining pairs are compacted per block
+// into und[block * kQueryNT ...] with their number in seg[block] (no shared counter).
+__global__ __launch_bounds__(kQueryNT) void k_query_label(const u64 *lab, const uint32_t *qu,
+                                                          const uint32_t *qv, uint64_t count,
+                                                          uint32_t n, const uint32_t *fdeg,
+                                                          uint8_t *out, uint32_t *und,
+                                                          uint32_t *seg, Ctl *ctl, u64 *qcls,
+                                                          uint32_t rules) {
+  __shared__ uint32_t s_cls[kQueryNT / 64][8];
+  __shared__ uint32_t s_und[kQueryNT / 64];
+  const uint64_t i = (uint64_t)blockIdx.x * kQueryNT + threadIdx.x;
+  const bool act = i < count;
+  int cls = -1;
+  bool undecided = false, bad = false;
+  if (act) {
+    const uint32_t u = qu[i], v = qv[i];
+    if (u >= n || v >= n) {
+      bad = true;
+      out[i] = 0xFF;
+    } else if (u == v) {
+      cls = 0;
+    } else {
+      const ulonglong2 fu = *reinterpret_cast<const ulonglong2 *>(lab + 4ull * u);
+      const ulonglong2 bu = *reinterpret_cast<const ulonglong2 *>(lab + 4ull * u + 2);
+      const ulonglong2 fv = *reinterpret_cast<const ulonglong2 *>(lab + 4ull * v);
+      const ulonglong2 bv = *reinterpret_cast<const ulonglong2 *>(lab + 4ull * v + 2);
+      // fu = {DL_in(u), BL_in(u)}, bu = {DL_out(u), BL_out(u)}; a disabled label reads as 0
+      // for the rules that use it (the ablations of Table 4)
+      const bool dl = rules & 1u, bl = (rules & 2u) != 0;
+      if (dl && (bu.x & fv.x)) cls = 1;                                   // Lemma 1
+      else if (bl && ((fu.y & ~fv.y) | (bv.y & ~bu.y))) cls = 2;          // Lemma 2
+      else if (dl && (bv.x & fu.x)) cls = 3;                              // Theorem 1
+      else if (dl && ((bu.x & fu.x) | (bv.x & fv.x))) cls = 4;            // Theorem 2
+      else if (fdeg[u] == 0) cls = 6;                                     // empty BFS
+      else undecided = true;
     }
-#pragma unroll
-    for (int c = 0; c < 5; c++) cls_cnt[c] += (uint32_t)__popcll(__ballot(cls == c));
-    wave_push(und, &ctl->und_count, undecided, (uint32_t)i);
+    if (cls >= 0) out[i] = (uint8_t)((cls <= 1 ? 1u : 0u) | ((uint32_t)cls << 1));
   }
-  if (__ballot(bad_any) && __lane_id() == 0) atomicOr(&ctl->err, kErrRange);
-  const uint32_t w = threadIdx.x >> 6;
-  if (__lane_id() == 0)
-    for (int c = 0; c < 5; c++) s_cls[w][c] = cls_cnt[c];
+  const uint32_t lane = __lane_id(), w = threadIdx.x >> 6;
+  const u64 um = __ballot(undecided);
+  if (lane == 0) {
+    for (int c = 0; c < 7; c++) s_cls[w][c] = (uint32_t)__popcll(__ballot(cls == c));
+    s_und[w] = (uint32_t)__popcll(um);
+  } else {
+    for (int c = 0; c < 7; c++) (void)__ballot(cls == c);
+  }
+  if (__ballot(bad) && lane == 0) atomicOr(&ctl->err, kErrRange);
   __syncthreads();
-  if (threadIdx.x < 5) {
+  uint32_t base = 0, tot = 0;
+  for (uint32_t j = 0; j < kQueryNT / 64; j++) {
+    if (j < w) base += s_und[j];
+    tot += s_und[j];
+  }
+  if (undecided)
+    und[(uint64_t)blockIdx.x * kQueryNT + base + lanemask_lt_popc(um)] = (uint32_t)i;
+  if (threadIdx.x == 0) seg[blockIdx.x] = tot;
+  if (threadIdx.x < 7) {
     const uint32_t c = threadIdx.x;
-    const uint32_t tot = s_cls[0][c] + s_cls[1][c] + s_cls[2][c] + s_cls[3][c];
-    if (tot) qcls[blockIdx.x * kQClsStride + c] += tot;
+    uint32_t sum = 0;
+    for (uint32_t j = 0; j < kQueryNT / 64; j++) sum += s_cls[j][c];
+    if (sum) atomicAdd(&qcls[(blockIdx.x % kQueryGrid) * kQClsStride + c], (u64)sum);
   }
 }
 
 hipError_t launch_query_label(LabelsView L, const uint32_t *u, const uint32_t *v, uint64_t count,
-                              uint32_t n, uint8_t *out, uint32_t *und, Ctl *ctl, u64 *qcls,
-                              hipStream_t s) {
+                              uint32_t n, const uint32_t *fdeg, uint8_t *out, uint32_t *und,
+                              uint32_t *seg, Ctl *ctl, u64 *qcls, uint32_t rules, hipStream_t s) {
   if (count == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_query_label, dim3(grid_for(count, 256, kQueryGrid)), dim3(256), 0, s,
-                     L.lab, u, v, count, n, out, und, ctl, qcls);
+  const uint64_t blocks = (count + kQueryNT - 1) / kQueryNT;
+  hipLaunchKernelGGL(k_query_label, dim3((uint32_t)blocks), dim3(kQueryNT), 0, s, L.lab, u, v,
+                     count, n, fdeg, out, und, seg, ctl, qcls, rules);
   return hipGetLastError();
 }
 
@@ -1022,19 +1042,26 @@ __global__ __launch_bounds__(kBfsNT) void k_query_bfs(BfsArgs a) {
   const uint32_t slot = blockIdx.x * (kBfsNT / 64u) + (threadIdx.x >> 6);
   u64 *vis = a.vis + (uint64_t)slot * a.vis_words;
   uint32_t *q = a.queue + (uint64_t)slot * a.qcap;
-  const uint32_t nund = ctl->und_count;
+  const uint32_t waves = gridDim.x * (kBfsNT / 64u);
   const u64 *lab = a.L.lab;
   u64 n_vert = 0, n_edge = 0, cls_t = 0, cls_f = 0;
+  // undecided pairs sit in per-block segments of the label kernel; wave `slot` takes segments
+  // slot, slot + waves, ... (no shared work counter)
+  uint32_t sg = slot, sj = 0, scnt = sg < a.nseg ? a.seg[sg] : 0u;
   for (;;) {
-    uint32_t item = 0;
-    if (lane == 0) item = atomicAdd(&ctl->bfs_next, 1u);
-    item = __shfl(item, 0, 64);
-    if (item >= nund) break;
-    const uint32_t qi = a.und[item];
+    while (sg < a.nseg && sj >= scnt) {
+      sg += waves;
+      sj = 0;
+      scnt = sg < a.nseg ? a.seg[sg] : 0u;
+    }
+    if (sg >= a.nseg) break;
+    const uint32_t qi = a.und[(uint64_t)sg * kQueryNT + sj];
+    sj++;
     const uint32_t u = a.u[qi], v = a.v[qi];
-    const u64 dlo_u = lab[4ull * u + 2];
-    const u64 bli_v = lab[4ull * v + 1];
-    const u64 blo_v = lab[4ull * v + 3];
+    // a disabled label prunes nothing: DL_out(u) = 0, BL_in(v) = all, BL_out(v) = none
+    const u64 dlo_u = (a.rules & 1u) ? lab[4ull * u + 2] : 0ull;
+    const u64 bli_v = (a.rules & 2u) ? lab[4ull * v + 1] : ~0ull;
+    const u64 blo_v = (a.rules & 2u) ? lab[4ull * v + 3] : 0ull;
     if (lane == 0) {
       atomicOr(&vis[u >> 6], 1ull << (u & 63u));
       q[0] = u;
@@ -1146,13 +1173,15 @@ hipError_t launch_gbfs_start(const PropArgs &a, u64 *vis, uint64_t vis_words, ui
 }
 
 __global__ __launch_bounds__(256) void k_gbfs_round(PropArgs a, u64 *vis, uint32_t u, uint32_t v,
-                                                    uint32_t ring) {
+                                                    uint32_t ring, uint32_t rules) {
   Ctl *ctl = a.ctl;
   const uint32_t nring = ring == 2u ? 0u : ring + 1u;
   const uint32_t fsz = ctl->fsize[ring];
   if (blockIdx.x == 0 && threadIdx.x == 0) ctl->fsize[nring == 2u ? 0u : nring + 1u] = 0;
   const u64 *lab = a.L.lab;
-  const u64 dlo_u = lab[4ull * u + 2], bli_v = lab[4ull * v + 1], blo_v = lab[4ull * v + 3];
+  const u64 dlo_u = (rules & 1u) ? lab[4ull * u + 2] : 0ull;
+  const u64 bli_v = (rules & 2u) ? lab[4ull * v + 1] : ~0ull;
+  const u64 blo_v = (rules & 2u) ? lab[4ull * v + 3] : 0ull;
   for (uint32_t i0 = blockIdx.x * blockDim.x; i0 < fsz; i0 += gridDim.x * blockDim.x) {
     const uint32_t i = i0 + threadIdx.x;
     if (i >= fsz) continue;
@@ -1177,8 +1206,8 @@ __global__ __launch_bounds__(256) void k_gbfs_round(PropArgs a, u64 *vis, uint32
 }
 
 hipError_t launch_gbfs_round(const PropArgs &a, u64 *vis, uint32_t u, uint32_t v, uint32_t ring,
-                             hipStream_t s) {
-  hipLaunchKernelGGL(k_gbfs_round, dim3(2048), dim3(256), 0, s, a, vis, u, v, ring);
+                             uint32_t rules, hipStream_t s) {
+  hipLaunchKernelGGL(k_gbfs_round, dim3(2048), dim3(256), 0, s, a, vis, u, v, ring, rules);
   return hipGetLastError();
 }
 

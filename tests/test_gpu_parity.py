@@ -115,6 +115,29 @@ def test_families_insert_batches(name, gr):
     assert_queries_equal(g, o, u, v)
 
 
+@pytest.mark.parametrize("rank,r", [(1, 0), (2, 0), (3, 0), (0, 3)])
+def test_selection_variants(rank, r):
+    """Table 3's landmark rankings and the leaf threshold r."""
+    w = dblgen.make_rmat_workload("sv", 11, 4, draws=8 << 11, n_query=20000,
+                                  query_kind="mixed")
+    g = gpu_index(w.n, w.src, w.dst, landmark_rank=rank, leaf_threshold=r)
+    o = oracle.OracleIndex(w.n, w.src, w.dst).build(rank=rank, leaf_threshold=r)
+    assert list(g.landmarks()) == list(o.landmarks())
+    assert_labels_equal(g, o, f"rank {rank} r {r}")
+    assert_queries_equal(g, o, w.q_u, w.q_v)
+
+
+@pytest.mark.parametrize("rules", [1, 2, 0, 3])
+def test_rule_ablations(tiny, rules):
+    """Table 4's ablations on the 2^14 workload: DL only, BL only, neither, both."""
+    w = tiny
+    g = gpu_index(w.n, w.src, w.dst)
+    o = oracle.OracleIndex(w.n, w.src, w.dst).build(threads=8)
+    got = g.query_rules(dev(w.q_u), dev(w.q_v), rules).cpu().numpy()
+    want = o.query_rules(w.q_u, w.q_v, rules, threads=8)
+    assert np.array_equal(got, want)
+
+
 def test_default_hash_matches_oracle():
     w = dblgen.make_rmat_workload("h", 10, 5, draws=8 << 10)
     g = gpu_index(w.n, w.src, w.dst)

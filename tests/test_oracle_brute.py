@@ -40,15 +40,22 @@ def distinct_degrees(n, src, dst):
     return indeg, outdeg
 
 
-def expected_landmarks(n, src, dst, k):
+RANKS = {0: lambda p, s: p * s, 1: max, 2: min, 3: lambda p, s: p + s}
+
+
+def expected_landmarks(n, src, dst, k, rank=0):
     indeg, outdeg = distinct_degrees(n, src, dst)
-    order = sorted(range(n), key=lambda x: (-(int(indeg[x]) * int(outdeg[x])), x))
+    f = RANKS[rank]
+    order = sorted(range(n), key=lambda x: (-f(int(indeg[x]), int(outdeg[x])), x))
     return order[:min(k, n)]
 
 
-def expected_leaves(n, src, dst, landmarks):
+def expected_leaves(n, src, dst, landmarks, r=0):
     indeg, outdeg = distinct_degrees(n, src, dst)
     lm = set(landmarks)
+    if r:
+        s = [x for x in range(n) if int(indeg[x]) * int(outdeg[x]) <= r and x not in lm]
+        return s, s
     s_in = [x for x in range(n) if indeg[x] == 0 and x not in lm]
     s_out = [x for x in range(n) if outdeg[x] == 0 and x not in lm]
     return s_in, s_out
@@ -67,17 +74,17 @@ def as_sets(words):
     return [{b for b in range(64) if (int(w) >> b) & 1} for w in words]
 
 
-def expected_query(R, lab, u, v):
+def expected_query(R, lab, u, v, dl=True, bl=True):
     dl_in, dl_out, bl_in, bl_out = lab
     if u == v:
         return 1 | (oracle.CLASS_SELF << 1)
-    if dl_out[u] & dl_in[v]:
+    if dl and dl_out[u] & dl_in[v]:
         return 1 | (oracle.CLASS_R1 << 1)
-    if not (bl_in[u] <= bl_in[v] and bl_out[v] <= bl_out[u]):
+    if bl and not (bl_in[u] <= bl_in[v] and bl_out[v] <= bl_out[u]):
         return 0 | (oracle.CLASS_R2 << 1)
-    if dl_out[v] & dl_in[u]:
+    if dl and dl_out[v] & dl_in[u]:
         return 0 | (oracle.CLASS_R3 << 1)
-    if (dl_out[u] & dl_in[u]) or (dl_out[v] & dl_in[v]):
+    if dl and ((dl_out[u] & dl_in[u]) or (dl_out[v] & dl_in[v])):
         return 0 | (oracle.CLASS_R4 << 1)
     ans = int(R[u, v])
     return ans | ((oracle.CLASS_BFS_TRUE if ans else oracle.CLASS_BFS_FALSE) << 1)
@@ -192,6 +199,46 @@ def test_labels_and_queries_vs_definitions(name, g, k, kp):
     assert np.array_equal(q, want)
     assert np.array_equal(ix.query_truth(u, v), R[u, v].astype(np.uint8))
     assert np.array_equal(ix.closure(), R)
+
+
+@pytest.mark.parametrize("name,g", FAMILIES[3:], ids=[f[0] for f in FAMILIES[3:]])
+@pytest.mark.parametrize("rank,r", [(1, 0), (2, 0), (3, 0), (0, 2), (3, 6)])
+def test_selection_variants_vs_definitions(name, g, rank, r):
+    """Table 3's landmark rankings and the leaf threshold r, against the definitions."""
+    n, src, dst = g
+    R = reach_matrix(n, src, dst)
+    bucket = random_bucket(n, 8, n + rank)
+    ix = oracle.OracleIndex(n, src, dst).build(k=5, kp=8, bucket_table=bucket, rank=rank,
+                                               leaf_threshold=r)
+    lm = expected_landmarks(n, src, dst, 5, rank)
+    assert list(ix.landmarks()) == lm
+    s_in, s_out = expected_leaves(n, src, dst, lm, r)
+    exp = expected_labels(R, lm, s_in, s_out, bucket)
+    assert [as_sets(w_) for w_ in ix.labels()] == list(exp)
+    u = np.repeat(np.arange(n), n).astype(np.uint32)
+    v = np.tile(np.arange(n), n).astype(np.uint32)
+    want = np.array([expected_query(R, exp, int(a), int(b)) for a, b in zip(u, v)], np.uint8)
+    assert np.array_equal(ix.query_dbl(u, v), want)
+
+
+@pytest.mark.parametrize("name,g", FAMILIES, ids=[f[0] for f in FAMILIES])
+@pytest.mark.parametrize("rules", [1, 2, 0])
+def test_rule_ablations_vs_definitions(name, g, rules):
+    """Table 4's ablations: DL only, BL only, neither; answers stay exact."""
+    n, src, dst = g
+    R = reach_matrix(n, src, dst)
+    bucket = random_bucket(n, 4, n)
+    ix = oracle.OracleIndex(n, src, dst).build(k=3, kp=4, bucket_table=bucket)
+    lm = expected_landmarks(n, src, dst, 3)
+    s_in, s_out = expected_leaves(n, src, dst, lm)
+    exp = expected_labels(R, lm, s_in, s_out, bucket)
+    u = np.repeat(np.arange(n), n).astype(np.uint32)
+    v = np.tile(np.arange(n), n).astype(np.uint32)
+    want = np.array([expected_query(R, exp, int(a), int(b), dl=bool(rules & 1),
+                                    bl=bool(rules & 2)) for a, b in zip(u, v)], np.uint8)
+    got = ix.query_rules(u, v, rules)
+    assert np.array_equal(got, want)
+    assert np.array_equal(got & 1, R[u, v].astype(np.uint8))
 
 
 def test_fibonacci_hash_range_and_spread():
