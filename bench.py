@@ -100,12 +100,116 @@ def cpu_baseline(w, n_ins_sample, n_q_sample):
     }
 
 
+def bench_scale(args):
+    """The batched form at scale: R-MAT 2^25 vertices, the distinct edges of 2^30 draws
+    (~1.0e9), 10M insertions in batches of 100k, 10M Zipf(1.1)-skewed queries in batches of
+    65,536. A step = build + all insertion batches + all query batches."""
+    import numpy as np
+    import torch
+
+    import dblgen
+    import paper_2101_09441_amd as dbl
+
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    w = dblgen.scale_workload()
+    log(f"scale workload generated in {time.perf_counter() - t0:.0f} s: n={w.n} m={w.m}")
+    src, dst = dbl.to_device_ids(w.src), dbl.to_device_ids(w.dst)
+    isrc, idst = dbl.to_device_ids(w.ins_src), dbl.to_device_ids(w.ins_dst)
+    qu, qv = dbl.to_device_ids(w.q_u), dbl.to_device_ids(w.q_v)
+    out = torch.empty(len(w.q_u), dtype=torch.uint8, device=dev)
+    n_ins, n_q, ib, qb = len(w.ins_src), len(w.q_u), 100_000, 65536
+
+    def step(timed):
+        r = {}
+        ta = time.perf_counter()
+        ix = dbl.Index.build(w.n, src, dst, edges_unique=True)
+        tb = time.perf_counter()
+        if timed:
+            ix.time_kernels("insert_apply,local_rounds,round,query_label,query_bfs")
+        lat_i = []
+        for lo in range(0, n_ins, ib):
+            t = time.perf_counter()
+            ix.insert_edges(isrc[lo:lo + ib], idst[lo:lo + ib])
+            lat_i.append(time.perf_counter() - t)
+        tc = time.perf_counter()
+        lat_q = []
+        for lo in range(0, n_q, qb):
+            t = time.perf_counter()
+            ix.query(qu[lo:lo + qb], qv[lo:lo + qb], out=out[lo:lo + qb])
+            lat_q.append(time.perf_counter() - t)
+        td = time.perf_counter()
+        r.update(build_s=tb - ta, insert_s=tc - tb, query_s=td - tc, lat_i=lat_i, lat_q=lat_q)
+        if timed:
+            r["ktimes"] = ix.kernel_times()
+            r["stats"] = ix.stats()
+        ix.close()
+        return r
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    res = [step(True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - ts) / args.steps * 1e3
+    for i, r in enumerate(res):
+        log(f"step {i}: build {r['build_s']:.3f} s, inserts {r['insert_s']:.3f} s, "
+            f"queries {r['query_s']:.3f} s")
+    st = res[-1]["stats"]
+    kt = {}
+    for r in res:
+        for k, v in r["ktimes"].items():
+            a = kt.setdefault(k, {"launches": 0, "total_ms": 0.0})
+            a["launches"] += v["launches"]
+            a["total_ms"] += v["total_ms"]
+    ans = out.cpu().numpy()
+    classes = np.bincount(ans >> 1, minlength=7)
+    roofline = None
+    if "query_label" in kt:
+        d = kt["query_label"]
+        avg = d["total_ms"] / d["launches"] / 1e3
+        per = QUERY_LABEL_BYTES * qb
+        roofline = {"bound": "hbm", "achieved": per / avg / 1e9, "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": per / avg / 1e9 / HBM_PEAK_GBS,
+                    "traffic": committed_traffic("query_label"), "kernel": "query_label",
+                    "avg_launch_us": avg * 1e6, "launches": d["launches"],
+                    "algorithmic_bytes_per_launch": per}
+    line = {
+        "metric": METRIC, "value": (n_ins + n_q) / (ms / 1e3),
+        "unit": "ops/s (inserted edges + answered queries)", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "R-MAT 2^25 vertices, distinct edges of 2^30 draws, 10M "
+                               "insertions in 100k batches, 10M Zipf(1.1) queries in 65,536 "
+                               "batches, 64 DL + 64 BL bits", "n": w.n, "m": w.m,
+                   "insertions": n_ins, "insert_batch": ib, "queries": n_q, "query_batch": qb},
+        "build_s": float(np.mean([r["build_s"] for r in res])),
+        "insert_edges_per_s": n_ins / float(np.mean([r["insert_s"] for r in res])),
+        "insert_batch_ms": {"p50": float(np.percentile(res[-1]["lat_i"], 50) * 1e3),
+                            "p99": float(np.percentile(res[-1]["lat_i"], 99) * 1e3)},
+        "queries_per_s": n_q / float(np.mean([r["query_s"] for r in res])),
+        "query_batch_ms": {"p50": float(np.percentile(res[-1]["lat_q"], 50) * 1e3),
+                           "p99": float(np.percentile(res[-1]["lat_q"], 99) * 1e3)},
+        "class_histogram": {dbl.CLASS_NAMES[i]: int(classes[i]) for i in range(7)},
+        "kernel_times_ms": {k: {"launches": v["launches"],
+                                "avg_us": v["total_ms"] / v["launches"] * 1e3}
+                            for k, v in kt.items()},
+        "propagation": {"build_rounds": st["build_rounds"], "edges_relaxed": st["edges_relaxed"],
+                        "vertices_expanded": st["vertices_expanded"],
+                        "csr_regrows": st["csr_regrows"], "bfs_heavy": st["bfs_heavy"]},
+        "roofline": roofline,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["lj", "tiny"], default="lj")
+    ap.add_argument("--workload", choices=["lj", "tiny", "scale"], default="lj")
     ap.add_argument("--cpu-baseline", choices=["on", "off"], default="on")
     ap.add_argument("--serving", choices=["on", "off"], default="on")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -128,6 +232,8 @@ def main():
 
     torch.cuda.init()
     dev = torch.device("cuda:0")
+    if args.workload == "scale":
+        return bench_scale(args)
     if args.workload == "lj":
         w = dblgen.cached("rmat22-lj-s1", dblgen.lj_workload)
         desc = ("R-MAT (a,b,c,d)=(0.57,0.19,0.19,0.05), 2^22 vertices, 68,993,773 unique edges, "

@@ -33,7 +33,8 @@ RMAT_A, RMAT_B, RMAT_C = 0.57, 0.19, 0.19
 def build() -> str:
     """Compile ``dblgen.c`` into ``libdblgen.so`` (always recompiles)."""
     tmp = _LIB + ".tmp"
-    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+    subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-pthread", "-o", tmp,
+                           _SRC, "-lm"])
     os.replace(tmp, _LIB)
     return _LIB
 
@@ -67,6 +68,8 @@ def _load():
     lib.dblgen_queries_mixed.restype = ctypes.c_int
     lib.dblgen_queries_zipf.argtypes = [u32, u64, u64, f64, P, P]
     lib.dblgen_queries_zipf.restype = ctypes.c_int
+    lib.dblgen_rmat_large.argtypes = [u32, u64, f64, f64, f64, u64, u64, u32, P, P, P, u64, P, P]
+    lib.dblgen_rmat_large.restype = ctypes.c_int
     lib.dblgen_xoshiro_outputs.argtypes = [u64, u64, P]
     lib.dblgen_xoshiro_outputs.restype = None
     _lib = lib
@@ -241,6 +244,34 @@ def serving_trace(q_u, q_v, ins_src, ins_dst, n_requests: int, rate: float, p_qu
             out.append((s, "query", q_u[idx].copy(), q_v[idx].copy(), float(t[s])))
             qi = (qi + k) % nq
     return out
+
+
+def rmat_large(scale: int, seed: int, draws: int, n_insert: int, threads: int = 0,
+               chunk: int = 1 << 20):
+    """Chunked-stream R-MAT (see dblgen.c): the distinct non-loop edges of `draws` draws,
+    sorted, plus `n_insert` new edges continuing the stream."""
+    threads = threads or max(1, min(16, os.cpu_count() or 1))
+    src = np.empty(max(draws, 1), dtype=np.uint32)
+    dst = np.empty(max(draws, 1), dtype=np.uint32)
+    isrc = np.empty(max(n_insert, 1), dtype=np.uint32)
+    idst = np.empty(max(n_insert, 1), dtype=np.uint32)
+    m = ctypes.c_uint64()
+    rc = _load().dblgen_rmat_large(scale, seed, RMAT_A, RMAT_B, RMAT_C, draws, chunk, threads,
+                                   _ptr(src), _ptr(dst), ctypes.addressof(m), n_insert,
+                                   _ptr(isrc), _ptr(idst))
+    if rc:
+        raise MemoryError("dblgen_rmat_large failed")
+    mm = int(m.value)
+    return src[:mm], dst[:mm], isrc[:n_insert], idst[:n_insert]
+
+
+def scale_workload(scale: int = 25, draws: int = 1 << 30, n_insert: int = 10_000_000,
+                   n_query: int = 10_000_000, seed: int = 1) -> Workload:
+    """Large R-MAT (2^25 vertices, the distinct edges of 2^30 draws, about 1.0e9), insertions
+    continuing the stream, Zipf(1.1)-skewed query sources with uniform targets."""
+    src, dst, isrc, idst = rmat_large(scale, seed, draws, n_insert)
+    qu, qv = queries_zipf(1 << scale, seed + 2, n_query)
+    return Workload(f"rmat{scale}-scale", 1 << scale, src, dst, isrc, idst, qu, qv, draws)
 
 
 def cached(name: str, make, cache_dir: str = None) -> Workload:

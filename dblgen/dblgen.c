@@ -368,3 +368,177 @@ void dblgen_xoshiro_outputs(uint64_t seed, uint64_t count, uint64_t *out) {
   xo_seed(&r, seed);
   for (uint64_t i = 0; i < count; i++) out[i] = xo_next(&r);
 }
+
+/* ---------------------------------------------------------------- large graphs, in parallel */
+/*
+ * The large workload uses a chunked stream so that draws can be made by several threads:
+ * chunk c (c = 0, 1, ...) holds `chunk` consecutive draws from its own xoshiro256** state,
+ * seeded with seed + 0x9E3779B97F4A7C15 * (c + 1) through splitmix64. The edge set is the set of
+ * distinct non-loop edges among the first `draws` draws (after the same Fisher-Yates relabelling
+ * as above), returned sorted by (src, dst). Insertion edges continue with the chunks after
+ * `draws`, skipping loops, edges of the set and repeats.
+ */
+#include <pthread.h>
+
+typedef struct {
+  uint32_t scale;
+  double a, b, c;
+  const uint32_t *perm;
+  uint64_t seed, chunk, draws;
+  uint64_t *keys; /* [draws] */
+  uint32_t nthreads, tid;
+} par_draw_job;
+
+static void draw_chunk_keys(const par_draw_job *j, uint64_t c, uint64_t *out, uint64_t count) {
+  xoshiro256 r;
+  xo_seed(&r, j->seed + 0x9E3779B97F4A7C15ULL * (c + 1));
+  dblgen_rmat g;
+  memset(&g, 0, sizeof(g));
+  g.scale = j->scale;
+  g.a = j->a; g.b = j->b; g.c = j->c;
+  g.rng = r;
+  for (uint64_t i = 0; i < count; i++) {
+    uint32_t s, d;
+    rmat_draw_raw(&g, &s, &d);
+    out[i] = s == d ? UINT64_MAX : (((uint64_t)j->perm[s] << 32) | j->perm[d]);
+  }
+}
+
+static void *par_draw_worker(void *arg) {
+  par_draw_job *j = (par_draw_job *)arg;
+  const uint64_t nchunks = (j->draws + j->chunk - 1) / j->chunk;
+  for (uint64_t c = j->tid; c < nchunks; c += j->nthreads) {
+    const uint64_t beg = c * j->chunk;
+    const uint64_t cnt = beg + j->chunk <= j->draws ? j->chunk : j->draws - beg;
+    draw_chunk_keys(j, c, j->keys + beg, cnt);
+  }
+  return NULL;
+}
+
+static int cmp_u64(const void *a, const void *b) {
+  uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
+  return (x > y) - (x < y);
+}
+
+typedef struct {
+  uint64_t *keys;       /* bucketed keys */
+  const uint64_t *bstart; /* [nb + 1] */
+  uint64_t *bunique;    /* [nb] unique count per bucket */
+  uint32_t nb, nthreads, tid;
+} par_sort_job;
+
+static void *par_sort_worker(void *arg) {
+  par_sort_job *j = (par_sort_job *)arg;
+  for (uint32_t b = j->tid; b < j->nb; b += j->nthreads) {
+    uint64_t *k = j->keys + j->bstart[b];
+    const uint64_t n = j->bstart[b + 1] - j->bstart[b];
+    qsort(k, n, sizeof(uint64_t), cmp_u64);
+    uint64_t w = 0;
+    for (uint64_t i = 0; i < n; i++)
+      if (k[i] != UINT64_MAX && (w == 0 || k[i] != k[w - 1])) k[w++] = k[i];
+    j->bunique[b] = w;
+  }
+  return NULL;
+}
+
+static int has_key(const uint64_t *sorted, uint64_t n, uint64_t key) {
+  uint64_t lo = 0, hi = n;
+  while (lo < hi) {
+    uint64_t mid = lo + (hi - lo) / 2;
+    if (sorted[mid] < key) lo = mid + 1; else hi = mid;
+  }
+  return lo < n && sorted[lo] == key;
+}
+
+/*
+ * Build edges of the large workload. On success *m receives the edge count and src/dst (each
+ * with room for `draws` entries) hold the sorted edge set; ins_src/ins_dst receive n_ins new
+ * edges. Returns 0, or -1 on allocation failure.
+ */
+int dblgen_rmat_large(uint32_t scale, uint64_t seed, double a, double b, double c, uint64_t draws,
+                      uint64_t chunk, uint32_t threads, uint32_t *src, uint32_t *dst, uint64_t *m,
+                      uint64_t n_ins, uint32_t *ins_src, uint32_t *ins_dst) {
+  if (scale == 0 || scale > 31 || threads == 0 || chunk == 0) return -1;
+  const uint32_t n = 1u << scale;
+  uint32_t *perm = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)n);
+  uint64_t *keys = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(draws ? draws : 1));
+  uint64_t *bkeys = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(draws ? draws : 1));
+  const uint32_t bbits = 12, nb = 1u << bbits;
+  uint64_t *cnt = (uint64_t *)calloc((size_t)nb * threads + 1, sizeof(uint64_t));
+  uint64_t *bstart = (uint64_t *)calloc(nb + 1, sizeof(uint64_t));
+  uint64_t *bunique = (uint64_t *)calloc(nb, sizeof(uint64_t));
+  pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * threads);
+  if (!perm || !keys || !bkeys || !cnt || !bstart || !bunique || !th) {
+    free(perm); free(keys); free(bkeys); free(cnt); free(bstart); free(bunique); free(th);
+    return -1;
+  }
+  xoshiro256 pr;
+  xo_seed(&pr, seed + 1);
+  for (uint32_t i = 0; i < n; i++) perm[i] = i;
+  for (uint32_t i = n - 1; i > 0; i--) {
+    uint32_t j = (uint32_t)xo_below(&pr, (uint64_t)i + 1);
+    uint32_t t = perm[i]; perm[i] = perm[j]; perm[j] = t;
+  }
+  par_draw_job *jobs = (par_draw_job *)calloc(threads, sizeof(par_draw_job));
+  for (uint32_t t = 0; t < threads; t++) {
+    jobs[t] = (par_draw_job){scale, a, b, c, perm, seed, chunk, draws, keys, threads, t};
+    pthread_create(&th[t], NULL, par_draw_worker, &jobs[t]);
+  }
+  for (uint32_t t = 0; t < threads; t++) pthread_join(th[t], NULL);
+  /* bucket by the top bits of the source id (ids are relabelled at random, so buckets are
+     balanced) and sort each bucket */
+  const uint32_t shift = 32 + scale - bbits;
+  for (uint64_t i = 0; i < draws; i++)
+    if (keys[i] != UINT64_MAX) bstart[(keys[i] >> shift) + 1]++;
+  for (uint32_t k = 0; k < nb; k++) bstart[k + 1] += bstart[k];
+  {
+    uint64_t *fill = cnt; /* reuse as fill pointers */
+    memcpy(fill, bstart, sizeof(uint64_t) * nb);
+    for (uint64_t i = 0; i < draws; i++)
+      if (keys[i] != UINT64_MAX) bkeys[fill[keys[i] >> shift]++] = keys[i];
+  }
+  par_sort_job *sj = (par_sort_job *)calloc(threads, sizeof(par_sort_job));
+  for (uint32_t t = 0; t < threads; t++) {
+    sj[t] = (par_sort_job){bkeys, bstart, bunique, nb, threads, t};
+    pthread_create(&th[t], NULL, par_sort_worker, &sj[t]);
+  }
+  for (uint32_t t = 0; t < threads; t++) pthread_join(th[t], NULL);
+  uint64_t w = 0;
+  for (uint32_t k = 0; k < nb; k++) {
+    const uint64_t *kb = bkeys + bstart[k];
+    for (uint64_t i = 0; i < bunique[k]; i++) {
+      keys[w] = kb[i];
+      src[w] = (uint32_t)(kb[i] >> 32);
+      dst[w] = (uint32_t)kb[i];
+      w++;
+    }
+  }
+  *m = w;
+  /* insertion edges: later chunks, skipping loops, existing edges and repeats */
+  int rc = 0;
+  if (n_ins) {
+    edge_set seen;
+    if (set_init(&seen, n_ins)) rc = -1;
+    uint64_t got = 0, cidx = (draws + chunk - 1) / chunk;
+    uint64_t *buf = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)chunk);
+    if (!buf) rc = -1;
+    while (rc == 0 && got < n_ins) {
+      draw_chunk_keys(&jobs[0], cidx++, buf, chunk);
+      for (uint64_t i = 0; i < chunk && got < n_ins; i++) {
+        const uint64_t k = buf[i];
+        if (k == UINT64_MAX || has_key(keys, w, k)) continue;
+        const int r = set_insert(&seen, k);
+        if (r < 0) { rc = -1; break; }
+        if (r == 0) continue;
+        ins_src[got] = (uint32_t)(k >> 32);
+        ins_dst[got] = (uint32_t)k;
+        got++;
+      }
+    }
+    free(buf);
+    free(seen.slot);
+  }
+  free(perm); free(keys); free(bkeys); free(cnt); free(bstart); free(bunique); free(th);
+  free(jobs); free(sj);
+  return rc;
+}

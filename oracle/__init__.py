@@ -82,6 +82,18 @@ def _load():
     lib.orc_in_degree.restype = u32
     lib.orc_out_degree.argtypes = [P, u32]
     lib.orc_out_degree.restype = u32
+    lib.orc_big_new.argtypes = [u32, u64, P, P]
+    lib.orc_big_new.restype = P
+    lib.orc_big_free.argtypes = [P]
+    lib.orc_big_free.restype = None
+    lib.orc_big_landmarks.argtypes = [P, u32, P]
+    lib.orc_big_landmarks.restype = u32
+    lib.orc_big_degrees.argtypes = [P, P, P]
+    lib.orc_big_degrees.restype = None
+    lib.orc_big_reach.argtypes = [P, u64, P, ctypes.c_int, P]
+    lib.orc_big_reach.restype = ctypes.c_int64
+    lib.orc_big_query_truth.argtypes = [P, u64, P, P, P, u32]
+    lib.orc_big_query_truth.restype = i32
     _lib = lib
     return lib
 
@@ -231,6 +243,72 @@ class OracleIndex:
         bits = np.unpackbits(rows.view(np.uint8).reshape(self.n, words * 8), axis=1,
                              bitorder="little")
         return bits[:, :self.n].astype(bool)
+
+
+class BigGraph:
+    """Oracle view of a large graph for sampled checks: CSR both ways, selection, the reachable
+    set of a source set (one BFS of Algorithm 1), plain BFS reachability per pair."""
+
+    def __init__(self, n: int, src, dst):
+        src, dst = _u32(src), _u32(dst)
+        self.n = int(n)
+        self._h = _load().orc_big_new(self.n, len(src), src.ctypes.data, dst.ctypes.data)
+        if not self._h:
+            raise ValueError("orc_big_new failed (id out of range or out of memory)")
+
+    def close(self):
+        if self._h:
+            _load().orc_big_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def landmarks(self, k: int = 64) -> np.ndarray:
+        out = np.zeros(max(k, 1), dtype=np.uint32)
+        got = _load().orc_big_landmarks(self._h, k, out.ctypes.data)
+        return out[:got].copy()
+
+    def degrees(self):
+        indeg = np.zeros(self.n, np.uint32)
+        outdeg = np.zeros(self.n, np.uint32)
+        _load().orc_big_degrees(self._h, indeg.ctypes.data, outdeg.ctypes.data)
+        return indeg, outdeg
+
+    def leaves(self, landmarks, kp: int = 64):
+        """(S_in mask, S_out mask, bucket) under the default leaf rule and Fibonacci hashing."""
+        indeg, outdeg = self.degrees()
+        lm = np.zeros(self.n, bool)
+        lm[np.asarray(landmarks, dtype=np.int64)] = True
+        bits = int(kp).bit_length() - 1
+        x = np.arange(self.n, dtype=np.uint64)
+        bucket = ((x * np.uint64(0x9E3779B97F4A7C15)) >> np.uint64(64 - bits)).astype(np.uint8) \
+            if bits else np.zeros(self.n, np.uint8)
+        return (indeg == 0) & ~lm, (outdeg == 0) & ~lm, bucket
+
+    def reach(self, sources, forward: bool = True) -> np.ndarray:
+        """Boolean mask of the vertices reached from the source set (sources included)."""
+        s = _u32(sources)
+        words = (self.n + 63) // 64
+        bm = np.zeros(words, dtype=np.uint64)
+        got = _load().orc_big_reach(self._h, len(s), s.ctypes.data, 1 if forward else 0,
+                                    bm.ctypes.data)
+        if got < 0:
+            raise MemoryError("orc_big_reach failed")
+        bits = np.unpackbits(bm.view(np.uint8), bitorder="little")[:self.n]
+        return bits.astype(bool)
+
+    def query_truth(self, u, v, threads: int = 1) -> np.ndarray:
+        u, v = _u32(u), _u32(v)
+        out = np.zeros(max(len(u), 1), dtype=np.uint8)
+        rc = _load().orc_big_query_truth(self._h, len(u), u.ctypes.data, v.ctypes.data,
+                                         out.ctypes.data, threads)
+        if rc:
+            raise ValueError("query failed")
+        return out[:len(u)].copy()
 
 
 def build_index(n, src, dst, **kw) -> OracleIndex:

@@ -666,3 +666,189 @@ int orc_closure(const orc_index *ix, uint64_t *rows) {
         for (uint32_t w = 0; w < words; w++) rows[(size_t)i * words + w] |= rows[(size_t)k * words + w];
   return 0;
 }
+
+/* ---------------------------------------------------------------- large graphs (sampled checks) */
+/*
+ * For graphs too large for the per-vertex lists above: forward and reverse CSR built by a
+ * counting sort (self-loops dropped; the edges are expected to be distinct), with
+ *   - the landmark selection of Section 3.1 and the leaf rule (readings R5, R7, R8),
+ *   - the reachable set of a source set (one BFS of Algorithm 1: the vertices whose label has
+ *     the source set's bit),
+ *   - plain BFS reachability per pair.
+ * A label column of the full index can then be checked one bit at a time.
+ */
+typedef struct {
+  uint32_t n;
+  uint64_t *fo, *ro; /* [n + 1] */
+  uint32_t *fc, *rc;
+} orc_big;
+
+void orc_big_free(orc_big *g) {
+  if (!g) return;
+  free(g->fo); free(g->ro); free(g->fc); free(g->rc);
+  free(g);
+}
+
+orc_big *orc_big_new(uint32_t n, uint64_t m, const uint32_t *src, const uint32_t *dst) {
+  orc_big *g = (orc_big *)calloc(1, sizeof(orc_big));
+  if (!g) return NULL;
+  g->n = n;
+  g->fo = (uint64_t *)calloc((size_t)n + 1, sizeof(uint64_t));
+  g->ro = (uint64_t *)calloc((size_t)n + 1, sizeof(uint64_t));
+  if (!g->fo || !g->ro) { orc_big_free(g); return NULL; }
+  uint64_t kept = 0;
+  for (uint64_t e = 0; e < m; e++) {
+    if (src[e] >= n || dst[e] >= n) { orc_big_free(g); return NULL; }
+    if (src[e] == dst[e]) continue;
+    g->fo[src[e] + 1]++;
+    g->ro[dst[e] + 1]++;
+    kept++;
+  }
+  for (uint32_t x = 0; x < n; x++) { g->fo[x + 1] += g->fo[x]; g->ro[x + 1] += g->ro[x]; }
+  g->fc = (uint32_t *)malloc(sizeof(uint32_t) * (kept ? kept : 1));
+  g->rc = (uint32_t *)malloc(sizeof(uint32_t) * (kept ? kept : 1));
+  uint64_t *ff = (uint64_t *)malloc(sizeof(uint64_t) * ((size_t)n + 1));
+  uint64_t *rf = (uint64_t *)malloc(sizeof(uint64_t) * ((size_t)n + 1));
+  if (!g->fc || !g->rc || !ff || !rf) { free(ff); free(rf); orc_big_free(g); return NULL; }
+  memcpy(ff, g->fo, sizeof(uint64_t) * ((size_t)n + 1));
+  memcpy(rf, g->ro, sizeof(uint64_t) * ((size_t)n + 1));
+  for (uint64_t e = 0; e < m; e++) {
+    if (src[e] == dst[e]) continue;
+    g->fc[ff[src[e]]++] = dst[e];
+    g->rc[rf[dst[e]]++] = src[e];
+  }
+  free(ff); free(rf);
+  return g;
+}
+
+/* top-k by |Pre|*|Suc| (ties by smaller id), as orc_select_landmarks */
+uint32_t orc_big_landmarks(const orc_big *g, uint32_t k, uint32_t *out) {
+  uint32_t have = 0;
+  for (uint32_t x = 0; x < g->n; x++) {
+    const uint64_t mx = (g->ro[x + 1] - g->ro[x]) * (g->fo[x + 1] - g->fo[x]);
+    uint32_t p;
+    if (have < k) {
+      p = have++;
+    } else if (k > 0) {
+      const uint32_t y = out[k - 1];
+      const uint64_t my = (g->ro[y + 1] - g->ro[y]) * (g->fo[y + 1] - g->fo[y]);
+      if (!(mx > my || (mx == my && x < y))) continue;
+      p = k - 1;
+    } else {
+      continue;
+    }
+    while (p > 0) {
+      const uint32_t y = out[p - 1];
+      const uint64_t my = (g->ro[y + 1] - g->ro[y]) * (g->fo[y + 1] - g->fo[y]);
+      if (!(mx > my || (mx == my && x < y))) break;
+      out[p] = out[p - 1];
+      p--;
+    }
+    out[p] = x;
+  }
+  return have;
+}
+
+/* in-degree and out-degree per vertex */
+void orc_big_degrees(const orc_big *g, uint32_t *indeg, uint32_t *outdeg) {
+  for (uint32_t x = 0; x < g->n; x++) {
+    indeg[x] = (uint32_t)(g->ro[x + 1] - g->ro[x]);
+    outdeg[x] = (uint32_t)(g->fo[x + 1] - g->fo[x]);
+  }
+}
+
+/* Reachable set (bitmap, n bits) of a source set, forward over Suc or backward over Pre;
+   sources included. Returns the number of vertices reached, or -1 on allocation failure. */
+int64_t orc_big_reach(const orc_big *g, uint64_t ns, const uint32_t *sources, int forward,
+                      uint64_t *bitmap) {
+  const uint64_t *off = forward ? g->fo : g->ro;
+  const uint32_t *col = forward ? g->fc : g->rc;
+  uint32_t *queue = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(g->n ? g->n : 1));
+  if (!queue) return -1;
+  memset(bitmap, 0, 8 * (size_t)((g->n + 63) / 64));
+  uint64_t head = 0, tail = 0;
+  for (uint64_t i = 0; i < ns; i++) {
+    const uint32_t s = sources[i];
+    if (bitmap[s >> 6] >> (s & 63) & 1) continue;
+    bitmap[s >> 6] |= 1ULL << (s & 63);
+    queue[tail++] = s;
+  }
+  while (head < tail) {
+    const uint32_t p = queue[head++];
+    for (uint64_t j = off[p]; j < off[p + 1]; j++) {
+      const uint32_t x = col[j];
+      if (bitmap[x >> 6] >> (x & 63) & 1) continue;
+      bitmap[x >> 6] |= 1ULL << (x & 63);
+      queue[tail++] = x;
+    }
+  }
+  free(queue);
+  return (int64_t)tail;
+}
+
+typedef struct {
+  const orc_big *g;
+  const uint32_t *u, *v;
+  uint8_t *out;
+  uint64_t count, next;
+  int failed;
+} orc_big_qpool;
+
+static void *big_query_worker(void *arg) {
+  orc_big_qpool *p = (orc_big_qpool *)arg;
+  const orc_big *g = p->g;
+  uint32_t *queue = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(g->n ? g->n : 1));
+  uint64_t *seen = (uint64_t *)calloc((g->n + 63) / 64 + 1, sizeof(uint64_t));
+  if (!queue || !seen) {
+    __atomic_store_n(&p->failed, 1, __ATOMIC_RELAXED);
+    free(queue); free(seen);
+    return NULL;
+  }
+  for (;;) {
+    const uint64_t i = __atomic_fetch_add(&p->next, 1, __ATOMIC_RELAXED);
+    if (i >= p->count) break;
+    const uint32_t u = p->u[i], v = p->v[i];
+    int found = u == v;
+    uint64_t head = 0, tail = 0;
+    if (!found) {
+      seen[u >> 6] |= 1ULL << (u & 63);
+      queue[tail++] = u;
+    }
+    while (!found && head < tail) {
+      const uint32_t w = queue[head++];
+      for (uint64_t j = g->fo[w]; j < g->fo[w + 1]; j++) {
+        const uint32_t x = g->fc[j];
+        if (x == v) { found = 1; break; }
+        if (seen[x >> 6] >> (x & 63) & 1) continue;
+        seen[x >> 6] |= 1ULL << (x & 63);
+        queue[tail++] = x;
+      }
+    }
+    for (uint64_t j = 0; j < tail; j++) seen[queue[j] >> 6] = 0;
+    p->out[i] = (uint8_t)found;
+  }
+  free(queue);
+  free(seen);
+  return NULL;
+}
+
+/* Plain BFS reachability per pair (u reaches u), on `threads` threads. */
+int orc_big_query_truth(const orc_big *g, uint64_t count, const uint32_t *u, const uint32_t *v,
+                        uint8_t *out, uint32_t threads) {
+  for (uint64_t i = 0; i < count; i++)
+    if (u[i] >= g->n || v[i] >= g->n) return -1;
+  orc_big_qpool pool = {g, u, v, out, count, 0, 0};
+  if (threads <= 1) {
+    big_query_worker(&pool);
+  } else {
+    pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * threads);
+    uint32_t started = 0;
+    if (th)
+      for (; started < threads; started++)
+        if (pthread_create(&th[started], NULL, big_query_worker, &pool)) break;
+    if (started == 0) big_query_worker(&pool);
+    for (uint32_t i = 0; i < started; i++) pthread_join(th[i], NULL);
+    free(th);
+  }
+  return pool.failed ? -1 : 0;
+}

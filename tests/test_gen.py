@@ -87,3 +87,14 @@ def test_zipf_sources_are_skewed():
     counts = np.sort(np.bincount(u, minlength=1 << 12))[::-1]
     assert counts[0] > 0.05 * 20000 and counts[:10].sum() > 0.2 * 20000
     assert v.max() < 1 << 12
+
+
+def test_large_chunked_stream_is_sorted_unique_and_thread_independent():
+    src, dst, isrc, idst = dblgen.rmat_large(15, 3, 1 << 19, 3000, threads=4, chunk=1 << 13)
+    keys = src.astype(np.uint64) << np.uint64(32) | dst.astype(np.uint64)
+    assert np.all(keys[1:] > keys[:-1]) and np.all(src != dst)
+    ik = isrc.astype(np.uint64) << np.uint64(32) | idst.astype(np.uint64)
+    assert len(np.intersect1d(keys, ik)) == 0 and len(np.unique(ik)) == len(ik)
+    s2, d2, i2, j2 = dblgen.rmat_large(15, 3, 1 << 19, 3000, threads=3, chunk=1 << 13)
+    assert np.array_equal(src, s2) and np.array_equal(dst, d2) and np.array_equal(isrc, i2)
+    assert 0.8 * (1 << 19) < len(src) < (1 << 19)

@@ -58,3 +58,31 @@ def test_threads_do_not_change_labels():
     b = oracle.OracleIndex(w.n, w.src, w.dst).build(threads=6).labels()
     for x, y in zip(a, b):
         assert np.array_equal(x, y)
+
+
+def test_big_graph_view_agrees_with_definitions():
+    """The large-graph view (CSR + one BFS per source set) against the per-vertex-list oracle,
+    itself pinned against brute force: landmarks, leaves, hash, every label bit column, and
+    plain reachability."""
+    w = dblgen.tiny_workload(1)
+    src = np.concatenate([w.src, w.ins_src])
+    dst = np.concatenate([w.dst, w.ins_dst])
+    big = oracle.BigGraph(w.n, src, dst)
+    ix = oracle.OracleIndex(w.n, src, dst).build(threads=4)
+    lm = big.landmarks(64)
+    assert np.array_equal(lm, ix.landmarks())
+    s_in, s_out, bucket = big.leaves(lm)
+    oi, oo, ob = ix.leaves()
+    assert np.array_equal(s_in, oi) and np.array_equal(s_out, oo) and np.array_equal(bucket, ob)
+    dl_in, dl_out, bl_in, bl_out = ix.labels()
+    one = np.uint64(1)
+    for i in range(0, 64, 7):
+        assert np.array_equal(big.reach([lm[i]], True), (dl_in >> np.uint64(i)) & one == 1)
+        assert np.array_equal(big.reach([lm[i]], False), (dl_out >> np.uint64(i)) & one == 1)
+    for j in range(0, 64, 5):
+        srcs = np.flatnonzero(s_in & (bucket == j))
+        assert np.array_equal(big.reach(srcs, True), (bl_in >> np.uint64(j)) & one == 1)
+        tgts = np.flatnonzero(s_out & (bucket == j))
+        assert np.array_equal(big.reach(tgts, False), (bl_out >> np.uint64(j)) & one == 1)
+    t = big.query_truth(w.q_u, w.q_v, threads=4)
+    assert np.array_equal(t, ix.query_truth(w.q_u, w.q_v, threads=4))
