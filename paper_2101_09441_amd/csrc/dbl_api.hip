@@ -511,7 +511,6 @@ dbl_status run_queries(dbl_index *ix, dbl_query_ctx *c, uint64_t count, const ui
                        const uint32_t *d_v, uint8_t *d_out, hipStream_t s,
                        uint32_t rules = DBL_RULES_ALL) {
   CKS(ctx_reserve(c, count));
-  CK(dbl::launch_ctl_reset_query(c->ctl, s));
   {
     Timed tm(ix, c->is_default ? (uint32_t)kTQueryLabel : (uint32_t)kTKinds, s);
     CK(dbl::launch_query_label({ix->lab}, d_u, d_v, count, ix->n, ix->f.deg, d_out, c->und,
@@ -534,11 +533,12 @@ dbl_status run_queries(dbl_index *ix, dbl_query_ctx *c, uint64_t count, const ui
   b.cnt = c->bfs_cnt;
   b.rules = rules;
   b.ctl = c->ctl;
+  const uint32_t seq = ++c->seq;
   {
     Timed tm(ix, c->is_default ? (uint32_t)kTQueryBfs : (uint32_t)kTKinds, s);
-    CK(dbl::launch_query_bfs(b, c->slots, s));
+    CK(dbl::launch_query_bfs(b, c->slots, c->mirror, seq, s));
   }
-  CKS(sync_chan(c->ctl, c->mirror, c->hs, c->seq, s));
+  CKS(wait_mirror(c->mirror, c->hs, s, seq));
   if (c->is_default && !ix->pending.empty()) resolve_times(ix);
   if (c->hs.err) {
     CK(dbl::launch_fill_u32((uint32_t *)((char *)c->ctl + offsetof(Ctl, err)), 0u, 1, s));

@@ -24,7 +24,7 @@ constexpr uint32_t kLocalMaxEdges = 1u << 16;
 constexpr uint32_t kLocalThreads = 1024;
 
 // Insert batches up to this size are validated, applied and propagated by one workgroup.
-constexpr uint32_t kSmallBatch = 256;
+constexpr uint32_t kSmallBatch = 2048;
 
 constexpr uint32_t kErrRange = 1u;
 
@@ -61,7 +61,8 @@ struct Ctl {
   uint32_t bfs_heavy;   // queries whose BFS outgrew a slot
   uint32_t found;       // grid BFS: target reached
   uint32_t local_rounds;
-  uint32_t pad[2];
+  uint32_t bfs_done;    // BFS waves finished (the last one publishes the status)
+  uint32_t pad[1];
   unsigned long long ctr[kCtrCount];
 };
 
@@ -195,7 +196,9 @@ struct BfsArgs {
   uint32_t rules;           // bit 0: DL prune, bit 1: BL prune
   Ctl *ctl;
 };
-hipError_t launch_query_bfs(const BfsArgs &a, uint32_t slots, hipStream_t s);
+// The last wave to finish publishes the context's status (mirror m, sequence seq).
+hipError_t launch_query_bfs(const BfsArgs &a, uint32_t slots, Mirror *m, uint32_t seq,
+                            hipStream_t s);
 // grid BFS for one query (u, v) whose slot overflowed
 hipError_t launch_gbfs_start(const PropArgs &a, unsigned long long *vis, uint64_t vis_words,
                              uint32_t u, hipStream_t s);

@@ -815,17 +815,17 @@ __global__ __launch_bounds__(kLocalThreads) void k_insert_small(PropArgs a, cons
   __shared__ uint32_t s_pushed, s_ovf;
   Ctl *ctl = a.ctl;
   const uint32_t t = threadIdx.x;
-  const bool act = t < 2 * count;  // 2 * count <= kLocalThreads
-  uint32_t u = 0, v = 0;
-  if (act) {
-    u = src[t >> 1];
-    v = dst[t >> 1];
-  }
+  const uint32_t halves = 2 * count;  // half j: edge j / 2, direction j % 2
   if (t == 0) {
     s_pushed = 0;
     s_ovf = 0;
   }
-  if (__syncthreads_or(act && (u >= n || v >= n))) {
+  bool bad = false;
+  for (uint32_t j = t; j < halves; j += kLocalThreads) {
+    const uint32_t i = j >> 1;
+    bad |= (src[i] >= n) | (dst[i] >= n);
+  }
+  if (__syncthreads_or(bad)) {
     if (t == 0) {
       atomicOr(&ctl->err, kErrRange);
       __hip_atomic_store(&m->fast, ((u64)kFastErr << 32) | seq, __ATOMIC_RELAXED,
@@ -838,8 +838,15 @@ __global__ __launch_bounds__(kLocalThreads) void k_insert_small(PropArgs a, cons
     ctl->heavy[0] = 0;
     ctl->heavy[1] = 0;
   }
-  bool ovfl = false;
-  if (apply_half(a, u, v, t & 1u, ring, stamp, ovf, ovf_cap, act, &ovfl)) s_pushed = 1;
+  bool pushed = false, ovfl = false;
+  for (uint32_t j0 = 0; j0 < halves; j0 += kLocalThreads) {
+    const uint32_t j = j0 + t;
+    const bool act = j < halves;
+    const uint32_t i = act ? j >> 1 : 0u;
+    pushed |= apply_half(a, act ? src[i] : 0u, act ? dst[i] : 0u, j & 1u, ring, stamp, ovf,
+                         ovf_cap, act, &ovfl);
+  }
+  if (pushed) s_pushed = 1;
   if (ovfl) s_ovf = 1;
   __syncthreads();
   // nothing changed: the pending frontier is still empty and no round is needed
@@ -965,6 +972,11 @@ __global__ __launch_bounds__(kQueryNT) void k_query_label(const u64 *lab, const 
   __shared__ uint32_t s_und[kQueryNT / 64];
   const uint64_t i = (uint64_t)blockIdx.x * kQueryNT + threadIdx.x;
   const bool act = i < count;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    // per-call counters of the BFS kernel that follows on the stream
+    ctl->bfs_heavy = 0;
+    ctl->bfs_done = 0;
+  }
   int cls = -1;
   bool undecided = false, bad = false;
   if (act) {
@@ -1036,7 +1048,7 @@ hipError_t launch_query_label(LabelsView L, const uint32_t *u, const uint32_t *v
 // queue, so a bitmap is clean again for the wave's next pair.
 constexpr uint32_t kBfsNT = 256;
 
-__global__ __launch_bounds__(kBfsNT) void k_query_bfs(BfsArgs a) {
+__global__ __launch_bounds__(kBfsNT) void k_query_bfs(BfsArgs a, Mirror *m, uint32_t seq) {
   Ctl *ctl = a.ctl;
   const uint32_t lane = __lane_id();
   const uint32_t slot = blockIdx.x * (kBfsNT / 64u) + (threadIdx.x >> 6);
@@ -1145,10 +1157,19 @@ __global__ __launch_bounds__(kBfsNT) void k_query_bfs(BfsArgs a) {
     c[2] += cls_t;
     c[3] += cls_f;
   }
+  if (lane == 0) {
+    // make this wave's answers visible before counting it as done; the last wave publishes
+    __threadfence();
+    if (atomicAdd(&ctl->bfs_done, 1u) == waves - 1u) {
+      __threadfence();
+      publish_status(ctl, m, seq);
+    }
+  }
 }
 
-hipError_t launch_query_bfs(const BfsArgs &a, uint32_t slots, hipStream_t s) {
-  hipLaunchKernelGGL(k_query_bfs, dim3(slots / (kBfsNT / 64u)), dim3(kBfsNT), 0, s, a);
+hipError_t launch_query_bfs(const BfsArgs &a, uint32_t slots, Mirror *m, uint32_t seq,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_query_bfs, dim3(slots / (kBfsNT / 64u)), dim3(kBfsNT), 0, s, a, m, seq);
   return hipGetLastError();
 }
 
