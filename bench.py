@@ -325,12 +325,17 @@ def main():
     def batched(plain_labels, plain_answers):
         """The batched form on the same inputs: insertion batches of 1k/10k/100k edges and query
         batches of 65,536 pairs; labels and answers must equal the plain form's."""
+        from paper_2101_09441_amd import autotune
         res = {}
         qb = 65536
+        mk = lambda: dbl.Index.build(w.n, src, dst, edges_unique=True)  # noqa: E731
         for bsz in (1000, 10000, 100000):
             if bsz > n_ins:
                 continue
-            ix = dbl.Index.build(w.n, src, dst, edges_unique=True)
+            tuned = autotune.tune_insertions(mk, isrc, idst, bsz, w.m, max_batches=10)
+            ix = mk()
+            ix.set_tuning(**{k: tuned[k] for k in ("small_batch", "local_max_frontier",
+                                                   "local_max_edges", "round_grid")})
             torch.cuda.synchronize()
             times = []
             t0 = time.perf_counter()
@@ -344,8 +349,11 @@ def main():
                      "batch_ms_p50": float(np.percentile(times, 50) * 1e3),
                      "batch_ms_p99": float(np.percentile(times, 99) * 1e3),
                      "speedup_vs_plain": (n_ins / t_ins) / (n_ins / insert_s),
-                     "labels_equal_plain": bool(same)}
+                     "labels_equal_plain": bool(same),
+                     "tuning": {k: tuned[k] for k in ("small_batch", "local_max_frontier",
+                                                      "local_max_edges", "round_grid")}}
             if bsz == 1000:
+                qtuned = autotune.tune_queries(ix, qu, qv, qb, w.m)
                 qout = torch.empty_like(out)
                 qt = []
                 torch.cuda.synchronize()
@@ -359,7 +367,8 @@ def main():
                     "queries_per_s": n_q / t_q, "batches": len(qt),
                     "batch_ms_p50": float(np.percentile(qt, 50) * 1e3),
                     "batch_ms_p99": float(np.percentile(qt, 99) * 1e3),
-                    "answers_equal_plain": bool(torch.equal(qout, plain_answers))}
+                    "answers_equal_plain": bool(torch.equal(qout, plain_answers)),
+                    "tuning": {"bfs_slots": qtuned["bfs_slots"]}}
             res[f"insert_batch_{bsz}"] = entry
             ix.close()
         return res

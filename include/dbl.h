@@ -216,6 +216,21 @@ dbl_status dbl_time_kernels(dbl_index *ix, const char *kinds);
 dbl_status dbl_read_kernel_times(dbl_index *ix, dbl_kernel_time *h_out, uint32_t cap,
                                  uint32_t *count);
 
+/* Runtime tuning. None of these changes a label or an answer (the labels are the unique least
+   fixpoint whatever the schedule); they change how work is split into launches. */
+typedef struct {
+  uint32_t small_batch;        /* insertion batches up to this size run in one workgroup
+                                  (0..65536; default 2048) */
+  uint32_t local_max_frontier; /* single-workgroup propagation rounds while the frontier has at
+                                  most this many entries (default 8192) */
+  uint32_t local_max_edges;    /* ... and would scan at most this many edges (default 65536) */
+  uint32_t round_grid;         /* blocks of a grid propagation round (1..2048; default 2048) */
+  uint32_t bfs_slots;          /* BFS slots of the index's own query context (default 1024) */
+} dbl_tuning;
+
+dbl_status dbl_get_tuning(const dbl_index *ix, dbl_tuning *out);
+dbl_status dbl_set_tuning(dbl_index *ix, const dbl_tuning *t);
+
 /* Vertex count of the index. */
 uint32_t dbl_num_vertices(const dbl_index *ix);
 

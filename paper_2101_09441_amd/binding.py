@@ -24,7 +24,8 @@ EXPORTS = [
     "dbl_query_batch", "dbl_query_ctx_bytes", "dbl_query_ctx_create", "dbl_query_batch_ctx",
     "dbl_query_ctx_destroy", "dbl_query_batch_rules",
     "dbl_read_labels", "dbl_get_landmarks", "dbl_get_leaves", "dbl_get_stats",
-    "dbl_time_kernels", "dbl_read_kernel_times", "dbl_num_vertices", "dbl_destroy",
+    "dbl_time_kernels", "dbl_read_kernel_times", "dbl_get_tuning", "dbl_set_tuning",
+    "dbl_num_vertices", "dbl_destroy",
     "dbl_status_str",
 ]
 
@@ -60,6 +61,16 @@ class DblStats(ctypes.Structure):
         ("bfs_vertices", ctypes.c_uint64),
         ("bfs_edges", ctypes.c_uint64),
         ("bfs_heavy", ctypes.c_uint64),
+    ]
+
+
+class DblTuning(ctypes.Structure):
+    _fields_ = [
+        ("small_batch", ctypes.c_uint32),
+        ("local_max_frontier", ctypes.c_uint32),
+        ("local_max_edges", ctypes.c_uint32),
+        ("round_grid", ctypes.c_uint32),
+        ("bfs_slots", ctypes.c_uint32),
     ]
 
 
@@ -125,6 +136,10 @@ def load_library():
     lib.dbl_read_kernel_times.argtypes = [P, ctypes.POINTER(DblKernelTime), u32,
                                           ctypes.POINTER(u32)]
     lib.dbl_read_kernel_times.restype = i32
+    lib.dbl_get_tuning.argtypes = [P, ctypes.POINTER(DblTuning)]
+    lib.dbl_get_tuning.restype = i32
+    lib.dbl_set_tuning.argtypes = [P, ctypes.POINTER(DblTuning)]
+    lib.dbl_set_tuning.restype = i32
     lib.dbl_num_vertices.argtypes = [P]
     lib.dbl_num_vertices.restype = u32
     lib.dbl_destroy.argtypes = [P]
@@ -369,6 +384,24 @@ class Index:
             _check(load_library().dbl_get_leaves(self._handle(), flags.ctypes.data,
                                                  bucket.ctypes.data), "dbl_get_leaves")
         return flags, bucket
+
+    def tuning(self) -> dict:
+        t = DblTuning()
+        _check(load_library().dbl_get_tuning(self._handle(), ctypes.byref(t)), "dbl_get_tuning")
+        return {name: getattr(t, name) for name, _ in DblTuning._fields_}
+
+    def set_tuning(self, **kw) -> None:
+        """Change tuning fields (small_batch, local_max_frontier, local_max_edges, round_grid,
+        bfs_slots); results never change."""
+        cur = self.tuning()
+        bad = set(kw) - set(cur)
+        if bad:
+            raise KeyError(f"unknown tuning fields {sorted(bad)}")
+        cur.update(kw)
+        t = DblTuning(**cur)
+        with torch.cuda.device(self.device):
+            _check(load_library().dbl_set_tuning(self._handle(), ctypes.byref(t)),
+                   "dbl_set_tuning")
 
     def time_kernels(self, kinds: Optional[str]) -> None:
         """Time launches of the given kernel kinds with HIP events ("all", a comma list, None)."""

@@ -66,6 +66,10 @@ struct dbl_index {
   uint8_t *leaf_flags = nullptr, *bucket = nullptr;
   u64 *scan_tmp = nullptr, *scan_total = nullptr;
   uint64_t scan_tmp_words = 0;
+  // runtime tuning (never changes a result)
+  uint32_t small_batch = dbl::kSmallBatch;
+  uint32_t local_max_frontier = dbl::kLocalMaxFrontier, local_max_edges = dbl::kLocalMaxEdges;
+  uint32_t round_grid = dbl::kRoundGridMax;
   // query contexts: the default one and those created by callers (guarded by ctx_mu)
   uint32_t slots_opt = 0, qcap_opt = 0;
   dbl_query_ctx *qctx = nullptr;
@@ -214,6 +218,8 @@ dbl::PropArgs prop_args(const dbl_index *ix) {
   a.heavy_list = ix->heavy_list;
   a.heavy_cap = ix->heavy_cap;
   a.pcnt = ix->pcnt;
+  a.local_max_frontier = ix->local_max_frontier;
+  a.local_max_edges = ix->local_max_edges;
   a.ctl = ix->ctl;
   return a;
 }
@@ -334,13 +340,15 @@ dbl_status grid_propagate(dbl_index *ix, hipStream_t s, uint32_t group, uint64_t
     }
     dbl::PropArgs a = prop_args(ix);
     uint32_t ring = cur;
-    uint32_t grid = (uint32_t)std::min<uint64_t>(2048, std::max<uint64_t>(64, (fsz + 255) / 256));
+    const uint32_t gmax = ix->round_grid;
+    uint32_t grid = (uint32_t)std::min<uint64_t>(gmax, std::max<uint64_t>(std::min(64u, gmax),
+                                                                          (fsz + 255) / 256));
     for (uint32_t g = 0; g < group; g++) {
       Timed tm(ix, kTRound, s);
       CK(dbl::launch_round(a, ring, stamp, grid, s));
       ring = ring == 2 ? 0 : ring + 1;
       stamp++;
-      grid = 2048;
+      grid = gmax;
     }
     *rounds += group;
   }
@@ -793,7 +801,7 @@ dbl_status dbl_insert_edges(dbl_index *ix, uint64_t count, const uint32_t *d_src
   }
   dbl::PropArgs a = prop_args(ix);
   const uint32_t seq = ++ix->seq;
-  if (count <= dbl::kSmallBatch) {
+  if (count <= ix->small_batch) {
     {
       Timed tm(ix, kTInsertSmall, s);
       CK(dbl::launch_insert_small(a, d_src, d_dst, (uint32_t)count, ix->n, ix->ovf, ix->ovf_cap,
@@ -1048,6 +1056,47 @@ dbl_status dbl_read_kernel_times(dbl_index *ix, dbl_kernel_time *h_out, uint32_t
     o.max_ms = ix->t_max[k];
   }
   *count = w;
+  return DBL_OK;
+}
+
+dbl_status dbl_get_tuning(const dbl_index *ix, dbl_tuning *out) {
+  if (!ix || !out) return DBL_ERR_INVALID_ARG;
+  out->small_batch = ix->small_batch;
+  out->local_max_frontier = ix->local_max_frontier;
+  out->local_max_edges = ix->local_max_edges;
+  out->round_grid = ix->round_grid;
+  out->bfs_slots = ix->qctx ? ix->qctx->slots : (ix->slots_opt ? ix->slots_opt : 1024);
+  return DBL_OK;
+}
+
+dbl_status dbl_set_tuning(dbl_index *ix, const dbl_tuning *t) {
+  if (!ix || !t) return DBL_ERR_INVALID_ARG;
+  if (t->small_batch > dbl::kSmallBatchMax || t->round_grid == 0 ||
+      t->round_grid > dbl::kRoundGridMax || t->bfs_slots > (1u << 16))
+    return DBL_ERR_INVALID_ARG;
+  DeviceGuard dg(ix->device);
+  ix->small_batch = t->small_batch;
+  ix->local_max_frontier = t->local_max_frontier;
+  ix->local_max_edges = t->local_max_edges;
+  ix->round_grid = t->round_grid;
+  const uint32_t slots = t->bfs_slots ? std::max<uint32_t>(4, (t->bfs_slots + 3) / 4 * 4) : 0;
+  if (slots && (!ix->qctx || ix->qctx->slots != slots)) {
+    // rebuild the index's own query context with the new slot count (its counters are kept)
+    ix->slots_opt = slots;
+    if (ix->qctx) {
+      std::lock_guard<std::mutex> lk(ix->ctx_mu);
+      uint64_t cls[7] = {}, bv = 0, be = 0;
+      CKS(ctx_add_counts(ix->qctx, cls, &bv, &be));
+      for (int k = 0; k < 7; k++) ix->retired_class[k] += cls[k];
+      ix->retired_bfs_v += bv;
+      ix->retired_bfs_e += be;
+      ix->retired_heavy += ix->qctx->bfs_heavy;
+      ctx_free(ix->qctx);
+      delete ix->qctx;
+      ix->qctx = nullptr;
+    }
+    CKS(ensure_default_ctx(ix));
+  }
   return DBL_OK;
 }
 

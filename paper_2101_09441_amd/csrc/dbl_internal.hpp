@@ -18,13 +18,16 @@ constexpr uint32_t kHeavyDeg = 4096;
 constexpr uint32_t kChunk = 4096;
 
 // Single-workgroup propagation handles a round itself while the frontier and the edges it
-// would scan stay below these bounds; above them it hands the frontier to grid rounds.
+// would scan stay below runtime bounds (defaults below); above them it hands the frontier to
+// grid rounds.
 constexpr uint32_t kLocalMaxFrontier = 8192;
 constexpr uint32_t kLocalMaxEdges = 1u << 16;
 constexpr uint32_t kLocalThreads = 1024;
 
-// Insert batches up to this size are validated, applied and propagated by one workgroup.
+// Insert batches up to this size (runtime, default below, at most kSmallBatchMax) are
+// validated, applied and propagated by one workgroup.
 constexpr uint32_t kSmallBatch = 2048;
+constexpr uint32_t kSmallBatchMax = 1u << 16;
 
 constexpr uint32_t kErrRange = 1u;
 
@@ -152,6 +155,7 @@ struct PropArgs {
   unsigned long long *heavy_list;
   uint64_t heavy_cap;
   unsigned long long *pcnt;  // [kPropCtrSlots * 2] per-block (expanded, relaxed) counters
+  uint32_t local_max_frontier, local_max_edges;
   Ctl *ctl;
 };
 // one grid round: expand the frontier at ring `ring` (entries stamped `stamp`)

@@ -691,7 +691,7 @@ __device__ void local_rounds_body(const PropArgs &a) {
   uint32_t rounds = 0;
   for (;;) {
     const uint32_t fsz = ld_agent32(&ctl->fsize[ring]);
-    if (fsz == 0 || fsz > kLocalMaxFrontier) break;
+    if (fsz == 0 || fsz > a.local_max_frontier) break;
     uint32_t my = 0;
     const uint32_t *fq = a.fq[ring];
     for (uint32_t i = t; i < fsz; i += kLocalThreads) {
@@ -705,7 +705,7 @@ __device__ void local_rounds_body(const PropArgs &a) {
     __syncthreads();
     const uint32_t edges = s_edges;
     __syncthreads();
-    if (edges > kLocalMaxEdges) break;
+    if (edges > a.local_max_edges) break;
     const uint32_t nring = ring == 2u ? 0u : ring + 1u;
     if (t == 0) st_agent32(&ctl->fsize[nring], 0u);
     __syncthreads();

@@ -348,3 +348,42 @@ def test_rmat18_build_insert_query():
     assert st["queries"] == 200000
     assert sum(st["query_class"].values()) == 200000
     assert np.bincount(got >> 1, minlength=7)[5:].sum() > 0  # some BFS ran
+
+
+@pytest.mark.parametrize("tuning", [
+    dict(small_batch=0, local_max_frontier=0, local_max_edges=0, round_grid=1, bfs_slots=4),
+    dict(small_batch=0, local_max_frontier=1 << 20, local_max_edges=1 << 30, round_grid=3),
+    dict(small_batch=65536, local_max_frontier=16, local_max_edges=64, round_grid=2048,
+         bfs_slots=2048),
+])
+def test_tuning_never_changes_results(tiny, tuning):
+    """Schedule independence: extreme tunings (every round on the grid, every round in one
+    workgroup, tiny grids, few or many BFS slots) give bit-identical labels and answers."""
+    w = tiny
+    g = gpu_index(w.n, w.src, w.dst)
+    g.set_tuning(**tuning)
+    assert all(g.tuning()[k] == v for k, v in tuning.items() if k != "bfs_slots")
+    o = oracle.OracleIndex(w.n, w.src, w.dst).build(threads=8)
+    for lo, hi in [(0, 1), (1, 400), (400, 1000)]:
+        g.insert_edges(dev(w.ins_src[lo:hi]), dev(w.ins_dst[lo:hi]))
+        o.insert(w.ins_src[lo:hi], w.ins_dst[lo:hi])
+    assert_labels_equal(g, o, str(tuning))
+    assert_queries_equal(g, o, w.q_u, w.q_v)
+
+
+def test_autotuner_picks_a_candidate(tiny, tmp_path, monkeypatch):
+    from paper_2101_09441_amd import autotune
+    monkeypatch.setenv("DBL_TUNE_CACHE", str(tmp_path / "tune.json"))
+    w = tiny
+    src, dst = dev(w.src), dev(w.dst)
+    mk = lambda: dbl.Index.build(w.n, src, dst)  # noqa: E731
+    r = autotune.tune_insertions(mk, dev(w.ins_src), dev(w.ins_dst), 100, w.m, max_batches=5)
+    assert {k: r[k] for k in ("small_batch", "round_grid")} in [
+        {k: c[k] for k in ("small_batch", "round_grid")} for c in autotune.INSERT_CANDIDATES]
+    g = mk()
+    q = autotune.tune_queries(g, dev(w.q_u), dev(w.q_v), 2000, w.m, reps=1)
+    assert g.tuning()["bfs_slots"] == q["bfs_slots"]
+    # cached second time
+    assert autotune.tune_queries(g, dev(w.q_u), dev(w.q_v), 2000, w.m)["bfs_slots"] == q["bfs_slots"]
+    o = oracle.OracleIndex(w.n, w.src, w.dst).build(threads=8)
+    assert_queries_equal(g, o, w.q_u, w.q_v)
