@@ -134,6 +134,15 @@ dbl_status dbl_insert_edges(dbl_index *ix, uint64_t count, const uint32_t *d_src
                             const uint32_t *d_dst, void *stream);
 
 /*
+ * Add `count` vertices (Section 1: the graph grows by new edges and vertices). The new ids are
+ * n .. n+count-1 (*first receives n; may be NULL). A new vertex has no edges and empty labels,
+ * and it is not a BL source: the leaf sets stay those fixed at build time. Edges to and from
+ * new vertices are then inserted with dbl_insert_edges. Any pending work on `stream` finishes
+ * first. Errors: INVALID_ARG if the vertex count would reach 2^31; OUT_OF_MEMORY.
+ */
+dbl_status dbl_add_vertices(dbl_index *ix, uint32_t count, uint32_t *first, void *stream);
+
+/*
  * The one-request-at-a-time form of dbl_insert_edges: edge i is inserted as its own request
  * (validate, append, seed, propagate to the fixpoint, report), in order, exactly as `count`
  * calls of dbl_insert_edges with one edge each. h_latency_us: optional HOST array [count] that

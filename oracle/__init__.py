@@ -82,6 +82,8 @@ def _load():
     lib.orc_in_degree.restype = u32
     lib.orc_out_degree.argtypes = [P, u32]
     lib.orc_out_degree.restype = u32
+    lib.orc_add_vertices.argtypes = [P, u32]
+    lib.orc_add_vertices.restype = u32
     lib.orc_big_new.argtypes = [u32, u64, P, P]
     lib.orc_big_new.restype = P
     lib.orc_big_free.argtypes = [P]
@@ -223,6 +225,14 @@ class OracleIndex:
         if rc:
             raise ValueError("orc_insert failed (vertex id out of range?)")
         return self
+
+    def add_vertices(self, count: int) -> int:
+        """Append `count` vertices without edges; returns the first new id."""
+        first = _load().orc_add_vertices(self._h, count)
+        if first == 0xFFFFFFFF:
+            raise MemoryError("orc_add_vertices failed")
+        self.n += count
+        return int(first)
 
     def num_edges(self) -> int:
         return int(_load().orc_num_edges(self._h))

@@ -44,6 +44,8 @@
  *   R11 The ablations of Table 4 ("the other label disabled"): with DL disabled the rules of
  *       Lemma 1 and Theorems 1-2 and the DL prune of the BFS are skipped; with BL disabled the
  *       rule of Lemma 2 and the BL prune are skipped. Answers stay exact.
+ *   R13 Vertex insertion (Section 1: "new edges and vertices"): a new vertex arrives without
+ *       edges; its labels are empty and it is not a BL source (the leaf sets stay fixed).
  *   R12 Selection variants of Table 3: the landmark rank may be max, min or sum of |Pre| and
  *       |Suc| instead of their product (ties by smaller id). Leaf threshold r (the leaf-
  *       selection paragraph of the experiments): r = 0 is the main body's rule (R7); r > 0
@@ -619,6 +621,40 @@ int orc_insert(orc_index *ix, uint64_t count, const uint32_t *src, const uint32_
   }
   ws_free(&w);
   return 0;
+}
+
+/* Append `count` new vertices (reading R13); returns the first new id, or UINT32_MAX on
+   allocation failure. */
+uint32_t orc_add_vertices(orc_index *ix, uint32_t count) {
+  const uint32_t n0 = ix->n, n1 = n0 + count;
+  if (n1 < n0) return ORC_NONE;
+  orc_list *suc = (orc_list *)realloc(ix->suc, sizeof(orc_list) * (size_t)n1);
+  if (!suc) return ORC_NONE;
+  ix->suc = suc;
+  orc_list *pre = (orc_list *)realloc(ix->pre, sizeof(orc_list) * (size_t)n1);
+  if (!pre) return ORC_NONE;
+  ix->pre = pre;
+  uint8_t **u8s[3] = {&ix->in_leaf, &ix->out_leaf, &ix->bucket};
+  for (int i = 0; i < 3; i++) {
+    uint8_t *p = (uint8_t *)realloc(*u8s[i], (size_t)n1);
+    if (!p) return ORC_NONE;
+    *u8s[i] = p;
+  }
+  uint64_t **labs[4] = {&ix->dl_in, &ix->dl_out, &ix->bl_in, &ix->bl_out};
+  for (int i = 0; i < 4; i++) {
+    uint64_t *p = (uint64_t *)realloc(*labs[i], 8 * (size_t)n1);
+    if (!p) return ORC_NONE;
+    *labs[i] = p;
+  }
+  for (uint32_t x = n0; x < n1; x++) {
+    memset(&ix->suc[x], 0, sizeof(orc_list));
+    memset(&ix->pre[x], 0, sizeof(orc_list));
+    ix->in_leaf[x] = ix->out_leaf[x] = 0;
+    ix->bucket[x] = (uint8_t)orc_hash(x, ix->kp ? ix->kp : 1);
+    ix->dl_in[x] = ix->dl_out[x] = ix->bl_in[x] = ix->bl_out[x] = 0;
+  }
+  ix->n = n1;
+  return n0;
 }
 
 /* ---------------------------------------------------------------- accessors */

@@ -20,7 +20,8 @@ CLASS_NAMES = ["self", "dl_hit", "bl_miss", "thm1", "thm2", "bfs_true", "bfs_fal
 
 # every symbol declared in include/dbl.h
 EXPORTS = [
-    "dbl_default_options", "dbl_build", "dbl_insert_edges", "dbl_insert_edges_each",
+    "dbl_default_options", "dbl_build", "dbl_add_vertices", "dbl_insert_edges",
+    "dbl_insert_edges_each",
     "dbl_query_batch", "dbl_query_ctx_bytes", "dbl_query_ctx_create", "dbl_query_batch_ctx",
     "dbl_query_ctx_destroy", "dbl_query_batch_rules",
     "dbl_read_labels", "dbl_get_landmarks", "dbl_get_leaves", "dbl_get_stats",
@@ -107,6 +108,8 @@ def load_library():
     lib.dbl_default_options.restype = None
     lib.dbl_build.argtypes = [u32, u64, P, P, ctypes.POINTER(DblOptions), P, ctypes.POINTER(P)]
     lib.dbl_build.restype = i32
+    lib.dbl_add_vertices.argtypes = [P, u32, ctypes.POINTER(u32), P]
+    lib.dbl_add_vertices.restype = i32
     lib.dbl_insert_edges.argtypes = [P, u64, P, P, P]
     lib.dbl_insert_edges.restype = i32
     lib.dbl_insert_edges_each.argtypes = [P, u64, P, P, P, P]
@@ -296,6 +299,16 @@ class Index:
         if self._h is None or not self._h.value:
             raise RuntimeError("index is closed")
         return self._h
+
+    def add_vertices(self, count: int, stream=None) -> int:
+        """Append `count` vertices without edges; returns the first new id."""
+        first = ctypes.c_uint32()
+        with torch.cuda.device(self.device):
+            st = load_library().dbl_add_vertices(self._handle(), count, ctypes.byref(first),
+                                                 _stream_ptr(stream))
+        _check(st, "dbl_add_vertices")
+        self.n += count
+        return int(first.value)
 
     def insert_edges(self, src: torch.Tensor, dst: torch.Tensor, stream=None) -> None:
         src, dst = _ids(src, "src"), _ids(dst, "dst")

@@ -45,6 +45,7 @@ struct dbl_query_ctx {
 struct dbl_index {
   int device = 0;
   uint32_t n = 0, k = 0, kp = 0, kp_bits = 0;
+  uint32_t n_cap = 0;  // vertices the per-vertex arrays have room for
   float slack_frac = 0.25f;
   uint32_t slack_min = 4;
   Csr f{}, r{};
@@ -435,15 +436,36 @@ void ctx_free(dbl_query_ctx *c) {
   for (int i = 0; i < 3; i++) dfree(c->gfq[i]);
 }
 
+// (Re)allocate the parts of a context sized by the vertex count: visited bitmaps and queues.
+dbl_status ctx_size_bfs(dbl_index *ix, dbl_query_ctx *c, uint32_t slots, uint32_t qcap) {
+  dfree(c->vis);
+  dfree(c->bfs_queue);
+  dfree(c->gvis);
+  for (int i = 0; i < 3; i++) dfree(c->gfq[i]);
+  const uint64_t words = (ix->n + 63) / 64;
+  hipStream_t s0 = nullptr;
+  CKS(dalloc(&c->vis, words * slots));
+  CKS(dalloc(&c->bfs_queue, (uint64_t)qcap * slots));
+  CK(dbl::launch_fill_u64(c->vis, 0ull, words * slots, s0));
+  CK(hipStreamSynchronize(s0));
+  c->slots = slots;
+  c->vis_words = words;
+  c->qcap = qcap;
+  return DBL_OK;
+}
+
+uint32_t ctx_qcap(const dbl_index *ix, uint32_t qcap) {
+  return qcap ? std::min<uint32_t>(qcap, ix->n)
+              : (ix->qcap_opt ? std::min<uint32_t>(ix->qcap_opt, ix->n)
+                              : (uint32_t)std::min<uint64_t>(ix->n, 1u << 18));
+}
+
 // Allocate a context's fixed scratch: control block, mirror, counters, BFS slots.
 dbl_status ctx_init(dbl_index *ix, dbl_query_ctx *c, uint32_t slots, uint32_t qcap) {
   c->ix = ix;
   slots = slots ? slots : (ix->slots_opt ? ix->slots_opt : 1024);
   slots = std::max<uint32_t>(4, (slots + 3) / 4 * 4);
-  qcap = qcap ? std::min<uint32_t>(qcap, ix->n)
-              : (ix->qcap_opt ? std::min<uint32_t>(ix->qcap_opt, ix->n)
-                              : (uint32_t)std::min<uint64_t>(ix->n, 1u << 18));
-  const uint64_t words = (ix->n + 63) / 64;
+  qcap = ctx_qcap(ix, qcap);
   hipStream_t s0 = nullptr;
   CKS(dalloc(&c->ctl, 1));
   CK(hipHostMalloc((void **)&c->mirror, sizeof(dbl::Mirror),
@@ -454,18 +476,12 @@ dbl_status ctx_init(dbl_index *ix, dbl_query_ctx *c, uint32_t slots, uint32_t qc
     memset(&init, 0, sizeof(init));
     CK(hipMemcpy(c->ctl, &init, sizeof(Ctl), hipMemcpyHostToDevice));
   }
-  CKS(dalloc(&c->vis, words * slots));
-  CKS(dalloc(&c->bfs_queue, (uint64_t)qcap * slots));
   CKS(dalloc(&c->bfs_cnt, (uint64_t)slots * dbl::kBfsCtrStride));
   CKS(dalloc(&c->qcls, (uint64_t)dbl::kQueryGrid * dbl::kQClsStride));
-  CK(dbl::launch_fill_u64(c->vis, 0ull, words * slots, s0));
   CK(dbl::launch_fill_u64(c->bfs_cnt, 0ull, (uint64_t)slots * dbl::kBfsCtrStride, s0));
   CK(dbl::launch_fill_u64(c->qcls, 0ull, (uint64_t)dbl::kQueryGrid * dbl::kQClsStride, s0));
   CK(hipStreamSynchronize(s0));
-  c->slots = slots;
-  c->vis_words = words;
-  c->qcap = qcap;
-  return DBL_OK;
+  return ctx_size_bfs(ix, c, slots, qcap);
 }
 
 dbl_status ctx_reserve(dbl_query_ctx *c, uint64_t count) {
@@ -714,6 +730,28 @@ dbl_status do_build(dbl_index *ix, uint64_t m, const uint32_t *src, const uint32
   return DBL_OK;
 }
 
+// Move p to a new allocation of new_count entries, keeping the first old_count.
+template <typename T>
+dbl_status grow(T *&p, uint64_t old_count, uint64_t new_count, hipStream_t s) {
+  T *q = nullptr;
+  CKS(dalloc(&q, new_count));
+  if (old_count) {
+    const hipError_t e = hipMemcpyAsync(q, p, sizeof(T) * old_count, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) {
+      dfree(q);
+      return from_hip(e);
+    }
+  }
+  const hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    dfree(q);
+    return from_hip(e);
+  }
+  dfree(p);
+  p = q;
+  return DBL_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -768,6 +806,7 @@ dbl_status dbl_build(uint32_t n, uint64_t m, const uint32_t *d_src, const uint32
     return DBL_ERR_DEVICE;
   }
   ix->n = n;
+  ix->n_cap = n;
   ix->k = k;
   ix->kp = o.bl_bits;
   ix->kp_bits = bits_of(o.bl_bits);
@@ -1056,6 +1095,54 @@ dbl_status dbl_read_kernel_times(dbl_index *ix, dbl_kernel_time *h_out, uint32_t
     o.max_ms = ix->t_max[k];
   }
   *count = w;
+  return DBL_OK;
+}
+
+
+dbl_status dbl_add_vertices(dbl_index *ix, uint32_t count, uint32_t *first, void *stream) {
+  if (!ix) return DBL_ERR_INVALID_ARG;
+  const uint64_t n0 = ix->n, n1 = n0 + count;
+  if (n1 > 0x7FFFFFFFull) return DBL_ERR_INVALID_ARG;
+  if (first) *first = (uint32_t)n0;
+  if (count == 0) return DBL_OK;
+  DeviceGuard dg(ix->device);
+  hipStream_t s = (hipStream_t)stream;
+  CK(hipStreamSynchronize(s));
+  if (n1 > ix->n_cap) {
+    const uint64_t cap = std::min<uint64_t>(0x7FFFFFFFull, std::max<uint64_t>(n1, ix->n_cap + ix->n_cap / 2));
+    for (Csr *g : {&ix->f, &ix->r}) {
+      CKS(grow(g->off, n0, cap, s));
+      CKS(grow(g->deg, n0, cap, s));
+      CKS(grow(g->cap, n0, cap, s));
+    }
+    CKS(grow(ix->lab, 4 * n0, 4 * cap, s));
+    for (int i = 0; i < 3; i++) CKS(grow(ix->fq[i], 0, 2 * cap, s));
+    CKS(grow(ix->inq, 2 * n0, 2 * cap, s));
+    CKS(grow(ix->leaf_flags, n0, cap, s));
+    CKS(grow(ix->bucket, n0, cap, s));
+    dfree(ix->scan_tmp);
+    ix->scan_tmp_words = dbl::scan_tmp_words((uint32_t)cap);
+    CKS(dalloc(&ix->scan_tmp, ix->scan_tmp_words));
+    ix->n_cap = (uint32_t)cap;
+  }
+  // new vertices: no edges (empty rows; the first append overflows and regrows the CSR),
+  // empty labels, not leaves, never queued
+  for (Csr *g : {&ix->f, &ix->r}) {
+    CK(dbl::launch_fill_u32(g->deg + n0, 0u, count, s));
+    CK(dbl::launch_fill_u32(g->cap + n0, 0u, count, s));
+    CK(dbl::launch_fill_u64(g->off + n0, 0ull, count, s));
+  }
+  CK(dbl::launch_fill_u64(ix->lab + 4 * n0, 0ull, 4ull * count, s));
+  CK(dbl::launch_fill_u32(ix->inq + 2 * n0, 0u, 2ull * count, s));
+  CK(hipMemsetAsync(ix->leaf_flags + n0, 0, count, s));
+  CK(dbl::launch_init_buckets(ix->bucket, (uint32_t)n0, (uint32_t)n1, ix->kp_bits, s));
+  CK(hipStreamSynchronize(s));
+  ix->n = (uint32_t)n1;
+  // query scratch is sized by the vertex count
+  std::lock_guard<std::mutex> lk(ix->ctx_mu);
+  std::vector<dbl_query_ctx *> all(ix->ctxs);
+  if (ix->qctx) all.push_back(ix->qctx);
+  for (dbl_query_ctx *c : all) CKS(ctx_size_bfs(ix, c, c->slots, ctx_qcap(ix, c->qcap == n0 ? 0 : c->qcap)));
   return DBL_OK;
 }
 

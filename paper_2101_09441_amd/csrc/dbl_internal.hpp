@@ -211,6 +211,10 @@ hipError_t launch_gbfs_round(const PropArgs &a, unsigned long long *vis, uint32_
 hipError_t launch_gbfs_finish(const PropArgs &a, uint32_t qi, uint8_t *out,
                               unsigned long long *qcls, hipStream_t s);
 
+// bucket[x] = h(x) for x in [n0, n1) (vertices added after the build; never BL sources)
+hipError_t launch_init_buckets(uint8_t *bucket, uint32_t n0, uint32_t n1, uint32_t kp_bits,
+                               hipStream_t s);
+
 hipError_t launch_unpack_labels(LabelsView L, uint32_t n, unsigned long long *dl_in,
                                 unsigned long long *dl_out, unsigned long long *bl_in,
                                 unsigned long long *bl_out, hipStream_t s);

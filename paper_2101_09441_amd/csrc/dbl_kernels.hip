@@ -1249,6 +1249,19 @@ hipError_t launch_gbfs_finish(const PropArgs &a, uint32_t qi, uint8_t *out, u64 
   return hipGetLastError();
 }
 
+__global__ void k_init_buckets(uint8_t *bucket, uint32_t n0, uint32_t n1, uint32_t kp_bits) {
+  for (uint32_t x = n0 + blockIdx.x * blockDim.x + threadIdx.x; x < n1; x += gridDim.x * blockDim.x)
+    bucket[x] = (uint8_t)fib_bucket(x, kp_bits);
+}
+
+hipError_t launch_init_buckets(uint8_t *bucket, uint32_t n0, uint32_t n1, uint32_t kp_bits,
+                               hipStream_t s) {
+  if (n1 <= n0) return hipSuccess;
+  hipLaunchKernelGGL(k_init_buckets, dim3(grid_for(n1 - n0, 256, 4096)), dim3(256), 0, s, bucket,
+                     n0, n1, kp_bits);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- label read-out
 
 __global__ void k_unpack_labels(const u64 *lab, uint32_t n, u64 *dl_in, u64 *dl_out, u64 *bl_in,

@@ -387,3 +387,33 @@ def test_autotuner_picks_a_candidate(tiny, tmp_path, monkeypatch):
     assert autotune.tune_queries(g, dev(w.q_u), dev(w.q_v), 2000, w.m)["bfs_slots"] == q["bfs_slots"]
     o = oracle.OracleIndex(w.n, w.src, w.dst).build(threads=8)
     assert_queries_equal(g, o, w.q_u, w.q_v)
+
+
+def test_vertex_insertion(tiny):
+    """Vertices added after the build (no edges, empty labels, not BL sources), then edges to
+    and from them, in several rounds that grow the per-vertex arrays more than once."""
+    w = tiny
+    g = gpu_index(w.n, w.src, w.dst)
+    o = oracle.OracleIndex(w.n, w.src, w.dst).build(threads=8)
+    rng = np.random.default_rng(12)
+    n = w.n
+    for add in (1, 100, 20000, 7):
+        assert g.add_vertices(add) == n
+        assert o.add_vertices(add) == n
+        n += add
+        iu = rng.integers(0, n, 300).astype(np.uint32)
+        iv = rng.integers(0, n, 300).astype(np.uint32)
+        iu[:50] = rng.integers(n - add, n, 50)
+        iv[50:100] = rng.integers(n - add, n, 50)
+        g.insert_edges(dev(iu), dev(iv))
+        o.insert(iu, iv)
+        assert_labels_equal(g, o, f"after adding {add}")
+        qu = rng.integers(0, n, 5000).astype(np.uint32)
+        qv = rng.integers(0, n, 5000).astype(np.uint32)
+        assert_queries_equal(g, o, qu, qv)
+    flags, bucket = g.leaves()
+    assert len(flags) == n and not flags[w.n:].any()
+    _, _, ob = o.leaves()
+    assert np.array_equal(bucket, ob)
+    with pytest.raises(dbl.DblError):
+        g.insert_edges(dev([0]), dev([n]))

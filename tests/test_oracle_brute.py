@@ -305,3 +305,35 @@ def test_insert_rejects_out_of_range():
     ix = oracle.OracleIndex(4, [0, 1], [1, 2]).build(k=2, kp=2)
     with pytest.raises(ValueError):
         ix.insert([0], [4])
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_vertex_insertion_vs_definitions(seed):
+    """New vertices (no edges, empty labels, not BL sources) then edges touching them: labels
+    equal the definitions on the grown graph with the build's landmarks, leaves and hash."""
+    rng = np.random.default_rng(300 + seed)
+    n0 = int(rng.integers(15, 60))
+    _, src, dst = g_er(n0, 0.05, 400 + seed)
+    kp = 8
+    bucket = random_bucket(n0, kp, seed)
+    ix = oracle.OracleIndex(n0, src, dst).build(k=4, kp=kp, bucket_table=bucket)
+    lm = list(ix.landmarks())
+    s_in, s_out = expected_leaves(n0, src, dst, lm)
+    add = int(rng.integers(1, 12))
+    assert ix.add_vertices(add) == n0
+    n = n0 + add
+    full_bucket = np.concatenate([bucket, np.array([oracle.fib_hash(x, kp) for x in range(n0, n)],
+                                                   np.uint8)])
+    iu = rng.integers(0, n, 30).astype(np.uint32)
+    iv = rng.integers(0, n, 30).astype(np.uint32)
+    iu[:5] = n - 1  # the newest vertex gains out-edges
+    ix.insert(iu, iv)
+    src = np.concatenate([src, iu]).astype(np.uint32)
+    dst = np.concatenate([dst, iv]).astype(np.uint32)
+    R = reach_matrix(n, src, dst)
+    exp = expected_labels(R, lm, s_in, s_out, full_bucket)
+    assert [as_sets(w_) for w_ in ix.labels()] == list(exp)
+    u = np.repeat(np.arange(n), n).astype(np.uint32)
+    v = np.tile(np.arange(n), n).astype(np.uint32)
+    want = np.array([expected_query(R, exp, int(a), int(b)) for a, b in zip(u, v)], np.uint8)
+    assert np.array_equal(ix.query_dbl(u, v), want)
