@@ -68,6 +68,8 @@ def _load():
     lib.orc_query_label_class.restype = i32
     lib.orc_insert.argtypes = [P, u64, P, P]
     lib.orc_insert.restype = i32
+    lib.orc_label_words.argtypes = [P, ctypes.POINTER(u32), ctypes.POINTER(u32)]
+    lib.orc_label_words.restype = None
     lib.orc_read_labels.argtypes = [P, P, P, P, P]
     lib.orc_read_labels.restype = None
     lib.orc_landmarks.argtypes = [P, P]
@@ -165,7 +167,7 @@ class OracleIndex:
         return out[:got].copy()
 
     def landmarks(self) -> np.ndarray:
-        out = np.zeros(64, dtype=np.uint32)
+        out = np.zeros(256, dtype=np.uint32)
         got = _load().orc_landmarks(self._h, out.ctypes.data)
         return out[:got].copy()
 
@@ -176,11 +178,18 @@ class OracleIndex:
         _load().orc_leaves(self._h, a.ctypes.data, b.ctypes.data, c.ctypes.data)
         return a.astype(bool), b.astype(bool), c
 
+    def label_words(self):
+        wd, wb = ctypes.c_uint32(), ctypes.c_uint32()
+        _load().orc_label_words(self._h, ctypes.byref(wd), ctypes.byref(wb))
+        return wd.value, wb.value
+
     def labels(self):
-        """(DL_in, DL_out, BL_in, BL_out), each uint64[n]."""
-        arrs = [np.zeros(self.n, dtype=np.uint64) for _ in range(4)]
+        """(DL_in, DL_out, BL_in, BL_out): uint64[n] for 64-bit labels, else uint64[n, words]
+        (bit i in word i // 64)."""
+        wd, wb = self.label_words()
+        arrs = [np.zeros((self.n, w), dtype=np.uint64) for w in (wd, wd, wb, wb)]
         _load().orc_read_labels(self._h, *[a.ctypes.data for a in arrs])
-        return tuple(arrs)
+        return tuple(a[:, 0].copy() if a.shape[1] == 1 else a for a in arrs)
 
     # -- queries (Algorithm 2)
     def _q(self, fn, u, v, threads):

@@ -44,6 +44,8 @@
  *   R11 The ablations of Table 4 ("the other label disabled"): with DL disabled the rules of
  *       Lemma 1 and Theorems 1-2 and the DL prune of the BFS are skipped; with BL disabled the
  *       rule of Lemma 2 and the BL prune are skipped. Answers stay exact.
+ *   R14 Labels longer than 64 bits (Table 5 uses k and k' up to 256): a label of k bits is
+ *       ceil(k / 64) 64-bit words per vertex; bit i lives in word i / 64 at position i % 64.
  *   R13 Vertex insertion (Section 1: "new edges and vertices"): a new vertex arrives without
  *       edges; its labels are empty and it is not a BL source (the leaf sets stay fixed).
  *   R12 Selection variants of Table 3: the landmark rank may be max, min or sum of |Pre| and
@@ -79,9 +81,10 @@ typedef struct {
   orc_list *suc; /* Suc(x) */
   orc_list *pre; /* Pre(x) */
   uint32_t k, kp;
+  uint32_t wd, wb;          /* 64-bit words per DL / BL label (reading R14) */
   uint32_t rank_mode;       /* 0 product, 1 max, 2 min, 3 sum */
   uint64_t leaf_threshold;  /* r */
-  uint32_t landmark[64];
+  uint32_t landmark[256];
   uint8_t *in_leaf, *out_leaf; /* membership in S_in / S_out, fixed at build */
   uint8_t *bucket;             /* h(x) for every x */
   uint64_t *dl_in, *dl_out, *bl_in, *bl_out;
@@ -147,6 +150,7 @@ orc_index *orc_new(uint32_t n, uint64_t m, const uint32_t *src, const uint32_t *
   ix->dl_out = (uint64_t *)calloc(nn, 8);
   ix->bl_in = (uint64_t *)calloc(nn, 8);
   ix->bl_out = (uint64_t *)calloc(nn, 8);
+  ix->wd = ix->wb = 1;
   if (!ix->suc || !ix->pre || !ix->in_leaf || !ix->out_leaf || !ix->bucket || !ix->dl_in ||
       !ix->dl_out || !ix->bl_in || !ix->bl_out) {
     orc_free(ix);
@@ -246,9 +250,10 @@ static void ws_next_stamp(orc_bfs_ws *w, uint32_t n) {
  * `bit` in `label` of every vertex reached, sources included (reading R1).
  */
 static void bfs_set_bit(const orc_index *ix, orc_bfs_ws *w, const uint32_t *sources, uint32_t ns,
-                        int forward, uint64_t *label, uint32_t bit, int atomic) {
+                        int forward, uint64_t *label, uint32_t words, uint32_t bit, int atomic) {
   const orc_list *adj = forward ? ix->suc : ix->pre;
-  const uint64_t mask = 1ULL << bit;
+  const uint64_t mask = 1ULL << (bit % 64);
+  label += bit / 64;
   ws_next_stamp(w, ix->n);
   uint64_t head = 0, tail = 0;
   for (uint32_t i = 0; i < ns; i++) {
@@ -259,8 +264,8 @@ static void bfs_set_bit(const orc_index *ix, orc_bfs_ws *w, const uint32_t *sour
   }
   while (head < tail) {
     uint32_t p = w->queue[head++];
-    if (atomic) __atomic_fetch_or(&label[p], mask, __ATOMIC_RELAXED);
-    else label[p] |= mask;
+    if (atomic) __atomic_fetch_or(&label[(size_t)p * words], mask, __ATOMIC_RELAXED);
+    else label[(size_t)p * words] |= mask;
     for (uint32_t j = 0; j < adj[p].len; j++) {
       uint32_t x = adj[p].v[j];
       if (w->seen[x] == w->stamp) continue;
@@ -274,6 +279,7 @@ static void bfs_set_bit(const orc_index *ix, orc_bfs_ws *w, const uint32_t *sour
 typedef struct {
   int forward;
   uint64_t *label;
+  uint32_t words;
   uint32_t bit;
   uint32_t *sources;
   uint32_t ns;
@@ -300,7 +306,8 @@ static void *pool_worker(void *arg) {
     uint32_t t = __atomic_fetch_add(&p->next, 1, __ATOMIC_RELAXED);
     if (t >= p->ntasks) break;
     orc_task *tk = &p->tasks[t];
-    bfs_set_bit(p->ix, &w, tk->sources, tk->ns, tk->forward, tk->label, tk->bit, p->atomic);
+    bfs_set_bit(p->ix, &w, tk->sources, tk->ns, tk->forward, tk->label, tk->words, tk->bit,
+                p->atomic);
   }
   ws_free(&w);
   return NULL;
@@ -315,8 +322,24 @@ static void *pool_worker(void *arg) {
  */
 int orc_build(orc_index *ix, uint32_t k, uint32_t kp, const uint32_t *landmarks,
               const uint8_t *bucket_table, const uint8_t *leaf_flags, uint32_t threads) {
-  if (k > 64 || kp == 0 || kp > 64 || (kp & (kp - 1))) return -1;
+  if (k > 256 || kp == 0 || kp > 256 || (kp & (kp - 1))) return -1;
   uint32_t n = ix->n;
+  {
+    /* label widths (reading R14), from the requested k before it is capped at n */
+    const uint32_t wd = k > 64 ? (k + 63) / 64 : 1, wb = kp > 64 ? kp / 64 : 1;
+    const size_t nn = n ? n : 1;
+    uint64_t **ld[2] = {&ix->dl_in, &ix->dl_out}, **lb[2] = {&ix->bl_in, &ix->bl_out};
+    for (int i = 0; i < 2; i++) {
+      uint64_t *p = (uint64_t *)realloc(*ld[i], 8 * nn * wd);
+      if (!p) return -1;
+      *ld[i] = p;
+      p = (uint64_t *)realloc(*lb[i], 8 * nn * wb);
+      if (!p) return -1;
+      *lb[i] = p;
+    }
+    ix->wd = wd;
+    ix->wb = wb;
+  }
   if (k > n) k = n;
   ix->k = k;
   ix->kp = kp;
@@ -346,10 +369,10 @@ int orc_build(orc_index *ix, uint32_t k, uint32_t kp, const uint32_t *landmarks,
     if (ix->bucket[x] >= kp) { free(is_landmark); return -1; }
   }
   free(is_landmark);
-  memset(ix->dl_in, 0, 8 * (size_t)(n ? n : 1));
-  memset(ix->dl_out, 0, 8 * (size_t)(n ? n : 1));
-  memset(ix->bl_in, 0, 8 * (size_t)(n ? n : 1));
-  memset(ix->bl_out, 0, 8 * (size_t)(n ? n : 1));
+  memset(ix->dl_in, 0, 8 * (size_t)(n ? n : 1) * ix->wd);
+  memset(ix->dl_out, 0, 8 * (size_t)(n ? n : 1) * ix->wd);
+  memset(ix->bl_in, 0, 8 * (size_t)(n ? n : 1) * ix->wb);
+  memset(ix->bl_out, 0, 8 * (size_t)(n ? n : 1) * ix->wb);
 
   /* task list: DL forward/backward per landmark, BL forward/backward per bucket */
   uint32_t ntasks = 2 * k + 2 * kp;
@@ -385,12 +408,14 @@ int orc_build(orc_index *ix, uint32_t k, uint32_t kp, const uint32_t *landmarks,
   }
   uint32_t t = 0;
   for (uint32_t i = 0; i < k; i++) {
-    tasks[t++] = (orc_task){1, ix->dl_in, i, &ix->landmark[i], 1};
-    tasks[t++] = (orc_task){0, ix->dl_out, i, &ix->landmark[i], 1};
+    tasks[t++] = (orc_task){1, ix->dl_in, ix->wd, i, &ix->landmark[i], 1};
+    tasks[t++] = (orc_task){0, ix->dl_out, ix->wd, i, &ix->landmark[i], 1};
   }
   for (uint32_t j = 0; j < kp; j++) {
-    tasks[t++] = (orc_task){1, ix->bl_in, j, src_in + cnt_in[j], cnt_in[j + 1] - cnt_in[j]};
-    tasks[t++] = (orc_task){0, ix->bl_out, j, src_out + cnt_out[j], cnt_out[j + 1] - cnt_out[j]};
+    tasks[t++] = (orc_task){1, ix->bl_in, ix->wb, j, src_in + cnt_in[j],
+                            cnt_in[j + 1] - cnt_in[j]};
+    tasks[t++] = (orc_task){0, ix->bl_out, ix->wb, j, src_out + cnt_out[j],
+                            cnt_out[j + 1] - cnt_out[j]};
   }
   orc_pool pool = {ix, tasks, ntasks, 0, threads > 1, 0};
   if (threads <= 1) {
@@ -413,12 +438,20 @@ int orc_build(orc_index *ix, uint32_t k, uint32_t kp, const uint32_t *landmarks,
 
 /* DL_Intersec(x, y) of Algorithm 2: DL_out(x) and DL_in(y) share a landmark. */
 static int dl_intersec(const orc_index *ix, uint32_t x, uint32_t y) {
-  return (ix->dl_out[x] & ix->dl_in[y]) != 0;
+  const uint64_t *a = ix->dl_out + (size_t)x * ix->wd, *b = ix->dl_in + (size_t)y * ix->wd;
+  for (uint32_t i = 0; i < ix->wd; i++)
+    if (a[i] & b[i]) return 1;
+  return 0;
 }
 
 /* BL_Contain(x, y) of Algorithm 2: BL_in(x) within BL_in(y) and BL_out(y) within BL_out(x). */
 static int bl_contain(const orc_index *ix, uint32_t x, uint32_t y) {
-  return (ix->bl_in[x] & ~ix->bl_in[y]) == 0 && (ix->bl_out[y] & ~ix->bl_out[x]) == 0;
+  const size_t wb = ix->wb;
+  for (uint32_t i = 0; i < wb; i++) {
+    if (ix->bl_in[x * wb + i] & ~ix->bl_in[y * wb + i]) return 0;
+    if (ix->bl_out[y * wb + i] & ~ix->bl_out[x * wb + i]) return 0;
+  }
+  return 1;
 }
 
 #define ORC_RULES_DL 1u
@@ -581,19 +614,29 @@ int orc_query_label_class(const orc_index *ix, uint64_t count, const uint32_t *u
  * update) to every vertex of Des(start) (forward) or Anc(start) (backward), pruning a vertex as
  * soon as it already contains `add`. Reading R2: start itself is checked and updated first.
  */
-static void alg3_propagate(const orc_index *ix, orc_bfs_ws *w, uint64_t *label, uint64_t add,
-                           uint32_t start, int forward) {
+static int misses(const uint64_t *add, const uint64_t *lab, uint32_t words) {
+  for (uint32_t i = 0; i < words; i++)
+    if (add[i] & ~lab[i]) return 1;
+  return 0;
+}
+
+static void absorb(const uint64_t *add, uint64_t *lab, uint32_t words) {
+  for (uint32_t i = 0; i < words; i++) lab[i] |= add[i];
+}
+
+static void alg3_propagate(const orc_index *ix, orc_bfs_ws *w, uint64_t *label, uint32_t words,
+                           const uint64_t *add, uint32_t start, int forward) {
   const orc_list *adj = forward ? ix->suc : ix->pre;
-  if ((add & ~label[start]) == 0) return;
-  label[start] |= add;
+  if (!misses(add, label + (size_t)start * words, words)) return;
+  absorb(add, label + (size_t)start * words, words);
   uint64_t head = 0, tail = 0;
   w->queue[tail++] = start;
   while (head < tail) {
     uint32_t p = w->queue[head++];
     for (uint32_t j = 0; j < adj[p].len; j++) {
       uint32_t x = adj[p].v[j];
-      if ((add & ~label[x]) != 0) {
-        label[x] |= add;
+      if (misses(add, label + (size_t)x * words, words)) {
+        absorb(add, label + (size_t)x * words, words);
         w->queue[tail++] = x; /* each vertex is enqueued at most once: it now contains `add` */
       }
     }
@@ -612,12 +655,15 @@ int orc_insert(orc_index *ix, uint64_t count, const uint32_t *src, const uint32_
     if (list_has(&ix->suc[u], v)) continue; /* duplicate: reachability unchanged */
     if (list_push(&ix->suc[u], v) || list_push(&ix->pre[v], u)) { ws_free(&w); return -1; }
     if (dl_intersec(ix, u, v)) continue;  /* reading R9: u already reaches v (Lemma 1) */
-    uint64_t dl_in_u = ix->dl_in[u], bl_in_u = ix->bl_in[u];
-    uint64_t dl_out_v = ix->dl_out[v], bl_out_v = ix->bl_out[v];
-    alg3_propagate(ix, &w, ix->dl_in, dl_in_u, v, 1);
-    alg3_propagate(ix, &w, ix->bl_in, bl_in_u, v, 1);
-    alg3_propagate(ix, &w, ix->dl_out, dl_out_v, u, 0);
-    alg3_propagate(ix, &w, ix->bl_out, bl_out_v, u, 0);
+    uint64_t dl_in_u[4], bl_in_u[4], dl_out_v[4], bl_out_v[4];
+    memcpy(dl_in_u, ix->dl_in + (size_t)u * ix->wd, 8 * ix->wd);
+    memcpy(bl_in_u, ix->bl_in + (size_t)u * ix->wb, 8 * ix->wb);
+    memcpy(dl_out_v, ix->dl_out + (size_t)v * ix->wd, 8 * ix->wd);
+    memcpy(bl_out_v, ix->bl_out + (size_t)v * ix->wb, 8 * ix->wb);
+    alg3_propagate(ix, &w, ix->dl_in, ix->wd, dl_in_u, v, 1);
+    alg3_propagate(ix, &w, ix->bl_in, ix->wb, bl_in_u, v, 1);
+    alg3_propagate(ix, &w, ix->dl_out, ix->wd, dl_out_v, u, 0);
+    alg3_propagate(ix, &w, ix->bl_out, ix->wb, bl_out_v, u, 0);
   }
   ws_free(&w);
   return 0;
@@ -641,9 +687,11 @@ uint32_t orc_add_vertices(orc_index *ix, uint32_t count) {
     *u8s[i] = p;
   }
   uint64_t **labs[4] = {&ix->dl_in, &ix->dl_out, &ix->bl_in, &ix->bl_out};
+  const uint32_t wds[4] = {ix->wd, ix->wd, ix->wb, ix->wb};
   for (int i = 0; i < 4; i++) {
-    uint64_t *p = (uint64_t *)realloc(*labs[i], 8 * (size_t)n1);
+    uint64_t *p = (uint64_t *)realloc(*labs[i], 8 * (size_t)n1 * wds[i]);
     if (!p) return ORC_NONE;
+    memset(p + (size_t)n0 * wds[i], 0, 8 * (size_t)count * wds[i]);
     *labs[i] = p;
   }
   for (uint32_t x = n0; x < n1; x++) {
@@ -651,7 +699,6 @@ uint32_t orc_add_vertices(orc_index *ix, uint32_t count) {
     memset(&ix->pre[x], 0, sizeof(orc_list));
     ix->in_leaf[x] = ix->out_leaf[x] = 0;
     ix->bucket[x] = (uint8_t)orc_hash(x, ix->kp ? ix->kp : 1);
-    ix->dl_in[x] = ix->dl_out[x] = ix->bl_in[x] = ix->bl_out[x] = 0;
   }
   ix->n = n1;
   return n0;
@@ -659,13 +706,19 @@ uint32_t orc_add_vertices(orc_index *ix, uint32_t count) {
 
 /* ---------------------------------------------------------------- accessors */
 
+void orc_label_words(const orc_index *ix, uint32_t *wd, uint32_t *wb) {
+  *wd = ix->wd;
+  *wb = ix->wb;
+}
+
+/* Copy the labels out: DL arrays hold n * wd words, BL arrays n * wb (vertex-major). */
 void orc_read_labels(const orc_index *ix, uint64_t *dl_in, uint64_t *dl_out, uint64_t *bl_in,
                      uint64_t *bl_out) {
-  size_t b = 8 * (size_t)ix->n;
-  memcpy(dl_in, ix->dl_in, b);
-  memcpy(dl_out, ix->dl_out, b);
-  memcpy(bl_in, ix->bl_in, b);
-  memcpy(bl_out, ix->bl_out, b);
+  const size_t bd = 8 * (size_t)ix->n * ix->wd, bb = 8 * (size_t)ix->n * ix->wb;
+  memcpy(dl_in, ix->dl_in, bd);
+  memcpy(dl_out, ix->dl_out, bd);
+  memcpy(bl_in, ix->bl_in, bb);
+  memcpy(bl_out, ix->bl_out, bb);
 }
 
 uint32_t orc_landmarks(const orc_index *ix, uint32_t *out) {

@@ -71,7 +71,11 @@ def expected_labels(R, landmarks, s_in, s_out, bucket):
 
 
 def as_sets(words):
-    return [{b for b in range(64) if (int(w) >> b) & 1} for w in words]
+    """Bit sets of a label array: uint64[n] or uint64[n, W] (bit i in word i // 64)."""
+    if words.ndim == 1:
+        return [{b for b in range(64) if (int(w) >> b) & 1} for w in words]
+    return [{64 * j + b for j in range(words.shape[1]) for b in range(64)
+             if (int(row[j]) >> b) & 1} for row in words]
 
 
 def expected_query(R, lab, u, v, dl=True, bl=True):
@@ -241,8 +245,36 @@ def test_rule_ablations_vs_definitions(name, g, rules):
     assert np.array_equal(got & 1, R[u, v].astype(np.uint8))
 
 
+@pytest.mark.parametrize("name,g", [f for f in FAMILIES if f[0] in
+                                    ("er_mid", "sccs", "rmat7", "rmat8", "star_out", "chain")],
+                         ids=lambda x: x if isinstance(x, str) else "")
+@pytest.mark.parametrize("k,kp", [(128, 64), (64, 256), (256, 128), (100, 128)])
+def test_multiword_labels_vs_definitions(name, g, k, kp):
+    """Labels longer than 64 bits (Table 5's sizes): labels, insertion and answers against the
+    definitions."""
+    n, src, dst = g
+    bucket = random_bucket(n, kp, n + k)
+    ix = oracle.OracleIndex(n, src, dst).build(k=k, kp=kp, bucket_table=bucket)
+    lm = expected_landmarks(n, src, dst, k)
+    assert list(ix.landmarks()) == lm
+    s_in, s_out = expected_leaves(n, src, dst, lm)
+    rng = np.random.default_rng(n)
+    iu = rng.integers(0, n, 20).astype(np.uint32)
+    iv = rng.integers(0, n, 20).astype(np.uint32)
+    ix.insert(iu, iv)
+    src = np.concatenate([src, iu]).astype(np.uint32)
+    dst = np.concatenate([dst, iv]).astype(np.uint32)
+    R = reach_matrix(n, src, dst)
+    exp = expected_labels(R, lm, s_in, s_out, bucket)
+    assert [as_sets(w_) for w_ in ix.labels()] == list(exp)
+    u = np.repeat(np.arange(n), n).astype(np.uint32)
+    v = np.tile(np.arange(n), n).astype(np.uint32)
+    want = np.array([expected_query(R, exp, int(a), int(b)) for a, b in zip(u, v)], np.uint8)
+    assert np.array_equal(ix.query_dbl(u, v), want)
+
+
 def test_fibonacci_hash_range_and_spread():
-    for kp in (1, 2, 4, 64):
+    for kp in (1, 2, 4, 64, 256):
         hs = [oracle.fib_hash(x, kp) for x in range(4096)]
         assert min(hs) >= 0 and max(hs) < kp
         if kp > 1:
@@ -253,6 +285,7 @@ def test_fibonacci_hash_range_and_spread():
         frac = (x * 0x9E3779B97F4A7C15) % (1 << 64)
         assert oracle.fib_hash(x, 64) == frac >> 58
         assert oracle.fib_hash(x, 2) == frac >> 63
+        assert oracle.fib_hash(x, 256) == frac >> 56
 
 
 @pytest.mark.parametrize("seed", range(6))
