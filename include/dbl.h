@@ -2,12 +2,14 @@
  * dbl.h — C ABI of the DBL reachability index on one MI355X (gfx950).
  *
  * DBL (Lyu, Li, He, Gong, arXiv 2101.09441) answers reachability queries q(u,v) on a directed
- * graph that only grows by edge insertion. Every vertex carries four 64-bit labels:
+ * graph that only grows by edge insertion. Every vertex carries four bitset labels:
  *   DL_in(v)  - the landmarks that reach v           (Definition 1)
  *   DL_out(v) - the landmarks v reaches              (Definition 1)
  *   BL_in(v)  - hashed zero-in-degree leaves reaching v   (Definition 2, hashed into k' bits)
  *   BL_out(v) - hashed zero-out-degree leaves v reaches   (Definition 2, hashed into k' bits)
  * Reachability includes the vertex itself (Table 1: Des(u) and Anc(u) contain u).
+ * A label takes W 64-bit words, W = 1, 2 or 4, the smallest that holds max(k, k') bits
+ * (dbl_label_words); bit i of a label is bit i % 64 of its word i / 64.
  *
  * Conventions for every entry point:
  *   - Array arguments named d_* are DEVICE pointers (for example the data pointer of a torch
@@ -53,11 +55,11 @@ typedef enum {
 } dbl_class;
 
 typedef struct {
-  /* k: number of landmarks, 0..64 (default 64). Landmarks are the top-k vertices by
+  /* k: number of landmarks, 0..256 (default 64). Landmarks are the top-k vertices by
      M(u) = |Pre(u)| * |Suc(u)| (Section 3.1), ties broken by smaller id; DL bit i stands for
      the i-th landmark. Bits >= k stay zero. */
   uint32_t num_landmarks;
-  /* k': number of BL hash buckets, a power of two in 1..64 (default 64). */
+  /* k': number of BL hash buckets, a power of two in 1..256 (default 64). */
   uint32_t bl_bits;
   /* Optional HOST array [num_landmarks]: explicit ordered landmark list (distinct ids < n). */
   const uint32_t *landmarks;
@@ -191,11 +193,13 @@ dbl_status dbl_query_batch_rules(dbl_index *ix, dbl_query_ctx *ctx, uint64_t cou
                                  const uint32_t *d_u, const uint32_t *d_v, uint8_t *d_out,
                                  uint32_t rules, void *stream);
 
-/* Copy the labels out: each argument is a device array [n] of uint64 (any may be NULL). */
+/* Copy the labels out: each argument is a device array [n * W] of uint64, W =
+   dbl_label_words(ix), vertex x's label in words [x * W, x * W + W) (any may be NULL). */
 dbl_status dbl_read_labels(const dbl_index *ix, uint64_t *d_dl_in, uint64_t *d_dl_out,
                            uint64_t *d_bl_in, uint64_t *d_bl_out, void *stream);
 
-/* Copy the ordered landmark list to HOST array h_out [64]; *k receives the landmark count. */
+/* Copy the ordered landmark list to HOST array h_out (room for num_landmarks entries, at most
+   256); *k receives the landmark count. */
 dbl_status dbl_get_landmarks(const dbl_index *ix, uint32_t *h_out, uint32_t *k);
 
 /* Copy the leaf sets fixed at build time to HOST array h_flags [n] (bit 0 S_in, bit 1 S_out)
@@ -242,6 +246,10 @@ dbl_status dbl_set_tuning(dbl_index *ix, const dbl_tuning *t);
 
 /* Vertex count of the index. */
 uint32_t dbl_num_vertices(const dbl_index *ix);
+
+/* Words per label W (1, 2 or 4; 0 for NULL): the smallest W with 64 W >= max(k, k') as
+   requested in dbl_options. */
+uint32_t dbl_label_words(const dbl_index *ix);
 
 /* Release every device buffer of the index (NULL is ignored). */
 void dbl_destroy(dbl_index *ix);

@@ -26,7 +26,7 @@ EXPORTS = [
     "dbl_query_ctx_destroy", "dbl_query_batch_rules",
     "dbl_read_labels", "dbl_get_landmarks", "dbl_get_leaves", "dbl_get_stats",
     "dbl_time_kernels", "dbl_read_kernel_times", "dbl_get_tuning", "dbl_set_tuning",
-    "dbl_num_vertices", "dbl_destroy",
+    "dbl_num_vertices", "dbl_label_words", "dbl_destroy",
     "dbl_status_str",
 ]
 
@@ -145,6 +145,8 @@ def load_library():
     lib.dbl_set_tuning.restype = i32
     lib.dbl_num_vertices.argtypes = [P]
     lib.dbl_num_vertices.restype = u32
+    lib.dbl_label_words.argtypes = [P]
+    lib.dbl_label_words.restype = u32
     lib.dbl_destroy.argtypes = [P]
     lib.dbl_destroy.restype = None
     lib.dbl_status_str.argtypes = [i32]
@@ -370,9 +372,16 @@ class Index:
     def query_context_bytes(self, bfs_slots: int = 0, queue_cap: int = 0, batch: int = 0) -> int:
         return int(load_library().dbl_query_ctx_bytes(self._handle(), bfs_slots, queue_cap, batch))
 
+    def label_words(self) -> int:
+        """64-bit words per label: 1, 2 or 4 (labels of up to 64, 128, 256 bits)."""
+        return int(load_library().dbl_label_words(self._handle()))
+
     def labels(self, stream=None):
-        """(DL_in, DL_out, BL_in, BL_out) as int64 device tensors holding the 64-bit patterns."""
-        outs = [torch.empty(self.n, dtype=torch.int64, device=self.device) for _ in range(4)]
+        """(DL_in, DL_out, BL_in, BL_out) as int64 device tensors holding the bit patterns:
+        shape (n,) for 64-bit labels, else (n, W) with bit i in word i // 64."""
+        w = self.label_words()
+        shape = (self.n,) if w == 1 else (self.n, w)
+        outs = [torch.empty(shape, dtype=torch.int64, device=self.device) for _ in range(4)]
         with torch.cuda.device(self.device):
             st = load_library().dbl_read_labels(self._handle(), *[o.data_ptr() for o in outs],
                                                 _stream_ptr(stream))
@@ -383,7 +392,7 @@ class Index:
         return tuple(t.cpu().numpy().view(np.uint64) for t in self.labels())
 
     def landmarks(self) -> np.ndarray:
-        buf = np.zeros(64, dtype=np.uint32)
+        buf = np.zeros(256, dtype=np.uint32)
         k = ctypes.c_uint32()
         _check(load_library().dbl_get_landmarks(self._handle(), buf.ctypes.data, ctypes.byref(k)),
                "dbl_get_landmarks")

@@ -45,6 +45,7 @@ struct dbl_query_ctx {
 struct dbl_index {
   int device = 0;
   uint32_t n = 0, k = 0, kp = 0, kp_bits = 0;
+  uint32_t lw = 1;  // 64-bit words per label (1, 2 or 4)
   uint32_t n_cap = 0;  // vertices the per-vertex arrays have room for
   float slack_frac = 0.25f;
   uint32_t slack_min = 4;
@@ -63,7 +64,7 @@ struct dbl_index {
   Ovf *ovf = nullptr;
   uint64_t ovf_cap = 0;
   uint32_t *landmarks_d = nullptr;
-  uint32_t landmarks_h[64] = {};
+  uint32_t landmarks_h[dbl::kMaxLabelBits] = {};
   uint8_t *leaf_flags = nullptr, *bucket = nullptr;
   u64 *scan_tmp = nullptr, *scan_total = nullptr;
   uint64_t scan_tmp_words = 0;
@@ -211,7 +212,7 @@ struct DeviceGuard {
 
 dbl::PropArgs prop_args(const dbl_index *ix) {
   dbl::PropArgs a;
-  a.L.lab = ix->lab;
+  a.L = {ix->lab, ix->lw};
   a.f = ix->f;
   a.r = ix->r;
   for (int i = 0; i < 3; i++) a.fq[i] = ix->fq[i];
@@ -537,11 +538,11 @@ dbl_status run_queries(dbl_index *ix, dbl_query_ctx *c, uint64_t count, const ui
   CKS(ctx_reserve(c, count));
   {
     Timed tm(ix, c->is_default ? (uint32_t)kTQueryLabel : (uint32_t)kTKinds, s);
-    CK(dbl::launch_query_label({ix->lab}, d_u, d_v, count, ix->n, ix->f.deg, d_out, c->und,
+    CK(dbl::launch_query_label({ix->lab, ix->lw}, d_u, d_v, count, ix->n, ix->f.deg, d_out, c->und,
                                c->seg, c->ctl, c->qcls, rules, s));
   }
   dbl::BfsArgs b;
-  b.L.lab = ix->lab;
+  b.L = {ix->lab, ix->lw};
   b.f = ix->f;
   b.u = d_u;
   b.v = d_v;
@@ -674,7 +675,7 @@ dbl_status do_build(dbl_index *ix, uint64_t m, const uint32_t *src, const uint32
   dfree(keep);
 
   // ---- a2: landmarks (top-k by |Pre|*|Suc|), leaves and their hash buckets
-  CKS(dalloc(&ix->landmarks_d, 64));
+  CKS(dalloc(&ix->landmarks_d, dbl::kMaxLabelBits));
   if (ix->k) {
     if (o.landmarks) {
       CK(hipMemcpyAsync(ix->landmarks_d, o.landmarks, sizeof(uint32_t) * ix->k,
@@ -694,8 +695,8 @@ dbl_status do_build(dbl_index *ix, uint64_t m, const uint32_t *src, const uint32
     CK(hipMemcpyAsync(ix->landmarks_h, ix->landmarks_d, sizeof(uint32_t) * ix->k,
                       hipMemcpyDeviceToHost, s));
   }
-  CKS(dalloc(&ix->lab, 4ull * n));
-  CK(dbl::launch_fill_u64(ix->lab, 0ull, 4ull * n, s));
+  CKS(dalloc(&ix->lab, 4ull * ix->lw * n));
+  CK(dbl::launch_fill_u64(ix->lab, 0ull, 4ull * ix->lw * n, s));
   uint8_t *is_lm = nullptr, *flags_in = nullptr, *bucket_in = nullptr;
   CKS(dalloc(&is_lm, n));
   CK(hipMemsetAsync(is_lm, 0, n, s));
@@ -709,7 +710,7 @@ dbl_status do_build(dbl_index *ix, uint64_t m, const uint32_t *src, const uint32
   }
   CKS(dalloc(&ix->leaf_flags, n));
   CKS(dalloc(&ix->bucket, n));
-  CK(dbl::launch_seed({ix->lab}, n, ix->landmarks_d, ix->k, indeg, outdeg, flags_in, bucket_in,
+  CK(dbl::launch_seed({ix->lab, ix->lw}, n, ix->landmarks_d, ix->k, indeg, outdeg, flags_in, bucket_in,
                       ix->kp_bits, o.leaf_threshold, ix->leaf_flags, ix->bucket, is_lm, s));
   CK(hipStreamSynchronize(s));
   dfree(is_lm);
@@ -723,7 +724,7 @@ dbl_status do_build(dbl_index *ix, uint64_t m, const uint32_t *src, const uint32
   CKS(dalloc(&ix->inq, 2ull * n));
   CK(dbl::launch_fill_u32(ix->inq, 0u, 2ull * n, s));
   CKS(ensure_heavy_cap(ix));
-  CK(dbl::launch_init_frontier({ix->lab}, n, ix->f, ix->r, ix->fq[0], ix->ctl, ix->inq, 1u, s));
+  CK(dbl::launch_init_frontier({ix->lab, ix->lw}, n, ix->f, ix->r, ix->fq[0], ix->ctl, ix->inq, 1u, s));
   uint64_t rounds = 0;
   CKS(grid_propagate(ix, s, 4, &rounds, false));
   ix->build_rounds = rounds;
@@ -784,8 +785,9 @@ dbl_status dbl_build(uint32_t n, uint64_t m, const uint32_t *d_src, const uint32
   if (m && (!d_src || !d_dst)) return DBL_ERR_INVALID_ARG;
   dbl_options o;
   if (opt) o = *opt; else dbl_default_options(&o);
-  if (o.num_landmarks > 64) return DBL_ERR_INVALID_ARG;
-  if (o.bl_bits == 0 || o.bl_bits > 64 || (o.bl_bits & (o.bl_bits - 1))) return DBL_ERR_INVALID_ARG;
+  if (o.num_landmarks > dbl::kMaxLabelBits) return DBL_ERR_INVALID_ARG;
+  if (o.bl_bits == 0 || o.bl_bits > dbl::kMaxLabelBits || (o.bl_bits & (o.bl_bits - 1)))
+    return DBL_ERR_INVALID_ARG;
   if (!(o.slack_fraction >= 0.0f) || o.slack_fraction > 16.0f) return DBL_ERR_INVALID_ARG;
   if (o.landmark_rank > 3) return DBL_ERR_INVALID_ARG;
   const uint32_t k = std::min<uint32_t>(o.num_landmarks, n);
@@ -810,6 +812,10 @@ dbl_status dbl_build(uint32_t n, uint64_t m, const uint32_t *d_src, const uint32
   ix->k = k;
   ix->kp = o.bl_bits;
   ix->kp_bits = bits_of(o.bl_bits);
+  {
+    const uint32_t bits = std::max<uint32_t>(o.num_landmarks, o.bl_bits);
+    ix->lw = bits <= 64 ? 1 : bits <= 128 ? 2 : 4;
+  }
   ix->slack_frac = o.slack_fraction;
   ix->slack_min = o.slack_min;
   ix->slots_opt = o.bfs_slots;
@@ -975,7 +981,7 @@ dbl_status dbl_read_labels(const dbl_index *ix, uint64_t *d_dl_in, uint64_t *d_d
   if (!ix) return DBL_ERR_INVALID_ARG;
   DeviceGuard dg(ix->device);
   hipStream_t s = (hipStream_t)stream;
-  CK(dbl::launch_unpack_labels({ix->lab}, ix->n, (u64 *)d_dl_in, (u64 *)d_dl_out, (u64 *)d_bl_in,
+  CK(dbl::launch_unpack_labels({ix->lab, ix->lw}, ix->n, (u64 *)d_dl_in, (u64 *)d_dl_out, (u64 *)d_bl_in,
                                (u64 *)d_bl_out, s));
   CK(hipStreamSynchronize(s));
   return DBL_OK;
@@ -1115,7 +1121,7 @@ dbl_status dbl_add_vertices(dbl_index *ix, uint32_t count, uint32_t *first, void
       CKS(grow(g->deg, n0, cap, s));
       CKS(grow(g->cap, n0, cap, s));
     }
-    CKS(grow(ix->lab, 4 * n0, 4 * cap, s));
+    CKS(grow(ix->lab, 4ull * ix->lw * n0, 4ull * ix->lw * cap, s));
     for (int i = 0; i < 3; i++) CKS(grow(ix->fq[i], 0, 2 * cap, s));
     CKS(grow(ix->inq, 2 * n0, 2 * cap, s));
     CKS(grow(ix->leaf_flags, n0, cap, s));
@@ -1132,7 +1138,7 @@ dbl_status dbl_add_vertices(dbl_index *ix, uint32_t count, uint32_t *first, void
     CK(dbl::launch_fill_u32(g->cap + n0, 0u, count, s));
     CK(dbl::launch_fill_u64(g->off + n0, 0ull, count, s));
   }
-  CK(dbl::launch_fill_u64(ix->lab + 4 * n0, 0ull, 4ull * count, s));
+  CK(dbl::launch_fill_u64(ix->lab + 4ull * ix->lw * n0, 0ull, 4ull * ix->lw * count, s));
   CK(dbl::launch_fill_u32(ix->inq + 2 * n0, 0u, 2ull * count, s));
   CK(hipMemsetAsync(ix->leaf_flags + n0, 0, count, s));
   CK(dbl::launch_init_buckets(ix->bucket, (uint32_t)n0, (uint32_t)n1, ix->kp_bits, s));
@@ -1188,6 +1194,8 @@ dbl_status dbl_set_tuning(dbl_index *ix, const dbl_tuning *t) {
 }
 
 uint32_t dbl_num_vertices(const dbl_index *ix) { return ix ? ix->n : 0; }
+
+uint32_t dbl_label_words(const dbl_index *ix) { return ix ? ix->lw : 0; }
 
 void dbl_destroy(dbl_index *ix) {
   if (!ix) return;

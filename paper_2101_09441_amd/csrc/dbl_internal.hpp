@@ -99,8 +99,14 @@ struct Ovf {
   uint32_t x, pos, y, pad;
 };
 
+// Labels of k (DL) and k' (BL) bits take W = words 64-bit words each, W in {1, 2, 4} (the
+// smallest power of two with 64 W >= max(k, k')); bit i of a label sits in word i / 64, bit
+// i % 64. Vertex x owns the record lab[4 W x .. 4 W x + 4 W) = {DL_in, BL_in, DL_out, BL_out},
+// so each propagation direction reads and ORs one contiguous half {DL, BL} of 2 W words.
+constexpr uint32_t kMaxLabelBits = 256;
 struct LabelsView {
-  unsigned long long *lab;  // [4n]: per vertex {DL_in, BL_in, DL_out, BL_out}
+  unsigned long long *lab;
+  uint32_t words;
 };
 
 // ---------------------------------------------------------------- launch wrappers

@@ -85,16 +85,79 @@ __device__ __forceinline__ void st_agent32(uint32_t *p, uint32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// OR (a, b) into the two label words at w. Returns true if the call added a bit. The plain
-// pre-read only avoids atomics on targets that already hold the bits; a stale pre-read costs
-// an extra atomic, never a missed change, because the decision uses the atomic's old value.
-__device__ __forceinline__ bool relax(u64 *__restrict__ w, u64 a, u64 b) {
-  const ulonglong2 cur = *reinterpret_cast<const ulonglong2 *>(w);
+// One direction half of a vertex's label record: W words of DL, then W words of BL.
+template <int W>
+struct alignas(16) Half {
+  u64 w[2 * W];
+};
+
+template <int W>
+__device__ __forceinline__ const u64 *half_ptr(const u64 *lab, uint32_t x, uint32_t dir) {
+  return lab + 4ull * W * x + 2u * W * dir;
+}
+template <int W>
+__device__ __forceinline__ u64 *half_ptr(u64 *lab, uint32_t x, uint32_t dir) {
+  return lab + 4ull * W * x + 2u * W * dir;
+}
+
+template <int W>
+__device__ __forceinline__ Half<W> ld_half(const u64 *p) {
+  Half<W> h;
+#pragma unroll
+  for (int i = 0; i < W; i++) {
+    const ulonglong2 t = reinterpret_cast<const ulonglong2 *>(p)[i];
+    h.w[2 * i] = t.x;
+    h.w[2 * i + 1] = t.y;
+  }
+  return h;
+}
+
+// Device-coherent read of a half (past the L1 cache), for labels other waves of the same kernel
+// may have grown.
+template <int W>
+__device__ __forceinline__ Half<W> ld_half_agent(const u64 *p) {
+  Half<W> h;
+#pragma unroll
+  for (int i = 0; i < 2 * W; i++) h.w[i] = ld_agent(p + i);
+  return h;
+}
+
+template <int W>
+__device__ __forceinline__ bool any_bits(const Half<W> &h) {
+  u64 a = 0;
+#pragma unroll
+  for (int i = 0; i < 2 * W; i++) a |= h.w[i];
+  return a != 0ull;
+}
+
+// OR the half `a` into the half at w, given `cur`, an earlier plain read of w. Returns true if
+// the call added a bit. The pre-read only avoids atomics on words that already hold the bits; a
+// stale pre-read costs an extra atomic, never a missed change, because the decision uses the
+// atomic's old value.
+template <int W>
+__device__ __forceinline__ bool or_half(u64 *__restrict__ w, const Half<W> &a, const Half<W> &cur) {
   bool changed = false;
-  if (a & ~cur.x) changed |= (a & ~atomicOr(w, a)) != 0ull;
-  if (b & ~cur.y) changed |= (b & ~atomicOr(w + 1, b)) != 0ull;
+#pragma unroll
+  for (int i = 0; i < 2 * W; i++)
+    if (a.w[i] & ~cur.w[i]) changed |= (a.w[i] & ~atomicOr(w + i, a.w[i])) != 0ull;
   return changed;
 }
+
+template <int W>
+__device__ __forceinline__ bool relax(u64 *__restrict__ w, const Half<W> &a) {
+  return or_half<W>(w, a, ld_half<W>(w));
+}
+
+// Launch kernel template `kern` instantiated for the label width `words` (1, 2 or 4).
+#define DBL_LAUNCH_W(words, kern, grid, block, stream, ...)                                    \
+  do {                                                                                         \
+    switch (words) {                                                                           \
+      case 1: hipLaunchKernelGGL(kern<1>, grid, block, 0, stream, __VA_ARGS__); break;         \
+      case 2: hipLaunchKernelGGL(kern<2>, grid, block, 0, stream, __VA_ARGS__); break;         \
+      case 4: hipLaunchKernelGGL(kern<4>, grid, block, 0, stream, __VA_ARGS__); break;         \
+      default: return hipErrorInvalidValue;                                                    \
+    }                                                                                          \
+  } while (0)
 
 // Claim the right to queue (vertex, direction) in the frontier stamped `stamp`. Stamps only
 // grow, so a stale read can never equal `stamp` by accident.
@@ -374,18 +437,18 @@ hipError_t launch_scatter(const uint32_t *src, const uint32_t *dst, const uint8_
 
 // ---------------------------------------------------------------- landmark selection
 // Tiles of 2048 candidates are bitonic-sorted in LDS by (M descending, id ascending); the best
-// 64 of each tile survive to the next pass until one tile remains.
-constexpr uint32_t kTkTile = 2048, kTkNT = 256, kTkKeep = 64;
+// `keep` (64, or 256 when k > 64) of each tile survive to the next pass until one tile remains.
+constexpr uint32_t kTkTile = 2048, kTkNT = 256, kTkKeepMax = kMaxLabelBits;
 
 uint64_t topk_tmp_entries(uint32_t n) {
   const uint64_t tiles = ((uint64_t)n + kTkTile - 1) / kTkTile;
-  return 2 * (tiles * kTkKeep + kTkKeep);
+  return 2 * (tiles * kTkKeepMax + kTkKeepMax);
 }
 
 __global__ __launch_bounds__(kTkNT) void k_topk(const uint32_t *indeg, const uint32_t *outdeg,
                                                 const u64 *in_m, const uint32_t *in_id,
-                                                uint64_t count, uint32_t rank, u64 *out_m,
-                                                uint32_t *out_id) {
+                                                uint64_t count, uint32_t rank, uint32_t keep,
+                                                u64 *out_m, uint32_t *out_id) {
   __shared__ u64 sm[kTkTile];
   __shared__ uint32_t sid[kTkTile];
   const uint64_t base = (uint64_t)blockIdx.x * kTkTile;
@@ -424,9 +487,9 @@ __global__ __launch_bounds__(kTkNT) void k_topk(const uint32_t *indeg, const uin
     }
   }
   __syncthreads();
-  for (uint32_t j = threadIdx.x; j < kTkKeep; j += kTkNT) {
-    out_m[(uint64_t)blockIdx.x * kTkKeep + j] = sm[j];
-    out_id[(uint64_t)blockIdx.x * kTkKeep + j] = sid[j];
+  for (uint32_t j = threadIdx.x; j < keep; j += kTkNT) {
+    out_m[(uint64_t)blockIdx.x * keep + j] = sm[j];
+    out_id[(uint64_t)blockIdx.x * keep + j] = sid[j];
   }
 }
 
@@ -434,6 +497,8 @@ hipError_t select_topk(const uint32_t *indeg, const uint32_t *outdeg, uint32_t n
                        uint32_t rank, u64 *tmp_m, uint32_t *tmp_id, uint32_t *out,
                        hipStream_t s) {
   if (k == 0) return hipSuccess;
+  if (k > kTkKeepMax) return hipErrorInvalidValue;
+  const uint32_t keep = k <= 64u ? 64u : kTkKeepMax;
   const uint64_t half = topk_tmp_entries(n) / 2;
   uint64_t count = n;
   const u64 *in_m = nullptr;
@@ -444,33 +509,37 @@ hipError_t select_topk(const uint32_t *indeg, const uint32_t *outdeg, uint32_t n
     u64 *om = tmp_m + side * half;
     uint32_t *oi = tmp_id + side * half;
     hipLaunchKernelGGL(k_topk, dim3((uint32_t)tiles), dim3(kTkNT), 0, s, indeg, outdeg, in_m,
-                       in_id, count, rank, om, oi);
+                       in_id, count, rank, keep, om, oi);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (tiles == 1) return hipMemcpyAsync(out, oi, sizeof(uint32_t) * k, hipMemcpyDeviceToDevice, s);
     in_m = om;
     in_id = oi;
-    count = tiles * kTkKeep;
+    count = tiles * keep;
     side ^= 1;
   }
 }
 
 // ---------------------------------------------------------------- seeds
 
-__global__ void k_mark_landmarks(u64 *lab, const uint32_t *landmarks, uint32_t k,
+// Landmark i sets bit i of its own DL_in and DL_out (a landmark reaches itself).
+__global__ void k_mark_landmarks(u64 *lab, uint32_t words, const uint32_t *landmarks, uint32_t k,
                                  uint8_t *is_landmark) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= k) return;
   const uint32_t x = landmarks[i];
   is_landmark[x] = 1;
-  atomicOr(&lab[4ull * x + 0], 1ull << i);  // DL_in: the landmark reaches itself
-  atomicOr(&lab[4ull * x + 2], 1ull << i);  // DL_out
+  u64 *rec = lab + 4ull * words * x;
+  atomicOr(&rec[i >> 6], 1ull << (i & 63u));              // DL_in
+  atomicOr(&rec[2u * words + (i >> 6)], 1ull << (i & 63u));  // DL_out
 }
 
-__global__ void k_seed_leaves(u64 *lab, uint32_t n, const uint32_t *indeg, const uint32_t *outdeg,
-                              const uint8_t *is_landmark, const uint8_t *flags_in,
-                              const uint8_t *bucket_in, uint32_t kp_bits, u64 leaf_threshold,
-                              uint8_t *flags_out, uint8_t *bucket_out) {
+// A leaf of S_in (S_out) sets bit h(x) of its own BL_in (BL_out). One thread per vertex, so the
+// plain read-modify-write is race-free.
+__global__ void k_seed_leaves(u64 *lab, uint32_t words, uint32_t n, const uint32_t *indeg,
+                              const uint32_t *outdeg, const uint8_t *is_landmark,
+                              const uint8_t *flags_in, const uint8_t *bucket_in, uint32_t kp_bits,
+                              u64 leaf_threshold, uint8_t *flags_out, uint8_t *bucket_out) {
   for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < n; x += gridDim.x * blockDim.x) {
     uint32_t fl;
     if (flags_in) {
@@ -483,8 +552,9 @@ __global__ void k_seed_leaves(u64 *lab, uint32_t n, const uint32_t *indeg, const
       fl = (uint32_t)(!lm && indeg[x] == 0) | ((uint32_t)(!lm && outdeg[x] == 0) << 1);
     }
     const uint32_t b = bucket_in ? bucket_in[x] : fib_bucket(x, kp_bits);
-    if (fl & 1u) lab[4ull * x + 1] |= 1ull << b;  // BL_in: the leaf reaches itself
-    if (fl & 2u) lab[4ull * x + 3] |= 1ull << b;  // BL_out
+    u64 *rec = lab + 4ull * words * x;
+    if (fl & 1u) rec[words + (b >> 6)] |= 1ull << (b & 63u);       // BL_in
+    if (fl & 2u) rec[3u * words + (b >> 6)] |= 1ull << (b & 63u);  // BL_out
     flags_out[x] = (uint8_t)fl;
     bucket_out[x] = (uint8_t)b;
   }
@@ -495,16 +565,19 @@ hipError_t launch_seed(LabelsView L, uint32_t n, const uint32_t *landmarks, uint
                        const uint8_t *leaf_flags_in, const uint8_t *bucket_in, uint32_t kp_bits,
                        u64 leaf_threshold, uint8_t *leaf_flags_out, uint8_t *bucket_out,
                        uint8_t *is_landmark, hipStream_t s) {
+  if (k > kMaxLabelBits || k > 64u * L.words || (1u << kp_bits) > 64u * L.words)
+    return hipErrorInvalidValue;
   if (k) {
-    hipLaunchKernelGGL(k_mark_landmarks, dim3(1), dim3(64), 0, s, L.lab, landmarks, k,
-                       is_landmark);
+    hipLaunchKernelGGL(k_mark_landmarks, dim3(1), dim3(kMaxLabelBits), 0, s, L.lab, L.words,
+                       landmarks, k, is_landmark);
   }
-  hipLaunchKernelGGL(k_seed_leaves, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, L.lab, n,
-                     indeg, outdeg, is_landmark, leaf_flags_in, bucket_in, kp_bits,
+  hipLaunchKernelGGL(k_seed_leaves, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, L.lab,
+                     L.words, n, indeg, outdeg, is_landmark, leaf_flags_in, bucket_in, kp_bits,
                      leaf_threshold, leaf_flags_out, bucket_out);
   return hipGetLastError();
 }
 
+template <int W>
 __global__ void k_init_frontier(const u64 *lab, uint32_t n, Csr f, Csr r, uint32_t *frontier,
                                 Ctl *ctl, uint32_t ring, uint32_t *inq, uint32_t stamp) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -515,10 +588,8 @@ __global__ void k_init_frontier(const u64 *lab, uint32_t n, Csr f, Csr r, uint32
     const uint32_t x = x0 + threadIdx.x;
     bool pf = false, pb = false;
     if (x < n) {
-      const ulonglong2 a = *reinterpret_cast<const ulonglong2 *>(lab + 4ull * x);
-      const ulonglong2 b = *reinterpret_cast<const ulonglong2 *>(lab + 4ull * x + 2);
-      pf = ((a.x | a.y) != 0ull) && min(f.deg[x], f.cap[x]) > 0u;
-      pb = ((b.x | b.y) != 0ull) && min(r.deg[x], r.cap[x]) > 0u;
+      pf = any_bits<W>(ld_half<W>(half_ptr<W>(lab, x, 0))) && min(f.deg[x], f.cap[x]) > 0u;
+      pb = any_bits<W>(ld_half<W>(half_ptr<W>(lab, x, 1))) && min(r.deg[x], r.cap[x]) > 0u;
       if (pf) inq[2ull * x] = stamp;
       if (pb) inq[2ull * x + 1] = stamp;
     }
@@ -530,8 +601,8 @@ __global__ void k_init_frontier(const u64 *lab, uint32_t n, Csr f, Csr r, uint32
 hipError_t launch_init_frontier(LabelsView L, uint32_t n, Csr f, Csr r, uint32_t *frontier,
                                 Ctl *ctl, uint32_t *inq, uint32_t stamp, hipStream_t s) {
   // the pending frontier is ring 0 at build time
-  hipLaunchKernelGGL(k_init_frontier, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, L.lab, n,
-                     f, r, frontier, ctl, 0u, inq, stamp);
+  DBL_LAUNCH_W(L.words, k_init_frontier, dim3(grid_for(n, 256, 8192)), dim3(256), s, L.lab, n, f,
+               r, frontier, ctl, 0u, inq, stamp);
   return hipGetLastError();
 }
 
@@ -542,12 +613,12 @@ hipError_t launch_init_frontier(LabelsView L, uint32_t n, Csr f, Csr r, uint32_t
 // list, rows longer than kHeavyDeg are split into chunks for k_heavy instead.
 // `coherent` reads the frontier vertices' labels past the L1 cache (needed when earlier rounds
 // of the same kernel changed them).
-template <int NT>
+template <int NT, int W>
 __device__ __forceinline__ void expand_tile(const PropArgs &a, const uint32_t *fq, uint32_t beg,
                                             uint32_t end, uint32_t *nq, uint32_t *ncnt,
                                             uint32_t nstamp, u64 *heavy_list,
                                             uint32_t *heavy_cnt, bool coherent,
-                                            uint32_t *s_start, u64 *s_off, ulonglong2 *s_lab,
+                                            uint32_t *s_start, u64 *s_off, Half<W> *s_lab,
                                             uint32_t *s_ent, uint32_t *s_wsum, u64 &relaxed) {
   const uint32_t t = threadIdx.x;
   const uint32_t i = beg + t;
@@ -559,14 +630,8 @@ __device__ __forceinline__ void expand_tile(const PropArgs &a, const uint32_t *f
     const uint32_t* degp = dir ? a.r.deg : a.f.deg;
     const uint32_t* capp = dir ? a.r.cap : a.f.cap;
     uint32_t dg = min(degp[x], capp[x]);
-    const u64 *lp = a.L.lab + 4ull * x + 2u * dir;
-    ulonglong2 lv;
-    if (coherent) {
-      lv.x = ld_agent(lp);
-      lv.y = ld_agent(lp + 1);
-    } else {
-      lv = *reinterpret_cast<const ulonglong2 *>(lp);
-    }
+    const u64 *lp = half_ptr<W>(a.L.lab, x, dir);
+    const Half<W> lv = coherent ? ld_half_agent<W>(lp) : ld_half<W>(lp);
     if (heavy_list && dg > kHeavyDeg) {
       const uint32_t nch = (dg + kChunk - 1) / kChunk;
       const uint32_t hb = atomicAdd(heavy_cnt, nch);
@@ -594,8 +659,7 @@ __device__ __forceinline__ void expand_tile(const PropArgs &a, const uint32_t *f
     const uint32_t dir = ent >> 31;
     const uint32_t *col = dir ? a.r.col : a.f.col;
     const uint32_t y = col[s_off[lo] + (e - s_start[lo])];
-    const ulonglong2 lv = s_lab[lo];
-    const bool ch = relax(a.L.lab + 4ull * y + 2u * dir, lv.x, lv.y);
+    const bool ch = relax<W>(half_ptr<W>(a.L.lab, y, dir), s_lab[lo]);
     const bool push = ch && claim(&a.inq[2ull * y + dir], nstamp);
     wave_push(nq, ncnt, push, y | (ent & kDirBit));
   }
@@ -603,10 +667,11 @@ __device__ __forceinline__ void expand_tile(const PropArgs &a, const uint32_t *f
   __syncthreads();
 }
 
+template <int W>
 __global__ __launch_bounds__(256) void k_round(PropArgs a, uint32_t ring, uint32_t stamp) {
   __shared__ uint32_t s_start[256];
   __shared__ u64 s_off[256];
-  __shared__ ulonglong2 s_lab[256];
+  __shared__ Half<W> s_lab[256];
   __shared__ uint32_t s_ent[256];
   __shared__ uint32_t s_wsum[4];
   Ctl *ctl = a.ctl;
@@ -622,7 +687,7 @@ __global__ __launch_bounds__(256) void k_round(PropArgs a, uint32_t ring, uint32
   for (uint32_t beg = blockIdx.x * 256u; beg < fsz; beg += gridDim.x * 256u) {
     const uint32_t end = min(beg + 256u, fsz);
     expanded += end - beg;
-    expand_tile<256>(a, a.fq[ring], beg, end, a.fq[nring], &ctl->fsize[nring], stamp + 1u,
+    expand_tile<256, W>(a, a.fq[ring], beg, end, a.fq[nring], &ctl->fsize[nring], stamp + 1u,
                      a.heavy_list, &ctl->heavy[stamp & 1u], false, s_start, s_off, s_lab, s_ent,
                      s_wsum, relaxed);
   }
@@ -633,6 +698,7 @@ __global__ __launch_bounds__(256) void k_round(PropArgs a, uint32_t ring, uint32
 }
 
 // Chunks of high-degree frontier rows: one block per chunk of kChunk entries.
+template <int W>
 __global__ __launch_bounds__(256) void k_heavy(PropArgs a, uint32_t hidx, uint32_t nring,
                                                uint32_t nstamp) {
   Ctl *ctl = a.ctl;
@@ -646,7 +712,7 @@ __global__ __launch_bounds__(256) void k_heavy(PropArgs a, uint32_t hidx, uint32
     const Csr g = dir ? a.r : a.f;
     const uint32_t dg = min(g.deg[x], g.cap[x]);
     const uint32_t b = c * kChunk, e_end = min(dg, b + kChunk);
-    const ulonglong2 lv = *reinterpret_cast<const ulonglong2 *>(a.L.lab + 4ull * x + 2u * dir);
+    const Half<W> lv = ld_half<W>(half_ptr<W>(a.L.lab, x, dir));
     const u64 o = g.off[x];
     for (uint32_t e0 = b; e0 < e_end; e0 += 256u) {
       const uint32_t e = e0 + threadIdx.x;
@@ -654,7 +720,7 @@ __global__ __launch_bounds__(256) void k_heavy(PropArgs a, uint32_t hidx, uint32
       uint32_t y = 0;
       if (e < e_end) {
         y = g.col[o + e];
-        push = relax(a.L.lab + 4ull * y + 2u * dir, lv.x, lv.y) &&
+        push = relax<W>(half_ptr<W>(a.L.lab, y, dir), lv) &&
                claim(&a.inq[2ull * y + dir], nstamp);
       }
       wave_push(a.fq[nring], &ctl->fsize[nring], push, y | (ent & kDirBit));
@@ -667,20 +733,21 @@ __global__ __launch_bounds__(256) void k_heavy(PropArgs a, uint32_t hidx, uint32
 hipError_t launch_round(const PropArgs &a, uint32_t ring, uint32_t stamp, uint32_t grid,
                         hipStream_t s) {
   if (grid > kRoundGridMax) grid = kRoundGridMax;
-  hipLaunchKernelGGL(k_round, dim3(grid), dim3(256), 0, s, a, ring, stamp);
+  DBL_LAUNCH_W(a.L.words, k_round, dim3(grid), dim3(256), s, a, ring, stamp);
   const uint32_t nring = ring == 2u ? 0u : ring + 1u;
-  hipLaunchKernelGGL(k_heavy, dim3(kHeavyGrid), dim3(256), 0, s, a, stamp & 1u, nring,
-                     stamp + 1u);
+  DBL_LAUNCH_W(a.L.words, k_heavy, dim3(kHeavyGrid), dim3(256), s, a, stamp & 1u, nring,
+               stamp + 1u);
   return hipGetLastError();
 }
 
 // Rounds inside one workgroup while the frontier is small (no kernel launch per round). Reads
 // the pending frontier from ctl->cur / ctl->stamp and writes back where it stopped: either the
 // frontier is empty, or it outgrew the local bounds and grid rounds take over.
+template <int W>
 __device__ void local_rounds_body(const PropArgs &a) {
   __shared__ uint32_t s_start[kLocalThreads];
   __shared__ u64 s_off[kLocalThreads];
-  __shared__ ulonglong2 s_lab[kLocalThreads];
+  __shared__ Half<W> s_lab[kLocalThreads];
   __shared__ uint32_t s_ent[kLocalThreads];
   __shared__ uint32_t s_wsum[kLocalThreads / 64];
   __shared__ uint32_t s_edges;
@@ -711,7 +778,7 @@ __device__ void local_rounds_body(const PropArgs &a) {
     __syncthreads();
     for (uint32_t beg = 0; beg < fsz; beg += kLocalThreads) {
       const uint32_t end = min(beg + kLocalThreads, fsz);
-      expand_tile<kLocalThreads>(a, fq, beg, end, a.fq[nring], &ctl->fsize[nring], stamp + 1u,
+      expand_tile<kLocalThreads, W>(a, fq, beg, end, a.fq[nring], &ctl->fsize[nring], stamp + 1u,
                                  nullptr, nullptr, true, s_start, s_off, s_lab, s_ent, s_wsum,
                                  relaxed);
     }
@@ -735,14 +802,15 @@ __device__ void local_rounds_body(const PropArgs &a) {
   }
 }
 
+template <int W>
 __global__ __launch_bounds__(kLocalThreads) void k_local_rounds(PropArgs a, Mirror *m,
                                                                 uint32_t seq) {
-  local_rounds_body(a);
+  local_rounds_body<W>(a);
   if (m && threadIdx.x == 0) publish_status(a.ctl, m, seq);
 }
 
 hipError_t launch_local_rounds(const PropArgs &a, Mirror *m, uint32_t seq, hipStream_t s) {
-  hipLaunchKernelGGL(k_local_rounds, dim3(1), dim3(kLocalThreads), 0, s, a, m, seq);
+  DBL_LAUNCH_W(a.L.words, k_local_rounds, dim3(1), dim3(kLocalThreads), s, a, m, seq);
   return hipGetLastError();
 }
 
@@ -773,6 +841,7 @@ __device__ __forceinline__ bool append_edge(const Csr &g, uint32_t x, uint32_t y
 // (DL_in(u), BL_in(u)) into v (Algorithm 3 starts from v). Backward: append u to Pre(v) and OR
 // (DL_out(v), BL_out(v)) into u. A changed endpoint joins the pending frontier. Returns whether
 // it was queued.
+template <int W>
 __device__ __forceinline__ bool apply_half(const PropArgs &a, uint32_t u, uint32_t v, uint32_t dir,
                                            uint32_t ring, uint32_t stamp, Ovf *ovf,
                                            uint64_t ovf_cap, bool active, bool *overflowed) {
@@ -780,33 +849,32 @@ __device__ __forceinline__ bool apply_half(const PropArgs &a, uint32_t u, uint32
   const uint32_t tail = dir ? v : u, head = dir ? u : v;
   if (active && u != v) {
     // the label reads do not depend on the append: issue them first
-    const ulonglong2 lt = *reinterpret_cast<const ulonglong2 *>(a.L.lab + 4ull * tail + 2u * dir);
-    u64 *wh = a.L.lab + 4ull * head + 2u * dir;
-    const ulonglong2 lh = *reinterpret_cast<const ulonglong2 *>(wh);
+    const Half<W> lt = ld_half<W>(half_ptr<W>(a.L.lab, tail, dir));
+    u64 *wh = half_ptr<W>(a.L.lab, head, dir);
+    const Half<W> lh = ld_half<W>(wh);
     if (!append_edge(dir ? a.r : a.f, tail, head, dir ? kDirBit : 0u, ovf, ovf_cap, a.ctl))
       *overflowed = true;
-    bool changed = false;
-    if (lt.x & ~lh.x) changed |= (lt.x & ~atomicOr(wh, lt.x)) != 0ull;
-    if (lt.y & ~lh.y) changed |= (lt.y & ~atomicOr(wh + 1, lt.y)) != 0ull;
-    p = changed && claim(&a.inq[2ull * head + dir], stamp);
+    p = or_half<W>(wh, lt, lh) && claim(&a.inq[2ull * head + dir], stamp);
   }
   wave_push(a.fq[ring], &a.ctl->fsize[ring], p, head | (dir ? kDirBit : 0u));
   return p;
 }
 
 // Both halves of insertion (u,v) by one thread (used by the grid kernel).
+template <int W>
 __device__ __forceinline__ void apply_edge(const PropArgs &a, uint32_t u, uint32_t v,
                                            uint32_t ring, uint32_t stamp, Ovf *ovf,
                                            uint64_t ovf_cap, bool active) {
   bool ovfl = false;
-  apply_half(a, u, v, 0u, ring, stamp, ovf, ovf_cap, active, &ovfl);
-  apply_half(a, u, v, 1u, ring, stamp, ovf, ovf_cap, active, &ovfl);
+  apply_half<W>(a, u, v, 0u, ring, stamp, ovf, ovf_cap, active, &ovfl);
+  apply_half<W>(a, u, v, 1u, ring, stamp, ovf, ovf_cap, active, &ovfl);
 }
 
 // A small batch in one workgroup: thread 2i handles the forward half of edge i and thread
 // 2i+1 the backward half. Every id is checked before anything changes (a block-wide vote);
 // then the halves are applied, the propagation rounds run here when something changed, and one
 // 64-bit word {seq, flags} is written to the host mirror.
+template <int W>
 __global__ __launch_bounds__(kLocalThreads) void k_insert_small(PropArgs a, const uint32_t *src,
                                                                 const uint32_t *dst,
                                                                 uint32_t count, uint32_t n,
@@ -843,14 +911,14 @@ __global__ __launch_bounds__(kLocalThreads) void k_insert_small(PropArgs a, cons
     const uint32_t j = j0 + t;
     const bool act = j < halves;
     const uint32_t i = act ? j >> 1 : 0u;
-    pushed |= apply_half(a, act ? src[i] : 0u, act ? dst[i] : 0u, j & 1u, ring, stamp, ovf,
+    pushed |= apply_half<W>(a, act ? src[i] : 0u, act ? dst[i] : 0u, j & 1u, ring, stamp, ovf,
                          ovf_cap, act, &ovfl);
   }
   if (pushed) s_pushed = 1;
   if (ovfl) s_ovf = 1;
   __syncthreads();
   // nothing changed: the pending frontier is still empty and no round is needed
-  if (s_pushed) local_rounds_body(a);
+  if (s_pushed) local_rounds_body<W>(a);
   __syncthreads();
   if (t == 0) {
     uint32_t flags = 0;
@@ -864,11 +932,12 @@ __global__ __launch_bounds__(kLocalThreads) void k_insert_small(PropArgs a, cons
 hipError_t launch_insert_small(const PropArgs &a, const uint32_t *src, const uint32_t *dst,
                                uint32_t count, uint32_t n, Ovf *ovf, uint64_t ovf_cap, Mirror *m,
                                uint32_t seq, hipStream_t s) {
-  hipLaunchKernelGGL(k_insert_small, dim3(1), dim3(kLocalThreads), 0, s, a, src, dst, count, n,
-                     ovf, ovf_cap, m, seq);
+  DBL_LAUNCH_W(a.L.words, k_insert_small, dim3(1), dim3(kLocalThreads), s, a, src, dst, count, n,
+               ovf, ovf_cap, m, seq);
   return hipGetLastError();
 }
 
+template <int W>
 __global__ __launch_bounds__(256) void k_insert_apply(PropArgs a, const uint32_t *src,
                                                       const uint32_t *dst, uint64_t count,
                                                       Ovf *ovf, uint64_t ovf_cap) {
@@ -883,14 +952,14 @@ __global__ __launch_bounds__(256) void k_insert_apply(PropArgs a, const uint32_t
        i0 += (uint64_t)gridDim.x * blockDim.x) {
     const uint64_t i = i0 + threadIdx.x;
     const bool act = i < count;
-    apply_edge(a, act ? src[i] : 0u, act ? dst[i] : 0u, ring, stamp, ovf, ovf_cap, act);
+    apply_edge<W>(a, act ? src[i] : 0u, act ? dst[i] : 0u, ring, stamp, ovf, ovf_cap, act);
   }
 }
 
 hipError_t launch_insert_apply(const PropArgs &a, const uint32_t *src, const uint32_t *dst,
                                uint64_t count, Ovf *ovf, uint64_t ovf_cap, hipStream_t s) {
-  hipLaunchKernelGGL(k_insert_apply, dim3(grid_for(count, 256, 4096)), dim3(256), 0, s, a, src,
-                     dst, count, ovf, ovf_cap);
+  DBL_LAUNCH_W(a.L.words, k_insert_apply, dim3(grid_for(count, 256, 4096)), dim3(256), s, a, src,
+               dst, count, ovf, ovf_cap);
   return hipGetLastError();
 }
 
@@ -962,6 +1031,7 @@ hipError_t launch_push_overflow(const PropArgs &a, const Ovf *ovf, uint32_t coun
 // A pair the rules leave open whose source has no out-edge is answered here too: the BFS from u
 // would scan nothing, so the answer is "BFS false". The remaining pairs are compacted per block
 // into und[block * kQueryNT ...] with their number in seg[block] (no shared counter).
+template <int W>
 __global__ __launch_bounds__(kQueryNT) void k_query_label(const u64 *lab, const uint32_t *qu,
                                                           const uint32_t *qv, uint64_t count,
                                                           uint32_t n, const uint32_t *fdeg,
@@ -987,18 +1057,24 @@ __global__ __launch_bounds__(kQueryNT) void k_query_label(const u64 *lab, const 
     } else if (u == v) {
       cls = 0;
     } else {
-      const ulonglong2 fu = *reinterpret_cast<const ulonglong2 *>(lab + 4ull * u);
-      const ulonglong2 bu = *reinterpret_cast<const ulonglong2 *>(lab + 4ull * u + 2);
-      const ulonglong2 fv = *reinterpret_cast<const ulonglong2 *>(lab + 4ull * v);
-      const ulonglong2 bv = *reinterpret_cast<const ulonglong2 *>(lab + 4ull * v + 2);
-      // fu = {DL_in(u), BL_in(u)}, bu = {DL_out(u), BL_out(u)}; a disabled label reads as 0
-      // for the rules that use it (the ablations of Table 4)
+      // fu = {DL_in(u), BL_in(u)}, bu = {DL_out(u), BL_out(u)}, likewise for v
+      const Half<W> fu = ld_half<W>(half_ptr<W>(lab, u, 0)), bu = ld_half<W>(half_ptr<W>(lab, u, 1));
+      const Half<W> fv = ld_half<W>(half_ptr<W>(lab, v, 0)), bv = ld_half<W>(half_ptr<W>(lab, v, 1));
+      u64 l1 = 0, l2 = 0, t1 = 0, t2 = 0;
+#pragma unroll
+      for (int j = 0; j < W; j++) {
+        l1 |= bu.w[j] & fv.w[j];
+        l2 |= (fu.w[W + j] & ~fv.w[W + j]) | (bv.w[W + j] & ~bu.w[W + j]);
+        t1 |= bv.w[j] & fu.w[j];
+        t2 |= (bu.w[j] & fu.w[j]) | (bv.w[j] & fv.w[j]);
+      }
+      // a disabled label reads as 0 for the rules that use it (the ablations of Table 4)
       const bool dl = rules & 1u, bl = (rules & 2u) != 0;
-      if (dl && (bu.x & fv.x)) cls = 1;                                   // Lemma 1
-      else if (bl && ((fu.y & ~fv.y) | (bv.y & ~bu.y))) cls = 2;          // Lemma 2
-      else if (dl && (bv.x & fu.x)) cls = 3;                              // Theorem 1
-      else if (dl && ((bu.x & fu.x) | (bv.x & fv.x))) cls = 4;            // Theorem 2
-      else if (fdeg[u] == 0) cls = 6;                                     // empty BFS
+      if (dl && l1) cls = 1;                   // Lemma 1
+      else if (bl && l2) cls = 2;              // Lemma 2
+      else if (dl && t1) cls = 3;              // Theorem 1
+      else if (dl && t2) cls = 4;              // Theorem 2
+      else if (fdeg[u] == 0) cls = 6;          // empty BFS
       else undecided = true;
     }
     if (cls >= 0) out[i] = (uint8_t)((cls <= 1 ? 1u : 0u) | ((uint32_t)cls << 1));
@@ -1034,8 +1110,8 @@ hipError_t launch_query_label(LabelsView L, const uint32_t *u, const uint32_t *v
                               uint32_t *seg, Ctl *ctl, u64 *qcls, uint32_t rules, hipStream_t s) {
   if (count == 0) return hipSuccess;
   const uint64_t blocks = (count + kQueryNT - 1) / kQueryNT;
-  hipLaunchKernelGGL(k_query_label, dim3((uint32_t)blocks), dim3(kQueryNT), 0, s, L.lab, u, v,
-                     count, n, fdeg, out, und, seg, ctl, qcls, rules);
+  DBL_LAUNCH_W(L.words, k_query_label, dim3((uint32_t)blocks), dim3(kQueryNT), s, L.lab, u, v,
+               count, n, fdeg, out, und, seg, ctl, qcls, rules);
   return hipGetLastError();
 }
 
@@ -1048,6 +1124,36 @@ hipError_t launch_query_label(LabelsView L, const uint32_t *u, const uint32_t *v
 // queue, so a bitmap is clean again for the wave's next pair.
 constexpr uint32_t kBfsNT = 256;
 
+// The prune of Algorithm 2 for a target x with record rx, against the query's wave-uniform
+// label words: skip x when DL_out(u) & DL_in(x) != 0 or when BL_in(x) is not inside BL_in(v) or
+// BL_out(v) is not inside BL_out(x).
+template <int W>
+__device__ __forceinline__ bool bfs_prune(const u64 *rx, const u64 *dlo_u, const u64 *bli_v,
+                                          const u64 *blo_v) {
+  const Half<W> fx = ld_half<W>(rx);
+  u64 hit = 0;
+#pragma unroll
+  for (int j = 0; j < W; j++)
+    hit |= (dlo_u[j] & fx.w[j]) | (fx.w[W + j] & ~bli_v[j]) | (blo_v[j] & ~rx[3 * W + j]);
+  return hit != 0ull;
+}
+
+// The query's side of the prune; a disabled label prunes nothing: DL_out(u) = 0, BL_in(v) =
+// all, BL_out(v) = none.
+template <int W>
+__device__ __forceinline__ void bfs_prune_words(const u64 *lab, uint32_t u, uint32_t v,
+                                                uint32_t rules, u64 *dlo_u, u64 *bli_v,
+                                                u64 *blo_v) {
+  const u64 *ru = lab + 4ull * W * u, *rv = lab + 4ull * W * v;
+#pragma unroll
+  for (int j = 0; j < W; j++) {
+    dlo_u[j] = (rules & 1u) ? ru[2 * W + j] : 0ull;
+    bli_v[j] = (rules & 2u) ? rv[W + j] : ~0ull;
+    blo_v[j] = (rules & 2u) ? rv[3 * W + j] : 0ull;
+  }
+}
+
+template <int W>
 __global__ __launch_bounds__(kBfsNT) void k_query_bfs(BfsArgs a, Mirror *m, uint32_t seq) {
   Ctl *ctl = a.ctl;
   const uint32_t lane = __lane_id();
@@ -1070,10 +1176,8 @@ __global__ __launch_bounds__(kBfsNT) void k_query_bfs(BfsArgs a, Mirror *m, uint
     const uint32_t qi = a.und[(uint64_t)sg * kQueryNT + sj];
     sj++;
     const uint32_t u = a.u[qi], v = a.v[qi];
-    // a disabled label prunes nothing: DL_out(u) = 0, BL_in(v) = all, BL_out(v) = none
-    const u64 dlo_u = (a.rules & 1u) ? lab[4ull * u + 2] : 0ull;
-    const u64 bli_v = (a.rules & 2u) ? lab[4ull * v + 1] : ~0ull;
-    const u64 blo_v = (a.rules & 2u) ? lab[4ull * v + 3] : 0ull;
+    u64 dlo_u[W], bli_v[W], blo_v[W];
+    bfs_prune_words<W>(lab, u, v, a.rules, dlo_u, bli_v, blo_v);
     if (lane == 0) {
       atomicOr(&vis[u >> 6], 1ull << (u & 63u));
       q[0] = u;
@@ -1117,9 +1221,7 @@ __global__ __launch_bounds__(kBfsNT) void k_query_bfs(BfsArgs a, Mirror *m, uint
         bool keep = false;
         u64 bit = 0;
         if (act) {
-          const ulonglong2 fx = *reinterpret_cast<const ulonglong2 *>(lab + 4ull * x);
-          const u64 blo_x = lab[4ull * x + 3];
-          keep = !(dlo_u & fx.x) && !(fx.y & ~bli_v) && !(blo_v & ~blo_x);
+          keep = !bfs_prune<W>(lab + 4ull * W * x, dlo_u, bli_v, blo_v);
           if (keep) {
             bit = 1ull << (x & 63u);
             keep = !(atomicOr(&vis[x >> 6], bit) & bit);
@@ -1169,7 +1271,7 @@ __global__ __launch_bounds__(kBfsNT) void k_query_bfs(BfsArgs a, Mirror *m, uint
 
 hipError_t launch_query_bfs(const BfsArgs &a, uint32_t slots, Mirror *m, uint32_t seq,
                             hipStream_t s) {
-  hipLaunchKernelGGL(k_query_bfs, dim3(slots / (kBfsNT / 64u)), dim3(kBfsNT), 0, s, a, m, seq);
+  DBL_LAUNCH_W(a.L.words, k_query_bfs, dim3(slots / (kBfsNT / 64u)), dim3(kBfsNT), s, a, m, seq);
   return hipGetLastError();
 }
 
@@ -1193,6 +1295,7 @@ hipError_t launch_gbfs_start(const PropArgs &a, u64 *vis, uint64_t vis_words, ui
   return hipGetLastError();
 }
 
+template <int W>
 __global__ __launch_bounds__(256) void k_gbfs_round(PropArgs a, u64 *vis, uint32_t u, uint32_t v,
                                                     uint32_t ring, uint32_t rules) {
   Ctl *ctl = a.ctl;
@@ -1200,9 +1303,8 @@ __global__ __launch_bounds__(256) void k_gbfs_round(PropArgs a, u64 *vis, uint32
   const uint32_t fsz = ctl->fsize[ring];
   if (blockIdx.x == 0 && threadIdx.x == 0) ctl->fsize[nring == 2u ? 0u : nring + 1u] = 0;
   const u64 *lab = a.L.lab;
-  const u64 dlo_u = (rules & 1u) ? lab[4ull * u + 2] : 0ull;
-  const u64 bli_v = (rules & 2u) ? lab[4ull * v + 1] : ~0ull;
-  const u64 blo_v = (rules & 2u) ? lab[4ull * v + 3] : 0ull;
+  u64 dlo_u[W], bli_v[W], blo_v[W];
+  bfs_prune_words<W>(lab, u, v, rules, dlo_u, bli_v, blo_v);
   for (uint32_t i0 = blockIdx.x * blockDim.x; i0 < fsz; i0 += gridDim.x * blockDim.x) {
     const uint32_t i = i0 + threadIdx.x;
     if (i >= fsz) continue;
@@ -1215,9 +1317,7 @@ __global__ __launch_bounds__(256) void k_gbfs_round(PropArgs a, u64 *vis, uint32
         ctl->found = 1;
         continue;
       }
-      const ulonglong2 fx = *reinterpret_cast<const ulonglong2 *>(lab + 4ull * x);
-      const u64 blo_x = lab[4ull * x + 3];
-      if ((dlo_u & fx.x) || (fx.y & ~bli_v) || (blo_v & ~blo_x)) continue;
+      if (bfs_prune<W>(lab + 4ull * W * x, dlo_u, bli_v, blo_v)) continue;
       const u64 bit = 1ull << (x & 63u);
       if (atomicOr(&vis[x >> 6], bit) & bit) continue;
       const uint32_t p = atomicAdd(&ctl->fsize[nring], 1u);
@@ -1228,7 +1328,7 @@ __global__ __launch_bounds__(256) void k_gbfs_round(PropArgs a, u64 *vis, uint32
 
 hipError_t launch_gbfs_round(const PropArgs &a, u64 *vis, uint32_t u, uint32_t v, uint32_t ring,
                              uint32_t rules, hipStream_t s) {
-  hipLaunchKernelGGL(k_gbfs_round, dim3(2048), dim3(256), 0, s, a, vis, u, v, ring, rules);
+  DBL_LAUNCH_W(a.L.words, k_gbfs_round, dim3(2048), dim3(256), s, a, vis, u, v, ring, rules);
   return hipGetLastError();
 }
 
@@ -1264,22 +1364,25 @@ hipError_t launch_init_buckets(uint8_t *bucket, uint32_t n0, uint32_t n1, uint32
 
 // ---------------------------------------------------------------- label read-out
 
-__global__ void k_unpack_labels(const u64 *lab, uint32_t n, u64 *dl_in, u64 *dl_out, u64 *bl_in,
-                                u64 *bl_out) {
-  for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < n; x += gridDim.x * blockDim.x) {
-    const ulonglong2 f = *reinterpret_cast<const ulonglong2 *>(lab + 4ull * x);
-    const ulonglong2 b = *reinterpret_cast<const ulonglong2 *>(lab + 4ull * x + 2);
-    if (dl_in) dl_in[x] = f.x;
-    if (bl_in) bl_in[x] = f.y;
-    if (dl_out) dl_out[x] = b.x;
-    if (bl_out) bl_out[x] = b.y;
+// Label i of vertex x goes to out[x * W + i / 64] bit i % 64.
+__global__ void k_unpack_labels(const u64 *lab, uint32_t words, uint32_t n, u64 *dl_in,
+                                u64 *dl_out, u64 *bl_in, u64 *bl_out) {
+  const uint64_t total = (uint64_t)n * words;
+  for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t x = e / words, j = e - x * words;
+    const u64 *rec = lab + 4ull * words * x;
+    if (dl_in) dl_in[e] = rec[j];
+    if (bl_in) bl_in[e] = rec[words + j];
+    if (dl_out) dl_out[e] = rec[2 * words + j];
+    if (bl_out) bl_out[e] = rec[3 * words + j];
   }
 }
 
 hipError_t launch_unpack_labels(LabelsView L, uint32_t n, u64 *dl_in, u64 *dl_out, u64 *bl_in,
                                 u64 *bl_out, hipStream_t s) {
-  hipLaunchKernelGGL(k_unpack_labels, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, L.lab, n,
-                     dl_in, dl_out, bl_in, bl_out);
+  hipLaunchKernelGGL(k_unpack_labels, dim3(grid_for((uint64_t)n * L.words, 256, 8192)), dim3(256),
+                     0, s, L.lab, L.words, n, dl_in, dl_out, bl_in, bl_out);
   return hipGetLastError();
 }
 

@@ -26,12 +26,22 @@ def gpu_index(n, src, dst, **kw):
     return dbl.Index.build(n, dev(src), dev(dst), **kw)
 
 
+def _words(a, w):
+    """A label array as (n, w) words: (n,) is one word; missing high words are zero."""
+    a = a.reshape(len(a), -1)
+    out = np.zeros((len(a), w), dtype=np.uint64)
+    out[:, :a.shape[1]] = a
+    return out
+
+
 def assert_labels_equal(gix, oix, what=""):
     g = gix.labels_numpy()
     o = oix.labels()
     for name, a, b in zip(("DL_in", "DL_out", "BL_in", "BL_out"), g, o):
+        w = max(a.reshape(len(a), -1).shape[1], b.reshape(len(b), -1).shape[1])
+        a, b = _words(a, w), _words(b, w)
         if not np.array_equal(a, b):
-            bad = np.flatnonzero(a != b)
+            bad = np.flatnonzero((a != b).any(axis=1))
             raise AssertionError(f"{what} {name} differs at {len(bad)} vertices, first {bad[:5]}: "
                                  f"gpu {a[bad[:5]]} oracle {b[bad[:5]]}")
 
@@ -113,6 +123,70 @@ def test_families_insert_batches(name, gr):
         assert_labels_equal(g, o, f"{name} after {hi}")
     u, v = all_pairs(n)
     assert_queries_equal(g, o, u, v)
+
+
+# ------------------------------------------------------------------ labels longer than 64 bits
+
+@pytest.mark.parametrize("k,kp,words", [(65, 2, 2), (128, 128, 2), (3, 256, 4), (200, 256, 4),
+                                        (256, 64, 4)])
+def test_multiword_labels_build_insert_query(k, kp, words):
+    """k landmarks and k' buckets beyond one 64-bit word: labels word for word, answers and
+    classes byte for byte, through a build, single-workgroup batches and a grid batch."""
+    w = dblgen.make_rmat_workload(f"mw{k}_{kp}", 11, 4, draws=6 << 11, n_query=30000,
+                                  query_kind="mixed")
+    bucket = random_bucket(w.n, kp, k + kp)
+    g = gpu_index(w.n, w.src, w.dst, num_landmarks=k, bl_bits=kp, leaf_bucket=bucket)
+    assert g.label_words() == words
+    o = oracle.OracleIndex(w.n, w.src, w.dst).build(k=k, kp=kp, bucket_table=bucket, threads=8)
+    assert list(g.landmarks()) == list(o.landmarks())
+    assert_labels_equal(g, o, "build")
+    assert_queries_equal(g, o, w.q_u, w.q_v)
+    rng = np.random.default_rng(k * 1000 + kp)
+    iu = rng.integers(0, w.n, 6000).astype(np.uint32)
+    iv = rng.integers(0, w.n, 6000).astype(np.uint32)
+    for lo, hi in [(0, 1), (1, 100), (100, 6000)]:
+        g.insert_edges(dev(iu[lo:hi]), dev(iv[lo:hi]))
+        o.insert(iu[lo:hi], iv[lo:hi])
+        assert_labels_equal(g, o, f"after {hi} insertions")
+    assert_queries_equal(g, o, w.q_u, w.q_v)
+    for rules in (1, 2):
+        got = g.query_rules(dev(w.q_u), dev(w.q_v), rules).cpu().numpy()
+        assert np.array_equal(got, o.query_rules(w.q_u, w.q_v, rules, threads=8))
+
+
+def test_multiword_default_selection_and_hash():
+    """Top-256 landmark selection (ties by id) and the Fibonacci hash into 256 buckets."""
+    w = dblgen.make_rmat_workload("mwsel", 12, 3, draws=8 << 12)
+    g = gpu_index(w.n, w.src, w.dst, num_landmarks=256, bl_bits=256)
+    o = oracle.OracleIndex(w.n, w.src, w.dst).build(k=256, kp=256, threads=8)
+    assert list(g.landmarks()) == list(o.landmarks())
+    _, bk = g.leaves()
+    assert np.array_equal(bk, o.leaves()[2])
+    assert_labels_equal(g, o, "k = k' = 256")
+
+
+def test_multiword_small_bfs_slots_overflow():
+    """The slot BFS and the whole-device BFS with multi-word prunes: on a 3000-vertex chain with
+    k = 130 the landmarks are vertices 1..130, so q(u, 2999) for u > 130 is left to a BFS that
+    walks the chain and outgrows a queue of 8 entries."""
+    n = 3000
+    src = np.arange(n - 1, dtype=np.uint32)
+    dst = src + 1
+    g = gpu_index(n, src, dst, num_landmarks=130, bl_bits=256, bfs_slots=4, bfs_queue_cap=8)
+    o = oracle.OracleIndex(n, src, dst).build(k=130, kp=256)
+    assert_labels_equal(g, o, "chain")
+    u = np.concatenate([np.arange(200, 2999, 97), np.full(20, 2999)]).astype(np.uint32)
+    v = np.concatenate([np.full(len(range(200, 2999, 97)), 2999), np.arange(20) * 101]
+                       ).astype(np.uint32)
+    got = assert_queries_equal(g, o, u, v)
+    assert ((got >> 1) == 5).sum() > 0
+    assert g.stats()["bfs_heavy"] > 0
+    w = dblgen.make_rmat_workload("mwbfs", 11, 4, draws=6 << 11, n_query=5000,
+                                  query_kind="mixed")
+    g = gpu_index(w.n, w.src, w.dst, num_landmarks=130, bl_bits=256, bfs_slots=4,
+                  bfs_queue_cap=8)
+    o = oracle.OracleIndex(w.n, w.src, w.dst).build(k=130, kp=256, threads=8)
+    assert_queries_equal(g, o, w.q_u, w.q_v)
 
 
 @pytest.mark.parametrize("rank,r", [(1, 0), (2, 0), (3, 0), (0, 3)])
