@@ -215,7 +215,7 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy one 1 GiB device buffer (reads 1 GiB, writes 1 GiB), the "
                          "reference for scaling memory counters")
-    ap.add_argument("--time-kernels", default="insert_small,query_label,query_bfs,round:8",
+    ap.add_argument("--time-kernels", default="insert_server,insert_small,query_label,query_bfs",
                     help="kernel kinds timed with HIP events during the timed steps "
                          "(':N' times one launch in N)")
     args = ap.parse_args()
@@ -261,10 +261,13 @@ def main():
     def step(timed):
         r = {}
         t0 = time.perf_counter()
-        ix = dbl.Index.build(w.n, src, dst, edges_unique=True)
+        # the build's grid propagation rounds are timed from inside dbl_build
+        ix = dbl.Index.build(w.n, src, dst, edges_unique=True,
+                             time_kernels="round" if timed else None)
         t1 = time.perf_counter()
-        if timed and args.time_kernels:
-            ix.time_kernels(args.time_kernels)
+        if timed:
+            r["ktimes_build"] = ix.kernel_times()
+            ix.time_kernels(args.time_kernels or None)
         lat = ix.insert_edges_each(isrc, idst, latencies=True)
         t2 = time.perf_counter()
         ix.query(qu, qv, out=out)
@@ -286,6 +289,22 @@ def main():
         labels = ix.labels()
         ix.close()
         return s_build, s_ins, s_q, labels
+
+    def launch_per_request(plain_labels):
+        """The same single-edge requests with one kernel launch per request instead of the
+        resident request server (untimed; labels must come out identical)."""
+        ix = dbl.Index.build(w.n, src, dst, edges_unique=True)
+        ix.set_tuning(insert_server=0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat2 = ix.insert_edges_each(isrc, idst, latencies=True)
+        dt = time.perf_counter() - t0
+        same = all(torch.equal(a, b) for a, b in zip(ix.labels(), plain_labels))
+        ix.close()
+        return {"edges_per_s": n_ins / dt,
+                "latency_us_p50": float(np.percentile(lat2, 50)),
+                "latency_us_p99": float(np.percentile(lat2, 99)),
+                "labels_equal_server": bool(same)}
 
     def serving():
         """Continuous-batching server on the resident graph: a Poisson stream of query batches
@@ -396,6 +415,7 @@ def main():
     insert_s = float(np.mean([r["insert_s"] for r in results]))
     query_s = float(np.mean([r["query_s"] for r in results]))
     s_build, s_ins, s_q, plain_labels = diagnostics()
+    per_request = launch_per_request(plain_labels)
     batched_res = batched(plain_labels, out.clone())
     serving_res = serving() if args.workload == "lj" and args.serving == "on" else None
     ins_expanded = s_ins["vertices_expanded"] - s_build["vertices_expanded"]
@@ -406,37 +426,51 @@ def main():
     # kernel times accumulated over all timed steps
     kt = {}
     for r in results:
-        for k, v in r["ktimes"].items():
+        for k, v in list(r["ktimes_build"].items()) + list(r["ktimes"].items()):
             a = kt.setdefault(k, {"launches": 0, "total_ms": 0.0})
             a["launches"] += v["launches"]
             a["total_ms"] += v["total_ms"]
     dominant = max(kt, key=lambda k: kt[k]["total_ms"]) if kt else None
 
-    roofline = None
-    if dominant:
-        d = kt[dominant]
-        avg_s = d["total_ms"] / d["launches"] / 1e3
-        if dominant == "query_label":
-            per_launch = QUERY_LABEL_BYTES * n_q
-        elif dominant == "insert_small":
+    def bytes_per_launch(kind):
+        """Algorithmic bytes of one launch of `kind` over this step's work."""
+        if kind == "query_label":
+            return QUERY_LABEL_BYTES * n_q
+        if kind == "insert_server":
+            # every request of the timed steps, spread over the server launches
+            prop = ins_expanded * EXPAND_BYTES + ins_relaxed * RELAX_BYTES
+            per_req = 8 + 8 + 24 + 8 + 32 + 32 + prop / n_ins
+            return per_req * n_ins * len(results) / kt[kind]["launches"]
+        if kind == "insert_small":
             # one edge per launch: the two appends and two seeds (ids 8 B, two degree RMWs 8 B,
             # two row offsets and capacities 24 B, two column writes 8 B, labels read 32 B and
             # OR-ed 32 B), plus the propagation the insertions triggered, averaged per launch
             prop = ins_expanded * EXPAND_BYTES + ins_relaxed * RELAX_BYTES
-            per_launch = 8 + 8 + 24 + 8 + 32 + 32 + prop / n_ins
-        elif dominant == "round":
+            return 8 + 8 + 24 + 8 + 32 + 32 + prop / n_ins
+        if kind == "round":
             prop = (s_build["vertices_expanded"] * EXPAND_BYTES
                     + s_build["edges_relaxed"] * RELAX_BYTES)
-            per_launch = prop / max(s_build["build_rounds"], 1)
-        else:  # query_bfs: per scanned edge 4 B id + 24 B of labels + the visited word
-            per_launch = (s_q["bfs_edges"] - s_ins["bfs_edges"]) * (4 + 24 + 8) + \
+            return prop / max(s_build["build_rounds"], 1)
+        if kind == "query_bfs":
+            # per scanned edge: 4 B id + 24 B of labels + the visited word; per vertex 16 B
+            return (s_q["bfs_edges"] - s_ins["bfs_edges"]) * (4 + 24 + 8) + \
                 (s_q["bfs_vertices"] - s_ins["bfs_vertices"]) * 16
+        return None
+
+    def roofline_of(kind):
+        d = kt[kind]
+        per_launch = bytes_per_launch(kind)
+        if per_launch is None or not d["launches"]:
+            return None
+        avg_s = d["total_ms"] / d["launches"] / 1e3
         achieved = per_launch / avg_s / 1e9
-        traffic = committed_traffic(dominant)
-        roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dominant,
-                    "avg_launch_us": avg_s * 1e6, "launches": d["launches"],
-                    "algorithmic_bytes_per_launch": per_launch}
+        return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": committed_traffic(kind),
+                "kernel": kind, "avg_launch_us": avg_s * 1e6, "launches": d["launches"],
+                "algorithmic_bytes_per_launch": per_launch}
+
+    roofline = roofline_of(dominant) if dominant else None
+    kernel_rooflines = {k: roofline_of(k) for k in kt}
 
     line = {
         "metric": METRIC,
@@ -473,9 +507,11 @@ def main():
                         "insert_vertices_expanded": ins_expanded,
                         "csr_regrows": s_ins["csr_regrows"],
                         "bfs_edges": s_q["bfs_edges"], "bfs_vertices": s_q["bfs_vertices"]},
+        "insert_launch_per_request": per_request,
         "batched": batched_res,
         "serving": serving_res,
         "roofline": roofline,
+        "kernel_rooflines": kernel_rooflines,
         "cpu_baseline": None,
     }
     if args.cpu_baseline == "on":

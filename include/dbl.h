@@ -88,6 +88,9 @@ typedef struct {
      zero-in / zero-out-degree vertices (default); r > 0 = every non-landmark vertex with
      |Pre|*|Suc| <= r is a source of both BL labels. */
   uint64_t leaf_threshold;
+  /* Kernel kinds to time from the build on, as the argument of dbl_time_kernels (NULL = none);
+     lets the build's own propagation rounds be timed. */
+  const char *time_kernels;
 } dbl_options;
 
 /* Which labels a query may use (the ablations of Table 4). */
@@ -147,7 +150,9 @@ dbl_status dbl_add_vertices(dbl_index *ix, uint32_t count, uint32_t *first, void
 /*
  * The one-request-at-a-time form of dbl_insert_edges: edge i is inserted as its own request
  * (validate, append, seed, propagate to the fixpoint, report), in order, exactly as `count`
- * calls of dbl_insert_edges with one edge each. h_latency_us: optional HOST array [count] that
+ * calls of dbl_insert_edges with one edge each. By default a resident workgroup serves the
+ * requests (dbl_tuning.insert_server); the host releases each one after the previous one was
+ * reported. h_latency_us: optional HOST array [count] that
  * receives each request's wall time in microseconds. Stops at the first failing request and
  * returns its status (earlier requests stay applied).
  */
@@ -221,7 +226,8 @@ typedef struct {
 /* Enable timing for a comma-separated list of kernel kinds ("all" = every kind; NULL or "" =
    off), optionally followed by ":N" to time one launch in every N of each kind (the first, the
    N+1-th, ...). Enabling clears the accumulated times. Kinds: insert_small, insert_apply, local_rounds,
-   round (one grid propagation round), query_label, query_bfs. */
+   insert_server (one request-server launch), round (one grid propagation round), query_label,
+   query_bfs. */
 dbl_status dbl_time_kernels(dbl_index *ix, const char *kinds);
 
 /* Copy up to `cap` per-kind records (kinds with at least one launch) to HOST array h_out;
@@ -239,6 +245,11 @@ typedef struct {
   uint32_t local_max_edges;    /* ... and would scan at most this many edges (default 65536) */
   uint32_t round_grid;         /* blocks of a grid propagation round (1..2048; default 2048) */
   uint32_t bfs_slots;          /* BFS slots of the index's own query context (default 1024) */
+  uint32_t insert_server;      /* 1 (default): dbl_insert_edges_each keeps one workgroup resident
+                                  that takes the requests one after another from pinned host
+                                  memory; 0: one launch per request */
+  uint32_t server_idle_us;     /* a server launch ends after this long without a request and is
+                                  started again by the next one (0..10^7; default 200000) */
 } dbl_tuning;
 
 dbl_status dbl_get_tuning(const dbl_index *ix, dbl_tuning *out);

@@ -45,6 +45,7 @@ class DblOptions(ctypes.Structure):
         ("edges_unique", ctypes.c_uint32),
         ("landmark_rank", ctypes.c_uint32),
         ("leaf_threshold", ctypes.c_uint64),
+        ("time_kernels", ctypes.c_char_p),
     ]
 
 
@@ -72,6 +73,8 @@ class DblTuning(ctypes.Structure):
         ("local_max_edges", ctypes.c_uint32),
         ("round_grid", ctypes.c_uint32),
         ("bfs_slots", ctypes.c_uint32),
+        ("insert_server", ctypes.c_uint32),
+        ("server_idle_us", ctypes.c_uint32),
     ]
 
 
@@ -240,7 +243,8 @@ class Index:
               bl_bits: int = 64, landmarks=None, leaf_bucket=None, leaf_flags=None,
               slack_fraction: float = 0.25, slack_min: int = 4, bfs_slots: int = 0,
               bfs_queue_cap: int = 0, edges_unique: bool = False, landmark_rank: int = 0,
-              leaf_threshold: int = 0, stream=None) -> "Index":
+              leaf_threshold: int = 0, time_kernels: Optional[str] = None,
+              stream=None) -> "Index":
         lib = load_library()
         src, dst = _ids(src, "src"), _ids(dst, "dst")
         if src.numel() != dst.numel():
@@ -273,6 +277,10 @@ class Index:
         opt.edges_unique = 1 if edges_unique else 0
         opt.landmark_rank = landmark_rank
         opt.leaf_threshold = leaf_threshold
+        if time_kernels:
+            tk = time_kernels.encode()
+            keep.append(tk)
+            opt.time_kernels = tk
         out = ctypes.c_void_p()
         with torch.cuda.device(src.device):
             st = lib.dbl_build(n, src.numel(), src.data_ptr(), dst.data_ptr(), ctypes.byref(opt),
@@ -414,7 +422,7 @@ class Index:
 
     def set_tuning(self, **kw) -> None:
         """Change tuning fields (small_batch, local_max_frontier, local_max_edges, round_grid,
-        bfs_slots); results never change."""
+        bfs_slots, insert_server, server_idle_us); results never change."""
         cur = self.tuning()
         bad = set(kw) - set(cur)
         if bad:

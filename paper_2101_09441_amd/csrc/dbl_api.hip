@@ -58,6 +58,9 @@ struct dbl_index {
   uint64_t heavy_cap = 0;
   Ctl *ctl = nullptr;
   dbl::Mirror *mirror = nullptr;  // pinned, device-mapped host memory written by the device
+  u64 *door = nullptr;            // pinned, device-mapped host memory written by the host
+  u64 clock_khz = 100000;         // device wall-clock rate
+  uint32_t server_idle_us = 200000;  // request-server idle limit
   dbl::Mirror hs{};               // host copy of the last published status
   uint32_t seq = 0;
   u64 *pcnt = nullptr;  // per-block propagation counters
@@ -72,6 +75,7 @@ struct dbl_index {
   uint32_t small_batch = dbl::kSmallBatch;
   uint32_t local_max_frontier = dbl::kLocalMaxFrontier, local_max_edges = dbl::kLocalMaxEdges;
   uint32_t round_grid = dbl::kRoundGridMax;
+  uint32_t insert_server = 1;  // dbl_insert_edges_each through the request server
   // query contexts: the default one and those created by callers (guarded by ctx_mu)
   uint32_t slots_opt = 0, qcap_opt = 0;
   dbl_query_ctx *qctx = nullptr;
@@ -100,12 +104,14 @@ enum TimedKind : uint32_t {
   kTInsertSmall = 0,
   kTInsertApply,
   kTLocalRounds,
+  kTInsertServer,
   kTRound,
   kTQueryLabel,
   kTQueryBfs,
   kTKinds
 };
-const char *const kKindNames[kTKinds] = {"insert_small", "insert_apply", "local_rounds", "round",
+const char *const kKindNames[kTKinds] = {"insert_small", "insert_apply", "local_rounds",
+                                         "insert_server", "round",
                                          "query_label", "query_bfs"};
 
 hipEvent_t take_event(dbl_index *ix) {
@@ -611,6 +617,14 @@ dbl_status do_build(dbl_index *ix, uint64_t m, const uint32_t *src, const uint32
   CK(hipHostMalloc((void **)&ix->mirror, sizeof(dbl::Mirror),
                    hipHostMallocMapped | hipHostMallocCoherent));
   memset((void *)ix->mirror, 0, sizeof(dbl::Mirror));
+  CK(hipHostMalloc((void **)&ix->door, 64, hipHostMallocMapped | hipHostMallocCoherent));
+  memset((void *)ix->door, 0, 64);
+  {
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, ix->device) == hipSuccess &&
+        khz > 0)
+      ix->clock_khz = (u64)khz;
+  }
   CKS(dalloc(&ix->pcnt, 2ull * dbl::kPropCtrSlots));
   CK(dbl::launch_fill_u64(ix->pcnt, 0ull, 2ull * dbl::kPropCtrSlots, s));
   {
@@ -731,6 +745,103 @@ dbl_status do_build(dbl_index *ix, uint64_t m, const uint32_t *src, const uint32
   return DBL_OK;
 }
 
+// The one-request-at-a-time form through the request server (k_insert_server): request i is
+// released by writing i + 1 to the doorbell and is done when the device publishes its sequence
+// number. A request whose flags need the host (bad id, full row, large frontier) ends the
+// launch; the host finishes it exactly as dbl_insert_edges does and starts a new launch for the
+// rest. A launch that timed out waiting (the host was slow) is started again.
+dbl_status insert_each_served(dbl_index *ix, uint32_t count, const uint32_t *d_src,
+                              const uint32_t *d_dst, float *h_latency_us, hipStream_t s) {
+  // whatever way this returns, a launch still waiting for a request ends at once
+  struct StopOnExit {
+    u64 *door;
+    ~StopOnExit() { __atomic_store_n(door, dbl::kDoorStop, __ATOMIC_SEQ_CST); }
+  } stop_on_exit{ix->door};
+  if (ix->ovf_cap < 2) {
+    dfree(ix->ovf);
+    CKS(dalloc(&ix->ovf, 1024));
+    ix->ovf_cap = 1024;
+  }
+  uint32_t i = 0;
+  while (i < count) {
+    __atomic_store_n(ix->door, 0ull, __ATOMIC_SEQ_CST);
+    const dbl::PropArgs a = prop_args(ix);
+    const uint32_t first = i, seq0 = ix->seq;
+    {
+      Timed tm(ix, kTInsertServer, s);
+      CK(dbl::launch_insert_server(a, d_src, d_dst, first, count, ix->n, ix->ovf, ix->ovf_cap,
+                                   ix->mirror, ix->door, seq0,
+                                   ix->clock_khz * ix->server_idle_us / 1000, s));
+    }
+    bool relaunch = false;
+    for (; i < count && !relaunch; i++) {
+      const uint32_t seq = seq0 + (i - first) + 1;
+      const auto t0 = std::chrono::steady_clock::now();
+      __atomic_store_n(ix->door, (u64)i + 1, __ATOMIC_SEQ_CST);
+      uint32_t flags = 0;
+      bool gone = false;
+      for (uint64_t spin = 1;; spin++) {
+        const u64 w = __atomic_load_n(&ix->mirror->fast, __ATOMIC_ACQUIRE);
+        if ((uint32_t)w == seq) {
+          flags = (uint32_t)(w >> 32);
+          break;
+        }
+        if ((spin & 4095) == 0) {
+          const hipError_t q = hipStreamQuery(s);
+          if (q == hipSuccess) {
+            const u64 w2 = __atomic_load_n(&ix->mirror->fast, __ATOMIC_ACQUIRE);
+            if ((uint32_t)w2 == seq) {
+              flags = (uint32_t)(w2 >> 32);
+              break;
+            }
+            gone = true;  // the launch ended before taking request i
+            break;
+          }
+          if (q != hipErrorNotReady) return from_hip(q);
+        }
+      }
+      if (gone) {
+        relaunch = true;
+        i--;  // request i again, in a new launch
+        ix->seq = seq - 1;
+        continue;
+      }
+      ix->seq = seq;
+      if (flags) {
+        // the launch has ended after this request; finish it on the host
+        CK(hipStreamSynchronize(s));
+        CKS(sync_ctl(ix, s));
+        if (ix->hs.err) {
+          CKS(set_ctl_u32(ix, offsetof(Ctl, err), 0u, s));
+          CK(hipStreamSynchronize(s));
+          if (h_latency_us)
+            h_latency_us[i] = std::chrono::duration<float, std::micro>(
+                                  std::chrono::steady_clock::now() - t0).count();
+          return DBL_ERR_VERTEX_RANGE;
+        }
+        uint64_t rounds = 0;
+        CKS(finish_insert(ix, s, &rounds));
+        ix->insert_calls++;
+        ix->insert_rounds += rounds;
+        relaunch = true;
+      } else {
+        ix->insert_calls++;
+        ix->hs.err = 0;
+        ix->hs.ovf_count = 0;
+        ix->hs.fsize[ix->hs.cur] = 0;
+      }
+      if (h_latency_us)
+        h_latency_us[i] = std::chrono::duration<float, std::micro>(
+                              std::chrono::steady_clock::now() - t0).count();
+    }
+    if (!relaunch) break;
+  }
+  __atomic_store_n(ix->door, dbl::kDoorStop, __ATOMIC_SEQ_CST);
+  CK(hipStreamSynchronize(s));
+  if (!ix->pending.empty()) resolve_times(ix);
+  return DBL_OK;
+}
+
 // Move p to a new allocation of new_count entries, keeping the first old_count.
 template <typename T>
 dbl_status grow(T *&p, uint64_t old_count, uint64_t new_count, hipStream_t s) {
@@ -821,6 +932,13 @@ dbl_status dbl_build(uint32_t n, uint64_t m, const uint32_t *d_src, const uint32
   ix->slots_opt = o.bfs_slots;
   ix->qcap_opt = o.bfs_queue_cap;
   hipStream_t s = (hipStream_t)stream;
+  if (o.time_kernels) {
+    const dbl_status ts = dbl_time_kernels(ix, o.time_kernels);
+    if (ts != DBL_OK) {
+      delete ix;
+      return ts;
+    }
+  }
   dbl_status st = do_build(ix, m, d_src, d_dst, o, s);
   if (st != DBL_OK) {
     (void)hipStreamSynchronize(s);
@@ -882,16 +1000,21 @@ dbl_status dbl_insert_edges_each(dbl_index *ix, uint64_t count, const uint32_t *
                                  const uint32_t *d_dst, float *h_latency_us, void *stream) {
   if (!ix) return DBL_ERR_INVALID_ARG;
   if (count == 0) return DBL_OK;
-  if (!d_src || !d_dst) return DBL_ERR_INVALID_ARG;
-  for (uint64_t i = 0; i < count; i++) {
-    const auto t0 = std::chrono::steady_clock::now();
-    const dbl_status st = dbl_insert_edges(ix, 1, d_src + i, d_dst + i, stream);
-    if (h_latency_us)
-      h_latency_us[i] = std::chrono::duration<float, std::micro>(
-                            std::chrono::steady_clock::now() - t0).count();
-    if (st != DBL_OK) return st;
+  if (!d_src || !d_dst || count > 0xFFFFFFFFull) return DBL_ERR_INVALID_ARG;
+  if (!ix->insert_server) {
+    for (uint64_t i = 0; i < count; i++) {
+      const auto t0 = std::chrono::steady_clock::now();
+      const dbl_status st = dbl_insert_edges(ix, 1, d_src + i, d_dst + i, stream);
+      if (h_latency_us)
+        h_latency_us[i] = std::chrono::duration<float, std::micro>(
+                              std::chrono::steady_clock::now() - t0).count();
+      if (st != DBL_OK) return st;
+    }
+    return DBL_OK;
   }
-  return DBL_OK;
+  DeviceGuard dg(ix->device);
+  return insert_each_served(ix, (uint32_t)count, d_src, d_dst, h_latency_us,
+                            (hipStream_t)stream);
 }
 
 dbl_status dbl_query_batch(dbl_index *ix, uint64_t count, const uint32_t *d_u,
@@ -1158,6 +1281,8 @@ dbl_status dbl_get_tuning(const dbl_index *ix, dbl_tuning *out) {
   out->local_max_frontier = ix->local_max_frontier;
   out->local_max_edges = ix->local_max_edges;
   out->round_grid = ix->round_grid;
+  out->insert_server = ix->insert_server;
+  out->server_idle_us = ix->server_idle_us;
   out->bfs_slots = ix->qctx ? ix->qctx->slots : (ix->slots_opt ? ix->slots_opt : 1024);
   return DBL_OK;
 }
@@ -1165,13 +1290,16 @@ dbl_status dbl_get_tuning(const dbl_index *ix, dbl_tuning *out) {
 dbl_status dbl_set_tuning(dbl_index *ix, const dbl_tuning *t) {
   if (!ix || !t) return DBL_ERR_INVALID_ARG;
   if (t->small_batch > dbl::kSmallBatchMax || t->round_grid == 0 ||
-      t->round_grid > dbl::kRoundGridMax || t->bfs_slots > (1u << 16))
+      t->round_grid > dbl::kRoundGridMax || t->bfs_slots > (1u << 16) || t->insert_server > 1 ||
+      t->server_idle_us > 10000000)
     return DBL_ERR_INVALID_ARG;
   DeviceGuard dg(ix->device);
   ix->small_batch = t->small_batch;
   ix->local_max_frontier = t->local_max_frontier;
   ix->local_max_edges = t->local_max_edges;
   ix->round_grid = t->round_grid;
+  ix->insert_server = t->insert_server;
+  ix->server_idle_us = t->server_idle_us;
   const uint32_t slots = t->bfs_slots ? std::max<uint32_t>(4, (t->bfs_slots + 3) / 4 * 4) : 0;
   if (slots && (!ix->qctx || ix->qctx->slots != slots)) {
     // rebuild the index's own query context with the new slot count (its counters are kept)
@@ -1208,6 +1336,7 @@ void dbl_destroy(dbl_index *ix) {
   dfree(ix->heavy_list);
   dfree(ix->ctl);
   if (ix->mirror) (void)hipHostFree((void *)ix->mirror);
+  if (ix->door) (void)hipHostFree((void *)ix->door);
   dfree(ix->pcnt);
   dfree(ix->ovf);
   dfree(ix->landmarks_d);

@@ -83,6 +83,9 @@ struct Mirror {
   unsigned long long fast;
 };
 constexpr uint32_t kFastErr = 1u, kFastOvf = 2u, kFastPending = 4u;
+// Doorbell word of the request server (pinned host memory written by the host): i + 1 releases
+// request i; kDoorStop ends the server.
+constexpr unsigned long long kDoorStop = ~0ull;
 
 // Per-block / per-slot statistics (plain read-modify-write by the owning block, no atomics).
 constexpr uint32_t kQueryGrid = 64;    // class-counter stripes (label-kernel block % 64)
@@ -175,6 +178,11 @@ hipError_t launch_local_rounds(const PropArgs &a, Mirror *m, uint32_t seq, hipSt
 hipError_t launch_insert_small(const PropArgs &a, const uint32_t *src, const uint32_t *dst,
                                uint32_t count, uint32_t n, Ovf *ovf, uint64_t ovf_cap, Mirror *m,
                                uint32_t seq, hipStream_t s);
+// request server for requests [first, count); see k_insert_server
+hipError_t launch_insert_server(const PropArgs &a, const uint32_t *src, const uint32_t *dst,
+                                uint32_t first, uint32_t count, uint32_t n, Ovf *ovf,
+                                uint64_t ovf_cap, Mirror *m, const unsigned long long *door,
+                                uint32_t seq0, unsigned long long idle_ticks, hipStream_t s);
 hipError_t launch_insert_apply(const PropArgs &a, const uint32_t *src, const uint32_t *dst,
                                uint64_t count, Ovf *ovf, uint64_t ovf_cap, hipStream_t s);
 hipError_t launch_regrow_copy(Csr old_g, Csr new_g, uint32_t n, hipStream_t s);

@@ -753,7 +753,7 @@ __device__ void local_rounds_body(const PropArgs &a) {
   __shared__ uint32_t s_edges;
   Ctl *ctl = a.ctl;
   const uint32_t t = threadIdx.x;
-  uint32_t ring = ctl->cur, stamp = ctl->stamp;
+  uint32_t ring = ld_agent32(&ctl->cur), stamp = ld_agent32(&ctl->stamp);
   u64 relaxed = 0, expanded = 0;
   uint32_t rounds = 0;
   for (;;) {
@@ -792,8 +792,8 @@ __device__ void local_rounds_body(const PropArgs &a) {
   if (t == 0) {
     const uint32_t nring = ring == 2u ? 0u : ring + 1u;
     st_agent32(&ctl->fsize[nring], 0u);
-    ctl->cur = ring;
-    ctl->stamp = stamp;
+    st_agent32(&ctl->cur, ring);
+    st_agent32(&ctl->stamp, stamp);
     ctl->local_rounds += rounds;
     if (expanded) {
       a.pcnt[2 * (kRoundGridMax + kHeavyGrid)] += expanded;
@@ -872,15 +872,14 @@ __device__ __forceinline__ void apply_edge(const PropArgs &a, uint32_t u, uint32
 
 // A small batch in one workgroup: thread 2i handles the forward half of edge i and thread
 // 2i+1 the backward half. Every id is checked before anything changes (a block-wide vote);
-// then the halves are applied, the propagation rounds run here when something changed, and one
-// 64-bit word {seq, flags} is written to the host mirror.
+// then the halves are applied and the propagation rounds run here when something changed.
+// Returns the flags of the host status word (kFastErr, kFastOvf, kFastPending), the same in
+// every thread. Control-block fields are read past the caches: the request server runs this
+// body many times in one launch.
 template <int W>
-__global__ __launch_bounds__(kLocalThreads) void k_insert_small(PropArgs a, const uint32_t *src,
-                                                                const uint32_t *dst,
-                                                                uint32_t count, uint32_t n,
-                                                                Ovf *ovf, uint64_t ovf_cap,
-                                                                Mirror *m, uint32_t seq) {
-  __shared__ uint32_t s_pushed, s_ovf;
+__device__ uint32_t insert_small_body(const PropArgs &a, const uint32_t *src, const uint32_t *dst,
+                                      uint32_t count, uint32_t n, Ovf *ovf, uint64_t ovf_cap) {
+  __shared__ uint32_t s_pushed, s_ovf, s_flags;
   Ctl *ctl = a.ctl;
   const uint32_t t = threadIdx.x;
   const uint32_t halves = 2 * count;  // half j: edge j / 2, direction j % 2
@@ -894,17 +893,13 @@ __global__ __launch_bounds__(kLocalThreads) void k_insert_small(PropArgs a, cons
     bad |= (src[i] >= n) | (dst[i] >= n);
   }
   if (__syncthreads_or(bad)) {
-    if (t == 0) {
-      atomicOr(&ctl->err, kErrRange);
-      __hip_atomic_store(&m->fast, ((u64)kFastErr << 32) | seq, __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_SYSTEM);
-    }
-    return;
+    if (t == 0) atomicOr(&ctl->err, kErrRange);
+    return kFastErr;
   }
-  const uint32_t ring = ctl->cur, stamp = ctl->stamp;
+  const uint32_t ring = ld_agent32(&ctl->cur), stamp = ld_agent32(&ctl->stamp);
   if (t == 0) {
-    ctl->heavy[0] = 0;
-    ctl->heavy[1] = 0;
+    st_agent32(&ctl->heavy[0], 0u);
+    st_agent32(&ctl->heavy[1], 0u);
   }
   bool pushed = false, ovfl = false;
   for (uint32_t j0 = 0; j0 < halves; j0 += kLocalThreads) {
@@ -912,7 +907,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_insert_small(PropArgs a, cons
     const bool act = j < halves;
     const uint32_t i = act ? j >> 1 : 0u;
     pushed |= apply_half<W>(a, act ? src[i] : 0u, act ? dst[i] : 0u, j & 1u, ring, stamp, ovf,
-                         ovf_cap, act, &ovfl);
+                            ovf_cap, act, &ovfl);
   }
   if (pushed) s_pushed = 1;
   if (ovfl) s_ovf = 1;
@@ -924,9 +919,26 @@ __global__ __launch_bounds__(kLocalThreads) void k_insert_small(PropArgs a, cons
     uint32_t flags = 0;
     if (s_ovf) flags |= kFastOvf;
     if (s_pushed && ld_agent32(&ctl->fsize[ld_agent32(&ctl->cur)])) flags |= kFastPending;
-    __hip_atomic_store(&m->fast, ((u64)flags << 32) | seq, __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_SYSTEM);
+    s_flags = flags;
   }
+  __syncthreads();
+  return s_flags;
+}
+
+__device__ __forceinline__ void publish_fast(Mirror *m, uint32_t flags, uint32_t seq) {
+  __hip_atomic_store(&m->fast, ((u64)flags << 32) | seq, __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// One small batch, then one 64-bit word {seq, flags} to the host mirror.
+template <int W>
+__global__ __launch_bounds__(kLocalThreads) void k_insert_small(PropArgs a, const uint32_t *src,
+                                                                const uint32_t *dst,
+                                                                uint32_t count, uint32_t n,
+                                                                Ovf *ovf, uint64_t ovf_cap,
+                                                                Mirror *m, uint32_t seq) {
+  const uint32_t flags = insert_small_body<W>(a, src, dst, count, n, ovf, ovf_cap);
+  if (threadIdx.x == 0) publish_fast(m, flags, seq);
 }
 
 hipError_t launch_insert_small(const PropArgs &a, const uint32_t *src, const uint32_t *dst,
@@ -934,6 +946,60 @@ hipError_t launch_insert_small(const PropArgs &a, const uint32_t *src, const uin
                                uint32_t seq, hipStream_t s) {
   DBL_LAUNCH_W(a.L.words, k_insert_small, dim3(1), dim3(kLocalThreads), s, a, src, dst, count, n,
                ovf, ovf_cap, m, seq);
+  return hipGetLastError();
+}
+
+constexpr uint32_t kServerMaxSpins = 1u << 23;
+
+// Request server: the one-request-at-a-time form without a launch per request. One workgroup
+// waits for the host to release request i (door == i + 1 in pinned host memory), inserts edge
+// (src[i], dst[i]) with the small-batch body and publishes {seq0 + i - first + 1, flags}. It
+// returns after the last request, after a request that needs the host (nonzero flags: a bad id,
+// a full row, a frontier too large for one workgroup), on kDoorStop, or when no request arrives
+// for idle_ticks of the device wall clock, so every launch ends by itself.
+template <int W>
+__global__ __launch_bounds__(kLocalThreads) void k_insert_server(
+    PropArgs a, const uint32_t *src, const uint32_t *dst, uint32_t first, uint32_t count,
+    uint32_t n, Ovf *ovf, uint64_t ovf_cap, Mirror *m, const u64 *door, uint32_t seq0,
+    u64 idle_ticks) {
+  __shared__ uint32_t s_go;
+  for (uint32_t i = first; i < count; i++) {
+    if (threadIdx.x == 0) {
+      uint32_t go = 0;
+      const u64 t0 = wall_clock64();
+      // the wall clock bounds the wait; the iteration bound (each iteration reads host memory,
+      // at least ~1 us) is a backstop that ends the wait even if the clock stood still
+      for (uint32_t spin = 0; spin < kServerMaxSpins; spin++) {
+        const u64 d = __hip_atomic_load(door, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        if (d == (u64)i + 1u) {
+          go = 1;
+          break;
+        }
+        if (d == kDoorStop || wall_clock64() - t0 > idle_ticks) break;
+        __builtin_amdgcn_s_sleep(2);
+      }
+      s_go = go;
+    }
+    __syncthreads();
+    if (!s_go) return;
+    // the previous request's atomics went to L2: drop this CU's cached lines before reading
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    const uint32_t flags = insert_small_body<W>(a, src + i, dst + i, 1u, n, ovf, ovf_cap);
+    if (threadIdx.x == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      publish_fast(m, flags, seq0 + (i - first) + 1u);
+    }
+    if (flags) return;
+  }
+}
+
+hipError_t launch_insert_server(const PropArgs &a, const uint32_t *src, const uint32_t *dst,
+                                uint32_t first, uint32_t count, uint32_t n, Ovf *ovf,
+                                uint64_t ovf_cap, Mirror *m, const u64 *door, uint32_t seq0,
+                                u64 idle_ticks, hipStream_t s) {
+  if (first >= count) return hipSuccess;
+  DBL_LAUNCH_W(a.L.words, k_insert_server, dim3(1), dim3(kLocalThreads), s, a, src, dst, first,
+               count, n, ovf, ovf_cap, m, door, seq0, idle_ticks);
   return hipGetLastError();
 }
 
@@ -1081,11 +1147,14 @@ __global__ __launch_bounds__(kQueryNT) void k_query_label(const u64 *lab, const 
   }
   const uint32_t lane = __lane_id(), w = threadIdx.x >> 6;
   const u64 um = __ballot(undecided);
+  // every lane takes part in the ballots (a ballot only sees the lanes that execute it)
+  uint32_t ccount[7];
+#pragma unroll
+  for (int c = 0; c < 7; c++) ccount[c] = (uint32_t)__popcll(__ballot(cls == c));
   if (lane == 0) {
-    for (int c = 0; c < 7; c++) s_cls[w][c] = (uint32_t)__popcll(__ballot(cls == c));
+#pragma unroll
+    for (int c = 0; c < 7; c++) s_cls[w][c] = ccount[c];
     s_und[w] = (uint32_t)__popcll(um);
-  } else {
-    for (int c = 0; c < 7; c++) (void)__ballot(cls == c);
   }
   if (__ballot(bad) && lane == 0) atomicOr(&ctl->err, kErrRange);
   __syncthreads();

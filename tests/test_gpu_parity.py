@@ -267,6 +267,56 @@ def test_tiny_insert_each_equals_single_calls(tiny):
         g.insert_edges_each(dev([1, 2, w.n]), dev([3, 4, 5]))
 
 
+@pytest.mark.parametrize("server,idle_us", [(0, 200000), (1, 0)])
+def test_insert_each_forms(tiny, server, idle_us):
+    """One launch per request, and the request server with a zero idle limit (a launch ends as
+    soon as the next request is not there yet, so most requests start a new launch)."""
+    w = tiny
+    g = gpu_index(w.n, w.src, w.dst)
+    g.set_tuning(insert_server=server, server_idle_us=idle_us)
+    o = oracle.OracleIndex(w.n, w.src, w.dst).build(threads=8)
+    k = 300
+    lat = g.insert_edges_each(dev(w.ins_src[:k]), dev(w.ins_dst[:k]), latencies=True)
+    o.insert(w.ins_src[:k], w.ins_dst[:k])
+    assert np.all(lat > 0)
+    assert_labels_equal(g, o, f"server {server} idle {idle_us}")
+    assert g.stats()["insert_calls"] == k
+
+
+def test_insert_each_server_hands_back_to_host(tiny):
+    """Requests that fill a row (no slack) or grow a frontier past one workgroup (tiny local
+    bounds) end the server launch; the host regrows the CSR or runs grid rounds, and a new
+    launch serves the rest."""
+    w = tiny
+    g = gpu_index(w.n, w.src, w.dst, slack_fraction=0.0, slack_min=0)
+    g.set_tuning(local_max_frontier=4, local_max_edges=64)
+    o = oracle.OracleIndex(w.n, w.src, w.dst).build(threads=8)
+    g.insert_edges_each(dev(w.ins_src), dev(w.ins_dst))
+    o.insert(w.ins_src, w.ins_dst)
+    st = g.stats()
+    assert st["csr_regrows"] > 0 and st["insert_rounds"] > 0
+    assert_labels_equal(g, o, "server with host hand-offs")
+    assert_queries_equal(g, o, w.q_u, w.q_v)
+
+
+def test_insert_each_stops_at_bad_id(tiny):
+    """A request with an out-of-range id fails; the requests before it stay applied, the ones
+    after it are not run, and the next call serves normally."""
+    w = tiny
+    g = gpu_index(w.n, w.src, w.dst)
+    o = oracle.OracleIndex(w.n, w.src, w.dst).build(threads=8)
+    a = np.array(list(w.ins_src[:10]) + [w.n] + list(w.ins_src[10:15]), dtype=np.uint32)
+    b = np.array(list(w.ins_dst[:10]) + [0] + list(w.ins_dst[10:15]), dtype=np.uint32)
+    with pytest.raises(dbl.DblError):
+        g.insert_edges_each(dev(a), dev(b))
+    o.insert(w.ins_src[:10], w.ins_dst[:10])
+    assert g.stats()["insert_calls"] == 10
+    assert_labels_equal(g, o, "stopped at the bad id")
+    g.insert_edges_each(dev(w.ins_src[10:200]), dev(w.ins_dst[10:200]))
+    o.insert(w.ins_src[10:200], w.ins_dst[10:200])
+    assert_labels_equal(g, o, "served after the failure")
+
+
 @pytest.mark.parametrize("batch", [1000, 333, 7])
 def test_tiny_batched_insertions_equal_sequential(tiny, batch):
     w = tiny
