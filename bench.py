@@ -212,12 +212,16 @@ def main():
     ap.add_argument("--workload", choices=["lj", "tiny", "scale"], default="lj")
     ap.add_argument("--cpu-baseline", choices=["on", "off"], default="on")
     ap.add_argument("--serving", choices=["on", "off"], default="on")
+    ap.add_argument("--extras", choices=["on", "off"], default="on",
+                    help="off: skip the launch-per-request comparison, the batched form and "
+                         "serving (leaves only same-sized plain passes, e.g. for profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy one 1 GiB device buffer (reads 1 GiB, writes 1 GiB), the "
                          "reference for scaling memory counters")
-    ap.add_argument("--time-kernels", default="insert_server,insert_small,query_label,query_bfs",
+    ap.add_argument("--time-kernels",
+                    default="round,insert_server,insert_small,query_label,query_bfs",
                     help="kernel kinds timed with HIP events during the timed steps "
-                         "(':N' times one launch in N)")
+                         "(':N' times one launch in N); 'round' times the build's rounds")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this path "
@@ -258,16 +262,18 @@ def main():
         log("calibration copy: 1 GiB read, 1 GiB written")
     torch.cuda.synchronize()
 
+    kinds = [k for k in args.time_kernels.split(",") if k]
+
     def step(timed):
         r = {}
         t0 = time.perf_counter()
         # the build's grid propagation rounds are timed from inside dbl_build
         ix = dbl.Index.build(w.n, src, dst, edges_unique=True,
-                             time_kernels="round" if timed else None)
+                             time_kernels="round" if timed and "round" in kinds else None)
         t1 = time.perf_counter()
         if timed:
             r["ktimes_build"] = ix.kernel_times()
-            ix.time_kernels(args.time_kernels or None)
+            ix.time_kernels(",".join(k for k in kinds if k != "round") or None)
         lat = ix.insert_edges_each(isrc, idst, latencies=True)
         t2 = time.perf_counter()
         ix.query(qu, qv, out=out)
@@ -415,9 +421,11 @@ def main():
     insert_s = float(np.mean([r["insert_s"] for r in results]))
     query_s = float(np.mean([r["query_s"] for r in results]))
     s_build, s_ins, s_q, plain_labels = diagnostics()
-    per_request = launch_per_request(plain_labels)
-    batched_res = batched(plain_labels, out.clone())
-    serving_res = serving() if args.workload == "lj" and args.serving == "on" else None
+    extras = args.extras == "on"
+    per_request = launch_per_request(plain_labels) if extras else None
+    batched_res = batched(plain_labels, out.clone()) if extras else None
+    serving_res = (serving() if extras and args.workload == "lj" and args.serving == "on"
+                   else None)
     ins_expanded = s_ins["vertices_expanded"] - s_build["vertices_expanded"]
     ins_relaxed = s_ins["edges_relaxed"] - s_build["edges_relaxed"]
     answers = out.cpu().numpy()

@@ -949,47 +949,94 @@ hipError_t launch_insert_small(const PropArgs &a, const uint32_t *src, const uin
   return hipGetLastError();
 }
 
+// Request server: the one-request-at-a-time form without a launch per request. Wave 0 waits
+// for the host to release request i (door == i + 1 in pinned host memory), inserts edge
+// (src[i], dst[i]) with lanes 0 and 1 (the two halves) and publishes {seq0 + i - first + 1,
+// flags}; requests that change no label need nothing else, so the other waves stay parked at a
+// barrier. A request whose halves queue a vertex wakes the workgroup, which runs the
+// propagation rounds and publishes. The launch returns after the last request, after a request
+// that needs the host (nonzero flags: a bad id, a full row, a frontier too large for one
+// workgroup), on kDoorStop, or when no request arrives for idle_ticks of the device wall clock.
 constexpr uint32_t kServerMaxSpins = 1u << 23;
+constexpr uint32_t kCmdExit = 0u, kCmdPropagate = 1u;
 
-// Request server: the one-request-at-a-time form without a launch per request. One workgroup
-// waits for the host to release request i (door == i + 1 in pinned host memory), inserts edge
-// (src[i], dst[i]) with the small-batch body and publishes {seq0 + i - first + 1, flags}. It
-// returns after the last request, after a request that needs the host (nonzero flags: a bad id,
-// a full row, a frontier too large for one workgroup), on kDoorStop, or when no request arrives
-// for idle_ticks of the device wall clock, so every launch ends by itself.
 template <int W>
 __global__ __launch_bounds__(kLocalThreads) void k_insert_server(
     PropArgs a, const uint32_t *src, const uint32_t *dst, uint32_t first, uint32_t count,
     uint32_t n, Ovf *ovf, uint64_t ovf_cap, Mirror *m, const u64 *door, uint32_t seq0,
     u64 idle_ticks) {
-  __shared__ uint32_t s_go;
-  for (uint32_t i = first; i < count; i++) {
-    if (threadIdx.x == 0) {
-      uint32_t go = 0;
-      const u64 t0 = wall_clock64();
-      // the wall clock bounds the wait; the iteration bound (each iteration reads host memory,
-      // at least ~1 us) is a backstop that ends the wait even if the clock stood still
-      for (uint32_t spin = 0; spin < kServerMaxSpins; spin++) {
-        const u64 d = __hip_atomic_load(door, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-        if (d == (u64)i + 1u) {
-          go = 1;
+  __shared__ uint32_t s_cmd, s_flags;
+  Ctl *ctl = a.ctl;
+  const uint32_t t = threadIdx.x, lane = t & 63u;
+  uint32_t i = first;   // meaningful in wave 0
+  bool any_ovf = false;  // ditto
+  for (;;) {
+    if (t < 64u) {
+      uint32_t cmd = kCmdExit;
+      for (; i < count; i++) {
+        uint32_t go = 0;
+        if (lane == 0) {
+          const u64 t0 = wall_clock64();
+          // the wall clock bounds the wait; the iteration bound (each iteration reads host
+          // memory, at least ~1 us) ends it even if the clock stood still
+          for (uint32_t spin = 0; spin < kServerMaxSpins; spin++) {
+            const u64 d = __hip_atomic_load(door, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            if (d == (u64)i + 1u) {
+              go = 1;
+              break;
+            }
+            if (d == kDoorStop || wall_clock64() - t0 > idle_ticks) break;
+            __builtin_amdgcn_s_sleep(2);
+          }
+        }
+        if (!__shfl(go, 0, 64)) break;
+        // earlier requests changed state through L2 atomics: drop this CU's cached lines
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const bool act = lane < 2u;
+        uint32_t u = 0, v = 0;
+        if (act) {
+          u = src[i];
+          v = dst[i];
+        }
+        const uint32_t ring = ld_agent32(&ctl->cur), stamp = ld_agent32(&ctl->stamp);
+        if (__ballot(act && (u >= n || v >= n))) {
+          if (lane == 0) {
+            atomicOr(&ctl->err, kErrRange);
+            publish_fast(m, kFastErr, seq0 + (i - first) + 1u);
+          }
           break;
         }
-        if (d == kDoorStop || wall_clock64() - t0 > idle_ticks) break;
-        __builtin_amdgcn_s_sleep(2);
+        bool ovfl = false;
+        const bool pushed = apply_half<W>(a, u, v, lane & 1u, ring, stamp, ovf, ovf_cap, act,
+                                          &ovfl);
+        any_ovf = __ballot(ovfl) != 0ull;
+        if (__ballot(pushed)) {
+          if (lane == 0) {
+            st_agent32(&ctl->heavy[0], 0u);
+            st_agent32(&ctl->heavy[1], 0u);
+          }
+          cmd = kCmdPropagate;
+          break;
+        }
+        if (lane == 0) publish_fast(m, any_ovf ? kFastOvf : 0u, seq0 + (i - first) + 1u);
+        if (any_ovf) break;
       }
-      s_go = go;
+      if (t == 0) s_cmd = cmd;
     }
     __syncthreads();
-    if (!s_go) return;
-    // the previous request's atomics went to L2: drop this CU's cached lines before reading
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    const uint32_t flags = insert_small_body<W>(a, src + i, dst + i, 1u, n, ovf, ovf_cap);
-    if (threadIdx.x == 0) {
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (s_cmd == kCmdExit) return;
+    // request i queued vertices: the whole workgroup propagates
+    local_rounds_body<W>(a);
+    __syncthreads();
+    if (t == 0) {
+      uint32_t flags = any_ovf ? kFastOvf : 0u;
+      if (ld_agent32(&ctl->fsize[ld_agent32(&ctl->cur)])) flags |= kFastPending;
       publish_fast(m, flags, seq0 + (i - first) + 1u);
+      s_flags = flags;
     }
-    if (flags) return;
+    __syncthreads();
+    if (s_flags) return;
+    i++;
   }
 }
 
