@@ -515,6 +515,8 @@ def main():
                         "insert_vertices_expanded": ins_expanded,
                         "csr_regrows": s_ins["csr_regrows"],
                         "bfs_edges": s_q["bfs_edges"], "bfs_vertices": s_q["bfs_vertices"]},
+        "insert_device_us_per_request": (s_ins["server_busy_us"] / s_ins["server_requests"]
+                                         if s_ins["server_requests"] else None),
         "insert_launch_per_request": per_request,
         "batched": batched_res,
         "serving": serving_res,

@@ -1164,6 +1164,10 @@ dbl_status dbl_get_stats(const dbl_index *ix_c, dbl_stats *out) {
   out->bfs_vertices = bv;
   out->bfs_edges = be;
   out->bfs_heavy = heavy;
+  u64 sc[2] = {0, 0};
+  CK(hipMemcpy(sc, ix->ctl->ctr + dbl::kCtrServerTicks, sizeof(sc), hipMemcpyDeviceToHost));
+  out->server_requests = sc[1];
+  out->server_busy_us = (double)sc[0] * 1000.0 / (double)ix->clock_khz;
   return DBL_OK;
 }
 

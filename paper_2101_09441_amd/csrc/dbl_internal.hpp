@@ -41,13 +41,10 @@ struct Csr {
   uint32_t *col;
 };
 
+// Counters in the control block (written by one thread at a time).
 enum CtrIdx : uint32_t {
-  kCtrExpanded = 0,
-  kCtrRelaxed = 1,
-  kCtrBfsVert = 2,
-  kCtrBfsEdge = 3,
-  kCtrClass0 = 4,  // 4..10: query classes
-  kCtrQueries = 11,
+  kCtrServerTicks = 0,  // device wall-clock ticks the request server spent on requests
+  kCtrServerReqs = 1,   // requests it published
   kCtrCount = 16
 };
 

@@ -970,6 +970,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_insert_server(
   const uint32_t t = threadIdx.x, lane = t & 63u;
   uint32_t i = first;   // meaningful in wave 0
   bool any_ovf = false;  // ditto
+  u64 t_go = 0, busy = 0, served = 0;  // meaningful in thread 0
   for (;;) {
     if (t < 64u) {
       uint32_t cmd = kCmdExit;
@@ -990,6 +991,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_insert_server(
           }
         }
         if (!__shfl(go, 0, 64)) break;
+        if (lane == 0) t_go = wall_clock64();
         // earlier requests changed state through L2 atomics: drop this CU's cached lines
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         const bool act = lane < 2u;
@@ -1018,10 +1020,20 @@ __global__ __launch_bounds__(kLocalThreads) void k_insert_server(
           cmd = kCmdPropagate;
           break;
         }
-        if (lane == 0) publish_fast(m, any_ovf ? kFastOvf : 0u, seq0 + (i - first) + 1u);
+        if (lane == 0) {
+          publish_fast(m, any_ovf ? kFastOvf : 0u, seq0 + (i - first) + 1u);
+          busy += wall_clock64() - t_go;
+          served++;
+        }
         if (any_ovf) break;
       }
-      if (t == 0) s_cmd = cmd;
+      if (t == 0) {
+        s_cmd = cmd;
+        if (cmd == kCmdExit) {
+          ctl->ctr[kCtrServerTicks] += busy;
+          ctl->ctr[kCtrServerReqs] += served;
+        }
+      }
     }
     __syncthreads();
     if (s_cmd == kCmdExit) return;
@@ -1032,7 +1044,13 @@ __global__ __launch_bounds__(kLocalThreads) void k_insert_server(
       uint32_t flags = any_ovf ? kFastOvf : 0u;
       if (ld_agent32(&ctl->fsize[ld_agent32(&ctl->cur)])) flags |= kFastPending;
       publish_fast(m, flags, seq0 + (i - first) + 1u);
+      busy += wall_clock64() - t_go;
+      served++;
       s_flags = flags;
+      if (flags) {
+        ctl->ctr[kCtrServerTicks] += busy;
+        ctl->ctr[kCtrServerReqs] += served;
+      }
     }
     __syncthreads();
     if (s_flags) return;
