@@ -19,6 +19,7 @@
  */
 #include <math.h>
 #include <stdint.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -485,6 +486,8 @@ int dblgen_rmat_large(uint32_t scale, uint64_t seed, double a, double b, double 
     pthread_create(&th[t], NULL, par_draw_worker, &jobs[t]);
   }
   for (uint32_t t = 0; t < threads; t++) pthread_join(th[t], NULL);
+  fprintf(stderr, "[dblgen] %llu draws done\n", (unsigned long long)draws);
+  fflush(stderr);
   /* bucket by the top bits of the source id (ids are relabelled at random, so buckets are
      balanced) and sort each bucket */
   const uint32_t shift = 32 + scale - bbits;
@@ -503,6 +506,8 @@ int dblgen_rmat_large(uint32_t scale, uint64_t seed, double a, double b, double 
     pthread_create(&th[t], NULL, par_sort_worker, &sj[t]);
   }
   for (uint32_t t = 0; t < threads; t++) pthread_join(th[t], NULL);
+  fprintf(stderr, "[dblgen] buckets sorted\n");
+  fflush(stderr);
   uint64_t w = 0;
   for (uint32_t k = 0; k < nb; k++) {
     const uint64_t *kb = bkeys + bstart[k];
@@ -514,6 +519,8 @@ int dblgen_rmat_large(uint32_t scale, uint64_t seed, double a, double b, double 
     }
   }
   *m = w;
+  fprintf(stderr, "[dblgen] %llu distinct edges\n", (unsigned long long)w);
+  fflush(stderr);
   /* insertion edges: later chunks, skipping loops, existing edges and repeats */
   int rc = 0;
   if (n_ins) {

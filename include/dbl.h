@@ -91,6 +91,9 @@ typedef struct {
   /* Kernel kinds to time from the build on, as the argument of dbl_time_kernels (NULL = none);
      lets the build's own propagation rounds be timed. */
   const char *time_kernels;
+  /* Initial dbl_tuning.pull_threshold, so that the build's own rounds follow it (default 128;
+     0 = push only). */
+  uint32_t pull_threshold;
 } dbl_options;
 
 /* Which labels a query may use (the ablations of Table 4). */
@@ -253,6 +256,10 @@ typedef struct {
                                   memory; 0: one launch per request */
   uint32_t server_idle_us;     /* a server launch ends after this long without a request and is
                                   started again by the next one (0..10^7; default 200000) */
+  uint32_t pull_threshold;     /* a grid propagation round pulls a direction (every vertex ORs in
+                                  its frontier neighbours' labels) when the frontier would push at
+                                  least pull_threshold / 1024 of that direction's edges, and
+                                  pushes otherwise; 0 = always push (default 128) */
 } dbl_tuning;
 
 dbl_status dbl_get_tuning(const dbl_index *ix, dbl_tuning *out);

@@ -46,6 +46,7 @@ class DblOptions(ctypes.Structure):
         ("landmark_rank", ctypes.c_uint32),
         ("leaf_threshold", ctypes.c_uint64),
         ("time_kernels", ctypes.c_char_p),
+        ("pull_threshold", ctypes.c_uint32),
     ]
 
 
@@ -77,6 +78,7 @@ class DblTuning(ctypes.Structure):
         ("bfs_slots", ctypes.c_uint32),
         ("insert_server", ctypes.c_uint32),
         ("server_idle_us", ctypes.c_uint32),
+        ("pull_threshold", ctypes.c_uint32),
     ]
 
 
@@ -246,7 +248,7 @@ class Index:
               slack_fraction: float = 0.25, slack_min: int = 4, bfs_slots: int = 0,
               bfs_queue_cap: int = 0, edges_unique: bool = False, landmark_rank: int = 0,
               leaf_threshold: int = 0, time_kernels: Optional[str] = None,
-              stream=None) -> "Index":
+              pull_threshold: Optional[int] = None, stream=None) -> "Index":
         lib = load_library()
         src, dst = _ids(src, "src"), _ids(dst, "dst")
         if src.numel() != dst.numel():
@@ -279,6 +281,8 @@ class Index:
         opt.edges_unique = 1 if edges_unique else 0
         opt.landmark_rank = landmark_rank
         opt.leaf_threshold = leaf_threshold
+        if pull_threshold is not None:
+            opt.pull_threshold = pull_threshold
         if time_kernels:
             tk = time_kernels.encode()
             keep.append(tk)
@@ -424,7 +428,7 @@ class Index:
 
     def set_tuning(self, **kw) -> None:
         """Change tuning fields (small_batch, local_max_frontier, local_max_edges, round_grid,
-        bfs_slots, insert_server, server_idle_us); results never change."""
+        bfs_slots, insert_server, server_idle_us, pull_threshold); results never change."""
         cur = self.tuning()
         bad = set(kw) - set(cur)
         if bad:

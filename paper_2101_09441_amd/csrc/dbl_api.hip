@@ -54,8 +54,11 @@ struct dbl_index {
   u64 *lab = nullptr;
   uint32_t *fq[3] = {nullptr, nullptr, nullptr};
   uint32_t *inq = nullptr;
-  u64 *heavy_list = nullptr;
+  u64 *heavy_list = nullptr;  // two lists of heavy_cap entries: push chunks, pull chunks
   uint64_t heavy_cap = 0;
+  u64 *fbm = nullptr;         // frontier bitmap of pull rounds (2 bits per vertex)
+  uint64_t fbm_words = 0;
+  uint64_t pull_expanded = 0;  // frontier entries expanded by pull rounds
   Ctl *ctl = nullptr;
   dbl::Mirror *mirror = nullptr;  // pinned, device-mapped host memory written by the device
   u64 *door = nullptr;            // pinned, device-mapped host memory written by the host
@@ -76,6 +79,7 @@ struct dbl_index {
   uint32_t local_max_frontier = dbl::kLocalMaxFrontier, local_max_edges = dbl::kLocalMaxEdges;
   uint32_t round_grid = dbl::kRoundGridMax;
   uint32_t insert_server = 1;  // dbl_insert_edges_each through the request server
+  uint32_t pull_threshold = 128;  // pull a direction when its push edges >= this/1024 of its edges
   // query contexts: the default one and those created by callers (guarded by ctx_mu)
   uint32_t slots_opt = 0, qcap_opt = 0;
   dbl_query_ctx *qctx = nullptr;
@@ -224,7 +228,9 @@ dbl::PropArgs prop_args(const dbl_index *ix) {
   for (int i = 0; i < 3; i++) a.fq[i] = ix->fq[i];
   a.inq = ix->inq;
   a.heavy_list = ix->heavy_list;
+  a.pheavy_list = ix->heavy_list ? ix->heavy_list + ix->heavy_cap : nullptr;
   a.heavy_cap = ix->heavy_cap;
+  a.fbm = ix->fbm;
   a.pcnt = ix->pcnt;
   a.local_max_frontier = ix->local_max_frontier;
   a.local_max_edges = ix->local_max_edges;
@@ -322,13 +328,17 @@ dbl_status ensure_heavy_cap(dbl_index *ix) {
   const uint64_t need = (ix->f_total + ix->r_total) / 2048 + 1024;
   if (need <= ix->heavy_cap) return DBL_OK;
   dfree(ix->heavy_list);
-  CKS(dalloc(&ix->heavy_list, need));
+  CKS(dalloc(&ix->heavy_list, 2 * need));
   ix->heavy_cap = need;
   return DBL_OK;
 }
 
-// Grid rounds until the pending frontier is empty. `group` rounds are enqueued between reads of
-// the control block; a round that finds an empty frontier does nothing.
+// Grid rounds until the pending frontier is empty.
+// With pulls enabled, every round starts with a frontier scan; after reading its counts the
+// host pulls each direction whose frontier would push at least pull_threshold / 1024 of the
+// direction's edges and pushes the rest (one control-block read per round). Without pulls,
+// `group` push rounds are enqueued between reads of the control block; a round that finds an
+// empty frontier does nothing.
 // `fresh`: ix->hs already holds the status after the last queued work.
 dbl_status grid_propagate(dbl_index *ix, hipStream_t s, uint32_t group, uint64_t *rounds,
                           bool fresh) {
@@ -346,11 +356,44 @@ dbl_status grid_propagate(dbl_index *ix, hipStream_t s, uint32_t group, uint64_t
       CKS(set_ctl_u32(ix, offsetof(Ctl, stamp), 1u, s));
       stamp = 1;
     }
-    dbl::PropArgs a = prop_args(ix);
-    uint32_t ring = cur;
     const uint32_t gmax = ix->round_grid;
     uint32_t grid = (uint32_t)std::min<uint64_t>(gmax, std::max<uint64_t>(std::min(64u, gmax),
                                                                           (fsz + 255) / 256));
+    if (ix->pull_threshold) {
+      const uint64_t words = (2ull * ix->n + 63) / 64;
+      if (words > ix->fbm_words) {
+        dfree(ix->fbm);
+        ix->fbm = nullptr;
+        ix->fbm_words = 0;
+        CKS(dalloc(&ix->fbm, words));
+        ix->fbm_words = words;
+      }
+      dbl::PropArgs a = prop_args(ix);
+      CK(dbl::launch_frontier_scan(a, cur, stamp, words, s));
+      CKS(sync_ctl(ix, s));
+      uint32_t pull = 0;
+      for (uint32_t d = 0; d < 2; d++) {
+        const uint64_t edges = d ? ix->r_total : ix->f_total;
+        if (ix->hs.dstat[2 + d] && ix->hs.dstat[2 + d] * 1024 >= (u64)ix->pull_threshold * edges) {
+          pull |= 1u << d;
+          ix->pull_expanded += ix->hs.dstat[d];
+        }
+      }
+      const uint64_t pushed = (pull & 1 ? 0 : ix->hs.dstat[0]) + (pull & 2 ? 0 : ix->hs.dstat[1]);
+      {
+        Timed tm(ix, kTRound, s);
+        if (pull) {
+          const uint64_t rows = (uint64_t)ix->n * (uint32_t)__builtin_popcount(pull);
+          CK(dbl::launch_pull(a, ix->n, pull, cur, stamp,
+                              (uint32_t)std::min<uint64_t>(gmax, (rows + 255) / 256), s));
+        }
+        if (pushed) CK(dbl::launch_round(a, cur, stamp, grid, s, pull, false));
+      }
+      *rounds += 1;
+      continue;
+    }
+    dbl::PropArgs a = prop_args(ix);
+    uint32_t ring = cur;
     for (uint32_t g = 0; g < group; g++) {
       Timed tm(ix, kTRound, s);
       CK(dbl::launch_round(a, ring, stamp, grid, s));
@@ -875,6 +918,7 @@ void dbl_default_options(dbl_options *opt) {
   opt->bl_bits = 64;
   opt->slack_fraction = 0.25f;
   opt->slack_min = 4;
+  opt->pull_threshold = 128;
 }
 
 const char *dbl_status_str(dbl_status s) {
@@ -901,6 +945,7 @@ dbl_status dbl_build(uint32_t n, uint64_t m, const uint32_t *d_src, const uint32
     return DBL_ERR_INVALID_ARG;
   if (!(o.slack_fraction >= 0.0f) || o.slack_fraction > 16.0f) return DBL_ERR_INVALID_ARG;
   if (o.landmark_rank > 3) return DBL_ERR_INVALID_ARG;
+  if (o.pull_threshold > 1u << 20) return DBL_ERR_INVALID_ARG;
   const uint32_t k = std::min<uint32_t>(o.num_landmarks, n);
   if (o.landmarks) {
     std::vector<uint32_t> seen(o.landmarks, o.landmarks + k);
@@ -930,6 +975,7 @@ dbl_status dbl_build(uint32_t n, uint64_t m, const uint32_t *d_src, const uint32
   ix->slack_frac = o.slack_fraction;
   ix->slack_min = o.slack_min;
   ix->slots_opt = o.bfs_slots;
+  ix->pull_threshold = o.pull_threshold;
   ix->qcap_opt = o.bfs_queue_cap;
   hipStream_t s = (hipStream_t)stream;
   if (o.time_kernels) {
@@ -1142,6 +1188,7 @@ dbl_status dbl_get_stats(const dbl_index *ix_c, dbl_stats *out) {
   out->build_rounds = ix->build_rounds;
   out->insert_calls = ix->insert_calls;
   out->insert_rounds = ix->insert_rounds;
+  out->vertices_expanded = ix->pull_expanded;
   for (uint32_t b = 0; b < dbl::kPropCtrSlots; b++) {
     out->vertices_expanded += pc[2 * b];
     out->edges_relaxed += pc[2 * b + 1];
@@ -1287,6 +1334,7 @@ dbl_status dbl_get_tuning(const dbl_index *ix, dbl_tuning *out) {
   out->round_grid = ix->round_grid;
   out->insert_server = ix->insert_server;
   out->server_idle_us = ix->server_idle_us;
+  out->pull_threshold = ix->pull_threshold;
   out->bfs_slots = ix->qctx ? ix->qctx->slots : (ix->slots_opt ? ix->slots_opt : 1024);
   return DBL_OK;
 }
@@ -1295,7 +1343,7 @@ dbl_status dbl_set_tuning(dbl_index *ix, const dbl_tuning *t) {
   if (!ix || !t) return DBL_ERR_INVALID_ARG;
   if (t->small_batch > dbl::kSmallBatchMax || t->round_grid == 0 ||
       t->round_grid > dbl::kRoundGridMax || t->bfs_slots > (1u << 16) || t->insert_server > 1 ||
-      t->server_idle_us > 10000000)
+      t->server_idle_us > 10000000 || t->pull_threshold > 1u << 20)
     return DBL_ERR_INVALID_ARG;
   DeviceGuard dg(ix->device);
   ix->small_batch = t->small_batch;
@@ -1304,6 +1352,7 @@ dbl_status dbl_set_tuning(dbl_index *ix, const dbl_tuning *t) {
   ix->round_grid = t->round_grid;
   ix->insert_server = t->insert_server;
   ix->server_idle_us = t->server_idle_us;
+  ix->pull_threshold = t->pull_threshold;
   const uint32_t slots = t->bfs_slots ? std::max<uint32_t>(4, (t->bfs_slots + 3) / 4 * 4) : 0;
   if (slots && (!ix->qctx || ix->qctx->slots != slots)) {
     // rebuild the index's own query context with the new slot count (its counters are kept)
@@ -1338,6 +1387,7 @@ void dbl_destroy(dbl_index *ix) {
   for (int i = 0; i < 3; i++) dfree(ix->fq[i]);
   dfree(ix->inq);
   dfree(ix->heavy_list);
+  dfree(ix->fbm);
   dfree(ix->ctl);
   if (ix->mirror) (void)hipHostFree((void *)ix->mirror);
   if (ix->door) (void)hipHostFree((void *)ix->door);

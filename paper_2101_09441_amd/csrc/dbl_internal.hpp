@@ -45,6 +45,8 @@ struct Csr {
 enum CtrIdx : uint32_t {
   kCtrServerTicks = 0,  // device wall-clock ticks the request server spent on requests
   kCtrServerReqs = 1,   // requests it published
+  kCtrFrontEntries = 2, // 2, 3: frontier entries per direction (frontier scan)
+  kCtrFrontEdges = 4,   // 4, 5: edges a push of those entries would scan, per direction
   kCtrCount = 16
 };
 
@@ -62,7 +64,7 @@ struct Ctl {
   uint32_t found;       // grid BFS: target reached
   uint32_t local_rounds;
   uint32_t bfs_done;    // BFS waves finished (the last one publishes the status)
-  uint32_t pad[1];
+  uint32_t pheavy;      // chunks of high-degree rows queued for the pull round
   unsigned long long ctr[kCtrCount];
 };
 
@@ -75,6 +77,7 @@ struct Mirror {
   uint32_t fsize[3];
   uint32_t ovf_count, und_count, bfs_heavy, found;
   uint32_t pad[5];
+  unsigned long long dstat[4];  // frontier scan: entries and push edges per direction
   // Fast path of one small insertion: sequence number (low 32 bits) and flags (high 32 bits)
   // in one store; the host reads the other fields only when a flag is set.
   unsigned long long fast;
@@ -159,14 +162,27 @@ struct PropArgs {
   uint32_t *fq[3];  // frontier ring
   uint32_t *inq;    // [2n] stamp of the frontier each (vertex, direction) is queued in
   unsigned long long *heavy_list;
+  unsigned long long *pheavy_list;  // chunks of the pull round (same capacity)
   uint64_t heavy_cap;
+  unsigned long long *fbm;          // frontier bitmap of the pull round: bit 2x + direction
   unsigned long long *pcnt;  // [kPropCtrSlots * 2] per-block (expanded, relaxed) counters
   uint32_t local_max_frontier, local_max_edges;
   Ctl *ctl;
 };
-// one grid round: expand the frontier at ring `ring` (entries stamped `stamp`)
+// one grid round: expand the frontier at ring `ring` (entries stamped `stamp`). skip_mask: the
+// directions (bit d) another kernel handles this round; bookkeep: advance ctl->cur / stamp (off
+// when the frontier scan has done it)
 hipError_t launch_round(const PropArgs &a, uint32_t ring, uint32_t stamp, uint32_t grid,
-                        hipStream_t s);
+                        hipStream_t s, uint32_t skip_mask = 0, bool bookkeep = true);
+// Direction-optimised rounds. frontier_scan: clear the bitmap (fbm_words words) and the
+// per-direction counters, mark the frontier, count entries and push edges per direction and
+// advance ctl->cur / stamp. pull: for the directions in dmask, every vertex ORs in the labels
+// of its frontier neighbours (Pre for forward, Suc for backward) and joins the next frontier
+// if it grew.
+hipError_t launch_frontier_scan(const PropArgs &a, uint32_t ring, uint32_t stamp,
+                                uint64_t fbm_words, hipStream_t s);
+hipError_t launch_pull(const PropArgs &a, uint32_t n, uint32_t dmask, uint32_t ring,
+                       uint32_t stamp, uint32_t grid, hipStream_t s);
 // single-workgroup rounds starting from ctl->cur / ctl->stamp; publishes the status to m (if
 // not null) with sequence number seq when done
 hipError_t launch_local_rounds(const PropArgs &a, Mirror *m, uint32_t seq, hipStream_t s);

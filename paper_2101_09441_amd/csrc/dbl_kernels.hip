@@ -230,6 +230,9 @@ __device__ void publish_status(Ctl *ctl, Mirror *m, uint32_t seq) {
   st_sys32(&m->und_count, ld_agent32(&ctl->und_count));
   st_sys32(&m->bfs_heavy, ld_agent32(&ctl->bfs_heavy));
   st_sys32(&m->found, ld_agent32(&ctl->found));
+  for (int i = 0; i < 4; i++)
+    __hip_atomic_store(&m->dstat[i], ld_agent(&ctl->ctr[kCtrFrontEntries + i]), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_SYSTEM);
   __hip_atomic_store(&m->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
@@ -619,19 +622,23 @@ __device__ __forceinline__ void expand_tile(const PropArgs &a, const uint32_t *f
                                             uint32_t nstamp, u64 *heavy_list,
                                             uint32_t *heavy_cnt, bool coherent,
                                             uint32_t *s_start, u64 *s_off, Half<W> *s_lab,
-                                            uint32_t *s_ent, uint32_t *s_wsum, u64 &relaxed) {
+                                            uint32_t *s_ent, uint32_t *s_wsum, u64 &relaxed,
+                                            u64 &expanded, uint32_t skip_mask) {
   const uint32_t t = threadIdx.x;
   const uint32_t i = beg + t;
   uint32_t d = 0;
+  bool mine = false;
   if (i < end) {
     const uint32_t ent = fq[i];
     const uint32_t dir = ent >> 31, x = ent & kIdMask;
+    mine = !((skip_mask >> dir) & 1u);
     const u64 *offp = dir ? a.r.off : a.f.off;
     const uint32_t* degp = dir ? a.r.deg : a.f.deg;
     const uint32_t* capp = dir ? a.r.cap : a.f.cap;
-    uint32_t dg = min(degp[x], capp[x]);
+    uint32_t dg = mine ? min(degp[x], capp[x]) : 0u;
     const u64 *lp = half_ptr<W>(a.L.lab, x, dir);
-    const Half<W> lv = coherent ? ld_half_agent<W>(lp) : ld_half<W>(lp);
+    Half<W> lv = {};
+    if (mine) lv = coherent ? ld_half_agent<W>(lp) : ld_half<W>(lp);
     if (heavy_list && dg > kHeavyDeg) {
       const uint32_t nch = (dg + kChunk - 1) / kChunk;
       const uint32_t hb = atomicAdd(heavy_cnt, nch);
@@ -647,7 +654,7 @@ __device__ __forceinline__ void expand_tile(const PropArgs &a, const uint32_t *f
   uint32_t total;
   const uint32_t ex = block_excl_scan<NT>(d, s_wsum, total);
   s_start[t] = ex;
-  __syncthreads();
+  const uint32_t nexp = (uint32_t)__syncthreads_count(mine);
   const uint32_t last = min((uint32_t)NT, end - beg) - 1u;
   for (uint32_t e = t; e < total; e += NT) {
     uint32_t lo = 0, hi = last;
@@ -663,12 +670,16 @@ __device__ __forceinline__ void expand_tile(const PropArgs &a, const uint32_t *f
     const bool push = ch && claim(&a.inq[2ull * y + dir], nstamp);
     wave_push(nq, ncnt, push, y | (ent & kDirBit));
   }
-  if (t == 0) relaxed += total;
+  if (t == 0) {
+    relaxed += total;
+    expanded += nexp;
+  }
   __syncthreads();
 }
 
 template <int W>
-__global__ __launch_bounds__(256) void k_round(PropArgs a, uint32_t ring, uint32_t stamp) {
+__global__ __launch_bounds__(256) void k_round(PropArgs a, uint32_t ring, uint32_t stamp,
+                                               uint32_t skip_mask, uint32_t bookkeep) {
   __shared__ uint32_t s_start[256];
   __shared__ u64 s_off[256];
   __shared__ Half<W> s_lab[256];
@@ -677,7 +688,7 @@ __global__ __launch_bounds__(256) void k_round(PropArgs a, uint32_t ring, uint32
   Ctl *ctl = a.ctl;
   const uint32_t nring = ring == 2u ? 0u : ring + 1u;
   const uint32_t fsz = ctl->fsize[ring];
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (bookkeep && blockIdx.x == 0 && threadIdx.x == 0) {
     ctl->fsize[nring == 2u ? 0u : nring + 1u] = 0;
     ctl->heavy[(stamp + 1u) & 1u] = 0;
     ctl->cur = nring;
@@ -686,12 +697,11 @@ __global__ __launch_bounds__(256) void k_round(PropArgs a, uint32_t ring, uint32
   u64 relaxed = 0, expanded = 0;
   for (uint32_t beg = blockIdx.x * 256u; beg < fsz; beg += gridDim.x * 256u) {
     const uint32_t end = min(beg + 256u, fsz);
-    expanded += end - beg;
     expand_tile<256, W>(a, a.fq[ring], beg, end, a.fq[nring], &ctl->fsize[nring], stamp + 1u,
                      a.heavy_list, &ctl->heavy[stamp & 1u], false, s_start, s_off, s_lab, s_ent,
-                     s_wsum, relaxed);
+                     s_wsum, relaxed, expanded, skip_mask);
   }
-  if (threadIdx.x == 0 && expanded) {
+  if (threadIdx.x == 0 && (expanded | relaxed)) {
     a.pcnt[2 * blockIdx.x] += expanded;
     a.pcnt[2 * blockIdx.x + 1] += relaxed;
   }
@@ -731,12 +741,265 @@ __global__ __launch_bounds__(256) void k_heavy(PropArgs a, uint32_t hidx, uint32
 }
 
 hipError_t launch_round(const PropArgs &a, uint32_t ring, uint32_t stamp, uint32_t grid,
-                        hipStream_t s) {
+                        hipStream_t s, uint32_t skip_mask, bool bookkeep) {
   if (grid > kRoundGridMax) grid = kRoundGridMax;
-  DBL_LAUNCH_W(a.L.words, k_round, dim3(grid), dim3(256), s, a, ring, stamp);
+  DBL_LAUNCH_W(a.L.words, k_round, dim3(grid), dim3(256), s, a, ring, stamp, skip_mask,
+               bookkeep ? 1u : 0u);
   const uint32_t nring = ring == 2u ? 0u : ring + 1u;
   DBL_LAUNCH_W(a.L.words, k_heavy, dim3(kHeavyGrid), dim3(256), s, a, stamp & 1u, nring,
                stamp + 1u);
+  return hipGetLastError();
+}
+
+// ---- direction-optimised rounds
+// A round whose frontier covers a large share of a direction's edges can run as a pull: every
+// vertex y ORs in the labels of its neighbours p that are in the frontier (Pre(y) for the
+// forward labels, Suc(y) for the backward ones). The result equals the push round's: each
+// frontier edge is relaxed once either way, and labels only grow. A pull reads the target
+// rows in order, reads source labels only for frontier edges, and writes each grown label once
+// without atomics (a row has one owner thread), so it moves far less memory per relaxation than
+// scattered pushes with their atomics and queue claims.
+
+__device__ __forceinline__ bool in_frontier(const u64 *fbm, uint32_t x, uint32_t dir) {
+  const u64 b = 2ull * x + dir;
+  return (fbm[b >> 6] >> (b & 63u)) & 1ull;
+}
+
+__global__ __launch_bounds__(256) void k_frontier_scan(PropArgs a, uint32_t ring,
+                                                       uint32_t stamp) {
+  __shared__ u64 s_red[4][4];
+  Ctl *ctl = a.ctl;
+  const uint32_t fsz = ctl->fsize[ring];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    // what k_round does at its start: the pending frontier moves on to the next ring
+    const uint32_t nring = ring == 2u ? 0u : ring + 1u;
+    ctl->fsize[nring == 2u ? 0u : nring + 1u] = 0;
+    ctl->heavy[(stamp + 1u) & 1u] = 0;
+    ctl->pheavy = 0;
+    ctl->cur = nring;
+    ctl->stamp = stamp + 1u;
+  }
+  u64 v[4] = {0, 0, 0, 0};  // entries fwd, bwd, push edges fwd, bwd
+  for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < fsz; i += gridDim.x * 256u) {
+    const uint32_t e = a.fq[ring][i];
+    const uint32_t d = e >> 31, x = e & kIdMask;
+    const uint32_t dg = d ? min(a.r.deg[x], a.r.cap[x]) : min(a.f.deg[x], a.f.cap[x]);
+    const u64 b = 2ull * x + d;
+    atomicOr(&a.fbm[b >> 6], 1ull << (b & 63u));
+    if (d) {
+      v[1] += 1;
+      v[3] += dg;
+    } else {
+      v[0] += 1;
+      v[2] += dg;
+    }
+  }
+  const uint32_t lane = __lane_id(), w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o, 64);
+    if (lane == 0) s_red[w][k] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    const u64 sum = s_red[0][threadIdx.x] + s_red[1][threadIdx.x] + s_red[2][threadIdx.x] +
+                    s_red[3][threadIdx.x];
+    if (sum) atomicAdd(&ctl->ctr[kCtrFrontEntries + threadIdx.x], sum);
+  }
+}
+
+hipError_t launch_frontier_scan(const PropArgs &a, uint32_t ring, uint32_t stamp,
+                                uint64_t fbm_words, hipStream_t s) {
+  hipError_t e = launch_fill_u64(a.fbm, 0ull, fbm_words, s);
+  if (e != hipSuccess) return e;
+  e = launch_fill_u64(&a.ctl->ctr[kCtrFrontEntries], 0ull, 4, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_frontier_scan, dim3(kRoundGridMax), dim3(256), 0, s, a, ring, stamp);
+  return hipGetLastError();
+}
+
+// Sum of a per-thread 64-bit count over a block of 256 threads; the result is valid in thread 0.
+__device__ __forceinline__ u64 block_sum256(u64 v, u64 *s_tmp) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if (__lane_id() == 0) s_tmp[threadIdx.x >> 6] = v;
+  __syncthreads();
+  const u64 r = s_tmp[0] + s_tmp[1] + s_tmp[2] + s_tmp[3];
+  __syncthreads();
+  return r;
+}
+
+// OR `v` (2W words) into the LDS accumulator of row `row` for every lane that holds a value.
+// When the whole wave works on one row (long rows) the wave reduces first and one lane adds.
+template <int W>
+__device__ __forceinline__ void acc_or(u64 (*s_acc)[2 * W], uint32_t row, bool act, bool hit,
+                                       Half<W> v) {
+  const uint32_t lane = __lane_id();
+  const uint32_t row0 = __shfl(row, 0, 64);
+  const bool uniform = __ballot(act && row != row0) == 0ull && __shfl(act ? 1u : 0u, 0, 64);
+  if (uniform) {
+#pragma unroll
+    for (int i = 0; i < 2 * W; i++) {
+      u64 x = hit ? v.w[i] : 0ull;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) x |= __shfl_xor(x, o, 64);
+      if (lane == 0 && x) atomicOr(&s_acc[row0][i], x);
+    }
+  } else if (hit) {
+#pragma unroll
+    for (int i = 0; i < 2 * W; i++)
+      if (v.w[i]) atomicOr(&s_acc[row][i], v.w[i]);
+  }
+}
+
+// Pull rows: 256 rows per tile, the rows' edges laid end to end and taken one per thread (as
+// in expand_tile). Rows longer than kHeavyDeg go to k_pull_heavy in chunks.
+template <int W>
+__global__ __launch_bounds__(256) void k_pull(PropArgs a, uint32_t n, uint32_t dmask,
+                                              uint32_t nring, uint32_t nstamp) {
+  __shared__ uint32_t s_start[256];
+  __shared__ u64 s_off[256];
+  __shared__ uint32_t s_row[256];
+  __shared__ uint32_t s_wsum[4];
+  __shared__ u64 s_acc[256][2 * W];
+  Ctl *ctl = a.ctl;
+  const uint32_t t = threadIdx.x;
+  const uint32_t ndir = __popc(dmask);
+  const uint32_t d_only = (dmask & 1u) ? 0u : 1u;
+  const uint64_t rows = (uint64_t)n * ndir;
+  u64 relaxed = 0;
+  for (uint64_t beg = (uint64_t)blockIdx.x * 256u; beg < rows;
+       beg += (uint64_t)gridDim.x * 256u) {
+    const uint64_t r = beg + t;
+    const bool act = r < rows;
+    uint32_t y = 0, d = 0, dg = 0;
+    if (act) {
+      d = ndir == 2 ? (r >= n ? 1u : 0u) : d_only;
+      y = (uint32_t)(r - (ndir == 2 && r >= n ? (uint64_t)n : 0ull));
+      const Csr g = d ? a.f : a.r;  // neighbours the labels come from
+      dg = min(g.deg[y], g.cap[y]);
+      if (dg > kHeavyDeg) {
+        const uint32_t nch = (dg + kChunk - 1) / kChunk;
+        const uint32_t hb = atomicAdd(&ctl->pheavy, nch);
+        for (uint32_t c = 0; c < nch; c++)
+          if (hb + c < a.heavy_cap)
+            a.pheavy_list[hb + c] = ((u64)(y | (d << 31)) << 32) | c;
+        dg = 0;
+      }
+      s_off[t] = g.off[y];
+    }
+    s_row[t] = y | (d << 31);
+#pragma unroll
+    for (int i = 0; i < 2 * W; i++) s_acc[t][i] = 0ull;
+    uint32_t total;
+    const uint32_t ex = block_excl_scan<256>(dg, s_wsum, total);
+    s_start[t] = ex;
+    __syncthreads();
+    const uint32_t last = (uint32_t)min<uint64_t>(256u, rows - beg) - 1u;
+    for (uint32_t e0 = 0; e0 < total; e0 += 256u) {
+      const uint32_t e = e0 + t;
+      const bool eact = e < total;
+      uint32_t lo = 0;
+      bool hit = false;
+      Half<W> lv = {};
+      if (eact) {
+        uint32_t hi = last;
+        while (lo < hi) {
+          const uint32_t mid = (lo + hi + 1) >> 1;
+          if (s_start[mid] <= e) lo = mid; else hi = mid - 1;
+        }
+        const uint32_t rd = s_row[lo] >> 31;
+        const uint32_t *col = rd ? a.f.col : a.r.col;
+        const uint32_t p = col[s_off[lo] + (e - s_start[lo])];
+        if (in_frontier(a.fbm, p, rd)) {
+          hit = true;
+          lv = ld_half<W>(half_ptr<W>(a.L.lab, p, rd));
+          relaxed++;
+        }
+      }
+      acc_or<W>(s_acc, lo, eact, hit, lv);
+    }
+    __syncthreads();
+    bool push = false;
+    if (act && dg) {
+      u64 *wl = half_ptr<W>(a.L.lab, y, d);
+      const Half<W> cur = ld_half<W>(wl);
+      bool grew = false;
+#pragma unroll
+      for (int i = 0; i < 2 * W; i++) {
+        const u64 add = s_acc[t][i] & ~cur.w[i];
+        if (add) {
+          wl[i] = cur.w[i] | add;  // this thread is the row's only writer in this kernel
+          grew = true;
+        }
+      }
+      push = grew && claim(&a.inq[2ull * y + d], nstamp);
+    }
+    wave_push(a.fq[nring], &ctl->fsize[nring], push, y | (d << 31));
+    __syncthreads();
+  }
+  __shared__ u64 s_tmp[4];
+  relaxed = block_sum256(relaxed, s_tmp);
+  if (t == 0 && relaxed) a.pcnt[2 * blockIdx.x + 1] += relaxed;
+}
+
+template <int W>
+__global__ __launch_bounds__(256) void k_pull_heavy(PropArgs a, uint32_t nring,
+                                                    uint32_t nstamp) {
+  __shared__ u64 s_acc[1][2 * W];
+  Ctl *ctl = a.ctl;
+  uint32_t cnt = ctl->pheavy;
+  if (cnt > a.heavy_cap) cnt = (uint32_t)a.heavy_cap;
+  u64 relaxed = 0;
+  for (uint32_t item = blockIdx.x; item < cnt; item += gridDim.x) {
+    const u64 h = a.pheavy_list[item];
+    const uint32_t row = (uint32_t)(h >> 32), c = (uint32_t)h;
+    const uint32_t d = row >> 31, y = row & kIdMask;
+    const Csr g = d ? a.f : a.r;
+    const uint32_t dg = min(g.deg[y], g.cap[y]);
+    const uint32_t b = c * kChunk, e_end = min(dg, b + kChunk);
+    const u64 o = g.off[y];
+    if (threadIdx.x < 2 * W) s_acc[0][threadIdx.x] = 0ull;
+    __syncthreads();
+    for (uint32_t e0 = b; e0 < e_end; e0 += 256u) {
+      const uint32_t e = e0 + threadIdx.x;
+      bool hit = false;
+      Half<W> lv = {};
+      if (e < e_end) {
+        const uint32_t p = g.col[o + e];
+        if (in_frontier(a.fbm, p, d)) {
+          hit = true;
+          lv = ld_half<W>(half_ptr<W>(a.L.lab, p, d));
+          relaxed++;
+        }
+      }
+      acc_or<W>(s_acc, 0u, e < e_end, hit, lv);
+    }
+    __syncthreads();
+    bool push = false;
+    if (threadIdx.x == 0) {
+      Half<W> acc;
+#pragma unroll
+      for (int i = 0; i < 2 * W; i++) acc.w[i] = s_acc[0][i];
+      // chunks of one row run in different blocks: OR with atomics
+      push = relax<W>(half_ptr<W>(a.L.lab, y, d), acc) && claim(&a.inq[2ull * y + d], nstamp);
+    }
+    if (threadIdx.x < 64) wave_push(a.fq[nring], &ctl->fsize[nring], push, row);
+    __syncthreads();
+  }
+  __shared__ u64 s_tmp[4];
+  relaxed = block_sum256(relaxed, s_tmp);
+  if (threadIdx.x == 0 && relaxed) a.pcnt[2 * (kRoundGridMax + blockIdx.x) + 1] += relaxed;
+}
+
+hipError_t launch_pull(const PropArgs &a, uint32_t n, uint32_t dmask, uint32_t ring,
+                       uint32_t stamp, uint32_t grid, hipStream_t s) {
+  if (!dmask) return hipSuccess;
+  if (grid > kRoundGridMax) grid = kRoundGridMax;
+  const uint32_t nring = ring == 2u ? 0u : ring + 1u;
+  DBL_LAUNCH_W(a.L.words, k_pull, dim3(grid), dim3(256), s, a, n, dmask, nring, stamp + 1u);
+  DBL_LAUNCH_W(a.L.words, k_pull_heavy, dim3(kHeavyGrid), dim3(256), s, a, nring, stamp + 1u);
   return hipGetLastError();
 }
 
@@ -780,9 +1043,8 @@ __device__ void local_rounds_body(const PropArgs &a) {
       const uint32_t end = min(beg + kLocalThreads, fsz);
       expand_tile<kLocalThreads, W>(a, fq, beg, end, a.fq[nring], &ctl->fsize[nring], stamp + 1u,
                                  nullptr, nullptr, true, s_start, s_off, s_lab, s_ent, s_wsum,
-                                 relaxed);
+                                 relaxed, expanded, 0u);
     }
-    expanded += fsz;
     __syncthreads();
     ring = nring;
     stamp++;

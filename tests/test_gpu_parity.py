@@ -125,6 +125,50 @@ def test_families_insert_batches(name, gr):
     assert_queries_equal(g, o, u, v)
 
 
+# ------------------------------------------------------------------ push and pull rounds
+
+@pytest.mark.parametrize("pull", [0, 1, 1 << 20])
+@pytest.mark.parametrize("name,gr", FAMILIES, ids=[f[0] for f in FAMILIES])
+def test_pull_rounds_families(name, gr, pull):
+    """Build rounds forced to push only (0), to pull any direction with frontier edges (1), or
+    never to pull (2^20): labels and answers equal the oracle's."""
+    n, src, dst = gr
+    g = gpu_index(n, src, dst, num_landmarks=6, bl_bits=8, pull_threshold=pull)
+    o = oracle.OracleIndex(n, src, dst).build(k=6, kp=8)
+    assert_labels_equal(g, o, f"{name} pull {pull}")
+    u, v = all_pairs(n)
+    assert_queries_equal(g, o, u, v)
+
+
+@pytest.mark.parametrize("words", [1, 4])
+def test_pull_rounds_rmat_equal_counts(words):
+    """On a 2^16-vertex R-MAT graph with hub rows: the pulled build gives the oracle's labels,
+    and relaxes exactly the edges the pushed build relaxes (each frontier edge once per round,
+    either way). Then grid-round insertion batches with pulls (tiny single-workgroup bounds)."""
+    k = 64 if words == 1 else 200
+    w = dblgen.make_rmat_workload(f"pr{words}", 16, 21, draws=16 << 16, n_insert=30000,
+                                  insert_kind="rmat", n_query=50000, query_kind="mixed")
+    o = oracle.OracleIndex(w.n, w.src, w.dst).build(k=k, kp=k, threads=8)
+    stats = {}
+    for pull in (0, 1, 128):
+        g = gpu_index(w.n, w.src, w.dst, num_landmarks=k, bl_bits=k, pull_threshold=pull)
+        assert g.label_words() == words
+        assert_labels_equal(g, o, f"pull {pull}")
+        stats[pull] = g.stats()
+        g.close()
+    for pull in (1, 128):
+        assert stats[pull]["edges_relaxed"] == stats[0]["edges_relaxed"]
+        assert stats[pull]["vertices_expanded"] == stats[0]["vertices_expanded"]
+        assert stats[pull]["build_rounds"] <= stats[0]["build_rounds"]
+    g = gpu_index(w.n, w.src, w.dst, num_landmarks=k, bl_bits=k, pull_threshold=1)
+    g.set_tuning(small_batch=0, local_max_frontier=16, local_max_edges=256)
+    o.insert(w.ins_src, w.ins_dst)
+    for lo in range(0, 30000, 10000):
+        g.insert_edges(dev(w.ins_src[lo:lo + 10000]), dev(w.ins_dst[lo:lo + 10000]))
+    assert_labels_equal(g, o, "pulled insertion rounds")
+    assert_queries_equal(g, o, w.q_u, w.q_v)
+
+
 # ------------------------------------------------------------------ labels longer than 64 bits
 
 @pytest.mark.parametrize("k,kp,words", [(65, 2, 2), (128, 128, 2), (3, 256, 4), (200, 256, 4),
