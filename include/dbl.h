@@ -112,6 +112,7 @@ typedef struct {
   uint64_t bfs_vertices;      /* vertices dequeued by query BFS */
   uint64_t bfs_edges;         /* adjacency entries scanned by query BFS */
   uint64_t bfs_heavy;         /* BFS that outgrew a slot and ran on the whole device */
+  uint64_t pull_rounds;       /* (round, direction) pairs propagated by pulling */
   uint64_t server_requests;   /* requests served by the request server (dbl_insert_edges_each) */
   double server_busy_us;      /* device time it spent on them, from seeing a request to
                                  publishing its status (device wall clock) */

@@ -64,6 +64,7 @@ class DblStats(ctypes.Structure):
         ("bfs_vertices", ctypes.c_uint64),
         ("bfs_edges", ctypes.c_uint64),
         ("bfs_heavy", ctypes.c_uint64),
+        ("pull_rounds", ctypes.c_uint64),
         ("server_requests", ctypes.c_uint64),
         ("server_busy_us", ctypes.c_double),
     ]

@@ -59,6 +59,7 @@ struct dbl_index {
   u64 *fbm = nullptr;         // frontier bitmap of pull rounds (2 bits per vertex)
   uint64_t fbm_words = 0;
   uint64_t pull_expanded = 0;  // frontier entries expanded by pull rounds
+  uint64_t pull_rounds = 0;    // (round, direction) pairs pulled
   Ctl *ctl = nullptr;
   dbl::Mirror *mirror = nullptr;  // pinned, device-mapped host memory written by the device
   u64 *door = nullptr;            // pinned, device-mapped host memory written by the host
@@ -263,6 +264,7 @@ dbl_status wait_mirror(dbl::Mirror *m, dbl::Mirror &h, hipStream_t s, uint32_t s
   h.und_count = vm->und_count;
   h.bfs_heavy = vm->bfs_heavy;
   h.found = vm->found;
+  for (int i = 0; i < 4; i++) h.dstat[i] = vm->dstat[i];
   return DBL_OK;
 }
 
@@ -372,14 +374,18 @@ dbl_status grid_propagate(dbl_index *ix, hipStream_t s, uint32_t group, uint64_t
       CK(dbl::launch_frontier_scan(a, cur, stamp, words, s));
       CKS(sync_ctl(ix, s));
       uint32_t pull = 0;
-      for (uint32_t d = 0; d < 2; d++) {
+      // the scan counted every entry of the frontier once; anything else: push them all
+      const bool counted = ix->hs.dstat[0] + ix->hs.dstat[1] == fsz;
+      for (uint32_t d = 0; d < 2 && counted; d++) {
         const uint64_t edges = d ? ix->r_total : ix->f_total;
         if (ix->hs.dstat[2 + d] && ix->hs.dstat[2 + d] * 1024 >= (u64)ix->pull_threshold * edges) {
           pull |= 1u << d;
           ix->pull_expanded += ix->hs.dstat[d];
+          ix->pull_rounds++;
         }
       }
-      const uint64_t pushed = (pull & 1 ? 0 : ix->hs.dstat[0]) + (pull & 2 ? 0 : ix->hs.dstat[1]);
+      const uint64_t pushed = !counted ? fsz
+                              : (pull & 1 ? 0 : ix->hs.dstat[0]) + (pull & 2 ? 0 : ix->hs.dstat[1]);
       {
         Timed tm(ix, kTRound, s);
         if (pull) {
@@ -1214,6 +1220,7 @@ dbl_status dbl_get_stats(const dbl_index *ix_c, dbl_stats *out) {
   u64 sc[2] = {0, 0};
   CK(hipMemcpy(sc, ix->ctl->ctr + dbl::kCtrServerTicks, sizeof(sc), hipMemcpyDeviceToHost));
   out->server_requests = sc[1];
+  out->pull_rounds = ix->pull_rounds;
   out->server_busy_us = (double)sc[0] * 1000.0 / (double)ix->clock_khz;
   return DBL_OK;
 }

@@ -142,30 +142,46 @@ def test_pull_rounds_families(name, gr, pull):
 
 @pytest.mark.parametrize("words", [1, 4])
 def test_pull_rounds_rmat_equal_counts(words):
-    """On a 2^16-vertex R-MAT graph with hub rows: the pulled build gives the oracle's labels,
-    and relaxes exactly the edges the pushed build relaxes (each frontier edge once per round,
-    either way). Then grid-round insertion batches with pulls (tiny single-workgroup bounds)."""
-    k = 64 if words == 1 else 200
+    """On a 2^16-vertex R-MAT graph with hub rows, builds that push only, pull whenever a
+    direction has frontier edges, or follow the default threshold all give the oracle's labels
+    (the least fixpoint; how many edges each relaxes depends on the schedule). Then grid-round
+    insertion batches with pulls (tiny single-workgroup bounds)."""
+    k, kp = (64, 64) if words == 1 else (200, 256)
     w = dblgen.make_rmat_workload(f"pr{words}", 16, 21, draws=16 << 16, n_insert=30000,
                                   insert_kind="rmat", n_query=50000, query_kind="mixed")
-    o = oracle.OracleIndex(w.n, w.src, w.dst).build(k=k, kp=k, threads=8)
+    o = oracle.OracleIndex(w.n, w.src, w.dst).build(k=k, kp=kp, threads=8)
     stats = {}
     for pull in (0, 1, 128):
-        g = gpu_index(w.n, w.src, w.dst, num_landmarks=k, bl_bits=k, pull_threshold=pull)
+        g = gpu_index(w.n, w.src, w.dst, num_landmarks=k, bl_bits=kp, pull_threshold=pull)
         assert g.label_words() == words
         assert_labels_equal(g, o, f"pull {pull}")
         stats[pull] = g.stats()
         g.close()
-    for pull in (1, 128):
-        assert stats[pull]["edges_relaxed"] == stats[0]["edges_relaxed"]
-        assert stats[pull]["vertices_expanded"] == stats[0]["vertices_expanded"]
-        assert stats[pull]["build_rounds"] <= stats[0]["build_rounds"]
-    g = gpu_index(w.n, w.src, w.dst, num_landmarks=k, bl_bits=k, pull_threshold=1)
+    assert stats[0]["pull_rounds"] == 0
+    assert stats[1]["pull_rounds"] >= stats[128]["pull_rounds"] > 0
+    g = gpu_index(w.n, w.src, w.dst, num_landmarks=k, bl_bits=kp, pull_threshold=1)
     g.set_tuning(small_batch=0, local_max_frontier=16, local_max_edges=256)
     o.insert(w.ins_src, w.ins_dst)
     for lo in range(0, 30000, 10000):
         g.insert_edges(dev(w.ins_src[lo:lo + 10000]), dev(w.ins_dst[lo:lo + 10000]))
-    assert_labels_equal(g, o, "pulled insertion rounds")
+    assert_labels_equal(g, o, "insertion rounds after a pulled build")
+    assert_queries_equal(g, o, w.q_u, w.q_v)
+
+
+def test_pull_rounds_in_insertion_batches():
+    """Insertion batches on a 2^12-vertex graph with the single-workgroup bounds tiny, so the
+    batches propagate in grid rounds, and the threshold at its minimum, so those rounds pull."""
+    w = dblgen.make_rmat_workload("pri", 12, 5, draws=8 << 12, n_insert=6000,
+                                  insert_kind="uniform", n_query=20000, query_kind="mixed")
+    g = gpu_index(w.n, w.src, w.dst, pull_threshold=1)
+    g.set_tuning(small_batch=0, local_max_frontier=4, local_max_edges=32)
+    o = oracle.OracleIndex(w.n, w.src, w.dst).build(threads=8)
+    built = g.stats()["pull_rounds"]
+    for lo in range(0, 6000, 1500):
+        g.insert_edges(dev(w.ins_src[lo:lo + 1500]), dev(w.ins_dst[lo:lo + 1500]))
+        o.insert(w.ins_src[lo:lo + 1500], w.ins_dst[lo:lo + 1500])
+        assert_labels_equal(g, o, f"after {lo + 1500} insertions")
+    assert g.stats()["pull_rounds"] > built
     assert_queries_equal(g, o, w.q_u, w.q_v)
 
 
