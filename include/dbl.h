@@ -261,6 +261,8 @@ typedef struct {
                                   its frontier neighbours' labels) when the frontier would push at
                                   least pull_threshold / 1024 of that direction's edges, and
                                   pushes otherwise; 0 = always push (default 128) */
+  uint32_t server_polls;       /* reads of the doorbell the request server keeps in flight: 1 or
+                                  4 (default 4) */
 } dbl_tuning;
 
 dbl_status dbl_get_tuning(const dbl_index *ix, dbl_tuning *out);

@@ -65,6 +65,7 @@ struct dbl_index {
   u64 *door = nullptr;            // pinned, device-mapped host memory written by the host
   u64 clock_khz = 100000;         // device wall-clock rate
   uint32_t server_idle_us = 200000;  // request-server idle limit
+  uint32_t server_polls = 4;         // doorbell reads in flight (1 or 4)
   dbl::Mirror hs{};               // host copy of the last published status
   uint32_t seq = 0;
   u64 *pcnt = nullptr;  // per-block propagation counters
@@ -820,7 +821,8 @@ dbl_status insert_each_served(dbl_index *ix, uint32_t count, const uint32_t *d_s
       Timed tm(ix, kTInsertServer, s);
       CK(dbl::launch_insert_server(a, d_src, d_dst, first, count, ix->n, ix->ovf, ix->ovf_cap,
                                    ix->mirror, ix->door, seq0,
-                                   ix->clock_khz * ix->server_idle_us / 1000, s));
+                                   ix->clock_khz * ix->server_idle_us / 1000, ix->server_polls,
+                                   s));
     }
     bool relaunch = false;
     for (; i < count && !relaunch; i++) {
@@ -1342,6 +1344,7 @@ dbl_status dbl_get_tuning(const dbl_index *ix, dbl_tuning *out) {
   out->insert_server = ix->insert_server;
   out->server_idle_us = ix->server_idle_us;
   out->pull_threshold = ix->pull_threshold;
+  out->server_polls = ix->server_polls;
   out->bfs_slots = ix->qctx ? ix->qctx->slots : (ix->slots_opt ? ix->slots_opt : 1024);
   return DBL_OK;
 }
@@ -1350,7 +1353,8 @@ dbl_status dbl_set_tuning(dbl_index *ix, const dbl_tuning *t) {
   if (!ix || !t) return DBL_ERR_INVALID_ARG;
   if (t->small_batch > dbl::kSmallBatchMax || t->round_grid == 0 ||
       t->round_grid > dbl::kRoundGridMax || t->bfs_slots > (1u << 16) || t->insert_server > 1 ||
-      t->server_idle_us > 10000000 || t->pull_threshold > 1u << 20)
+      t->server_idle_us > 10000000 || t->pull_threshold > 1u << 20 ||
+      (t->server_polls != 1 && t->server_polls != 4))
     return DBL_ERR_INVALID_ARG;
   DeviceGuard dg(ix->device);
   ix->small_batch = t->small_batch;
@@ -1360,6 +1364,7 @@ dbl_status dbl_set_tuning(dbl_index *ix, const dbl_tuning *t) {
   ix->insert_server = t->insert_server;
   ix->server_idle_us = t->server_idle_us;
   ix->pull_threshold = t->pull_threshold;
+  ix->server_polls = t->server_polls;
   const uint32_t slots = t->bfs_slots ? std::max<uint32_t>(4, (t->bfs_slots + 3) / 4 * 4) : 0;
   if (slots && (!ix->qctx || ix->qctx->slots != slots)) {
     // rebuild the index's own query context with the new slot count (its counters are kept)

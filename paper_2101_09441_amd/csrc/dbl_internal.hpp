@@ -195,7 +195,8 @@ hipError_t launch_insert_small(const PropArgs &a, const uint32_t *src, const uin
 hipError_t launch_insert_server(const PropArgs &a, const uint32_t *src, const uint32_t *dst,
                                 uint32_t first, uint32_t count, uint32_t n, Ovf *ovf,
                                 uint64_t ovf_cap, Mirror *m, const unsigned long long *door,
-                                uint32_t seq0, unsigned long long idle_ticks, hipStream_t s);
+                                uint32_t seq0, unsigned long long idle_ticks, uint32_t polls,
+                                hipStream_t s);
 hipError_t launch_insert_apply(const PropArgs &a, const uint32_t *src, const uint32_t *dst,
                                uint64_t count, Ovf *ovf, uint64_t ovf_cap, hipStream_t s);
 hipError_t launch_regrow_copy(Csr old_g, Csr new_g, uint32_t n, hipStream_t s);

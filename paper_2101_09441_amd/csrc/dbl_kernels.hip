@@ -166,6 +166,27 @@ __device__ __forceinline__ bool claim(uint32_t *slot, uint32_t stamp) {
   return atomicExch(slot, stamp) != stamp;
 }
 
+// A pointer that is the same in every lane, held in scalar registers.
+template <typename T>
+__device__ __forceinline__ T *uniform_ptr(T *p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return reinterpret_cast<T *>(((uint64_t)hi << 32) | lo);
+}
+
+// r when sel is set, else f, chosen field by field from scalar copies of the (uniform)
+// kernel-argument pointers, so a per-lane `sel` costs a select instead of per-lane loads of the
+// pointers from argument memory.
+__device__ __forceinline__ Csr pick_csr(const Csr &f, const Csr &r, bool sel) {
+  Csr g;
+  g.off = sel ? uniform_ptr(r.off) : uniform_ptr(f.off);
+  g.deg = sel ? uniform_ptr(r.deg) : uniform_ptr(f.deg);
+  g.cap = sel ? uniform_ptr(r.cap) : uniform_ptr(f.cap);
+  g.col = sel ? uniform_ptr(r.col) : uniform_ptr(f.col);
+  return g;
+}
+
 __device__ __forceinline__ uint32_t fib_bucket(uint32_t x, uint32_t bits) {
   return bits == 0 ? 0u : (uint32_t)(((u64)x * 0x9E3779B97F4A7C15ull) >> (64u - bits));
 }
@@ -877,7 +898,7 @@ __global__ __launch_bounds__(256) void k_pull(PropArgs a, uint32_t n, uint32_t d
     if (act) {
       d = ndir == 2 ? (r >= n ? 1u : 0u) : d_only;
       y = (uint32_t)(r - (ndir == 2 && r >= n ? (uint64_t)n : 0ull));
-      const Csr g = d ? a.f : a.r;  // neighbours the labels come from
+      const Csr g = pick_csr(a.r, a.f, d);  // neighbours the labels come from
       dg = min(g.deg[y], g.cap[y]);
       if (dg > kHeavyDeg) {
         const uint32_t nch = (dg + kChunk - 1) / kChunk;
@@ -956,7 +977,7 @@ __global__ __launch_bounds__(256) void k_pull_heavy(PropArgs a, uint32_t nring,
     const u64 h = a.pheavy_list[item];
     const uint32_t row = (uint32_t)(h >> 32), c = (uint32_t)h;
     const uint32_t d = row >> 31, y = row & kIdMask;
-    const Csr g = d ? a.f : a.r;
+    const Csr g = pick_csr(a.r, a.f, d);
     const uint32_t dg = min(g.deg[y], g.cap[y]);
     const uint32_t b = c * kChunk, e_end = min(dg, b + kChunk);
     const u64 o = g.off[y];
@@ -1082,9 +1103,12 @@ hipError_t launch_local_rounds(const PropArgs &a, Mirror *m, uint32_t seq, hipSt
 __device__ __forceinline__ bool append_edge(const Csr &g, uint32_t x, uint32_t y,
                                             uint32_t dirbit, Ovf *ovf, uint64_t ovf_cap,
                                             Ctl *ctl) {
+  // the row's capacity and offset do not depend on the append: read them first
+  const uint32_t cap = g.cap[x];
+  const u64 off = g.off[x];
   const uint32_t pos = atomicAdd(&g.deg[x], 1u);
-  if (pos < g.cap[x]) {
-    g.col[g.off[x] + pos] = y;
+  if (pos < cap) {
+    g.col[off + pos] = y;
     return true;
   }
   const uint32_t k = atomicAdd(&ctl->ovf_count, 1u);
@@ -1102,19 +1126,23 @@ __device__ __forceinline__ bool append_edge(const Csr &g, uint32_t x, uint32_t y
 // Half of an insertion (u,v) for one direction. Forward: append v to Suc(u) and OR
 // (DL_in(u), BL_in(u)) into v (Algorithm 3 starts from v). Backward: append u to Pre(v) and OR
 // (DL_out(v), BL_out(v)) into u. A changed endpoint joins the pending frontier. Returns whether
-// it was queued.
+// it was queued. `coherent_tail` reads the tail's label past the L1 cache (the request server,
+// whose earlier requests may have grown it through L2 atomics); the head's label is only a
+// pre-read, where an older value merely costs an extra atomic.
 template <int W>
 __device__ __forceinline__ bool apply_half(const PropArgs &a, uint32_t u, uint32_t v, uint32_t dir,
                                            uint32_t ring, uint32_t stamp, Ovf *ovf,
-                                           uint64_t ovf_cap, bool active, bool *overflowed) {
+                                           uint64_t ovf_cap, bool active, bool *overflowed,
+                                           bool coherent_tail = false) {
   bool p = false;
   const uint32_t tail = dir ? v : u, head = dir ? u : v;
   if (active && u != v) {
     // the label reads do not depend on the append: issue them first
-    const Half<W> lt = ld_half<W>(half_ptr<W>(a.L.lab, tail, dir));
+    const u64 *tp = half_ptr<W>(a.L.lab, tail, dir);
+    const Half<W> lt = coherent_tail ? ld_half_agent<W>(tp) : ld_half<W>(tp);
     u64 *wh = half_ptr<W>(a.L.lab, head, dir);
     const Half<W> lh = ld_half<W>(wh);
-    if (!append_edge(dir ? a.r : a.f, tail, head, dir ? kDirBit : 0u, ovf, ovf_cap, a.ctl))
+    if (!append_edge(pick_csr(a.f, a.r, dir), tail, head, dir ? kDirBit : 0u, ovf, ovf_cap, a.ctl))
       *overflowed = true;
     p = or_half<W>(wh, lt, lh) && claim(&a.inq[2ull * head + dir], stamp);
   }
@@ -1222,11 +1250,45 @@ hipError_t launch_insert_small(const PropArgs &a, const uint32_t *src, const uin
 constexpr uint32_t kServerMaxSpins = 1u << 23;
 constexpr uint32_t kCmdExit = 0u, kCmdPropagate = 1u;
 
+// Wait for the doorbell word to become `want`: returns 1 when it does, 0 on kDoorStop or after
+// idle_ticks of the device wall clock. D reads of the (host-memory) word are kept in flight,
+// first issued a fraction of a round trip apart, so a release is seen sooner than with one read
+// at a time. The iteration bound is a backstop that ends the wait even if the clock stood still
+// (each iteration waits for a host-memory read).
+template <int D>
+__device__ __forceinline__ uint32_t wait_door(const u64 *door, u64 want, u64 idle_ticks) {
+  const u64 t0 = wall_clock64();
+  u64 d[D];
+#pragma unroll
+  for (int k = 0; k < D; k++) {
+    d[k] = __hip_atomic_load(door, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    if (k + 1 < D) __builtin_amdgcn_s_sleep(8);
+  }
+  // branch-free body; each reissue's address depends (opaquely, by zero) on its compare, so it
+  // is not scheduled ahead of the compares and the reads stay spread out
+  for (uint32_t spin = 0; spin < kServerMaxSpins; spin++) {
+    bool hit = false, stop = false;
+#pragma unroll
+    for (int k = 0; k < D; k++) {
+      const bool h = d[k] == want;
+      hit |= h;
+      stop |= d[k] == kDoorStop;
+      uint32_t dep = h ? 1u : 0u;
+      asm volatile("" : "+v"(dep));
+      d[k] = __hip_atomic_load(door + (dep >> 31), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    if (hit) return 1u;
+    if (stop || wall_clock64() - t0 > idle_ticks) return 0u;
+    if (D == 1) __builtin_amdgcn_s_sleep(2);
+  }
+  return 0u;
+}
+
 template <int W>
 __global__ __launch_bounds__(kLocalThreads) void k_insert_server(
     PropArgs a, const uint32_t *src, const uint32_t *dst, uint32_t first, uint32_t count,
     uint32_t n, Ovf *ovf, uint64_t ovf_cap, Mirror *m, const u64 *door, uint32_t seq0,
-    u64 idle_ticks) {
+    u64 idle_ticks, uint32_t polls) {
   __shared__ uint32_t s_cmd, s_flags;
   Ctl *ctl = a.ctl;
   const uint32_t t = threadIdx.x, lane = t & 63u;
@@ -1238,24 +1300,14 @@ __global__ __launch_bounds__(kLocalThreads) void k_insert_server(
       uint32_t cmd = kCmdExit;
       for (; i < count; i++) {
         uint32_t go = 0;
-        if (lane == 0) {
-          const u64 t0 = wall_clock64();
-          // the wall clock bounds the wait; the iteration bound (each iteration reads host
-          // memory, at least ~1 us) ends it even if the clock stood still
-          for (uint32_t spin = 0; spin < kServerMaxSpins; spin++) {
-            const u64 d = __hip_atomic_load(door, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-            if (d == (u64)i + 1u) {
-              go = 1;
-              break;
-            }
-            if (d == kDoorStop || wall_clock64() - t0 > idle_ticks) break;
-            __builtin_amdgcn_s_sleep(2);
-          }
-        }
+        if (lane == 0)
+          go = polls > 1 ? wait_door<4>(door, (u64)i + 1u, idle_ticks)
+                         : wait_door<1>(door, (u64)i + 1u, idle_ticks);
         if (!__shfl(go, 0, 64)) break;
         if (lane == 0) t_go = wall_clock64();
-        // earlier requests changed state through L2 atomics: drop this CU's cached lines
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        // No cache invalidation here: this path reads ids and row bounds (fixed during the
+        // launch), the control block and the tail label past L1, and pre-reads where an older
+        // value only costs an atomic (head label, queue stamp).
         const bool act = lane < 2u;
         uint32_t u = 0, v = 0;
         if (act) {
@@ -1272,7 +1324,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_insert_server(
         }
         bool ovfl = false;
         const bool pushed = apply_half<W>(a, u, v, lane & 1u, ring, stamp, ovf, ovf_cap, act,
-                                          &ovfl);
+                                          &ovfl, true);
         any_ovf = __ballot(ovfl) != 0ull;
         if (__ballot(pushed)) {
           if (lane == 0) {
@@ -1299,7 +1351,9 @@ __global__ __launch_bounds__(kLocalThreads) void k_insert_server(
     }
     __syncthreads();
     if (s_cmd == kCmdExit) return;
-    // request i queued vertices: the whole workgroup propagates
+    // request i queued vertices: the whole workgroup propagates. Earlier requests changed
+    // labels and queues through L2: drop this CU's cached lines first.
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     local_rounds_body<W>(a);
     __syncthreads();
     if (t == 0) {
@@ -1323,10 +1377,10 @@ __global__ __launch_bounds__(kLocalThreads) void k_insert_server(
 hipError_t launch_insert_server(const PropArgs &a, const uint32_t *src, const uint32_t *dst,
                                 uint32_t first, uint32_t count, uint32_t n, Ovf *ovf,
                                 uint64_t ovf_cap, Mirror *m, const u64 *door, uint32_t seq0,
-                                u64 idle_ticks, hipStream_t s) {
+                                u64 idle_ticks, uint32_t polls, hipStream_t s) {
   if (first >= count) return hipSuccess;
   DBL_LAUNCH_W(a.L.words, k_insert_server, dim3(1), dim3(kLocalThreads), s, a, src, dst, first,
-               count, n, ovf, ovf_cap, m, door, seq0, idle_ticks);
+               count, n, ovf, ovf_cap, m, door, seq0, idle_ticks, polls);
   return hipGetLastError();
 }
 

@@ -327,19 +327,20 @@ def test_tiny_insert_each_equals_single_calls(tiny):
         g.insert_edges_each(dev([1, 2, w.n]), dev([3, 4, 5]))
 
 
-@pytest.mark.parametrize("server,idle_us", [(0, 200000), (1, 0)])
-def test_insert_each_forms(tiny, server, idle_us):
-    """One launch per request, and the request server with a zero idle limit (a launch ends as
-    soon as the next request is not there yet, so most requests start a new launch)."""
+@pytest.mark.parametrize("server,idle_us,polls", [(0, 200000, 4), (1, 0, 4), (1, 200000, 1)])
+def test_insert_each_forms(tiny, server, idle_us, polls):
+    """One launch per request; the request server with a zero idle limit (a launch ends as soon
+    as the next request is not there yet, so most requests start a new launch); the server
+    reading its doorbell one read at a time."""
     w = tiny
     g = gpu_index(w.n, w.src, w.dst)
-    g.set_tuning(insert_server=server, server_idle_us=idle_us)
+    g.set_tuning(insert_server=server, server_idle_us=idle_us, server_polls=polls)
     o = oracle.OracleIndex(w.n, w.src, w.dst).build(threads=8)
     k = 300
     lat = g.insert_edges_each(dev(w.ins_src[:k]), dev(w.ins_dst[:k]), latencies=True)
     o.insert(w.ins_src[:k], w.ins_dst[:k])
     assert np.all(lat > 0)
-    assert_labels_equal(g, o, f"server {server} idle {idle_us}")
+    assert_labels_equal(g, o, f"server {server} idle {idle_us} polls {polls}")
     assert g.stats()["insert_calls"] == k
 
 
