@@ -211,10 +211,14 @@ def bench_scale(args):
         "build_s": float(np.mean([r["build_s"] for r in res])),
         "insert_edges_per_s": n_ins / float(np.mean([r["insert_s"] for r in res])),
         "insert_batch_ms": {"p50": float(np.percentile(res[-1]["lat_i"], 50) * 1e3),
-                            "p99": float(np.percentile(res[-1]["lat_i"], 99) * 1e3)},
+                            "p99": float(np.percentile(res[-1]["lat_i"], 99) * 1e3),
+                            "first": res[-1]["lat_i"][0] * 1e3,
+                            "max": float(np.max(res[-1]["lat_i"]) * 1e3)},
         "queries_per_s": n_q / float(np.mean([r["query_s"] for r in res])),
         "query_batch_ms": {"p50": float(np.percentile(res[-1]["lat_q"], 50) * 1e3),
-                           "p99": float(np.percentile(res[-1]["lat_q"], 99) * 1e3)},
+                           "p99": float(np.percentile(res[-1]["lat_q"], 99) * 1e3),
+                           "first": res[-1]["lat_q"][0] * 1e3,
+                           "max": float(np.max(res[-1]["lat_q"]) * 1e3)},
         "class_histogram": {dbl.CLASS_NAMES[i]: int(classes[i]) for i in range(7)},
         "kernel_times_ms": {k: {"launches": v["launches"],
                                 "avg_us": v["total_ms"] / v["launches"] * 1e3}

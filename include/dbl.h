@@ -275,8 +275,19 @@ uint32_t dbl_num_vertices(const dbl_index *ix);
    requested in dbl_options. */
 uint32_t dbl_label_words(const dbl_index *ix);
 
-/* Release every device buffer of the index (NULL is ignored). */
+/* Release every device buffer of the index (NULL is ignored). Waits for the device first. */
 void dbl_destroy(dbl_index *ix);
+
+/* Memory cache. Device and pinned host blocks the library frees (dbl_destroy, internal resizes)
+   are kept for reuse by later allocations of the same size on the same device, so repeated
+   builds and query contexts do not go back to the driver. Up to the limit (default 64 GiB) of
+   cached bytes is kept; everything cached is returned when an allocation fails.
+     dbl_release_cache: return every cached block to the driver.
+     dbl_set_cache_limit: change the limit (0 = cache nothing), trimming at once.
+     dbl_cached_bytes: bytes currently cached (not in use by any index). */
+void dbl_release_cache(void);
+void dbl_set_cache_limit(uint64_t bytes);
+uint64_t dbl_cached_bytes(void);
 
 /* Static text for a status code. */
 const char *dbl_status_str(dbl_status s);

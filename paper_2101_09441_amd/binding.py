@@ -27,6 +27,7 @@ EXPORTS = [
     "dbl_read_labels", "dbl_get_landmarks", "dbl_get_leaves", "dbl_get_stats",
     "dbl_time_kernels", "dbl_read_kernel_times", "dbl_get_tuning", "dbl_set_tuning",
     "dbl_num_vertices", "dbl_label_words", "dbl_destroy",
+    "dbl_release_cache", "dbl_set_cache_limit", "dbl_cached_bytes",
     "dbl_status_str",
 ]
 
@@ -158,6 +159,12 @@ def load_library():
     lib.dbl_label_words.restype = u32
     lib.dbl_destroy.argtypes = [P]
     lib.dbl_destroy.restype = None
+    lib.dbl_release_cache.argtypes = []
+    lib.dbl_release_cache.restype = None
+    lib.dbl_set_cache_limit.argtypes = [u64]
+    lib.dbl_set_cache_limit.restype = None
+    lib.dbl_cached_bytes.argtypes = []
+    lib.dbl_cached_bytes.restype = u64
     lib.dbl_status_str.argtypes = [i32]
     lib.dbl_status_str.restype = ctypes.c_char_p
     _lib = lib
@@ -190,6 +197,20 @@ def _stream_ptr(stream) -> int:
     if stream is None:
         stream = torch.cuda.current_stream()
     return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def release_cache() -> None:
+    """Return every device / pinned block the library keeps for reuse to the driver."""
+    load_library().dbl_release_cache()
+
+
+def set_cache_limit(nbytes: int) -> None:
+    """Cap the bytes the library keeps cached for reuse (0 = cache nothing)."""
+    load_library().dbl_set_cache_limit(int(nbytes))
+
+
+def cached_bytes() -> int:
+    return int(load_library().dbl_cached_bytes())
 
 
 def to_device_ids(a, device="cuda") -> torch.Tensor:

@@ -10,6 +10,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "dbl.h"
@@ -191,22 +192,123 @@ dbl_status from_hip(hipError_t e) {
     if (s_ != DBL_OK) return s_;                   \
   } while (0)
 
+// ---------------------------------------------------------------- memory cache
+// Freed device and pinned host blocks are kept, keyed by (kind, device, size), and handed out
+// again, so repeated builds of one workload and each index's query scratch cost no driver
+// allocation (and no hipFree, which waits for the whole device). Block sizes are rounded up to
+// 64 KiB (4 KiB below that). Cached bytes are capped (dbl_set_cache_limit); everything cached
+// goes back to the driver on dbl_release_cache and when an allocation fails. A block is put
+// back only after the work that used it has finished (every call synchronises its stream before
+// returning, and dbl_destroy waits for the device first).
+struct Block {
+  void *p;
+  size_t size;
+  int dev;
+  bool host;
+};
+
+struct MemCache {
+  std::mutex mu;
+  std::unordered_map<void *, Block> live;
+  std::vector<Block> spare;
+  uint64_t cached = 0;
+  uint64_t limit = 64ull << 30;
+};
+
+MemCache &mem_cache() {
+  static MemCache *c = new MemCache();  // never destroyed: usable until the process ends
+  return *c;
+}
+
+size_t granule(size_t bytes) {
+  return bytes <= 4096 ? 4096 : (bytes + 65535) & ~(size_t)65535;
+}
+
+void release_block(const Block &b) {
+  if (b.host) (void)hipHostFree(b.p);
+  else (void)hipFree(b.p);
+}
+
+// Return cached blocks to the driver (of one device, or all with dev < 0) until at most `keep`
+// bytes stay cached. Caller holds the lock.
+void trim_locked(MemCache &c, int dev, uint64_t keep) {
+  for (size_t i = 0; i < c.spare.size() && c.cached > keep;) {
+    if (dev >= 0 && c.spare[i].dev != dev) {
+      i++;
+      continue;
+    }
+    release_block(c.spare[i]);
+    c.cached -= c.spare[i].size;
+    c.spare[i] = c.spare.back();
+    c.spare.pop_back();
+  }
+}
+
+void *take_block(size_t size, bool host) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  MemCache &c = mem_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  for (size_t i = 0; i < c.spare.size(); i++) {
+    const Block b = c.spare[i];
+    if (b.size == size && b.dev == dev && b.host == host) {
+      c.spare[i] = c.spare.back();
+      c.spare.pop_back();
+      c.cached -= b.size;
+      c.live[b.p] = b;
+      return b.p;
+    }
+  }
+  for (int attempt = 0; attempt < 2; attempt++) {
+    void *p = nullptr;
+    const hipError_t e = host ? hipHostMalloc(&p, size, hipHostMallocMapped | hipHostMallocCoherent)
+                              : hipMalloc(&p, size);
+    if (e == hipSuccess) {
+      c.live[p] = Block{p, size, dev, host};
+      return p;
+    }
+    (void)hipGetLastError();
+    trim_locked(c, -1, 0);  // out of memory: give the cache back and try once more
+  }
+  return nullptr;
+}
+
+void put_block(void *p) {
+  if (!p) return;
+  MemCache &c = mem_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  auto it = c.live.find(p);
+  if (it == c.live.end()) return;
+  const Block b = it->second;
+  c.live.erase(it);
+  c.spare.push_back(b);
+  c.cached += b.size;
+  if (c.cached > c.limit) trim_locked(c, -1, c.limit);
+}
+
 template <typename T>
 dbl_status dalloc(T **p, uint64_t count) {
-  *p = nullptr;
   if (count == 0) count = 1;
-  hipError_t e = hipMalloc((void **)p, sizeof(T) * count);
-  if (e != hipSuccess) {
-    *p = nullptr;
-    (void)hipGetLastError();
-    return DBL_ERR_OUT_OF_MEMORY;
-  }
-  return DBL_OK;
+  *p = (T *)take_block(granule(sizeof(T) * count), false);
+  return *p ? DBL_OK : DBL_ERR_OUT_OF_MEMORY;
 }
 
 template <typename T>
 void dfree(T *&p) {
-  if (p) (void)hipFree((void *)p);
+  put_block((void *)p);
+  p = nullptr;
+}
+
+// pinned, device-mapped, coherent host memory (status mirrors, doorbells)
+template <typename T>
+dbl_status halloc(T **p, size_t bytes) {
+  *p = (T *)take_block(granule(bytes), true);
+  return *p ? DBL_OK : DBL_ERR_OUT_OF_MEMORY;
+}
+
+template <typename T>
+void hfree(T *&p) {
+  put_block((void *)p);
   p = nullptr;
 }
 
@@ -480,7 +582,7 @@ uint64_t ctx_bytes(const dbl_index *ix, uint32_t slots, uint32_t qcap, uint64_t 
 
 void ctx_free(dbl_query_ctx *c) {
   dfree(c->ctl);
-  if (c->mirror) (void)hipHostFree((void *)c->mirror);
+  hfree(c->mirror);
   c->mirror = nullptr;
   dfree(c->und);
   dfree(c->heavy_q);
@@ -525,8 +627,7 @@ dbl_status ctx_init(dbl_index *ix, dbl_query_ctx *c, uint32_t slots, uint32_t qc
   qcap = ctx_qcap(ix, qcap);
   hipStream_t s0 = nullptr;
   CKS(dalloc(&c->ctl, 1));
-  CK(hipHostMalloc((void **)&c->mirror, sizeof(dbl::Mirror),
-                   hipHostMallocMapped | hipHostMallocCoherent));
+  CKS(halloc(&c->mirror, sizeof(dbl::Mirror)));
   memset((void *)c->mirror, 0, sizeof(dbl::Mirror));
   {
     Ctl init;
@@ -664,10 +765,9 @@ dbl_status do_build(dbl_index *ix, uint64_t m, const uint32_t *src, const uint32
                     const dbl_options &o, hipStream_t s) {
   const uint32_t n = ix->n;
   CKS(dalloc(&ix->ctl, 1));
-  CK(hipHostMalloc((void **)&ix->mirror, sizeof(dbl::Mirror),
-                   hipHostMallocMapped | hipHostMallocCoherent));
+  CKS(halloc(&ix->mirror, sizeof(dbl::Mirror)));
   memset((void *)ix->mirror, 0, sizeof(dbl::Mirror));
-  CK(hipHostMalloc((void **)&ix->door, 64, hipHostMallocMapped | hipHostMallocCoherent));
+  CKS(halloc(&ix->door, 64));
   memset((void *)ix->door, 0, 64);
   {
     int khz = 0;
@@ -1388,11 +1488,32 @@ dbl_status dbl_set_tuning(dbl_index *ix, const dbl_tuning *t) {
 
 uint32_t dbl_num_vertices(const dbl_index *ix) { return ix ? ix->n : 0; }
 
+void dbl_release_cache(void) {
+  MemCache &c = mem_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  trim_locked(c, -1, 0);
+}
+
+void dbl_set_cache_limit(uint64_t bytes) {
+  MemCache &c = mem_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  c.limit = bytes;
+  trim_locked(c, -1, c.limit);
+}
+
+uint64_t dbl_cached_bytes(void) {
+  MemCache &c = mem_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  return c.cached;
+}
+
 uint32_t dbl_label_words(const dbl_index *ix) { return ix ? ix->lw : 0; }
 
 void dbl_destroy(dbl_index *ix) {
   if (!ix) return;
   DeviceGuard dg(ix->device);
+  // the blocks go back to the cache for reuse: nothing may still be using them
+  (void)hipDeviceSynchronize();
   dfree(ix->f.off); dfree(ix->f.deg); dfree(ix->f.cap); dfree(ix->f.col);
   dfree(ix->r.off); dfree(ix->r.deg); dfree(ix->r.cap); dfree(ix->r.col);
   dfree(ix->lab);
@@ -1401,8 +1522,8 @@ void dbl_destroy(dbl_index *ix) {
   dfree(ix->heavy_list);
   dfree(ix->fbm);
   dfree(ix->ctl);
-  if (ix->mirror) (void)hipHostFree((void *)ix->mirror);
-  if (ix->door) (void)hipHostFree((void *)ix->door);
+  hfree(ix->mirror);
+  hfree(ix->door);
   dfree(ix->pcnt);
   dfree(ix->ovf);
   dfree(ix->landmarks_d);

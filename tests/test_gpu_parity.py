@@ -125,6 +125,33 @@ def test_families_insert_batches(name, gr):
     assert_queries_equal(g, o, u, v)
 
 
+# ------------------------------------------------------------------ memory cache
+
+def test_memory_cache_reuse_and_release(tiny):
+    """Blocks of a destroyed index are cached and reused by the next build of the same graph;
+    labels stay the oracle's; releasing and a zero limit empty the cache."""
+    w = tiny
+    o = oracle.OracleIndex(w.n, w.src, w.dst).build(threads=8)
+    dbl.release_cache()
+    g = gpu_index(w.n, w.src, w.dst)
+    g.query(dev(w.q_u[:1000]), dev(w.q_v[:1000]))
+    g.close()
+    held = dbl.cached_bytes()
+    assert held > 0
+    g = gpu_index(w.n, w.src, w.dst)
+    assert dbl.cached_bytes() < held  # the build took blocks back out of the cache
+    assert_labels_equal(g, o, "build on reused blocks")
+    assert_queries_equal(g, o, w.q_u, w.q_v)
+    g.close()
+    dbl.release_cache()
+    assert dbl.cached_bytes() == 0
+    dbl.set_cache_limit(0)
+    g = gpu_index(w.n, w.src, w.dst)
+    g.close()
+    assert dbl.cached_bytes() == 0
+    dbl.set_cache_limit(64 << 30)
+
+
 # ------------------------------------------------------------------ push and pull rounds
 
 @pytest.mark.parametrize("pull", [0, 1, 1 << 20])
