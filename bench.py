@@ -40,6 +40,28 @@ RELAX_BYTES = 4 + 16
 EXPAND_BYTES = 4 + 12 + 16
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def with_counters(rl):
+    """Add the counter view to a roofline object: measured HBM-side bytes (rocprofv3
+    FETCH_SIZE + WRITE_SIZE, calibrated) over the same launch time."""
+    if rl and rl.get("traffic"):
+        t = rl["traffic"]
+        rl["counter_achieved"] = t / (rl["avg_launch_us"] / 1e6) / 1e9
+        rl["counter_frac"] = rl["counter_achieved"] / rl["peak"]
+        rl["traffic_over_algorithmic"] = t / rl["algorithmic_bytes_per_launch"]
+    return rl
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -91,6 +113,8 @@ def cpu_baseline(w, n_ins_sample, n_q_sample):
         "value": (n_ins + n_q) / t_step,
         "unit": "ops/s (inserted edges + answered queries)",
         "cores": threads,
+        "cpu_model": cpu_model(),
+        "host_cpus": os.cpu_count(),
         "kind": "oracle",
         "sample": (f"oracle build of the full graph ({t_build:.1f} s, {threads} threads), first "
                    f"{n_ins_sample} insertions one at a time ({t_ins * 1e3:.1f} ms, 1 thread), "
@@ -128,7 +152,6 @@ def bench_scale(args):
         tb = time.perf_counter()
         if timed:
             r["ktimes_build"] = ix.kernel_times()
-            r["stats_build"] = ix.stats()
             ix.time_kernels("insert_apply,local_rounds,query_label,query_bfs")
         lat_i = []
         for lo in range(0, n_ins, ib):
@@ -136,8 +159,6 @@ def bench_scale(args):
             ix.insert_edges(isrc[lo:lo + ib], idst[lo:lo + ib])
             lat_i.append(time.perf_counter() - t)
         tc = time.perf_counter()
-        if timed:
-            r["stats_ins"] = ix.stats()
         lat_q = []
         for lo in range(0, n_q, qb):
             t = time.perf_counter()
@@ -147,9 +168,21 @@ def bench_scale(args):
         r.update(build_s=tb - ta, insert_s=tc - tb, query_s=td - tc, lat_i=lat_i, lat_q=lat_q)
         if timed:
             r["ktimes"] = ix.kernel_times()
-            r["stats"] = ix.stats()
         ix.close()
         return r
+
+    def diagnostics():
+        """Untimed pass over the same inputs: counters after each phase."""
+        ix = dbl.Index.build(w.n, src, dst, edges_unique=True)
+        s_b = ix.stats()
+        for lo in range(0, n_ins, ib):
+            ix.insert_edges(isrc[lo:lo + ib], idst[lo:lo + ib])
+        s_i = ix.stats()
+        for lo in range(0, n_q, qb):
+            ix.query(qu[lo:lo + qb], qv[lo:lo + qb], out=out[lo:lo + qb])
+        s_q = ix.stats()
+        ix.close()
+        return s_b, s_i, s_q
 
     for _ in range(args.warmup):
         step(False)
@@ -161,7 +194,7 @@ def bench_scale(args):
     for i, r in enumerate(res):
         log(f"step {i}: build {r['build_s']:.3f} s, inserts {r['insert_s']:.3f} s, "
             f"queries {r['query_s']:.3f} s")
-    st, sb, si = res[-1]["stats"], res[-1]["stats_build"], res[-1]["stats_ins"]
+    sb, si, st = diagnostics()
     kt = {}
     for r in res:
         for k, v in list(r["ktimes_build"].items()) + list(r["ktimes"].items()):
@@ -191,11 +224,12 @@ def bench_scale(args):
             kernel_rooflines[k] = None
             continue
         avg = d["total_ms"] / d["launches"] / 1e3
-        kernel_rooflines[k] = {"bound": "hbm", "achieved": per / avg / 1e9, "peak": HBM_PEAK_GBS,
-                               "unit": "GB/s", "frac": per / avg / 1e9 / HBM_PEAK_GBS,
-                               "traffic": committed_traffic(k), "kernel": k,
-                               "avg_launch_us": avg * 1e6, "launches": d["launches"],
-                               "algorithmic_bytes_per_launch": per}
+        kernel_rooflines[k] = with_counters({
+            "bound": "hbm", "achieved": per / avg / 1e9, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": per / avg / 1e9 / HBM_PEAK_GBS,
+            "traffic": committed_traffic(k), "kernel": k,
+            "avg_launch_us": avg * 1e6, "launches": d["launches"],
+            "algorithmic_bytes_per_launch": per})
     timed_kinds = [k for k in kt if kernel_rooflines.get(k)]
     dominant = max(timed_kinds, key=lambda k: kt[k]["total_ms"]) if timed_kinds else None
     roofline = kernel_rooflines[dominant] if dominant else None
@@ -225,7 +259,10 @@ def bench_scale(args):
                             for k, v in kt.items()},
         "propagation": {"build_rounds": st["build_rounds"], "edges_relaxed": st["edges_relaxed"],
                         "vertices_expanded": st["vertices_expanded"],
-                        "csr_regrows": st["csr_regrows"], "bfs_heavy": st["bfs_heavy"]},
+                        "csr_regrows": st["csr_regrows"], "bfs_heavy": st["bfs_heavy"],
+                        "pull_rounds": st["pull_rounds"],
+                        "bfs_vertices": st["bfs_vertices"] - si["bfs_vertices"],
+                        "bfs_edges": st["bfs_edges"] - si["bfs_edges"]},
         "roofline": roofline,
         "kernel_rooflines": kernel_rooflines,
         "cpu_baseline": None,
@@ -501,10 +538,11 @@ def main():
             return None
         avg_s = d["total_ms"] / d["launches"] / 1e3
         achieved = per_launch / avg_s / 1e9
-        return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": committed_traffic(kind),
-                "kernel": kind, "avg_launch_us": avg_s * 1e6, "launches": d["launches"],
-                "algorithmic_bytes_per_launch": per_launch}
+        return with_counters({
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": committed_traffic(kind),
+            "kernel": kind, "avg_launch_us": avg_s * 1e6, "launches": d["launches"],
+            "algorithmic_bytes_per_launch": per_launch})
 
     roofline = roofline_of(dominant) if dominant else None
     kernel_rooflines = {k: roofline_of(k) for k in kt}

@@ -1285,12 +1285,10 @@ dbl_status dbl_get_stats(const dbl_index *ix_c, dbl_stats *out) {
   DeviceGuard dg(ix->device);
   std::vector<u64> pc(2ull * dbl::kPropCtrSlots);
   CK(hipMemcpy(pc.data(), ix->pcnt, sizeof(u64) * pc.size(), hipMemcpyDeviceToHost));
+  // stored forward entries: summed on the device (scan_total is free outside build and regrow)
   uint64_t stored = 0;
-  {
-    std::vector<uint32_t> deg(ix->n);
-    CK(hipMemcpy(deg.data(), ix->f.deg, sizeof(uint32_t) * ix->n, hipMemcpyDeviceToHost));
-    for (uint32_t d : deg) stored += d;
-  }
+  CK(dbl::launch_sum_u32(ix->f.deg, ix->n, ix->scan_total, nullptr));
+  CK(hipMemcpy(&stored, ix->scan_total, sizeof(stored), hipMemcpyDeviceToHost));
   memset(out, 0, sizeof(*out));
   out->num_edges = stored;
   out->build_rounds = ix->build_rounds;

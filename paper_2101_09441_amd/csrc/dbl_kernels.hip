@@ -219,6 +219,30 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t value, uint64_t count, hipStrea
   return hipGetLastError();
 }
 
+// *out += sum of a[0..count): per-block partial sums, one atomic per block.
+__global__ __launch_bounds__(256) void k_sum_u32(const uint32_t *a, uint64_t count, u64 *out) {
+  __shared__ u64 s_w[4];
+  u64 v = 0;
+  for (uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x; i < count;
+       i += (uint64_t)gridDim.x * 256u)
+    v += a[i];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if (__lane_id() == 0) s_w[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const u64 t = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+    if (t) atomicAdd(out, t);
+  }
+}
+
+hipError_t launch_sum_u32(const uint32_t *a, uint64_t count, u64 *out, hipStream_t s) {
+  hipError_t e = launch_fill_u64(out, 0ull, 1, s);
+  if (e != hipSuccess || count == 0) return e;
+  hipLaunchKernelGGL(k_sum_u32, dim3(grid_for(count, 256, 2048)), dim3(256), 0, s, a, count, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill_u64(u64 *p, u64 value, uint64_t count, hipStream_t s) {
   if (count == 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(count, 256, 8192)), dim3(256), 0, s, p, value,

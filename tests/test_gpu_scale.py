@@ -29,6 +29,8 @@ BL_BITS = (0, 17, 33, 50, 63)
 
 def _columns_match(gl, big, lm, s_in, s_out, bucket, what):
     dl_in, dl_out, bl_in, bl_out = gl
+    print(f"{what}: checking {len(DL_BITS)} DL and {len(BL_BITS)} BL bit columns per direction",
+          flush=True)
     for i in DL_BITS:
         col = (dl_in >> i) & 1
         want = torch.from_numpy(big.reach([lm[i]], True)).to(col.device)
@@ -36,6 +38,7 @@ def _columns_match(gl, big, lm, s_in, s_out, bucket, what):
         col = (dl_out >> i) & 1
         want = torch.from_numpy(big.reach([lm[i]], False)).to(col.device)
         assert torch.equal(col.bool(), want), f"{what}: DL_out bit {i}"
+        print(f"{what}: DL bit {i} ok", flush=True)
     for j in BL_BITS:
         col = (bl_in >> j) & 1
         want = torch.from_numpy(big.reach(np.flatnonzero(s_in & (bucket == j)), True))
@@ -43,6 +46,7 @@ def _columns_match(gl, big, lm, s_in, s_out, bucket, what):
         col = (bl_out >> j) & 1
         want = torch.from_numpy(big.reach(np.flatnonzero(s_out & (bucket == j)), False))
         assert torch.equal(col.bool(), want.to(col.device)), f"{what}: BL_out bit {j}"
+        print(f"{what}: BL bit {j} ok", flush=True)
 
 
 def _edge_monotone(gl, src, dst, chunk=1 << 26):
@@ -62,6 +66,7 @@ def test_scale_build_insert_query():
     src, dst = dbl.to_device_ids(w.src), dbl.to_device_ids(w.dst)
     g = dbl.Index.build(w.n, src, dst, edges_unique=True)
     del src, dst
+    print("built on the GPU; building the oracle's CSR", flush=True)
     big = oracle.BigGraph(w.n, w.src, w.dst)
     lm = big.landmarks(64)
     assert np.array_equal(g.landmarks(), lm)
@@ -72,10 +77,12 @@ def test_scale_build_insert_query():
     assert np.array_equal(gbucket, bucket)
     _columns_match(g.labels(), big, lm, s_in, s_out, bucket, "build")
     _edge_monotone(g.labels(), w.src, w.dst)
+    print("labels monotone along every build edge", flush=True)
     big.close()
     isrc, idst = dbl.to_device_ids(w.ins_src), dbl.to_device_ids(w.ins_dst)
     for lo in range(0, len(w.ins_src), 100_000):
         g.insert_edges(isrc[lo:lo + 100_000], idst[lo:lo + 100_000])
+    print("insertions done", flush=True)
     all_src = np.concatenate([w.src, w.ins_src])
     all_dst = np.concatenate([w.dst, w.ins_dst])
     big = oracle.BigGraph(w.n, all_src, all_dst)
@@ -86,6 +93,7 @@ def test_scale_build_insert_query():
     for lo in range(0, len(w.q_u), 65536):
         g.query(qu[lo:lo + 65536], qv[lo:lo + 65536], out=out[lo:lo + 65536])
     ans = out.cpu().numpy()
+    print(f"queries done: classes {np.bincount(ans >> 1, minlength=7).tolist()}", flush=True)
     rng = np.random.default_rng(5)
     # a sample of every class, answers against plain BFS
     cls = ans >> 1
