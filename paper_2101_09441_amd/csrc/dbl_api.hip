@@ -808,32 +808,76 @@ dbl_status do_build(dbl_index *ix, uint64_t m, const uint32_t *src, const uint32
   CKS(dalloc(&ix->r.cap, n));
   CKS(dalloc(&ix->f.off, n));
   CKS(dalloc(&ix->r.off, n));
-  CK(dbl::launch_fill_u32(ix->f.deg, 0u, n, s));
-  CK(dbl::launch_fill_u32(ix->r.deg, 0u, n, s));
-  CK(dbl::launch_degree_count(src, dst, keep, m, ix->f.deg, ix->r.deg, s));
-  CK(dbl::launch_slack_cap(ix->f.deg, ix->f.cap, n, ix->slack_frac, ix->slack_min, s));
-  CK(dbl::launch_slack_cap(ix->r.deg, ix->r.cap, n, ix->slack_frac, ix->slack_min, s));
   ix->scan_tmp_words = dbl::scan_tmp_words(n);
   CKS(dalloc(&ix->scan_tmp, ix->scan_tmp_words));
   CKS(dalloc(&ix->scan_total, 2));
-  CK(dbl::scan_exclusive(ix->f.cap, ix->f.off, n, ix->scan_tmp, ix->scan_total, s));
-  CK(dbl::scan_exclusive(ix->r.cap, ix->r.off, n, ix->scan_tmp, ix->scan_total + 1, s));
-  u64 totals[2] = {0, 0};
-  CK(hipMemcpyAsync(totals, ix->scan_total, sizeof(totals), hipMemcpyDeviceToHost, s));
-  CK(hipStreamSynchronize(s));
-  ix->f_total = totals[0];
-  ix->r_total = totals[1];
-  CKS(dalloc(&ix->f.col, ix->f_total));
-  CKS(dalloc(&ix->r.col, ix->r_total));
-  // in/out degrees are needed by selection and seeding before the scatter recounts them
+  // in/out degrees are needed by selection and seeding; the row fill recounts deg
   uint32_t *indeg = nullptr, *outdeg = nullptr;
   CKS(dalloc(&indeg, n));
   CKS(dalloc(&outdeg, n));
-  CK(hipMemcpyAsync(indeg, ix->r.deg, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s));
-  CK(hipMemcpyAsync(outdeg, ix->f.deg, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s));
-  CK(dbl::launch_fill_u32(ix->f.deg, 0u, n, s));
-  CK(dbl::launch_fill_u32(ix->r.deg, 0u, n, s));
-  CK(dbl::launch_scatter(src, dst, keep, m, ix->f, ix->r, s));
+  {
+    // per direction: partition the kept edges by vertex range, count degrees, reserve slack,
+    // lay out the rows, fill them in partition order
+    const uint32_t nbins = dbl::bin_count(n);
+    const uint32_t nblk = (uint32_t)std::max<uint64_t>(
+        1, std::min<uint64_t>(dbl::kBinBlocks, (m + 65535) / 65536));
+    uint32_t *counts = nullptr;
+    u64 *offs = nullptr, *tot = nullptr, *base = nullptr, *edges = nullptr;
+    dbl_status st = dalloc(&counts, (uint64_t)nblk * nbins);
+    if (st == DBL_OK) st = dalloc(&offs, (uint64_t)nblk * nbins);
+    if (st == DBL_OK) st = dalloc(&tot, nbins + 1);
+    if (st == DBL_OK) st = dalloc(&base, nbins + 1);
+    if (st == DBL_OK) st = dalloc(&edges, m);
+    for (uint32_t d = 0; d < 2 && st == DBL_OK; d++) {
+      Csr &g = d ? ix->r : ix->f;
+      uint64_t &total = d ? ix->r_total : ix->f_total;
+      hipError_t e = hipSuccess;
+      u64 kept = 0;
+      if (m) {
+        e = dbl::launch_bin_edges(d ? dst : src, d ? src : dst, keep, m, n, nblk, counts, offs,
+                                  tot, base, edges, s);
+        if (e == hipSuccess)
+          e = hipMemcpyAsync(&kept, base + nbins, sizeof(u64), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+      }
+      if (e == hipSuccess) e = dbl::launch_fill_u32(g.deg, 0u, n, s);
+      if (e == hipSuccess) e = dbl::launch_deg_binned(edges, kept, g.deg, s);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(d ? indeg : outdeg, g.deg, sizeof(uint32_t) * n,
+                           hipMemcpyDeviceToDevice, s);
+      if (e == hipSuccess)
+        e = dbl::launch_slack_cap(g.deg, g.cap, n, ix->slack_frac, ix->slack_min, s);
+      if (e == hipSuccess)
+        e = dbl::scan_exclusive(g.cap, g.off, n, ix->scan_tmp, ix->scan_total + d, s);
+      u64 t = 0;
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(&t, ix->scan_total + d, sizeof(u64), hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) {
+        st = from_hip(e);
+        break;
+      }
+      total = t;
+      st = dalloc(&g.col, total);
+      if (st != DBL_OK) break;
+      e = dbl::launch_fill_u32(g.deg, 0u, n, s);
+      if (e == hipSuccess) e = dbl::launch_fill_binned(edges, kept, g, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) st = from_hip(e);
+    }
+    dfree(counts);
+    dfree(offs);
+    dfree(tot);
+    dfree(base);
+    dfree(edges);
+    if (st != DBL_OK) {
+      dfree(indeg);
+      dfree(outdeg);
+      dfree(table);
+      dfree(keep);
+      return st;
+    }
+  }
   CK(hipStreamSynchronize(s));
   dfree(table);
   dfree(keep);

@@ -130,16 +130,27 @@ hipError_t launch_validate_pairs(const uint32_t *a, const uint32_t *b, uint64_t 
 hipError_t launch_dedup_mark(const uint32_t *src, const uint32_t *dst, uint64_t m,
                              unsigned long long *table, uint64_t mask, uint8_t *keep,
                              int assume_unique, hipStream_t s);
-hipError_t launch_degree_count(const uint32_t *src, const uint32_t *dst, const uint8_t *keep,
-                               uint64_t m, uint32_t *fdeg, uint32_t *rdeg, hipStream_t s);
 hipError_t launch_slack_cap(const uint32_t *deg, uint32_t *cap, uint32_t n, float frac,
                             uint32_t smin, hipStream_t s);
 // exclusive scan of cap[n] into off[n]; *total receives the sum. tmp: scan_tmp_words(n) words.
 uint64_t scan_tmp_words(uint32_t n);
 hipError_t scan_exclusive(const uint32_t *in, unsigned long long *out, uint32_t n, unsigned long long *tmp,
                           unsigned long long *total, hipStream_t s);
-hipError_t launch_scatter(const uint32_t *src, const uint32_t *dst, const uint8_t *keep,
-                          uint64_t m, Csr f, Csr r, hipStream_t s);
+// Binned ingest of one direction: partition the kept (key, val) edges by key range into
+// out[cnt] = key << 32 | val (base[nbins] receives cnt); nblk chunks (<= kBinBlocks);
+// counts/offs: nblk * bin_count(n) entries; tot, base: bin_count(n) + 1 entries.
+constexpr uint32_t kBinBlocks = 2048;
+uint32_t bin_shift(uint32_t n);
+inline uint32_t bin_count(uint32_t n) { return ((n - 1) >> bin_shift(n)) + 1; }
+hipError_t launch_bin_edges(const uint32_t *key, const uint32_t *val, const uint8_t *keep,
+                            uint64_t m, uint32_t n, uint32_t nblk, uint32_t *counts,
+                            unsigned long long *offs, unsigned long long *tot,
+                            unsigned long long *base, unsigned long long *out, hipStream_t s);
+// deg[key] += 1 per partitioned edge; rows filled from partitioned edges (g.deg zero on entry)
+hipError_t launch_deg_binned(const unsigned long long *edges, uint64_t cnt, uint32_t *deg,
+                             hipStream_t s);
+hipError_t launch_fill_binned(const unsigned long long *edges, uint64_t cnt, Csr g,
+                              hipStream_t s);
 
 // build: landmark selection. Writes the top-k vertex ids by (M desc, id asc) into out[k].
 // tmp_m / tmp_id: topk_tmp_entries(n) entries each.

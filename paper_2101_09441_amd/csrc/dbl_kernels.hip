@@ -346,23 +346,6 @@ hipError_t launch_dedup_mark(const uint32_t *src, const uint32_t *dst, uint64_t 
   return hipGetLastError();
 }
 
-__global__ void k_degree_count(const uint32_t *src, const uint32_t *dst, const uint8_t *keep,
-                               uint64_t m, uint32_t *fdeg, uint32_t *rdeg) {
-  for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < m;
-       e += (uint64_t)gridDim.x * blockDim.x) {
-    if (!keep[e]) continue;
-    atomicAdd(&fdeg[src[e]], 1u);
-    atomicAdd(&rdeg[dst[e]], 1u);
-  }
-}
-
-hipError_t launch_degree_count(const uint32_t *src, const uint32_t *dst, const uint8_t *keep,
-                               uint64_t m, uint32_t *fdeg, uint32_t *rdeg, hipStream_t s) {
-  if (m == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_degree_count, dim3(grid_for(m, 256, 16384)), dim3(256), 0, s, src, dst,
-                     keep, m, fdeg, rdeg);
-  return hipGetLastError();
-}
 
 __global__ void k_slack_cap(const uint32_t *deg, uint32_t *cap, uint32_t n, float frac,
                             uint32_t smin) {
@@ -462,24 +445,126 @@ hipError_t scan_exclusive(const uint32_t *in, u64 *out, uint32_t n, u64 *tmp, u6
   return hipGetLastError();
 }
 
-__global__ void k_scatter(const uint32_t *src, const uint32_t *dst, const uint8_t *keep,
-                          uint64_t m, Csr f, Csr r) {
-  for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < m;
-       e += (uint64_t)gridDim.x * blockDim.x) {
+// ---- binned ingest
+// Scattering edges straight into rows costs one random atomic and one random store per edge
+// and direction, spread over the whole graph. Instead the kept edges of one direction are first
+// partitioned by key range (bin = key >> shift, at most kMaxBins bins, each bin's edges
+// contiguous and bins in increasing key order); degree counts and row fills then walk the
+// partitioned edges in order, so the atomics and stores of neighbouring threads fall into the
+// rows of one or two bins at a time, a window that stays in cache.
+constexpr uint32_t kMaxBins = 4096;
+
+uint32_t bin_shift(uint32_t n) {
+  uint32_t sh = 0;
+  while (((uint64_t)(n - 1) >> sh) >= kMaxBins) sh++;
+  return sh;
+}
+
+// counts[b * nbins + bin]: kept edges of block b's chunk whose key falls in `bin`
+__global__ __launch_bounds__(256) void k_bin_hist(const uint32_t *key, const uint8_t *keep,
+                                                  uint64_t m, uint32_t shift, uint32_t nbins,
+                                                  uint64_t chunk, uint32_t *counts) {
+  __shared__ uint32_t hist[kMaxBins];
+  for (uint32_t i = threadIdx.x; i < nbins; i += 256u) hist[i] = 0;
+  __syncthreads();
+  const uint64_t lo = blockIdx.x * chunk, hi = min(m, lo + chunk);
+  for (uint64_t e = lo + threadIdx.x; e < hi; e += 256u)
+    if (keep[e]) atomicAdd(&hist[key[e] >> shift], 1u);
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < nbins; i += 256u)
+    counts[(uint64_t)blockIdx.x * nbins + i] = hist[i];
+}
+
+// offs[b * nbins + bin] = kept edges of `bin` in the chunks before block b; tot[bin] = all of
+// them. One thread per bin walks the blocks (loads of consecutive bins are coalesced).
+__global__ __launch_bounds__(256) void k_bin_colscan(const uint32_t *counts, uint32_t nbins,
+                                                     uint32_t nblk, u64 *offs, u64 *tot) {
+  const uint32_t bin = blockIdx.x * 256u + threadIdx.x;
+  if (bin >= nbins) return;
+  u64 run = 0;
+  for (uint32_t b = 0; b < nblk; b++) {
+    const uint64_t i = (uint64_t)b * nbins + bin;
+    const uint32_t c = counts[i];
+    offs[i] = run;
+    run += c;
+  }
+  tot[bin] = run;
+}
+
+// base[bin] = exclusive prefix of tot over bins; base[nbins] = total kept edges (nbins <= 4096:
+// one thread is enough)
+__global__ void k_bin_base(const u64 *tot, uint32_t nbins, u64 *base) {
+  u64 run = 0;
+  for (uint32_t i = 0; i < nbins; i++) {
+    base[i] = run;
+    run += tot[i];
+  }
+  base[nbins] = run;
+}
+
+// out[pos] = key << 32 | val for every kept edge, grouped by bin (order inside a bin is
+// arbitrary)
+__global__ __launch_bounds__(256) void k_bin_scatter(const uint32_t *key, const uint32_t *val,
+                                                     const uint8_t *keep, uint64_t m,
+                                                     uint32_t shift, uint32_t nbins,
+                                                     uint64_t chunk, const u64 *offs,
+                                                     const u64 *base, u64 *out) {
+  __shared__ u64 cur[kMaxBins];
+  for (uint32_t i = threadIdx.x; i < nbins; i += 256u)
+    cur[i] = base[i] + offs[(uint64_t)blockIdx.x * nbins + i];
+  __syncthreads();
+  const uint64_t lo = blockIdx.x * chunk, hi = min(m, lo + chunk);
+  for (uint64_t e = lo + threadIdx.x; e < hi; e += 256u) {
     if (!keep[e]) continue;
-    const uint32_t a = src[e], b = dst[e];
-    const uint32_t p = atomicAdd(&f.deg[a], 1u);
-    f.col[f.off[a] + p] = b;
-    const uint32_t q = atomicAdd(&r.deg[b], 1u);
-    r.col[r.off[b] + q] = a;
+    const uint32_t k = key[e];
+    const u64 pos = atomicAdd(&cur[k >> shift], 1ull);
+    out[pos] = ((u64)k << 32) | val[e];
   }
 }
 
-hipError_t launch_scatter(const uint32_t *src, const uint32_t *dst, const uint8_t *keep,
-                          uint64_t m, Csr f, Csr r, hipStream_t s) {
-  if (m == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_scatter, dim3(grid_for(m, 256, 16384)), dim3(256), 0, s, src, dst, keep,
-                     m, f, r);
+hipError_t launch_bin_edges(const uint32_t *key, const uint32_t *val, const uint8_t *keep,
+                            uint64_t m, uint32_t n, uint32_t nblk, uint32_t *counts, u64 *offs,
+                            u64 *tot, u64 *base, u64 *out, hipStream_t s) {
+  if (m == 0 || nblk == 0) return hipErrorInvalidValue;
+  const uint32_t shift = bin_shift(n), nbins = ((n - 1) >> shift) + 1;
+  const uint64_t chunk = (m + nblk - 1) / nblk;
+  hipLaunchKernelGGL(k_bin_hist, dim3(nblk), dim3(256), 0, s, key, keep, m, shift, nbins, chunk,
+                     counts);
+  hipLaunchKernelGGL(k_bin_colscan, dim3((nbins + 255) / 256), dim3(256), 0, s, counts, nbins,
+                     nblk, offs, tot);
+  hipLaunchKernelGGL(k_bin_base, dim3(1), dim3(1), 0, s, tot, nbins, base);
+  hipLaunchKernelGGL(k_bin_scatter, dim3(nblk), dim3(256), 0, s, key, val, keep, m, shift, nbins,
+                     chunk, offs, base, out);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_deg_binned(const u64 *edges, uint64_t cnt,
+                                                    uint32_t *deg) {
+  for (uint64_t e = blockIdx.x * 256ull + threadIdx.x; e < cnt; e += gridDim.x * 256ull)
+    atomicAdd(&deg[(uint32_t)(edges[e] >> 32)], 1u);
+}
+
+hipError_t launch_deg_binned(const u64 *edges, uint64_t cnt, uint32_t *deg, hipStream_t s) {
+  if (cnt == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_deg_binned, dim3(grid_for(cnt, 256, 4096)), dim3(256), 0, s, edges, cnt,
+                     deg);
+  return hipGetLastError();
+}
+
+// g.deg must be zero: it is counted up again while the rows fill
+__global__ __launch_bounds__(256) void k_fill_binned(const u64 *edges, uint64_t cnt, Csr g) {
+  for (uint64_t e = blockIdx.x * 256ull + threadIdx.x; e < cnt; e += gridDim.x * 256ull) {
+    const u64 kv = edges[e];
+    const uint32_t k = (uint32_t)(kv >> 32);
+    const uint32_t p = atomicAdd(&g.deg[k], 1u);
+    g.col[g.off[k] + p] = (uint32_t)kv;
+  }
+}
+
+hipError_t launch_fill_binned(const u64 *edges, uint64_t cnt, Csr g, hipStream_t s) {
+  if (cnt == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_binned, dim3(grid_for(cnt, 256, 4096)), dim3(256), 0, s, edges, cnt,
+                     g);
   return hipGetLastError();
 }
 
