@@ -822,11 +822,11 @@ dbl_status do_build(dbl_index *ix, uint64_t m, const uint32_t *src, const uint32
     const uint32_t nblk = (uint32_t)std::max<uint64_t>(
         1, std::min<uint64_t>(dbl::kBinBlocks, (m + 65535) / 65536));
     uint32_t *counts = nullptr;
-    u64 *offs = nullptr, *tot = nullptr, *base = nullptr, *edges = nullptr;
+    u64 *offs = nullptr, *btmp = nullptr, *bkept = nullptr, *edges = nullptr;
     dbl_status st = dalloc(&counts, (uint64_t)nblk * nbins);
     if (st == DBL_OK) st = dalloc(&offs, (uint64_t)nblk * nbins);
-    if (st == DBL_OK) st = dalloc(&tot, nbins + 1);
-    if (st == DBL_OK) st = dalloc(&base, nbins + 1);
+    if (st == DBL_OK) st = dalloc(&btmp, dbl::scan_tmp_words(nblk * nbins));
+    if (st == DBL_OK) st = dalloc(&bkept, 1);
     if (st == DBL_OK) st = dalloc(&edges, m);
     for (uint32_t d = 0; d < 2 && st == DBL_OK; d++) {
       Csr &g = d ? ix->r : ix->f;
@@ -835,13 +835,15 @@ dbl_status do_build(dbl_index *ix, uint64_t m, const uint32_t *src, const uint32
       u64 kept = 0;
       if (m) {
         e = dbl::launch_bin_edges(d ? dst : src, d ? src : dst, keep, m, n, nblk, counts, offs,
-                                  tot, base, edges, s);
+                                  btmp, bkept, edges, s);
         if (e == hipSuccess)
-          e = hipMemcpyAsync(&kept, base + nbins, sizeof(u64), hipMemcpyDeviceToHost, s);
+          e = hipMemcpyAsync(&kept, bkept, sizeof(u64), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
       }
-      if (e == hipSuccess) e = dbl::launch_fill_u32(g.deg, 0u, n, s);
-      if (e == hipSuccess) e = dbl::launch_deg_binned(edges, kept, g.deg, s);
+      if (e == hipSuccess && m)
+        e = dbl::launch_bin_rows(edges, offs, nblk, n, bkept, kept, g.deg, nullptr, s);
+      else if (e == hipSuccess)
+        e = dbl::launch_fill_u32(g.deg, 0u, n, s);
       if (e == hipSuccess)
         e = hipMemcpyAsync(d ? indeg : outdeg, g.deg, sizeof(uint32_t) * n,
                            hipMemcpyDeviceToDevice, s);
@@ -860,15 +862,14 @@ dbl_status do_build(dbl_index *ix, uint64_t m, const uint32_t *src, const uint32
       total = t;
       st = dalloc(&g.col, total);
       if (st != DBL_OK) break;
-      e = dbl::launch_fill_u32(g.deg, 0u, n, s);
-      if (e == hipSuccess) e = dbl::launch_fill_binned(edges, kept, g, s);
+      if (m) e = dbl::launch_bin_rows(edges, offs, nblk, n, bkept, kept, g.deg, &g, s);
       if (e == hipSuccess) e = hipStreamSynchronize(s);
       if (e != hipSuccess) st = from_hip(e);
     }
     dfree(counts);
     dfree(offs);
-    dfree(tot);
-    dfree(base);
+    dfree(btmp);
+    dfree(bkept);
     dfree(edges);
     if (st != DBL_OK) {
       dfree(indeg);

@@ -137,15 +137,21 @@ uint64_t scan_tmp_words(uint32_t n);
 hipError_t scan_exclusive(const uint32_t *in, unsigned long long *out, uint32_t n, unsigned long long *tmp,
                           unsigned long long *total, hipStream_t s);
 // Binned ingest of one direction: partition the kept (key, val) edges by key range into
-// out[cnt] = key << 32 | val (base[nbins] receives cnt); nblk chunks (<= kBinBlocks);
-// counts/offs: nblk * bin_count(n) entries; tot, base: bin_count(n) + 1 entries.
+// out[cnt] = key << 32 | val (*kept receives cnt); nblk chunks (<= kBinBlocks);
+// counts/offs: nblk * bin_count(n) entries; scan_tmp: scan_tmp_words(nblk * bin_count(n)).
 constexpr uint32_t kBinBlocks = 2048;
 uint32_t bin_shift(uint32_t n);
 inline uint32_t bin_count(uint32_t n) { return ((n - 1) >> bin_shift(n)) + 1; }
 hipError_t launch_bin_edges(const uint32_t *key, const uint32_t *val, const uint8_t *keep,
                             uint64_t m, uint32_t n, uint32_t nblk, uint32_t *counts,
-                            unsigned long long *offs, unsigned long long *tot,
-                            unsigned long long *base, unsigned long long *out, hipStream_t s);
+                            unsigned long long *offs, unsigned long long *scan_tmp,
+                            unsigned long long *kept, unsigned long long *out, hipStream_t s);
+// From partitioned edges (offs, nblk, kept as left by launch_bin_edges; kept_host = *kept):
+// g == nullptr: deg[v] = degree of v; else fill g's rows (g.off set; g.deg is the degree and
+// stays so).
+hipError_t launch_bin_rows(const unsigned long long *edges, const unsigned long long *offs,
+                           uint32_t nblk, uint32_t n, const unsigned long long *kept,
+                           uint64_t kept_host, uint32_t *deg, const Csr *g, hipStream_t s);
 // deg[key] += 1 per partitioned edge; rows filled from partitioned edges (g.deg zero on entry)
 hipError_t launch_deg_binned(const unsigned long long *edges, uint64_t cnt, uint32_t *deg,
                              hipStream_t s);

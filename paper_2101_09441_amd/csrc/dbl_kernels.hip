@@ -460,7 +460,8 @@ uint32_t bin_shift(uint32_t n) {
   return sh;
 }
 
-// counts[b * nbins + bin]: kept edges of block b's chunk whose key falls in `bin`
+// counts[bin * nblk + b]: kept edges of block b's chunk whose key falls in `bin` (bin-major, so
+// one exclusive scan over the array gives every (bin, block) its output offset)
 __global__ __launch_bounds__(256) void k_bin_hist(const uint32_t *key, const uint8_t *keep,
                                                   uint64_t m, uint32_t shift, uint32_t nbins,
                                                   uint64_t chunk, uint32_t *counts) {
@@ -472,34 +473,7 @@ __global__ __launch_bounds__(256) void k_bin_hist(const uint32_t *key, const uin
     if (keep[e]) atomicAdd(&hist[key[e] >> shift], 1u);
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < nbins; i += 256u)
-    counts[(uint64_t)blockIdx.x * nbins + i] = hist[i];
-}
-
-// offs[b * nbins + bin] = kept edges of `bin` in the chunks before block b; tot[bin] = all of
-// them. One thread per bin walks the blocks (loads of consecutive bins are coalesced).
-__global__ __launch_bounds__(256) void k_bin_colscan(const uint32_t *counts, uint32_t nbins,
-                                                     uint32_t nblk, u64 *offs, u64 *tot) {
-  const uint32_t bin = blockIdx.x * 256u + threadIdx.x;
-  if (bin >= nbins) return;
-  u64 run = 0;
-  for (uint32_t b = 0; b < nblk; b++) {
-    const uint64_t i = (uint64_t)b * nbins + bin;
-    const uint32_t c = counts[i];
-    offs[i] = run;
-    run += c;
-  }
-  tot[bin] = run;
-}
-
-// base[bin] = exclusive prefix of tot over bins; base[nbins] = total kept edges (nbins <= 4096:
-// one thread is enough)
-__global__ void k_bin_base(const u64 *tot, uint32_t nbins, u64 *base) {
-  u64 run = 0;
-  for (uint32_t i = 0; i < nbins; i++) {
-    base[i] = run;
-    run += tot[i];
-  }
-  base[nbins] = run;
+    counts[(uint64_t)i * gridDim.x + blockIdx.x] = hist[i];
 }
 
 // out[pos] = key << 32 | val for every kept edge, grouped by bin (order inside a bin is
@@ -507,11 +481,10 @@ __global__ void k_bin_base(const u64 *tot, uint32_t nbins, u64 *base) {
 __global__ __launch_bounds__(256) void k_bin_scatter(const uint32_t *key, const uint32_t *val,
                                                      const uint8_t *keep, uint64_t m,
                                                      uint32_t shift, uint32_t nbins,
-                                                     uint64_t chunk, const u64 *offs,
-                                                     const u64 *base, u64 *out) {
+                                                     uint64_t chunk, const u64 *offs, u64 *out) {
   __shared__ u64 cur[kMaxBins];
   for (uint32_t i = threadIdx.x; i < nbins; i += 256u)
-    cur[i] = base[i] + offs[(uint64_t)blockIdx.x * nbins + i];
+    cur[i] = offs[(uint64_t)i * gridDim.x + blockIdx.x];
   __syncthreads();
   const uint64_t lo = blockIdx.x * chunk, hi = min(m, lo + chunk);
   for (uint64_t e = lo + threadIdx.x; e < hi; e += 256u) {
@@ -524,18 +497,97 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const uint32_t *key, const 
 
 hipError_t launch_bin_edges(const uint32_t *key, const uint32_t *val, const uint8_t *keep,
                             uint64_t m, uint32_t n, uint32_t nblk, uint32_t *counts, u64 *offs,
-                            u64 *tot, u64 *base, u64 *out, hipStream_t s) {
+                            u64 *scan_tmp, u64 *kept, u64 *out, hipStream_t s) {
   if (m == 0 || nblk == 0) return hipErrorInvalidValue;
   const uint32_t shift = bin_shift(n), nbins = ((n - 1) >> shift) + 1;
   const uint64_t chunk = (m + nblk - 1) / nblk;
   hipLaunchKernelGGL(k_bin_hist, dim3(nblk), dim3(256), 0, s, key, keep, m, shift, nbins, chunk,
                      counts);
-  hipLaunchKernelGGL(k_bin_colscan, dim3((nbins + 255) / 256), dim3(256), 0, s, counts, nbins,
-                     nblk, offs, tot);
-  hipLaunchKernelGGL(k_bin_base, dim3(1), dim3(1), 0, s, tot, nbins, base);
+  hipError_t e = scan_exclusive(counts, offs, nbins * nblk, scan_tmp, kept, s);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_bin_scatter, dim3(nblk), dim3(256), 0, s, key, val, keep, m, shift, nbins,
-                     chunk, offs, base, out);
+                     chunk, offs, out);
   return hipGetLastError();
+}
+
+// One workgroup per bin (while a bin spans at most kBinVerts vertices): the bin's edges are
+// contiguous, so degrees and row cursors are counted in LDS, degrees are written in order and
+// row writes stay within the bin's rows; no global atomics.
+constexpr uint32_t kBinVerts = 16384, kBinNT = 1024;
+
+__device__ __forceinline__ void bin_range(const u64 *offs, uint32_t nblk, uint32_t nbins,
+                                          u64 kept, uint32_t bin, u64 &lo, u64 &hi) {
+  lo = offs[(uint64_t)bin * nblk];
+  hi = bin + 1 < nbins ? offs[(uint64_t)(bin + 1) * nblk] : kept;
+}
+
+__global__ __launch_bounds__(kBinNT) void k_bin_deg(const u64 *edges, const u64 *offs,
+                                                    uint32_t nblk, uint32_t nbins,
+                                                    uint32_t shift, const u64 *kept, uint32_t n,
+                                                    uint32_t *deg) {
+  __shared__ uint32_t cnt[kBinVerts];
+  for (uint32_t bin = blockIdx.x; bin < nbins; bin += gridDim.x) {
+    const uint32_t first = bin << shift, nv = min(1u << shift, n - first);
+    for (uint32_t i = threadIdx.x; i < nv; i += kBinNT) cnt[i] = 0;
+    __syncthreads();
+    u64 lo, hi;
+    bin_range(offs, nblk, nbins, *kept, bin, lo, hi);
+    for (u64 e = lo + threadIdx.x; e < hi; e += kBinNT)
+      atomicAdd(&cnt[(uint32_t)(edges[e] >> 32) - first], 1u);
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < nv; i += kBinNT) deg[first + i] = cnt[i];
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kBinNT) void k_bin_fill(const u64 *edges, const u64 *offs,
+                                                     uint32_t nblk, uint32_t nbins,
+                                                     uint32_t shift, const u64 *kept, uint32_t n,
+                                                     Csr g) {
+  __shared__ uint32_t cur[kBinVerts];
+  for (uint32_t bin = blockIdx.x; bin < nbins; bin += gridDim.x) {
+    const uint32_t first = bin << shift, nv = min(1u << shift, n - first);
+    for (uint32_t i = threadIdx.x; i < nv; i += kBinNT) cur[i] = 0;
+    __syncthreads();
+    u64 lo, hi;
+    bin_range(offs, nblk, nbins, *kept, bin, lo, hi);
+    for (u64 e = lo + threadIdx.x; e < hi; e += kBinNT) {
+      const u64 kv = edges[e];
+      const uint32_t k = (uint32_t)(kv >> 32);
+      const uint32_t p = atomicAdd(&cur[k - first], 1u);
+      g.col[g.off[k] + p] = (uint32_t)kv;
+    }
+    __syncthreads();
+  }
+}
+
+// Degrees (deg[key] = edges of key) and row fill of partitioned edges. Rows are filled from
+// position 0; deg is left as the degree.
+hipError_t launch_bin_rows(const u64 *edges, const u64 *offs, uint32_t nblk, uint32_t n,
+                           const u64 *kept, uint64_t kept_host, uint32_t *deg, const Csr *g,
+                           hipStream_t s) {
+  const uint32_t shift = bin_shift(n), nbins = ((n - 1) >> shift) + 1;
+  if ((1u << shift) <= kBinVerts) {
+    const uint32_t grid = min(nbins, 8192u);
+    if (!g) {
+      hipLaunchKernelGGL(k_bin_deg, dim3(grid), dim3(kBinNT), 0, s, edges, offs, nblk, nbins,
+                         shift, kept, n, deg);
+    } else {
+      hipLaunchKernelGGL(k_bin_fill, dim3(grid), dim3(kBinNT), 0, s, edges, offs, nblk, nbins,
+                         shift, kept, n, *g);
+    }
+    return hipGetLastError();
+  }
+  // very large vertex counts: bins too wide for LDS counters, count with global atomics
+  hipError_t e;
+  if (!g) {
+    e = launch_fill_u32(deg, 0u, n, s);
+    if (e == hipSuccess) e = launch_deg_binned(edges, kept_host, deg, s);
+    return e;
+  }
+  e = launch_fill_u32(g->deg, 0u, n, s);
+  if (e == hipSuccess) e = launch_fill_binned(edges, kept_host, *g, s);
+  return e;
 }
 
 __global__ __launch_bounds__(256) void k_deg_binned(const u64 *edges, uint64_t cnt,
