@@ -335,6 +335,7 @@ dbl::PropArgs prop_args(const dbl_index *ix) {
   a.pheavy_list = ix->heavy_list ? ix->heavy_list + ix->heavy_cap : nullptr;
   a.heavy_cap = ix->heavy_cap;
   a.fbm = ix->fbm;
+  a.fbm_wpd = ix->fbm_words / 2;
   a.pcnt = ix->pcnt;
   a.local_max_frontier = ix->local_max_frontier;
   a.local_max_edges = ix->local_max_edges;
@@ -465,7 +466,7 @@ dbl_status grid_propagate(dbl_index *ix, hipStream_t s, uint32_t group, uint64_t
     uint32_t grid = (uint32_t)std::min<uint64_t>(gmax, std::max<uint64_t>(std::min(64u, gmax),
                                                                           (fsz + 255) / 256));
     if (ix->pull_threshold) {
-      const uint64_t words = (2ull * ix->n + 63) / 64;
+      const uint64_t words = 2 * (((uint64_t)ix->n + 63) / 64);
       if (words > ix->fbm_words) {
         dfree(ix->fbm);
         ix->fbm = nullptr;
@@ -474,7 +475,7 @@ dbl_status grid_propagate(dbl_index *ix, hipStream_t s, uint32_t group, uint64_t
         ix->fbm_words = words;
       }
       dbl::PropArgs a = prop_args(ix);
-      CK(dbl::launch_frontier_scan(a, cur, stamp, words, s));
+      CK(dbl::launch_frontier_scan(a, cur, stamp, ix->fbm_words, s));
       CKS(sync_ctl(ix, s));
       uint32_t pull = 0;
       // the scan counted every entry of the frontier once; anything else: push them all

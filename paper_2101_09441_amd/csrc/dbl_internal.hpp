@@ -184,7 +184,8 @@ struct PropArgs {
   unsigned long long *heavy_list;
   unsigned long long *pheavy_list;  // chunks of the pull round (same capacity)
   uint64_t heavy_cap;
-  unsigned long long *fbm;          // frontier bitmap of the pull round: bit 2x + direction
+  unsigned long long *fbm;          // frontier bitmaps of the pull round, one per direction:
+  uint64_t fbm_wpd;                 // bit x of fbm[dir * fbm_wpd + x / 64]
   unsigned long long *pcnt;  // [kPropCtrSlots * 2] per-block (expanded, relaxed) counters
   uint32_t local_max_frontier, local_max_edges;
   Ctl *ctl;

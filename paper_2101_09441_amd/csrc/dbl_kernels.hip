@@ -75,6 +75,21 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t *s_wsum
   return off + incl - x;
 }
 
+// Append `val` to q for every thread with `pred`, with one atomic on the queue counter per
+// block (for kernels where whole waves push at once and the counter would otherwise see one
+// atomic per wave). Every thread of the block must call it.
+template <int NT>
+__device__ __forceinline__ void block_push(uint32_t *q, uint32_t *cnt, bool pred, uint32_t val,
+                                           uint32_t *s_wsum, uint32_t *s_base) {
+  uint32_t total;
+  const uint32_t ex = block_excl_scan<NT>(pred ? 1u : 0u, s_wsum, total);
+  if (total == 0) return;
+  if (threadIdx.x == 0) *s_base = atomicAdd(cnt, total);
+  __syncthreads();
+  if (pred) q[*s_base + ex] = val;
+  __syncthreads();
+}
+
 __device__ __forceinline__ u64 ld_agent(const u64 *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -763,8 +778,11 @@ hipError_t launch_seed(LabelsView L, uint32_t n, const uint32_t *landmarks, uint
 }
 
 template <int W>
-__global__ void k_init_frontier(const u64 *lab, uint32_t n, Csr f, Csr r, uint32_t *frontier,
-                                Ctl *ctl, uint32_t ring, uint32_t *inq, uint32_t stamp) {
+__global__ __launch_bounds__(256) void k_init_frontier(const u64 *lab, uint32_t n, Csr f, Csr r,
+                                                       uint32_t *frontier, Ctl *ctl,
+                                                       uint32_t ring, uint32_t *inq,
+                                                       uint32_t stamp) {
+  __shared__ uint32_t s_wsum[4], s_base;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     ctl->heavy[0] = 0;
     ctl->heavy[1] = 0;
@@ -778,8 +796,8 @@ __global__ void k_init_frontier(const u64 *lab, uint32_t n, Csr f, Csr r, uint32
       if (pf) inq[2ull * x] = stamp;
       if (pb) inq[2ull * x + 1] = stamp;
     }
-    wave_push(frontier, &ctl->fsize[ring], pf, x);
-    wave_push(frontier, &ctl->fsize[ring], pb, x | kDirBit);
+    block_push<256>(frontier, &ctl->fsize[ring], pf, x, s_wsum, &s_base);
+    block_push<256>(frontier, &ctl->fsize[ring], pb, x | kDirBit, s_wsum, &s_base);
   }
 }
 
@@ -942,9 +960,11 @@ hipError_t launch_round(const PropArgs &a, uint32_t ring, uint32_t stamp, uint32
 // without atomics (a row has one owner thread), so it moves far less memory per relaxation than
 // scattered pushes with their atomics and queue claims.
 
-__device__ __forceinline__ bool in_frontier(const u64 *fbm, uint32_t x, uint32_t dir) {
-  const u64 b = 2ull * x + dir;
-  return (fbm[b >> 6] >> (b & 63u)) & 1ull;
+// One bitmap per direction (a pull of one direction tests only its own, half the footprint of
+// an interleaved layout, which matters for staying in L2): bit x of fbm[dir * wpd ...].
+__device__ __forceinline__ bool in_frontier(const u64 *fbm, uint64_t wpd, uint32_t x,
+                                            uint32_t dir) {
+  return (fbm[dir * wpd + (x >> 6)] >> (x & 63u)) & 1ull;
 }
 
 __global__ __launch_bounds__(256) void k_frontier_scan(PropArgs a, uint32_t ring,
@@ -966,8 +986,7 @@ __global__ __launch_bounds__(256) void k_frontier_scan(PropArgs a, uint32_t ring
     const uint32_t e = a.fq[ring][i];
     const uint32_t d = e >> 31, x = e & kIdMask;
     const uint32_t dg = d ? min(a.r.deg[x], a.r.cap[x]) : min(a.f.deg[x], a.f.cap[x]);
-    const u64 b = 2ull * x + d;
-    atomicOr(&a.fbm[b >> 6], 1ull << (b & 63u));
+    atomicOr(&a.fbm[d * a.fbm_wpd + (x >> 6)], 1ull << (x & 63u));
     if (d) {
       v[1] += 1;
       v[3] += dg;
@@ -1045,6 +1064,7 @@ __global__ __launch_bounds__(256) void k_pull(PropArgs a, uint32_t n, uint32_t d
   __shared__ uint32_t s_row[256];
   __shared__ uint32_t s_wsum[4];
   __shared__ u64 s_acc[256][2 * W];
+  __shared__ uint32_t s_base;
   Ctl *ctl = a.ctl;
   const uint32_t t = threadIdx.x;
   const uint32_t ndir = __popc(dmask);
@@ -1094,7 +1114,7 @@ __global__ __launch_bounds__(256) void k_pull(PropArgs a, uint32_t n, uint32_t d
         const uint32_t rd = s_row[lo] >> 31;
         const uint32_t *col = rd ? a.f.col : a.r.col;
         const uint32_t p = col[s_off[lo] + (e - s_start[lo])];
-        if (in_frontier(a.fbm, p, rd)) {
+        if (in_frontier(a.fbm, a.fbm_wpd, p, rd)) {
           hit = true;
           lv = ld_half<W>(half_ptr<W>(a.L.lab, p, rd));
           relaxed++;
@@ -1118,7 +1138,7 @@ __global__ __launch_bounds__(256) void k_pull(PropArgs a, uint32_t n, uint32_t d
       }
       push = grew && claim(&a.inq[2ull * y + d], nstamp);
     }
-    wave_push(a.fq[nring], &ctl->fsize[nring], push, y | (d << 31));
+    block_push<256>(a.fq[nring], &ctl->fsize[nring], push, y | (d << 31), s_wsum, &s_base);
     __syncthreads();
   }
   __shared__ u64 s_tmp[4];
@@ -1150,7 +1170,7 @@ __global__ __launch_bounds__(256) void k_pull_heavy(PropArgs a, uint32_t nring,
       Half<W> lv = {};
       if (e < e_end) {
         const uint32_t p = g.col[o + e];
-        if (in_frontier(a.fbm, p, d)) {
+        if (in_frontier(a.fbm, a.fbm_wpd, p, d)) {
           hit = true;
           lv = ld_half<W>(half_ptr<W>(a.L.lab, p, d));
           relaxed++;
