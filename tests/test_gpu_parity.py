@@ -504,6 +504,49 @@ def test_empty_loops_duplicates_and_degenerate_graphs():
     assert_queries_equal(g, o, u, v)
 
 
+def test_wide_vertex_range_ingest_fallback():
+    """Above 2^26 vertices a bin spans more vertices than LDS counters hold, and the build
+    counts degrees and fills rows with global atomics instead. A 3,000-vertex R-MAT graph is
+    spread over 2^26 + 3 ids (every other id isolated); with the same explicit landmarks and
+    leaf hash, its labels and answers must equal the oracle's on the compact graph, and an
+    isolated vertex carries only its own BL bit."""
+    n_big = (1 << 26) + 3
+    w = dblgen.make_rmat_workload("wide", 11, 13, draws=8 << 11, n_insert=500,
+                                  insert_kind="uniform", n_query=20000, query_kind="mixed")
+    rng = np.random.default_rng(17)
+    ids = np.sort(rng.choice(n_big - 2, size=w.n - 2, replace=False) + 1)
+    ids = np.concatenate([[0], ids, [n_big - 1]]).astype(np.uint32)  # compact -> wide
+    kp = 64
+    bucket_big = rng.integers(0, kp, n_big).astype(np.uint8)
+    o = oracle.OracleIndex(w.n, w.src, w.dst)
+    lm_small = o.select_landmarks(16)
+    o.build(k=16, kp=kp, landmarks=lm_small, bucket_table=bucket_big[ids], threads=8)
+    g = gpu_index(n_big, ids[w.src], ids[w.dst], num_landmarks=16, bl_bits=kp,
+                  landmarks=ids[lm_small], leaf_bucket=bucket_big, bfs_slots=64)
+
+    def check(what):
+        got = g.labels()
+        t_ids = torch.from_numpy(ids.astype(np.int64)).to(got[0].device)
+        for name, a, b in zip(("DL_in", "DL_out", "BL_in", "BL_out"), got, o.labels()):
+            sub = a[t_ids].cpu().numpy().view(np.uint64)
+            assert np.array_equal(sub, b), f"{what}: {name} differs on the graph's vertices"
+        iso = torch.from_numpy(rng.choice(n_big, 200000).astype(np.int64)).to(got[0].device)
+        iso = iso[~torch.isin(iso, t_ids)]
+        own = torch.from_numpy(bucket_big.astype(np.int64)).to(got[0].device)[iso]
+        assert torch.all(got[0][iso] == 0) and torch.all(got[1][iso] == 0), what
+        assert torch.equal(got[2][iso], torch.ones_like(own) << own), what
+        assert torch.equal(got[3][iso], torch.ones_like(own) << own), what
+
+    check("build")
+    qa = g.query(dev(ids[w.q_u]), dev(ids[w.q_v])).cpu().numpy()
+    assert np.array_equal(qa, o.query_dbl(w.q_u, w.q_v, threads=8))
+    g.insert_edges(dev(ids[w.ins_src]), dev(ids[w.ins_dst]))
+    o.insert(w.ins_src, w.ins_dst)
+    check("after insertions")
+    qa = g.query(dev(ids[w.q_u]), dev(ids[w.q_v])).cpu().numpy()
+    assert np.array_equal(qa, o.query_dbl(w.q_u, w.q_v, threads=8))
+
+
 def test_long_chain_many_rounds():
     """A 20,000-vertex path: propagation needs one round per hop, grid and local forms both."""
     n = 20000
