@@ -445,21 +445,27 @@ def main():
                                                       "local_max_edges", "round_grid")}}
             if bsz == 1000:
                 qtuned = autotune.tune_queries(ix, qu, qv, qb, w.m)
-                qout = torch.empty_like(out)
-                qt = []
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                for lo in range(0, n_q, qb):
-                    tb = time.perf_counter()
-                    ix.query(qu[lo:lo + qb], qv[lo:lo + qb], out=qout[lo:lo + qb])
-                    qt.append(time.perf_counter() - tb)
-                t_q = time.perf_counter() - t0
-                res["query_batches_65536"] = {
-                    "queries_per_s": n_q / t_q, "batches": len(qt),
-                    "batch_ms_p50": float(np.percentile(qt, 50) * 1e3),
-                    "batch_ms_p99": float(np.percentile(qt, 99) * 1e3),
-                    "answers_equal_plain": bool(torch.equal(qout, plain_answers)),
-                    "tuning": {"bfs_slots": qtuned["bfs_slots"]}}
+                # each batch as two kernel launches, then as one graph launch (the graph is
+                # instantiated by an untimed first batch and replayed with new arguments)
+                for graph in (0, 1):
+                    ix.set_tuning(query_graph=graph)
+                    qout = torch.empty_like(out)
+                    ix.query(qu[:qb], qv[:qb], out=qout[:qb])
+                    qt = []
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    for lo in range(0, n_q, qb):
+                        tb = time.perf_counter()
+                        ix.query(qu[lo:lo + qb], qv[lo:lo + qb], out=qout[lo:lo + qb])
+                        qt.append(time.perf_counter() - tb)
+                    t_q = time.perf_counter() - t0
+                    res["query_batches_65536" + ("_graph" if graph else "")] = {
+                        "queries_per_s": n_q / t_q, "batches": len(qt),
+                        "batch_ms_p50": float(np.percentile(qt, 50) * 1e3),
+                        "batch_ms_p99": float(np.percentile(qt, 99) * 1e3),
+                        "answers_equal_plain": bool(torch.equal(qout, plain_answers)),
+                        "tuning": {"bfs_slots": qtuned["bfs_slots"], "query_graph": graph}}
+                ix.set_tuning(query_graph=0)
             res[f"insert_batch_{bsz}"] = entry
             ix.close()
         return res

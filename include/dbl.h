@@ -234,7 +234,7 @@ typedef struct {
    off), optionally followed by ":N" to time one launch in every N of each kind (the first, the
    N+1-th, ...). Enabling clears the accumulated times. Kinds: insert_small, insert_apply, local_rounds,
    insert_server (one request-server launch), round (one grid propagation round), query_label,
-   query_bfs. */
+   query_bfs, query_graph (one graph launch of a query batch). */
 dbl_status dbl_time_kernels(dbl_index *ix, const char *kinds);
 
 /* Copy up to `cap` per-kind records (kinds with at least one launch) to HOST array h_out;
@@ -263,6 +263,9 @@ typedef struct {
                                   pushes otherwise; 0 = always push (default 128) */
   uint32_t server_polls;       /* reads of the doorbell the request server keeps in flight: 1 or
                                   4 (default 4) */
+  uint32_t query_graph;        /* 1: each query batch is one HIP graph launch (label kernel, then
+                                  the BFS kernel), instantiated once per query context and replayed
+                                  with the batch's arguments; 0 (default): two kernel launches */
 } dbl_tuning;
 
 dbl_status dbl_get_tuning(const dbl_index *ix, dbl_tuning *out);

@@ -82,6 +82,7 @@ class DblTuning(ctypes.Structure):
         ("server_idle_us", ctypes.c_uint32),
         ("pull_threshold", ctypes.c_uint32),
         ("server_polls", ctypes.c_uint32),
+        ("query_graph", ctypes.c_uint32),
     ]
 
 
@@ -451,8 +452,8 @@ class Index:
 
     def set_tuning(self, **kw) -> None:
         """Change tuning fields (small_batch, local_max_frontier, local_max_edges, round_grid,
-        bfs_slots, insert_server, server_idle_us, pull_threshold, server_polls); results never
-        change."""
+        bfs_slots, insert_server, server_idle_us, pull_threshold, server_polls, query_graph);
+        results never change."""
         cur = self.tuning()
         bad = set(kw) - set(cur)
         if bad:

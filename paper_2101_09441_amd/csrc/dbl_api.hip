@@ -41,6 +41,12 @@ struct dbl_query_ctx {
   u64 *gvis = nullptr;     // whole-device BFS: visited bitmap and frontier ring
   uint32_t *gfq[3] = {nullptr, nullptr, nullptr};
   uint64_t bfs_heavy = 0;
+  // graph form of a batch (label kernel -> BFS kernel), instantiated on first use and
+  // replayed with new node arguments
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  hipGraphNode_t gn_label = nullptr, gn_bfs = nullptr;
+  uint32_t g_words = 0;
 };
 
 struct dbl_index {
@@ -83,6 +89,7 @@ struct dbl_index {
   uint32_t round_grid = dbl::kRoundGridMax;
   uint32_t insert_server = 1;  // dbl_insert_edges_each through the request server
   uint32_t pull_threshold = 128;  // pull a direction when its push edges >= this/1024 of its edges
+  uint32_t query_graph = 0;       // query batches as one graph launch
   // query contexts: the default one and those created by callers (guarded by ctx_mu)
   uint32_t slots_opt = 0, qcap_opt = 0;
   dbl_query_ctx *qctx = nullptr;
@@ -115,11 +122,12 @@ enum TimedKind : uint32_t {
   kTRound,
   kTQueryLabel,
   kTQueryBfs,
+  kTQueryGraph,
   kTKinds
 };
 const char *const kKindNames[kTKinds] = {"insert_small", "insert_apply", "local_rounds",
                                          "insert_server", "round",
-                                         "query_label", "query_bfs"};
+                                         "query_label", "query_bfs", "query_graph"};
 
 hipEvent_t take_event(dbl_index *ix) {
   if (!ix->spare.empty()) {
@@ -582,6 +590,10 @@ uint64_t ctx_bytes(const dbl_index *ix, uint32_t slots, uint32_t qcap, uint64_t 
 }
 
 void ctx_free(dbl_query_ctx *c) {
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->gexec = nullptr;
+  c->graph = nullptr;
   dfree(c->ctl);
   hfree(c->mirror);
   c->mirror = nullptr;
@@ -694,11 +706,6 @@ dbl_status run_queries(dbl_index *ix, dbl_query_ctx *c, uint64_t count, const ui
                        const uint32_t *d_v, uint8_t *d_out, hipStream_t s,
                        uint32_t rules = DBL_RULES_ALL) {
   CKS(ctx_reserve(c, count));
-  {
-    Timed tm(ix, c->is_default ? (uint32_t)kTQueryLabel : (uint32_t)kTKinds, s);
-    CK(dbl::launch_query_label({ix->lab, ix->lw}, d_u, d_v, count, ix->n, ix->f.deg, d_out, c->und,
-                               c->seg, c->ctl, c->qcls, rules, s));
-  }
   dbl::BfsArgs b;
   b.L = {ix->lab, ix->lw};
   b.f = ix->f;
@@ -717,7 +724,41 @@ dbl_status run_queries(dbl_index *ix, dbl_query_ctx *c, uint64_t count, const ui
   b.rules = rules;
   b.ctl = c->ctl;
   const uint32_t seq = ++c->seq;
-  {
+  if (ix->query_graph) {
+    // one graph launch per batch: instantiate once, then replay with this batch's arguments
+    const u64 *lab = ix->lab;
+    uint32_t n = ix->n;
+    const uint32_t *fdeg = ix->f.deg;
+    void *la[12] = {(void *)&lab, (void *)&d_u, (void *)&d_v, (void *)&count, (void *)&n,
+                    (void *)&fdeg, (void *)&d_out, (void *)&c->und, (void *)&c->seg,
+                    (void *)&c->ctl, (void *)&c->qcls, (void *)&rules};
+    dbl::Mirror *mirror = c->mirror;
+    uint32_t sq = seq;
+    void *ba[3] = {(void *)&b, (void *)&mirror, (void *)&sq};
+    hipKernelNodeParams lp, bp;
+    CK(dbl::query_node_params({ix->lab, ix->lw}, count, c->slots, la, ba, &lp, &bp));
+    if (!c->gexec || c->g_words != ix->lw) {
+      if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+      if (c->graph) (void)hipGraphDestroy(c->graph);
+      c->gexec = nullptr;
+      c->graph = nullptr;
+      CK(hipGraphCreate(&c->graph, 0));
+      CK(hipGraphAddKernelNode(&c->gn_label, c->graph, nullptr, 0, &lp));
+      CK(hipGraphAddKernelNode(&c->gn_bfs, c->graph, &c->gn_label, 1, &bp));
+      CK(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+      c->g_words = ix->lw;
+    } else {
+      CK(hipGraphExecKernelNodeSetParams(c->gexec, c->gn_label, &lp));
+      CK(hipGraphExecKernelNodeSetParams(c->gexec, c->gn_bfs, &bp));
+    }
+    Timed tm(ix, c->is_default ? (uint32_t)kTQueryGraph : (uint32_t)kTKinds, s);
+    CK(hipGraphLaunch(c->gexec, s));
+  } else {
+    {
+      Timed tm(ix, c->is_default ? (uint32_t)kTQueryLabel : (uint32_t)kTKinds, s);
+      CK(dbl::launch_query_label({ix->lab, ix->lw}, d_u, d_v, count, ix->n, ix->f.deg, d_out,
+                                 c->und, c->seg, c->ctl, c->qcls, rules, s));
+    }
     Timed tm(ix, c->is_default ? (uint32_t)kTQueryBfs : (uint32_t)kTKinds, s);
     CK(dbl::launch_query_bfs(b, c->slots, c->mirror, seq, s));
   }
@@ -1489,6 +1530,7 @@ dbl_status dbl_get_tuning(const dbl_index *ix, dbl_tuning *out) {
   out->server_idle_us = ix->server_idle_us;
   out->pull_threshold = ix->pull_threshold;
   out->server_polls = ix->server_polls;
+  out->query_graph = ix->query_graph;
   out->bfs_slots = ix->qctx ? ix->qctx->slots : (ix->slots_opt ? ix->slots_opt : 1024);
   return DBL_OK;
 }
@@ -1498,7 +1540,7 @@ dbl_status dbl_set_tuning(dbl_index *ix, const dbl_tuning *t) {
   if (t->small_batch > dbl::kSmallBatchMax || t->round_grid == 0 ||
       t->round_grid > dbl::kRoundGridMax || t->bfs_slots > (1u << 16) || t->insert_server > 1 ||
       t->server_idle_us > 10000000 || t->pull_threshold > 1u << 20 ||
-      (t->server_polls != 1 && t->server_polls != 4))
+      (t->server_polls != 1 && t->server_polls != 4) || t->query_graph > 1)
     return DBL_ERR_INVALID_ARG;
   DeviceGuard dg(ix->device);
   ix->small_batch = t->small_batch;
@@ -1509,6 +1551,7 @@ dbl_status dbl_set_tuning(dbl_index *ix, const dbl_tuning *t) {
   ix->server_idle_us = t->server_idle_us;
   ix->pull_threshold = t->pull_threshold;
   ix->server_polls = t->server_polls;
+  ix->query_graph = t->query_graph;
   const uint32_t slots = t->bfs_slots ? std::max<uint32_t>(4, (t->bfs_slots + 3) / 4 * 4) : 0;
   if (slots && (!ix->qctx || ix->qctx->slots != slots)) {
     // rebuild the index's own query context with the new slot count (its counters are kept)

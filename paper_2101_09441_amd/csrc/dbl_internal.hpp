@@ -252,6 +252,12 @@ struct BfsArgs {
 // The last wave to finish publishes the context's status (mirror m, sequence seq).
 hipError_t launch_query_bfs(const BfsArgs &a, uint32_t slots, Mirror *m, uint32_t seq,
                             hipStream_t s);
+// Kernel-node parameters of the two query kernels (for a graph). label_args points to the 12
+// arguments of the label kernel in order (lab, u, v, count, n, fdeg, out, und, seg, ctl, qcls,
+// rules); bfs_args to the 3 of the BFS kernel (BfsArgs, mirror, seq).
+hipError_t query_node_params(LabelsView L, uint64_t count, uint32_t slots, void **label_args,
+                             void **bfs_args, hipKernelNodeParams *label,
+                             hipKernelNodeParams *bfs);
 // grid BFS for one query (u, v) whose slot overflowed
 hipError_t launch_gbfs_start(const PropArgs &a, unsigned long long *vis, uint64_t vis_words,
                              uint32_t u, hipStream_t s);

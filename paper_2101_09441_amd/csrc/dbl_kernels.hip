@@ -1906,6 +1906,31 @@ hipError_t launch_query_bfs(const BfsArgs &a, uint32_t slots, Mirror *m, uint32_
   return hipGetLastError();
 }
 
+// Graph-node form of a query batch: the two kernels of launch_query_label and
+// launch_query_bfs with their launch shapes and arguments (pointed to, in kernel order).
+hipError_t query_node_params(LabelsView L, uint64_t count, uint32_t slots, void **label_args,
+                             void **bfs_args, hipKernelNodeParams *label,
+                             hipKernelNodeParams *bfs) {
+  const void *fl = nullptr, *fb = nullptr;
+  switch (L.words) {
+    case 1: fl = (const void *)k_query_label<1>; fb = (const void *)k_query_bfs<1>; break;
+    case 2: fl = (const void *)k_query_label<2>; fb = (const void *)k_query_bfs<2>; break;
+    case 4: fl = (const void *)k_query_label<4>; fb = (const void *)k_query_bfs<4>; break;
+    default: return hipErrorInvalidValue;
+  }
+  *label = hipKernelNodeParams{};
+  label->func = const_cast<void *>(fl);
+  label->gridDim = dim3((uint32_t)((count + kQueryNT - 1) / kQueryNT));
+  label->blockDim = dim3(kQueryNT);
+  label->kernelParams = label_args;
+  *bfs = hipKernelNodeParams{};
+  bfs->func = const_cast<void *>(fb);
+  bfs->gridDim = dim3(slots / (kBfsNT / 64u));
+  bfs->blockDim = dim3(kBfsNT);
+  bfs->kernelParams = bfs_args;
+  return hipSuccess;
+}
+
 // ---- whole-device BFS for one pair whose slot queue overflowed (rare)
 
 __global__ void k_gbfs_start(PropArgs a, u64 *vis, uint32_t u) {

@@ -405,6 +405,40 @@ def test_insert_each_stops_at_bad_id(tiny):
     assert_labels_equal(g, o, "served after the failure")
 
 
+def test_query_graph_replays(tiny):
+    """Query batches as graph launches: instantiated on the first batch, then replayed with new
+    arguments. Every replay (sizes from 1 to 10,000, DL-only and BL-only rules, direct-launch
+    batches and insertions in between) gives the oracle's answers."""
+    w = tiny
+    g = gpu_index(w.n, w.src, w.dst)
+    o = oracle.OracleIndex(w.n, w.src, w.dst).build(threads=8)
+    lo = 0
+    for k in (10000, 7, 4096, 1, 9999, 10000):
+        qu, qv = w.q_u[:k], w.q_v[:k]
+        want = o.query_dbl(qu, qv, threads=8)
+        g.set_tuning(query_graph=1)
+        assert np.array_equal(g.query(dev(qu), dev(qv)).cpu().numpy(), want)
+        for rules in (1, 2):
+            got = g.query_rules(dev(qu), dev(qv), rules).cpu().numpy()
+            assert np.array_equal(got, o.query_rules(qu, qv, rules, threads=8))
+        g.set_tuning(query_graph=0)
+        assert np.array_equal(g.query(dev(qu), dev(qv)).cpu().numpy(), want)
+        g.insert_edges(dev(w.ins_src[lo:lo + 150]), dev(w.ins_dst[lo:lo + 150]))
+        o.insert(w.ins_src[lo:lo + 150], w.ins_dst[lo:lo + 150])
+        lo += 150
+    # a slot queue too small for the BFS: the whole-device BFS runs after the graph launch
+    n = 3000
+    src = np.arange(n - 1, dtype=np.uint32)
+    g = gpu_index(n, src, src + 1, num_landmarks=0, bl_bits=1, bfs_slots=4, bfs_queue_cap=8)
+    g.set_tuning(query_graph=1)
+    o = oracle.OracleIndex(n, src, src + 1).build(k=0, kp=1)
+    u = np.array([0, 5, 100, 2999, 7], dtype=np.uint32)
+    v = np.array([2999, 4, 2500, 0, 7], dtype=np.uint32)
+    for _ in range(3):
+        assert np.array_equal(g.query(dev(u), dev(v)).cpu().numpy(), o.query_dbl(u, v))
+    assert g.stats()["bfs_heavy"] > 0
+
+
 @pytest.mark.parametrize("batch", [1000, 333, 7])
 def test_tiny_batched_insertions_equal_sequential(tiny, batch):
     w = tiny
