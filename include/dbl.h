@@ -266,6 +266,9 @@ typedef struct {
   uint32_t query_graph;        /* 1: each query batch is one HIP graph launch (label kernel, then
                                   the BFS kernel), instantiated once per query context and replayed
                                   with the batch's arguments; 0 (default): two kernel launches */
+  uint32_t server_warm;        /* 1 (default): before serving, dbl_insert_edges_each reads the
+                                  labels and row descriptors once so that the requests find them
+                                  in the memory-side cache; 0: it does not */
 } dbl_tuning;
 
 dbl_status dbl_get_tuning(const dbl_index *ix, dbl_tuning *out);

@@ -83,6 +83,7 @@ class DblTuning(ctypes.Structure):
         ("pull_threshold", ctypes.c_uint32),
         ("server_polls", ctypes.c_uint32),
         ("query_graph", ctypes.c_uint32),
+        ("server_warm", ctypes.c_uint32),
     ]
 
 
@@ -452,8 +453,8 @@ class Index:
 
     def set_tuning(self, **kw) -> None:
         """Change tuning fields (small_batch, local_max_frontier, local_max_edges, round_grid,
-        bfs_slots, insert_server, server_idle_us, pull_threshold, server_polls, query_graph);
-        results never change."""
+        bfs_slots, insert_server, server_idle_us, pull_threshold, server_polls, query_graph,
+        server_warm); results never change."""
         cur = self.tuning()
         bad = set(kw) - set(cur)
         if bad:

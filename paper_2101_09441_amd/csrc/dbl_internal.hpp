@@ -119,6 +119,8 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t value, uint64_t count, hipStrea
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long value, uint64_t count,
                            hipStream_t s);
 hipError_t launch_ctl_reset_query(Ctl *ctl, hipStream_t s);
+// read `bytes` at p once (16-byte aligned) so they are cached for what follows
+hipError_t launch_touch(const void *p, uint64_t bytes, unsigned long long *sink, hipStream_t s);
 // *out = sum of a[0..count)
 hipError_t launch_sum_u32(const uint32_t *a, uint64_t count, unsigned long long *out,
                           hipStream_t s);
