@@ -425,8 +425,7 @@ def main():
                 continue
             tuned = autotune.tune_insertions(mk, isrc, idst, bsz, w.m, max_batches=10)
             ix = mk()
-            ix.set_tuning(**{k: tuned[k] for k in ("small_batch", "local_max_frontier",
-                                                   "local_max_edges", "round_grid")})
+            ix.set_tuning(**{k: tuned[k] for k in autotune.INSERT_KNOBS})
             torch.cuda.synchronize()
             times = []
             t0 = time.perf_counter()
@@ -441,8 +440,7 @@ def main():
                      "batch_ms_p99": float(np.percentile(times, 99) * 1e3),
                      "speedup_vs_plain": (n_ins / t_ins) / (n_ins / insert_s),
                      "labels_equal_plain": bool(same),
-                     "tuning": {k: tuned[k] for k in ("small_batch", "local_max_frontier",
-                                                      "local_max_edges", "round_grid")}}
+                     "tuning": {k: tuned[k] for k in autotune.INSERT_KNOBS}}
             if bsz == 1000:
                 qtuned = autotune.tune_queries(ix, qu, qv, qb, w.m)
                 # each batch as two kernel launches, then as one graph launch (the graph is

@@ -1,7 +1,7 @@
 """Autotuner for the batched form: picks the runtime tuning of an index by measurement.
 
 Insertion knobs (the single-workgroup batch limit and the local-round limits, the grid-round
-block count) are timed on fresh indexes built from the same graph, because insertions change
+block count, the pull threshold of grid rounds) are timed on fresh indexes built from the same graph, because insertions change
 the index; query knobs (BFS slots) are timed on the index itself, because queries do not. The
 choice is cached per (device, graph size, phase, batch size) in a JSON file. No knob can change
 a label or an answer, only the time they take.
@@ -16,11 +16,15 @@ from typing import Callable, Dict, List, Optional
 import torch
 
 INSERT_CANDIDATES: List[dict] = [
-    dict(small_batch=sb, local_max_frontier=lf, local_max_edges=le, round_grid=rg)
+    dict(small_batch=sb, local_max_frontier=lf, local_max_edges=le, round_grid=rg,
+         pull_threshold=pt)
     for sb in (256, 2048, 16384)
     for lf, le in ((8192, 1 << 16), (32768, 1 << 18))
     for rg in (1024, 2048)
+    for pt in (0, 128)
 ]
+INSERT_KNOBS = ("small_batch", "local_max_frontier", "local_max_edges", "round_grid",
+                "pull_threshold")
 QUERY_CANDIDATES: List[dict] = [dict(bfs_slots=s) for s in (256, 512, 1024, 2048)]
 
 
@@ -63,7 +67,7 @@ def tune_insertions(make_index: Callable, src: torch.Tensor, dst: torch.Tensor, 
     probe = make_index()
     key = _key(probe, m, "insert", batch)
     cache = _load_cache()
-    if use_cache and key in cache:
+    if use_cache and key in cache and all(k in cache[key] for k in INSERT_KNOBS):
         probe.close()
         return cache[key]
     probe.close()
