@@ -63,8 +63,9 @@ struct dbl_index {
   uint32_t *inq = nullptr;
   u64 *heavy_list = nullptr;  // two lists of heavy_cap entries: push chunks, pull chunks
   uint64_t heavy_cap = 0;
-  u64 *fbm = nullptr;         // frontier bitmap of pull rounds (2 bits per vertex)
+  u64 *fbm = nullptr;         // frontier bitmaps of pull rounds (one bit per vertex per direction)
   uint64_t fbm_words = 0;
+  u64 *fu = nullptr;          // OR of the frontier's labels per direction (2 x 8 words)
   uint64_t pull_expanded = 0;  // frontier entries expanded by pull rounds
   uint64_t pull_rounds = 0;    // (round, direction) pairs pulled
   Ctl *ctl = nullptr;
@@ -345,6 +346,7 @@ dbl::PropArgs prop_args(const dbl_index *ix) {
   a.heavy_cap = ix->heavy_cap;
   a.fbm = ix->fbm;
   a.fbm_wpd = ix->fbm_words / 2;
+  a.fu = ix->fu;
   a.pcnt = ix->pcnt;
   a.local_max_frontier = ix->local_max_frontier;
   a.local_max_edges = ix->local_max_edges;
@@ -482,6 +484,7 @@ dbl_status grid_propagate(dbl_index *ix, hipStream_t s, uint32_t group, uint64_t
         ix->fbm_words = 0;
         CKS(dalloc(&ix->fbm, words));
         ix->fbm_words = words;
+        if (!ix->fu) CKS(dalloc(&ix->fu, 16));
       }
       dbl::PropArgs a = prop_args(ix);
       CK(dbl::launch_frontier_scan(a, cur, stamp, ix->fbm_words, s));
@@ -1624,6 +1627,7 @@ void dbl_destroy(dbl_index *ix) {
   dfree(ix->inq);
   dfree(ix->heavy_list);
   dfree(ix->fbm);
+  dfree(ix->fu);
   dfree(ix->ctl);
   hfree(ix->mirror);
   hfree(ix->door);

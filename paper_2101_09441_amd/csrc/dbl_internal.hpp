@@ -188,6 +188,7 @@ struct PropArgs {
   uint64_t heavy_cap;
   unsigned long long *fbm;          // frontier bitmaps of the pull round, one per direction:
   uint64_t fbm_wpd;                 // bit x of fbm[dir * fbm_wpd + x / 64]
+  unsigned long long *fu;           // OR of the frontier's labels, per direction: fu[dir * 8 ...]
   unsigned long long *pcnt;  // [kPropCtrSlots * 2] per-block (expanded, relaxed) counters
   uint32_t local_max_frontier, local_max_edges;
   Ctl *ctl;

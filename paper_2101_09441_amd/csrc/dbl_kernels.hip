@@ -987,9 +987,11 @@ __device__ __forceinline__ bool in_frontier(const u64 *fbm, uint64_t wpd, uint32
   return (fbm[dir * wpd + (x >> 6)] >> (x & 63u)) & 1ull;
 }
 
+template <int W>
 __global__ __launch_bounds__(256) void k_frontier_scan(PropArgs a, uint32_t ring,
                                                        uint32_t stamp) {
   __shared__ u64 s_red[4][4];
+  __shared__ u64 s_or[4][2][2 * W];
   Ctl *ctl = a.ctl;
   const uint32_t fsz = ctl->fsize[ring];
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1002,17 +1004,23 @@ __global__ __launch_bounds__(256) void k_frontier_scan(PropArgs a, uint32_t ring
     ctl->stamp = stamp + 1u;
   }
   u64 v[4] = {0, 0, 0, 0};  // entries fwd, bwd, push edges fwd, bwd
+  Half<W> un[2] = {};       // OR of the entries' labels, per direction
   for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < fsz; i += gridDim.x * 256u) {
     const uint32_t e = a.fq[ring][i];
     const uint32_t d = e >> 31, x = e & kIdMask;
     const uint32_t dg = d ? min(a.r.deg[x], a.r.cap[x]) : min(a.f.deg[x], a.f.cap[x]);
     atomicOr(&a.fbm[d * a.fbm_wpd + (x >> 6)], 1ull << (x & 63u));
+    const Half<W> l = ld_half<W>(half_ptr<W>(a.L.lab, x, d));
     if (d) {
       v[1] += 1;
       v[3] += dg;
+#pragma unroll
+      for (int j = 0; j < 2 * W; j++) un[1].w[j] |= l.w[j];
     } else {
       v[0] += 1;
       v[2] += dg;
+#pragma unroll
+      for (int j = 0; j < 2 * W; j++) un[0].w[j] |= l.w[j];
     }
   }
   const uint32_t lane = __lane_id(), w = threadIdx.x >> 6;
@@ -1022,11 +1030,25 @@ __global__ __launch_bounds__(256) void k_frontier_scan(PropArgs a, uint32_t ring
     for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o, 64);
     if (lane == 0) s_red[w][k] = v[k];
   }
+#pragma unroll
+  for (int d = 0; d < 2; d++)
+#pragma unroll
+    for (int j = 0; j < 2 * W; j++) {
+      u64 x = un[d].w[j];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) x |= __shfl_xor(x, o, 64);
+      if (lane == 0) s_or[w][d][j] = x;
+    }
   __syncthreads();
   if (threadIdx.x < 4) {
     const u64 sum = s_red[0][threadIdx.x] + s_red[1][threadIdx.x] + s_red[2][threadIdx.x] +
                     s_red[3][threadIdx.x];
     if (sum) atomicAdd(&ctl->ctr[kCtrFrontEntries + threadIdx.x], sum);
+  }
+  if (threadIdx.x < 4 * W) {
+    const uint32_t d = threadIdx.x / (2 * W), j = threadIdx.x % (2 * W);
+    const u64 x = s_or[0][d][j] | s_or[1][d][j] | s_or[2][d][j] | s_or[3][d][j];
+    if (x) atomicOr(&a.fu[d * 8 + j], x);
   }
 }
 
@@ -1036,7 +1058,9 @@ hipError_t launch_frontier_scan(const PropArgs &a, uint32_t ring, uint32_t stamp
   if (e != hipSuccess) return e;
   e = launch_fill_u64(&a.ctl->ctr[kCtrFrontEntries], 0ull, 4, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_frontier_scan, dim3(kRoundGridMax), dim3(256), 0, s, a, ring, stamp);
+  e = launch_fill_u64(a.fu, 0ull, 16, s);
+  if (e != hipSuccess) return e;
+  DBL_LAUNCH_W(a.L.words, k_frontier_scan, dim3(kRoundGridMax), dim3(256), s, a, ring, stamp);
   return hipGetLastError();
 }
 
@@ -1096,11 +1120,19 @@ __global__ __launch_bounds__(256) void k_pull(PropArgs a, uint32_t n, uint32_t d
     const uint64_t r = beg + t;
     const bool act = r < rows;
     uint32_t y = 0, d = 0, dg = 0;
+    Half<W> cur = {};
     if (act) {
       d = ndir == 2 ? (r >= n ? 1u : 0u) : d_only;
       y = (uint32_t)(r - (ndir == 2 && r >= n ? (uint64_t)n : 0ull));
       const Csr g = pick_csr(a.r, a.f, d);  // neighbours the labels come from
       dg = min(g.deg[y], g.cap[y]);
+      // a row already holding every bit of this direction's frontier cannot grow this round
+      // (a source that grows later in the round is queued again and delivers next round)
+      cur = ld_half<W>(half_ptr<W>(a.L.lab, y, d));
+      u64 miss = 0;
+#pragma unroll
+      for (int i = 0; i < 2 * W; i++) miss |= a.fu[d * 8 + i] & ~cur.w[i];
+      if (!miss) dg = 0;
       if (dg > kHeavyDeg) {
         const uint32_t nch = (dg + kChunk - 1) / kChunk;
         const uint32_t hb = atomicAdd(&ctl->pheavy, nch);
@@ -1146,7 +1178,6 @@ __global__ __launch_bounds__(256) void k_pull(PropArgs a, uint32_t n, uint32_t d
     bool push = false;
     if (act && dg) {
       u64 *wl = half_ptr<W>(a.L.lab, y, d);
-      const Half<W> cur = ld_half<W>(wl);
       bool grew = false;
 #pragma unroll
       for (int i = 0; i < 2 * W; i++) {
@@ -1180,7 +1211,15 @@ __global__ __launch_bounds__(256) void k_pull_heavy(PropArgs a, uint32_t nring,
     const uint32_t d = row >> 31, y = row & kIdMask;
     const Csr g = pick_csr(a.r, a.f, d);
     const uint32_t dg = min(g.deg[y], g.cap[y]);
-    const uint32_t b = c * kChunk, e_end = min(dg, b + kChunk);
+    uint32_t b = c * kChunk, e_end = min(dg, b + kChunk);
+    {
+      // as in k_pull: a row holding every bit of the frontier cannot grow this round
+      const Half<W> cur = ld_half<W>(half_ptr<W>(a.L.lab, y, d));
+      u64 miss = 0;
+#pragma unroll
+      for (int i = 0; i < 2 * W; i++) miss |= a.fu[d * 8 + i] & ~cur.w[i];
+      if (!miss) e_end = b;
+    }
     const u64 o = g.off[y];
     if (threadIdx.x < 2 * W) s_acc[0][threadIdx.x] = 0ull;
     __syncthreads();
