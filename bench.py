@@ -257,6 +257,7 @@ def bench_scale(args):
         "kernel_times_ms": {k: {"launches": v["launches"],
                                 "avg_us": v["total_ms"] / v["launches"] * 1e3}
                             for k, v in kt.items()},
+        "build_teps": sb["edges_relaxed"] / float(np.mean([r["build_s"] for r in res])),
         "propagation": {"build_rounds": st["build_rounds"], "edges_relaxed": st["edges_relaxed"],
                         "vertices_expanded": st["vertices_expanded"],
                         "csr_regrows": st["csr_regrows"], "bfs_heavy": st["bfs_heavy"],
@@ -579,6 +580,7 @@ def main():
         "class_histogram": {dbl.CLASS_NAMES[i]: int(classes[i]) for i in range(7)},
         "kernel_times_ms": {k: {"launches": v["launches"], "avg_us": v["total_ms"] / v["launches"]
                                 * 1e3} for k, v in kt.items()},
+        "build_teps": s_build["edges_relaxed"] / build_s,
         "propagation": {"build_rounds": s_build["build_rounds"],
                         "build_edges_relaxed": s_build["edges_relaxed"],
                         "build_vertices_expanded": s_build["vertices_expanded"],
