@@ -158,8 +158,9 @@ dbl_status dbl_add_vertices(dbl_index *ix, uint32_t count, uint32_t *first, void
  * The one-request-at-a-time form of dbl_insert_edges: edge i is inserted as its own request
  * (validate, append, seed, propagate to the fixpoint, report), in order, exactly as `count`
  * calls of dbl_insert_edges with one edge each. By default a resident workgroup serves the
- * requests (dbl_tuning.insert_server); the host releases each one after the previous one was
- * reported. h_latency_us: optional HOST array [count] that
+ * requests (dbl_tuning.insert_server): the ids are first copied to the host (the stream is
+ * synchronised), and the host then hands each edge to the device with its release, after the
+ * previous request was reported. h_latency_us: optional HOST array [count] that
  * receives each request's wall time in microseconds. Stops at the first failing request and
  * returns its status (earlier requests stay applied).
  */

@@ -70,7 +70,7 @@ struct dbl_index {
   uint64_t pull_rounds = 0;    // (round, direction) pairs pulled
   Ctl *ctl = nullptr;
   dbl::Mirror *mirror = nullptr;  // pinned, device-mapped host memory written by the device
-  u64 *door = nullptr;            // pinned, device-mapped host memory written by the host
+  u64 *door = nullptr;            // request server doorbell slots (pinned host memory, 2 words)
   u64 clock_khz = 100000;         // device wall-clock rate
   uint32_t server_idle_us = 200000;  // request-server idle limit
   uint32_t server_polls = 4;         // doorbell reads in flight (1 or 4)
@@ -814,7 +814,7 @@ dbl_status do_build(dbl_index *ix, uint64_t m, const uint32_t *src, const uint32
   CKS(halloc(&ix->mirror, sizeof(dbl::Mirror)));
   memset((void *)ix->mirror, 0, sizeof(dbl::Mirror));
   CKS(halloc(&ix->door, 64));
-  memset((void *)ix->door, 0, 64);
+  ix->door[0] = ix->door[1] = dbl::kDoorStop;
   {
     int khz = 0;
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, ix->device) == hipSuccess &&
@@ -986,18 +986,33 @@ dbl_status do_build(dbl_index *ix, uint64_t m, const uint32_t *src, const uint32
   return DBL_OK;
 }
 
-// The one-request-at-a-time form through the request server (k_insert_server): request i is
-// released by writing i + 1 to the doorbell and is done when the device publishes its sequence
-// number. A request whose flags need the host (bad id, full row, large frontier) ends the
-// launch; the host finishes it exactly as dbl_insert_edges does and starts a new launch for the
-// rest. A launch that timed out waiting (the host was slow) is started again.
+// The one-request-at-a-time form through the request server (k_insert_server). The host holds
+// the request stream (a copy of the ids, as a server receives them) and releases request i by
+// writing its edge into doorbell slot i & 1; the request is done when the device publishes its
+// sequence number, and its slot is emptied before the next release. An id out of range is
+// refused before its release. A request whose flags need the host (a full row, a large
+// frontier) ends the launch; the host finishes it exactly as dbl_insert_edges does and starts a
+// new launch for the rest. A launch that timed out waiting (the host was slow) is started again.
 dbl_status insert_each_served(dbl_index *ix, uint32_t count, const uint32_t *d_src,
                               const uint32_t *d_dst, float *h_latency_us, hipStream_t s) {
-  // whatever way this returns, a launch still waiting for a request ends at once
-  struct StopOnExit {
+  u64 *door = ix->door;
+  auto put = [](u64 *slot, u64 v) { __atomic_store_n(slot, v, __ATOMIC_SEQ_CST); };
+  // whatever way this returns, a launch still waiting for a request ends at once, and the
+  // staging copy of the ids goes back to the cache
+  struct OnExit {
     u64 *door;
-    ~StopOnExit() { __atomic_store_n(door, dbl::kDoorStop, __ATOMIC_SEQ_CST); }
-  } stop_on_exit{ix->door};
+    uint32_t *ids;
+    ~OnExit() {
+      __atomic_store_n(door, dbl::kDoorStop, __ATOMIC_SEQ_CST);
+      __atomic_store_n(door + 1, dbl::kDoorStop, __ATOMIC_SEQ_CST);
+      hfree(ids);
+    }
+  } on_exit{door, nullptr};
+  CKS(halloc(&on_exit.ids, 8ull * count));
+  const uint32_t *h_src = on_exit.ids, *h_dst = on_exit.ids + count;
+  CK(hipMemcpyAsync(on_exit.ids, d_src, 4ull * count, hipMemcpyDeviceToHost, s));
+  CK(hipMemcpyAsync(on_exit.ids + count, d_dst, 4ull * count, hipMemcpyDeviceToHost, s));
+  CK(hipStreamSynchronize(s));
   if (ix->ovf_cap < 2) {
     dfree(ix->ovf);
     CKS(dalloc(&ix->ovf, 1024));
@@ -1017,21 +1032,31 @@ dbl_status insert_each_served(dbl_index *ix, uint32_t count, const uint32_t *d_s
   }
   uint32_t i = 0;
   while (i < count) {
-    __atomic_store_n(ix->door, 0ull, __ATOMIC_SEQ_CST);
+    put(door, dbl::kDoorEmpty);
+    put(door + 1, dbl::kDoorEmpty);
     const dbl::PropArgs a = prop_args(ix);
     const uint32_t first = i, seq0 = ix->seq;
     {
       Timed tm(ix, kTInsertServer, s);
-      CK(dbl::launch_insert_server(a, d_src, d_dst, first, count, ix->n, ix->ovf, ix->ovf_cap,
-                                   ix->mirror, ix->door, seq0,
-                                   ix->clock_khz * ix->server_idle_us / 1000, ix->server_polls,
-                                   s));
+      CK(dbl::launch_insert_server(a, first, count, ix->n, ix->ovf, ix->ovf_cap, ix->mirror,
+                                   door, seq0, ix->clock_khz * ix->server_idle_us / 1000,
+                                   ix->server_polls, s));
     }
     bool relaunch = false;
     for (; i < count && !relaunch; i++) {
       const uint32_t seq = seq0 + (i - first) + 1;
       const auto t0 = std::chrono::steady_clock::now();
-      __atomic_store_n(ix->door, (u64)i + 1, __ATOMIC_SEQ_CST);
+      if (h_src[i] >= ix->n || h_dst[i] >= ix->n) {
+        // refused before release: the index stays as the earlier requests left it
+        put(door, dbl::kDoorStop);
+        put(door + 1, dbl::kDoorStop);
+        CK(hipStreamSynchronize(s));
+        if (h_latency_us)
+          h_latency_us[i] = std::chrono::duration<float, std::micro>(
+                                std::chrono::steady_clock::now() - t0).count();
+        return DBL_ERR_VERTEX_RANGE;
+      }
+      put(door + (i & 1u), ((u64)h_src[i] << 32) | h_dst[i]);
       uint32_t flags = 0;
       bool gone = false;
       for (uint64_t spin = 1;; spin++) {
@@ -1060,6 +1085,7 @@ dbl_status insert_each_served(dbl_index *ix, uint32_t count, const uint32_t *d_s
         ix->seq = seq - 1;
         continue;
       }
+      put(door + (i & 1u), dbl::kDoorEmpty);
       ix->seq = seq;
       if (flags) {
         // the launch has ended after this request; finish it on the host
@@ -1090,7 +1116,8 @@ dbl_status insert_each_served(dbl_index *ix, uint32_t count, const uint32_t *d_s
     }
     if (!relaunch) break;
   }
-  __atomic_store_n(ix->door, dbl::kDoorStop, __ATOMIC_SEQ_CST);
+  put(door, dbl::kDoorStop);
+  put(door + 1, dbl::kDoorStop);
   CK(hipStreamSynchronize(s));
   if (!ix->pending.empty()) resolve_times(ix);
   return DBL_OK;

@@ -83,9 +83,12 @@ struct Mirror {
   unsigned long long fast;
 };
 constexpr uint32_t kFastErr = 1u, kFastOvf = 2u, kFastPending = 4u;
-// Doorbell word of the request server (pinned host memory written by the host): i + 1 releases
-// request i; kDoorStop ends the server.
-constexpr unsigned long long kDoorStop = ~0ull;
+// Doorbell of the request server: two 64-bit slots in pinned host memory written by the host.
+// Request i is released by writing its edge ((u << 32) | v) into slot i & 1; the host empties
+// that slot again once request i is done (before it releases request i + 2). kDoorStop in a
+// slot ends the server. Neither marker is an edge: their u is 0xFFFFFFFF, never a vertex id.
+constexpr unsigned long long kDoorEmpty = ~0ull;
+constexpr unsigned long long kDoorStop = ~0ull - 1ull;
 
 // Per-block / per-slot statistics (plain read-modify-write by the owning block, no atomics).
 constexpr uint32_t kQueryGrid = 64;    // class-counter stripes (label-kernel block % 64)
@@ -216,11 +219,10 @@ hipError_t launch_insert_small(const PropArgs &a, const uint32_t *src, const uin
                                uint32_t count, uint32_t n, Ovf *ovf, uint64_t ovf_cap, Mirror *m,
                                uint32_t seq, hipStream_t s);
 // request server for requests [first, count); see k_insert_server
-hipError_t launch_insert_server(const PropArgs &a, const uint32_t *src, const uint32_t *dst,
-                                uint32_t first, uint32_t count, uint32_t n, Ovf *ovf,
-                                uint64_t ovf_cap, Mirror *m, const unsigned long long *door,
-                                uint32_t seq0, unsigned long long idle_ticks, uint32_t polls,
-                                hipStream_t s);
+hipError_t launch_insert_server(const PropArgs &a, uint32_t first, uint32_t count, uint32_t n,
+                                Ovf *ovf, uint64_t ovf_cap, Mirror *m,
+                                const unsigned long long *door, uint32_t seq0,
+                                unsigned long long idle_ticks, uint32_t polls, hipStream_t s);
 hipError_t launch_insert_apply(const PropArgs &a, const uint32_t *src, const uint32_t *dst,
                                uint64_t count, Ovf *ovf, uint64_t ovf_cap, hipStream_t s);
 hipError_t launch_regrow_copy(Csr old_g, Csr new_g, uint32_t n, hipStream_t s);

@@ -497,15 +497,32 @@ uint32_t bin_shift(uint32_t n) {
 
 // counts[bin * nblk + b]: kept edges of block b's chunk whose key falls in `bin` (bin-major, so
 // one exclusive scan over the array gives every (bin, block) its output offset)
-__global__ __launch_bounds__(256) void k_bin_hist(const uint32_t *key, const uint8_t *keep,
-                                                  uint64_t m, uint32_t shift, uint32_t nbins,
-                                                  uint64_t chunk, uint32_t *counts) {
+// Every thread walks its part of the chunk kBinUnroll edges at a time: all their loads are
+// issued before the first LDS update, so a wave keeps that many reads in flight.
+constexpr uint32_t kBinUnroll = 8;
+
+__global__ __launch_bounds__(256) void k_bin_hist(const uint32_t *__restrict__ key,
+                                                  const uint8_t *__restrict__ keep, uint64_t m,
+                                                  uint32_t shift, uint32_t nbins, uint64_t chunk,
+                                                  uint32_t *__restrict__ counts) {
   __shared__ uint32_t hist[kMaxBins];
   for (uint32_t i = threadIdx.x; i < nbins; i += 256u) hist[i] = 0;
   __syncthreads();
   const uint64_t lo = blockIdx.x * chunk, hi = min(m, lo + chunk);
-  for (uint64_t e = lo + threadIdx.x; e < hi; e += 256u)
-    if (keep[e]) atomicAdd(&hist[key[e] >> shift], 1u);
+  for (uint64_t e0 = lo + threadIdx.x; e0 < hi; e0 += 256u * kBinUnroll) {
+    uint32_t k[kBinUnroll];
+    bool ok[kBinUnroll];
+#pragma unroll
+    for (uint32_t j = 0; j < kBinUnroll; j++) {
+      const uint64_t e = e0 + 256u * j;
+      ok[j] = e < hi;
+      k[j] = ok[j] ? key[e] : 0u;
+      ok[j] = ok[j] && keep[e];
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < kBinUnroll; j++)
+      if (ok[j]) atomicAdd(&hist[k[j] >> shift], 1u);
+  }
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < nbins; i += 256u)
     counts[(uint64_t)i * gridDim.x + blockIdx.x] = hist[i];
@@ -513,20 +530,34 @@ __global__ __launch_bounds__(256) void k_bin_hist(const uint32_t *key, const uin
 
 // out[pos] = key << 32 | val for every kept edge, grouped by bin (order inside a bin is
 // arbitrary)
-__global__ __launch_bounds__(256) void k_bin_scatter(const uint32_t *key, const uint32_t *val,
-                                                     const uint8_t *keep, uint64_t m,
+__global__ __launch_bounds__(256) void k_bin_scatter(const uint32_t *__restrict__ key,
+                                                     const uint32_t *__restrict__ val,
+                                                     const uint8_t *__restrict__ keep, uint64_t m,
                                                      uint32_t shift, uint32_t nbins,
-                                                     uint64_t chunk, const u64 *offs, u64 *out) {
+                                                     uint64_t chunk, const u64 *__restrict__ offs,
+                                                     u64 *__restrict__ out) {
   __shared__ u64 cur[kMaxBins];
   for (uint32_t i = threadIdx.x; i < nbins; i += 256u)
     cur[i] = offs[(uint64_t)i * gridDim.x + blockIdx.x];
   __syncthreads();
   const uint64_t lo = blockIdx.x * chunk, hi = min(m, lo + chunk);
-  for (uint64_t e = lo + threadIdx.x; e < hi; e += 256u) {
-    if (!keep[e]) continue;
-    const uint32_t k = key[e];
-    const u64 pos = atomicAdd(&cur[k >> shift], 1ull);
-    out[pos] = ((u64)k << 32) | val[e];
+  for (uint64_t e0 = lo + threadIdx.x; e0 < hi; e0 += 256u * kBinUnroll) {
+    uint32_t k[kBinUnroll], x[kBinUnroll];
+    bool ok[kBinUnroll];
+#pragma unroll
+    for (uint32_t j = 0; j < kBinUnroll; j++) {
+      const uint64_t e = e0 + 256u * j;
+      ok[j] = e < hi;
+      k[j] = ok[j] ? key[e] : 0u;
+      x[j] = ok[j] ? val[e] : 0u;
+      ok[j] = ok[j] && keep[e];
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < kBinUnroll; j++)
+      if (ok[j]) {
+        const u64 pos = atomicAdd(&cur[k[j] >> shift], 1ull);
+        out[pos] = ((u64)k[j] << 32) | x[j];
+      }
   }
 }
 
@@ -556,10 +587,11 @@ __device__ __forceinline__ void bin_range(const u64 *offs, uint32_t nblk, uint32
   hi = bin + 1 < nbins ? offs[(uint64_t)(bin + 1) * nblk] : kept;
 }
 
-__global__ __launch_bounds__(kBinNT) void k_bin_deg(const u64 *edges, const u64 *offs,
-                                                    uint32_t nblk, uint32_t nbins,
-                                                    uint32_t shift, const u64 *kept, uint32_t n,
-                                                    uint32_t *deg) {
+__global__ __launch_bounds__(kBinNT) void k_bin_deg(const u64 *__restrict__ edges,
+                                                    const u64 *__restrict__ offs, uint32_t nblk,
+                                                    uint32_t nbins, uint32_t shift,
+                                                    const u64 *__restrict__ kept, uint32_t n,
+                                                    uint32_t *__restrict__ deg) {
   __shared__ uint32_t cnt[kBinVerts];
   for (uint32_t bin = blockIdx.x; bin < nbins; bin += gridDim.x) {
     const uint32_t first = bin << shift, nv = min(1u << shift, n - first);
@@ -567,17 +599,27 @@ __global__ __launch_bounds__(kBinNT) void k_bin_deg(const u64 *edges, const u64 
     __syncthreads();
     u64 lo, hi;
     bin_range(offs, nblk, nbins, *kept, bin, lo, hi);
-    for (u64 e = lo + threadIdx.x; e < hi; e += kBinNT)
-      atomicAdd(&cnt[(uint32_t)(edges[e] >> 32) - first], 1u);
+    for (u64 e0 = lo + threadIdx.x; e0 < hi; e0 += kBinNT * 4u) {
+      uint32_t k[4];
+#pragma unroll
+      for (uint32_t j = 0; j < 4; j++) {
+        const u64 e = e0 + kBinNT * j;
+        k[j] = e < hi ? (uint32_t)(edges[e] >> 32) : ~0u;
+      }
+#pragma unroll
+      for (uint32_t j = 0; j < 4; j++)
+        if (k[j] != ~0u) atomicAdd(&cnt[k[j] - first], 1u);
+    }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < nv; i += kBinNT) deg[first + i] = cnt[i];
     __syncthreads();
   }
 }
 
-__global__ __launch_bounds__(kBinNT) void k_bin_fill(const u64 *edges, const u64 *offs,
-                                                     uint32_t nblk, uint32_t nbins,
-                                                     uint32_t shift, const u64 *kept, uint32_t n,
+__global__ __launch_bounds__(kBinNT) void k_bin_fill(const u64 *__restrict__ edges,
+                                                     const u64 *__restrict__ offs, uint32_t nblk,
+                                                     uint32_t nbins, uint32_t shift,
+                                                     const u64 *__restrict__ kept, uint32_t n,
                                                      Csr g) {
   __shared__ uint32_t cur[kBinVerts];
   for (uint32_t bin = blockIdx.x; bin < nbins; bin += gridDim.x) {
@@ -586,11 +628,24 @@ __global__ __launch_bounds__(kBinNT) void k_bin_fill(const u64 *edges, const u64
     __syncthreads();
     u64 lo, hi;
     bin_range(offs, nblk, nbins, *kept, bin, lo, hi);
-    for (u64 e = lo + threadIdx.x; e < hi; e += kBinNT) {
-      const u64 kv = edges[e];
-      const uint32_t k = (uint32_t)(kv >> 32);
-      const uint32_t p = atomicAdd(&cur[k - first], 1u);
-      g.col[g.off[k] + p] = (uint32_t)kv;
+    for (u64 e0 = lo + threadIdx.x; e0 < hi; e0 += kBinNT * 4u) {
+      u64 kv[4];
+      u64 o[4];
+#pragma unroll
+      for (uint32_t j = 0; j < 4; j++) {
+        const u64 e = e0 + kBinNT * j;
+        kv[j] = e < hi ? edges[e] : ~0ull;
+      }
+#pragma unroll
+      for (uint32_t j = 0; j < 4; j++)
+        o[j] = kv[j] != ~0ull ? g.off[(uint32_t)(kv[j] >> 32)] : 0ull;
+#pragma unroll
+      for (uint32_t j = 0; j < 4; j++)
+        if (kv[j] != ~0ull) {
+          const uint32_t k = (uint32_t)(kv[j] >> 32);
+          const uint32_t p = atomicAdd(&cur[k - first], 1u);
+          g.col[o[j] + p] = (uint32_t)kv[j];
+        }
     }
     __syncthreads();
   }
@@ -831,6 +886,8 @@ hipError_t launch_init_frontier(LabelsView L, uint32_t n, Csr f, Csr r, uint32_t
 
 // ---------------------------------------------------------------- propagation
 
+constexpr uint32_t kExpandUnroll = 4;
+
 // Expand frontier entries [beg, end) (at most NT, one per thread): every edge of every entry
 // relaxes its target; targets whose label grew are queued in nq with stamp nstamp. With a heavy
 // list, rows longer than kHeavyDeg are split into chunks for k_heavy instead.
@@ -876,19 +933,41 @@ __device__ __forceinline__ void expand_tile(const PropArgs &a, const uint32_t *f
   s_start[t] = ex;
   const uint32_t nexp = (uint32_t)__syncthreads_count(mine);
   const uint32_t last = min((uint32_t)NT, end - beg) - 1u;
-  for (uint32_t e = t; e < total; e += NT) {
-    uint32_t lo = 0, hi = last;
-    while (lo < hi) {
-      const uint32_t mid = (lo + hi + 1) >> 1;
-      if (s_start[mid] <= e) lo = mid; else hi = mid - 1;
+  // kExpandUnroll / W edges per thread at a time: their column reads, then their target-label
+  // reads are each issued together before the first update
+  constexpr uint32_t U = kExpandUnroll / W;
+  for (uint32_t e0 = t; e0 < total; e0 += NT * U) {
+    uint32_t lo[U], y[U];
+    Half<W> cur[U];
+#pragma unroll
+    for (uint32_t j = 0; j < U; j++) {
+      const uint32_t e = e0 + NT * j;
+      lo[j] = 0;
+      y[j] = 0;
+      if (e < total) {
+        uint32_t hi = last;
+        while (lo[j] < hi) {
+          const uint32_t mid = (lo[j] + hi + 1) >> 1;
+          if (s_start[mid] <= e) lo[j] = mid; else hi = mid - 1;
+        }
+        const uint32_t *col = (s_ent[lo[j]] >> 31) ? a.r.col : a.f.col;
+        y[j] = col[s_off[lo[j]] + (e - s_start[lo[j]])];
+      }
     }
-    const uint32_t ent = s_ent[lo];
-    const uint32_t dir = ent >> 31;
-    const uint32_t *col = dir ? a.r.col : a.f.col;
-    const uint32_t y = col[s_off[lo] + (e - s_start[lo])];
-    const bool ch = relax<W>(half_ptr<W>(a.L.lab, y, dir), s_lab[lo]);
-    const bool push = ch && claim(&a.inq[2ull * y + dir], nstamp);
-    wave_push(nq, ncnt, push, y | (ent & kDirBit));
+#pragma unroll
+    for (uint32_t j = 0; j < U; j++) {
+      cur[j] = {};
+      if (e0 + NT * j < total) cur[j] = ld_half<W>(half_ptr<W>(a.L.lab, y[j], s_ent[lo[j]] >> 31));
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < U; j++) {
+      const bool ea = e0 + NT * j < total;
+      const uint32_t ent = s_ent[lo[j]];
+      const uint32_t dir = ent >> 31;
+      const bool ch = ea && or_half<W>(half_ptr<W>(a.L.lab, y[j], dir), s_lab[lo[j]], cur[j]);
+      const bool push = ch && claim(&a.inq[2ull * y[j] + dir], nstamp);
+      wave_push(nq, ncnt, push, y[j] | (ent & kDirBit));
+    }
   }
   if (t == 0) {
     relaxed += total;
@@ -1100,6 +1179,8 @@ __device__ __forceinline__ void acc_or(u64 (*s_acc)[2 * W], uint32_t row, bool a
 
 // Pull rows: 256 rows per tile, the rows' edges laid end to end and taken one per thread (as
 // in expand_tile). Rows longer than kHeavyDeg go to k_pull_heavy in chunks.
+constexpr uint32_t kPullUnroll = 4;
+
 template <int W>
 __global__ __launch_bounds__(256) void k_pull(PropArgs a, uint32_t n, uint32_t dmask,
                                               uint32_t nring, uint32_t nstamp) {
@@ -1151,28 +1232,43 @@ __global__ __launch_bounds__(256) void k_pull(PropArgs a, uint32_t n, uint32_t d
     s_start[t] = ex;
     __syncthreads();
     const uint32_t last = (uint32_t)min<uint64_t>(256u, rows - beg) - 1u;
-    for (uint32_t e0 = 0; e0 < total; e0 += 256u) {
-      const uint32_t e = e0 + t;
-      const bool eact = e < total;
-      uint32_t lo = 0;
-      bool hit = false;
-      Half<W> lv = {};
-      if (eact) {
-        uint32_t hi = last;
-        while (lo < hi) {
-          const uint32_t mid = (lo + hi + 1) >> 1;
-          if (s_start[mid] <= e) lo = mid; else hi = mid - 1;
+    // kPullUnroll edges per thread at a time: their column reads, then their frontier-bit
+    // reads, then their label reads are each issued together
+    constexpr uint32_t U = kPullUnroll / W;
+    for (uint32_t e0 = 0; e0 < total; e0 += 256u * U) {
+      uint32_t lo[U], p[U], rd[U];
+      bool eact[U], hit[U];
+      Half<W> lv[U];
+#pragma unroll
+      for (uint32_t j = 0; j < U; j++) {
+        const uint32_t e = e0 + 256u * j + t;
+        eact[j] = e < total;
+        lo[j] = 0;
+        p[j] = 0;
+        rd[j] = 0;
+        if (eact[j]) {
+          uint32_t hi = last;
+          while (lo[j] < hi) {
+            const uint32_t mid = (lo[j] + hi + 1) >> 1;
+            if (s_start[mid] <= e) lo[j] = mid; else hi = mid - 1;
+          }
+          rd[j] = s_row[lo[j]] >> 31;
+          const uint32_t *col = rd[j] ? a.f.col : a.r.col;
+          p[j] = col[s_off[lo[j]] + (e - s_start[lo[j]])];
         }
-        const uint32_t rd = s_row[lo] >> 31;
-        const uint32_t *col = rd ? a.f.col : a.r.col;
-        const uint32_t p = col[s_off[lo] + (e - s_start[lo])];
-        if (in_frontier(a.fbm, a.fbm_wpd, p, rd)) {
-          hit = true;
-          lv = ld_half<W>(half_ptr<W>(a.L.lab, p, rd));
+      }
+#pragma unroll
+      for (uint32_t j = 0; j < U; j++) hit[j] = eact[j] && in_frontier(a.fbm, a.fbm_wpd, p[j], rd[j]);
+#pragma unroll
+      for (uint32_t j = 0; j < U; j++) {
+        lv[j] = {};
+        if (hit[j]) {
+          lv[j] = ld_half<W>(half_ptr<W>(a.L.lab, p[j], rd[j]));
           relaxed++;
         }
       }
-      acc_or<W>(s_acc, lo, eact, hit, lv);
+#pragma unroll
+      for (uint32_t j = 0; j < U; j++) acc_or<W>(s_acc, lo[j], eact[j], hit[j], lv[j]);
     }
     __syncthreads();
     bool push = false;
@@ -1479,83 +1575,106 @@ hipError_t launch_insert_small(const PropArgs &a, const uint32_t *src, const uin
   return hipGetLastError();
 }
 
-// Request server: the one-request-at-a-time form without a launch per request. Wave 0 waits
-// for the host to release request i (door == i + 1 in pinned host memory), inserts edge
-// (src[i], dst[i]) with lanes 0 and 1 (the two halves) and publishes {seq0 + i - first + 1,
-// flags}; requests that change no label need nothing else, so the other waves stay parked at a
+// Request server: the one-request-at-a-time form without a launch per request. Request i is
+// released by the host writing its edge into doorbell slot i & 1 (pinned host memory), so its
+// ids arrive with the release itself. Lane 0 of wave 1 watches the doorbell and hands each
+// request to wave 0 through LDS; wave 0 inserts it with lanes 0 and 1 (the two halves) and
+// publishes {seq0 + i - first + 1, flags}. The watching and the serving sit in different waves
+// because a wave's memory counter covers all its reads in issue order: host-memory polls still
+// in flight in the serving wave would hold up the label reads of the request just released.
+// Requests that change no label need nothing else, so the other waves stay parked at a
 // barrier. A request whose halves queue a vertex wakes the workgroup, which runs the
 // propagation rounds and publishes. The launch returns after the last request, after a request
 // that needs the host (nonzero flags: a bad id, a full row, a frontier too large for one
 // workgroup), on kDoorStop, or when no request arrives for idle_ticks of the device wall clock.
 constexpr uint32_t kServerMaxSpins = 1u << 23;
 constexpr uint32_t kCmdExit = 0u, kCmdPropagate = 1u;
+constexpr u64 kDoorHalt = ~0ull - 2ull;  // internal: the serving wave asked the watcher to stop
 
-// Wait for the doorbell word to become `want`: returns 1 when it does, 0 on kDoorStop or after
-// idle_ticks of the device wall clock. D reads of the (host-memory) word are kept in flight,
-// first issued a fraction of a round trip apart, so a release is seen sooner than with one read
-// at a time. The iteration bound is a backstop that ends the wait even if the clock stood still
-// (each iteration waits for a host-memory read).
+// Wait for a doorbell slot to leave kDoorEmpty and return what it holds (an edge, or
+// kDoorStop); kDoorStop also after idle_ticks of the device wall clock, kDoorHalt once *halt is
+// set. D reads of the (host-memory) slot are kept in flight, first issued a fraction of a round
+// trip apart, so a release is seen sooner than with one read at a time. The iteration bound is
+// a backstop that ends the wait even if the clock stood still (each iteration waits for a
+// host-memory read).
 template <int D>
-__device__ __forceinline__ uint32_t wait_door(const u64 *door, u64 want, u64 idle_ticks) {
+__device__ __forceinline__ u64 wait_door(const u64 *slot, u64 idle_ticks, const uint32_t *halt) {
   const u64 t0 = wall_clock64();
   u64 d[D];
 #pragma unroll
   for (int k = 0; k < D; k++) {
-    d[k] = __hip_atomic_load(door, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    d[k] = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     if (k + 1 < D) __builtin_amdgcn_s_sleep(8);
   }
-  // branch-free body; each reissue's address depends (opaquely, by zero) on its compare, so it
-  // is not scheduled ahead of the compares and the reads stay spread out
+  // branch-free body in which read k is checked and reissued before read k + 1 is looked at
+  // (scheduling barriers keep the compiler from hoisting the later checks, which would wait for
+  // every read in flight and bunch the reissues), so the reads stay spread out
   for (uint32_t spin = 0; spin < kServerMaxSpins; spin++) {
-    bool hit = false, stop = false;
+    u64 got = kDoorEmpty;
 #pragma unroll
     for (int k = 0; k < D; k++) {
-      const bool h = d[k] == want;
-      hit |= h;
-      stop |= d[k] == kDoorStop;
-      uint32_t dep = h ? 1u : 0u;
-      asm volatile("" : "+v"(dep));
-      d[k] = __hip_atomic_load(door + (dep >> 31), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __builtin_amdgcn_sched_barrier(0);
+      const bool h = d[k] != kDoorEmpty;
+      got = h ? d[k] : got;
+      d[k] = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
-    if (hit) return 1u;
-    if (stop || wall_clock64() - t0 > idle_ticks) return 0u;
+    __builtin_amdgcn_sched_barrier(0);
+    if (got != kDoorEmpty) return got;
+    if (__hip_atomic_load(halt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) return kDoorHalt;
+    if (wall_clock64() - t0 > idle_ticks) return kDoorStop;
     if (D == 1) __builtin_amdgcn_s_sleep(2);
   }
-  return 0u;
+  return kDoorStop;
 }
 
 template <int W>
 __global__ __launch_bounds__(kLocalThreads) void k_insert_server(
-    PropArgs a, const uint32_t *src, const uint32_t *dst, uint32_t first, uint32_t count,
-    uint32_t n, Ovf *ovf, uint64_t ovf_cap, Mirror *m, const u64 *door, uint32_t seq0,
-    u64 idle_ticks, uint32_t polls) {
+    PropArgs a, uint32_t first, uint32_t count, uint32_t n, Ovf *ovf, uint64_t ovf_cap,
+    Mirror *m, const u64 *door, uint32_t seq0, u64 idle_ticks, uint32_t polls) {
   __shared__ uint32_t s_cmd, s_flags;
+  __shared__ u64 s_req;        // request handed from the watching wave to the serving wave
+  __shared__ uint32_t s_req_i;  // ... and its index (~0u: none yet)
+  __shared__ uint32_t s_halt;   // serving wave -> watching wave: stop watching
+  __shared__ uint32_t s_next;   // first request index of the next serving pass
   Ctl *ctl = a.ctl;
   const uint32_t t = threadIdx.x, lane = t & 63u;
   uint32_t i = first;   // meaningful in wave 0
   bool any_ovf = false;  // ditto
   u64 t_go = 0, busy = 0, served = 0;  // meaningful in thread 0
+  if (t == 0) {
+    s_req_i = ~0u;
+    s_halt = 0;
+    s_next = first;
+  }
+  __syncthreads();
   for (;;) {
     if (t < 64u) {
       uint32_t cmd = kCmdExit;
+      // the frontier ring and the queue stamp change only in propagation rounds
+      const uint32_t ring = ld_agent32(&ctl->cur), stamp = ld_agent32(&ctl->stamp);
       for (; i < count; i++) {
-        uint32_t go = 0;
-        if (lane == 0)
-          go = polls > 1 ? wait_door<4>(door, (u64)i + 1u, idle_ticks)
-                         : wait_door<1>(door, (u64)i + 1u, idle_ticks);
-        if (!__shfl(go, 0, 64)) break;
-        if (lane == 0) t_go = wall_clock64();
-        // No cache invalidation here: this path reads ids and row bounds (fixed during the
-        // launch), the control block and the tail label past L1, and pre-reads where an older
-        // value only costs an atomic (head label, queue stamp).
-        const bool act = lane < 2u;
-        uint32_t u = 0, v = 0;
-        if (act) {
-          u = src[i];
-          v = dst[i];
+        u64 req = kDoorStop;
+        if (lane == 0) {
+          // the watcher hands over request i (or a stop) within idle_ticks, or within its
+          // iteration bound; twice the idle limit is a backstop for this wait
+          const u64 w0 = wall_clock64();
+          for (uint32_t spin = 0;; spin++) {
+            if (__hip_atomic_load(&s_req_i, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) == i) {
+              req = s_req;
+              break;
+            }
+            if ((spin & 255u) == 255u && wall_clock64() - w0 > 2 * idle_ticks + 1000000ull) break;
+          }
+          t_go = wall_clock64();
         }
-        const uint32_t ring = ld_agent32(&ctl->cur), stamp = ld_agent32(&ctl->stamp);
-        if (__ballot(act && (u >= n || v >= n))) {
+        req = __shfl(req, 0, 64);
+        if (req == kDoorStop) break;
+        // No cache invalidation here: this path reads row bounds (fixed during the launch), the
+        // tail label past L1, and pre-reads where an older value only costs an atomic (head
+        // label, queue stamp).
+        const bool act = lane < 2u;
+        const uint32_t u = (uint32_t)(req >> 32), v = (uint32_t)req;
+        if (u >= n || v >= n) {  // the host releases no such request; kept as a guard
           if (lane == 0) {
             atomicOr(&ctl->err, kErrRange);
             publish_fast(m, kFastErr, seq0 + (i - first) + 1u);
@@ -1583,10 +1702,21 @@ __global__ __launch_bounds__(kLocalThreads) void k_insert_server(
       }
       if (t == 0) {
         s_cmd = cmd;
+        __hip_atomic_store(&s_halt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (cmd == kCmdExit) {
           ctl->ctr[kCtrServerTicks] += busy;
           ctl->ctr[kCtrServerReqs] += served;
         }
+      }
+    } else if (t == 64u) {
+      // the watcher: hand over requests in order until a stop, the last one, or a halt
+      for (uint32_t j = s_next; j < count; j++) {
+        const u64 r = polls > 1 ? wait_door<4>(door + (j & 1u), idle_ticks, &s_halt)
+                                : wait_door<1>(door + (j & 1u), idle_ticks, &s_halt);
+        if (r == kDoorHalt) break;
+        s_req = r;
+        __hip_atomic_store(&s_req_i, j, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (r == kDoorStop) break;
       }
     }
     __syncthreads();
@@ -1603,6 +1733,8 @@ __global__ __launch_bounds__(kLocalThreads) void k_insert_server(
       busy += wall_clock64() - t_go;
       served++;
       s_flags = flags;
+      s_halt = 0;
+      s_next = i + 1;
       if (flags) {
         ctl->ctr[kCtrServerTicks] += busy;
         ctl->ctr[kCtrServerReqs] += served;
@@ -1614,13 +1746,12 @@ __global__ __launch_bounds__(kLocalThreads) void k_insert_server(
   }
 }
 
-hipError_t launch_insert_server(const PropArgs &a, const uint32_t *src, const uint32_t *dst,
-                                uint32_t first, uint32_t count, uint32_t n, Ovf *ovf,
-                                uint64_t ovf_cap, Mirror *m, const u64 *door, uint32_t seq0,
-                                u64 idle_ticks, uint32_t polls, hipStream_t s) {
+hipError_t launch_insert_server(const PropArgs &a, uint32_t first, uint32_t count, uint32_t n,
+                                Ovf *ovf, uint64_t ovf_cap, Mirror *m, const u64 *door,
+                                uint32_t seq0, u64 idle_ticks, uint32_t polls, hipStream_t s) {
   if (first >= count) return hipSuccess;
-  DBL_LAUNCH_W(a.L.words, k_insert_server, dim3(1), dim3(kLocalThreads), s, a, src, dst, first,
-               count, n, ovf, ovf_cap, m, door, seq0, idle_ticks, polls);
+  DBL_LAUNCH_W(a.L.words, k_insert_server, dim3(1), dim3(kLocalThreads), s, a, first, count, n,
+               ovf, ovf_cap, m, door, seq0, idle_ticks, polls);
   return hipGetLastError();
 }
 

@@ -403,6 +403,18 @@ def test_insert_each_stops_at_bad_id(tiny):
     g.insert_edges_each(dev(w.ins_src[10:200]), dev(w.ins_dst[10:200]))
     o.insert(w.ins_src[10:200], w.ins_dst[10:200])
     assert_labels_equal(g, o, "served after the failure")
+    # ids of all ones, as the first request and after a good one
+    full = np.uint32(0xFFFFFFFF)
+    for k in (0, 1):
+        a = np.array(list(w.ins_src[200:200 + k]) + [full], dtype=np.uint32)
+        b = np.array(list(w.ins_dst[200:200 + k]) + [full], dtype=np.uint32)
+        with pytest.raises(dbl.DblError):
+            g.insert_edges_each(dev(a), dev(b))
+        o.insert(w.ins_src[200:200 + k], w.ins_dst[200:200 + k])
+    assert_labels_equal(g, o, "refused ids of all ones")
+    g.insert_edges_each(dev(w.ins_src[201:300]), dev(w.ins_dst[201:300]))
+    o.insert(w.ins_src[201:300], w.ins_dst[201:300])
+    assert_labels_equal(g, o, "served after ids of all ones")
 
 
 def test_query_graph_replays(tiny):
