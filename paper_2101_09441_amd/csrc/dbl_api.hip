@@ -996,7 +996,9 @@ dbl_status do_build(dbl_index *ix, uint64_t m, const uint32_t *src, const uint32
 dbl_status insert_each_served(dbl_index *ix, uint32_t count, const uint32_t *d_src,
                               const uint32_t *d_dst, float *h_latency_us, hipStream_t s) {
   u64 *door = ix->door;
-  auto put = [](u64 *slot, u64 v) { __atomic_store_n(slot, v, __ATOMIC_SEQ_CST); };
+  // release stores: x86 makes stores visible in program order, so an emptied slot is seen
+  // empty before the next release becomes visible, with no fence on the request path
+  auto put = [](u64 *slot, u64 v) { __atomic_store_n(slot, v, __ATOMIC_RELEASE); };
   // whatever way this returns, a launch still waiting for a request ends at once, and the
   // staging copy of the ids goes back to the cache
   struct OnExit {

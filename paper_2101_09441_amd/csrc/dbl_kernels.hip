@@ -488,7 +488,12 @@ hipError_t scan_exclusive(const uint32_t *in, u64 *out, uint32_t n, u64 *tmp, u6
 // partitioned edges in order, so the atomics and stores of neighbouring threads fall into the
 // rows of one or two bins at a time, a window that stays in cache.
 constexpr uint32_t kMaxBins = 4096;
+// One workgroup per bin counts degrees and fills rows in LDS while a bin spans at most kBinVerts
+// vertices (see k_bin_deg).
+constexpr uint32_t kBinVerts = 16384, kBinNT = 1024;
 
+// The fewest bins of at most kMaxBins: narrow bins keep the row writes of k_bin_fill within a
+// small window of the rows.
 uint32_t bin_shift(uint32_t n) {
   uint32_t sh = 0;
   while (((uint64_t)(n - 1) >> sh) >= kMaxBins) sh++;
@@ -529,35 +534,80 @@ __global__ __launch_bounds__(256) void k_bin_hist(const uint32_t *__restrict__ k
 }
 
 // out[pos] = key << 32 | val for every kept edge, grouped by bin (order inside a bin is
-// arbitrary)
-__global__ __launch_bounds__(256) void k_bin_scatter(const uint32_t *__restrict__ key,
-                                                     const uint32_t *__restrict__ val,
-                                                     const uint8_t *__restrict__ keep, uint64_t m,
-                                                     uint32_t shift, uint32_t nbins,
-                                                     uint64_t chunk, const u64 *__restrict__ offs,
-                                                     u64 *__restrict__ out) {
-  __shared__ u64 cur[kMaxBins];
-  for (uint32_t i = threadIdx.x; i < nbins; i += 256u)
-    cur[i] = offs[(uint64_t)i * gridDim.x + blockIdx.x];
+// arbitrary). Each block sorts its chunk by bin one tile of kScatTile edges at a time in LDS
+// (rank by LDS atomic, exclusive scan of the tile's bin counts) and writes the tile out in
+// sorted order: consecutive threads write consecutive slots of one bin's run, so the output is
+// written in runs instead of one scattered 8-byte store per edge.
+constexpr uint32_t kScatNT = 512, kScatPer = 16, kScatTile = kScatNT * kScatPer;
+
+__global__ __launch_bounds__(kScatNT) void k_bin_scatter(const uint32_t *__restrict__ key,
+                                                         const uint32_t *__restrict__ val,
+                                                         const uint8_t *__restrict__ keep,
+                                                         uint64_t m, uint32_t shift,
+                                                         uint32_t nbins, uint64_t chunk,
+                                                         const u64 *__restrict__ offs,
+                                                         u64 *__restrict__ out) {
+  __shared__ u64 s_item[kScatTile];
+  __shared__ u64 s_cur[kMaxBins];      // next output slot of each bin for this block
+  __shared__ uint32_t s_pos[kMaxBins];  // tile counts, then their exclusive scan
+  __shared__ uint32_t s_wsum[kScatNT / 64];
+  const uint32_t t = threadIdx.x;
+  constexpr uint32_t kPerT = (kMaxBins + kScatNT - 1) / kScatNT;  // bins per thread in the scan
+  for (uint32_t i = t; i < nbins; i += kScatNT) {
+    s_cur[i] = offs[(uint64_t)i * gridDim.x + blockIdx.x];
+    s_pos[i] = 0;
+  }
   __syncthreads();
   const uint64_t lo = blockIdx.x * chunk, hi = min(m, lo + chunk);
-  for (uint64_t e0 = lo + threadIdx.x; e0 < hi; e0 += 256u * kBinUnroll) {
-    uint32_t k[kBinUnroll], x[kBinUnroll];
-    bool ok[kBinUnroll];
+  for (uint64_t base = lo; base < hi; base += kScatTile) {
+    u64 item[kScatPer];
+    uint32_t rank[kScatPer];
+    bool ok[kScatPer];
 #pragma unroll
-    for (uint32_t j = 0; j < kBinUnroll; j++) {
-      const uint64_t e = e0 + 256u * j;
+    for (uint32_t j = 0; j < kScatPer; j++) {
+      const uint64_t e = base + kScatNT * j + t;
       ok[j] = e < hi;
-      k[j] = ok[j] ? key[e] : 0u;
-      x[j] = ok[j] ? val[e] : 0u;
+      item[j] = ok[j] ? ((u64)key[e] << 32) | val[e] : 0ull;
       ok[j] = ok[j] && keep[e];
     }
 #pragma unroll
-    for (uint32_t j = 0; j < kBinUnroll; j++)
-      if (ok[j]) {
-        const u64 pos = atomicAdd(&cur[k[j] >> shift], 1ull);
-        out[pos] = ((u64)k[j] << 32) | x[j];
-      }
+    for (uint32_t j = 0; j < kScatPer; j++)
+      rank[j] = ok[j] ? atomicAdd(&s_pos[(uint32_t)(item[j] >> 32) >> shift], 1u) : 0u;
+    __syncthreads();
+    // exclusive scan of the tile's counts over the bins (thread t owns bins [t*kPerT, ...))
+    uint32_t c[kPerT], sum = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kPerT; k++) {
+      const uint32_t b = t * kPerT + k;
+      c[k] = b < nbins ? s_pos[b] : 0u;
+      sum += c[k];
+    }
+    uint32_t total;
+    uint32_t run = block_excl_scan<kScatNT>(sum, s_wsum, total);
+#pragma unroll
+    for (uint32_t k = 0; k < kPerT; k++) {
+      const uint32_t b = t * kPerT + k;
+      if (b < nbins) s_pos[b] = run;
+      run += c[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (uint32_t j = 0; j < kScatPer; j++)
+      if (ok[j]) s_item[s_pos[(uint32_t)(item[j] >> 32) >> shift] + rank[j]] = item[j];
+    __syncthreads();
+    for (uint32_t p = t; p < total; p += kScatNT) {
+      const u64 x = s_item[p];
+      const uint32_t b = (uint32_t)(x >> 32) >> shift;
+      out[s_cur[b] + (p - s_pos[b])] = x;
+    }
+    __syncthreads();
+    for (uint32_t b = t; b < nbins; b += kScatNT) {
+      const uint32_t end = b + 1 < nbins ? s_pos[b + 1] : total;
+      s_cur[b] += end - s_pos[b];
+    }
+    __syncthreads();
+    for (uint32_t b = t; b < nbins; b += kScatNT) s_pos[b] = 0;
+    __syncthreads();
   }
 }
 
@@ -571,15 +621,14 @@ hipError_t launch_bin_edges(const uint32_t *key, const uint32_t *val, const uint
                      counts);
   hipError_t e = scan_exclusive(counts, offs, nbins * nblk, scan_tmp, kept, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_bin_scatter, dim3(nblk), dim3(256), 0, s, key, val, keep, m, shift, nbins,
-                     chunk, offs, out);
+  hipLaunchKernelGGL(k_bin_scatter, dim3(nblk), dim3(kScatNT), 0, s, key, val, keep, m, shift,
+                     nbins, chunk, offs, out);
   return hipGetLastError();
 }
 
 // One workgroup per bin (while a bin spans at most kBinVerts vertices): the bin's edges are
 // contiguous, so degrees and row cursors are counted in LDS, degrees are written in order and
 // row writes stay within the bin's rows; no global atomics.
-constexpr uint32_t kBinVerts = 16384, kBinNT = 1024;
 
 __device__ __forceinline__ void bin_range(const u64 *offs, uint32_t nblk, uint32_t nbins,
                                           u64 kept, uint32_t bin, u64 &lo, u64 &hi) {
