@@ -1985,14 +1985,18 @@ hipError_t launch_query_label(LabelsView L, const uint32_t *u, const uint32_t *v
   return hipGetLastError();
 }
 
-// Pruned BFS of Algorithm 2, one wavefront per undecided pair, pairs pulled from a counter.
-// Each wave owns a visited bitmap and a queue. The queue is processed 64 entries at a time:
-// their rows are laid end to end and every lane takes one edge (a prefix sum over the lanes'
-// degrees maps edge slots to rows), so short and long rows both keep the lanes busy.
-// Prunes: a target x is skipped when a landmark of u reaches it (DL_out(u) & DL_in(x)) or when
-// it cannot reach v (BL_Contain(x, v) fails). The visited bits are cleared by replaying the
-// queue, so a bitmap is clean again for the wave's next pair.
+// Pruned BFS of Algorithm 2, one wavefront per undecided pair. A search runs first in the wave's
+// LDS: a queue of up to kBfsLdsQ vertices and an open-addressing visited set, so that no step
+// of a small search waits for a global queue write to come back or for a global atomic. A
+// search that outgrows the LDS queue starts again over the slot's global queue and visited
+// bitmap (up to the context's queue capacity); one that outgrows that goes to the whole-device
+// BFS. The queue is processed 64 entries at a time: their rows are laid end to end and every
+// lane takes one edge (a prefix sum over the lanes' degrees maps edge slots to rows), so short
+// and long rows both keep the lanes busy. Prunes: a target x is skipped when a landmark of u
+// reaches it (DL_out(u) & DL_in(x)) or when it cannot reach v (BL_Contain(x, v) fails).
 constexpr uint32_t kBfsNT = 256;
+constexpr uint32_t kBfsLdsQ = 1024, kBfsHashBits = 11, kBfsHash = 1u << kBfsHashBits;
+constexpr uint32_t kBfsEmpty = 0xFFFFFFFFu;
 
 // The prune of Algorithm 2 for a target x with record rx, against the query's wave-uniform
 // label words: skip x when DL_out(u) & DL_in(x) != 0 or when BL_in(x) is not inside BL_in(v) or
@@ -2023,102 +2027,152 @@ __device__ __forceinline__ void bfs_prune_words(const u64 *lab, uint32_t u, uint
   }
 }
 
-template <int W>
-__global__ __launch_bounds__(kBfsNT) void k_query_bfs(BfsArgs a, Mirror *m, uint32_t seq) {
-  Ctl *ctl = a.ctl;
-  const uint32_t lane = __lane_id();
-  const uint32_t slot = blockIdx.x * (kBfsNT / 64u) + (threadIdx.x >> 6);
-  u64 *vis = a.vis + (uint64_t)slot * a.vis_words;
-  uint32_t *q = a.queue + (uint64_t)slot * a.qcap;
-  const uint32_t waves = gridDim.x * (kBfsNT / 64u);
-  const u64 *lab = a.L.lab;
-  u64 n_vert = 0, n_edge = 0, cls_t = 0, cls_f = 0;
-  // undecided pairs sit in per-block segments of the label kernel; wave `slot` takes segments
-  // slot, slot + waves, ... (no shared work counter)
-  uint32_t sg = slot, sj = 0, scnt = sg < a.nseg ? a.seg[sg] : 0u;
+// Insert x into a wave's LDS visited set (linear probing); true when x was not in it. The set
+// never holds more than kBfsLdsQ + 64 ids (inserts stop once the queue is full), so a probe
+// always reaches a free slot.
+__device__ __forceinline__ bool lds_visit(uint32_t *h, uint32_t x) {
+  uint32_t i = (x * 2654435761u) >> (32 - kBfsHashBits);
   for (;;) {
-    while (sg < a.nseg && sj >= scnt) {
-      sg += waves;
-      sj = 0;
-      scnt = sg < a.nseg ? a.seg[sg] : 0u;
+    const uint32_t old = atomicCAS(&h[i], kBfsEmpty, x);
+    if (old == kBfsEmpty) return true;
+    if (old == x) return false;
+    i = (i + 1u) & (kBfsHash - 1u);
+  }
+}
+
+// One pruned BFS from u toward v over the forward rows, with the queue at qp (capacity cap)
+// and the visited set in LDS (LOCAL, hs) or in the bitmap vis. Returns 1 when v is reached, 0
+// when the search is exhausted, 2 when the queue would exceed cap (then, in the bitmap form,
+// every set bit is listed in the queue). *tail_out: the queue length at the end.
+template <int W, bool LOCAL>
+__device__ uint32_t bfs_run(const BfsArgs &a, uint32_t u, uint32_t v, const u64 *dlo_u,
+                            const u64 *bli_v, const u64 *blo_v, uint32_t *qp, u64 *vis,
+                            uint32_t *hs, uint32_t cap, uint32_t *tail_out, u64 &n_vert,
+                            u64 &n_edge) {
+  const uint32_t lane = __lane_id();
+  const u64 *lab = a.L.lab;
+  if (lane == 0) {
+    if (LOCAL) lds_visit(hs, u);
+    else atomicOr(&vis[u >> 6], 1ull << (u & 63u));
+    qp[0] = u;
+  }
+  uint32_t head = 0, tail = 1, st = 0;
+  while (head < tail) {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    const uint32_t chunk = min(64u, tail - head);
+    uint32_t d = 0;
+    u64 o = 0;
+    if (lane < chunk) {
+      const uint32_t w = qp[head + lane];
+      d = min(a.f.deg[w], a.f.cap[w]);
+      o = a.f.off[w];
     }
-    if (sg >= a.nseg) break;
-    const uint32_t qi = a.und[(uint64_t)sg * kQueryNT + sj];
-    sj++;
-    const uint32_t u = a.u[qi], v = a.v[qi];
-    u64 dlo_u[W], bli_v[W], blo_v[W];
-    bfs_prune_words<W>(lab, u, v, a.rules, dlo_u, bli_v, blo_v);
-    if (lane == 0) {
-      atomicOr(&vis[u >> 6], 1ull << (u & 63u));
-      q[0] = u;
-    }
-    uint32_t head = 0, tail = 1;
-    bool found = false, overflow = false;
-    while (head < tail) {
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      const uint32_t chunk = min(64u, tail - head);
-      uint32_t d = 0;
-      u64 o = 0;
-      if (lane < chunk) {
-        const uint32_t w = q[head + lane];
-        d = min(a.f.deg[w], a.f.cap[w]);
-        o = a.f.off[w];
-      }
-      const uint32_t incl = wave_incl_scan(d);
-      const uint32_t ex = incl - d;
-      const uint32_t total = __shfl(incl, 63, 64);
-      n_vert += chunk;
-      n_edge += total;
-      for (uint32_t base = 0; base < total; base += 64u) {
-        const uint32_t e = base + lane;
-        // owner row of edge slot e: the last lane whose exclusive prefix is <= e
-        uint32_t lo = 0;
+    const uint32_t incl = wave_incl_scan(d);
+    const uint32_t ex = incl - d;
+    const uint32_t total = __shfl(incl, 63, 64);
+    n_vert += chunk;
+    n_edge += total;
+    for (uint32_t base = 0; base < total; base += 64u) {
+      const uint32_t e = base + lane;
+      // owner row of edge slot e: the last lane whose exclusive prefix is <= e
+      uint32_t lo = 0;
 #pragma unroll
-        for (uint32_t step = 32; step > 0; step >>= 1) {
-          const uint32_t cand = lo + step;
-          const uint32_t st = __shfl(ex, (int)cand, 64);
-          if (cand < 64u && st <= e) lo = cand;
-        }
-        const u64 ow_off = __shfl(o, (int)lo, 64);
-        const uint32_t ow_ex = __shfl(ex, (int)lo, 64);
-        const bool act = e < total;
-        uint32_t x = 0;
-        if (act) x = a.f.col[ow_off + (e - ow_ex)];
-        if (__ballot(act && x == v)) {
-          found = true;
-          break;
-        }
-        bool keep = false;
-        u64 bit = 0;
-        if (act) {
-          keep = !bfs_prune<W>(lab + 4ull * W * x, dlo_u, bli_v, blo_v);
-          if (keep) {
+      for (uint32_t step = 32; step > 0; step >>= 1) {
+        const uint32_t cand = lo + step;
+        const uint32_t stt = __shfl(ex, (int)cand, 64);
+        if (cand < 64u && stt <= e) lo = cand;
+      }
+      const u64 ow_off = __shfl(o, (int)lo, 64);
+      const uint32_t ow_ex = __shfl(ex, (int)lo, 64);
+      const bool act = e < total;
+      uint32_t x = 0;
+      if (act) x = a.f.col[ow_off + (e - ow_ex)];
+      if (__ballot(act && x == v)) {
+        st = 1;
+        break;
+      }
+      bool keep = false;
+      u64 bit = 0;
+      if (act) {
+        keep = !bfs_prune<W>(lab + 4ull * W * x, dlo_u, bli_v, blo_v);
+        if (keep) {
+          if (LOCAL) {
+            keep = lds_visit(hs, x);
+          } else {
             bit = 1ull << (x & 63u);
             keep = !(atomicOr(&vis[x >> 6], bit) & bit);
           }
         }
-        const u64 km = __ballot(keep);
-        const uint32_t cnt = (uint32_t)__popcll(km);
-        if (tail + cnt > a.qcap) {
-          if (keep) atomicAnd(&vis[x >> 6], ~bit);  // every set bit stays listed in the queue
-          overflow = true;
-          break;
-        }
-        if (keep) q[tail + lanemask_lt_popc(km)] = x;
-        tail += cnt;
       }
-      if (found || overflow) break;
-      head += chunk;
+      const u64 km = __ballot(keep);
+      const uint32_t cnt = (uint32_t)__popcll(km);
+      if (tail + cnt > cap) {
+        if (!LOCAL && keep) atomicAnd(&vis[x >> 6], ~bit);  // every set bit stays listed
+        st = 2;
+        break;
+      }
+      if (keep) qp[tail + lanemask_lt_popc(km)] = x;
+      tail += cnt;
     }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    for (uint32_t i = lane; i < tail; i += 64u) atomicExch(&vis[q[i] >> 6], 0ull);
-    if (lane == 0) {
-      if (overflow) {
-        const uint32_t h = atomicAdd(&ctl->bfs_heavy, 1u);
-        a.heavy_q[h] = qi;
-      } else {
-        a.out[qi] = found ? (uint8_t)(1u | (5u << 1)) : (uint8_t)(6u << 1);
-        if (found) cls_t++; else cls_f++;
+    if (st) break;
+    head += chunk;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  *tail_out = tail;
+  return st;
+}
+
+// Undecided pairs sit in per-block segments of the label kernel; wave `slot` takes segments
+// slot, slot + waves, ..., reading 64 segment counts at a time (one per lane).
+template <int W>
+__global__ __launch_bounds__(kBfsNT) void k_query_bfs(BfsArgs a, Mirror *m, uint32_t seq) {
+  __shared__ uint32_t s_q[kBfsNT / 64][kBfsLdsQ];
+  __shared__ uint32_t s_h[kBfsNT / 64][kBfsHash];
+  Ctl *ctl = a.ctl;
+  const uint32_t lane = __lane_id(), wv = threadIdx.x >> 6;
+  const uint32_t slot = blockIdx.x * (kBfsNT / 64u) + wv;
+  u64 *vis = a.vis + (uint64_t)slot * a.vis_words;
+  uint32_t *q = a.queue + (uint64_t)slot * a.qcap;
+  uint32_t *sq = s_q[wv], *hs = s_h[wv];
+  const uint32_t waves = gridDim.x * (kBfsNT / 64u);
+  const uint32_t lcap = min(kBfsLdsQ, a.qcap);
+  const u64 *lab = a.L.lab;
+  u64 n_vert = 0, n_edge = 0, cls_t = 0, cls_f = 0;
+  for (uint32_t i = lane; i < kBfsHash; i += 64u) hs[i] = kBfsEmpty;
+  for (uint64_t sb = slot; sb < a.nseg; sb += 64ull * waves) {
+    const uint64_t my = sb + (uint64_t)lane * waves;
+    const uint32_t mycnt = my < a.nseg ? a.seg[my] : 0u;
+    u64 busy = __ballot(mycnt != 0u);
+    while (busy) {
+      const uint32_t k = (uint32_t)__builtin_ctzll(busy);
+      busy &= busy - 1ull;
+      const uint64_t sg = sb + (uint64_t)k * waves;
+      const uint32_t scnt = __shfl(mycnt, (int)k, 64);
+      for (uint32_t sj = 0; sj < scnt; sj++) {
+        const uint32_t qi = a.und[sg * kQueryNT + sj];
+        const uint32_t u = a.u[qi], v = a.v[qi];
+        u64 dlo_u[W], bli_v[W], blo_v[W];
+        bfs_prune_words<W>(lab, u, v, a.rules, dlo_u, bli_v, blo_v);
+        uint32_t tail = 0;
+        uint32_t st = bfs_run<W, true>(a, u, v, dlo_u, bli_v, blo_v, sq, vis, hs, lcap, &tail,
+                                       n_vert, n_edge);
+        for (uint32_t i = lane; i < kBfsHash; i += 64u) hs[i] = kBfsEmpty;
+        if (st == 2 && a.qcap > lcap) {
+          // too large for LDS: again over the slot's global queue and bitmap
+          st = bfs_run<W, false>(a, u, v, dlo_u, bli_v, blo_v, q, vis, hs, a.qcap, &tail,
+                                 n_vert, n_edge);
+          for (uint32_t i = lane; i < tail; i += 64u) atomicExch(&vis[q[i] >> 6], 0ull);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        if (lane == 0) {
+          if (st == 2) {
+            const uint32_t h = atomicAdd(&ctl->bfs_heavy, 1u);
+            a.heavy_q[h] = qi;
+          } else {
+            a.out[qi] = st == 1 ? (uint8_t)(1u | (5u << 1)) : (uint8_t)(6u << 1);
+            if (st == 1) cls_t++; else cls_f++;
+          }
+        }
       }
     }
   }
@@ -2130,12 +2184,12 @@ __global__ __launch_bounds__(kBfsNT) void k_query_bfs(BfsArgs a, Mirror *m, uint
     c[3] += cls_f;
   }
   if (lane == 0) {
-    // make this wave's answers visible before counting it as done; the last wave publishes
-    __threadfence();
-    if (atomicAdd(&ctl->bfs_done, 1u) == waves - 1u) {
-      __threadfence();
-      publish_status(ctl, m, seq);
-    }
+    // The last wave to finish publishes. No device-wide fence per wave: on a multi-XCD device
+    // each one writes back and invalidates the XCD's L2 under the waves still searching. The
+    // answers are only read through work ordered after this kernel on its stream, and the
+    // status fields are device-scope atomics that every wave has seen performed (it waited for
+    // their results) before its done count.
+    if (atomicAdd(&ctl->bfs_done, 1u) == waves - 1u) publish_status(ctl, m, seq);
   }
 }
 
