@@ -484,7 +484,10 @@ dbl_status grid_propagate(dbl_index *ix, hipStream_t s, uint32_t group, uint64_t
         ix->fbm_words = 0;
         CKS(dalloc(&ix->fbm, words));
         ix->fbm_words = words;
-        if (!ix->fu) CKS(dalloc(&ix->fu, 16));
+        if (!ix->fu) {
+          CKS(dalloc(&ix->fu, dbl::kFuWords));
+          CK(dbl::launch_fill_u64(ix->fu, 0ull, dbl::kFuWords, s));  // stripes start at zero
+        }
       }
       dbl::PropArgs a = prop_args(ix);
       CK(dbl::launch_frontier_scan(a, cur, stamp, ix->fbm_words, s));

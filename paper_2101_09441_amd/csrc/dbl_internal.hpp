@@ -63,7 +63,7 @@ struct Ctl {
   uint32_t bfs_heavy;   // queries whose BFS outgrew a slot
   uint32_t found;       // grid BFS: target reached
   uint32_t local_rounds;
-  uint32_t bfs_done;    // BFS waves finished (the last one publishes the status)
+  uint32_t bfs_done;    // BFS blocks finished (the last one publishes the status)
   uint32_t pheavy;      // chunks of high-degree rows queued for the pull round
   unsigned long long ctr[kCtrCount];
 };
@@ -98,6 +98,9 @@ constexpr uint32_t kBfsCtrStride = 4;  // vertices, edges, true, false per BFS s
 // propagation counters: grid rounds use slots [0, 2048), heavy chunks [2048, 3072), the
 // single-workgroup rounds slot 3072
 constexpr uint32_t kRoundGridMax = 2048, kHeavyGrid = 1024;
+// Stripes of the frontier scan's block reductions (atomics on one address are served one at a
+// time); stripe s holds 16 label words and 4 counts at fu + kFuStride * (1 + s).
+constexpr uint32_t kFuStripes = 64, kFuStride = 32, kFuWords = kFuStride * (1 + kFuStripes);
 constexpr uint32_t kPropCtrSlots = kRoundGridMax + kHeavyGrid + 1;
 
 // Overflowing append: row `x` (bit 31 = reverse CSR) wanted entry `y` at position `pos`.
@@ -191,7 +194,10 @@ struct PropArgs {
   uint64_t heavy_cap;
   unsigned long long *fbm;          // frontier bitmaps of the pull round, one per direction:
   uint64_t fbm_wpd;                 // bit x of fbm[dir * fbm_wpd + x / 64]
-  unsigned long long *fu;           // OR of the frontier's labels, per direction: fu[dir * 8 ...]
+  // OR of the frontier's labels, per direction, in fu[dir * 8 ...]; the frontier scan adds
+  // into kFuStripes stripes (each kFuStride words, from word kFuStride on) that a one-block
+  // kernel then reduces
+  unsigned long long *fu;
   unsigned long long *pcnt;  // [kPropCtrSlots * 2] per-block (expanded, relaxed) counters
   uint32_t local_max_frontier, local_max_edges;
   Ctl *ctl;

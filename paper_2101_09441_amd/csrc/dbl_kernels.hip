@@ -75,18 +75,36 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t *s_wsum
   return off + incl - x;
 }
 
-// Append `val` to q for every thread with `pred`, with one atomic on the queue counter per
-// block (for kernels where whole waves push at once and the counter would otherwise see one
-// atomic per wave). Every thread of the block must call it.
+// Queue appends staged in LDS: a block collects the appends of many tiles in s_buf (CAP
+// entries, CAP >= NT) and writes them out with one atomic on the queue counter per flush
+// instead of one per tile (atomics on one address are served one at a time, ~10 ns each).
+// Every thread of the block must call both; *s_n starts at 0.
 template <int NT>
-__device__ __forceinline__ void block_push(uint32_t *q, uint32_t *cnt, bool pred, uint32_t val,
-                                           uint32_t *s_wsum, uint32_t *s_base) {
+__device__ __forceinline__ void stage_flush(uint32_t *q, uint32_t *cnt, uint32_t *s_buf,
+                                            uint32_t *s_n, uint32_t *s_base) {
+  const uint32_t k = *s_n;
+  if (k == 0) return;
+  if (threadIdx.x == 0) *s_base = atomicAdd(cnt, k);
+  __syncthreads();
+  const uint32_t base = *s_base;
+  for (uint32_t i = threadIdx.x; i < k; i += NT) q[base + i] = s_buf[i];
+  __syncthreads();
+  if (threadIdx.x == 0) *s_n = 0;
+  __syncthreads();
+}
+
+template <int NT, uint32_t CAP>
+__device__ __forceinline__ void stage_push(uint32_t *q, uint32_t *cnt, bool pred, uint32_t val,
+                                           uint32_t *s_buf, uint32_t *s_n, uint32_t *s_base,
+                                           uint32_t *s_wsum) {
+  static_assert(CAP >= (uint32_t)NT, "a tile must fit the stage");
   uint32_t total;
   const uint32_t ex = block_excl_scan<NT>(pred ? 1u : 0u, s_wsum, total);
   if (total == 0) return;
-  if (threadIdx.x == 0) *s_base = atomicAdd(cnt, total);
+  if (*s_n + total > CAP) stage_flush<NT>(q, cnt, s_buf, s_n, s_base);
+  if (pred) s_buf[*s_n + ex] = val;
   __syncthreads();
-  if (pred) q[*s_base + ex] = val;
+  if (threadIdx.x == 0) *s_n += total;
   __syncthreads();
 }
 
@@ -901,16 +919,20 @@ hipError_t launch_seed(LabelsView L, uint32_t n, const uint32_t *landmarks, uint
   return hipGetLastError();
 }
 
+constexpr uint32_t kInitStage = 4096;
+
 template <int W>
 __global__ __launch_bounds__(256) void k_init_frontier(const u64 *lab, uint32_t n, Csr f, Csr r,
                                                        uint32_t *frontier, Ctl *ctl,
                                                        uint32_t ring, uint32_t *inq,
                                                        uint32_t stamp) {
-  __shared__ uint32_t s_wsum[4], s_base;
+  __shared__ uint32_t s_wsum[4], s_base, s_n;
+  __shared__ uint32_t s_stage[kInitStage];
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     ctl->heavy[0] = 0;
     ctl->heavy[1] = 0;
   }
+  if (threadIdx.x == 0) s_n = 0;
   for (uint32_t x0 = blockIdx.x * blockDim.x; x0 < n; x0 += gridDim.x * blockDim.x) {
     const uint32_t x = x0 + threadIdx.x;
     bool pf = false, pb = false;
@@ -920,15 +942,18 @@ __global__ __launch_bounds__(256) void k_init_frontier(const u64 *lab, uint32_t 
       if (pf) inq[2ull * x] = stamp;
       if (pb) inq[2ull * x + 1] = stamp;
     }
-    block_push<256>(frontier, &ctl->fsize[ring], pf, x, s_wsum, &s_base);
-    block_push<256>(frontier, &ctl->fsize[ring], pb, x | kDirBit, s_wsum, &s_base);
+    stage_push<256, kInitStage>(frontier, &ctl->fsize[ring], pf, x, s_stage, &s_n, &s_base,
+                                s_wsum);
+    stage_push<256, kInitStage>(frontier, &ctl->fsize[ring], pb, x | kDirBit, s_stage, &s_n,
+                                &s_base, s_wsum);
   }
+  stage_flush<256>(frontier, &ctl->fsize[ring], s_stage, &s_n, &s_base);
 }
 
 hipError_t launch_init_frontier(LabelsView L, uint32_t n, Csr f, Csr r, uint32_t *frontier,
                                 Ctl *ctl, uint32_t *inq, uint32_t stamp, hipStream_t s) {
   // the pending frontier is ring 0 at build time
-  DBL_LAUNCH_W(L.words, k_init_frontier, dim3(grid_for(n, 256, 8192)), dim3(256), s, L.lab, n, f,
+  DBL_LAUNCH_W(L.words, k_init_frontier, dim3(grid_for(n, 256, 1024)), dim3(256), s, L.lab, n, f,
                r, frontier, ctl, 0u, inq, stamp);
   return hipGetLastError();
 }
@@ -1168,15 +1193,35 @@ __global__ __launch_bounds__(256) void k_frontier_scan(PropArgs a, uint32_t ring
       if (lane == 0) s_or[w][d][j] = x;
     }
   __syncthreads();
+  u64 *stripe = a.fu + kFuStride * (1u + (blockIdx.x & (kFuStripes - 1u)));
   if (threadIdx.x < 4) {
     const u64 sum = s_red[0][threadIdx.x] + s_red[1][threadIdx.x] + s_red[2][threadIdx.x] +
                     s_red[3][threadIdx.x];
-    if (sum) atomicAdd(&ctl->ctr[kCtrFrontEntries + threadIdx.x], sum);
+    if (sum) atomicAdd(&stripe[16 + threadIdx.x], sum);
   }
   if (threadIdx.x < 4 * W) {
     const uint32_t d = threadIdx.x / (2 * W), j = threadIdx.x % (2 * W);
     const u64 x = s_or[0][d][j] | s_or[1][d][j] | s_or[2][d][j] | s_or[3][d][j];
-    if (x) atomicOr(&a.fu[d * 8 + j], x);
+    if (x) atomicOr(&stripe[d * 8 + j], x);
+  }
+}
+
+// One wave: reduce the scan's stripes into fu[0, 16) and the four frontier counts, and zero
+// the stripes for the next scan.
+__global__ __launch_bounds__(64) void k_frontier_reduce(u64 *fu, Ctl *ctl) {
+  u64 *st = fu + kFuStride * (1u + threadIdx.x);
+  for (uint32_t k = 0; k < 20; k++) {
+    u64 x = st[k];
+    st[k] = 0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const u64 y = __shfl_xor(x, o, 64);
+      x = k < 16 ? (x | y) : (x + y);
+    }
+    if (threadIdx.x == 0) {
+      if (k < 16) fu[k] = x;
+      else ctl->ctr[kCtrFrontEntries + (k - 16)] = x;
+    }
   }
 }
 
@@ -1184,11 +1229,8 @@ hipError_t launch_frontier_scan(const PropArgs &a, uint32_t ring, uint32_t stamp
                                 uint64_t fbm_words, hipStream_t s) {
   hipError_t e = launch_fill_u64(a.fbm, 0ull, fbm_words, s);
   if (e != hipSuccess) return e;
-  e = launch_fill_u64(&a.ctl->ctr[kCtrFrontEntries], 0ull, 4, s);
-  if (e != hipSuccess) return e;
-  e = launch_fill_u64(a.fu, 0ull, 16, s);
-  if (e != hipSuccess) return e;
   DBL_LAUNCH_W(a.L.words, k_frontier_scan, dim3(kRoundGridMax), dim3(256), s, a, ring, stamp);
+  hipLaunchKernelGGL(k_frontier_reduce, dim3(1), dim3(kFuStripes), 0, s, a.fu, a.ctl);
   return hipGetLastError();
 }
 
@@ -1228,7 +1270,7 @@ __device__ __forceinline__ void acc_or(u64 (*s_acc)[2 * W], uint32_t row, bool a
 
 // Pull rows: 256 rows per tile, the rows' edges laid end to end and taken one per thread (as
 // in expand_tile). Rows longer than kHeavyDeg go to k_pull_heavy in chunks.
-constexpr uint32_t kPullUnroll = 4;
+constexpr uint32_t kPullUnroll = 4, kPullStage = 2048;
 
 template <int W>
 __global__ __launch_bounds__(256) void k_pull(PropArgs a, uint32_t n, uint32_t dmask,
@@ -1238,9 +1280,11 @@ __global__ __launch_bounds__(256) void k_pull(PropArgs a, uint32_t n, uint32_t d
   __shared__ uint32_t s_row[256];
   __shared__ uint32_t s_wsum[4];
   __shared__ u64 s_acc[256][2 * W];
-  __shared__ uint32_t s_base;
+  __shared__ uint32_t s_base, s_n;
+  __shared__ uint32_t s_stage[kPullStage];
   Ctl *ctl = a.ctl;
   const uint32_t t = threadIdx.x;
+  if (t == 0) s_n = 0;
   const uint32_t ndir = __popc(dmask);
   const uint32_t d_only = (dmask & 1u) ? 0u : 1u;
   const uint64_t rows = (uint64_t)n * ndir;
@@ -1334,9 +1378,11 @@ __global__ __launch_bounds__(256) void k_pull(PropArgs a, uint32_t n, uint32_t d
       }
       push = grew && claim(&a.inq[2ull * y + d], nstamp);
     }
-    block_push<256>(a.fq[nring], &ctl->fsize[nring], push, y | (d << 31), s_wsum, &s_base);
+    stage_push<256, kPullStage>(a.fq[nring], &ctl->fsize[nring], push, y | (d << 31), s_stage,
+                                &s_n, &s_base, s_wsum);
     __syncthreads();
   }
+  stage_flush<256>(a.fq[nring], &ctl->fsize[nring], s_stage, &s_n, &s_base);
   __shared__ u64 s_tmp[4];
   relaxed = block_sum256(relaxed, s_tmp);
   if (t == 0 && relaxed) a.pcnt[2 * blockIdx.x + 1] += relaxed;
@@ -2183,14 +2229,15 @@ __global__ __launch_bounds__(kBfsNT) void k_query_bfs(BfsArgs a, Mirror *m, uint
     c[2] += cls_t;
     c[3] += cls_f;
   }
-  if (lane == 0) {
-    // The last wave to finish publishes. No device-wide fence per wave: on a multi-XCD device
-    // each one writes back and invalidates the XCD's L2 under the waves still searching. The
-    // answers are only read through work ordered after this kernel on its stream, and the
-    // status fields are device-scope atomics that every wave has seen performed (it waited for
-    // their results) before its done count.
-    if (atomicAdd(&ctl->bfs_done, 1u) == waves - 1u) publish_status(ctl, m, seq);
-  }
+  // The last block to finish publishes; one done count per block, not per wave (atomics on one
+  // address are served one at a time, ~10 ns each). No device-wide fence: on a multi-XCD device
+  // each one writes back and invalidates the XCD's L2 under the waves still searching. The
+  // answers are only read through work ordered after this kernel on its stream, and the status
+  // fields are device-scope atomics that every wave has seen performed (it waited for their
+  // results) before the block's done count.
+  __syncthreads();
+  if (threadIdx.x == 0 && atomicAdd(&ctl->bfs_done, 1u) == gridDim.x - 1u)
+    publish_status(ctl, m, seq);
 }
 
 hipError_t launch_query_bfs(const BfsArgs &a, uint32_t slots, Mirror *m, uint32_t seq,
