@@ -1581,16 +1581,6 @@ __device__ __forceinline__ bool apply_half(const PropArgs &a, uint32_t u, uint32
   return p;
 }
 
-// Both halves of insertion (u,v) by one thread (used by the grid kernel).
-template <int W>
-__device__ __forceinline__ void apply_edge(const PropArgs &a, uint32_t u, uint32_t v,
-                                           uint32_t ring, uint32_t stamp, Ovf *ovf,
-                                           uint64_t ovf_cap, bool active) {
-  bool ovfl = false;
-  apply_half<W>(a, u, v, 0u, ring, stamp, ovf, ovf_cap, active, &ovfl);
-  apply_half<W>(a, u, v, 1u, ring, stamp, ovf, ovf_cap, active, &ovfl);
-}
-
 // A small batch in one workgroup: thread 2i handles the forward half of edge i and thread
 // 2i+1 the backward half. Every id is checked before anything changes (a block-wide vote);
 // then the halves are applied and the propagation rounds run here when something changed.
@@ -1865,18 +1855,24 @@ __global__ __launch_bounds__(256) void k_insert_apply(PropArgs a, const uint32_t
     ctl->heavy[0] = 0;
     ctl->heavy[1] = 0;
   }
-  for (uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x; i0 < count;
-       i0 += (uint64_t)gridDim.x * blockDim.x) {
-    const uint64_t i = i0 + threadIdx.x;
-    const bool act = i < count;
-    apply_edge<W>(a, act ? src[i] : 0u, act ? dst[i] : 0u, ring, stamp, ovf, ovf_cap, act);
+  // one half per thread (thread 2i: edge i forward, 2i + 1: backward), so the two halves'
+  // dependent memory chains run side by side
+  const uint64_t halves = 2 * count;
+  for (uint64_t j0 = (uint64_t)blockIdx.x * blockDim.x; j0 < halves;
+       j0 += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t j = j0 + threadIdx.x;
+    const bool act = j < halves;
+    const uint64_t i = act ? j >> 1 : 0;
+    bool ovfl = false;
+    apply_half<W>(a, act ? src[i] : 0u, act ? dst[i] : 0u, (uint32_t)(j & 1u), ring, stamp, ovf,
+                  ovf_cap, act, &ovfl);
   }
 }
 
 hipError_t launch_insert_apply(const PropArgs &a, const uint32_t *src, const uint32_t *dst,
                                uint64_t count, Ovf *ovf, uint64_t ovf_cap, hipStream_t s) {
-  DBL_LAUNCH_W(a.L.words, k_insert_apply, dim3(grid_for(count, 256, 4096)), dim3(256), s, a, src,
-               dst, count, ovf, ovf_cap);
+  DBL_LAUNCH_W(a.L.words, k_insert_apply, dim3(grid_for(2 * count, 256, 4096)), dim3(256), s, a,
+               src, dst, count, ovf, ovf_cap);
   return hipGetLastError();
 }
 
