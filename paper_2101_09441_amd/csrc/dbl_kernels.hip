@@ -1876,19 +1876,44 @@ hipError_t launch_insert_apply(const PropArgs &a, const uint32_t *src, const uin
   return hipGetLastError();
 }
 
-// Copy every row of old_g into new_g (same deg array; new offsets and capacities).
+// Copy every row of old_g into new_g (same deg array; new offsets and capacities). A block takes
+// 256 consecutive rows at a time, lays their entries end to end (prefix sum of the degrees in
+// LDS) and copies them one entry per thread, so reads and writes both run along the rows
+// however short or long they are.
 __global__ __launch_bounds__(256) void k_regrow_copy(Csr old_g, Csr new_g, uint32_t n) {
-  const uint32_t lane = __lane_id();
-  const uint32_t waves = gridDim.x * (blockDim.x / 64u);
-  for (uint32_t x = blockIdx.x * (blockDim.x / 64u) + (threadIdx.x >> 6); x < n; x += waves) {
-    const uint32_t d = min(old_g.deg[x], old_g.cap[x]);
-    const u64 so = old_g.off[x], dof = new_g.off[x];
-    for (uint32_t j = lane; j < d; j += 64u) new_g.col[dof + j] = old_g.col[so + j];
+  __shared__ uint32_t s_start[256];
+  __shared__ u64 s_src[256], s_dst[256];
+  __shared__ uint32_t s_wsum[4];
+  const uint32_t t = threadIdx.x;
+  for (uint32_t beg = blockIdx.x * 256u; beg < n; beg += gridDim.x * 256u) {
+    const uint32_t x = beg + t;
+    uint32_t d = 0;
+    if (x < n) {
+      d = min(old_g.deg[x], old_g.cap[x]);
+      s_src[t] = old_g.off[x];
+      s_dst[t] = new_g.off[x];
+    }
+    uint32_t total;
+    const uint32_t ex = block_excl_scan<256>(d, s_wsum, total);
+    s_start[t] = ex;
+    __syncthreads();
+    const uint32_t last = min(256u, n - beg) - 1u;
+    for (uint32_t e = t; e < total; e += 256u) {
+      uint32_t lo = 0, hi = last;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (s_start[mid] <= e) lo = mid; else hi = mid - 1;
+      }
+      const uint32_t k = e - s_start[lo];
+      new_g.col[s_dst[lo] + k] = old_g.col[s_src[lo] + k];
+    }
+    __syncthreads();
   }
 }
 
 hipError_t launch_regrow_copy(Csr old_g, Csr new_g, uint32_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_regrow_copy, dim3(grid_for(n, 4, 8192)), dim3(256), 0, s, old_g, new_g, n);
+  hipLaunchKernelGGL(k_regrow_copy, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, old_g, new_g,
+                     n);
   return hipGetLastError();
 }
 
