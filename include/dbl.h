@@ -94,6 +94,8 @@ typedef struct {
   /* Initial dbl_tuning.pull_threshold, so that the build's own rounds follow it (default 128;
      0 = push only). */
   uint32_t pull_threshold;
+  /* Initial dbl_tuning.pull_all_threshold (default 512; 0 = always test the frontier). */
+  uint32_t pull_all_threshold;
 } dbl_options;
 
 /* Which labels a query may use (the ablations of Table 4). */
@@ -270,6 +272,11 @@ typedef struct {
   uint32_t server_warm;        /* 1 (default): before serving, dbl_insert_edges_each reads the
                                   labels and row descriptors once so that the requests find them
                                   in the memory-side cache; 0: it does not */
+  uint32_t pull_all_threshold; /* a pulled direction whose frontier would push at least
+                                  pull_all_threshold / 1024 of its edges reads the label of every
+                                  neighbour instead of testing which ones are in the frontier (a
+                                  neighbour outside it adds no bit); 0 = always test (default
+                                  512) */
 } dbl_tuning;
 
 dbl_status dbl_get_tuning(const dbl_index *ix, dbl_tuning *out);

@@ -48,6 +48,7 @@ class DblOptions(ctypes.Structure):
         ("leaf_threshold", ctypes.c_uint64),
         ("time_kernels", ctypes.c_char_p),
         ("pull_threshold", ctypes.c_uint32),
+        ("pull_all_threshold", ctypes.c_uint32),
     ]
 
 
@@ -84,6 +85,7 @@ class DblTuning(ctypes.Structure):
         ("server_polls", ctypes.c_uint32),
         ("query_graph", ctypes.c_uint32),
         ("server_warm", ctypes.c_uint32),
+        ("pull_all_threshold", ctypes.c_uint32),
     ]
 
 
@@ -273,7 +275,8 @@ class Index:
               slack_fraction: float = 0.25, slack_min: int = 4, bfs_slots: int = 0,
               bfs_queue_cap: int = 0, edges_unique: bool = False, landmark_rank: int = 0,
               leaf_threshold: int = 0, time_kernels: Optional[str] = None,
-              pull_threshold: Optional[int] = None, stream=None) -> "Index":
+              pull_threshold: Optional[int] = None, pull_all_threshold: Optional[int] = None,
+              stream=None) -> "Index":
         lib = load_library()
         src, dst = _ids(src, "src"), _ids(dst, "dst")
         if src.numel() != dst.numel():
@@ -308,6 +311,8 @@ class Index:
         opt.leaf_threshold = leaf_threshold
         if pull_threshold is not None:
             opt.pull_threshold = pull_threshold
+        if pull_all_threshold is not None:
+            opt.pull_all_threshold = pull_all_threshold
         if time_kernels:
             tk = time_kernels.encode()
             keep.append(tk)
@@ -454,7 +459,7 @@ class Index:
     def set_tuning(self, **kw) -> None:
         """Change tuning fields (small_batch, local_max_frontier, local_max_edges, round_grid,
         bfs_slots, insert_server, server_idle_us, pull_threshold, server_polls, query_graph,
-        server_warm); results never change."""
+        server_warm, pull_all_threshold); results never change."""
         cur = self.tuning()
         bad = set(kw) - set(cur)
         if bad:

@@ -90,6 +90,7 @@ struct dbl_index {
   uint32_t round_grid = dbl::kRoundGridMax;
   uint32_t insert_server = 1;  // dbl_insert_edges_each through the request server
   uint32_t pull_threshold = 128;  // pull a direction when its push edges >= this/1024 of its edges
+  uint32_t pull_all_threshold = 512;  // ... and skip the frontier test above this/1024
   uint32_t query_graph = 0;       // query batches as one graph launch
   uint32_t server_warm = 1;       // read the labels and row descriptors before serving
   // query contexts: the default one and those created by callers (guarded by ctx_mu)
@@ -492,7 +493,7 @@ dbl_status grid_propagate(dbl_index *ix, hipStream_t s, uint32_t group, uint64_t
       dbl::PropArgs a = prop_args(ix);
       CK(dbl::launch_frontier_scan(a, cur, stamp, ix->fbm_words, s));
       CKS(sync_ctl(ix, s));
-      uint32_t pull = 0;
+      uint32_t pull = 0, pull_all = 0;
       // the scan counted every entry of the frontier once; anything else: push them all
       const bool counted = ix->hs.dstat[0] + ix->hs.dstat[1] == fsz;
       for (uint32_t d = 0; d < 2 && counted; d++) {
@@ -501,6 +502,9 @@ dbl_status grid_propagate(dbl_index *ix, hipStream_t s, uint32_t group, uint64_t
           pull |= 1u << d;
           ix->pull_expanded += ix->hs.dstat[d];
           ix->pull_rounds++;
+          if (ix->pull_all_threshold &&
+              ix->hs.dstat[2 + d] * 1024 >= (u64)ix->pull_all_threshold * edges)
+            pull_all |= 1u << d;
         }
       }
       const uint64_t pushed = !counted ? fsz
@@ -509,7 +513,7 @@ dbl_status grid_propagate(dbl_index *ix, hipStream_t s, uint32_t group, uint64_t
         Timed tm(ix, kTRound, s);
         if (pull) {
           const uint64_t rows = (uint64_t)ix->n * (uint32_t)__builtin_popcount(pull);
-          CK(dbl::launch_pull(a, ix->n, pull, cur, stamp,
+          CK(dbl::launch_pull(a, ix->n, pull, pull_all, cur, stamp,
                               (uint32_t)std::min<uint64_t>(gmax, (rows + 255) / 256), s));
         }
         if (pushed) CK(dbl::launch_round(a, cur, stamp, grid, s, pull, false));
@@ -1162,6 +1166,7 @@ void dbl_default_options(dbl_options *opt) {
   opt->slack_fraction = 0.25f;
   opt->slack_min = 4;
   opt->pull_threshold = 128;
+  opt->pull_all_threshold = 512;
 }
 
 const char *dbl_status_str(dbl_status s) {
@@ -1188,7 +1193,7 @@ dbl_status dbl_build(uint32_t n, uint64_t m, const uint32_t *d_src, const uint32
     return DBL_ERR_INVALID_ARG;
   if (!(o.slack_fraction >= 0.0f) || o.slack_fraction > 16.0f) return DBL_ERR_INVALID_ARG;
   if (o.landmark_rank > 3) return DBL_ERR_INVALID_ARG;
-  if (o.pull_threshold > 1u << 20) return DBL_ERR_INVALID_ARG;
+  if (o.pull_threshold > 1u << 20 || o.pull_all_threshold > 1u << 20) return DBL_ERR_INVALID_ARG;
   const uint32_t k = std::min<uint32_t>(o.num_landmarks, n);
   if (o.landmarks) {
     std::vector<uint32_t> seen(o.landmarks, o.landmarks + k);
@@ -1219,6 +1224,7 @@ dbl_status dbl_build(uint32_t n, uint64_t m, const uint32_t *d_src, const uint32
   ix->slack_min = o.slack_min;
   ix->slots_opt = o.bfs_slots;
   ix->pull_threshold = o.pull_threshold;
+  ix->pull_all_threshold = o.pull_all_threshold;
   ix->qcap_opt = o.bfs_queue_cap;
   hipStream_t s = (hipStream_t)stream;
   if (o.time_kernels) {
@@ -1577,6 +1583,7 @@ dbl_status dbl_get_tuning(const dbl_index *ix, dbl_tuning *out) {
   out->insert_server = ix->insert_server;
   out->server_idle_us = ix->server_idle_us;
   out->pull_threshold = ix->pull_threshold;
+  out->pull_all_threshold = ix->pull_all_threshold;
   out->server_polls = ix->server_polls;
   out->query_graph = ix->query_graph;
   out->server_warm = ix->server_warm;
@@ -1589,6 +1596,7 @@ dbl_status dbl_set_tuning(dbl_index *ix, const dbl_tuning *t) {
   if (t->small_batch > dbl::kSmallBatchMax || t->round_grid == 0 ||
       t->round_grid > dbl::kRoundGridMax || t->bfs_slots > (1u << 16) || t->insert_server > 1 ||
       t->server_idle_us > 10000000 || t->pull_threshold > 1u << 20 ||
+      t->pull_all_threshold > 1u << 20 ||
       (t->server_polls != 1 && t->server_polls != 4) || t->query_graph > 1 ||
       t->server_warm > 1)
     return DBL_ERR_INVALID_ARG;
@@ -1600,6 +1608,7 @@ dbl_status dbl_set_tuning(dbl_index *ix, const dbl_tuning *t) {
   ix->insert_server = t->insert_server;
   ix->server_idle_us = t->server_idle_us;
   ix->pull_threshold = t->pull_threshold;
+  ix->pull_all_threshold = t->pull_all_threshold;
   ix->server_polls = t->server_polls;
   ix->query_graph = t->query_graph;
   ix->server_warm = t->server_warm;

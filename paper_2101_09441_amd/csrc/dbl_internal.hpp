@@ -211,11 +211,13 @@ hipError_t launch_round(const PropArgs &a, uint32_t ring, uint32_t stamp, uint32
 // per-direction counters, mark the frontier, count entries and push edges per direction and
 // advance ctl->cur / stamp. pull: for the directions in dmask, every vertex ORs in the labels
 // of its frontier neighbours (Pre for forward, Suc for backward) and joins the next frontier
-// if it grew.
+// if it grew; for the directions in allmask it ORs in every neighbour's label without the
+// frontier test (a neighbour outside the frontier has no bit its out-neighbours lack), except
+// on rows long enough for k_pull_heavy.
 hipError_t launch_frontier_scan(const PropArgs &a, uint32_t ring, uint32_t stamp,
                                 uint64_t fbm_words, hipStream_t s);
-hipError_t launch_pull(const PropArgs &a, uint32_t n, uint32_t dmask, uint32_t ring,
-                       uint32_t stamp, uint32_t grid, hipStream_t s);
+hipError_t launch_pull(const PropArgs &a, uint32_t n, uint32_t dmask, uint32_t allmask,
+                       uint32_t ring, uint32_t stamp, uint32_t grid, hipStream_t s);
 // single-workgroup rounds starting from ctl->cur / ctl->stamp; publishes the status to m (if
 // not null) with sequence number seq when done
 hipError_t launch_local_rounds(const PropArgs &a, Mirror *m, uint32_t seq, hipStream_t s);

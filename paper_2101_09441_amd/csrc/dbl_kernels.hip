@@ -1269,12 +1269,17 @@ __device__ __forceinline__ void acc_or(u64 (*s_acc)[2 * W], uint32_t row, bool a
 }
 
 // Pull rows: 256 rows per tile, the rows' edges laid end to end and taken one per thread (as
-// in expand_tile). Rows longer than kHeavyDeg go to k_pull_heavy in chunks.
+// in expand_tile). Rows longer than kHeavyDeg go to k_pull_heavy in chunks. For a direction in
+// allmask (a frontier that holds most of the direction's edges) every neighbour's label is
+// read without the frontier-bitmap test: a neighbour outside the frontier adds nothing, and at
+// 2^25 vertices the bitmap lookups and the label reads evict each other from L2 (measured: the
+// first pull of the build takes 39 ms with the test, 27 ms without, 12 ms with either the
+// label reads or the bitmap misses alone).
 constexpr uint32_t kPullUnroll = 4, kPullStage = 2048;
 
 template <int W>
 __global__ __launch_bounds__(256) void k_pull(PropArgs a, uint32_t n, uint32_t dmask,
-                                              uint32_t nring, uint32_t nstamp) {
+                                              uint32_t allmask, uint32_t nring, uint32_t nstamp) {
   __shared__ uint32_t s_start[256];
   __shared__ u64 s_off[256];
   __shared__ uint32_t s_row[256];
@@ -1351,7 +1356,8 @@ __global__ __launch_bounds__(256) void k_pull(PropArgs a, uint32_t n, uint32_t d
         }
       }
 #pragma unroll
-      for (uint32_t j = 0; j < U; j++) hit[j] = eact[j] && in_frontier(a.fbm, a.fbm_wpd, p[j], rd[j]);
+      for (uint32_t j = 0; j < U; j++)
+        hit[j] = eact[j] && (((allmask >> rd[j]) & 1u) || in_frontier(a.fbm, a.fbm_wpd, p[j], rd[j]));
 #pragma unroll
       for (uint32_t j = 0; j < U; j++) {
         lv[j] = {};
@@ -1445,12 +1451,14 @@ __global__ __launch_bounds__(256) void k_pull_heavy(PropArgs a, uint32_t nring,
   if (threadIdx.x == 0 && relaxed) a.pcnt[2 * (kRoundGridMax + blockIdx.x) + 1] += relaxed;
 }
 
-hipError_t launch_pull(const PropArgs &a, uint32_t n, uint32_t dmask, uint32_t ring,
-                       uint32_t stamp, uint32_t grid, hipStream_t s) {
+hipError_t launch_pull(const PropArgs &a, uint32_t n, uint32_t dmask, uint32_t allmask,
+                       uint32_t ring, uint32_t stamp, uint32_t grid, hipStream_t s) {
   if (!dmask) return hipSuccess;
   if (grid > kRoundGridMax) grid = kRoundGridMax;
   const uint32_t nring = ring == 2u ? 0u : ring + 1u;
-  DBL_LAUNCH_W(a.L.words, k_pull, dim3(grid), dim3(256), s, a, n, dmask, nring, stamp + 1u);
+  allmask &= dmask;
+  DBL_LAUNCH_W(a.L.words, k_pull, dim3(grid), dim3(256), s, a, n, dmask, allmask, nring,
+               stamp + 1u);
   DBL_LAUNCH_W(a.L.words, k_pull_heavy, dim3(kHeavyGrid), dim3(256), s, a, nring, stamp + 1u);
   return hipGetLastError();
 }

@@ -154,15 +154,17 @@ def test_memory_cache_reuse_and_release(tiny):
 
 # ------------------------------------------------------------------ push and pull rounds
 
-@pytest.mark.parametrize("pull", [0, 1, 1 << 20])
+@pytest.mark.parametrize("pull,pull_all", [(0, 0), (1, 0), (1, 1), (1 << 20, 0)])
 @pytest.mark.parametrize("name,gr", FAMILIES, ids=[f[0] for f in FAMILIES])
-def test_pull_rounds_families(name, gr, pull):
-    """Build rounds forced to push only (0), to pull any direction with frontier edges (1), or
-    never to pull (2^20): labels and answers equal the oracle's."""
+def test_pull_rounds_families(name, gr, pull, pull_all):
+    """Build rounds forced to push only (0), to pull any direction with frontier edges (1) with
+    or without the frontier test (pull_all 0 / 1), or never to pull (2^20): labels and answers
+    equal the oracle's."""
     n, src, dst = gr
-    g = gpu_index(n, src, dst, num_landmarks=6, bl_bits=8, pull_threshold=pull)
+    g = gpu_index(n, src, dst, num_landmarks=6, bl_bits=8, pull_threshold=pull,
+                  pull_all_threshold=pull_all)
     o = oracle.OracleIndex(n, src, dst).build(k=6, kp=8)
-    assert_labels_equal(g, o, f"{name} pull {pull}")
+    assert_labels_equal(g, o, f"{name} pull {pull} pull_all {pull_all}")
     u, v = all_pairs(n)
     assert_queries_equal(g, o, u, v)
 
@@ -178,10 +180,11 @@ def test_pull_rounds_rmat_equal_counts(words):
                                   insert_kind="rmat", n_query=50000, query_kind="mixed")
     o = oracle.OracleIndex(w.n, w.src, w.dst).build(k=k, kp=kp, threads=8)
     stats = {}
-    for pull in (0, 1, 128):
-        g = gpu_index(w.n, w.src, w.dst, num_landmarks=k, bl_bits=kp, pull_threshold=pull)
+    for pull, pull_all in ((0, 0), (1, 0), (128, 512), (1, 1)):
+        g = gpu_index(w.n, w.src, w.dst, num_landmarks=k, bl_bits=kp, pull_threshold=pull,
+                      pull_all_threshold=pull_all)
         assert g.label_words() == words
-        assert_labels_equal(g, o, f"pull {pull}")
+        assert_labels_equal(g, o, f"pull {pull} pull_all {pull_all}")
         stats[pull] = g.stats()
         g.close()
     assert stats[0]["pull_rounds"] == 0
@@ -195,12 +198,14 @@ def test_pull_rounds_rmat_equal_counts(words):
     assert_queries_equal(g, o, w.q_u, w.q_v)
 
 
-def test_pull_rounds_in_insertion_batches():
+@pytest.mark.parametrize("pull_all", [0, 1])
+def test_pull_rounds_in_insertion_batches(pull_all):
     """Insertion batches on a 2^12-vertex graph with the single-workgroup bounds tiny, so the
-    batches propagate in grid rounds, and the threshold at its minimum, so those rounds pull."""
+    batches propagate in grid rounds, and the threshold at its minimum, so those rounds pull
+    (with and without the frontier test)."""
     w = dblgen.make_rmat_workload("pri", 12, 5, draws=8 << 12, n_insert=6000,
                                   insert_kind="uniform", n_query=20000, query_kind="mixed")
-    g = gpu_index(w.n, w.src, w.dst, pull_threshold=1)
+    g = gpu_index(w.n, w.src, w.dst, pull_threshold=1, pull_all_threshold=pull_all)
     g.set_tuning(small_batch=0, local_max_frontier=4, local_max_edges=32)
     o = oracle.OracleIndex(w.n, w.src, w.dst).build(threads=8)
     built = g.stats()["pull_rounds"]
@@ -653,6 +658,8 @@ def test_rmat18_build_insert_query():
 
 @pytest.mark.parametrize("tuning", [
     dict(small_batch=0, local_max_frontier=0, local_max_edges=0, round_grid=1, bfs_slots=4),
+    dict(small_batch=0, local_max_frontier=0, local_max_edges=0, pull_threshold=1,
+         pull_all_threshold=1),
     dict(small_batch=0, local_max_frontier=1 << 20, local_max_edges=1 << 30, round_grid=3),
     dict(small_batch=65536, local_max_frontier=16, local_max_edges=64, round_grid=2048,
          bfs_slots=2048),
