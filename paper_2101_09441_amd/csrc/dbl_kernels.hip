@@ -585,8 +585,10 @@ __global__ __launch_bounds__(kScatNT) void k_bin_scatter(const uint32_t *__restr
     for (uint32_t j = 0; j < kScatPer; j++) {
       const uint64_t e = base + kScatNT * j + t;
       ok[j] = e < hi;
-      item[j] = ok[j] ? ((u64)key[e] << 32) | val[e] : 0ull;
-      ok[j] = ok[j] && keep[e];
+      item[j] = ok[j] ? ((u64)__builtin_nontemporal_load(&key[e]) << 32) |
+                            __builtin_nontemporal_load(&val[e])
+                      : 0ull;
+      ok[j] = ok[j] && __builtin_nontemporal_load(&keep[e]);
     }
 #pragma unroll
     for (uint32_t j = 0; j < kScatPer; j++)
@@ -701,7 +703,7 @@ __global__ __launch_bounds__(kBinNT) void k_bin_fill(const u64 *__restrict__ edg
 #pragma unroll
       for (uint32_t j = 0; j < 4; j++) {
         const u64 e = e0 + kBinNT * j;
-        kv[j] = e < hi ? edges[e] : ~0ull;
+        kv[j] = e < hi ? __builtin_nontemporal_load(&edges[e]) : ~0ull;
       }
 #pragma unroll
       for (uint32_t j = 0; j < 4; j++)
