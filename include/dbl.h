@@ -96,6 +96,11 @@ typedef struct {
   uint32_t pull_threshold;
   /* Initial dbl_tuning.pull_all_threshold (default 512; 0 = always test the frontier). */
   uint32_t pull_all_threshold;
+  /* Row fill of the build's CSRs (layout only; the labels never depend on it): 0 = auto
+     (default; rows are assembled in on-chip memory when a direction's edges are not grouped by
+     source row and the rows being filled at once span more than the last-level cache),
+     1 = always direct, 2 = always assembled when possible. Values above 2 are rejected. */
+  uint32_t row_fill;
 } dbl_options;
 
 /* Which labels a query may use (the ablations of Table 4). */

@@ -49,6 +49,7 @@ class DblOptions(ctypes.Structure):
         ("time_kernels", ctypes.c_char_p),
         ("pull_threshold", ctypes.c_uint32),
         ("pull_all_threshold", ctypes.c_uint32),
+        ("row_fill", ctypes.c_uint32),
     ]
 
 
@@ -276,7 +277,7 @@ class Index:
               bfs_queue_cap: int = 0, edges_unique: bool = False, landmark_rank: int = 0,
               leaf_threshold: int = 0, time_kernels: Optional[str] = None,
               pull_threshold: Optional[int] = None, pull_all_threshold: Optional[int] = None,
-              stream=None) -> "Index":
+              row_fill: int = 0, stream=None) -> "Index":
         lib = load_library()
         src, dst = _ids(src, "src"), _ids(dst, "dst")
         if src.numel() != dst.numel():
@@ -313,6 +314,7 @@ class Index:
             opt.pull_threshold = pull_threshold
         if pull_all_threshold is not None:
             opt.pull_all_threshold = pull_all_threshold
+        opt.row_fill = row_fill
         if time_kernels:
             tk = time_kernels.encode()
             keep.append(tk)

@@ -814,6 +814,21 @@ dbl_status run_queries(dbl_index *ix, dbl_query_ctx *c, uint64_t count, const ui
   return DBL_OK;
 }
 
+// Row fill choice for one direction (dbl_options.row_fill). The direct fill writes each edge
+// straight into its row; its scattered writes combine in cache while the rows of the bins in
+// flight (two fill workgroups per compute unit, 256 units) fit in the 256 MiB last-level cache,
+// or while edges arrive grouped by row (a partition tile then covers a few whole rows). Past
+// that, assembling rows in LDS first costs an extra pass over the edges but writes every column
+// once, in runs.
+// same / sampled: the grouping sample of launch_bin_edges.
+bool use_staged_fill(uint32_t mode, u64 same, u64 sampled, u64 total, uint32_t n) {
+  if (mode != 0) return mode == 2;
+  const u64 nbins = dbl::bin_count(n);
+  const u64 in_flight = std::min<u64>(nbins, 512);
+  const u64 window_bytes = total * sizeof(uint32_t) / nbins * in_flight;
+  return same * 2 < sampled && window_bytes > (256ull << 20);
+}
+
 dbl_status do_build(dbl_index *ix, uint64_t m, const uint32_t *src, const uint32_t *dst,
                     const dbl_options &o, hipStream_t s) {
   const uint32_t n = ix->n;
@@ -879,22 +894,30 @@ dbl_status do_build(dbl_index *ix, uint64_t m, const uint32_t *src, const uint32
     dbl_status st = dalloc(&counts, (uint64_t)nblk * nbins);
     if (st == DBL_OK) st = dalloc(&offs, (uint64_t)nblk * nbins);
     if (st == DBL_OK) st = dalloc(&btmp, dbl::scan_tmp_words(nblk * nbins));
-    if (st == DBL_OK) st = dalloc(&bkept, 1);
+    if (st == DBL_OK) st = dalloc(&bkept, 3);  // kept edges, then the grouping sample
     if (st == DBL_OK) st = dalloc(&edges, m);
+    // staging for the row fill: the dedup table (at least 2m entries) is free by then; without
+    // one, a buffer of its own, and without that the rows fill directly
+    u64 *own_tmp = nullptr;
+    if (st == DBL_OK && !table && m && dalloc(&own_tmp, m) != DBL_OK) own_tmp = nullptr;
+    u64 *const stage_tmp = table ? table : own_tmp;
     for (uint32_t d = 0; d < 2 && st == DBL_OK; d++) {
       Csr &g = d ? ix->r : ix->f;
       uint64_t &total = d ? ix->r_total : ix->f_total;
       hipError_t e = hipSuccess;
-      u64 kept = 0;
+      u64 kept = 0, same = 0, sampled = 0;
       if (m) {
         e = dbl::launch_bin_edges(d ? dst : src, d ? src : dst, keep, m, n, nblk, counts, offs,
-                                  btmp, bkept, edges, s);
-        if (e == hipSuccess)
-          e = hipMemcpyAsync(&kept, bkept, sizeof(u64), hipMemcpyDeviceToHost, s);
+                                  btmp, bkept, bkept + 1, edges, s);
+        u64 kr[3] = {0, 0, 0};
+        if (e == hipSuccess) e = hipMemcpyAsync(kr, bkept, sizeof(kr), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
+        kept = kr[0];
+        same = kr[1];
+        sampled = kr[2];
       }
       if (e == hipSuccess && m)
-        e = dbl::launch_bin_rows(edges, offs, nblk, n, bkept, kept, g.deg, nullptr, s);
+        e = dbl::launch_bin_rows(edges, offs, nblk, n, bkept, kept, g.deg, nullptr, nullptr, s);
       else if (e == hipSuccess)
         e = dbl::launch_fill_u32(g.deg, 0u, n, s);
       if (e == hipSuccess)
@@ -915,7 +938,11 @@ dbl_status do_build(dbl_index *ix, uint64_t m, const uint32_t *src, const uint32
       total = t;
       st = dalloc(&g.col, total);
       if (st != DBL_OK) break;
-      if (m) e = dbl::launch_bin_rows(edges, offs, nblk, n, bkept, kept, g.deg, &g, s);
+      u64 *const fill_tmp =
+          total < (1ull << 32) && use_staged_fill(o.row_fill, same, sampled, total, n)
+              ? stage_tmp
+              : nullptr;
+      if (m) e = dbl::launch_bin_rows(edges, offs, nblk, n, bkept, kept, g.deg, &g, fill_tmp, s);
       if (e == hipSuccess) e = hipStreamSynchronize(s);
       if (e != hipSuccess) st = from_hip(e);
     }
@@ -924,6 +951,7 @@ dbl_status do_build(dbl_index *ix, uint64_t m, const uint32_t *src, const uint32
     dfree(btmp);
     dfree(bkept);
     dfree(edges);
+    if (own_tmp) dfree(own_tmp);
     if (st != DBL_OK) {
       dfree(indeg);
       dfree(outdeg);
@@ -1192,7 +1220,7 @@ dbl_status dbl_build(uint32_t n, uint64_t m, const uint32_t *d_src, const uint32
   if (o.bl_bits == 0 || o.bl_bits > dbl::kMaxLabelBits || (o.bl_bits & (o.bl_bits - 1)))
     return DBL_ERR_INVALID_ARG;
   if (!(o.slack_fraction >= 0.0f) || o.slack_fraction > 16.0f) return DBL_ERR_INVALID_ARG;
-  if (o.landmark_rank > 3) return DBL_ERR_INVALID_ARG;
+  if (o.landmark_rank > 3 || o.row_fill > 2) return DBL_ERR_INVALID_ARG;
   if (o.pull_threshold > 1u << 20 || o.pull_all_threshold > 1u << 20) return DBL_ERR_INVALID_ARG;
   const uint32_t k = std::min<uint32_t>(o.num_landmarks, n);
   if (o.landmarks) {

@@ -145,7 +145,9 @@ uint64_t scan_tmp_words(uint32_t n);
 hipError_t scan_exclusive(const uint32_t *in, unsigned long long *out, uint32_t n, unsigned long long *tmp,
                           unsigned long long *total, hipStream_t s);
 // Binned ingest of one direction: partition the kept (key, val) edges by key range into
-// out[cnt] = key << 32 | val (*kept receives cnt); nblk chunks (<= kBinBlocks);
+// out[cnt] = key << 32 | val (*kept receives cnt; runs[1] counts a sample of the kept edges and
+// runs[0] those of the sample whose key repeats the key of the input edge before them); nblk
+// chunks (<= kBinBlocks);
 // counts/offs: nblk * bin_count(n) entries; scan_tmp: scan_tmp_words(nblk * bin_count(n)).
 constexpr uint32_t kBinBlocks = 2048;
 uint32_t bin_shift(uint32_t n);
@@ -153,13 +155,16 @@ inline uint32_t bin_count(uint32_t n) { return ((n - 1) >> bin_shift(n)) + 1; }
 hipError_t launch_bin_edges(const uint32_t *key, const uint32_t *val, const uint8_t *keep,
                             uint64_t m, uint32_t n, uint32_t nblk, uint32_t *counts,
                             unsigned long long *offs, unsigned long long *scan_tmp,
-                            unsigned long long *kept, unsigned long long *out, hipStream_t s);
+                            unsigned long long *kept, unsigned long long *runs,
+                            unsigned long long *out, hipStream_t s);
 // From partitioned edges (offs, nblk, kept as left by launch_bin_edges; kept_host = *kept):
 // g == nullptr: deg[v] = degree of v; else fill g's rows (g.off set; g.deg is the degree and
-// stays so).
+// stays so). fill_tmp (optional; kept_host entries, allowed only while the CSR holds fewer than
+// 2^32 column slots) lets the fill assemble runs of rows in LDS.
 hipError_t launch_bin_rows(const unsigned long long *edges, const unsigned long long *offs,
                            uint32_t nblk, uint32_t n, const unsigned long long *kept,
-                           uint64_t kept_host, uint32_t *deg, const Csr *g, hipStream_t s);
+                           uint64_t kept_host, uint32_t *deg, const Csr *g,
+                           unsigned long long *fill_tmp, hipStream_t s);
 // deg[key] += 1 per partitioned edge; rows filled from partitioned edges (g.deg zero on entry)
 hipError_t launch_deg_binned(const unsigned long long *edges, uint64_t cnt, uint32_t *deg,
                              hipStream_t s);

@@ -522,16 +522,24 @@ uint32_t bin_shift(uint32_t n) {
 // one exclusive scan over the array gives every (bin, block) its output offset)
 // Every thread walks its part of the chunk kBinUnroll edges at a time: all their loads are
 // issued before the first LDS update, so a wave keeps that many reads in flight.
+// runs[0..1] (zero on entry) sample how far the input is grouped by key: over the first edge
+// of every thread's group of kBinUnroll (lanes 1..63), runs[1] counts the kept ones and runs[0]
+// those whose key equals the key of the input edge before them.
 constexpr uint32_t kBinUnroll = 8;
 
 __global__ __launch_bounds__(256) void k_bin_hist(const uint32_t *__restrict__ key,
                                                   const uint8_t *__restrict__ keep, uint64_t m,
                                                   uint32_t shift, uint32_t nbins, uint64_t chunk,
-                                                  uint32_t *__restrict__ counts) {
+                                                  uint32_t *__restrict__ counts,
+                                                  u64 *__restrict__ runs) {
   __shared__ uint32_t hist[kMaxBins];
+  __shared__ uint32_t s_runs[2];
   for (uint32_t i = threadIdx.x; i < nbins; i += 256u) hist[i] = 0;
+  if (threadIdx.x < 2) s_runs[threadIdx.x] = 0;
   __syncthreads();
   const uint64_t lo = blockIdx.x * chunk, hi = min(m, lo + chunk);
+  const uint32_t lane = threadIdx.x & 63u;
+  uint32_t same = 0, sampled = 0;
   for (uint64_t e0 = lo + threadIdx.x; e0 < hi; e0 += 256u * kBinUnroll) {
     uint32_t k[kBinUnroll];
     bool ok[kBinUnroll];
@@ -542,11 +550,28 @@ __global__ __launch_bounds__(256) void k_bin_hist(const uint32_t *__restrict__ k
       k[j] = ok[j] ? key[e] : 0u;
       ok[j] = ok[j] && keep[e];
     }
+    {
+      const uint32_t prev = __shfl_up(k[0], 1);  // the input edge before, for lanes 1..63
+      if (lane && ok[0]) {
+        sampled++;
+        same += prev == k[0];
+      }
+    }
 #pragma unroll
     for (uint32_t j = 0; j < kBinUnroll; j++)
       if (ok[j]) atomicAdd(&hist[k[j] >> shift], 1u);
   }
+  for (uint32_t o = 32; o; o >>= 1) {
+    same += __shfl_xor(same, o);
+    sampled += __shfl_xor(sampled, o);
+  }
+  if (lane == 0 && sampled) {
+    atomicAdd(&s_runs[0], same);
+    atomicAdd(&s_runs[1], sampled);
+  }
   __syncthreads();
+  if (threadIdx.x < 2 && s_runs[threadIdx.x])
+    atomicAdd(&runs[threadIdx.x], (u64)s_runs[threadIdx.x]);
   for (uint32_t i = threadIdx.x; i < nbins; i += 256u)
     counts[(uint64_t)i * gridDim.x + blockIdx.x] = hist[i];
 }
@@ -633,13 +658,15 @@ __global__ __launch_bounds__(kScatNT) void k_bin_scatter(const uint32_t *__restr
 
 hipError_t launch_bin_edges(const uint32_t *key, const uint32_t *val, const uint8_t *keep,
                             uint64_t m, uint32_t n, uint32_t nblk, uint32_t *counts, u64 *offs,
-                            u64 *scan_tmp, u64 *kept, u64 *out, hipStream_t s) {
+                            u64 *scan_tmp, u64 *kept, u64 *runs, u64 *out, hipStream_t s) {
   if (m == 0 || nblk == 0) return hipErrorInvalidValue;
   const uint32_t shift = bin_shift(n), nbins = ((n - 1) >> shift) + 1;
   const uint64_t chunk = (m + nblk - 1) / nblk;
+  hipError_t e = launch_fill_u64(runs, 0ull, 2, s);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_bin_hist, dim3(nblk), dim3(256), 0, s, key, keep, m, shift, nbins, chunk,
-                     counts);
-  hipError_t e = scan_exclusive(counts, offs, nbins * nblk, scan_tmp, kept, s);
+                     counts, runs);
+  e = scan_exclusive(counts, offs, nbins * nblk, scan_tmp, kept, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_bin_scatter, dim3(nblk), dim3(kScatNT), 0, s, key, val, keep, m, shift,
                      nbins, chunk, offs, out);
@@ -720,17 +747,125 @@ __global__ __launch_bounds__(kBinNT) void k_bin_fill(const u64 *__restrict__ edg
   }
 }
 
+// Row fill through LDS, for bins of at most kFillVerts vertices. A bin's rows are cut into
+// sub-bins by where each row starts (a new sub-bin every kFillSub column slots); the bin's edges
+// are first regrouped by sub-bin into tmp (same index range as the bin), then each sub-bin's rows
+// are assembled in LDS and written out as one contiguous run of columns, slack included (slack
+// slots are never read). Row cursors start at the row's offset from the bin's first column, so
+// the fill itself reads no offsets. A sub-bin whose rows span more than kFillStage slots (a long
+// row) is filled directly. Whatever order the bin's edges arrive in, the columns reach memory in
+// whole runs.
+constexpr uint32_t kFillVerts = 8192, kFillSub = 4096, kFillStage = 8192, kFillMaxSub = 256;
+
+__global__ __launch_bounds__(kBinNT) void k_bin_fill_staged(const u64 *__restrict__ edges,
+                                                            const u64 *__restrict__ offs,
+                                                            uint32_t nblk, uint32_t nbins,
+                                                            uint32_t shift,
+                                                            const u64 *__restrict__ kept,
+                                                            uint32_t n, Csr g,
+                                                            u64 *__restrict__ tmp) {
+  __shared__ uint32_t cur[kFillVerts];
+  __shared__ uint32_t stage[kFillStage];
+  __shared__ uint8_t sbid[kFillVerts];
+  __shared__ uint32_t sbcnt[kFillMaxSub], sbstart[kFillMaxSub], sbcur[kFillMaxSub];
+  __shared__ uint32_t sbfirst[kFillMaxSub + 1];
+  const uint32_t t = threadIdx.x;
+  for (uint32_t bin = blockIdx.x; bin < nbins; bin += gridDim.x) {
+    const uint32_t first = bin << shift, nv = min(1u << shift, n - first);
+    const u64 base = g.off[first];
+    const u64 span = g.off[first + nv - 1] + g.cap[first + nv - 1] - base;
+    const uint32_t nsb =
+        (uint32_t)max<u64>(1, min<u64>(kFillMaxSub, (span + kFillSub - 1) / kFillSub));
+    for (uint32_t i = t; i <= kFillMaxSub; i += kBinNT) {
+      if (i < kFillMaxSub) {
+        sbcnt[i] = 0;
+        sbcur[i] = 0;
+      }
+      sbfirst[i] = nv;
+    }
+    __syncthreads();
+    // per row: cursor, sub-bin; per sub-bin: edge count and first row
+    for (uint32_t v = t; v < nv; v += kBinNT) {
+      const uint32_t rel = (uint32_t)(g.off[first + v] - base);
+      cur[v] = rel;
+      const uint32_t sb = min(nsb - 1u, rel / kFillSub);
+      sbid[v] = (uint8_t)sb;
+      const uint32_t d = g.deg[first + v];
+      if (d) atomicAdd(&sbcnt[sb], d);
+      atomicMin(&sbfirst[sb], v);
+    }
+    __syncthreads();
+    if (t == 0) {
+      // exclusive scan of the counts; a sub-bin where no row starts takes the next one's first
+      // row, so every sub-bin's rows are [sbfirst[sb], sbfirst[sb + 1])
+      uint32_t acc = 0;
+      for (uint32_t sb = 0; sb < nsb; sb++) {
+        sbstart[sb] = acc;
+        acc += sbcnt[sb];
+      }
+      for (uint32_t sb = nsb; sb-- > 1;)
+        sbfirst[sb - 1] = min(sbfirst[sb - 1], sbfirst[sb]);
+    }
+    __syncthreads();
+    u64 lo, hi;
+    bin_range(offs, nblk, nbins, *kept, bin, lo, hi);
+    for (u64 e0 = lo + t; e0 < hi; e0 += kBinNT * 4u) {
+      u64 kv[4];
+#pragma unroll
+      for (uint32_t j = 0; j < 4; j++) {
+        const u64 e = e0 + kBinNT * j;
+        kv[j] = e < hi ? __builtin_nontemporal_load(&edges[e]) : ~0ull;
+      }
+#pragma unroll
+      for (uint32_t j = 0; j < 4; j++)
+        if (kv[j] != ~0ull) {
+          const uint32_t sb = sbid[(uint32_t)(kv[j] >> 32) - first];
+          tmp[lo + sbstart[sb] + atomicAdd(&sbcur[sb], 1u)] = kv[j];
+        }
+    }
+    __syncthreads();
+    for (uint32_t sb = 0; sb < nsb; sb++) {
+      const uint32_t v0 = sbfirst[sb], v1 = sbfirst[sb + 1];
+      if (v0 >= v1) continue;  // no row starts here (same for every thread)
+      const uint32_t r0 = cur[v0];
+      const uint32_t r1 = v1 < nv ? cur[v1] : (uint32_t)span;
+      const u64 e_lo = lo + sbstart[sb], e_hi = e_lo + sbcnt[sb];
+      __syncthreads();  // every thread has read cur[v0] before the fill moves it
+      if (r1 - r0 <= kFillStage) {
+        for (uint32_t i = t; i < r1 - r0; i += kBinNT) stage[i] = 0;
+        __syncthreads();
+        for (u64 e = e_lo + t; e < e_hi; e += kBinNT) {
+          const u64 kv = tmp[e];
+          stage[atomicAdd(&cur[(uint32_t)(kv >> 32) - first], 1u) - r0] = (uint32_t)kv;
+        }
+        __syncthreads();
+        for (uint32_t i = t; i < r1 - r0; i += kBinNT) g.col[base + r0 + i] = stage[i];
+      } else {
+        for (u64 e = e_lo + t; e < e_hi; e += kBinNT) {
+          const u64 kv = tmp[e];
+          g.col[base + atomicAdd(&cur[(uint32_t)(kv >> 32) - first], 1u)] = (uint32_t)kv;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
 // Degrees (deg[key] = edges of key) and row fill of partitioned edges. Rows are filled from
-// position 0; deg is left as the degree.
+// position 0; deg is left as the degree. With fill_tmp (kept_host entries, and every row of the
+// CSR within 2^32 column slots of its bin's first row) the fill goes through LDS.
 hipError_t launch_bin_rows(const u64 *edges, const u64 *offs, uint32_t nblk, uint32_t n,
                            const u64 *kept, uint64_t kept_host, uint32_t *deg, const Csr *g,
-                           hipStream_t s) {
+                           u64 *fill_tmp, hipStream_t s) {
   const uint32_t shift = bin_shift(n), nbins = ((n - 1) >> shift) + 1;
   if ((1u << shift) <= kBinVerts) {
     const uint32_t grid = min(nbins, 8192u);
     if (!g) {
       hipLaunchKernelGGL(k_bin_deg, dim3(grid), dim3(kBinNT), 0, s, edges, offs, nblk, nbins,
                          shift, kept, n, deg);
+    } else if (fill_tmp && (1u << shift) <= kFillVerts) {
+      hipLaunchKernelGGL(k_bin_fill_staged, dim3(grid), dim3(kBinNT), 0, s, edges, offs, nblk,
+                         nbins, shift, kept, n, *g, fill_tmp);
     } else {
       hipLaunchKernelGGL(k_bin_fill, dim3(grid), dim3(kBinNT), 0, s, edges, offs, nblk, nbins,
                          shift, kept, n, *g);

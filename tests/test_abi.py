@@ -42,5 +42,10 @@ def test_host_only_entry_points():
     bad.bl_bits = 48
     assert lib.dbl_build(4, 0, None, None, ctypes.byref(bad), None,
                          ctypes.byref(out)) == dbl.DBL_ERR_INVALID_ARG
+    assert opt.row_fill == 0
+    lib.dbl_default_options(ctypes.byref(bad))
+    bad.row_fill = 3
+    assert lib.dbl_build(4, 0, None, None, ctypes.byref(bad), None,
+                         ctypes.byref(out)) == dbl.DBL_ERR_INVALID_ARG
     assert lib.dbl_insert_edges(None, 1, None, None, None) == dbl.DBL_ERR_INVALID_ARG
     assert lib.dbl_query_batch(None, 1, None, None, None, None) == dbl.DBL_ERR_INVALID_ARG

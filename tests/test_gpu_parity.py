@@ -125,6 +125,58 @@ def test_families_insert_batches(name, gr):
     assert_queries_equal(g, o, u, v)
 
 
+@pytest.mark.parametrize("name,gr", FAMILIES, ids=[f[0] for f in FAMILIES])
+@pytest.mark.parametrize("row_fill", [1, 2])
+@pytest.mark.parametrize("unique", [False, True])
+def test_row_fill_modes(name, gr, row_fill, unique):
+    """Direct and LDS-assembled row fills (staging in the dedup table or in a buffer of its
+    own): labels and all-pairs answers equal the oracle's."""
+    n, src, dst = gr
+    if unique:
+        pairs = np.unique(np.stack([src, dst], 1), axis=0)
+        src, dst = pairs[:, 0].copy(), pairs[:, 1].copy()
+    g = gpu_index(n, src, dst, num_landmarks=64, bl_bits=64, row_fill=row_fill,
+                  edges_unique=unique)
+    o = oracle.OracleIndex(n, src, dst).build(k=64, kp=64)
+    assert_labels_equal(g, o, f"{name} fill {row_fill}")
+    u, v = all_pairs(n)
+    assert_queries_equal(g, o, u, v)
+
+
+@pytest.mark.parametrize("slack_min", [0, 40, 3000])
+def test_row_fill_assembled_sub_bins(slack_min):
+    """Assembled fill over bins of several sub-bins: many short rows, rows wider than the LDS
+    stage (filled directly) and sub-bins where no row starts; labels and queries as the oracle."""
+    rng = np.random.default_rng(17 + slack_min)
+    n = 20000
+    src = rng.integers(0, n, 120000).astype(np.uint32)
+    dst = rng.integers(0, n, 120000).astype(np.uint32)
+    # a few hubs with rows longer than the stage, in and out
+    hub_dst = rng.integers(0, n, 30000).astype(np.uint32)
+    src = np.concatenate([src, np.full(30000, 77, np.uint32), hub_dst])
+    dst = np.concatenate([dst, hub_dst, np.full(30000, 12345, np.uint32)])
+    perm = rng.permutation(src.size)
+    src, dst = src[perm], dst[perm]
+    outs = {}
+    for row_fill in (1, 2):
+        g = gpu_index(n, src, dst, num_landmarks=16, bl_bits=16, row_fill=row_fill,
+                      slack_min=slack_min)
+        outs[row_fill] = g
+    o = oracle.OracleIndex(n, src, dst).build(k=16, kp=16, threads=8)
+    u = rng.integers(0, n, 20000).astype(np.uint32)
+    v = rng.integers(0, n, 20000).astype(np.uint32)
+    for row_fill, g in outs.items():
+        assert_labels_equal(g, o, f"fill {row_fill} slack {slack_min}")
+        assert_queries_equal(g, o, u, v)
+    # rows keep their slack: insertions after the build land in place and stay exact
+    iu = rng.integers(0, n, 200).astype(np.uint32)
+    iv = rng.integers(0, n, 200).astype(np.uint32)
+    outs[2].insert_edges(dev(iu), dev(iv))
+    o.insert(iu, iv)
+    assert_labels_equal(outs[2], o, f"fill 2 slack {slack_min} after inserts")
+    assert_queries_equal(outs[2], o, u, v)
+
+
 # ------------------------------------------------------------------ memory cache
 
 def test_memory_cache_reuse_and_release(tiny):
@@ -626,6 +678,9 @@ def test_star_hub_heavy_rows():
     g = gpu_index(n, src, dst, num_landmarks=8, bl_bits=64)
     o = oracle.OracleIndex(n, src, dst).build(k=8, kp=64, threads=8)
     assert_labels_equal(g, o, "star")
+    # the hub's rows are wider than the LDS stage of the assembled fill
+    assert_labels_equal(gpu_index(n, src, dst, num_landmarks=8, bl_bits=64, row_fill=2), o,
+                        "star, assembled fill")
     rng = np.random.default_rng(9)
     u = rng.integers(0, n, 5000).astype(np.uint32)
     v = rng.integers(0, n, 5000).astype(np.uint32)
