@@ -55,6 +55,40 @@ __device__ __forceinline__ void wave_push(uint32_t *q, uint32_t *cnt, bool pred,
   if (pred) q[base + lanemask_lt_popc(mask)] = val;
 }
 
+// Neighbouring active lanes with the same target form a run; an active lane receives the first
+// and last lane of its run. Counting into LDS with one atomic per run (by its last lane) keeps
+// input sorted by key, where the lanes of a wave share a few counters, from serialising on
+// them.
+__device__ __forceinline__ void lane_run(uint32_t tgt, bool active, uint32_t &first,
+                                         uint32_t &last) {
+  const uint32_t lane = __lane_id();
+  const uint32_t up = __shfl_up(tgt, 1, 64), dn = __shfl_down(tgt, 1, 64);
+  const u64 act = __ballot(active);
+  const bool head = active && (lane == 0 || !((act >> (lane - 1)) & 1ull) || up != tgt);
+  const bool tail = active && (lane == 63 || !((act >> (lane + 1)) & 1ull) || dn != tgt);
+  const u64 heads = __ballot(head) & (~0ull >> (63 - lane));
+  const u64 tails = __ballot(tail) & (~0ull << lane);
+  first = heads ? 63u - (uint32_t)__builtin_clzll(heads) : lane;
+  last = tails ? (uint32_t)__builtin_ctzll(tails) : lane;
+}
+
+// ctr[idx] += 1 for every active lane, returning the old value plus the lane's place among the
+// active lanes. When every active lane of the wave targets the same counter (sorted input) one
+// atomic serves them all; otherwise each lane adds its own (the test costs two ballots and a
+// lane read, less than forming runs when targets are scattered).
+__device__ __forceinline__ uint32_t wave_add(uint32_t *ctr, uint32_t idx, bool active) {
+  const u64 act = __ballot(active);
+  if (act == 0) return 0;
+  const uint32_t leader = (uint32_t)__builtin_ctzll(act);
+  const uint32_t lead = __builtin_amdgcn_readlane(idx, leader);
+  if (__ballot(active && idx != lead) == 0) {
+    uint32_t old = 0;
+    if (__lane_id() == leader) old = atomicAdd(&ctr[lead], (uint32_t)__popcll(act));
+    return __builtin_amdgcn_readlane(old, leader) + lanemask_lt_popc(act);
+  }
+  return active ? atomicAdd(&ctr[idx], 1u) : 0u;
+}
+
 // Exclusive scan over a block of NT threads; *total receives the block sum.
 template <int NT>
 __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t *s_wsum,
@@ -558,8 +592,7 @@ __global__ __launch_bounds__(256) void k_bin_hist(const uint32_t *__restrict__ k
       }
     }
 #pragma unroll
-    for (uint32_t j = 0; j < kBinUnroll; j++)
-      if (ok[j]) atomicAdd(&hist[k[j] >> shift], 1u);
+    for (uint32_t j = 0; j < kBinUnroll; j++) (void)wave_add(hist, k[j] >> shift, ok[j]);
   }
   for (uint32_t o = 32; o; o >>= 1) {
     same += __shfl_xor(same, o);
@@ -617,7 +650,7 @@ __global__ __launch_bounds__(kScatNT) void k_bin_scatter(const uint32_t *__restr
     }
 #pragma unroll
     for (uint32_t j = 0; j < kScatPer; j++)
-      rank[j] = ok[j] ? atomicAdd(&s_pos[(uint32_t)(item[j] >> 32) >> shift], 1u) : 0u;
+      rank[j] = wave_add(s_pos, (uint32_t)(item[j] >> 32) >> shift, ok[j]);
     __syncthreads();
     // exclusive scan of the tile's counts over the bins (thread t owns bins [t*kPerT, ...))
     uint32_t c[kPerT], sum = 0;
@@ -703,8 +736,12 @@ __global__ __launch_bounds__(kBinNT) void k_bin_deg(const u64 *__restrict__ edge
         k[j] = e < hi ? (uint32_t)(edges[e] >> 32) : ~0u;
       }
 #pragma unroll
-      for (uint32_t j = 0; j < 4; j++)
-        if (k[j] != ~0u) atomicAdd(&cnt[k[j] - first], 1u);
+      for (uint32_t j = 0; j < 4; j++) {
+        const bool ok = k[j] != ~0u;
+        uint32_t f, l;
+        lane_run(k[j], ok, f, l);
+        if (ok && __lane_id() == l) atomicAdd(&cnt[k[j] - first], l - f + 1u);
+      }
     }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < nv; i += kBinNT) deg[first + i] = cnt[i];
