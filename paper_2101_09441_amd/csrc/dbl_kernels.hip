@@ -614,7 +614,7 @@ __global__ __launch_bounds__(256) void k_bin_hist(const uint32_t *__restrict__ k
 // (rank by LDS atomic, exclusive scan of the tile's bin counts) and writes the tile out in
 // sorted order: consecutive threads write consecutive slots of one bin's run, so the output is
 // written in runs instead of one scattered 8-byte store per edge.
-constexpr uint32_t kScatNT = 512, kScatPer = 16, kScatTile = kScatNT * kScatPer;
+constexpr uint32_t kScatNT = 512, kScatPer = 24, kScatTile = kScatNT * kScatPer;
 
 __global__ __launch_bounds__(kScatNT) void k_bin_scatter(const uint32_t *__restrict__ key,
                                                          const uint32_t *__restrict__ val,
