@@ -788,7 +788,7 @@ __global__ __launch_bounds__(kBinNT) void k_bin_fill(const u64 *__restrict__ edg
 // sub-bins by where each row starts (a new sub-bin every kFillSub column slots); the bin's edges
 // are first regrouped by sub-bin into tmp (same index range as the bin), then each sub-bin's rows
 // are assembled in LDS and written out as one contiguous run of columns, slack included (slack
-// slots are never read). Row cursors start at the row's offset from the bin's first column, so
+// slots are never read, so they carry whatever the stage held). Row cursors start at the row's offset from the bin's first column, so
 // the fill itself reads no offsets. A sub-bin whose rows span more than kFillStage slots (a long
 // row) is filled directly. Whatever order the bin's edges arrive in, the columns reach memory in
 // whole runs.
@@ -806,6 +806,7 @@ __global__ __launch_bounds__(kBinNT) void k_bin_fill_staged(const u64 *__restric
   __shared__ uint8_t sbid[kFillVerts];
   __shared__ uint32_t sbcnt[kFillMaxSub], sbstart[kFillMaxSub], sbcur[kFillMaxSub];
   __shared__ uint32_t sbfirst[kFillMaxSub + 1];
+  __shared__ uint32_t sbrow[kFillMaxSub + 1];  // column (from the bin's first) of sbfirst's row
   const uint32_t t = threadIdx.x;
   for (uint32_t bin = blockIdx.x; bin < nbins; bin += gridDim.x) {
     const uint32_t first = bin << shift, nv = min(1u << shift, n - first);
@@ -842,6 +843,8 @@ __global__ __launch_bounds__(kBinNT) void k_bin_fill_staged(const u64 *__restric
       }
       for (uint32_t sb = nsb; sb-- > 1;)
         sbfirst[sb - 1] = min(sbfirst[sb - 1], sbfirst[sb]);
+      for (uint32_t sb = 0; sb <= nsb; sb++)
+        sbrow[sb] = sbfirst[sb] < nv ? cur[sbfirst[sb]] : (uint32_t)span;
     }
     __syncthreads();
     u64 lo, hi;
@@ -862,18 +865,21 @@ __global__ __launch_bounds__(kBinNT) void k_bin_fill_staged(const u64 *__restric
     }
     __syncthreads();
     for (uint32_t sb = 0; sb < nsb; sb++) {
-      const uint32_t v0 = sbfirst[sb], v1 = sbfirst[sb + 1];
-      if (v0 >= v1) continue;  // no row starts here (same for every thread)
-      const uint32_t r0 = cur[v0];
-      const uint32_t r1 = v1 < nv ? cur[v1] : (uint32_t)span;
+      if (sbfirst[sb] >= sbfirst[sb + 1]) continue;  // no row starts here (same for every thread)
+      const uint32_t r0 = sbrow[sb], r1 = sbrow[sb + 1];
       const u64 e_lo = lo + sbstart[sb], e_hi = e_lo + sbcnt[sb];
-      __syncthreads();  // every thread has read cur[v0] before the fill moves it
       if (r1 - r0 <= kFillStage) {
-        for (uint32_t i = t; i < r1 - r0; i += kBinNT) stage[i] = 0;
-        __syncthreads();
-        for (u64 e = e_lo + t; e < e_hi; e += kBinNT) {
-          const u64 kv = tmp[e];
-          stage[atomicAdd(&cur[(uint32_t)(kv >> 32) - first], 1u) - r0] = (uint32_t)kv;
+        for (u64 e0 = e_lo + t; e0 < e_hi; e0 += kBinNT * 4u) {
+          u64 kv[4];
+#pragma unroll
+          for (uint32_t j = 0; j < 4; j++) {
+            const u64 e = e0 + kBinNT * j;
+            kv[j] = e < e_hi ? tmp[e] : ~0ull;
+          }
+#pragma unroll
+          for (uint32_t j = 0; j < 4; j++)
+            if (kv[j] != ~0ull)
+              stage[atomicAdd(&cur[(uint32_t)(kv[j] >> 32) - first], 1u) - r0] = (uint32_t)kv[j];
         }
         __syncthreads();
         for (uint32_t i = t; i < r1 - r0; i += kBinNT) g.col[base + r0 + i] = stage[i];
@@ -885,6 +891,9 @@ __global__ __launch_bounds__(kBinNT) void k_bin_fill_staged(const u64 *__restric
       }
       __syncthreads();
     }
+    // the sub-bin table is rebuilt for the next bin only once every thread has walked it to the
+    // end (trailing sub-bins where no row starts pass no barrier)
+    __syncthreads();
   }
 }
 

@@ -151,9 +151,10 @@ def test_row_fill_assembled_sub_bins(slack_min):
     n = 20000
     src = rng.integers(0, n, 120000).astype(np.uint32)
     dst = rng.integers(0, n, 120000).astype(np.uint32)
-    # a few hubs with rows longer than the stage, in and out
+    # hubs with rows longer than the stage, in and out; bins hold 8 vertices here, so the out-hub
+    # 79 is the last row of its bin and leaves sub-bins where no row starts at the bin's end
     hub_dst = rng.integers(0, n, 30000).astype(np.uint32)
-    src = np.concatenate([src, np.full(30000, 77, np.uint32), hub_dst])
+    src = np.concatenate([src, np.full(30000, 79, np.uint32), hub_dst])
     dst = np.concatenate([dst, hub_dst, np.full(30000, 12345, np.uint32)])
     perm = rng.permutation(src.size)
     src, dst = src[perm], dst[perm]
