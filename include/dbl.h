@@ -134,9 +134,10 @@ void dbl_default_options(dbl_options *opt);
  *   n: vertex count, 1 <= n < 2^31.  m: edge count (0 allowed).
  *   d_src, d_dst: device arrays [m]. Self-loops are dropped; duplicate edges are dropped.
  *   opt: NULL = defaults.  *out receives the new index (NULL on error).
- * Device memory: besides the index, the build holds scratch of about 16 bytes per edge (plus
- * the de-duplication table, 16-32 bytes per edge, unless edges_unique) until it returns; if
- * the staging buffer of the row fill cannot be had, the rows are filled directly instead.
+ * Device memory: besides the index, the build holds scratch until it returns: 9 bytes per
+ * edge for the partitioned edges and keep flags, the de-duplication table (16-32 bytes per
+ * edge) unless edges_unique, and 8 bytes per edge of row-fill staging that lives in that table
+ * when there is one. If the staging buffer cannot be had, rows are filled directly instead.
  * Errors: INVALID_ARG (bad options or sizes), VERTEX_RANGE (an id >= n), OUT_OF_MEMORY,
  * DEVICE. On error no index is returned and nothing is leaked.
  */
