@@ -2071,6 +2071,8 @@ hipError_t launch_insert_apply(const PropArgs &a, const uint32_t *src, const uin
 // 256 consecutive rows at a time, lays their entries end to end (prefix sum of the degrees in
 // LDS) and copies them one entry per thread, so reads and writes both run along the rows
 // however short or long they are.
+constexpr uint32_t kCopyUnroll = 4;
+
 __global__ __launch_bounds__(256) void k_regrow_copy(Csr old_g, Csr new_g, uint32_t n) {
   __shared__ uint32_t s_start[256];
   __shared__ u64 s_src[256], s_dst[256];
@@ -2089,14 +2091,29 @@ __global__ __launch_bounds__(256) void k_regrow_copy(Csr old_g, Csr new_g, uint3
     s_start[t] = ex;
     __syncthreads();
     const uint32_t last = min(256u, n - beg) - 1u;
-    for (uint32_t e = t; e < total; e += 256u) {
-      uint32_t lo = 0, hi = last;
-      while (lo < hi) {
-        const uint32_t mid = (lo + hi + 1) >> 1;
-        if (s_start[mid] <= e) lo = mid; else hi = mid - 1;
+    // kCopyUnroll entries per thread at a time, all their reads in flight together; a thread's
+    // entries only move forward, so each row search starts from the row found before
+    uint32_t lo = 0;
+    for (uint32_t e0 = t; e0 < total; e0 += 256u * kCopyUnroll) {
+      uint32_t v[kCopyUnroll];
+      u64 to[kCopyUnroll];
+#pragma unroll
+      for (uint32_t j = 0; j < kCopyUnroll; j++) {
+        const uint32_t e = e0 + 256u * j;
+        if (e < total) {
+          uint32_t hi = last;
+          while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) >> 1;
+            if (s_start[mid] <= e) lo = mid; else hi = mid - 1;
+          }
+          const uint32_t k = e - s_start[lo];
+          to[j] = s_dst[lo] + k;
+          v[j] = old_g.col[s_src[lo] + k];
+        }
       }
-      const uint32_t k = e - s_start[lo];
-      new_g.col[s_dst[lo] + k] = old_g.col[s_src[lo] + k];
+#pragma unroll
+      for (uint32_t j = 0; j < kCopyUnroll; j++)
+        if (e0 + 256u * j < total) new_g.col[to[j]] = v[j];
     }
     __syncthreads();
   }
