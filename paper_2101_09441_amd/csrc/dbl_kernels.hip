@@ -793,8 +793,12 @@ __global__ __launch_bounds__(kBinNT) void k_bin_fill(const u64 *__restrict__ edg
 // row) is filled directly. Whatever order the bin's edges arrive in, the columns reach memory in
 // whole runs.
 constexpr uint32_t kFillVerts = 8192, kFillSub = 4096, kFillStage = 8192, kFillMaxSub = 256;
+constexpr uint32_t kFillTile = kBinNT * 4;  // edges regrouped at a time (fills the stage as u64)
+static_assert(kFillTile * sizeof(u64) <= kFillStage * sizeof(uint32_t), "tile exceeds the stage");
+static_assert(kFillTile <= 65536 && kFillMaxSub <= 65536, "packed sub-bin and rank");
 
-__global__ __launch_bounds__(kBinNT) void k_bin_fill_staged(const u64 *__restrict__ edges,
+// two workgroups per compute unit (8 waves per SIMD): at most 64 VGPRs
+__global__ __launch_bounds__(kBinNT, 8) void k_bin_fill_staged(const u64 *__restrict__ edges,
                                                             const u64 *__restrict__ offs,
                                                             uint32_t nblk, uint32_t nbins,
                                                             uint32_t shift,
@@ -807,6 +811,8 @@ __global__ __launch_bounds__(kBinNT) void k_bin_fill_staged(const u64 *__restric
   __shared__ uint32_t sbcnt[kFillMaxSub], sbstart[kFillMaxSub], sbcur[kFillMaxSub];
   __shared__ uint32_t sbfirst[kFillMaxSub + 1];
   __shared__ uint32_t sbrow[kFillMaxSub + 1];  // column (from the bin's first) of sbfirst's row
+  __shared__ uint32_t tcnt[kFillMaxSub], tpos[kFillMaxSub];  // per tile of the regrouping
+  __shared__ uint32_t s_wsum[kBinNT / 64];
   const uint32_t t = threadIdx.x;
   for (uint32_t bin = blockIdx.x; bin < nbins; bin += gridDim.x) {
     const uint32_t first = bin << shift, nv = min(1u << shift, n - first);
@@ -818,6 +824,7 @@ __global__ __launch_bounds__(kBinNT) void k_bin_fill_staged(const u64 *__restric
       if (i < kFillMaxSub) {
         sbcnt[i] = 0;
         sbcur[i] = 0;
+        tcnt[i] = 0;
       }
       sbfirst[i] = nv;
     }
@@ -849,21 +856,49 @@ __global__ __launch_bounds__(kBinNT) void k_bin_fill_staged(const u64 *__restric
     __syncthreads();
     u64 lo, hi;
     bin_range(offs, nblk, nbins, *kept, bin, lo, hi);
-    for (u64 e0 = lo + t; e0 < hi; e0 += kBinNT * 4u) {
+    // regroup by sub-bin one tile of kFillTile edges at a time: rank each edge within its
+    // sub-bin by LDS atomic, scan the tile's sub-bin counts, sort the tile in the (still idle)
+    // stage and write it out, so that each sub-bin's edges of the tile leave as one run
+    u64 *const s_tile = reinterpret_cast<u64 *>(stage);
+    uint32_t run = 0;  // thread sb < nsb: edges of sub-bin sb written so far
+    for (u64 e0 = lo; e0 < hi; e0 += kFillTile) {
       u64 kv[4];
+      uint32_t sr[4];  // sub-bin << 16 | rank within the tile (rank < kFillTile <= 2^16)
 #pragma unroll
       for (uint32_t j = 0; j < 4; j++) {
-        const u64 e = e0 + kBinNT * j;
+        const u64 e = e0 + t + kBinNT * j;
         kv[j] = e < hi ? __builtin_nontemporal_load(&edges[e]) : ~0ull;
       }
 #pragma unroll
-      for (uint32_t j = 0; j < 4; j++)
+      for (uint32_t j = 0; j < 4; j++) {
+        sr[j] = 0;
         if (kv[j] != ~0ull) {
-          const uint32_t sb = sbid[(uint32_t)(kv[j] >> 32) - first];
-          tmp[lo + sbstart[sb] + atomicAdd(&sbcur[sb], 1u)] = kv[j];
+          const uint32_t s = sbid[(uint32_t)(kv[j] >> 32) - first];
+          sr[j] = s << 16 | atomicAdd(&tcnt[s], 1u);
         }
+      }
+      __syncthreads();
+      const uint32_t c = t < nsb ? tcnt[t] : 0u;
+      uint32_t n_tile;
+      const uint32_t ex = block_excl_scan<kBinNT>(c, s_wsum, n_tile);
+      if (t < nsb) {
+        tcnt[t] = 0;
+        tpos[t] = ex;
+        sbcur[t] = run;
+        run += c;
+      }
+      __syncthreads();
+#pragma unroll
+      for (uint32_t j = 0; j < 4; j++)
+        if (kv[j] != ~0ull) s_tile[tpos[sr[j] >> 16] + (sr[j] & 0xFFFFu)] = kv[j];
+      __syncthreads();
+      for (uint32_t p = t; p < n_tile; p += kBinNT) {
+        const u64 x = s_tile[p];
+        const uint32_t s = sbid[(uint32_t)(x >> 32) - first];
+        tmp[lo + sbstart[s] + sbcur[s] + (p - tpos[s])] = x;
+      }
+      __syncthreads();
     }
-    __syncthreads();
     for (uint32_t sb = 0; sb < nsb; sb++) {
       if (sbfirst[sb] >= sbfirst[sb + 1]) continue;  // no row starts here (same for every thread)
       const uint32_t r0 = sbrow[sb], r1 = sbrow[sb + 1];
