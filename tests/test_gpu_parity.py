@@ -143,10 +143,13 @@ def test_row_fill_modes(name, gr, row_fill, unique):
     assert_queries_equal(g, o, u, v)
 
 
+@pytest.mark.parametrize("order", ["shuffled", "by_src", "by_dst"])
 @pytest.mark.parametrize("slack_min", [0, 40, 3000])
-def test_row_fill_assembled_sub_bins(slack_min):
+def test_row_fill_assembled_sub_bins(slack_min, order):
     """Assembled fill over bins of several sub-bins: many short rows, rows wider than the LDS
-    stage (filled directly) and sub-bins where no row starts; labels and queries as the oracle."""
+    stage (filled directly) and sub-bins where no row starts; labels and queries as the oracle.
+    Input sorted by one endpoint sends whole waves of the ingest's counters to one bin or key
+    (one atomic per wave or per run) in that direction."""
     rng = np.random.default_rng(17 + slack_min)
     n = 20000
     src = rng.integers(0, n, 120000).astype(np.uint32)
@@ -156,10 +159,12 @@ def test_row_fill_assembled_sub_bins(slack_min):
     hub_dst = rng.integers(0, n, 30000).astype(np.uint32)
     src = np.concatenate([src, np.full(30000, 79, np.uint32), hub_dst])
     dst = np.concatenate([dst, hub_dst, np.full(30000, 12345, np.uint32)])
-    perm = rng.permutation(src.size)
+    perm = {"shuffled": rng.permutation(src.size),
+            "by_src": np.lexsort((dst, src)),
+            "by_dst": np.lexsort((src, dst))}[order]
     src, dst = src[perm], dst[perm]
     outs = {}
-    for row_fill in (1, 2):
+    for row_fill in (0, 1, 2):
         g = gpu_index(n, src, dst, num_landmarks=16, bl_bits=16, row_fill=row_fill,
                       slack_min=slack_min)
         outs[row_fill] = g
