@@ -136,8 +136,9 @@ void dbl_default_options(dbl_options *opt);
  *   opt: NULL = defaults.  *out receives the new index (NULL on error).
  * Device memory: besides the index, the build holds scratch until it returns: 9 bytes per
  * edge for the partitioned edges and keep flags, the de-duplication table (16-32 bytes per
- * edge) unless edges_unique, and 8 bytes per edge of row-fill staging that lives in that table
- * when there is one. If the staging buffer cannot be had, rows are filled directly instead.
+ * edge) unless edges_unique, and, once a direction's rows are assembled in LDS (row_fill), 8
+ * bytes per edge of staging, which lives in that table when there is one. If the staging
+ * buffer cannot be had, rows are filled directly instead.
  * Errors: INVALID_ARG (bad options or sizes), VERTEX_RANGE (an id >= n), OUT_OF_MEMORY,
  * DEVICE. On error no index is returned and nothing is leaked.
  */

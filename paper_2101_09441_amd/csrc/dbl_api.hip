@@ -896,11 +896,10 @@ dbl_status do_build(dbl_index *ix, uint64_t m, const uint32_t *src, const uint32
     if (st == DBL_OK) st = dalloc(&btmp, dbl::scan_tmp_words(nblk * nbins));
     if (st == DBL_OK) st = dalloc(&bkept, 3);  // kept edges, then the grouping sample
     if (st == DBL_OK) st = dalloc(&edges, m);
-    // staging for the row fill: the dedup table (at least 2m entries) is free by then; without
-    // one, a buffer of its own, and without that the rows fill directly
+    // staging for the row fill, taken when a direction wants it: the dedup table (at least 2m
+    // entries) is free by then; without one, a buffer of its own, and without that the rows
+    // fill directly
     u64 *own_tmp = nullptr;
-    if (st == DBL_OK && !table && m && dalloc(&own_tmp, m) != DBL_OK) own_tmp = nullptr;
-    u64 *const stage_tmp = table ? table : own_tmp;
     for (uint32_t d = 0; d < 2 && st == DBL_OK; d++) {
       Csr &g = d ? ix->r : ix->f;
       uint64_t &total = d ? ix->r_total : ix->f_total;
@@ -938,10 +937,11 @@ dbl_status do_build(dbl_index *ix, uint64_t m, const uint32_t *src, const uint32
       total = t;
       st = dalloc(&g.col, total);
       if (st != DBL_OK) break;
-      u64 *const fill_tmp =
-          total < (1ull << 32) && use_staged_fill(o.row_fill, same, sampled, total, n)
-              ? stage_tmp
-              : nullptr;
+      u64 *fill_tmp = nullptr;
+      if (m && total < (1ull << 32) && use_staged_fill(o.row_fill, same, sampled, total, n)) {
+        if (!table && !own_tmp && dalloc(&own_tmp, m) != DBL_OK) own_tmp = nullptr;
+        fill_tmp = table ? table : own_tmp;
+      }
       if (m) e = dbl::launch_bin_rows(edges, offs, nblk, n, bkept, kept, g.deg, &g, fill_tmp, s);
       if (e == hipSuccess) e = hipStreamSynchronize(s);
       if (e != hipSuccess) st = from_hip(e);
