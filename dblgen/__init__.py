@@ -24,7 +24,12 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "dblgen.c")
-_LIB = os.path.join(_HERE, "libdblgen.so")
+# DBL_SANITIZE=1 selects a build instrumented with AddressSanitizer and UndefinedBehaviorSanitizer
+# (a library of its own name; the process must preload the ASan runtime).
+_SANITIZE = os.environ.get("DBL_SANITIZE") == "1"
+_LIB = os.path.join(_HERE, "libdblgen_san.so" if _SANITIZE else "libdblgen.so")
+_SAN_FLAGS = ["-g", "-O1", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+              "-fno-sanitize-recover=undefined"]
 _lib = None
 
 RMAT_A, RMAT_B, RMAT_C = 0.57, 0.19, 0.19
@@ -33,7 +38,8 @@ RMAT_A, RMAT_B, RMAT_C = 0.57, 0.19, 0.19
 def build() -> str:
     """Compile ``dblgen.c`` into ``libdblgen.so`` (always recompiles)."""
     tmp = _LIB + ".tmp"
-    subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-pthread", "-o", tmp,
+    opt = _SAN_FLAGS if _SANITIZE else ["-O2"]
+    subprocess.check_call(["gcc", *opt, "-std=gnu11", "-fPIC", "-shared", "-pthread", "-o", tmp,
                            _SRC, "-lm"])
     os.replace(tmp, _LIB)
     return _LIB

@@ -19,7 +19,13 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "dbl_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# DBL_SANITIZE=1 selects a build instrumented with AddressSanitizer and UndefinedBehaviorSanitizer
+# (a library of its own name; the process must preload the ASan runtime, see
+# tests/test_sanitizers.py).
+_SANITIZE = os.environ.get("DBL_SANITIZE") == "1"
+_LIB = os.path.join(_HERE, "liboracle_san.so" if _SANITIZE else "liboracle.so")
+_SAN_FLAGS = ["-g", "-O1", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+              "-fno-sanitize-recover=undefined"]
 _lib = None
 
 CLASS_SELF, CLASS_R1, CLASS_R2, CLASS_R3, CLASS_R4, CLASS_BFS_TRUE, CLASS_BFS_FALSE = range(7)
@@ -29,9 +35,10 @@ RANK_PRODUCT, RANK_MAX, RANK_MIN, RANK_SUM = range(4)
 
 
 def build() -> str:
-    """Compile the oracle with gcc (always recompiles)."""
+    """Compile the oracle with gcc (always recompiles; instrumented under DBL_SANITIZE=1)."""
     tmp = _LIB + ".tmp"
-    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-pthread", "-o", tmp,
+    opt = _SAN_FLAGS if _SANITIZE else ["-O2"]
+    subprocess.check_call(["gcc", *opt, "-std=c11", "-fPIC", "-shared", "-pthread", "-o", tmp,
                            _SRC])
     os.replace(tmp, _LIB)
     return _LIB
@@ -64,8 +71,6 @@ def _load():
     lib.orc_query_dbl_rules.restype = i32
     lib.orc_set_selection.argtypes = [P, u32, u64]
     lib.orc_set_selection.restype = None
-    lib.orc_query_label_class.argtypes = [P, u64, P, P, P]
-    lib.orc_query_label_class.restype = i32
     lib.orc_insert.argtypes = [P, u64, P, P]
     lib.orc_insert.restype = i32
     lib.orc_label_words.argtypes = [P, ctypes.POINTER(u32), ctypes.POINTER(u32)]
@@ -217,15 +222,6 @@ class OracleIndex:
     def query_truth(self, u, v, threads: int = 1) -> np.ndarray:
         """Plain BFS reachability (no labels): 1 if u reaches v."""
         return self._q(_load().orc_query_truth, u, v, threads)
-
-    def label_class(self, u, v) -> np.ndarray:
-        u, v = _u32(u), _u32(v)
-        out = np.zeros(max(len(u), 1), dtype=np.uint8)
-        rc = _load().orc_query_label_class(self._h, len(u), u.ctypes.data, v.ctypes.data,
-                                           out.ctypes.data)
-        if rc:
-            raise ValueError("label_class failed")
-        return out[:len(u)].copy()
 
     # -- insertion (Algorithm 3)
     def insert(self, src, dst) -> "OracleIndex":

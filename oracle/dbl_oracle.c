@@ -596,17 +596,6 @@ int orc_query_truth(const orc_index *ix, uint64_t count, const uint32_t *u, cons
   return run_queries(ix, count, u, v, out, 1, 0, threads);
 }
 
-/* Label-only part of Algorithm 2: out[i] = class of the first deciding rule, or 0xFF. */
-int orc_query_label_class(const orc_index *ix, uint64_t count, const uint32_t *u,
-                          const uint32_t *v, uint8_t *out) {
-  for (uint64_t i = 0; i < count; i++) {
-    if (u[i] >= ix->n || v[i] >= ix->n) return -1;
-    int c = label_rules(ix, u[i], v[i], ORC_RULES_DL | ORC_RULES_BL);
-    out[i] = (uint8_t)(c < 0 ? 0xFF : c);
-  }
-  return 0;
-}
-
 /* ---------------------------------------------------------------- insertion (Algorithm 3) */
 
 /*
