@@ -313,6 +313,14 @@ void dbl_release_cache(void);
 void dbl_set_cache_limit(uint64_t bytes);
 uint64_t dbl_cached_bytes(void);
 
+/* Device memory the library holds in use (every index, query context and scratch block, over
+   all devices; cached blocks not included), and a cap on it: a device allocation that would
+   take the bytes in use above `bytes` fails as DBL_ERR_OUT_OF_MEMORY, exactly as if the device
+   were full (0 = no cap, the default). For admission decisions, and to force the out-of-memory
+   paths. */
+uint64_t dbl_live_bytes(void);
+void dbl_set_device_limit(uint64_t bytes);
+
 /* Static text for a status code. */
 const char *dbl_status_str(dbl_status s);
 

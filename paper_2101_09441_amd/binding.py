@@ -27,7 +27,8 @@ EXPORTS = [
     "dbl_read_labels", "dbl_get_landmarks", "dbl_get_leaves", "dbl_get_stats",
     "dbl_time_kernels", "dbl_read_kernel_times", "dbl_get_tuning", "dbl_set_tuning",
     "dbl_num_vertices", "dbl_label_words", "dbl_destroy",
-    "dbl_release_cache", "dbl_set_cache_limit", "dbl_cached_bytes",
+    "dbl_release_cache", "dbl_set_cache_limit", "dbl_cached_bytes", "dbl_live_bytes",
+    "dbl_set_device_limit",
     "dbl_status_str",
 ]
 
@@ -170,6 +171,10 @@ def load_library():
     lib.dbl_set_cache_limit.restype = None
     lib.dbl_cached_bytes.argtypes = []
     lib.dbl_cached_bytes.restype = u64
+    lib.dbl_live_bytes.argtypes = []
+    lib.dbl_live_bytes.restype = u64
+    lib.dbl_set_device_limit.argtypes = [u64]
+    lib.dbl_set_device_limit.restype = None
     lib.dbl_status_str.argtypes = [i32]
     lib.dbl_status_str.restype = ctypes.c_char_p
     _lib = lib
@@ -216,6 +221,17 @@ def set_cache_limit(nbytes: int) -> None:
 
 def cached_bytes() -> int:
     return int(load_library().dbl_cached_bytes())
+
+
+def live_bytes() -> int:
+    """Device bytes the library holds in use (indexes, query contexts, scratch)."""
+    return int(load_library().dbl_live_bytes())
+
+
+def set_device_limit(nbytes: int) -> None:
+    """Cap the device bytes the library may hold in use (0 = no cap); an allocation beyond it
+    fails as out of memory."""
+    load_library().dbl_set_device_limit(int(nbytes))
 
 
 def to_device_ids(a, device="cuda") -> torch.Tensor:

@@ -224,6 +224,8 @@ struct MemCache {
   std::vector<Block> spare;
   uint64_t cached = 0;
   uint64_t limit = 64ull << 30;
+  uint64_t live_device = 0;    // bytes of device blocks in use
+  uint64_t device_limit = 0;   // refuse device blocks beyond this many live bytes (0 = no cap)
 };
 
 MemCache &mem_cache() {
@@ -260,6 +262,7 @@ void *take_block(size_t size, bool host) {
   (void)hipGetDevice(&dev);
   MemCache &c = mem_cache();
   std::lock_guard<std::mutex> lk(c.mu);
+  if (!host && c.device_limit && c.live_device + size > c.device_limit) return nullptr;
   for (size_t i = 0; i < c.spare.size(); i++) {
     const Block b = c.spare[i];
     if (b.size == size && b.dev == dev && b.host == host) {
@@ -267,6 +270,7 @@ void *take_block(size_t size, bool host) {
       c.spare.pop_back();
       c.cached -= b.size;
       c.live[b.p] = b;
+      if (!host) c.live_device += b.size;
       return b.p;
     }
   }
@@ -276,6 +280,7 @@ void *take_block(size_t size, bool host) {
                               : hipMalloc(&p, size);
     if (e == hipSuccess) {
       c.live[p] = Block{p, size, dev, host};
+      if (!host) c.live_device += size;
       return p;
     }
     (void)hipGetLastError();
@@ -292,6 +297,7 @@ void put_block(void *p) {
   if (it == c.live.end()) return;
   const Block b = it->second;
   c.live.erase(it);
+  if (!b.host) c.live_device -= b.size;
   c.spare.push_back(b);
   c.cached += b.size;
   if (c.cached > c.limit) trim_locked(c, -1, c.limit);
@@ -322,6 +328,25 @@ void hfree(T *&p) {
   put_block((void *)p);
   p = nullptr;
 }
+
+// Device scratch local to one call. The normal path frees it explicitly once the work using it
+// has finished; on an early (error) return the destructor waits for the stream first, so no
+// path leaks it or hands it out again while a kernel may still use it.
+template <typename T>
+struct Scoped {
+  T *p = nullptr;
+  hipStream_t s;
+  explicit Scoped(hipStream_t st) : s(st) {}
+  Scoped(const Scoped &) = delete;
+  Scoped &operator=(const Scoped &) = delete;
+  ~Scoped() {
+    if (p) {
+      (void)hipStreamSynchronize(s);
+      dfree(p);
+    }
+  }
+  void release() { dfree(p); }
+};
 
 struct DeviceGuard {
   int prev = -1;
@@ -857,19 +882,18 @@ dbl_status do_build(dbl_index *ix, uint64_t m, const uint32_t *src, const uint32
   CK(dbl::launch_validate_pairs(src, dst, m, n, ix->ctl, s));
   CKS(sync_ctl(ix, s));
   if (ix->hs.err) return DBL_ERR_VERTEX_RANGE;
-  uint8_t *keep = nullptr;
-  u64 *table = nullptr;
-  CKS(dalloc(&keep, m));
+  Scoped<uint8_t> keep(s);
+  Scoped<u64> table(s);
+  CKS(dalloc(&keep.p, m));
   uint64_t mask = 0;
   if (!o.edges_unique && m) {
     uint64_t cap = 1024;
     while (cap < 2 * m) cap <<= 1;
-    dbl_status st = dalloc(&table, cap);
-    if (st != DBL_OK) { dfree(keep); return st; }
-    CK(dbl::launch_fill_u64(table, ~0ull, cap, s));
+    CKS(dalloc(&table.p, cap));
+    CK(dbl::launch_fill_u64(table.p, ~0ull, cap, s));
     mask = cap - 1;
   }
-  CK(dbl::launch_dedup_mark(src, dst, m, table, mask, keep, o.edges_unique ? 1 : 0, s));
+  CK(dbl::launch_dedup_mark(src, dst, m, table.p, mask, keep.p, o.edges_unique ? 1 : 0, s));
   CKS(dalloc(&ix->f.deg, n));
   CKS(dalloc(&ix->r.deg, n));
   CKS(dalloc(&ix->f.cap, n));
@@ -880,9 +904,10 @@ dbl_status do_build(dbl_index *ix, uint64_t m, const uint32_t *src, const uint32
   CKS(dalloc(&ix->scan_tmp, ix->scan_tmp_words));
   CKS(dalloc(&ix->scan_total, 2));
   // in/out degrees are needed by selection and seeding; the row fill recounts deg
-  uint32_t *indeg = nullptr, *outdeg = nullptr;
-  CKS(dalloc(&indeg, n));
-  CKS(dalloc(&outdeg, n));
+  Scoped<uint32_t> indeg_s(s), outdeg_s(s);
+  CKS(dalloc(&indeg_s.p, n));
+  CKS(dalloc(&outdeg_s.p, n));
+  uint32_t *const indeg = indeg_s.p, *const outdeg = outdeg_s.p;
   {
     // per direction: partition the kept edges by vertex range, count degrees, reserve slack,
     // lay out the rows, fill them in partition order
@@ -906,7 +931,7 @@ dbl_status do_build(dbl_index *ix, uint64_t m, const uint32_t *src, const uint32
       hipError_t e = hipSuccess;
       u64 kept = 0, same = 0, sampled = 0;
       if (m) {
-        e = dbl::launch_bin_edges(d ? dst : src, d ? src : dst, keep, m, n, nblk, counts, offs,
+        e = dbl::launch_bin_edges(d ? dst : src, d ? src : dst, keep.p, m, n, nblk, counts, offs,
                                   btmp, bkept, bkept + 1, edges, s);
         u64 kr[3] = {0, 0, 0};
         if (e == hipSuccess) e = hipMemcpyAsync(kr, bkept, sizeof(kr), hipMemcpyDeviceToHost, s);
@@ -939,30 +964,25 @@ dbl_status do_build(dbl_index *ix, uint64_t m, const uint32_t *src, const uint32
       if (st != DBL_OK) break;
       u64 *fill_tmp = nullptr;
       if (m && total < (1ull << 32) && use_staged_fill(o.row_fill, same, sampled, total, n)) {
-        if (!table && !own_tmp && dalloc(&own_tmp, m) != DBL_OK) own_tmp = nullptr;
-        fill_tmp = table ? table : own_tmp;
+        if (!table.p && !own_tmp && dalloc(&own_tmp, m) != DBL_OK) own_tmp = nullptr;
+        fill_tmp = table.p ? table.p : own_tmp;
       }
       if (m) e = dbl::launch_bin_rows(edges, offs, nblk, n, bkept, kept, g.deg, &g, fill_tmp, s);
       if (e == hipSuccess) e = hipStreamSynchronize(s);
       if (e != hipSuccess) st = from_hip(e);
     }
+    if (st != DBL_OK) (void)hipStreamSynchronize(s);
     dfree(counts);
     dfree(offs);
     dfree(btmp);
     dfree(bkept);
     dfree(edges);
     if (own_tmp) dfree(own_tmp);
-    if (st != DBL_OK) {
-      dfree(indeg);
-      dfree(outdeg);
-      dfree(table);
-      dfree(keep);
-      return st;
-    }
+    if (st != DBL_OK) return st;
   }
   CK(hipStreamSynchronize(s));
-  dfree(table);
-  dfree(keep);
+  table.release();
+  keep.release();
 
   // ---- a2: landmarks (top-k by |Pre|*|Suc|), leaves and their hash buckets
   CKS(dalloc(&ix->landmarks_d, dbl::kMaxLabelBits));
@@ -972,42 +992,43 @@ dbl_status do_build(dbl_index *ix, uint64_t m, const uint32_t *src, const uint32
                         hipMemcpyHostToDevice, s));
     } else {
       const uint64_t te = dbl::topk_tmp_entries(n);
-      u64 *tm = nullptr;
-      uint32_t *tid = nullptr;
-      CKS(dalloc(&tm, te));
-      dbl_status st = dalloc(&tid, te);
-      if (st != DBL_OK) { dfree(tm); return st; }
-      CK(dbl::select_topk(indeg, outdeg, n, ix->k, o.landmark_rank, tm, tid, ix->landmarks_d, s));
+      Scoped<u64> tm(s);
+      Scoped<uint32_t> tid(s);
+      CKS(dalloc(&tm.p, te));
+      CKS(dalloc(&tid.p, te));
+      CK(dbl::select_topk(indeg, outdeg, n, ix->k, o.landmark_rank, tm.p, tid.p, ix->landmarks_d,
+                          s));
       CK(hipStreamSynchronize(s));
-      dfree(tm);
-      dfree(tid);
+      tm.release();
+      tid.release();
     }
     CK(hipMemcpyAsync(ix->landmarks_h, ix->landmarks_d, sizeof(uint32_t) * ix->k,
                       hipMemcpyDeviceToHost, s));
   }
   CKS(dalloc(&ix->lab, 4ull * ix->lw * n));
   CK(dbl::launch_fill_u64(ix->lab, 0ull, 4ull * ix->lw * n, s));
-  uint8_t *is_lm = nullptr, *flags_in = nullptr, *bucket_in = nullptr;
-  CKS(dalloc(&is_lm, n));
-  CK(hipMemsetAsync(is_lm, 0, n, s));
+  Scoped<uint8_t> is_lm(s), flags_in(s), bucket_in(s);
+  CKS(dalloc(&is_lm.p, n));
+  CK(hipMemsetAsync(is_lm.p, 0, n, s));
   if (o.leaf_flags) {
-    CKS(dalloc(&flags_in, n));
-    CK(hipMemcpyAsync(flags_in, o.leaf_flags, n, hipMemcpyHostToDevice, s));
+    CKS(dalloc(&flags_in.p, n));
+    CK(hipMemcpyAsync(flags_in.p, o.leaf_flags, n, hipMemcpyHostToDevice, s));
   }
   if (o.leaf_bucket) {
-    CKS(dalloc(&bucket_in, n));
-    CK(hipMemcpyAsync(bucket_in, o.leaf_bucket, n, hipMemcpyHostToDevice, s));
+    CKS(dalloc(&bucket_in.p, n));
+    CK(hipMemcpyAsync(bucket_in.p, o.leaf_bucket, n, hipMemcpyHostToDevice, s));
   }
   CKS(dalloc(&ix->leaf_flags, n));
   CKS(dalloc(&ix->bucket, n));
-  CK(dbl::launch_seed({ix->lab, ix->lw}, n, ix->landmarks_d, ix->k, indeg, outdeg, flags_in, bucket_in,
-                      ix->kp_bits, o.leaf_threshold, ix->leaf_flags, ix->bucket, is_lm, s));
+  CK(dbl::launch_seed({ix->lab, ix->lw}, n, ix->landmarks_d, ix->k, indeg, outdeg, flags_in.p,
+                      bucket_in.p, ix->kp_bits, o.leaf_threshold, ix->leaf_flags, ix->bucket,
+                      is_lm.p, s));
   CK(hipStreamSynchronize(s));
-  dfree(is_lm);
-  dfree(flags_in);
-  dfree(bucket_in);
-  dfree(indeg);
-  dfree(outdeg);
+  is_lm.release();
+  flags_in.release();
+  bucket_in.release();
+  indeg_s.release();
+  outdeg_s.release();
 
   // ---- a3: bit-parallel propagation of the seeds to the least fixpoint
   for (int i = 0; i < 3; i++) CKS(dalloc(&ix->fq[i], 2ull * n));
@@ -1674,6 +1695,18 @@ void dbl_set_cache_limit(uint64_t bytes) {
   std::lock_guard<std::mutex> lk(c.mu);
   c.limit = bytes;
   trim_locked(c, -1, c.limit);
+}
+
+uint64_t dbl_live_bytes(void) {
+  MemCache &c = mem_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  return c.live_device;
+}
+
+void dbl_set_device_limit(uint64_t bytes) {
+  MemCache &c = mem_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  c.device_limit = bytes;
 }
 
 uint64_t dbl_cached_bytes(void) {

@@ -7,8 +7,9 @@ defined by its sequence number:
 * a query request observes exactly the insertions that precede it, so queries are never in
   flight while an insertion runs, and an insertion waits until every earlier query finished;
 * query requests between two insertions are read-only and run concurrently: whenever a worker
-  (a query context with its own stream) is free and device memory admits it, the queued query
-  requests at the head of the line are coalesced into one device batch and handed to it;
+  (a query context with its own stream) is free, the queued query requests at the head of the
+  line are coalesced into one device batch, as large as the memory budget admits next to the
+  batches already in flight, and handed to it;
 * consecutive insertion requests are coalesced into one insertion batch (a batch is a set, so
   this equals applying them one after another).
 
@@ -54,6 +55,8 @@ class Executor:
         raise NotImplementedError
 
     def admit(self, pairs: int) -> bool:
+        """Whether a device batch of `pairs` pairs may start now, next to the batches in
+        flight. Raises MemoryError if it could not start even with nothing else in flight."""
         return True
 
     def close(self) -> None:
@@ -110,19 +113,26 @@ class Scheduler:
                     if not self.free:
                         self.cv.wait()
                         continue
-                    if not self.ex.admit(min(head.size, self.max_batch)):
+                    # coalesce the ready queries at the head of the line, up to max_batch pairs
+                    # and as far as memory admits the batch next to those in flight
+                    take, total = 0, 0
+                    for r in pending:
+                        if r.kind != "query" or offset(r) > now:
+                            break
+                        if take and total + r.size > self.max_batch:
+                            break
+                        if not self.ex.admit(total + r.size):
+                            break
+                        take += 1
+                        total += r.size
+                    if take == 0:
                         self.refusals += 1
                         if self.inflight:
                             self.cv.wait()
                         else:
                             self.cv.wait(0.001)
                         continue
-                    batch, total = [], 0
-                    while (pending and pending[0].kind == "query" and offset(pending[0]) <= now
-                           and (not batch or total + pending[0].size <= self.max_batch)):
-                        r = pending.popleft()
-                        batch.append(r)
-                        total += r.size
+                    batch = [pending.popleft() for _ in range(take)]
                     worker = self.free.pop()
                     self.inflight += 1
                     tb = self.clock() - t0
@@ -157,9 +167,20 @@ class Scheduler:
         return self.clock() - t0
 
 
+# Device bytes of one query batch in flight, per pair: the staged pairs (4 + 4 B) and their
+# answer bytes (1 B), allocated for the batch and released when it completes.
+BATCH_BYTES_PER_PAIR = 9
+
+
 class GpuExecutor(Executor):
-    """Query workers (a query context, a stream, pinned staging and a host thread each) and an
-    insertion path, over one resident index."""
+    """Query workers (a query context, a stream, pinned host staging and a host thread each)
+    and an insertion path, over one resident index.
+
+    Device memory is budgeted: the budget is `memory_cap` (or the free device memory less
+    `reserve`). Each worker's context is a fixed part (visited bitmaps, queues and counters,
+    and its undecided-pair list sized for max_batch); each batch in flight adds its staged
+    pairs and answers. A batch is admitted only while the fixed parts plus every batch in flight
+    plus the new one fit the budget; otherwise it waits for a batch to finish."""
 
     def __init__(self, index, workers: int = 4, max_batch: int = 1 << 17, bfs_slots: int = 256,
                  memory_cap: Optional[int] = None, reserve: int = 256 << 20):
@@ -171,23 +192,25 @@ class GpuExecutor(Executor):
         self.index = index
         self.max_batch = max_batch
         dev = index.device
-        per = index.query_context_bytes(bfs_slots, 0, max_batch) + max_batch * 9 * 2
+        fixed = index.query_context_bytes(bfs_slots, 0, max_batch)
         free, _ = torch.cuda.mem_get_info(dev)
         budget = free - reserve if memory_cap is None else min(memory_cap, free - reserve)
-        fit = max(0, budget // per)
+        # at least one worker and one batch of max_batch pairs must fit
+        fit = max(0, (budget - self.footprint(max_batch)) // fixed) if budget > 0 else 0
         if fit < 1:
-            raise MemoryError(f"device memory admits no query worker ({per} bytes each, "
-                              f"{budget} available)")
+            raise MemoryError(f"device memory admits no query worker ({fixed} bytes each plus "
+                              f"{self.footprint(max_batch)} for a batch; {budget} available)")
         self.workers = int(min(workers, fit))
         self.memory_cap = memory_cap
         self.reserve = reserve
-        self.ctx, self.streams, self.dbuf, self.hbuf = [], [], [], []
+        self.batch_budget = budget - self.workers * fixed
+        self.inflight_bytes = 0
+        self.peak_inflight_bytes = 0
+        self.mem_lock = threading.Lock()
+        self.ctx, self.streams, self.hbuf = [], [], []
         for _ in range(self.workers):
             self.ctx.append(index.query_context(bfs_slots=bfs_slots))
             self.streams.append(torch.cuda.Stream(device=dev))
-            self.dbuf.append((torch.empty(max_batch, dtype=torch.int32, device=dev),
-                              torch.empty(max_batch, dtype=torch.int32, device=dev),
-                              torch.empty(max_batch, dtype=torch.uint8, device=dev)))
             self.hbuf.append((torch.empty(max_batch, dtype=torch.int32).pin_memory(),
                               torch.empty(max_batch, dtype=torch.int32).pin_memory(),
                               torch.empty(max_batch, dtype=torch.uint8).pin_memory()))
@@ -209,16 +232,24 @@ class GpuExecutor(Executor):
                 return
             self._run_query(w, *job)
 
+    @staticmethod
+    def footprint(pairs: int) -> int:
+        """Device bytes a batch of `pairs` pairs holds while in flight."""
+        return pairs * BATCH_BYTES_PER_PAIR
+
     def admit(self, pairs: int) -> bool:
-        """Room for one more batch in flight: the free device memory stays above the reserve."""
-        free, _ = self.torch.cuda.mem_get_info(self.index.device)
-        return free >= self.reserve
+        need = self.footprint(pairs)
+        if need > self.batch_budget:
+            raise MemoryError(f"a query batch of {pairs} pairs needs {need} bytes; the memory "
+                              f"budget leaves {self.batch_budget} for batches")
+        with self.mem_lock:
+            return self.inflight_bytes + need <= self.batch_budget
 
     def _run_query(self, w: int, reqs: List[Request], on_done):
         torch = self.torch
+        total = sum(r.size for r in reqs)
         try:
             hu, hv, ho = self.hbuf[w]
-            du, dv, do = self.dbuf[w]
             nu, nv = hu.numpy().view(np.uint32), hv.numpy().view(np.uint32)
             off = 0
             for r in reqs:
@@ -227,21 +258,35 @@ class GpuExecutor(Executor):
                 off += r.size
             s = self.streams[w]
             with torch.cuda.stream(s):
-                du[:off].copy_(hu[:off], non_blocking=True)
-                dv[:off].copy_(hv[:off], non_blocking=True)
-                self.ctx[w].query(du[:off], dv[:off], out=do[:off], stream=s)
-                ho[:off].copy_(do[:off], non_blocking=True)
+                # the batch's device staging, admitted against the budget by the scheduler
+                du = torch.empty(off, dtype=torch.int32, device=self.index.device)
+                dv = torch.empty(off, dtype=torch.int32, device=self.index.device)
+                do = torch.empty(off, dtype=torch.uint8, device=self.index.device)
+                du.copy_(hu[:off], non_blocking=True)
+                dv.copy_(hv[:off], non_blocking=True)
+                self.ctx[w].query(du, dv, out=do, stream=s)
+                ho[:off].copy_(do, non_blocking=True)
             s.synchronize()
+            del du, dv, do
             no = ho.numpy()
             off = 0
             for r in reqs:
                 r.answers = no[off:off + r.size].copy()
                 off += r.size
+            self._release(total)
             on_done(w, reqs)
         except BaseException as e:  # reported by the scheduler
+            self._release(total)
             on_done(w, reqs, e)
 
+    def _release(self, pairs: int) -> None:
+        with self.mem_lock:
+            self.inflight_bytes -= self.footprint(pairs)
+
     def query_async(self, worker: int, reqs: List[Request], on_done) -> None:
+        with self.mem_lock:
+            self.inflight_bytes += self.footprint(sum(r.size for r in reqs))
+            self.peak_inflight_bytes = max(self.peak_inflight_bytes, self.inflight_bytes)
         self.jobs[worker].put((reqs, on_done))
 
     def insert(self, reqs: List[Request]) -> None:
@@ -306,5 +351,7 @@ def serve(index, trace: List[Request], workers: int = 4, max_batch: int = 1 << 1
     finally:
         ex.close()
     s = latency_summary(trace, span)
-    s.update(workers=ex.workers, device_batches=sch.batches, admission_waits=sch.refusals)
+    s.update(workers=ex.workers, device_batches=sch.batches, admission_waits=sch.refusals,
+             batch_budget_bytes=int(ex.batch_budget),
+             peak_inflight_batch_bytes=int(ex.peak_inflight_bytes))
     return s

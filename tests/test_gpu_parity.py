@@ -396,9 +396,7 @@ def test_tiny_single_insertions_then_queries(tiny):
     for i in range(len(w.ins_src)):
         g.insert_edges(su[i:i + 1], sv[i:i + 1])
         o.insert(w.ins_src[i:i + 1], w.ins_dst[i:i + 1])
-        if i % 50 == 49 or i < 20:
-            assert_labels_equal(g, o, f"after insertion {i}")
-    assert_labels_equal(g, o, "after all insertions")
+        assert_labels_equal(g, o, f"after insertion {i}")
     got = assert_queries_equal(g, o, w.q_u, w.q_v)
     truth = o.query_truth(w.q_u, w.q_v, threads=8)
     assert np.array_equal(got & 1, truth)
@@ -577,6 +575,23 @@ def test_out_of_range_ids_leave_index_unchanged(tiny):
     for a, b in zip(before, after):
         assert np.array_equal(a, b)
     assert g.stats()["num_edges"] == edges_before
+    # batches above the single-workgroup limit (validated by the grid path), and a small one
+    # with that limit at zero, each with a single bad id somewhere in it
+    rng = np.random.default_rng(9)
+    for count, small_batch in ((5000, None), (70000, None), (10, 0)):
+        if small_batch is not None:
+            g.set_tuning(small_batch=small_batch)
+        a = rng.integers(0, w.n, count).astype(np.uint32)
+        b = rng.integers(0, w.n, count).astype(np.uint32)
+        bad = int(rng.integers(0, count))
+        (a if bad % 2 else b)[bad] = w.n + bad
+        with pytest.raises(dbl.DblError) as e:
+            g.insert_edges(dev(a), dev(b))
+        assert e.value.status == dbl.DBL_ERR_VERTEX_RANGE
+        for x, y in zip(before, g.labels_numpy()):
+            assert np.array_equal(x, y), f"labels changed by a refused batch of {count}"
+        assert g.stats()["num_edges"] == edges_before
+    g.set_tuning(small_batch=2048)
     with pytest.raises(dbl.DblError) as e:
         g.query(dev([0, w.n]), dev([1, 2]))
     assert e.value.status == dbl.DBL_ERR_VERTEX_RANGE
@@ -786,3 +801,37 @@ def test_vertex_insertion(tiny):
     assert np.array_equal(bucket, ob)
     with pytest.raises(dbl.DblError):
         g.insert_edges(dev([0]), dev([n]))
+
+
+def test_build_out_of_memory_leaks_nothing(tiny):
+    """Every device allocation of a build can fail: under a device cap swept from just above
+    what the library already holds up to what a build needs, each build either fails with
+    OUT_OF_MEMORY and leaves the library's bytes in use exactly as before, or succeeds with
+    labels equal to the oracle's."""
+    w = tiny
+    src, dst = dev(w.src), dev(w.dst)
+    dbl.release_cache()
+    base = dbl.live_bytes()
+    g = gpu_index(w.n, w.src, w.dst)
+    need = dbl.live_bytes() - base
+    g.close()
+    assert dbl.live_bytes() == base
+    o = oracle.OracleIndex(w.n, w.src, w.dst).build(threads=8)
+    failures = 0
+    try:
+        for frac in np.linspace(0.0, 1.2, 41):
+            dbl.set_device_limit(base + int(frac * need) + 1)
+            try:
+                g = dbl.Index.build(w.n, src, dst)
+            except dbl.DblError as e:
+                assert e.status == dbl.DBL_ERR_OUT_OF_MEMORY
+                assert dbl.live_bytes() == base, f"build failing at {frac:.2f} leaked"
+                failures += 1
+                continue
+            dbl.set_device_limit(0)
+            assert_labels_equal(g, o, f"build under a cap of {frac:.2f}")
+            g.close()
+            assert dbl.live_bytes() == base
+    finally:
+        dbl.set_device_limit(0)
+    assert failures >= 20

@@ -73,20 +73,47 @@ def test_serving_results_equal_alone(tiny, realtime, rate):
     g = dbl.Index.build(w.n, dev(w.src), dev(w.dst))
     summ = serve(g, trace, workers=4, max_batch=4096, bfs_slots=64, realtime=realtime)
     assert summ["query"]["requests"] + summ["insert"]["requests"] == len(trace)
-    # alone: each request by itself, in sequence order, on a fresh index
+    _check_against_alone_and_oracle(w, g, trace)
+    if not realtime:
+        assert summ["device_batches"] < len(trace)  # the backlog was coalesced
+
+
+def _check_against_alone_and_oracle(w, g, trace):
+    """Every answer of the mix equals the same request run alone on a fresh index in sequence
+    order, and the oracle's Algorithm 2 on the state its sequence number defines; the final
+    labels equal both."""
     a = dbl.Index.build(w.n, dev(w.src), dev(w.dst))
     o = oracle.OracleIndex(w.n, w.src, w.dst).build(threads=8)
     for r in sorted(trace, key=lambda r: r.seq):
         if r.kind == "query":
             alone = a.query(dev(r.a), dev(r.b)).cpu().numpy()
-            assert np.array_equal(r.answers, alone), f"request {r.seq}"
+            assert np.array_equal(r.answers, alone), f"request {r.seq} vs alone"
+            assert np.array_equal(r.answers, o.query_dbl(r.a, r.b, threads=8)), \
+                f"request {r.seq} vs oracle"
         else:
             a.insert_edges(dev(r.a), dev(r.b))
             o.insert(r.a, r.b)
     for x, y, z in zip(g.labels_numpy(), a.labels_numpy(), o.labels()):
         assert np.array_equal(x, y) and np.array_equal(x, z)
-    if not realtime:
-        assert summ["device_batches"] < len(trace)  # the backlog was coalesced
+
+
+def test_serving_memory_budget_defers_batches(tiny):
+    """A budget with room for the workers' fixed scratch and one full batch in flight: a
+    backlog of query batches is admitted one batch at a time (the rest wait), and every answer
+    still equals the oracle's on its sequence state."""
+    from paper_2101_09441_amd.serve import GpuExecutor
+    w = tiny
+    trace = _trace(w, 120, 1.0, seed=21, q_size=(500, 3000))
+    g = dbl.Index.build(w.n, dev(w.src), dev(w.dst))
+    max_batch = 4096
+    fixed = g.query_context_bytes(64, 0, max_batch)
+    cap = 3 * fixed + GpuExecutor.footprint(max_batch) + GpuExecutor.footprint(max_batch) // 2
+    summ = serve(g, trace, workers=4, max_batch=max_batch, bfs_slots=64, realtime=False,
+                 memory_cap=cap)
+    assert summ["workers"] == 3
+    assert summ["admission_waits"] > 0
+    assert 0 < summ["peak_inflight_batch_bytes"] <= summ["batch_budget_bytes"]
+    _check_against_alone_and_oracle(w, g, trace)
 
 
 def test_serving_memory_cap_refuses(tiny):

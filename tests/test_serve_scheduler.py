@@ -125,3 +125,47 @@ def test_admission_refusals_delay_but_do_not_reorder():
     sch.run(trace, realtime=False)
     assert sch.refusals >= 25
     _check(w, trace, ex)
+
+
+class BudgetExecutor(OracleExecutor):
+    """Admits a batch while the pairs in flight, the new batch's included, fit a budget."""
+
+    def __init__(self, o, budget, **kw):
+        super().__init__(o, **kw)
+        self.budget = budget
+        self.inflight = 0
+        self.peak = 0
+
+    def admit(self, pairs):
+        if pairs > self.budget:
+            raise MemoryError("batch larger than the budget")
+        with self.lock:
+            return self.inflight + pairs <= self.budget
+
+    def query_async(self, worker, reqs, on_done):
+        k = sum(r.size for r in reqs)
+        with self.lock:
+            self.inflight += k
+            self.peak = max(self.peak, self.inflight)
+
+        def done(w, rs, err=None):
+            with self.lock:
+                self.inflight -= k
+            on_done(w, rs, err) if err else on_done(w, rs)
+
+        super().query_async(worker, reqs, done)
+
+
+def test_memory_budget_limits_batches_in_flight():
+    """Batches are cut and deferred so that the pairs in flight never exceed the budget; the
+    answers still equal the requests run alone."""
+    w = dblgen.tiny_workload(1)
+    trace = _trace(w, n=120, seed=13)
+    budget = 450
+    ex = BudgetExecutor(oracle.OracleIndex(w.n, w.src, w.dst).build(), budget, workers=4,
+                        delay=0.005)
+    sch = Scheduler(ex, max_batch=400)
+    sch.run(trace, realtime=False)
+    _check(w, trace, ex)
+    assert 0 < ex.peak <= budget
+    assert sch.refusals > 0
