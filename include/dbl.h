@@ -218,6 +218,26 @@ dbl_status dbl_query_batch_rules(dbl_index *ix, dbl_query_ctx *ctx, uint64_t cou
                                  const uint32_t *d_u, const uint32_t *d_v, uint8_t *d_out,
                                  uint32_t rules, void *stream);
 
+/*
+ * dbl_query_batch for callers that cannot allocate device memory (code that must not call
+ * hipMalloc, tight serving loops, harnesses that forbid allocation). Same arguments, answers
+ * and errors as dbl_query_batch; it calls no allocator at all. Its scratch (control block,
+ * undecided-pair list, BFS slots, the whole-device BFS's bitmap and frontier ring) lives in one
+ * static device array of 128 MiB that every GPU the library runs on holds from the loading of
+ * the library's code until the process ends. Limits: with n the index's vertex count and
+ * B = ceil(count / 256), 12.125 n + 2 KiB * B + 4 (n / 8 + 4 q) bytes (q = min(n, 65536, the
+ * index's bfs_queue_cap if set), each part rounded up to 256 bytes) must fit in the 128 MiB
+ * less a 16 KiB header, i.e. at least four BFS slots must fit; a larger n or count returns
+ * DBL_ERR_INVALID_ARG and does nothing. Up to 256 BFS slots (at most the index's bfs_slots
+ * option) are used, as many as fit. The array keeps what the last call left; each call clears
+ * what must start at zero. All calls on one GPU share its array, so two calls that overlapped
+ * on one GPU would race; the library serialises them instead (a call holds the GPU's array
+ * until its work has finished). The stream is synchronised before the call returns. These
+ * batches are not counted in dbl_get_stats.
+ */
+dbl_status dbl_query_batch_noalloc(dbl_index *ix, uint64_t count, const uint32_t *d_u,
+                                   const uint32_t *d_v, uint8_t *d_out, void *stream);
+
 /* Copy the labels out: each argument is a device array [n * W] of uint64, W =
    dbl_label_words(ix), vertex x's label in words [x * W, x * W + W) (any may be NULL). */
 dbl_status dbl_read_labels(const dbl_index *ix, uint64_t *d_dl_in, uint64_t *d_dl_out,

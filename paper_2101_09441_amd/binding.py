@@ -23,7 +23,7 @@ EXPORTS = [
     "dbl_default_options", "dbl_build", "dbl_add_vertices", "dbl_insert_edges",
     "dbl_insert_edges_each",
     "dbl_query_batch", "dbl_query_ctx_bytes", "dbl_query_ctx_create", "dbl_query_batch_ctx",
-    "dbl_query_ctx_destroy", "dbl_query_batch_rules",
+    "dbl_query_ctx_destroy", "dbl_query_batch_rules", "dbl_query_batch_noalloc",
     "dbl_read_labels", "dbl_get_landmarks", "dbl_get_leaves", "dbl_get_stats",
     "dbl_time_kernels", "dbl_read_kernel_times", "dbl_get_tuning", "dbl_set_tuning",
     "dbl_num_vertices", "dbl_label_words", "dbl_destroy",
@@ -132,6 +132,8 @@ def load_library():
     lib.dbl_insert_edges_each.restype = i32
     lib.dbl_query_batch.argtypes = [P, u64, P, P, P, P]
     lib.dbl_query_batch.restype = i32
+    lib.dbl_query_batch_noalloc.argtypes = [P, u64, P, P, P, P]
+    lib.dbl_query_batch_noalloc.restype = i32
     lib.dbl_query_ctx_bytes.argtypes = [P, u32, u32, u64]
     lib.dbl_query_ctx_bytes.restype = u64
     lib.dbl_query_ctx_create.argtypes = [P, u32, u32, ctypes.POINTER(P)]
@@ -411,6 +413,21 @@ class Index:
             st = load_library().dbl_query_batch(self._handle(), u.numel(), u.data_ptr(),
                                                 v.data_ptr(), out.data_ptr(), _stream_ptr(stream))
         _check(st, "dbl_query_batch")
+        return out
+
+    def query_noalloc(self, u: torch.Tensor, v: torch.Tensor, out: torch.Tensor,
+                      stream=None) -> torch.Tensor:
+        """dbl_query_batch_noalloc: the library allocates nothing; `out` is the caller's."""
+        u, v = _ids(u, "u"), _ids(v, "v")
+        if u.numel() != v.numel():
+            raise ValueError("u and v differ in length")
+        if out.dtype != torch.uint8 or out.numel() < u.numel() or not out.is_contiguous():
+            raise ValueError("out must be a contiguous uint8 tensor with room for every pair")
+        with torch.cuda.device(self.device):
+            st = load_library().dbl_query_batch_noalloc(self._handle(), u.numel(), u.data_ptr(),
+                                                        v.data_ptr(), out.data_ptr(),
+                                                        _stream_ptr(stream))
+        _check(st, "dbl_query_batch_noalloc")
         return out
 
     def query_rules(self, u: torch.Tensor, v: torch.Tensor, rules: int,

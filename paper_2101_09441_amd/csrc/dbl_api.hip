@@ -1203,6 +1203,183 @@ dbl_status grow(T *&p, uint64_t old_count, uint64_t new_count, hipStream_t s) {
   return DBL_OK;
 }
 
+// ---------------------------------------------------------------- allocation-free queries
+// dbl_query_batch_noalloc keeps all of a batch's scratch in one static device array: every GPU
+// the library runs on holds its own copy from the moment the code object is loaded until the
+// process ends. In host code `scratch` only names a host-side stand-in; the device address of
+// each GPU's copy comes from hipGetSymbolAddress, taken once per device with that device
+// current, and only that address is ever handed to kernels.
+constexpr uint64_t kScratchBytes = 128ull << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kScratchDevices = 64;
+constexpr uint32_t kScratchMaxSlots = 256;
+constexpr uint32_t kScratchMaxQueue = 1u << 16;
+
+struct ScratchDev {
+  std::mutex mu;                 // held by a call for as long as its work uses the array
+  unsigned char *ptr = nullptr;  // device address of this GPU's `scratch`
+  uint64_t zero_bytes = 0;       // leading bytes of the visited-bitmap area known to be zero
+};
+ScratchDev g_scratch[kScratchDevices];
+
+// Fixed header: control block, device-side status, class counters, per-slot BFS counters.
+constexpr uint64_t kScrCtl = 0, kScrMirror = 256, kScrQcls = 512;
+constexpr uint64_t kScrBfsCnt = kScrQcls + (uint64_t)dbl::kQueryGrid * dbl::kQClsStride * 8;
+constexpr uint64_t kScrVis = 16384;  // visited bitmaps start here (the zero-tracked area)
+static_assert(sizeof(Ctl) <= 256 && sizeof(dbl::Mirror) <= 256, "header fields");
+static_assert(kScrBfsCnt + (uint64_t)kScratchMaxSlots * dbl::kBfsCtrStride * 8 <= kScrVis,
+              "header size");
+
+uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
+
+// Where each part of one batch goes in the scratch array.
+struct ScratchLayout {
+  uint32_t slots = 0, qcap = 0;
+  uint64_t vis_words = 0, vis = 0, queue = 0, und = 0, heavy_q = 0, seg = 0, gvis = 0;
+  uint64_t gfq[3] = {0, 0, 0};
+  uint64_t end = 0;
+};
+
+// Lay out a batch of `count` pairs on an index of ix->n vertices: as many BFS slots (a multiple
+// of four, at most the index's bfs_slots option or 256) as fit beside the rest. False when not
+// even four slots fit.
+bool scratch_layout(const dbl_index *ix, uint64_t count, ScratchLayout *L) {
+  const uint64_t n = ix->n;
+  L->vis_words = (n + 63) / 64;
+  L->qcap = (uint32_t)std::min<uint64_t>(n, ix->qcap_opt ? std::min(ix->qcap_opt, kScratchMaxQueue)
+                                                           : kScratchMaxQueue);
+  const uint64_t blocks = (count + dbl::kQueryNT - 1) / dbl::kQueryNT;
+  const uint64_t fixed = align256(blocks * dbl::kQueryNT * 4) * 2 + align256(blocks * 4) +
+                         align256(L->vis_words * 8) + 3 * align256(n * 4);
+  const uint64_t per_slot = L->vis_words * 8 + (uint64_t)L->qcap * 4;
+  const uint64_t room = kScratchBytes - kScrVis;
+  if (fixed + 4 * per_slot + 512 > room) return false;
+  uint64_t slots = (room - fixed - 512) / per_slot;
+  const uint32_t want = ix->slots_opt ? std::min(ix->slots_opt, kScratchMaxSlots) : kScratchMaxSlots;
+  slots = std::min<uint64_t>(slots, std::max<uint32_t>(4, want)) / 4 * 4;
+  L->slots = (uint32_t)slots;
+  uint64_t at = kScrVis;
+  L->vis = at;
+  at = align256(at + slots * L->vis_words * 8);
+  L->queue = at;
+  at = align256(at + slots * (uint64_t)L->qcap * 4);
+  L->und = at;
+  at += align256(blocks * dbl::kQueryNT * 4);
+  L->heavy_q = at;
+  at += align256(blocks * dbl::kQueryNT * 4);
+  L->seg = at;
+  at += align256(blocks * 4);
+  L->gvis = at;
+  at += align256(L->vis_words * 8);
+  for (int i = 0; i < 3; i++) {
+    L->gfq[i] = at;
+    at += align256(n * 4);
+  }
+  L->end = at;
+  return at <= kScratchBytes;
+}
+
+// Device address of the current device's `scratch`, resolved on the first call per device
+// (the caller holds that device's lock and has made the device current).
+dbl_status scratch_ptr(ScratchDev &d) {
+  if (!d.ptr) {
+    void *p = nullptr;
+    CK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return DBL_ERR_DEVICE;
+    d.ptr = (unsigned char *)p;
+    d.zero_bytes = 0;
+  }
+  return DBL_OK;
+}
+
+// Algorithm 2 over a batch (as run_queries) with every piece of scratch in the static array.
+dbl_status run_queries_noalloc(const dbl_index *ix, ScratchDev *sd, uint64_t count, const uint32_t *d_u,
+                               const uint32_t *d_v, uint8_t *d_out, hipStream_t s) {
+  ScratchLayout L;
+  if (!scratch_layout(ix, count, &L)) return DBL_ERR_INVALID_ARG;
+  unsigned char *base = sd->ptr;
+  Ctl *ctl = (Ctl *)(base + kScrCtl);
+  dbl::Mirror *mirror = (dbl::Mirror *)(base + kScrMirror);
+  u64 *qcls = (u64 *)(base + kScrQcls);
+  u64 *bfs_cnt = (u64 *)(base + kScrBfsCnt);
+  // The array keeps whatever the last call left: the header starts at zero on every call; the
+  // visited bitmaps must be zero where this batch's slots lie (searches clear what they set, so
+  // after a completed call the bitmap area it used is zero again).
+  CK(dbl::launch_fill_u64((u64 *)base, 0ull, kScrVis / 8, s));
+  const uint64_t vis_bytes = L.queue - L.vis;
+  if (sd->zero_bytes < vis_bytes)
+    CK(dbl::launch_fill_u64((u64 *)(base + L.vis + sd->zero_bytes), 0ull,
+                            (vis_bytes - sd->zero_bytes) / 8, s));
+  sd->zero_bytes = 0;  // until this call completes
+  dbl::BfsArgs b;
+  b.L = {ix->lab, ix->lw};
+  b.f = ix->f;
+  b.u = d_u;
+  b.v = d_v;
+  b.und = (uint32_t *)(base + L.und);
+  b.seg = (uint32_t *)(base + L.seg);
+  b.nseg = (uint32_t)((count + dbl::kQueryNT - 1) / dbl::kQueryNT);
+  b.out = d_out;
+  b.vis = (u64 *)(base + L.vis);
+  b.vis_words = L.vis_words;
+  b.queue = (uint32_t *)(base + L.queue);
+  b.qcap = L.qcap;
+  b.heavy_q = (uint32_t *)(base + L.heavy_q);
+  b.cnt = bfs_cnt;
+  b.rules = DBL_RULES_ALL;
+  b.ctl = ctl;
+  CK(dbl::launch_query_label({ix->lab, ix->lw}, d_u, d_v, count, ix->n, ix->f.deg, d_out,
+                             (uint32_t *)(base + L.und), (uint32_t *)(base + L.seg), ctl, qcls,
+                             DBL_RULES_ALL, s));
+  CK(dbl::launch_query_bfs(b, L.slots, mirror, 1u, s));
+  dbl::Mirror h;
+  CK(hipMemcpyAsync(&h, mirror, sizeof(h), hipMemcpyDeviceToHost, s));
+  CK(hipStreamSynchronize(s));
+  if (h.seq != 1u) return DBL_ERR_DEVICE;
+  if (h.err) {
+    sd->zero_bytes = vis_bytes;
+    return DBL_ERR_VERTEX_RANGE;
+  }
+  if (h.bfs_heavy) {
+    // pairs whose pruned BFS outgrew a slot: one whole-device BFS each (rare), over the
+    // scratch's own bitmap and frontier ring
+    dbl::PropArgs a = prop_args(ix);
+    for (int i = 0; i < 3; i++) a.fq[i] = (uint32_t *)(base + L.gfq[i]);
+    a.ctl = ctl;
+    u64 *gvis = (u64 *)(base + L.gvis);
+    const uint32_t *heavy_q = (const uint32_t *)(base + L.heavy_q);
+    uint32_t seq = 1;
+    uint32_t qi[64];
+    for (uint32_t i0 = 0; i0 < h.bfs_heavy; i0 += 64) {
+      const uint32_t nb = std::min<uint32_t>(64, h.bfs_heavy - i0);
+      CK(hipMemcpyAsync(qi, heavy_q + i0, sizeof(uint32_t) * nb, hipMemcpyDeviceToHost, s));
+      CK(hipStreamSynchronize(s));
+      for (uint32_t i = 0; i < nb; i++) {
+        uint32_t uv[2] = {0, 0};
+        CK(hipMemcpyAsync(&uv[0], d_u + qi[i], sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        CK(hipMemcpyAsync(&uv[1], d_v + qi[i], sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        CK(hipStreamSynchronize(s));
+        CK(dbl::launch_gbfs_start(a, gvis, L.vis_words, uv[0], s));
+        uint32_t ring = 0;
+        for (;;) {
+          CK(dbl::launch_gbfs_round(a, gvis, uv[0], uv[1], ring, DBL_RULES_ALL, s));
+          ring = ring == 2 ? 0 : ring + 1;
+          CK(dbl::launch_publish(ctl, mirror, ++seq, s));
+          CK(hipMemcpyAsync(&h, mirror, sizeof(h), hipMemcpyDeviceToHost, s));
+          CK(hipStreamSynchronize(s));
+          if (h.seq != seq) return DBL_ERR_DEVICE;
+          if (h.found || h.fsize[ring] == 0) break;
+        }
+        CK(dbl::launch_gbfs_finish(a, qi[i], d_out, qcls, s));
+      }
+    }
+    CK(hipStreamSynchronize(s));
+  }
+  sd->zero_bytes = vis_bytes;
+  return DBL_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1359,6 +1536,21 @@ dbl_status dbl_insert_edges_each(dbl_index *ix, uint64_t count, const uint32_t *
   DeviceGuard dg(ix->device);
   return insert_each_served(ix, (uint32_t)count, d_src, d_dst, h_latency_us,
                             (hipStream_t)stream);
+}
+
+dbl_status dbl_query_batch_noalloc(dbl_index *ix, uint64_t count, const uint32_t *d_u,
+                                   const uint32_t *d_v, uint8_t *d_out, void *stream) {
+  if (!ix) return DBL_ERR_INVALID_ARG;
+  if (count == 0) return DBL_OK;
+  if (!d_u || !d_v || !d_out || count > 0xFFFFFFFFull) return DBL_ERR_INVALID_ARG;
+  if (ix->device < 0 || ix->device >= kScratchDevices) return DBL_ERR_DEVICE;
+  ScratchLayout L;
+  if (!scratch_layout(ix, count, &L)) return DBL_ERR_INVALID_ARG;
+  DeviceGuard dg(ix->device);
+  ScratchDev &sd = g_scratch[ix->device];
+  std::lock_guard<std::mutex> lk(sd.mu);
+  CKS(scratch_ptr(sd));
+  return run_queries_noalloc(ix, &sd, count, d_u, d_v, d_out, (hipStream_t)stream);
 }
 
 dbl_status dbl_query_batch(dbl_index *ix, uint64_t count, const uint32_t *d_u,

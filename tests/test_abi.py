@@ -49,3 +49,5 @@ def test_host_only_entry_points():
                          ctypes.byref(out)) == dbl.DBL_ERR_INVALID_ARG
     assert lib.dbl_insert_edges(None, 1, None, None, None) == dbl.DBL_ERR_INVALID_ARG
     assert lib.dbl_query_batch(None, 1, None, None, None, None) == dbl.DBL_ERR_INVALID_ARG
+    assert lib.dbl_query_batch_noalloc(None, 1, None, None, None,
+                                       None) == dbl.DBL_ERR_INVALID_ARG
