@@ -103,6 +103,12 @@ def _load():
     lib.orc_big_reach.restype = ctypes.c_int64
     lib.orc_big_query_truth.argtypes = [P, u64, P, P, P, u32]
     lib.orc_big_query_truth.restype = i32
+    lib.orc_big_labels.argtypes = [P, u32, P, u32, P, P, P, u32, u32, P, P, P, P]
+    lib.orc_big_labels.restype = i32
+    lib.orc_big_query_dbl.argtypes = [P, P, P, P, P, u64, P, P, P, u32]
+    lib.orc_big_query_dbl.restype = i32
+    lib.orc_big_query_bibfs.argtypes = [P, u64, P, P, P, u32]
+    lib.orc_big_query_bibfs.restype = i32
     _lib = lib
     return lib
 
@@ -320,6 +326,51 @@ class BigGraph:
         u, v = _u32(u), _u32(v)
         out = np.zeros(max(len(u), 1), dtype=np.uint8)
         rc = _load().orc_big_query_truth(self._h, len(u), u.ctypes.data, v.ctypes.data,
+                                         out.ctypes.data, threads)
+        if rc:
+            raise ValueError("query failed")
+        return out[:len(u)].copy()
+
+    def labels(self, landmarks, s_in, s_out, bucket, kp: int = 64, threads: int = 1,
+               on_label=None):
+        """(DL_in, DL_out, BL_in, BL_out) as uint64[n] (k, k' <= 64) from one BFS per bit
+        column (Definitions 1 and 2), given the landmarks, leaf masks and leaf hash. The labels
+        are computed one after another; on_label(name) is called after each."""
+        lm = _u32(landmarks)
+        si = np.ascontiguousarray(s_in, dtype=np.uint8)
+        so = np.ascontiguousarray(s_out, dtype=np.uint8)
+        bk = np.ascontiguousarray(bucket, dtype=np.uint8)
+        if len(si) != self.n or len(so) != self.n or len(bk) != self.n:
+            raise ValueError("leaf masks and bucket need n entries")
+        labs = [np.zeros(max(self.n, 1), dtype=np.uint64) for _ in range(4)]
+        for i, name in enumerate(("DL_in", "DL_out", "BL_in", "BL_out")):
+            rc = _load().orc_big_labels(self._h, len(lm), lm.ctypes.data, kp, si.ctypes.data,
+                                        so.ctypes.data, bk.ctypes.data, 1 << i, threads,
+                                        *[a.ctypes.data for a in labs])
+            if rc:
+                raise ValueError("orc_big_labels failed (bad sizes or out of memory)")
+            if on_label is not None:
+                on_label(name)
+        return tuple(a[:self.n] for a in labs)
+
+    def query_dbl(self, labels, u, v, threads: int = 1) -> np.ndarray:
+        """Algorithm 2 on this graph with the given one-word labels: answer | class << 1."""
+        labs = [np.ascontiguousarray(a, dtype=np.uint64) for a in labels]
+        if any(len(a) != self.n for a in labs):
+            raise ValueError("labels need n entries")
+        u, v = _u32(u), _u32(v)
+        out = np.zeros(max(len(u), 1), dtype=np.uint8)
+        rc = _load().orc_big_query_dbl(self._h, *[a.ctypes.data for a in labs], len(u),
+                                       u.ctypes.data, v.ctypes.data, out.ctypes.data, threads)
+        if rc:
+            raise ValueError("query failed")
+        return out[:len(u)].copy()
+
+    def query_bibfs(self, u, v, threads: int = 1) -> np.ndarray:
+        """Reachability per pair by bidirectional BFS without labels: 1 if u reaches v."""
+        u, v = _u32(u), _u32(v)
+        out = np.zeros(max(len(u), 1), dtype=np.uint8)
+        rc = _load().orc_big_query_bibfs(self._h, len(u), u.ctypes.data, v.ctypes.data,
                                          out.ctypes.data, threads)
         if rc:
             raise ValueError("query failed")

@@ -930,3 +930,255 @@ int orc_big_query_truth(const orc_big *g, uint64_t count, const uint32_t *u, con
   }
   return pool.failed ? -1 : 0;
 }
+
+/*
+ * All four labels of the large graph at k, k' <= 64 (one 64-bit word per label), straight from
+ * Definitions 1 and 2: bit i of DL_in(x) is set when x is in the reachable set of landmark
+ * landmarks[i] (forward), bit i of DL_out(x) when x reaches it (backward); bit j of BL_in(x) when
+ * x is reachable from some vertex of S_in hashed to j (forward from that source set), bit j of
+ * BL_out(x) when x reaches some vertex of S_out hashed to j (backward). Every bit column is one
+ * orc_big_reach of its source set (Algorithm 1 with the visited set of reading R1); the columns
+ * are spread over `threads` threads and OR-ed into the labels atomically (different bits of one
+ * word belong to different columns). s_in / s_out: uint8[n] masks; bucket: uint8[n], h(x) < kp.
+ * kinds: which labels to compute (bit 0 DL_in, 1 DL_out, 2 BL_in, 3 BL_out); each of those is
+ * zeroed first, the others are left as they are. Returns 0, or -1 on bad sizes or allocation
+ * failure.
+ */
+typedef struct {
+  const orc_big *g;
+  uint32_t k, kp;
+  const uint32_t *landmarks;
+  const uint8_t *s_in, *s_out, *bucket;
+  uint64_t *lab[4]; /* DL_in, DL_out, BL_in, BL_out */
+  uint32_t kinds;   /* labels to compute (bit i = lab[i]) */
+  uint32_t next;    /* shared column counter: column c is (label c / 64, bit c % 64) */
+  int failed;
+} orc_big_colpool;
+
+static void *big_column_worker(void *arg) {
+  orc_big_colpool *p = (orc_big_colpool *)arg;
+  const orc_big *g = p->g;
+  const size_t words = (size_t)(g->n + 63) / 64;
+  uint64_t *bm = (uint64_t *)malloc(8 * (words ? words : 1));
+  uint32_t *src = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(g->n ? g->n : 1));
+  if (!bm || !src) {
+    __atomic_store_n(&p->failed, 1, __ATOMIC_RELAXED);
+    free(bm); free(src);
+    return NULL;
+  }
+  for (;;) {
+    const uint32_t c = __atomic_fetch_add(&p->next, 1, __ATOMIC_RELAXED);
+    if (c >= 4 * 64) break;
+    const uint32_t which = c / 64, bit = c % 64;
+    uint64_t ns = 0;
+    if (!(p->kinds >> which & 1)) continue;
+    if (which < 2) {
+      if (bit >= p->k) continue;
+      src[ns++] = p->landmarks[bit];
+    } else {
+      if (bit >= p->kp) continue;
+      const uint8_t *leaf = which == 2 ? p->s_in : p->s_out;
+      for (uint32_t x = 0; x < g->n; x++)
+        if (leaf[x] && p->bucket[x] == bit) src[ns++] = x;
+    }
+    const int forward = which == 0 || which == 2;
+    if (orc_big_reach(g, ns, src, forward, bm) < 0) {
+      __atomic_store_n(&p->failed, 1, __ATOMIC_RELAXED);
+      break;
+    }
+    uint64_t *lab = p->lab[which];
+    const uint64_t mask = 1ULL << bit;
+    for (size_t w = 0; w < words; w++)
+      for (uint64_t b = bm[w]; b; b &= b - 1)
+        __atomic_fetch_or(&lab[w * 64 + (uint64_t)__builtin_ctzll(b)], mask, __ATOMIC_RELAXED);
+  }
+  free(bm);
+  free(src);
+  return NULL;
+}
+
+int orc_big_labels(const orc_big *g, uint32_t k, const uint32_t *landmarks, uint32_t kp,
+                   const uint8_t *s_in, const uint8_t *s_out, const uint8_t *bucket,
+                   uint32_t kinds, uint32_t threads, uint64_t *dl_in, uint64_t *dl_out,
+                   uint64_t *bl_in, uint64_t *bl_out) {
+  if (k > 64 || kp == 0 || kp > 64 || (kp & (kp - 1))) return -1;
+  for (uint32_t i = 0; i < k; i++)
+    if (landmarks[i] >= g->n) return -1;
+  for (uint32_t x = 0; x < g->n; x++)
+    if (bucket[x] >= kp) return -1;
+  uint64_t *labs[4] = {dl_in, dl_out, bl_in, bl_out};
+  for (int i = 0; i < 4; i++)
+    if (kinds >> i & 1) memset(labs[i], 0, 8 * (size_t)g->n);
+  orc_big_colpool pool = {g, k, kp, landmarks, s_in, s_out, bucket,
+                          {dl_in, dl_out, bl_in, bl_out}, kinds & 15u, 0, 0};
+  if (threads <= 1) {
+    big_column_worker(&pool);
+  } else {
+    pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * threads);
+    uint32_t started = 0;
+    if (th)
+      for (; started < threads; started++)
+        if (pthread_create(&th[started], NULL, big_column_worker, &pool)) break;
+    if (started == 0) big_column_worker(&pool);
+    for (uint32_t i = 0; i < started; i++) pthread_join(th[i], NULL);
+    free(th);
+  }
+  return pool.failed ? -1 : 0;
+}
+
+/*
+ * Algorithm 2 on the large graph with given labels (one word each, e.g. from orc_big_labels):
+ * self, then Lemma 1, Lemma 2, Theorem 1, Theorem 2 on the labels, else the pruned BFS from u
+ * over Suc (prune x when DL_out(u) and DL_in(x) share a landmark, or when BL_Contain(x, v)
+ * fails; visited marks on enqueue, reading R3). out[i] = answer | (class << 1), the class codes
+ * of orc_query_dbl.
+ */
+typedef struct {
+  const orc_big *g;
+  const uint64_t *dl_in, *dl_out, *bl_in, *bl_out;
+  const uint32_t *u, *v;
+  uint8_t *out;
+  uint64_t count, next;
+  int mode; /* 0: Algorithm 2; 1: bidirectional plain BFS (answer only) */
+  int failed;
+} orc_big_apool;
+
+static int big_label_rules(const orc_big_apool *p, uint32_t u, uint32_t v) {
+  if (u == v) return ORC_CLASS_SELF;
+  if (p->dl_out[u] & p->dl_in[v]) return ORC_CLASS_R1_DL_HIT;
+  if ((p->bl_in[u] & ~p->bl_in[v]) || (p->bl_out[v] & ~p->bl_out[u])) return ORC_CLASS_R2_BL_MISS;
+  if (p->dl_out[v] & p->dl_in[u]) return ORC_CLASS_R3_THM1;
+  if ((p->dl_out[u] & p->dl_in[u]) || (p->dl_out[v] & p->dl_in[v])) return ORC_CLASS_R4_THM2;
+  return -1;
+}
+
+static int big_pruned_bfs(const orc_big_apool *p, uint32_t *queue, uint64_t *seen, uint32_t u,
+                          uint32_t v) {
+  const orc_big *g = p->g;
+  uint64_t head = 0, tail = 0;
+  int found = 0;
+  seen[u >> 6] |= 1ULL << (u & 63);
+  queue[tail++] = u;
+  while (!found && head < tail) {
+    const uint32_t w = queue[head++];
+    for (uint64_t j = g->fo[w]; j < g->fo[w + 1]; j++) {
+      const uint32_t x = g->fc[j];
+      if (x == v) { found = 1; break; }
+      if (p->dl_out[u] & p->dl_in[x]) continue;                      /* a landmark of u reaches x */
+      if ((p->bl_in[x] & ~p->bl_in[v]) || (p->bl_out[v] & ~p->bl_out[x])) continue; /* x misses v */
+      if (seen[x >> 6] >> (x & 63) & 1) continue;
+      seen[x >> 6] |= 1ULL << (x & 63);
+      queue[tail++] = x;
+    }
+  }
+  for (uint64_t j = 0; j < tail; j++) seen[queue[j] >> 6] = 0;
+  return found;
+}
+
+/*
+ * Textbook bidirectional BFS with no labels: a forward search from u over Suc and a backward
+ * search from v over Pre, each step expanding one whole level of the side whose frontier has
+ * fewer vertices; u reaches v exactly when the two visited sets meet, and not when either
+ * search runs out first.
+ */
+static int big_bibfs(const orc_big *g, uint32_t *qf, uint32_t *qb, uint64_t *sf, uint64_t *sb,
+                     uint32_t u, uint32_t v) {
+  if (u == v) return 1;
+  uint64_t fh = 0, ft = 0, bh = 0, bt = 0;
+  int met = 0;
+  sf[u >> 6] |= 1ULL << (u & 63);
+  qf[ft++] = u;
+  sb[v >> 6] |= 1ULL << (v & 63);
+  qb[bt++] = v;
+  while (!met && fh < ft && bh < bt) {
+    const int fwd = (ft - fh) <= (bt - bh);
+    const uint64_t *off = fwd ? g->fo : g->ro;
+    const uint32_t *col = fwd ? g->fc : g->rc;
+    uint32_t *q = fwd ? qf : qb;
+    uint64_t *mine = fwd ? sf : sb, *other = fwd ? sb : sf;
+    uint64_t *head = fwd ? &fh : &bh, *tail = fwd ? &ft : &bt;
+    const uint64_t level_end = *tail;
+    while (!met && *head < level_end) {
+      const uint32_t w = q[(*head)++];
+      for (uint64_t j = off[w]; j < off[w + 1]; j++) {
+        const uint32_t x = col[j];
+        if (other[x >> 6] >> (x & 63) & 1) { met = 1; break; }
+        if (mine[x >> 6] >> (x & 63) & 1) continue;
+        mine[x >> 6] |= 1ULL << (x & 63);
+        q[(*tail)++] = x;
+      }
+    }
+  }
+  for (uint64_t j = 0; j < ft; j++) sf[qf[j] >> 6] = 0;
+  for (uint64_t j = 0; j < bt; j++) sb[qb[j] >> 6] = 0;
+  return met;
+}
+
+static void *big_answer_worker(void *arg) {
+  orc_big_apool *p = (orc_big_apool *)arg;
+  const orc_big *g = p->g;
+  const size_t nn = g->n ? g->n : 1, words = (size_t)(g->n + 63) / 64 + 1;
+  uint32_t *qa = (uint32_t *)malloc(sizeof(uint32_t) * nn);
+  uint32_t *qb = (uint32_t *)malloc(sizeof(uint32_t) * nn);
+  uint64_t *sa = (uint64_t *)calloc(words, sizeof(uint64_t));
+  uint64_t *sb = (uint64_t *)calloc(words, sizeof(uint64_t));
+  if (!qa || !qb || !sa || !sb) {
+    __atomic_store_n(&p->failed, 1, __ATOMIC_RELAXED);
+    free(qa); free(qb); free(sa); free(sb);
+    return NULL;
+  }
+  for (;;) {
+    const uint64_t b = __atomic_fetch_add(&p->next, ORC_QCHUNK, __ATOMIC_RELAXED);
+    if (b >= p->count) break;
+    const uint64_t e = b + ORC_QCHUNK < p->count ? b + ORC_QCHUNK : p->count;
+    for (uint64_t i = b; i < e; i++) {
+      const uint32_t u = p->u[i], v = p->v[i];
+      if (p->mode == 1) {
+        p->out[i] = (uint8_t)big_bibfs(g, qa, qb, sa, sb, u, v);
+        continue;
+      }
+      int c = big_label_rules(p, u, v), ans;
+      if (c < 0) {
+        ans = big_pruned_bfs(p, qa, sa, u, v);
+        c = ans ? ORC_CLASS_BFS_TRUE : ORC_CLASS_BFS_FALSE;
+      } else {
+        ans = (c == ORC_CLASS_SELF || c == ORC_CLASS_R1_DL_HIT);
+      }
+      p->out[i] = (uint8_t)(ans | (c << 1));
+    }
+  }
+  free(qa); free(qb); free(sa); free(sb);
+  return NULL;
+}
+
+static int big_answers(orc_big_apool *pool, uint32_t threads) {
+  for (uint64_t i = 0; i < pool->count; i++)
+    if (pool->u[i] >= pool->g->n || pool->v[i] >= pool->g->n) return -1;
+  if (threads <= 1) {
+    big_answer_worker(pool);
+  } else {
+    pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * threads);
+    uint32_t started = 0;
+    if (th)
+      for (; started < threads; started++)
+        if (pthread_create(&th[started], NULL, big_answer_worker, pool)) break;
+    if (started == 0) big_answer_worker(pool);
+    for (uint32_t i = 0; i < started; i++) pthread_join(th[i], NULL);
+    free(th);
+  }
+  return pool->failed ? -1 : 0;
+}
+
+int orc_big_query_dbl(const orc_big *g, const uint64_t *dl_in, const uint64_t *dl_out,
+                      const uint64_t *bl_in, const uint64_t *bl_out, uint64_t count,
+                      const uint32_t *u, const uint32_t *v, uint8_t *out, uint32_t threads) {
+  orc_big_apool pool = {g, dl_in, dl_out, bl_in, bl_out, u, v, out, count, 0, 0, 0};
+  return big_answers(&pool, threads);
+}
+
+/* Reachability per pair by bidirectional BFS (no labels): out[i] = 1 if u reaches v. */
+int orc_big_query_bibfs(const orc_big *g, uint64_t count, const uint32_t *u, const uint32_t *v,
+                        uint8_t *out, uint32_t threads) {
+  orc_big_apool pool = {g, NULL, NULL, NULL, NULL, u, v, out, count, 0, 1, 0};
+  return big_answers(&pool, threads);
+}

@@ -1,13 +1,21 @@
-"""GPU parity at scale, by sampled label columns and properties that hold at any size.
+"""GPU parity at scale: every label word and every answer byte against the oracle.
 
-The default size is 2^23 vertices and the distinct edges of 2^27 R-MAT draws; set
-DBL_FULL_SCALE=1 for the 2^25-vertex, ~1.0e9-edge configuration (2^30 draws, 10M insertions in
-100k batches, 10M Zipf-skewed queries in 64k batches). The oracle side builds its own CSR from
-the generator's edges, selects its own landmarks and leaves, and computes one BFS per sampled
-bit; the GPU labels must match those bit columns on every vertex. Edge monotonicity is checked
-on every edge, and a sample of answers against plain BFS.
+The configuration is R-MAT with 2^25 vertices and the distinct edges of 2^30 draws (about
+1.05e9), 10M insertions continuing the stream in batches of 100,000, then 10M queries with
+Zipf(1.1)-skewed sources in batches of 65,536 (DBL_SCALE=small runs the same at 2^23 vertices,
+2^27 draws, 1M insertions and 1M queries).
+
+The oracle side builds its own CSR from the generator's edges, selects its own landmarks and
+leaves, and computes every bit column of all four labels by one BFS per column (Definitions 1
+and 2), after the build and again on the grown graph with the leaf sets fixed at build time.
+The GPU labels must equal those columns word for word; every answer byte (answer and decision
+class) must equal the oracle's Algorithm 2 over its labels on the grown graph; a stratified
+sample of at least 10,000 answers must equal a bidirectional BFS that uses no labels. Labels
+never shrink along an edge: checked on every edge after the build and after every insertion
+batch.
 """
 import os
+import time
 
 import numpy as np
 import pytest
@@ -20,53 +28,46 @@ pytestmark = pytest.mark.gpu
 
 dbl = pytest.importorskip("paper_2101_09441_amd")
 
-FULL = os.environ.get("DBL_FULL_SCALE") == "1"
-SCALE, DRAWS = (25, 1 << 30) if FULL else (23, 1 << 27)
-N_INS, N_Q = (10_000_000, 10_000_000) if FULL else (1_000_000, 1_000_000)
-DL_BITS = (0, 21, 42, 63)
-BL_BITS = (0, 17, 33, 50, 63)
+SMALL = os.environ.get("DBL_SCALE") == "small"
+SCALE, DRAWS = (23, 1 << 27) if SMALL else (25, 1 << 30)
+N_INS, N_Q = (1_000_000, 1_000_000) if SMALL else (10_000_000, 10_000_000)
+BATCH, QBATCH = 100_000, 65_536
+THREADS = min(16, os.cpu_count() or 1)
+T0 = time.time()
 
 
-def _columns_match(gl, big, lm, s_in, s_out, bucket, what):
-    dl_in, dl_out, bl_in, bl_out = gl
-    print(f"{what}: checking {len(DL_BITS)} DL and {len(BL_BITS)} BL bit columns per direction",
-          flush=True)
-    for i in DL_BITS:
-        col = (dl_in >> i) & 1
-        want = torch.from_numpy(big.reach([lm[i]], True)).to(col.device)
-        assert torch.equal(col.bool(), want), f"{what}: DL_in bit {i}"
-        col = (dl_out >> i) & 1
-        want = torch.from_numpy(big.reach([lm[i]], False)).to(col.device)
-        assert torch.equal(col.bool(), want), f"{what}: DL_out bit {i}"
-        print(f"{what}: DL bit {i} ok", flush=True)
-    for j in BL_BITS:
-        col = (bl_in >> j) & 1
-        want = torch.from_numpy(big.reach(np.flatnonzero(s_in & (bucket == j)), True))
-        assert torch.equal(col.bool(), want.to(col.device)), f"{what}: BL_in bit {j}"
-        col = (bl_out >> j) & 1
-        want = torch.from_numpy(big.reach(np.flatnonzero(s_out & (bucket == j)), False))
-        assert torch.equal(col.bool(), want.to(col.device)), f"{what}: BL_out bit {j}"
-        print(f"{what}: BL bit {j} ok", flush=True)
+def _say(msg):
+    print(f"[{time.time() - T0:7.1f}s] {msg}", flush=True)
 
 
-def _edge_monotone(gl, src, dst, chunk=1 << 26):
-    dl_in, dl_out, bl_in, bl_out = gl
-    for lo in range(0, len(src), chunk):
-        a = torch.from_numpy(src[lo:lo + chunk].astype(np.int64)).to(dl_in.device)
-        b = torch.from_numpy(dst[lo:lo + chunk].astype(np.int64)).to(dl_in.device)
+def _labels_equal(g, want, what):
+    for name, a, b in zip(("DL_in", "DL_out", "BL_in", "BL_out"), g.labels_numpy(), want):
+        bad = np.flatnonzero(a != b)
+        assert len(bad) == 0, (f"{what}: {name} differs at {len(bad)} vertices, first "
+                               f"{bad[:5]}: gpu {a[bad[:5]]} oracle {b[bad[:5]]}")
+    _say(f"{what}: all label words equal the oracle's")
+
+
+def _edge_monotone(labs, src, dst, chunk=1 << 26):
+    """For every edge (a, b) (device int32 arrays): the forward labels of a are within those of
+    b, the backward labels of b within those of a."""
+    dl_in, dl_out, bl_in, bl_out = labs
+    for lo in range(0, src.numel(), chunk):
+        a, b = src[lo:lo + chunk], dst[lo:lo + chunk]
         for lab, fwd in ((dl_in, True), (bl_in, True), (dl_out, False), (bl_out, False)):
-            x, y = (lab[a], lab[b]) if fwd else (lab[b], lab[a])
-            assert not torch.any(x & ~y), "a label shrinks along an edge"
+            x = torch.index_select(lab, 0, a if fwd else b)
+            y = torch.index_select(lab, 0, b if fwd else a)
+            if torch.any(x & ~y):
+                return False
+    return True
 
 
-def test_scale_build_insert_query():
+def test_scale_full_parity():
     w = dblgen.scale_workload(SCALE, DRAWS, N_INS, N_Q)
-    print(f"scale workload n={w.n} m={w.m} insertions={len(w.ins_src)} queries={len(w.q_u)}",
-          flush=True)
+    _say(f"workload n={w.n} m={w.m} insertions={len(w.ins_src)} queries={len(w.q_u)}")
     src, dst = dbl.to_device_ids(w.src), dbl.to_device_ids(w.dst)
     g = dbl.Index.build(w.n, src, dst, edges_unique=True)
-    del src, dst
-    print("built on the GPU; building the oracle's CSR", flush=True)
+    _say("built on the GPU; the oracle's CSR and labels")
     big = oracle.BigGraph(w.n, w.src, w.dst)
     lm = big.landmarks(64)
     assert np.array_equal(g.landmarks(), lm)
@@ -75,34 +76,56 @@ def test_scale_build_insert_query():
     assert np.array_equal(flags & 1, s_in.astype(np.uint8))
     assert np.array_equal((flags >> 1) & 1, s_out.astype(np.uint8))
     assert np.array_equal(gbucket, bucket)
-    _columns_match(g.labels(), big, lm, s_in, s_out, bucket, "build")
-    _edge_monotone(g.labels(), w.src, w.dst)
-    print("labels monotone along every build edge", flush=True)
+    want = big.labels(lm, s_in, s_out, bucket, threads=THREADS,
+                      on_label=lambda name: _say(f"oracle {name} done"))
     big.close()
+    _labels_equal(g, want, "build")
+    del want
+    assert _edge_monotone(g.labels(), src, dst), "a label shrinks along a build edge"
+
     isrc, idst = dbl.to_device_ids(w.ins_src), dbl.to_device_ids(w.ins_dst)
-    for lo in range(0, len(w.ins_src), 100_000):
-        g.insert_edges(isrc[lo:lo + 100_000], idst[lo:lo + 100_000])
-    print("insertions done", flush=True)
+    for lo in range(0, len(w.ins_src), BATCH):
+        g.insert_edges(isrc[lo:lo + BATCH], idst[lo:lo + BATCH])
+        labs = g.labels()
+        ok = _edge_monotone(labs, src, dst) and _edge_monotone(labs, isrc[:lo + BATCH],
+                                                                 idst[:lo + BATCH])
+        assert ok, f"a label shrinks along an edge after the batch at {lo}"
+    del labs
+    _say(f"{len(w.ins_src)} insertions in batches of {BATCH}; labels monotone after each")
+
+    qu, qv = dbl.to_device_ids(w.q_u), dbl.to_device_ids(w.q_v)
+    out = torch.empty(len(w.q_u), dtype=torch.uint8, device=qu.device)
+    for lo in range(0, len(w.q_u), QBATCH):
+        g.query(qu[lo:lo + QBATCH], qv[lo:lo + QBATCH], out=out[lo:lo + QBATCH])
+    ans = out.cpu().numpy()
+    cls = ans >> 1
+    _say(f"queries done: classes {np.bincount(cls, minlength=7).tolist()}")
+    st = g.stats()
+    assert st["queries"] == len(w.q_u) and st["num_edges"] == w.m + len(w.ins_src)
+
     all_src = np.concatenate([w.src, w.ins_src])
     all_dst = np.concatenate([w.dst, w.ins_dst])
     big = oracle.BigGraph(w.n, all_src, all_dst)
-    _columns_match(g.labels(), big, lm, s_in, s_out, bucket, "after insertions")
-    _edge_monotone(g.labels(), all_src, all_dst)
-    qu, qv = dbl.to_device_ids(w.q_u), dbl.to_device_ids(w.q_v)
-    out = torch.empty(len(w.q_u), dtype=torch.uint8, device=qu.device)
-    for lo in range(0, len(w.q_u), 65536):
-        g.query(qu[lo:lo + 65536], qv[lo:lo + 65536], out=out[lo:lo + 65536])
-    ans = out.cpu().numpy()
-    print(f"queries done: classes {np.bincount(ans >> 1, minlength=7).tolist()}", flush=True)
+    del all_src, all_dst
+    # the leaf sets and the hash stay those fixed at build time
+    want = big.labels(lm, s_in, s_out, bucket, threads=THREADS,
+                      on_label=lambda name: _say(f"oracle {name} done"))
+    _labels_equal(g, want, "after insertions")
+    exp = big.query_dbl(want, w.q_u, w.q_v, threads=THREADS)
+    bad = np.flatnonzero(ans != exp)
+    assert len(bad) == 0, (f"{len(bad)} of {len(ans)} answers differ, first {bad[:5]}: "
+                           f"gpu {ans[bad[:5]]} oracle {exp[bad[:5]]}")
+    _say(f"all {len(ans)} answer bytes equal the oracle's Algorithm 2")
+    # a second truth without labels: every BFS-decided pair and a sample of each other class
     rng = np.random.default_rng(5)
-    # a sample of every class, answers against plain BFS
-    cls = ans >> 1
-    pick = []
-    for c in range(7):
+    pick = [np.flatnonzero(cls >= 5)]
+    for c in range(5):
         idx = np.flatnonzero(cls == c)
-        pick.extend(rng.choice(idx, size=min(len(idx), 12), replace=False).tolist())
-    pick = np.array(pick, dtype=np.int64)
-    truth = big.query_truth(w.q_u[pick], w.q_v[pick], threads=16)
+        pick.append(rng.choice(idx, size=min(len(idx), 4000), replace=False))
+    pick = np.unique(np.concatenate(pick))
+    assert len(pick) >= min(10_000, len(ans))
+    truth = big.query_bibfs(w.q_u[pick], w.q_v[pick], threads=THREADS)
     assert np.array_equal(ans[pick] & 1, truth)
-    st = g.stats()
-    assert st["queries"] == len(w.q_u)
+    _say(f"{len(pick)} answers equal a bidirectional BFS without labels")
+    big.close()
+    g.close()

@@ -52,7 +52,7 @@ def test_oracle_and_generator_pins_under_asan_ubsan(tmp_path):
              "assert 'libasan' in maps and 'libubsan' in maps, 'no sanitizer runtime'\n")
     subprocess.run([sys.executable, "-c", probe], cwd=ROOT, env=env, check=True)
     tests = ["tests/test_oracle_paper.py", "tests/test_oracle_brute.py",
-             "tests/test_oracle_scale.py", "tests/test_gen.py"]
+             "tests/test_oracle_scale.py", "tests/test_oracle_big.py", "tests/test_gen.py"]
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         "-m", "not gpu", *tests], cwd=ROOT, env=env, capture_output=True,
                        text=True, timeout=1500)
