@@ -382,37 +382,72 @@ def main():
     def serving():
         """Continuous-batching server on the resident graph: a Poisson stream of query batches
         (1..100k pairs) and insertion batches (1k..10k edges) at 80:20, swept over arrival
-        rates; next to it the same trace replayed one request at a time (batched form, no
-        overlap, no coalescing)."""
-        from paper_2101_09441_amd.serve import Request, latency_summary, serve
+        rates up to saturation; next to it the same trace served one request at a time in
+        sequence order against the same arrival times (no overlap, no coalescing; queueing
+        counts in its latency)."""
+        from paper_2101_09441_amd.serve import Request, serve, serve_alone
         res = {}
-        n_req = 300
-        for rate in (500.0, 2000.0, 8000.0):
+        n_req = 1200
+        for rate in (2000.0, 8000.0, 32000.0, 128000.0, 512000.0):
             spec = dblgen.serving_trace(w.q_u, w.q_v, w.ins_src, w.ins_dst, n_req, rate, seed=5)
             trace = [Request(s_, k, a, b, t) for s_, k, a, b, t in spec]
             ix = dbl.Index.build(w.n, src, dst, edges_unique=True)
             summ = serve(ix, trace, workers=4, max_batch=1 << 17, bfs_slots=256)
             ix.close()
-            # the same trace, each request alone in sequence order
             ix = dbl.Index.build(w.n, src, dst, edges_unique=True)
-            seq = [Request(s_, k, a, b, t) for s_, k, a, b, t in spec]
-            same = True
-            t0 = time.perf_counter()
-            for r, m in zip(seq, trace):
-                tb = time.perf_counter()
-                if r.kind == "query":
-                    r.answers = ix.query(dbl.to_device_ids(r.a), dbl.to_device_ids(r.b)).cpu().numpy()
-                    same &= bool(np.array_equal(r.answers, m.answers))
-                else:
-                    ix.insert_edges(dbl.to_device_ids(r.a), dbl.to_device_ids(r.b))
-                r.arrival, r.done = tb - t0, time.perf_counter() - t0
-            seq_summ = latency_summary(seq, time.perf_counter() - t0)
+            alone = [Request(s_, k, a, b, t) for s_, k, a, b, t in spec]
+            alone_summ = serve_alone(ix, alone)
             ix.close()
-            res[f"rate_{int(rate)}_per_s"] = {"serving": summ, "one_at_a_time": seq_summ,
-                                              "answers_equal_alone": same}
-            log(f"serving rate {rate}: queries/s {summ['query']['per_s']:.3g}, "
-                f"query p99 {summ['query']['latency_ms_p99']:.2f} ms, equal {same}")
+            same = all(r.kind != "query" or np.array_equal(r.answers, m.answers)
+                       for r, m in zip(alone, trace))
+            res[f"rate_{int(rate)}_per_s"] = {"serving": summ, "one_at_a_time": alone_summ,
+                                              "answers_equal_alone": bool(same)}
+            log(f"serving rate {rate}: queries/s {summ['query']['per_s']:.3g} "
+                f"(alone {alone_summ['query']['per_s']:.3g}), query p99 "
+                f"{summ['query']['latency_ms_p99']:.2f} ms (alone "
+                f"{alone_summ['query']['latency_ms_p99']:.2f}), equal {same}")
         return res
+
+    def table4(plain_answers):
+        """The shape of the paper's Table 4 on this workload: the 1,000,000 queries answered
+        with DL only, BL only and both (DBL), on the index after the plain form's insertions;
+        the share each decides by labels alone, its class histogram and its batch time. The
+        answers are exact in every mode."""
+        ix = dbl.Index.build(w.n, src, dst, edges_unique=True)
+        ix.insert_edges(isrc, idst)
+        res = {}
+        for name, rules in (("DL", 1), ("BL", 2), ("DBL", 3)):
+            o = torch.empty_like(out)
+            ix.query_rules(qu, qv, rules, out=o)  # warm
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ix.query_rules(qu, qv, rules, out=o)
+            dt = time.perf_counter() - t0
+            a = o.cpu().numpy()
+            cls = np.bincount(a >> 1, minlength=7)
+            res[name] = {"label_decided_frac": float(cls[:5].sum() / n_q),
+                         "class_histogram": {dbl.CLASS_NAMES[i]: int(cls[i]) for i in range(7)},
+                         "batch_ms": dt * 1e3,
+                         "answers_equal_plain": bool(np.array_equal(a & 1, plain_answers & 1))}
+        ix.close()
+        return res
+
+    def server_warm_off(plain_labels):
+        """The single-edge requests through the request server without its cache warm-up."""
+        ix = dbl.Index.build(w.n, src, dst, edges_unique=True)
+        ix.set_tuning(server_warm=0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat2 = ix.insert_edges_each(isrc, idst, latencies=True)
+        dt = time.perf_counter() - t0
+        st = ix.stats()
+        same = all(torch.equal(a, b) for a, b in zip(ix.labels(), plain_labels))
+        ix.close()
+        return {"edges_per_s": n_ins / dt,
+                "latency_us_p50": float(np.percentile(lat2, 50)),
+                "latency_us_p99": float(np.percentile(lat2, 99)),
+                "device_us_per_request": st["server_busy_us"] / max(st["server_requests"], 1),
+                "labels_equal_server": bool(same)}
 
     def batched(plain_labels, plain_answers):
         """The batched form on the same inputs: insertion batches of 1k/10k/100k edges and query
@@ -421,12 +456,8 @@ def main():
         res = {}
         qb = 65536
         mk = lambda: dbl.Index.build(w.n, src, dst, edges_unique=True)  # noqa: E731
-        for bsz in (1000, 10000, 100000):
-            if bsz > n_ins:
-                continue
-            tuned = autotune.tune_insertions(mk, isrc, idst, bsz, w.m, max_batches=10)
-            ix = mk()
-            ix.set_tuning(**{k: tuned[k] for k in autotune.INSERT_KNOBS})
+        def insert_stream(ix, bsz):
+            """Insert the whole stream in batches of bsz on ix; the timing entry."""
             torch.cuda.synchronize()
             times = []
             t0 = time.perf_counter()
@@ -436,12 +467,24 @@ def main():
                 times.append(time.perf_counter() - tb)
             t_ins = time.perf_counter() - t0
             same = all(torch.equal(a, b) for a, b in zip(ix.labels(), plain_labels))
-            entry = {"edges_per_s": n_ins / t_ins, "batches": len(times),
-                     "batch_ms_p50": float(np.percentile(times, 50) * 1e3),
-                     "batch_ms_p99": float(np.percentile(times, 99) * 1e3),
-                     "speedup_vs_plain": (n_ins / t_ins) / (n_ins / insert_s),
-                     "labels_equal_plain": bool(same),
-                     "tuning": {k: tuned[k] for k in autotune.INSERT_KNOBS}}
+            return {"edges_per_s": n_ins / t_ins, "batches": len(times),
+                    "batch_ms_p50": float(np.percentile(times, 50) * 1e3),
+                    "batch_ms_p99": float(np.percentile(times, 99) * 1e3),
+                    "speedup_vs_plain": (n_ins / t_ins) / (n_ins / insert_s),
+                    "labels_equal_plain": bool(same), "batch_stalls": ix.stats()["batch_stalls"]}
+
+        # the three forms of an insertion batch above the single-workgroup limit, default knobs
+        forms = {"multi_launch": dict(insert_persistent=0),
+                 "persistent": dict(insert_persistent=1, insert_graph=0),
+                 "persistent_graph": dict(insert_persistent=1, insert_graph=1)}
+        for bsz in (1000, 10000, 100000):
+            if bsz > n_ins:
+                continue
+            tuned = autotune.tune_insertions(mk, isrc, idst, bsz, w.m, max_batches=10)
+            ix = mk()
+            ix.set_tuning(**{k: tuned[k] for k in autotune.INSERT_KNOBS})
+            entry = insert_stream(ix, bsz)
+            entry["tuning"] = {k: tuned[k] for k in autotune.INSERT_KNOBS}
             if bsz == 1000:
                 qtuned = autotune.tune_queries(ix, qu, qv, qb, w.m)
                 # each batch as two kernel launches, then as one graph launch (the graph is
@@ -465,8 +508,14 @@ def main():
                         "answers_equal_plain": bool(torch.equal(qout, plain_answers)),
                         "tuning": {"bfs_slots": qtuned["bfs_slots"], "query_graph": graph}}
                 ix.set_tuning(query_graph=0)
-            res[f"insert_batch_{bsz}"] = entry
             ix.close()
+            entry["forms"] = {}
+            for name, kw in forms.items():
+                fx = mk()
+                fx.set_tuning(small_batch=min(bsz - 1, 2048), **kw)
+                entry["forms"][name] = insert_stream(fx, bsz)
+                fx.close()
+            res[f"insert_batch_{bsz}"] = entry
         return res
 
     for i in range(args.warmup):
@@ -494,6 +543,8 @@ def main():
     s_build, s_ins, s_q, plain_labels = diagnostics()
     extras = args.extras == "on"
     per_request = launch_per_request(plain_labels) if extras else None
+    warm_off = server_warm_off(plain_labels) if extras else None
+    table4_res = table4(out.cpu().numpy()) if extras else None
     batched_res = batched(plain_labels, out.clone()) if extras else None
     serving_res = (serving() if extras and args.workload == "lj" and args.serving == "on"
                    else None)
@@ -601,6 +652,8 @@ def main():
                         "bfs_edges": s_q["bfs_edges"], "bfs_vertices": s_q["bfs_vertices"]},
         "insert_device_us_per_request": per_request_device_us,
         "insert_launch_per_request": per_request,
+        "insert_server_warm_off": warm_off,
+        "table4_shape": table4_res,
         "batched": batched_res,
         "serving": serving_res,
         "roofline": roofline,

@@ -123,6 +123,8 @@ typedef struct {
   uint64_t server_requests;   /* requests served by the request server (dbl_insert_edges_each) */
   double server_busy_us;      /* device time it spent on them, from seeing a request to
                                  publishing its status (device wall clock) */
+  uint64_t batch_stalls;      /* persistent insertion launches that ran out of time at a grid
+                                 barrier and were finished another way (dbl_tuning) */
 } dbl_stats;
 
 /* Fill *opt with the defaults listed above. */
@@ -267,7 +269,8 @@ typedef struct {
    off), optionally followed by ":N" to time one launch in every N of each kind (the first, the
    N+1-th, ...). Enabling clears the accumulated times. Kinds: insert_small, insert_apply, local_rounds,
    insert_server (one request-server launch), round (one grid propagation round), query_label,
-   query_bfs, query_graph (one graph launch of a query batch). */
+   query_bfs, query_graph (one graph launch of a query batch), insert_batch (one persistent
+   launch of an insertion batch, or its graph launch). */
 dbl_status dbl_time_kernels(dbl_index *ix, const char *kinds);
 
 /* Copy up to `cap` per-kind records (kinds with at least one launch) to HOST array h_out;
@@ -307,6 +310,26 @@ typedef struct {
                                   neighbour instead of testing which ones are in the frontier (a
                                   neighbour outside it adds no bit); 0 = always test (default
                                   512) */
+  uint32_t insert_persistent;  /* 1 (default): an insertion batch above small_batch runs in one
+                                  persistent launch (one workgroup per compute unit): validation,
+                                  appends and seeds, and the propagation rounds separated by grid
+                                  barriers; 0: several launches, rounds driven by the host */
+  uint32_t insert_graph;       /* 1: that launch is the replay of a one-node HIP graph
+                                  instantiated once per index and given each batch's arguments;
+                                  0 (default): a plain launch */
+  uint32_t batch_max_frontier; /* the persistent launch leaves a frontier of more entries than
+                                  this to the host's direction-optimised rounds (default 131072;
+                                  at least 1) */
+  uint32_t gather_wait_us;     /* the persistent launch first waits until all its workgroups are
+                                  resident, at most this long (default 20000, at most 10^7); if
+                                  they are not, nothing has changed and the batch runs in several
+                                  launches instead */
+  uint32_t barrier_wait_us;    /* longest wait at one of its later grid barriers (default
+                                  2000000, at most 10^8); past it the launch stops and the host
+                                  re-propagates from every vertex (the result is the same) */
+  uint32_t batch_grid;         /* workgroups of the persistent launch (0 = one per compute unit,
+                                  the default; at most 2048). More than fit on the device at once
+                                  never gather: such a launch gives up after gather_wait_us */
 } dbl_tuning;
 
 dbl_status dbl_get_tuning(const dbl_index *ix, dbl_tuning *out);

@@ -1,8 +1,9 @@
 """Autotuner for the batched form: picks the runtime tuning of an index by measurement.
 
 Insertion knobs (the single-workgroup batch limit and the local-round limits, the grid-round
-block count, the pull threshold of grid rounds) are timed on fresh indexes built from the same graph, because insertions change
-the index; query knobs (BFS slots) are timed on the index itself, because queries do not. The
+block count, the pull threshold of grid rounds, the persistent one-launch form and its graph
+replay) are timed on fresh indexes built from the same graph, because insertions change the
+index; query knobs (BFS slots) are timed on the index itself, because queries do not. The
 choice is cached per (device, graph size, phase, batch size) in a JSON file. No knob can change
 a label or an answer, only the time they take.
 """
@@ -15,16 +16,24 @@ from typing import Callable, Dict, List, Optional
 
 import torch
 
+# the multi-launch form (host-driven rounds) over its knobs, then the persistent form (one launch
+# per batch above small_batch, plain or as a graph replay) over the knobs that reach it
 INSERT_CANDIDATES: List[dict] = [
     dict(small_batch=sb, local_max_frontier=lf, local_max_edges=le, round_grid=rg,
-         pull_threshold=pt)
+         pull_threshold=pt, insert_persistent=0, insert_graph=0)
     for sb in (256, 2048, 16384)
     for lf, le in ((8192, 1 << 16), (32768, 1 << 18))
     for rg in (1024, 2048)
     for pt in (0, 128)
+] + [
+    dict(small_batch=sb, local_max_frontier=lf, local_max_edges=le, round_grid=2048,
+         pull_threshold=128, insert_persistent=1, insert_graph=gr)
+    for sb in (0, 256, 2048)
+    for lf, le in ((8192, 1 << 16), (32768, 1 << 18))
+    for gr in (0, 1)
 ]
 INSERT_KNOBS = ("small_batch", "local_max_frontier", "local_max_edges", "round_grid",
-                "pull_threshold")
+                "pull_threshold", "insert_persistent", "insert_graph")
 QUERY_CANDIDATES: List[dict] = [dict(bfs_slots=s) for s in (256, 512, 1024, 2048)]
 
 

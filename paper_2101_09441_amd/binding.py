@@ -71,6 +71,7 @@ class DblStats(ctypes.Structure):
         ("pull_rounds", ctypes.c_uint64),
         ("server_requests", ctypes.c_uint64),
         ("server_busy_us", ctypes.c_double),
+        ("batch_stalls", ctypes.c_uint64),
     ]
 
 
@@ -88,6 +89,12 @@ class DblTuning(ctypes.Structure):
         ("query_graph", ctypes.c_uint32),
         ("server_warm", ctypes.c_uint32),
         ("pull_all_threshold", ctypes.c_uint32),
+        ("insert_persistent", ctypes.c_uint32),
+        ("insert_graph", ctypes.c_uint32),
+        ("batch_max_frontier", ctypes.c_uint32),
+        ("gather_wait_us", ctypes.c_uint32),
+        ("barrier_wait_us", ctypes.c_uint32),
+        ("batch_grid", ctypes.c_uint32),
     ]
 
 
@@ -494,7 +501,8 @@ class Index:
     def set_tuning(self, **kw) -> None:
         """Change tuning fields (small_batch, local_max_frontier, local_max_edges, round_grid,
         bfs_slots, insert_server, server_idle_us, pull_threshold, server_polls, query_graph,
-        server_warm, pull_all_threshold); results never change."""
+        server_warm, pull_all_threshold, insert_persistent, insert_graph, batch_max_frontier,
+        gather_wait_us, barrier_wait_us, batch_grid); results never change."""
         cur = self.tuning()
         bad = set(kw) - set(cur)
         if bad:

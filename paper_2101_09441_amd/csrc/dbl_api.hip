@@ -93,6 +93,19 @@ struct dbl_index {
   uint32_t pull_all_threshold = 512;  // ... and skip the frontier test above this/1024
   uint32_t query_graph = 0;       // query batches as one graph launch
   uint32_t server_warm = 1;       // read the labels and row descriptors before serving
+  uint32_t insert_persistent = 1;  // batches above small_batch in one persistent launch
+  uint32_t insert_graph = 0;       // ... launched as a replayed one-node graph
+  uint32_t batch_max_frontier = 1u << 17;  // larger frontiers go to the host's rounds
+  uint32_t gather_wait_us = 20000;        // persistent launch: longest wait for all blocks
+  uint32_t barrier_wait_us = 2000000;     // ... and at one later grid barrier
+  uint32_t batch_grid_opt = 0;            // its blocks (0 = one per compute unit)
+  // persistent insertion kernel: launch shape (0 = not yet queried) and its graph
+  uint32_t batch_grid = 0, batch_grid_words = 0;
+  hipGraph_t igraph = nullptr;
+  hipGraphExec_t igexec = nullptr;
+  hipGraphNode_t ig_node = nullptr;
+  uint32_t ig_words = 0, ig_grid = 0;
+  uint64_t batch_stalls_early = 0, batch_stalls_late = 0;
   // query contexts: the default one and those created by callers (guarded by ctx_mu)
   uint32_t slots_opt = 0, qcap_opt = 0;
   dbl_query_ctx *qctx = nullptr;
@@ -126,11 +139,13 @@ enum TimedKind : uint32_t {
   kTQueryLabel,
   kTQueryBfs,
   kTQueryGraph,
+  kTInsertBatch,
   kTKinds
 };
 const char *const kKindNames[kTKinds] = {"insert_small", "insert_apply", "local_rounds",
                                          "insert_server", "round",
-                                         "query_label", "query_bfs", "query_graph"};
+                                         "query_label", "query_bfs", "query_graph",
+                                         "insert_batch"};
 
 hipEvent_t take_event(dbl_index *ix) {
   if (!ix->spare.empty()) {
@@ -610,6 +625,86 @@ dbl_status finish_insert(dbl_index *ix, hipStream_t s, uint64_t *rounds) {
     CKS(wait_status(ix, s, seq));
   }
   return grid_propagate(ix, s, 2, rounds, true);
+}
+
+// One batch in one persistent launch (k_insert_batch), directly or as the replay of a one-node
+// graph instantiated on first use and given each batch's arguments. Waits for its status.
+dbl_status insert_persistent(dbl_index *ix, uint64_t count, const uint32_t *d_src,
+                             const uint32_t *d_dst, hipStream_t s, uint32_t seq) {
+  if (ix->batch_grid_words != ix->lw) {
+    dbl::BatchLaunch bl;
+    CK(dbl::insert_batch_grid(ix->lw, &bl));
+    ix->batch_grid = bl.grid;
+    ix->batch_grid_words = ix->lw;
+  }
+  const uint32_t grid = ix->batch_grid_opt ? ix->batch_grid_opt : ix->batch_grid;
+  dbl::PropArgs a = prop_args(ix);
+  uint32_t n = ix->n, maxf = ix->batch_max_frontier, sq = seq;
+  Ovf *ovf = ix->ovf;
+  uint64_t ovf_cap = ix->ovf_cap;
+  dbl::Mirror *m = ix->mirror;
+  u64 start_ticks = ix->clock_khz * ix->gather_wait_us / 1000;
+  u64 wait_ticks = ix->clock_khz * ix->barrier_wait_us / 1000;
+  if (ix->insert_graph) {
+    void *args[12] = {(void *)&a, (void *)&d_src, (void *)&d_dst, (void *)&count, (void *)&n,
+                      (void *)&ovf, (void *)&ovf_cap, (void *)&m, (void *)&sq, (void *)&maxf,
+                      (void *)&start_ticks, (void *)&wait_ticks};
+    hipKernelNodeParams p;
+    CK(dbl::insert_batch_node_params(ix->lw, grid, args, &p));
+    if (!ix->igexec || ix->ig_words != ix->lw || ix->ig_grid != grid) {
+      if (ix->igexec) (void)hipGraphExecDestroy(ix->igexec);
+      if (ix->igraph) (void)hipGraphDestroy(ix->igraph);
+      ix->igexec = nullptr;
+      ix->igraph = nullptr;
+      CK(hipGraphCreate(&ix->igraph, 0));
+      CK(hipGraphAddKernelNode(&ix->ig_node, ix->igraph, nullptr, 0, &p));
+      CK(hipGraphInstantiate(&ix->igexec, ix->igraph, nullptr, nullptr, 0));
+      ix->ig_words = ix->lw;
+      ix->ig_grid = grid;
+    } else {
+      CK(hipGraphExecKernelNodeSetParams(ix->igexec, ix->ig_node, &p));
+    }
+    Timed tm(ix, kTInsertBatch, s);
+    CK(hipGraphLaunch(ix->igexec, s));
+  } else {
+    Timed tm(ix, kTInsertBatch, s);
+    CK(dbl::launch_insert_batch(a, d_src, d_dst, count, n, ovf, ovf_cap, m, seq, maxf,
+                                start_ticks, wait_ticks, grid, s));
+  }
+  uint32_t flags = 0;
+  return wait_fast(ix, s, seq, &flags);
+}
+
+// The multi-launch form of a batch above small_batch: validation, the appends and seeds, then
+// single-workgroup rounds; waits for the status.
+dbl_status insert_launches(dbl_index *ix, uint64_t count, const uint32_t *d_src,
+                           const uint32_t *d_dst, hipStream_t s, uint32_t seq) {
+  dbl::PropArgs a = prop_args(ix);
+  CK(dbl::launch_validate_pairs(d_src, d_dst, count, ix->n, ix->ctl, s));
+  {
+    Timed tm(ix, kTInsertApply, s);
+    CK(dbl::launch_insert_apply(a, d_src, d_dst, count, ix->ovf, ix->ovf_cap, s));
+  }
+  {
+    Timed tm(ix, kTLocalRounds, s);
+    CK(dbl::launch_local_rounds(a, ix->mirror, seq, s));
+  }
+  return wait_status(ix, s, seq);
+}
+
+// After a persistent launch stalled past its gathering (every append and seed is done, the
+// rounds stopped somewhere): restart propagation from every vertex that has a label bit and an
+// edge. The labels only grow toward the least fixpoint, so rounds from there reach it.
+dbl_status repropagate_all(dbl_index *ix, hipStream_t s) {
+  // fresh claim stamps: whatever the stopped rounds claimed is forgotten
+  const uint32_t stamp = 1u;
+  CK(dbl::launch_fill_u32(ix->inq, 0u, 2ull * ix->n, s));
+  CKS(set_ctl_u32(ix, offsetof(Ctl, cur), 0u, s));
+  CKS(set_ctl_u32(ix, offsetof(Ctl, stamp), stamp, s));
+  for (int i = 0; i < 3; i++) CKS(set_ctl_u32(ix, offsetof(Ctl, fsize) + 4 * i, 0u, s));
+  CK(dbl::launch_init_frontier({ix->lab, ix->lw}, ix->n, ix->f, ix->r, ix->fq[0], ix->ctl,
+                               ix->inq, stamp, s));
+  return sync_ctl(ix, s);
 }
 
 uint32_t bits_of(uint32_t kp) {
@@ -1485,6 +1580,7 @@ dbl_status dbl_insert_edges(dbl_index *ix, uint64_t count, const uint32_t *d_src
   }
   dbl::PropArgs a = prop_args(ix);
   const uint32_t seq = ++ix->seq;
+  bool late_stall = false;
   if (count <= ix->small_batch) {
     {
       Timed tm(ix, kTInsertSmall, s);
@@ -1493,18 +1589,24 @@ dbl_status dbl_insert_edges(dbl_index *ix, uint64_t count, const uint32_t *d_src
     }
     uint32_t flags = 0;
     CKS(wait_fast(ix, s, seq, &flags));
+  } else if (ix->insert_persistent) {
+    CKS(insert_persistent(ix, count, d_src, d_dst, s, seq));
+    if (ix->hs.err & dbl::kErrStallEarly) {
+      // not every block became resident in time, and nothing was changed: the same batch in
+      // several launches instead
+      ix->batch_stalls_early++;
+      CKS(set_ctl_u32(ix, offsetof(Ctl, err), 0u, s));
+      CKS(insert_launches(ix, count, d_src, d_dst, s, ++ix->seq));
+    } else if (ix->hs.err & dbl::kErrStallLate) {
+      ix->batch_stalls_late++;
+      CKS(set_ctl_u32(ix, offsetof(Ctl, err), 0u, s));
+      ix->hs.err = 0;
+      late_stall = true;
+    }
   } else {
-    CK(dbl::launch_validate_pairs(d_src, d_dst, count, ix->n, ix->ctl, s));
-    {
-      Timed tm(ix, kTInsertApply, s);
-      CK(dbl::launch_insert_apply(a, d_src, d_dst, count, ix->ovf, ix->ovf_cap, s));
-    }
-    {
-      Timed tm(ix, kTLocalRounds, s);
-      CK(dbl::launch_local_rounds(a, ix->mirror, seq, s));
-    }
-    CKS(wait_status(ix, s, seq));
+    CKS(insert_launches(ix, count, d_src, d_dst, s, seq));
   }
+  if (late_stall) CKS(repropagate_all(ix, s));
   if (ix->hs.err) {
     CKS(set_ctl_u32(ix, offsetof(Ctl, err), 0u, s));
     CK(hipStreamSynchronize(s));
@@ -1704,6 +1806,7 @@ dbl_status dbl_get_stats(const dbl_index *ix_c, dbl_stats *out) {
   out->server_requests = sc[1];
   out->pull_rounds = ix->pull_rounds;
   out->server_busy_us = (double)sc[0] * 1000.0 / (double)ix->clock_khz;
+  out->batch_stalls = ix->batch_stalls_early + ix->batch_stalls_late;
   return DBL_OK;
 }
 
@@ -1828,6 +1931,12 @@ dbl_status dbl_get_tuning(const dbl_index *ix, dbl_tuning *out) {
   out->server_polls = ix->server_polls;
   out->query_graph = ix->query_graph;
   out->server_warm = ix->server_warm;
+  out->insert_persistent = ix->insert_persistent;
+  out->insert_graph = ix->insert_graph;
+  out->batch_max_frontier = ix->batch_max_frontier;
+  out->gather_wait_us = ix->gather_wait_us;
+  out->barrier_wait_us = ix->barrier_wait_us;
+  out->batch_grid = ix->batch_grid_opt;
   out->bfs_slots = ix->qctx ? ix->qctx->slots : (ix->slots_opt ? ix->slots_opt : 1024);
   return DBL_OK;
 }
@@ -1839,7 +1948,9 @@ dbl_status dbl_set_tuning(dbl_index *ix, const dbl_tuning *t) {
       t->server_idle_us > 10000000 || t->pull_threshold > 1u << 20 ||
       t->pull_all_threshold > 1u << 20 ||
       (t->server_polls != 1 && t->server_polls != 4) || t->query_graph > 1 ||
-      t->server_warm > 1)
+      t->server_warm > 1 || t->insert_persistent > 1 || t->insert_graph > 1 ||
+      t->batch_max_frontier == 0 || t->gather_wait_us > 10000000 ||
+      t->barrier_wait_us > 100000000 || t->batch_grid > dbl::kRoundGridMax)
     return DBL_ERR_INVALID_ARG;
   DeviceGuard dg(ix->device);
   ix->small_batch = t->small_batch;
@@ -1853,6 +1964,12 @@ dbl_status dbl_set_tuning(dbl_index *ix, const dbl_tuning *t) {
   ix->server_polls = t->server_polls;
   ix->query_graph = t->query_graph;
   ix->server_warm = t->server_warm;
+  ix->insert_persistent = t->insert_persistent;
+  ix->insert_graph = t->insert_graph;
+  ix->batch_max_frontier = t->batch_max_frontier;
+  ix->gather_wait_us = t->gather_wait_us;
+  ix->barrier_wait_us = t->barrier_wait_us;
+  ix->batch_grid_opt = t->batch_grid;
   const uint32_t slots = t->bfs_slots ? std::max<uint32_t>(4, (t->bfs_slots + 3) / 4 * 4) : 0;
   if (slots && (!ix->qctx || ix->qctx->slots != slots)) {
     // rebuild the index's own query context with the new slot count (its counters are kept)
@@ -1925,6 +2042,8 @@ void dbl_destroy(dbl_index *ix) {
   dfree(ix->ctl);
   hfree(ix->mirror);
   hfree(ix->door);
+  if (ix->igexec) (void)hipGraphExecDestroy(ix->igexec);
+  if (ix->igraph) (void)hipGraphDestroy(ix->igraph);
   dfree(ix->pcnt);
   dfree(ix->ovf);
   dfree(ix->landmarks_d);

@@ -30,6 +30,9 @@ constexpr uint32_t kSmallBatch = 2048;
 constexpr uint32_t kSmallBatchMax = 1u << 16;
 
 constexpr uint32_t kErrRange = 1u;
+// A grid barrier of the persistent insertion kernel ran out of time: before anything was
+// changed (the host runs the batch another way) or after (the host re-propagates every label).
+constexpr uint32_t kErrStallEarly = 2u, kErrStallLate = 4u;
 
 // One direction of the adjacency: row x holds entries col[off[x] .. off[x] + min(deg, cap)).
 // deg may exceed cap after an append found the row full; the overflowing entries wait in the
@@ -65,6 +68,13 @@ struct Ctl {
   uint32_t local_rounds;
   uint32_t bfs_done;    // BFS blocks finished (the last one publishes the status)
   uint32_t pheavy;      // chunks of high-degree rows queued for the pull round
+  uint32_t bar_gather;  // persistent insertion kernel: blocks gathered at its start,
+  uint32_t bar_count;   // arrivals at the current grid barrier,
+  uint32_t bar_gen;     // the barrier's generation,
+  uint32_t bar_done;    // and blocks that have finished (the last one publishes);
+  uint32_t local_stop;  // 1: its last single-workgroup pass stopped on its round budget
+  uint32_t snap[4];     // {cur, stamp, fsize[cur], local_stop} as of the last barrier
+  uint32_t pad0[3];
   unsigned long long ctr[kCtrCount];
 };
 
@@ -238,6 +248,26 @@ hipError_t launch_insert_server(const PropArgs &a, uint32_t first, uint32_t coun
                                 unsigned long long idle_ticks, uint32_t polls, hipStream_t s);
 hipError_t launch_insert_apply(const PropArgs &a, const uint32_t *src, const uint32_t *dst,
                                uint64_t count, Ovf *ovf, uint64_t ovf_cap, hipStream_t s);
+// One insertion batch in one persistent launch (see k_insert_batch): validation, the appends and
+// seeds, and the propagation rounds, separated by grid barriers; publishes the fast status word
+// {seq, flags} to m. grid: blocks of kLocalThreads threads, all of which must fit on the device
+// at once (insert_batch_grid). max_frontier: a frontier larger than this is left pending for the
+// host's rounds. start_ticks / wait_ticks: the longest wait at the first two barriers / at any
+// later one, in device wall-clock ticks.
+struct BatchLaunch {
+  const void *func;   // kernel for the label width
+  uint32_t grid;
+};
+hipError_t insert_batch_grid(uint32_t words, BatchLaunch *out);
+hipError_t launch_insert_batch(const PropArgs &a, const uint32_t *src, const uint32_t *dst,
+                               uint64_t count, uint32_t n, Ovf *ovf, uint64_t ovf_cap, Mirror *m,
+                               uint32_t seq, uint32_t max_frontier,
+                               unsigned long long start_ticks, unsigned long long wait_ticks,
+                               uint32_t grid, hipStream_t s);
+// Kernel-node parameters of the same launch, for a graph; args points to its 12 arguments in
+// order (a, src, dst, count, n, ovf, ovf_cap, m, seq, max_frontier, start_ticks, wait_ticks).
+hipError_t insert_batch_node_params(uint32_t words, uint32_t grid, void **args,
+                                    hipKernelNodeParams *p);
 hipError_t launch_regrow_copy(Csr old_g, Csr new_g, uint32_t n, hipStream_t s);
 hipError_t launch_place_overflow(const Ovf *ovf, uint32_t count, uint32_t dir, Csr new_g,
                                  hipStream_t s);

@@ -1684,22 +1684,38 @@ hipError_t launch_pull(const PropArgs &a, uint32_t n, uint32_t dmask, uint32_t a
 // Rounds inside one workgroup while the frontier is small (no kernel launch per round). Reads
 // the pending frontier from ctl->cur / ctl->stamp and writes back where it stopped: either the
 // frontier is empty, or it outgrew the local bounds and grid rounds take over.
+// LDS of one kLocalThreads-wide workgroup expanding frontier tiles.
 template <int W>
-__device__ void local_rounds_body(const PropArgs &a) {
-  __shared__ uint32_t s_start[kLocalThreads];
-  __shared__ u64 s_off[kLocalThreads];
-  __shared__ Half<W> s_lab[kLocalThreads];
-  __shared__ uint32_t s_ent[kLocalThreads];
-  __shared__ uint32_t s_wsum[kLocalThreads / 64];
-  __shared__ uint32_t s_edges;
+struct TileLds {
+  uint32_t start[kLocalThreads];
+  u64 off[kLocalThreads];
+  Half<W> lab[kLocalThreads];
+  uint32_t ent[kLocalThreads];
+  uint32_t wsum[kLocalThreads / 64];
+  uint32_t edges;
+};
+
+// Returns true when it stopped only because it had run max_rounds rounds.
+template <int W>
+__device__ bool local_rounds_core(const PropArgs &a, TileLds<W> &sm,
+                                  uint32_t max_rounds = 0xFFFFFFFFu) {
+  uint32_t *s_start = sm.start, *s_ent = sm.ent, *s_wsum = sm.wsum;
+  u64 *s_off = sm.off;
+  Half<W> *s_lab = sm.lab;
+  uint32_t &s_edges = sm.edges;
   Ctl *ctl = a.ctl;
   const uint32_t t = threadIdx.x;
   uint32_t ring = ld_agent32(&ctl->cur), stamp = ld_agent32(&ctl->stamp);
   u64 relaxed = 0, expanded = 0;
   uint32_t rounds = 0;
+  bool budget = false;
   for (;;) {
     const uint32_t fsz = ld_agent32(&ctl->fsize[ring]);
     if (fsz == 0 || fsz > a.local_max_frontier) break;
+    if (rounds == max_rounds) {
+      budget = true;
+      break;
+    }
     uint32_t my = 0;
     const uint32_t *fq = a.fq[ring];
     for (uint32_t i = t; i < fsz; i += kLocalThreads) {
@@ -1740,6 +1756,13 @@ __device__ void local_rounds_body(const PropArgs &a) {
       a.pcnt[2 * (kRoundGridMax + kHeavyGrid) + 1] += relaxed;
     }
   }
+  return budget;
+}
+
+template <int W>
+__device__ void local_rounds_body(const PropArgs &a) {
+  __shared__ TileLds<W> sm;
+  local_rounds_core<W>(a, sm);
 }
 
 template <int W>
@@ -2100,6 +2123,320 @@ hipError_t launch_insert_apply(const PropArgs &a, const uint32_t *src, const uin
   DBL_LAUNCH_W(a.L.words, k_insert_apply, dim3(grid_for(2 * count, 256, 4096)), dim3(256), s, a,
                src, dst, count, ovf, ovf_cap);
   return hipGetLastError();
+}
+
+// ---- one insertion batch in one persistent launch
+//
+// Every block of the launch stays resident from the first barrier to its exit, and the phases
+// of Algorithm 3 for a whole batch follow each other inside the launch: validation of every id,
+// the appends and seeds of every edge (both halves), then the propagation rounds until the
+// frontier is empty. Rounds whose frontier fits one workgroup run in block 0 alone (no barrier
+// per round); larger ones are expanded by every block, with high-degree rows split into chunks
+// handled after a barrier. A frontier above max_frontier is left for the host's
+// direction-optimised rounds.
+//
+// Before anything is modified, every block validates its share of the ids and then waits,
+// bounded, until every block of the launch is resident (grid_gather). That wait ends the same
+// way for every block: either all arrived, or one block, having waited too long, cancels the
+// gathering before the last arrival, and then no block modifies anything (kErrStallEarly: the
+// host runs the batch without this kernel). Once gathered, the blocks stay resident until they
+// exit, so the later grid barriers (grid_barrier) only wait for the slowest block's share of a
+// phase; their waits are bounded too, and a wait that runs out (kErrStallLate; it would take a
+// share of seconds) leaves every block to finish its current phase and leave at its next
+// barrier, after which the host re-propagates from every vertex. No wait is unbounded,
+// whatever the occupancy.
+//
+// Every decision the blocks take after a barrier (where the frontier is, how large it is, how
+// the last single-workgroup pass ended) comes from a snapshot that the last block to arrive
+// takes while every other block is still waiting, so all blocks decide alike even when block 0
+// has already moved on and changed those fields again.
+
+constexpr uint32_t kGatherCancel = 0x80000000u;
+constexpr uint32_t kBatchLocalRounds = 1024;
+
+__device__ bool grid_gather(Ctl *ctl, uint32_t nblocks, u64 limit) {
+  __shared__ uint32_t s_ok;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    uint32_t c = __hip_atomic_fetch_add(&ctl->bar_gather, 1u, __ATOMIC_ACQ_REL,
+                                        __HIP_MEMORY_SCOPE_AGENT) + 1u;
+    const u64 t0 = wall_clock64();
+    u64 spins = 0;
+    while (c < nblocks) {  // c has the cancel bit once cancelled, which ends the loop too
+      // past the time limit (or, should the clock stand still, as many polls as ticks)
+      if (wall_clock64() - t0 > limit || ++spins > limit) {
+        // cancel, unless the last block arrives first
+        const uint32_t seen = atomicCAS(&ctl->bar_gather, c, c | kGatherCancel);
+        if (seen == c) {
+          atomicOr(&ctl->err, kErrStallEarly);
+          c |= kGatherCancel;
+        } else {
+          c = seen;
+        }
+        continue;
+      }
+      __builtin_amdgcn_s_sleep(2);
+      c = __hip_atomic_load(&ctl->bar_gather, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    // every block's range check was made visible before its arrival
+    s_ok = c == nblocks && !(ld_agent32(&ctl->err) & kErrRange);
+  }
+  __syncthreads();
+  return s_ok != 0u;
+}
+
+struct Snap {
+  uint32_t cur, stamp, fsz, local_stop;
+};
+
+__device__ bool grid_barrier(Ctl *ctl, uint32_t nblocks, u64 limit, uint32_t stall_bit,
+                             Snap *snap) {
+  __shared__ uint32_t s_ok;
+  __shared__ Snap s_snap;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t ok = 1;
+    const uint32_t gen =
+        __hip_atomic_load(&ctl->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const uint32_t arrived = __hip_atomic_fetch_add(&ctl->bar_count, 1u, __ATOMIC_ACQ_REL,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+    if (arrived == nblocks - 1u) {
+      // every block has finished the phase: its results are final until the next barrier
+      const uint32_t cur = ld_agent32(&ctl->cur);
+      st_agent32(&ctl->snap[0], cur);
+      st_agent32(&ctl->snap[1], ld_agent32(&ctl->stamp));
+      st_agent32(&ctl->snap[2], ld_agent32(&ctl->fsize[cur]));
+      st_agent32(&ctl->snap[3], ld_agent32(&ctl->local_stop));
+      __hip_atomic_store(&ctl->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&ctl->bar_gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      const u64 t0 = wall_clock64();
+      u64 spins = 0;
+      while (__hip_atomic_load(&ctl->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+        if (__hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
+            (kErrStallEarly | kErrStallLate)) {
+          ok = 0;
+          break;
+        }
+        if (wall_clock64() - t0 > limit || ++spins > limit) {
+          atomicOr(&ctl->err, stall_bit);
+          ok = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (ok && __hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
+                  (kErrStallEarly | kErrStallLate))
+      ok = 0;
+    // the snapshot stays as it is until this block has arrived at the next barrier
+    if (ok) {
+      s_snap.cur = ld_agent32(&ctl->snap[0]);
+      s_snap.stamp = ld_agent32(&ctl->snap[1]);
+      s_snap.fsz = ld_agent32(&ctl->snap[2]);
+      s_snap.local_stop = ld_agent32(&ctl->snap[3]);
+    }
+    s_ok = ok;
+  }
+  __syncthreads();
+  *snap = s_snap;
+  return s_ok != 0u;
+}
+
+template <int W>
+__global__ __launch_bounds__(kLocalThreads) void k_insert_batch(
+    PropArgs a, const uint32_t *src, const uint32_t *dst, uint64_t count, uint32_t n, Ovf *ovf,
+    uint64_t ovf_cap, Mirror *m, uint32_t seq, uint32_t max_frontier, u64 start_ticks,
+    u64 wait_ticks) {
+  __shared__ TileLds<W> sm;
+  __shared__ uint32_t s_bad;
+  Ctl *ctl = a.ctl;
+  const uint32_t t = threadIdx.x, nb = gridDim.x;
+  const uint64_t halves = 2 * count;
+  u64 relaxed = 0, expanded = 0;
+  // state of the pending frontier as of the launch (the same in every block: every block reads
+  // it before the gathering, and nothing changes it before)
+  uint32_t ring = ld_agent32(&ctl->cur), stamp = ld_agent32(&ctl->stamp);
+  Snap sn;
+  {
+    bool bad = false;
+    for (uint64_t i = (uint64_t)blockIdx.x * kLocalThreads + t; i < count;
+         i += (uint64_t)nb * kLocalThreads)
+      bad |= (src[i] >= n) | (dst[i] >= n);
+    if (t == 0) s_bad = 0;
+    __syncthreads();
+    if (bad) s_bad = 1;
+    __syncthreads();
+    if (t == 0 && s_bad) atomicOr(&ctl->err, kErrRange);
+  }
+  // every block resident and every id checked; nothing is modified before this point
+  bool go = grid_gather(ctl, nb, start_ticks);
+  if (go) {
+    // Algorithm 3's first step for every edge: append, seed the head, queue it if it grew
+    if (blockIdx.x == 0 && t == 0) {
+      st_agent32(&ctl->heavy[0], 0u);
+      st_agent32(&ctl->heavy[1], 0u);
+      const uint32_t r1 = ring == 2u ? 0u : ring + 1u;
+      st_agent32(&ctl->fsize[r1], 0u);
+      st_agent32(&ctl->fsize[r1 == 2u ? 0u : r1 + 1u], 0u);
+    }
+    for (uint64_t j0 = (uint64_t)blockIdx.x * kLocalThreads; j0 < halves;
+         j0 += (uint64_t)nb * kLocalThreads) {
+      const uint64_t j = j0 + t;
+      const bool act = j < halves;
+      const uint64_t i = act ? j >> 1 : 0;
+      bool ovfl = false;
+      apply_half<W>(a, act ? src[i] : 0u, act ? dst[i] : 0u, (uint32_t)(j & 1u), ring, stamp,
+                    ovf, ovf_cap, act, &ovfl);
+    }
+    go = grid_barrier(ctl, nb, wait_ticks, kErrStallLate, &sn);
+  }
+  bool local_done = false;  // the last single-workgroup pass stopped on its edge bound
+  while (go) {
+    ring = sn.cur;
+    stamp = sn.stamp;
+    const uint32_t fsz = sn.fsz;
+    if (fsz == 0 || fsz > max_frontier) break;
+    if (fsz <= a.local_max_frontier && !local_done) {
+      // small frontier: block 0 runs rounds alone until it empties, outgrows one workgroup or
+      // has run kBatchLocalRounds rounds (the other blocks wait at the barrier meanwhile)
+      if (blockIdx.x == 0) {
+        const bool budget = local_rounds_core<W>(a, sm, kBatchLocalRounds);
+        if (t == 0) {
+          st_agent32(&ctl->local_stop, budget ? 1u : 0u);
+          // the next grid round starts from empty chunk counts
+          st_agent32(&ctl->heavy[0], 0u);
+          st_agent32(&ctl->heavy[1], 0u);
+        }
+      }
+      go = grid_barrier(ctl, nb, wait_ticks, kErrStallLate, &sn);
+      // a pass that ran out of rounds continues as another pass; one that stopped on the edge
+      // bound hands its frontier to a grid round
+      local_done = sn.local_stop == 0u;
+      continue;
+    }
+    local_done = false;
+    // one round over every block: frontier tiles of kLocalThreads entries, long rows deferred.
+    // Block 0 records the round's bookkeeping (read by the next single-workgroup pass).
+    const uint32_t nring = ring == 2u ? 0u : ring + 1u;
+    if (blockIdx.x == 0 && t == 0) {
+      st_agent32(&ctl->fsize[nring == 2u ? 0u : nring + 1u], 0u);
+      st_agent32(&ctl->heavy[(stamp + 1u) & 1u], 0u);
+      st_agent32(&ctl->cur, nring);
+      st_agent32(&ctl->stamp, stamp + 1u);
+    }
+    for (uint32_t beg = blockIdx.x * kLocalThreads; beg < fsz; beg += nb * kLocalThreads) {
+      const uint32_t end = min(beg + kLocalThreads, fsz);
+      expand_tile<kLocalThreads, W>(a, a.fq[ring], beg, end, a.fq[nring], &ctl->fsize[nring],
+                                    stamp + 1u, a.heavy_list, &ctl->heavy[stamp & 1u], true,
+                                    sm.start, sm.off, sm.lab, sm.ent, sm.wsum, relaxed, expanded,
+                                    0u);
+    }
+    go = grid_barrier(ctl, nb, wait_ticks, kErrStallLate, &sn);
+    if (!go) break;
+    // the deferred chunks of long rows, one chunk per block at a time (the count is final: the
+    // phase that adds to it ended at the barrier, and it is cleared only after the next one)
+    uint32_t hcnt = ld_agent32(&ctl->heavy[stamp & 1u]);
+    if (hcnt > a.heavy_cap) hcnt = (uint32_t)a.heavy_cap;
+    for (uint32_t item = blockIdx.x; item < hcnt; item += nb) {
+      const u64 h = a.heavy_list[item];
+      const uint32_t ent = (uint32_t)(h >> 32), c = (uint32_t)h;
+      const uint32_t dir = ent >> 31, x = ent & kIdMask;
+      const Csr g = dir ? a.r : a.f;
+      const uint32_t dg = min(g.deg[x], g.cap[x]);
+      const uint32_t b = c * kChunk, e_end = min(dg, b + kChunk);
+      const Half<W> lv = ld_half_agent<W>(half_ptr<W>(a.L.lab, x, dir));
+      const u64 o = g.off[x];
+      for (uint32_t e0 = b; e0 < e_end; e0 += kLocalThreads) {
+        const uint32_t e = e0 + t;
+        bool push = false;
+        uint32_t y = 0;
+        if (e < e_end) {
+          y = g.col[o + e];
+          push = relax<W>(half_ptr<W>(a.L.lab, y, dir), lv) &&
+                 claim(&a.inq[2ull * y + dir], stamp + 1u);
+        }
+        wave_push(a.fq[nring], &ctl->fsize[nring], push, y | (ent & kDirBit));
+      }
+      if (t == 0) relaxed += e_end > b ? e_end - b : 0;
+    }
+    go = grid_barrier(ctl, nb, wait_ticks, kErrStallLate, &sn);
+  }
+  if (t == 0 && (expanded | relaxed)) {
+    a.pcnt[2 * blockIdx.x] += expanded;
+    a.pcnt[2 * blockIdx.x + 1] += relaxed;
+  }
+  // ctl->cur / ctl->stamp already say where the frontier stands (kept by block 0 every
+  // round). The last block to finish resets the gathering and the barrier and publishes.
+  __syncthreads();
+  if (t == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const uint32_t done = __hip_atomic_fetch_add(&ctl->bar_done, 1u, __ATOMIC_ACQ_REL,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+    if (done == nb - 1u) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      st_agent32(&ctl->bar_done, 0u);
+      st_agent32(&ctl->bar_gather, 0u);
+      st_agent32(&ctl->bar_count, 0u);
+      const uint32_t err = ld_agent32(&ctl->err);
+      uint32_t flags = 0;
+      if (err) flags |= kFastErr;
+      if (ld_agent32(&ctl->ovf_count)) flags |= kFastOvf;
+      if (ld_agent32(&ctl->fsize[ld_agent32(&ctl->cur)])) flags |= kFastPending;
+      publish_fast(m, flags, seq);
+    }
+  }
+}
+
+hipError_t insert_batch_grid(uint32_t words, BatchLaunch *out) {
+  const void *f = nullptr;
+  switch (words) {
+    case 1: f = (const void *)k_insert_batch<1>; break;
+    case 2: f = (const void *)k_insert_batch<2>; break;
+    case 4: f = (const void *)k_insert_batch<4>; break;
+    default: return hipErrorInvalidValue;
+  }
+  int dev = 0, cus = 0, per_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, (int)kLocalThreads, 0);
+  if (e != hipSuccess) return e;
+  if (cus <= 0 || per_cu <= 0) return hipErrorInvalidValue;
+  out->func = f;
+  // one block per compute unit (blocks of 16 waves; more per unit only lengthen the barriers)
+  out->grid = (uint32_t)std::min<int>(cus, (int)kRoundGridMax);
+  return hipSuccess;
+}
+
+hipError_t launch_insert_batch(const PropArgs &a, const uint32_t *src, const uint32_t *dst,
+                               uint64_t count, uint32_t n, Ovf *ovf, uint64_t ovf_cap, Mirror *m,
+                               uint32_t seq, uint32_t max_frontier, u64 start_ticks,
+                               u64 wait_ticks, uint32_t grid, hipStream_t s) {
+  DBL_LAUNCH_W(a.L.words, k_insert_batch, dim3(grid), dim3(kLocalThreads), s, a, src, dst, count,
+               n, ovf, ovf_cap, m, seq, max_frontier, start_ticks, wait_ticks);
+  return hipGetLastError();
+}
+
+hipError_t insert_batch_node_params(uint32_t words, uint32_t grid, void **args,
+                                    hipKernelNodeParams *p) {
+  const void *f = nullptr;
+  switch (words) {
+    case 1: f = (const void *)k_insert_batch<1>; break;
+    case 2: f = (const void *)k_insert_batch<2>; break;
+    case 4: f = (const void *)k_insert_batch<4>; break;
+    default: return hipErrorInvalidValue;
+  }
+  *p = hipKernelNodeParams{};
+  p->func = const_cast<void *>(f);
+  p->gridDim = dim3(grid);
+  p->blockDim = dim3(kLocalThreads);
+  p->kernelParams = args;
+  return hipSuccess;
 }
 
 // Copy every row of old_g into new_g (same deg array; new offsets and capacities). A block takes

@@ -340,6 +340,30 @@ def latency_summary(trace: List[Request], makespan: float) -> dict:
     return out
 
 
+def serve_alone(index, trace: List[Request], realtime: bool = True) -> dict:
+    """The same trace without continuous batching: one request at a time in sequence order, each
+    started when it has arrived and the one before it is done (so queueing counts in its
+    latency), on one stream; returns the summary of `serve`."""
+    import torch
+
+    from .binding import to_device_ids
+
+    t0 = time.perf_counter()
+    for r in sorted(trace, key=lambda x: x.seq):
+        if realtime:
+            while time.perf_counter() - t0 < r.arrival:
+                pass
+        r.start = time.perf_counter() - t0
+        a, b = to_device_ids(r.a, index.device), to_device_ids(r.b, index.device)
+        if r.kind == "query":
+            r.answers = index.query(a, b).cpu().numpy()
+        else:
+            index.insert_edges(a, b)
+            torch.cuda.current_stream(index.device).synchronize()
+        r.done = time.perf_counter() - t0
+    return latency_summary(trace, time.perf_counter() - t0)
+
+
 def serve(index, trace: List[Request], workers: int = 4, max_batch: int = 1 << 17,
           bfs_slots: int = 256, realtime: bool = True, memory_cap: Optional[int] = None):
     """Run `trace` through a continuous-batching server over `index`; returns a summary."""

@@ -256,15 +256,17 @@ def test_pull_rounds_rmat_equal_counts(words):
     assert_queries_equal(g, o, w.q_u, w.q_v)
 
 
+@pytest.mark.parametrize("form", [dict(insert_persistent=0), dict(batch_max_frontier=16)])
 @pytest.mark.parametrize("pull_all", [0, 1])
-def test_pull_rounds_in_insertion_batches(pull_all):
+def test_pull_rounds_in_insertion_batches(pull_all, form):
     """Insertion batches on a 2^12-vertex graph with the single-workgroup bounds tiny, so the
     batches propagate in grid rounds, and the threshold at its minimum, so those rounds pull
-    (with and without the frontier test)."""
+    (with and without the frontier test): in the multi-launch form, and in the persistent form
+    with every frontier above 16 entries handed to the host's rounds."""
     w = dblgen.make_rmat_workload("pri", 12, 5, draws=8 << 12, n_insert=6000,
                                   insert_kind="uniform", n_query=20000, query_kind="mixed")
     g = gpu_index(w.n, w.src, w.dst, pull_threshold=1, pull_all_threshold=pull_all)
-    g.set_tuning(small_batch=0, local_max_frontier=4, local_max_edges=32)
+    g.set_tuning(small_batch=0, local_max_frontier=4, local_max_edges=32, **form)
     o = oracle.OracleIndex(w.n, w.src, w.dst).build(threads=8)
     built = g.stats()["pull_rounds"]
     for lo in range(0, 6000, 1500):

@@ -34,10 +34,16 @@ N_INS, N_Q = (1_000_000, 1_000_000) if SMALL else (10_000_000, 10_000_000)
 BATCH, QBATCH = 100_000, 65_536
 THREADS = min(16, os.cpu_count() or 1)
 T0 = time.time()
+_CAP = []  # the capture fixture of the running test: progress goes past it to the terminal
 
 
 def _say(msg):
-    print(f"[{time.time() - T0:7.1f}s] {msg}", flush=True)
+    line = f"[{time.time() - T0:7.1f}s] {msg}"
+    if _CAP:
+        with _CAP[0].disabled():
+            print(line, flush=True)
+    else:
+        print(line, flush=True)
 
 
 def _labels_equal(g, want, what):
@@ -62,7 +68,9 @@ def _edge_monotone(labs, src, dst, chunk=1 << 26):
     return True
 
 
-def test_scale_full_parity():
+def test_scale_full_parity(capsys):
+    # a run of several minutes reports each step as it ends, also under pytest's capture
+    _CAP[:] = [capsys]
     w = dblgen.scale_workload(SCALE, DRAWS, N_INS, N_Q)
     _say(f"workload n={w.n} m={w.m} insertions={len(w.ins_src)} queries={len(w.q_u)}")
     src, dst = dbl.to_device_ids(w.src), dbl.to_device_ids(w.dst)
