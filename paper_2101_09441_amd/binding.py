@@ -212,9 +212,18 @@ def _ids(t: torch.Tensor, name: str) -> torch.Tensor:
     return t.contiguous()
 
 
-def _stream_ptr(stream) -> int:
+try:  # the current stream's raw handle without building a Stream object
+    _raw_stream = torch._C._cuda_getCurrentRawStream
+except AttributeError:  # pragma: no cover - older torch
+    _raw_stream = None
+
+
+def _stream_ptr(stream, device=None) -> int:
     if stream is None:
-        stream = torch.cuda.current_stream()
+        if _raw_stream is not None:
+            idx = device.index if isinstance(device, torch.device) else device
+            return int(_raw_stream(torch.cuda.current_device() if idx is None else idx))
+        stream = torch.cuda.current_stream(device)
     return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
 
 
@@ -387,9 +396,9 @@ class Index:
         src, dst = _ids(src, "src"), _ids(dst, "dst")
         if src.numel() != dst.numel():
             raise ValueError("src and dst differ in length")
-        with torch.cuda.device(self.device):
-            st = load_library().dbl_insert_edges(self._handle(), src.numel(), src.data_ptr(),
-                                                 dst.data_ptr(), _stream_ptr(stream))
+        # the library makes the index's device current itself
+        st = load_library().dbl_insert_edges(self._handle(), src.numel(), src.data_ptr(),
+                                             dst.data_ptr(), _stream_ptr(stream, self.device))
         _check(st, "dbl_insert_edges")
 
     def insert_edges_each(self, src: torch.Tensor, dst: torch.Tensor, latencies: bool = False,
@@ -416,9 +425,9 @@ class Index:
             out = torch.empty(u.numel(), dtype=torch.uint8, device=u.device)
         elif out.dtype != torch.uint8 or out.numel() < u.numel() or not out.is_contiguous():
             raise ValueError("out must be a contiguous uint8 tensor with room for every pair")
-        with torch.cuda.device(self.device):
-            st = load_library().dbl_query_batch(self._handle(), u.numel(), u.data_ptr(),
-                                                v.data_ptr(), out.data_ptr(), _stream_ptr(stream))
+        st = load_library().dbl_query_batch(self._handle(), u.numel(), u.data_ptr(),
+                                            v.data_ptr(), out.data_ptr(),
+                                            _stream_ptr(stream, self.device))
         _check(st, "dbl_query_batch")
         return out
 

@@ -99,8 +99,10 @@ struct dbl_index {
   uint32_t gather_wait_us = 20000;        // persistent launch: longest wait for all blocks
   uint32_t barrier_wait_us = 2000000;     // ... and at one later grid barrier
   uint32_t batch_grid_opt = 0;            // its blocks (0 = one per compute unit)
-  // persistent insertion kernel: launch shape (0 = not yet queried) and its graph
+  // persistent insertion kernel: blocks per launch at most (0 = not yet queried), its
+  // synchronisation words and its graph
   uint32_t batch_grid = 0, batch_grid_words = 0;
+  uint32_t *bar = nullptr;
   hipGraph_t igraph = nullptr;
   hipGraphExec_t igexec = nullptr;
   hipGraphNode_t ig_node = nullptr;
@@ -637,7 +639,19 @@ dbl_status insert_persistent(dbl_index *ix, uint64_t count, const uint32_t *d_sr
     ix->batch_grid = bl.grid;
     ix->batch_grid_words = ix->lw;
   }
-  const uint32_t grid = ix->batch_grid_opt ? ix->batch_grid_opt : ix->batch_grid;
+  if (!ix->bar) {
+    CKS(dalloc(&ix->bar, dbl::kBarWords));
+    CK(dbl::launch_fill_u32(ix->bar, 0u, dbl::kBarWords, s));
+  }
+  // As many blocks as the batch's halves fill, one per compute unit at most: the appends queue at
+  // most one frontier entry per half, so the first grid round has at most one tile per block,
+  // and a grid barrier's cost grows with the blocks that arrive at it.
+  const uint64_t halves = 2 * count;
+  const uint32_t grid =
+      ix->batch_grid_opt
+          ? ix->batch_grid_opt
+          : (uint32_t)std::min<uint64_t>(ix->batch_grid,
+                                         (halves + dbl::kLocalThreads - 1) / dbl::kLocalThreads);
   dbl::PropArgs a = prop_args(ix);
   uint32_t n = ix->n, maxf = ix->batch_max_frontier, sq = seq;
   Ovf *ovf = ix->ovf;
@@ -646,9 +660,10 @@ dbl_status insert_persistent(dbl_index *ix, uint64_t count, const uint32_t *d_sr
   u64 start_ticks = ix->clock_khz * ix->gather_wait_us / 1000;
   u64 wait_ticks = ix->clock_khz * ix->barrier_wait_us / 1000;
   if (ix->insert_graph) {
-    void *args[12] = {(void *)&a, (void *)&d_src, (void *)&d_dst, (void *)&count, (void *)&n,
+    uint32_t *bar = ix->bar;
+    void *args[13] = {(void *)&a, (void *)&d_src, (void *)&d_dst, (void *)&count, (void *)&n,
                       (void *)&ovf, (void *)&ovf_cap, (void *)&m, (void *)&sq, (void *)&maxf,
-                      (void *)&start_ticks, (void *)&wait_ticks};
+                      (void *)&start_ticks, (void *)&wait_ticks, (void *)&bar};
     hipKernelNodeParams p;
     CK(dbl::insert_batch_node_params(ix->lw, grid, args, &p));
     if (!ix->igexec || ix->ig_words != ix->lw || ix->ig_grid != grid) {
@@ -669,7 +684,7 @@ dbl_status insert_persistent(dbl_index *ix, uint64_t count, const uint32_t *d_sr
   } else {
     Timed tm(ix, kTInsertBatch, s);
     CK(dbl::launch_insert_batch(a, d_src, d_dst, count, n, ovf, ovf_cap, m, seq, maxf,
-                                start_ticks, wait_ticks, grid, s));
+                                start_ticks, wait_ticks, ix->bar, grid, s));
   }
   uint32_t flags = 0;
   return wait_fast(ix, s, seq, &flags);
@@ -2044,6 +2059,7 @@ void dbl_destroy(dbl_index *ix) {
   hfree(ix->door);
   if (ix->igexec) (void)hipGraphExecDestroy(ix->igexec);
   if (ix->igraph) (void)hipGraphDestroy(ix->igraph);
+  dfree(ix->bar);
   dfree(ix->pcnt);
   dfree(ix->ovf);
   dfree(ix->landmarks_d);

@@ -68,13 +68,6 @@ struct Ctl {
   uint32_t local_rounds;
   uint32_t bfs_done;    // BFS blocks finished (the last one publishes the status)
   uint32_t pheavy;      // chunks of high-degree rows queued for the pull round
-  uint32_t bar_gather;  // persistent insertion kernel: blocks gathered at its start,
-  uint32_t bar_count;   // arrivals at the current grid barrier,
-  uint32_t bar_gen;     // the barrier's generation,
-  uint32_t bar_done;    // and blocks that have finished (the last one publishes);
-  uint32_t local_stop;  // 1: its last single-workgroup pass stopped on its round budget
-  uint32_t snap[4];     // {cur, stamp, fsize[cur], local_stop} as of the last barrier
-  uint32_t pad0[3];
   unsigned long long ctr[kCtrCount];
 };
 
@@ -251,21 +244,26 @@ hipError_t launch_insert_apply(const PropArgs &a, const uint32_t *src, const uin
 // One insertion batch in one persistent launch (see k_insert_batch): validation, the appends and
 // seeds, and the propagation rounds, separated by grid barriers; publishes the fast status word
 // {seq, flags} to m. grid: blocks of kLocalThreads threads, all of which must fit on the device
-// at once (insert_batch_grid). max_frontier: a frontier larger than this is left pending for the
-// host's rounds. start_ticks / wait_ticks: the longest wait at the first two barriers / at any
-// later one, in device wall-clock ticks.
+// at once (insert_batch_grid gives one per compute unit). max_frontier: a frontier larger than
+// this is left pending for the host's rounds. start_ticks / wait_ticks: the longest wait at the
+// start gathering / at a later barrier, in device wall-clock ticks. bar: kBarWords words, zero
+// before the first launch (every launch leaves them zero).
 struct BatchLaunch {
   const void *func;   // kernel for the label width
   uint32_t grid;
 };
 hipError_t insert_batch_grid(uint32_t words, BatchLaunch *out);
+constexpr uint32_t kBarLine = 32;  // 32-bit words per 128-byte line
+constexpr uint32_t kBarGather = 0, kBarCount = kBarLine, kBarGen = 2 * kBarLine,
+                   kBarDone = 3 * kBarLine, kBarWords = 4 * kBarLine;
 hipError_t launch_insert_batch(const PropArgs &a, const uint32_t *src, const uint32_t *dst,
                                uint64_t count, uint32_t n, Ovf *ovf, uint64_t ovf_cap, Mirror *m,
                                uint32_t seq, uint32_t max_frontier,
                                unsigned long long start_ticks, unsigned long long wait_ticks,
-                               uint32_t grid, hipStream_t s);
-// Kernel-node parameters of the same launch, for a graph; args points to its 12 arguments in
-// order (a, src, dst, count, n, ovf, ovf_cap, m, seq, max_frontier, start_ticks, wait_ticks).
+                               uint32_t *bar, uint32_t grid, hipStream_t s);
+// Kernel-node parameters of the same launch, for a graph; args points to its 13 arguments in
+// order (a, src, dst, count, n, ovf, ovf_cap, m, seq, max_frontier, start_ticks, wait_ticks,
+// bar).
 hipError_t insert_batch_node_params(uint32_t words, uint32_t grid, void **args,
                                     hipKernelNodeParams *p);
 hipError_t launch_regrow_copy(Csr old_g, Csr new_g, uint32_t n, hipStream_t s);

@@ -1695,10 +1695,8 @@ struct TileLds {
   uint32_t edges;
 };
 
-// Returns true when it stopped only because it had run max_rounds rounds.
 template <int W>
-__device__ bool local_rounds_core(const PropArgs &a, TileLds<W> &sm,
-                                  uint32_t max_rounds = 0xFFFFFFFFu) {
+__device__ void local_rounds_core(const PropArgs &a, TileLds<W> &sm) {
   uint32_t *s_start = sm.start, *s_ent = sm.ent, *s_wsum = sm.wsum;
   u64 *s_off = sm.off;
   Half<W> *s_lab = sm.lab;
@@ -1708,14 +1706,9 @@ __device__ bool local_rounds_core(const PropArgs &a, TileLds<W> &sm,
   uint32_t ring = ld_agent32(&ctl->cur), stamp = ld_agent32(&ctl->stamp);
   u64 relaxed = 0, expanded = 0;
   uint32_t rounds = 0;
-  bool budget = false;
   for (;;) {
     const uint32_t fsz = ld_agent32(&ctl->fsize[ring]);
     if (fsz == 0 || fsz > a.local_max_frontier) break;
-    if (rounds == max_rounds) {
-      budget = true;
-      break;
-    }
     uint32_t my = 0;
     const uint32_t *fq = a.fq[ring];
     for (uint32_t i = t; i < fsz; i += kLocalThreads) {
@@ -1756,7 +1749,6 @@ __device__ bool local_rounds_core(const PropArgs &a, TileLds<W> &sm,
       a.pcnt[2 * (kRoundGridMax + kHeavyGrid) + 1] += relaxed;
     }
   }
-  return budget;
 }
 
 template <int W>
@@ -2127,47 +2119,53 @@ hipError_t launch_insert_apply(const PropArgs &a, const uint32_t *src, const uin
 
 // ---- one insertion batch in one persistent launch
 //
-// Every block of the launch stays resident from the first barrier to its exit, and the phases
-// of Algorithm 3 for a whole batch follow each other inside the launch: validation of every id,
-// the appends and seeds of every edge (both halves), then the propagation rounds until the
-// frontier is empty. Rounds whose frontier fits one workgroup run in block 0 alone (no barrier
-// per round); larger ones are expanded by every block, with high-degree rows split into chunks
-// handled after a barrier. A frontier above max_frontier is left for the host's
-// direction-optimised rounds.
+// The phases of Algorithm 3 for a whole batch follow each other inside one launch: validation of
+// every id, the appends and seeds of every edge (both halves), then propagation. While the
+// frontier is larger than one workgroup handles, every block expands it (grid rounds, with
+// high-degree rows split into chunks handled after a barrier); once it is small, block 0
+// finishes the rounds alone and the other blocks leave. A frontier above max_frontier, or one
+// that block 0 cannot take on (it would scan more than local_max_edges), is left pending for the
+// host's direction-optimised rounds.
 //
 // Before anything is modified, every block validates its share of the ids and then waits,
 // bounded, until every block of the launch is resident (grid_gather). That wait ends the same
 // way for every block: either all arrived, or one block, having waited too long, cancels the
 // gathering before the last arrival, and then no block modifies anything (kErrStallEarly: the
 // host runs the batch without this kernel). Once gathered, the blocks stay resident until they
-// exit, so the later grid barriers (grid_barrier) only wait for the slowest block's share of a
+// leave, so the later grid barriers (grid_barrier) only wait for the slowest block's share of a
 // phase; their waits are bounded too, and a wait that runs out (kErrStallLate; it would take a
 // share of seconds) leaves every block to finish its current phase and leave at its next
 // barrier, after which the host re-propagates from every vertex. No wait is unbounded,
 // whatever the occupancy.
 //
-// Every decision the blocks take after a barrier (where the frontier is, how large it is, how
-// the last single-workgroup pass ended) comes from a snapshot that the last block to arrive
-// takes while every other block is still waiting, so all blocks decide alike even when block 0
-// has already moved on and changed those fields again.
+// Every decision the blocks take after a barrier (where the frontier is and how large it is)
+// comes from a snapshot that the last block to arrive takes while every other block still
+// waits, so all blocks decide alike even when block 0 has already moved on and changed those
+// fields again. Waiting blocks poll with plain device-scope loads and fence once when the wait
+// is over: a polling load that also invalidated the cache would slow every other block.
+//
+// Synchronisation words, each on a 128-byte line of its own so that polling one does not slow
+// the atomics on another: bar[kBarGather] blocks gathered (kGatherCancel once cancelled),
+// bar[kBarCount] arrivals at the current barrier, bar[kBarGen] its generation followed by the
+// snapshot {cur, stamp, fsize[cur]}, bar[kBarDone] blocks that have left (the last one resets the
+// words and publishes).
 
 constexpr uint32_t kGatherCancel = 0x80000000u;
-constexpr uint32_t kBatchLocalRounds = 1024;
 
-__device__ bool grid_gather(Ctl *ctl, uint32_t nblocks, u64 limit) {
+__device__ bool grid_gather(uint32_t *bar, Ctl *ctl, uint32_t nblocks, u64 limit) {
   __shared__ uint32_t s_ok;
   __syncthreads();
   if (threadIdx.x == 0) {
+    uint32_t *g = bar + kBarGather;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    uint32_t c = __hip_atomic_fetch_add(&ctl->bar_gather, 1u, __ATOMIC_ACQ_REL,
-                                        __HIP_MEMORY_SCOPE_AGENT) + 1u;
+    uint32_t c = __hip_atomic_fetch_add(g, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
     const u64 t0 = wall_clock64();
     u64 spins = 0;
     while (c < nblocks) {  // c has the cancel bit once cancelled, which ends the loop too
       // past the time limit (or, should the clock stand still, as many polls as ticks)
       if (wall_clock64() - t0 > limit || ++spins > limit) {
         // cancel, unless the last block arrives first
-        const uint32_t seen = atomicCAS(&ctl->bar_gather, c, c | kGatherCancel);
+        const uint32_t seen = atomicCAS(g, c, c | kGatherCancel);
         if (seen == c) {
           atomicOr(&ctl->err, kErrStallEarly);
           c |= kGatherCancel;
@@ -2177,7 +2175,7 @@ __device__ bool grid_gather(Ctl *ctl, uint32_t nblocks, u64 limit) {
         continue;
       }
       __builtin_amdgcn_s_sleep(2);
-      c = __hip_atomic_load(&ctl->bar_gather, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+      c = __hip_atomic_load(g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     // every block's range check was made visible before its arrival
@@ -2188,40 +2186,40 @@ __device__ bool grid_gather(Ctl *ctl, uint32_t nblocks, u64 limit) {
 }
 
 struct Snap {
-  uint32_t cur, stamp, fsz, local_stop;
+  uint32_t cur, stamp, fsz;
 };
 
-__device__ bool grid_barrier(Ctl *ctl, uint32_t nblocks, u64 limit, uint32_t stall_bit,
-                             Snap *snap) {
+__device__ bool grid_barrier(uint32_t *bar, Ctl *ctl, uint32_t nblocks, u64 limit,
+                             uint32_t stall_bit, Snap *snap) {
   __shared__ uint32_t s_ok;
   __shared__ Snap s_snap;
   __syncthreads();
   if (threadIdx.x == 0) {
     uint32_t ok = 1;
-    const uint32_t gen =
-        __hip_atomic_load(&ctl->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t *gen = bar + kBarGen;
+    const uint32_t g0 = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    const uint32_t arrived = __hip_atomic_fetch_add(&ctl->bar_count, 1u, __ATOMIC_ACQ_REL,
+    const uint32_t arrived = __hip_atomic_fetch_add(bar + kBarCount, 1u, __ATOMIC_RELAXED,
                                                     __HIP_MEMORY_SCOPE_AGENT);
     if (arrived == nblocks - 1u) {
       // every block has finished the phase: its results are final until the next barrier
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       const uint32_t cur = ld_agent32(&ctl->cur);
-      st_agent32(&ctl->snap[0], cur);
-      st_agent32(&ctl->snap[1], ld_agent32(&ctl->stamp));
-      st_agent32(&ctl->snap[2], ld_agent32(&ctl->fsize[cur]));
-      st_agent32(&ctl->snap[3], ld_agent32(&ctl->local_stop));
-      __hip_atomic_store(&ctl->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_add(&ctl->bar_gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      st_agent32(gen + 1, cur);
+      st_agent32(gen + 2, ld_agent32(&ctl->stamp));
+      st_agent32(gen + 3, ld_agent32(&ctl->fsize[cur]));
+      st_agent32(bar + kBarCount, 0u);
+      __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     } else {
       const u64 t0 = wall_clock64();
       u64 spins = 0;
-      while (__hip_atomic_load(&ctl->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-        if (__hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
-            (kErrStallEarly | kErrStallLate)) {
+      while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g0) {
+        ++spins;
+        if ((spins & 63u) == 0u && (ld_agent32(&ctl->err) & (kErrStallEarly | kErrStallLate))) {
           ok = 0;
           break;
         }
-        if (wall_clock64() - t0 > limit || ++spins > limit) {
+        if (wall_clock64() - t0 > limit || spins > limit) {
           atomicOr(&ctl->err, stall_bit);
           ok = 0;
           break;
@@ -2230,15 +2228,12 @@ __device__ bool grid_barrier(Ctl *ctl, uint32_t nblocks, u64 limit, uint32_t sta
       }
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    if (ok && __hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
-                  (kErrStallEarly | kErrStallLate))
-      ok = 0;
+    if (ok && (ld_agent32(&ctl->err) & (kErrStallEarly | kErrStallLate))) ok = 0;
     // the snapshot stays as it is until this block has arrived at the next barrier
     if (ok) {
-      s_snap.cur = ld_agent32(&ctl->snap[0]);
-      s_snap.stamp = ld_agent32(&ctl->snap[1]);
-      s_snap.fsz = ld_agent32(&ctl->snap[2]);
-      s_snap.local_stop = ld_agent32(&ctl->snap[3]);
+      s_snap.cur = ld_agent32(gen + 1);
+      s_snap.stamp = ld_agent32(gen + 2);
+      s_snap.fsz = ld_agent32(gen + 3);
     }
     s_ok = ok;
   }
@@ -2251,7 +2246,7 @@ template <int W>
 __global__ __launch_bounds__(kLocalThreads) void k_insert_batch(
     PropArgs a, const uint32_t *src, const uint32_t *dst, uint64_t count, uint32_t n, Ovf *ovf,
     uint64_t ovf_cap, Mirror *m, uint32_t seq, uint32_t max_frontier, u64 start_ticks,
-    u64 wait_ticks) {
+    u64 wait_ticks, uint32_t *bar) {
   __shared__ TileLds<W> sm;
   __shared__ uint32_t s_bad;
   Ctl *ctl = a.ctl;
@@ -2274,7 +2269,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_insert_batch(
     if (t == 0 && s_bad) atomicOr(&ctl->err, kErrRange);
   }
   // every block resident and every id checked; nothing is modified before this point
-  bool go = grid_gather(ctl, nb, start_ticks);
+  bool go = grid_gather(bar, ctl, nb, start_ticks);
   if (go) {
     // Algorithm 3's first step for every edge: append, seed the head, queue it if it grew
     if (blockIdx.x == 0 && t == 0) {
@@ -2293,35 +2288,21 @@ __global__ __launch_bounds__(kLocalThreads) void k_insert_batch(
       apply_half<W>(a, act ? src[i] : 0u, act ? dst[i] : 0u, (uint32_t)(j & 1u), ring, stamp,
                     ovf, ovf_cap, act, &ovfl);
     }
-    go = grid_barrier(ctl, nb, wait_ticks, kErrStallLate, &sn);
+    go = grid_barrier(bar, ctl, nb, wait_ticks, kErrStallLate, &sn);
   }
-  bool local_done = false;  // the last single-workgroup pass stopped on its edge bound
   while (go) {
     ring = sn.cur;
     stamp = sn.stamp;
     const uint32_t fsz = sn.fsz;
     if (fsz == 0 || fsz > max_frontier) break;
-    if (fsz <= a.local_max_frontier && !local_done) {
-      // small frontier: block 0 runs rounds alone until it empties, outgrows one workgroup or
-      // has run kBatchLocalRounds rounds (the other blocks wait at the barrier meanwhile)
-      if (blockIdx.x == 0) {
-        const bool budget = local_rounds_core<W>(a, sm, kBatchLocalRounds);
-        if (t == 0) {
-          st_agent32(&ctl->local_stop, budget ? 1u : 0u);
-          // the next grid round starts from empty chunk counts
-          st_agent32(&ctl->heavy[0], 0u);
-          st_agent32(&ctl->heavy[1], 0u);
-        }
-      }
-      go = grid_barrier(ctl, nb, wait_ticks, kErrStallLate, &sn);
-      // a pass that ran out of rounds continues as another pass; one that stopped on the edge
-      // bound hands its frontier to a grid round
-      local_done = sn.local_stop == 0u;
-      continue;
+    if (fsz <= a.local_max_frontier) {
+      // small frontier: block 0 runs the remaining rounds alone and the other blocks leave; a
+      // frontier that outgrows one workgroup again is left pending for the host
+      if (blockIdx.x == 0) local_rounds_core<W>(a, sm);
+      break;
     }
-    local_done = false;
     // one round over every block: frontier tiles of kLocalThreads entries, long rows deferred.
-    // Block 0 records the round's bookkeeping (read by the next single-workgroup pass).
+    // Block 0 records the round's bookkeeping.
     const uint32_t nring = ring == 2u ? 0u : ring + 1u;
     if (blockIdx.x == 0 && t == 0) {
       st_agent32(&ctl->fsize[nring == 2u ? 0u : nring + 1u], 0u);
@@ -2336,7 +2317,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_insert_batch(
                                     sm.start, sm.off, sm.lab, sm.ent, sm.wsum, relaxed, expanded,
                                     0u);
     }
-    go = grid_barrier(ctl, nb, wait_ticks, kErrStallLate, &sn);
+    go = grid_barrier(bar, ctl, nb, wait_ticks, kErrStallLate, &sn);
     if (!go) break;
     // the deferred chunks of long rows, one chunk per block at a time (the count is final: the
     // phase that adds to it ended at the barrier, and it is cleared only after the next one)
@@ -2364,24 +2345,24 @@ __global__ __launch_bounds__(kLocalThreads) void k_insert_batch(
       }
       if (t == 0) relaxed += e_end > b ? e_end - b : 0;
     }
-    go = grid_barrier(ctl, nb, wait_ticks, kErrStallLate, &sn);
+    go = grid_barrier(bar, ctl, nb, wait_ticks, kErrStallLate, &sn);
   }
   if (t == 0 && (expanded | relaxed)) {
     a.pcnt[2 * blockIdx.x] += expanded;
     a.pcnt[2 * blockIdx.x + 1] += relaxed;
   }
-  // ctl->cur / ctl->stamp already say where the frontier stands (kept by block 0 every
-  // round). The last block to finish resets the gathering and the barrier and publishes.
+  // ctl->cur / ctl->stamp already say where the frontier stands (kept by block 0). The last
+  // block to leave resets the synchronisation words and publishes.
   __syncthreads();
   if (t == 0) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    const uint32_t done = __hip_atomic_fetch_add(&ctl->bar_done, 1u, __ATOMIC_ACQ_REL,
+    const uint32_t done = __hip_atomic_fetch_add(bar + kBarDone, 1u, __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_AGENT);
     if (done == nb - 1u) {
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      st_agent32(&ctl->bar_done, 0u);
-      st_agent32(&ctl->bar_gather, 0u);
-      st_agent32(&ctl->bar_count, 0u);
+      st_agent32(bar + kBarDone, 0u);
+      st_agent32(bar + kBarGather, 0u);
+      st_agent32(bar + kBarCount, 0u);
       const uint32_t err = ld_agent32(&ctl->err);
       uint32_t flags = 0;
       if (err) flags |= kFastErr;
@@ -2416,9 +2397,9 @@ hipError_t insert_batch_grid(uint32_t words, BatchLaunch *out) {
 hipError_t launch_insert_batch(const PropArgs &a, const uint32_t *src, const uint32_t *dst,
                                uint64_t count, uint32_t n, Ovf *ovf, uint64_t ovf_cap, Mirror *m,
                                uint32_t seq, uint32_t max_frontier, u64 start_ticks,
-                               u64 wait_ticks, uint32_t grid, hipStream_t s) {
+                               u64 wait_ticks, uint32_t *bar, uint32_t grid, hipStream_t s) {
   DBL_LAUNCH_W(a.L.words, k_insert_batch, dim3(grid), dim3(kLocalThreads), s, a, src, dst, count,
-               n, ovf, ovf_cap, m, seq, max_frontier, start_ticks, wait_ticks);
+               n, ovf, ovf_cap, m, seq, max_frontier, start_ticks, wait_ticks, bar);
   return hipGetLastError();
 }
 
