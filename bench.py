@@ -408,27 +408,41 @@ def main():
                 f"{alone_summ['query']['latency_ms_p99']:.2f}), equal {same}")
         return res
 
+    T4_SAMPLE = 1024
+
     def table4(plain_answers):
-        """The shape of the paper's Table 4 on this workload: the 1,000,000 queries answered
-        with DL only, BL only and both (DBL), on the index after the plain form's insertions;
-        the share each decides by labels alone, its class histogram and its batch time. The
-        answers are exact in every mode."""
+        """The shape of the paper's Table 4 on this workload: queries answered with DL only, BL
+        only and both (DBL), on the index after the plain form's insertions; the share each
+        decides by labels alone, its class histogram and its batch time. The answers are exact
+        in every mode. DL only and DBL run on all the queries. Without the DL rules and prune,
+        every reachable pair needs a pruned BFS that explores much of the graph, so BL only
+        runs on the first T4_SAMPLE queries (the other two modes too, for a like-for-like
+        comparison), in a query context whose BFS queues hold every vertex (no search leaves
+        its wave for the whole-device BFS)."""
         ix = dbl.Index.build(w.n, src, dst, edges_unique=True)
         ix.insert_edges(isrc, idst)
-        res = {}
-        for name, rules in (("DL", 1), ("BL", 2), ("DBL", 3)):
-            o = torch.empty_like(out)
-            ix.query_rules(qu, qv, rules, out=o)  # warm
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            ix.query_rules(qu, qv, rules, out=o)
-            dt = time.perf_counter() - t0
-            a = o.cpu().numpy()
-            cls = np.bincount(a >> 1, minlength=7)
-            res[name] = {"label_decided_frac": float(cls[:5].sum() / n_q),
-                         "class_histogram": {dbl.CLASS_NAMES[i]: int(cls[i]) for i in range(7)},
-                         "batch_ms": dt * 1e3,
-                         "answers_equal_plain": bool(np.array_equal(a & 1, plain_answers & 1))}
+        ctx = ix.query_context(bfs_slots=256, queue_cap=w.n)
+        k = min(T4_SAMPLE, n_q)
+        res = {"all": {"queries": n_q}, "sample": {"queries": k, "which": "the first queries"}}
+        for part, cnt, modes in (("all", n_q, (("DL", 1), ("DBL", 3))),
+                                 ("sample", k, (("DL", 1), ("BL", 2), ("DBL", 3)))):
+            for name, rules in modes:
+                o = torch.empty(cnt, dtype=torch.uint8, device=dev)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                ctx.query_rules(qu[:cnt], qv[:cnt], rules, out=o)
+                dt = time.perf_counter() - t0
+                a = o.cpu().numpy()
+                cls = np.bincount(a >> 1, minlength=7)
+                res[part][name] = {
+                    "label_decided_frac": float(cls[:5].sum() / cnt),
+                    "class_histogram": {dbl.CLASS_NAMES[i]: int(cls[i]) for i in range(7)},
+                    "batch_ms": dt * 1e3,
+                    "answers_equal_plain": bool(np.array_equal(a & 1, plain_answers[:cnt] & 1))}
+                log(f"table 4 shape ({part}, {cnt} queries), {name}: "
+                    f"{res[part][name]['label_decided_frac']:.4f} decided by labels, "
+                    f"{dt * 1e3:.1f} ms")
+        ctx.close()
         ix.close()
         return res
 
@@ -456,22 +470,30 @@ def main():
         res = {}
         qb = 65536
         mk = lambda: dbl.Index.build(w.n, src, dst, edges_unique=True)  # noqa: E731
-        def insert_stream(ix, bsz):
-            """Insert the whole stream in batches of bsz on ix; the timing entry."""
-            torch.cuda.synchronize()
-            times = []
-            t0 = time.perf_counter()
-            for lo in range(0, n_ins, bsz):
-                tb = time.perf_counter()
-                ix.insert_edges(isrc[lo:lo + bsz], idst[lo:lo + bsz])
-                times.append(time.perf_counter() - tb)
-            t_ins = time.perf_counter() - t0
-            same = all(torch.equal(a, b) for a, b in zip(ix.labels(), plain_labels))
-            return {"edges_per_s": n_ins / t_ins, "batches": len(times),
+        def insert_stream(make, tuning, bsz):
+            """Insert the whole stream in batches of bsz, on fresh indexes with `tuning`, repeated
+            until at least 10 batches were timed (the 100k stream is one batch); the timing
+            entry, with the median pass as its rate."""
+            times, passes, same, stalls = [], [], True, 0
+            while len(times) < 10:
+                ix = make()
+                ix.set_tuning(**tuning)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for lo in range(0, n_ins, bsz):
+                    tb = time.perf_counter()
+                    ix.insert_edges(isrc[lo:lo + bsz], idst[lo:lo + bsz])
+                    times.append(time.perf_counter() - tb)
+                passes.append(time.perf_counter() - t0)
+                same &= all(torch.equal(a, b) for a, b in zip(ix.labels(), plain_labels))
+                stalls += ix.stats()["batch_stalls"]
+                ix.close()
+            t_ins = float(np.median(passes))
+            return {"edges_per_s": n_ins / t_ins, "batches": len(times), "passes": len(passes),
                     "batch_ms_p50": float(np.percentile(times, 50) * 1e3),
                     "batch_ms_p99": float(np.percentile(times, 99) * 1e3),
                     "speedup_vs_plain": (n_ins / t_ins) / (n_ins / insert_s),
-                    "labels_equal_plain": bool(same), "batch_stalls": ix.stats()["batch_stalls"]}
+                    "labels_equal_plain": bool(same), "batch_stalls": stalls}
 
         # the three forms of an insertion batch above the single-workgroup limit, default knobs
         forms = {"multi_launch": dict(insert_persistent=0),
@@ -480,12 +502,16 @@ def main():
         for bsz in (1000, 10000, 100000):
             if bsz > n_ins:
                 continue
-            tuned = autotune.tune_insertions(mk, isrc, idst, bsz, w.m, max_batches=10)
-            ix = mk()
-            ix.set_tuning(**{k: tuned[k] for k in autotune.INSERT_KNOBS})
-            entry = insert_stream(ix, bsz)
-            entry["tuning"] = {k: tuned[k] for k in autotune.INSERT_KNOBS}
+            tuned = autotune.tune_insertions(mk, isrc, idst, bsz, w.m, max_batches=30,
+                                             progress=log)
+            knobs = {k: tuned[k] for k in autotune.INSERT_KNOBS}
+            entry = insert_stream(mk, knobs, bsz)
+            entry["tuning"] = knobs
+            log(f"batches of {bsz}: {entry['edges_per_s']:.3g} edges/s with {entry['tuning']}")
             if bsz == 1000:
+                # query batches on the index after every insertion
+                ix = mk()
+                ix.insert_edges(isrc, idst)
                 qtuned = autotune.tune_queries(ix, qu, qv, qb, w.m)
                 # each batch as two kernel launches, then as one graph launch (the graph is
                 # instantiated by an untimed first batch and replayed with new arguments)
@@ -507,14 +533,18 @@ def main():
                         "batch_ms_p99": float(np.percentile(qt, 99) * 1e3),
                         "answers_equal_plain": bool(torch.equal(qout, plain_answers)),
                         "tuning": {"bfs_slots": qtuned["bfs_slots"], "query_graph": graph}}
-                ix.set_tuning(query_graph=0)
-            ix.close()
-            entry["forms"] = {}
-            for name, kw in forms.items():
-                fx = mk()
-                fx.set_tuning(small_batch=min(bsz - 1, 2048), **kw)
-                entry["forms"][name] = insert_stream(fx, bsz)
-                fx.close()
+                ix.close()
+            entry["forms"] = {name: insert_stream(mk, dict(small_batch=min(bsz - 1, 2048), **kw),
+                                                  bsz)
+                              for name, kw in forms.items()}
+            # the autotuner times a few batches per candidate, so its pick can lose to a fixed
+            # form on the whole stream: the entry's rate is the fastest setting measured here
+            best = max([("tuned", entry)] + list(entry["forms"].items()),
+                       key=lambda kv: kv[1]["edges_per_s"])
+            entry["tuned_edges_per_s"] = entry["edges_per_s"]
+            entry["edges_per_s"] = best[1]["edges_per_s"]
+            entry["speedup_vs_plain"] = best[1]["speedup_vs_plain"]
+            entry["fastest"] = best[0]
             res[f"insert_batch_{bsz}"] = entry
         return res
 
@@ -541,9 +571,12 @@ def main():
     insert_s = float(np.mean([r["insert_s"] for r in results]))
     query_s = float(np.mean([r["query_s"] for r in results]))
     s_build, s_ins, s_q, plain_labels = diagnostics()
+    log("diagnostic pass done")
     extras = args.extras == "on"
     per_request = launch_per_request(plain_labels) if extras else None
     warm_off = server_warm_off(plain_labels) if extras else None
+    if extras:
+        log("single-request comparisons done")
     table4_res = table4(out.cpu().numpy()) if extras else None
     batched_res = batched(plain_labels, out.clone()) if extras else None
     serving_res = (serving() if extras and args.workload == "lj" and args.serving == "on"
@@ -628,7 +661,11 @@ def main():
         "dtype": "u64",
         "data": "synthetic",
         "config": {"workload": desc, "n": w.n, "m": w.m, "insertions": n_ins,
-                   "insertion_form": "one edge per request", "queries": n_q,
+                   "insertion_form": "one edge per request",
+                   "insertion_note": ("R-MAT insertions continuing the build stream: "
+                                      f"{ins_relaxed} edges relaxed over all {n_ins} requests, "
+                                      "so most requests change no label"),
+                   "queries": n_q,
                    "query_batch": n_q, "landmarks": 64, "bl_bits": 64},
         "build_ms": build_s * 1e3,
         "insert_edges_per_s": n_ins / insert_s,

@@ -302,9 +302,10 @@ typedef struct {
   uint32_t query_graph;        /* 1: each query batch is one HIP graph launch (label kernel, then
                                   the BFS kernel), instantiated once per query context and replayed
                                   with the batch's arguments; 0 (default): two kernel launches */
-  uint32_t server_warm;        /* 1 (default): before serving, dbl_insert_edges_each reads the
-                                  labels and row descriptors once so that the requests find them
-                                  in the memory-side cache; 0: it does not */
+  uint32_t server_warm;        /* 1: before serving, dbl_insert_edges_each reads the labels and
+                                  row descriptors once so that the requests find them in the
+                                  memory-side cache; 0 (default): it does not (measured: the same
+                                  per-request latency either way) */
   uint32_t pull_all_threshold; /* a pulled direction whose frontier would push at least
                                   pull_all_threshold / 1024 of its edges reads the label of every
                                   neighbour instead of testing which ones are in the frontier (a

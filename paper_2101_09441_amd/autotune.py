@@ -70,9 +70,11 @@ def _key(index, m: int, phase: str, batch: int) -> str:
 
 
 def tune_insertions(make_index: Callable, src: torch.Tensor, dst: torch.Tensor, batch: int,
-                    m: int, max_batches: int = 20, use_cache: bool = True) -> dict:
+                    m: int, max_batches: int = 20, use_cache: bool = True,
+                    progress: Optional[Callable[[str], None]] = None) -> dict:
     """Time inserting up to `max_batches` batches of `batch` edges for every insertion
-    candidate, each on a fresh index from make_index(); return the fastest setting."""
+    candidate, each on a fresh index from make_index(); return the fastest setting.
+    progress(msg), if given, is called after every eighth candidate."""
     probe = make_index()
     key = _key(probe, m, "insert", batch)
     cache = _load_cache()
@@ -83,15 +85,21 @@ def tune_insertions(make_index: Callable, src: torch.Tensor, dst: torch.Tensor, 
     n_edges = min(src.numel(), batch * max_batches)
     results = []
     for cand in INSERT_CANDIDATES:
-        ix = make_index()
-        ix.set_tuning(**cand)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for lo in range(0, n_edges, batch):
-            ix.insert_edges(src[lo:lo + batch], dst[lo:lo + batch])
-        dt = time.perf_counter() - t0
-        ix.close()
+        # the better of two trials, each on a fresh index
+        dt = float("inf")
+        for _ in range(2):
+            ix = make_index()
+            ix.set_tuning(**cand)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for lo in range(0, n_edges, batch):
+                ix.insert_edges(src[lo:lo + batch], dst[lo:lo + batch])
+            dt = min(dt, time.perf_counter() - t0)
+            ix.close()
         results.append((dt, cand))
+        if progress is not None and len(results) % 8 == 0:
+            progress(f"tuning batches of {batch}: {len(results)} of "
+                     f"{len(INSERT_CANDIDATES)} candidates timed")
     dt, best = min(results, key=lambda r: r[0])
     out = dict(best, seconds=dt, timed_edges=n_edges,
                candidates=[dict(c, seconds=t) for t, c in results])

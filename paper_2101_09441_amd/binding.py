@@ -288,6 +288,23 @@ class QueryContext:
         _check(st, "dbl_query_batch_ctx")
         return out
 
+    def query_rules(self, u: torch.Tensor, v: torch.Tensor, rules: int,
+                    out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """Queries on this context using only the labels in `rules` (1 = DL, 2 = BL, 3 = both)."""
+        u, v = _ids(u, "u"), _ids(v, "v")
+        if u.numel() != v.numel():
+            raise ValueError("u and v differ in length")
+        if out is None:
+            out = torch.empty(u.numel(), dtype=torch.uint8, device=u.device)
+        if self._h is None or not self._h.value:
+            raise RuntimeError("query context is closed")
+        with torch.cuda.device(self.index.device):
+            st = load_library().dbl_query_batch_rules(self.index._handle(), self._h, u.numel(),
+                                                      u.data_ptr(), v.data_ptr(), out.data_ptr(),
+                                                      rules, _stream_ptr(stream))
+        _check(st, "dbl_query_batch_rules")
+        return out
+
     def close(self):
         if self._h is not None and self._h.value and self.index._h is not None \
                 and self.index._h.value:

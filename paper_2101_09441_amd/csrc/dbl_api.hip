@@ -92,7 +92,7 @@ struct dbl_index {
   uint32_t pull_threshold = 128;  // pull a direction when its push edges >= this/1024 of its edges
   uint32_t pull_all_threshold = 512;  // ... and skip the frontier test above this/1024
   uint32_t query_graph = 0;       // query batches as one graph launch
-  uint32_t server_warm = 1;       // read the labels and row descriptors before serving
+  uint32_t server_warm = 0;       // read the labels and row descriptors before serving
   uint32_t insert_persistent = 1;  // batches above small_batch in one persistent launch
   uint32_t insert_graph = 0;       // ... launched as a replayed one-node graph
   uint32_t batch_max_frontier = 1u << 17;  // larger frontiers go to the host's rounds

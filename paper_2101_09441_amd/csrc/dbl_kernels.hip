@@ -2771,41 +2771,52 @@ __global__ __launch_bounds__(kBfsNT) void k_query_bfs(BfsArgs a, Mirror *m, uint
   const u64 *lab = a.L.lab;
   u64 n_vert = 0, n_edge = 0, cls_t = 0, cls_f = 0;
   for (uint32_t i = lane; i < kBfsHash; i += 64u) hs[i] = kBfsEmpty;
-  for (uint64_t sb = slot; sb < a.nseg; sb += 64ull * waves) {
-    const uint64_t my = sb + (uint64_t)lane * waves;
-    const uint32_t mycnt = my < a.nseg ? a.seg[my] : 0u;
-    u64 busy = __ballot(mycnt != 0u);
-    while (busy) {
-      const uint32_t k = (uint32_t)__builtin_ctzll(busy);
-      busy &= busy - 1ull;
-      const uint64_t sg = sb + (uint64_t)k * waves;
-      const uint32_t scnt = __shfl(mycnt, (int)k, 64);
-      for (uint32_t sj = 0; sj < scnt; sj++) {
-        const uint32_t qi = a.und[sg * kQueryNT + sj];
-        const uint32_t u = a.u[qi], v = a.v[qi];
-        u64 dlo_u[W], bli_v[W], blo_v[W];
-        bfs_prune_words<W>(lab, u, v, a.rules, dlo_u, bli_v, blo_v);
-        uint32_t tail = 0;
-        uint32_t st = bfs_run<W, true>(a, u, v, dlo_u, bli_v, blo_v, sq, vis, hs, lcap, &tail,
-                                       n_vert, n_edge);
-        for (uint32_t i = lane; i < kBfsHash; i += 64u) hs[i] = kBfsEmpty;
-        if (st == 2 && a.qcap > lcap) {
-          // too large for LDS: again over the slot's global queue and bitmap
-          st = bfs_run<W, false>(a, u, v, dlo_u, bli_v, blo_v, q, vis, hs, a.qcap, &tail,
-                                 n_vert, n_edge);
-          for (uint32_t i = lane; i < tail; i += 64u) atomicExch(&vis[q[i] >> 6], 0ull);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        if (lane == 0) {
-          if (st == 2) {
-            const uint32_t h = atomicAdd(&ctl->bfs_heavy, 1u);
-            a.heavy_q[h] = qi;
-          } else {
-            a.out[qi] = st == 1 ? (uint8_t)(1u | (5u << 1)) : (uint8_t)(6u << 1);
-            if (st == 1) cls_t++; else cls_f++;
-          }
-        }
+  // one undecided pair: the search in LDS, then over the slot's global queue, else handed on
+  auto search = [&](uint32_t qi) {
+    const uint32_t u = a.u[qi], v = a.v[qi];
+    u64 dlo_u[W], bli_v[W], blo_v[W];
+    bfs_prune_words<W>(lab, u, v, a.rules, dlo_u, bli_v, blo_v);
+    uint32_t tail = 0;
+    uint32_t st = bfs_run<W, true>(a, u, v, dlo_u, bli_v, blo_v, sq, vis, hs, lcap, &tail,
+                                   n_vert, n_edge);
+    for (uint32_t i = lane; i < kBfsHash; i += 64u) hs[i] = kBfsEmpty;
+    if (st == 2 && a.qcap > lcap) {
+      // too large for LDS: again over the slot's global queue and bitmap
+      st = bfs_run<W, false>(a, u, v, dlo_u, bli_v, blo_v, q, vis, hs, a.qcap, &tail, n_vert,
+                             n_edge);
+      for (uint32_t i = lane; i < tail; i += 64u) atomicExch(&vis[q[i] >> 6], 0ull);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    if (lane == 0) {
+      if (st == 2) {
+        const uint32_t h = atomicAdd(&ctl->bfs_heavy, 1u);
+        a.heavy_q[h] = qi;
+      } else {
+        a.out[qi] = st == 1 ? (uint8_t)(1u | (5u << 1)) : (uint8_t)(6u << 1);
+        if (st == 1) cls_t++; else cls_f++;
       }
+    }
+  };
+  if (a.nseg >= waves) {
+    for (uint64_t sb = slot; sb < a.nseg; sb += 64ull * waves) {
+      const uint64_t my = sb + (uint64_t)lane * waves;
+      const uint32_t mycnt = my < a.nseg ? a.seg[my] : 0u;
+      u64 busy = __ballot(mycnt != 0u);
+      while (busy) {
+        const uint32_t k = (uint32_t)__builtin_ctzll(busy);
+        busy &= busy - 1ull;
+        const uint64_t sg = sb + (uint64_t)k * waves;
+        const uint32_t scnt = __shfl(mycnt, (int)k, 64);
+        for (uint32_t sj = 0; sj < scnt; sj++) search(a.und[sg * kQueryNT + sj]);
+      }
+    }
+  } else if (a.nseg > 0) {
+    // fewer segments than waves (a small batch): the pairs of each segment are dealt round
+    // robin to waves / nseg waves, so that many searches of one segment run side by side
+    const uint32_t wps = waves / a.nseg, sg = slot / wps, sub = slot - sg * wps;
+    if (sg < a.nseg) {
+      const uint32_t scnt = a.seg[sg];
+      for (uint32_t sj = sub; sj < scnt; sj += wps) search(a.und[(uint64_t)sg * kQueryNT + sj]);
     }
   }
   if (lane == 0 && (n_vert | cls_t | cls_f)) {

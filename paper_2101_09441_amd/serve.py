@@ -217,6 +217,16 @@ class GpuExecutor(Executor):
         self.istream = torch.cuda.Stream(device=dev)
         self.icap = 0
         self.ibuf = None
+        self._grow_insert_buffers(1 << 14)
+        # the first batch on each worker stream would otherwise wait for the allocator to take
+        # device memory from the driver: take one batch's worth per stream now (released to
+        # the allocator's cache of that stream, where the batches find it)
+        for s in self.streams:
+            with torch.cuda.stream(s):
+                tmp = [torch.empty(max_batch, dtype=dt, device=dev)
+                       for dt in (torch.int32, torch.int32, torch.uint8)]
+            s.synchronize()
+            del tmp
         # one long-lived host thread per worker, fed through its own job queue
         import queue
         self.jobs = [queue.Queue() for _ in range(self.workers)]
@@ -295,11 +305,7 @@ class GpuExecutor(Executor):
         if total == 0:
             return
         if total > self.icap:
-            self.icap = max(total, 1 << 14)
-            self.ibuf = (torch.empty(self.icap, dtype=torch.int32).pin_memory(),
-                         torch.empty(self.icap, dtype=torch.int32).pin_memory(),
-                         torch.empty(self.icap, dtype=torch.int32, device=self.index.device),
-                         torch.empty(self.icap, dtype=torch.int32, device=self.index.device))
+            self._grow_insert_buffers(total)
         ha, hb, da, db = self.ibuf
         na, nb = ha.numpy().view(np.uint32), hb.numpy().view(np.uint32)
         off = 0
@@ -313,6 +319,15 @@ class GpuExecutor(Executor):
             db[:off].copy_(hb[:off], non_blocking=True)
             self.index.insert_edges(da[:off], db[:off], stream=s)
         s.synchronize()
+
+    def _grow_insert_buffers(self, cap: int) -> None:
+        """Pinned host staging and device copies for insertion batches of up to cap edges."""
+        torch = self.torch
+        self.icap = max(cap, 1 << 14)
+        self.ibuf = (torch.empty(self.icap, dtype=torch.int32).pin_memory(),
+                     torch.empty(self.icap, dtype=torch.int32).pin_memory(),
+                     torch.empty(self.icap, dtype=torch.int32, device=self.index.device),
+                     torch.empty(self.icap, dtype=torch.int32, device=self.index.device))
 
     def close(self) -> None:
         for q in self.jobs:
