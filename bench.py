@@ -124,6 +124,19 @@ def cpu_baseline(w, n_ins_sample, n_q_sample):
     }
 
 
+def calibration_copy(dev):
+    """One 1 GiB device-to-device copy (1 GiB read, 1 GiB written): the reference dispatch for
+    scaling memory counters."""
+    import torch
+    a = torch.ones(1 << 28, dtype=torch.int32, device=dev)
+    c = torch.empty_like(a)
+    torch.cuda.synchronize()
+    c.copy_(a)
+    torch.cuda.synchronize()
+    del a, c
+    log("calibration copy: 1 GiB read, 1 GiB written")
+
+
 def bench_scale(args):
     """The batched form at scale: R-MAT 2^25 vertices, the distinct edges of 2^30 draws
     (~1.0e9), 10M insertions in batches of 100k, 10M Zipf(1.1)-skewed queries in batches of
@@ -135,6 +148,8 @@ def bench_scale(args):
     import paper_2101_09441_amd as dbl
 
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        calibration_copy(dev)
     t0 = time.perf_counter()
     w = dblgen.scale_workload()
     log(f"scale workload generated in {time.perf_counter() - t0:.0f} s: n={w.n} m={w.m}")
@@ -320,13 +335,7 @@ def main():
     qu, qv = dbl.to_device_ids(w.q_u), dbl.to_device_ids(w.q_v)
     out = torch.empty(len(w.q_u), dtype=torch.uint8, device=dev)
     if args.calibrate_copy:
-        a = torch.ones(1 << 28, dtype=torch.int32, device=dev)
-        c = torch.empty_like(a)
-        torch.cuda.synchronize()
-        c.copy_(a)
-        torch.cuda.synchronize()
-        del a, c
-        log("calibration copy: 1 GiB read, 1 GiB written")
+        calibration_copy(dev)
     torch.cuda.synchronize()
 
     kinds = [k for k in args.time_kernels.split(",") if k]
