@@ -125,6 +125,8 @@ typedef struct {
                                  publishing its status (device wall clock) */
   uint64_t batch_stalls;      /* persistent insertion launches that ran out of time at a grid
                                  barrier and were finished another way (dbl_tuning) */
+  uint64_t build_long_bins;   /* vertex-range bins of the last build (both directions) that held
+                                 so many edges that they were split over several workgroups */
 } dbl_stats;
 
 /* Fill *opt with the defaults listed above. */
@@ -140,7 +142,9 @@ void dbl_default_options(dbl_options *opt);
  * edge for the partitioned edges and keep flags, the de-duplication table (16-32 bytes per
  * edge) unless edges_unique, and, once a direction's rows are assembled in LDS (row_fill), 8
  * bytes per edge of staging, which lives in that table when there is one. If the staging
- * buffer cannot be had, rows are filled directly instead.
+ * buffer cannot be had, rows are filled directly instead. A vertex range holding far more than
+ * its share of the edges (ids numbered by degree) is split over several workgroups, with a few
+ * MB of cursors.
  * Errors: INVALID_ARG (bad options or sizes), VERTEX_RANGE (an id >= n), OUT_OF_MEMORY,
  * DEVICE. On error no index is returned and nothing is leaked.
  */

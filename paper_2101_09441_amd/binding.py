@@ -72,6 +72,7 @@ class DblStats(ctypes.Structure):
         ("server_requests", ctypes.c_uint64),
         ("server_busy_us", ctypes.c_double),
         ("batch_stalls", ctypes.c_uint64),
+        ("build_long_bins", ctypes.c_uint64),
     ]
 
 

@@ -108,6 +108,7 @@ struct dbl_index {
   hipGraphNode_t ig_node = nullptr;
   uint32_t ig_words = 0, ig_grid = 0;
   uint64_t batch_stalls_early = 0, batch_stalls_late = 0;
+  uint64_t build_long_bins = 0;  // bins of the last build split over several workgroups
   // query contexts: the default one and those created by callers (guarded by ctx_mu)
   uint32_t slots_opt = 0, qcap_opt = 0;
   dbl_query_ctx *qctx = nullptr;
@@ -1030,11 +1031,16 @@ dbl_status do_build(dbl_index *ix, uint64_t m, const uint32_t *src, const uint32
     if (st == DBL_OK) st = dalloc(&offs, (uint64_t)nblk * nbins);
     if (st == DBL_OK) st = dalloc(&btmp, dbl::scan_tmp_words(nblk * nbins));
     if (st == DBL_OK) st = dalloc(&bkept, 3);  // kept edges, then the grouping sample
+    u64 *bstarts = nullptr;                    // first edge of each bin (long-bin test)
+    if (st == DBL_OK) st = dalloc(&bstarts, nbins);
     if (st == DBL_OK) st = dalloc(&edges, m);
     // staging for the row fill, taken when a direction wants it: the dedup table (at least 2m
     // entries) is free by then; without one, a buffer of its own, and without that the rows
     // fill directly
     u64 *own_tmp = nullptr;
+    // long bins of the current direction: chunk table and per-bin row cursors
+    dbl::LongChunk *chunks_d = nullptr;
+    uint32_t *cursors_d = nullptr;
     for (uint32_t d = 0; d < 2 && st == DBL_OK; d++) {
       Csr &g = d ? ix->r : ix->f;
       uint64_t &total = d ? ix->r_total : ix->f_total;
@@ -1050,8 +1056,47 @@ dbl_status do_build(dbl_index *ix, uint64_t m, const uint32_t *src, const uint32
         same = kr[1];
         sampled = kr[2];
       }
+      // A bin with far more than its share of the edges (ids that put the high-degree vertices
+      // in a few ranges) would hold up the one workgroup it gets: such bins are cut into chunks
+      // of about one workgroup's share (kept / 512: two workgroups on each of 256 units), each
+      // taken by a workgroup of its own.
+      u64 long_min = ~0ull;
+      std::vector<dbl::LongChunk> chunks;
+      uint32_t nlong = 0;
+      dfree(chunks_d);
+      dfree(cursors_d);
+      if (e == hipSuccess && m && (1u << dbl::bin_shift(n)) <= dbl::kBinVertsMax) {
+        std::vector<u64> starts(nbins);
+        e = dbl::launch_bin_starts(offs, nblk, nbins, bstarts, s);
+        if (e == hipSuccess)
+          e = hipMemcpyAsync(starts.data(), bstarts, sizeof(u64) * nbins, hipMemcpyDeviceToHost,
+                             s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        const u64 share = (kept + 511) / 512;
+        long_min = std::max<u64>(4 * share, 1ull << 16);
+        const u64 chunk = std::max<u64>(share, 1ull << 16);
+        for (uint32_t b = 0; e == hipSuccess && b < nbins; b++) {
+          const u64 lo = starts[b], hi = b + 1 < nbins ? starts[b + 1] : kept;
+          if (hi - lo < long_min) continue;
+          for (u64 c = lo; c < hi; c += chunk) chunks.push_back({b, nlong, c, std::min(c + chunk, hi)});
+          nlong++;
+        }
+        ix->build_long_bins += nlong;
+        if (!chunks.empty() && e == hipSuccess) {
+          st = dalloc(&chunks_d, chunks.size());
+          if (st == DBL_OK) st = dalloc(&cursors_d, (uint64_t)nlong * dbl::kBinVertsMax);
+          if (st != DBL_OK) break;
+          e = hipMemcpyAsync(chunks_d, chunks.data(), sizeof(dbl::LongChunk) * chunks.size(),
+                             hipMemcpyHostToDevice, s);
+          if (e == hipSuccess)
+            e = dbl::launch_fill_u32(cursors_d, 0u, (uint64_t)nlong * dbl::kBinVertsMax, s);
+          if (e == hipSuccess) e = dbl::launch_fill_u32(g.deg, 0u, n, s);  // long bins add up
+        }
+      }
+      const uint32_t nchunks = (uint32_t)chunks.size();
       if (e == hipSuccess && m)
-        e = dbl::launch_bin_rows(edges, offs, nblk, n, bkept, kept, g.deg, nullptr, nullptr, s);
+        e = dbl::launch_bin_rows(edges, offs, nblk, n, bkept, kept, g.deg, nullptr, nullptr,
+                                 long_min, chunks_d, nchunks, cursors_d, s);
       else if (e == hipSuccess)
         e = dbl::launch_fill_u32(g.deg, 0u, n, s);
       if (e == hipSuccess)
@@ -1077,11 +1122,16 @@ dbl_status do_build(dbl_index *ix, uint64_t m, const uint32_t *src, const uint32
         if (!table.p && !own_tmp && dalloc(&own_tmp, m) != DBL_OK) own_tmp = nullptr;
         fill_tmp = table.p ? table.p : own_tmp;
       }
-      if (m) e = dbl::launch_bin_rows(edges, offs, nblk, n, bkept, kept, g.deg, &g, fill_tmp, s);
+      if (m)
+        e = dbl::launch_bin_rows(edges, offs, nblk, n, bkept, kept, g.deg, &g, fill_tmp,
+                                 long_min, chunks_d, nchunks, cursors_d, s);
       if (e == hipSuccess) e = hipStreamSynchronize(s);
       if (e != hipSuccess) st = from_hip(e);
     }
     if (st != DBL_OK) (void)hipStreamSynchronize(s);
+    dfree(chunks_d);
+    dfree(cursors_d);
+    dfree(bstarts);
     dfree(counts);
     dfree(offs);
     dfree(btmp);
@@ -1822,6 +1872,7 @@ dbl_status dbl_get_stats(const dbl_index *ix_c, dbl_stats *out) {
   out->pull_rounds = ix->pull_rounds;
   out->server_busy_us = (double)sc[0] * 1000.0 / (double)ix->clock_khz;
   out->batch_stalls = ix->batch_stalls_early + ix->batch_stalls_late;
+  out->build_long_bins = ix->build_long_bins;
   return DBL_OK;
 }
 

@@ -164,10 +164,24 @@ hipError_t launch_bin_edges(const uint32_t *key, const uint32_t *val, const uint
 // g == nullptr: deg[v] = degree of v; else fill g's rows (g.off set; g.deg is the degree and
 // stays so). fill_tmp (optional; kept_host entries, allowed only while the CSR holds fewer than
 // 2^32 column slots) lets the fill assemble runs of rows in LDS.
+// Bins of at least long_min edges are cut into chunks (LongChunk entries in device memory,
+// nchunks of them; slot = the bin's index among the long bins) handled by one workgroup each;
+// deg must be zero on entry when there are any, and the fill needs `cursors`, kBinVerts zeroed
+// words per long bin. long_min = ~0 and nchunks = 0: every bin in one workgroup.
+struct LongChunk {
+  uint32_t bin, slot;
+  unsigned long long lo, hi;
+};
+constexpr uint32_t kBinVertsMax = 16384;  // vertices of a bin handled in LDS (kBinVerts)
+// out[b] = offs[b * nblk] for b < nbins: the first partitioned edge of each bin
+hipError_t launch_bin_starts(const unsigned long long *offs, uint32_t nblk, uint32_t nbins,
+                             unsigned long long *out, hipStream_t s);
 hipError_t launch_bin_rows(const unsigned long long *edges, const unsigned long long *offs,
                            uint32_t nblk, uint32_t n, const unsigned long long *kept,
                            uint64_t kept_host, uint32_t *deg, const Csr *g,
-                           unsigned long long *fill_tmp, hipStream_t s);
+                           unsigned long long *fill_tmp, unsigned long long long_min,
+                           const LongChunk *chunks, uint32_t nchunks, uint32_t *cursors,
+                           hipStream_t s);
 // deg[key] += 1 per partitioned edge; rows filled from partitioned edges (g.deg zero on entry)
 hipError_t launch_deg_binned(const unsigned long long *edges, uint64_t cnt, uint32_t *deg,
                              hipStream_t s);

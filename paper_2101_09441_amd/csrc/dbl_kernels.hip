@@ -543,6 +543,7 @@ constexpr uint32_t kMaxBins = 4096;
 // One workgroup per bin counts degrees and fills rows in LDS while a bin spans at most kBinVerts
 // vertices (see k_bin_deg).
 constexpr uint32_t kBinVerts = 16384, kBinNT = 1024;
+static_assert(kBinVerts == kBinVertsMax, "bin width of the LDS kernels");
 
 // The fewest bins of at most kMaxBins: narrow bins keep the row writes of k_bin_fill within a
 // small window of the rows.
@@ -720,14 +721,15 @@ __global__ __launch_bounds__(kBinNT) void k_bin_deg(const u64 *__restrict__ edge
                                                     const u64 *__restrict__ offs, uint32_t nblk,
                                                     uint32_t nbins, uint32_t shift,
                                                     const u64 *__restrict__ kept, uint32_t n,
-                                                    uint32_t *__restrict__ deg) {
+                                                    uint32_t *__restrict__ deg, u64 long_min) {
   __shared__ uint32_t cnt[kBinVerts];
   for (uint32_t bin = blockIdx.x; bin < nbins; bin += gridDim.x) {
     const uint32_t first = bin << shift, nv = min(1u << shift, n - first);
-    for (uint32_t i = threadIdx.x; i < nv; i += kBinNT) cnt[i] = 0;
-    __syncthreads();
     u64 lo, hi;
     bin_range(offs, nblk, nbins, *kept, bin, lo, hi);
+    if (hi - lo >= long_min) continue;  // a long bin: k_bin_deg_long
+    for (uint32_t i = threadIdx.x; i < nv; i += kBinNT) cnt[i] = 0;
+    __syncthreads();
     for (u64 e0 = lo + threadIdx.x; e0 < hi; e0 += kBinNT * 4u) {
       uint32_t k[4];
 #pragma unroll
@@ -753,14 +755,15 @@ __global__ __launch_bounds__(kBinNT) void k_bin_fill(const u64 *__restrict__ edg
                                                      const u64 *__restrict__ offs, uint32_t nblk,
                                                      uint32_t nbins, uint32_t shift,
                                                      const u64 *__restrict__ kept, uint32_t n,
-                                                     Csr g) {
+                                                     Csr g, u64 long_min) {
   __shared__ uint32_t cur[kBinVerts];
   for (uint32_t bin = blockIdx.x; bin < nbins; bin += gridDim.x) {
     const uint32_t first = bin << shift, nv = min(1u << shift, n - first);
-    for (uint32_t i = threadIdx.x; i < nv; i += kBinNT) cur[i] = 0;
-    __syncthreads();
     u64 lo, hi;
     bin_range(offs, nblk, nbins, *kept, bin, lo, hi);
+    if (hi - lo >= long_min) continue;  // a long bin: k_bin_fill_long
+    for (uint32_t i = threadIdx.x; i < nv; i += kBinNT) cur[i] = 0;
+    __syncthreads();
     for (u64 e0 = lo + threadIdx.x; e0 < hi; e0 += kBinNT * 4u) {
       u64 kv[4];
       u64 o[4];
@@ -804,7 +807,8 @@ __global__ __launch_bounds__(kBinNT, 8) void k_bin_fill_staged(const u64 *__rest
                                                             uint32_t shift,
                                                             const u64 *__restrict__ kept,
                                                             uint32_t n, Csr g,
-                                                            u64 *__restrict__ tmp) {
+                                                            u64 *__restrict__ tmp,
+                                                            u64 long_min) {
   __shared__ uint32_t cur[kFillVerts];
   __shared__ uint32_t stage[kFillStage];
   __shared__ uint8_t sbid[kFillVerts];
@@ -816,6 +820,11 @@ __global__ __launch_bounds__(kBinNT, 8) void k_bin_fill_staged(const u64 *__rest
   const uint32_t t = threadIdx.x;
   for (uint32_t bin = blockIdx.x; bin < nbins; bin += gridDim.x) {
     const uint32_t first = bin << shift, nv = min(1u << shift, n - first);
+    {
+      u64 lo, hi;
+      bin_range(offs, nblk, nbins, *kept, bin, lo, hi);
+      if (hi - lo >= long_min) continue;  // a long bin: k_bin_fill_long
+    }
     const u64 base = g.off[first];
     const u64 span = g.off[first + nv - 1] + g.cap[first + nv - 1] - base;
     const uint32_t nsb =
@@ -932,24 +941,119 @@ __global__ __launch_bounds__(kBinNT, 8) void k_bin_fill_staged(const u64 *__rest
   }
 }
 
+// out[b] = offs[b * nblk]: where each bin's edges start (for the host's long-bin test)
+__global__ void k_bin_starts(const u64 *offs, uint32_t nblk, uint32_t nbins, u64 *out) {
+  for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < nbins; b += gridDim.x * blockDim.x)
+    out[b] = offs[(uint64_t)b * nblk];
+}
+
+hipError_t launch_bin_starts(const u64 *offs, uint32_t nblk, uint32_t nbins, u64 *out,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_bin_starts, dim3(grid_for(nbins, 256, 64)), dim3(256), 0, s, offs, nblk,
+                     nbins, out);
+  return hipGetLastError();
+}
+
+// Long bins. One workgroup per bin serialises a bin that holds far more than its share of the
+// edges (ids numbered so that the high-degree vertices share a few ranges). Such a bin is cut
+// into chunks of its edges, each taken by a workgroup of its own: a chunk counts its keys in LDS
+// and adds the counts to the (zeroed) global degrees; for the fill, it counts again, reserves
+// each row's share with one global atomic per row on the bin's cursor table (zeroed), and writes
+// its edges from those bases with LDS cursors.
+
+__global__ __launch_bounds__(kBinNT) void k_bin_deg_long(const u64 *__restrict__ edges,
+                                                         const LongChunk *__restrict__ chunks,
+                                                         uint32_t nchunks, uint32_t shift,
+                                                         uint32_t n, uint32_t *__restrict__ deg) {
+  __shared__ uint32_t cnt[kBinVerts];
+  for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    const LongChunk ch = chunks[c];
+    const uint32_t first = ch.bin << shift, nv = min(1u << shift, n - first);
+    for (uint32_t i = threadIdx.x; i < nv; i += kBinNT) cnt[i] = 0;
+    __syncthreads();
+    for (u64 e = ch.lo + threadIdx.x; e < ch.hi; e += kBinNT) {
+      const uint32_t k = (uint32_t)(__builtin_nontemporal_load(&edges[e]) >> 32);
+      uint32_t f, l;
+      lane_run(k, true, f, l);
+      if (__lane_id() == l) atomicAdd(&cnt[k - first], l - f + 1u);
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < nv; i += kBinNT)
+      if (cnt[i]) atomicAdd(&deg[first + i], cnt[i]);
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kBinNT) void k_bin_fill_long(const u64 *__restrict__ edges,
+                                                          const LongChunk *__restrict__ chunks,
+                                                          uint32_t nchunks, uint32_t shift,
+                                                          uint32_t n, Csr g,
+                                                          uint32_t *__restrict__ cursors) {
+  __shared__ uint32_t cur[kBinVerts];
+  for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    const LongChunk ch = chunks[c];
+    const uint32_t first = ch.bin << shift, nv = min(1u << shift, n - first);
+    for (uint32_t i = threadIdx.x; i < nv; i += kBinNT) cur[i] = 0;
+    __syncthreads();
+    for (u64 e = ch.lo + threadIdx.x; e < ch.hi; e += kBinNT) {
+      const uint32_t k = (uint32_t)(edges[e] >> 32);
+      uint32_t f, l;
+      lane_run(k, true, f, l);
+      if (__lane_id() == l) atomicAdd(&cur[k - first], l - f + 1u);
+    }
+    __syncthreads();
+    // this chunk's part of each row starts where the chunks before it (in any order) ended
+    uint32_t *bc = cursors + (uint64_t)ch.slot * kBinVerts;
+    for (uint32_t i = threadIdx.x; i < nv; i += kBinNT)
+      if (cur[i]) cur[i] = atomicAdd(&bc[i], cur[i]);
+    __syncthreads();
+    for (u64 e = ch.lo + threadIdx.x; e < ch.hi; e += kBinNT) {
+      const u64 kv = __builtin_nontemporal_load(&edges[e]);
+      const uint32_t k = (uint32_t)(kv >> 32);
+      // neighbouring lanes with the same row (long rows fill whole waves) take their slots
+      // with one LDS atomic per run, made by the run's last lane
+      uint32_t f, l;
+      lane_run(k, true, f, l);
+      uint32_t old = 0;
+      if (__lane_id() == l) old = atomicAdd(&cur[k - first], l - f + 1u);
+      const uint32_t base = __shfl(old, (int)l, 64);
+      g.col[g.off[k] + base + (__lane_id() - f)] = (uint32_t)kv;
+    }
+    __syncthreads();
+  }
+}
+
 // Degrees (deg[key] = edges of key) and row fill of partitioned edges. Rows are filled from
 // position 0; deg is left as the degree. With fill_tmp (kept_host entries, and every row of the
-// CSR within 2^32 column slots of its bin's first row) the fill goes through LDS.
+// CSR within 2^32 column slots of its bin's first row) the fill goes through LDS. Bins of at
+// least long_min edges are skipped by the per-bin kernels and handled in the chunks of `chunks`
+// (nchunks entries, device memory): for the degrees, deg must then be zero on entry; for the
+// fill, `cursors` holds kBinVerts zeroed words per long bin.
 hipError_t launch_bin_rows(const u64 *edges, const u64 *offs, uint32_t nblk, uint32_t n,
                            const u64 *kept, uint64_t kept_host, uint32_t *deg, const Csr *g,
-                           u64 *fill_tmp, hipStream_t s) {
+                           u64 *fill_tmp, u64 long_min, const LongChunk *chunks,
+                           uint32_t nchunks, uint32_t *cursors, hipStream_t s) {
   const uint32_t shift = bin_shift(n), nbins = ((n - 1) >> shift) + 1;
   if ((1u << shift) <= kBinVerts) {
     const uint32_t grid = min(nbins, 8192u);
+    const uint32_t cgrid = min(nchunks, 8192u);
     if (!g) {
       hipLaunchKernelGGL(k_bin_deg, dim3(grid), dim3(kBinNT), 0, s, edges, offs, nblk, nbins,
-                         shift, kept, n, deg);
-    } else if (fill_tmp && (1u << shift) <= kFillVerts) {
-      hipLaunchKernelGGL(k_bin_fill_staged, dim3(grid), dim3(kBinNT), 0, s, edges, offs, nblk,
-                         nbins, shift, kept, n, *g, fill_tmp);
+                         shift, kept, n, deg, long_min);
+      if (nchunks)
+        hipLaunchKernelGGL(k_bin_deg_long, dim3(cgrid), dim3(kBinNT), 0, s, edges, chunks,
+                           nchunks, shift, n, deg);
     } else {
-      hipLaunchKernelGGL(k_bin_fill, dim3(grid), dim3(kBinNT), 0, s, edges, offs, nblk, nbins,
-                         shift, kept, n, *g);
+      if (fill_tmp && (1u << shift) <= kFillVerts) {
+        hipLaunchKernelGGL(k_bin_fill_staged, dim3(grid), dim3(kBinNT), 0, s, edges, offs, nblk,
+                           nbins, shift, kept, n, *g, fill_tmp, long_min);
+      } else {
+        hipLaunchKernelGGL(k_bin_fill, dim3(grid), dim3(kBinNT), 0, s, edges, offs, nblk, nbins,
+                           shift, kept, n, *g, long_min);
+      }
+      if (nchunks)
+        hipLaunchKernelGGL(k_bin_fill_long, dim3(cgrid), dim3(kBinNT), 0, s, edges, chunks,
+                           nchunks, shift, n, *g, cursors);
     }
     return hipGetLastError();
   }

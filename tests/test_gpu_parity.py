@@ -713,6 +713,55 @@ def test_star_hub_heavy_rows():
     assert_labels_equal(g, o, "star insert")
 
 
+# ------------------------------------------------------------------ skewed vertex numbering
+
+def _degree_numbering(n, src, dst):
+    """New ids by descending total degree (ties by old id), so that the high-degree vertices
+    share the first id ranges: new_of[old id]."""
+    deg = np.bincount(src, minlength=n).astype(np.int64) + np.bincount(dst, minlength=n)
+    order = np.argsort(-deg, kind="stable")
+    new_of = np.empty(n, np.uint32)
+    new_of[order] = np.arange(n, dtype=np.uint32)
+    return new_of
+
+
+@pytest.mark.parametrize("row_fill", [1, 2])
+def test_degree_numbered_ids_split_long_bins(row_fill):
+    """R-MAT 2^18 numbered by descending degree: the first vertex-range bins hold far more than
+    their share of the edges and are split over several workgroups (direct and LDS-assembled
+    fill of the other bins); then a block of hubs with 40,000 edges each. Labels, answers and
+    insertions into the kept slack against the oracle."""
+    w = dblgen.make_rmat_workload("skew18", 18, 13, draws=8 << 18, n_insert=3000,
+                                  insert_kind="rmat", n_query=30000, query_kind="mixed")
+    new_of = _degree_numbering(w.n, w.src, w.dst)
+    src, dst = new_of[w.src], new_of[w.dst]
+    isrc, idst = new_of[w.ins_src], new_of[w.ins_dst]
+    g = gpu_index(w.n, src, dst, row_fill=row_fill)
+    assert g.stats()["build_long_bins"] > 0
+    o = oracle.OracleIndex(w.n, src, dst).build(threads=8)
+    assert_labels_equal(g, o, "degree-numbered build")
+    assert_queries_equal(g, o, w.q_u, w.q_v)
+    g.insert_edges(dev(isrc), dev(idst))
+    o.insert(isrc, idst)
+    assert_labels_equal(g, o, "degree-numbered, after insertions")
+    # hubs 0..7 with 40,000 out-edges and 40,000 in-edges each, over a sparse random rest
+    n = 1 << 16
+    rng = np.random.default_rng(21)
+    hs = np.repeat(np.arange(8, dtype=np.uint32), 40000)
+    ht = rng.integers(8, n, len(hs)).astype(np.uint32)
+    rs = rng.integers(8, n, 200000).astype(np.uint32)
+    rt = rng.integers(8, n, 200000).astype(np.uint32)
+    bsrc = np.concatenate([hs, ht, rs])
+    bdst = np.concatenate([ht, hs[::-1], rt])
+    g = gpu_index(n, bsrc, bdst, row_fill=row_fill, num_landmarks=16, bl_bits=16)
+    assert g.stats()["build_long_bins"] > 0
+    o = oracle.OracleIndex(n, bsrc, bdst).build(k=16, kp=16, threads=8)
+    assert_labels_equal(g, o, "hub block")
+    u = rng.integers(0, n, 20000).astype(np.uint32)
+    v = rng.integers(0, n, 20000).astype(np.uint32)
+    assert_queries_equal(g, o, u, v)
+
+
 # ------------------------------------------------------------------ several tiles, heavy rows
 
 def test_rmat18_build_insert_query():
