@@ -228,10 +228,10 @@ dbl_status dbl_query_batch_rules(dbl_index *ix, dbl_query_ctx *ctx, uint64_t cou
  * dbl_query_batch for callers that cannot allocate device memory (code that must not call
  * hipMalloc, tight serving loops, harnesses that forbid allocation). Same arguments, answers
  * and errors as dbl_query_batch; it calls no allocator at all. Its scratch (control block,
- * undecided-pair list, BFS slots, the whole-device BFS's bitmap and frontier ring) lives in one
+ * undecided-pair list, BFS slots, the whole-device BFS's bitmaps and queues) lives in one
  * static device array of 128 MiB that every GPU the library runs on holds from the loading of
  * the library's code until the process ends. Limits: with n the index's vertex count and
- * B = ceil(count / 256), 12.125 n + 2 KiB * B + 4 (n / 8 + 4 q) bytes (q = min(n, 65536, the
+ * B = ceil(count / 256), 8.25 n + 2 KiB * B + 4 (n / 8 + 4 q) bytes (q = min(n, 65536, the
  * index's bfs_queue_cap if set), each part rounded up to 256 bytes) must fit in the 128 MiB
  * less a 16 KiB header, i.e. at least four BFS slots must fit; a larger n or count returns
  * DBL_ERR_INVALID_ARG and does nothing. Up to 256 BFS slots (at most the index's bfs_slots

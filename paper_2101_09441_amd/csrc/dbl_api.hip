@@ -38,8 +38,8 @@ struct dbl_query_ctx {
   uint32_t slots = 0, qcap = 0;
   u64 *bfs_cnt = nullptr;  // per-slot BFS counters
   u64 *qcls = nullptr;     // per-block query class counters
-  u64 *gvis = nullptr;     // whole-device BFS: visited bitmap and frontier ring
-  uint32_t *gfq[3] = {nullptr, nullptr, nullptr};
+  u64 *gvis = nullptr;     // whole-device BFS: both sides' visited bitmaps and queues
+  uint32_t *gq[2] = {nullptr, nullptr};
   uint64_t bfs_heavy = 0;
   // graph form of a batch (label kernel -> BFS kernel), instantiated on first use and
   // replayed with new node arguments
@@ -752,7 +752,7 @@ void ctx_free(dbl_query_ctx *c) {
   dfree(c->bfs_cnt);
   dfree(c->qcls);
   dfree(c->gvis);
-  for (int i = 0; i < 3; i++) dfree(c->gfq[i]);
+  for (int i = 0; i < 2; i++) dfree(c->gq[i]);
 }
 
 // (Re)allocate the parts of a context sized by the vertex count: visited bitmaps and queues.
@@ -760,7 +760,7 @@ dbl_status ctx_size_bfs(dbl_index *ix, dbl_query_ctx *c, uint32_t slots, uint32_
   dfree(c->vis);
   dfree(c->bfs_queue);
   dfree(c->gvis);
-  for (int i = 0; i < 3; i++) dfree(c->gfq[i]);
+  for (int i = 0; i < 2; i++) dfree(c->gq[i]);
   const uint64_t words = (ix->n + 63) / 64;
   hipStream_t s0 = nullptr;
   CKS(dalloc(&c->vis, words * slots));
@@ -848,6 +848,47 @@ dbl_status ensure_default_ctx(dbl_index *ix) {
   return DBL_OK;
 }
 
+dbl::GbfsArgs gbfs_args(const dbl_index *ix, u64 *vis, uint64_t vis_words, uint32_t *const q[2],
+                        Ctl *ctl) {
+  dbl::GbfsArgs g;
+  g.L = {ix->lab, ix->lw};
+  g.g[0] = ix->f;
+  g.g[1] = ix->r;
+  g.vis[0] = vis;
+  g.vis[1] = vis + vis_words;
+  g.q[0] = q[0];
+  g.q[1] = q[1];
+  g.ctl = ctl;
+  return g;
+}
+
+// Whole-device BFS of pair qi = (u, v) from both ends (Algorithm 2's BFS, with each side's
+// prunes): each step expands the level of the side whose level has fewer edges; the search
+// ends when a side reaches the other's visited set (a path) or a side's next level is empty (no
+// path). sync() publishes the control block into h.
+template <class Sync>
+dbl_status gbfs_pair(const dbl::GbfsArgs &g, uint64_t vis_words, uint32_t u, uint32_t v,
+                     uint32_t qi, uint32_t rules, uint8_t *d_out, u64 *qcls, hipStream_t s,
+                     const dbl::Mirror &h, Sync sync) {
+  CK(dbl::launch_gbfs_start(g, vis_words, u, v, s));
+  CKS(sync());
+  uint32_t lo[2] = {0, 0}, hi[2] = {1, 1};
+  u64 seen[2] = {h.dstat[2], h.dstat[3]};  // summed degrees up to each side's level end
+  u64 pend[2] = {seen[0], seen[1]};        // edges of each side's pending level
+  while (!h.found) {
+    const uint32_t side = pend[1] < pend[0] ? 1u : 0u;
+    CK(dbl::launch_gbfs_round(g, side, lo[side], hi[side], u, v, rules, s));
+    CKS(sync());
+    lo[side] = hi[side];
+    hi[side] = h.fsize[side];
+    pend[side] = h.dstat[2 + side] - seen[side];
+    seen[side] = h.dstat[2 + side];
+    if (hi[side] == lo[side]) break;
+  }
+  CK(dbl::launch_gbfs_finish(g, qi, d_out, qcls, s));
+  return DBL_OK;
+}
+
 // Algorithm 2 over a batch with the scratch of context c (see dbl_query_batch).
 dbl_status run_queries(dbl_index *ix, dbl_query_ctx *c, uint64_t count, const uint32_t *d_u,
                        const uint32_t *d_v, uint8_t *d_out, hipStream_t s,
@@ -923,26 +964,17 @@ dbl_status run_queries(dbl_index *ix, dbl_query_ctx *c, uint64_t count, const ui
     CK(hipMemcpyAsync(hq.data(), c->heavy_q, sizeof(uint32_t) * nheavy, hipMemcpyDeviceToHost, s));
     CK(hipStreamSynchronize(s));
     if (!c->gvis) {
-      CKS(dalloc(&c->gvis, c->vis_words));
-      for (int i = 0; i < 3; i++) CKS(dalloc(&c->gfq[i], ix->n));
+      CKS(dalloc(&c->gvis, 2 * c->vis_words));
+      for (int i = 0; i < 2; i++) CKS(dalloc(&c->gq[i], ix->n));
     }
-    dbl::PropArgs a = prop_args(ix);
-    for (int i = 0; i < 3; i++) a.fq[i] = c->gfq[i];
-    a.ctl = c->ctl;
+    const dbl::GbfsArgs g = gbfs_args(ix, c->gvis, c->vis_words, c->gq, c->ctl);
     for (uint32_t i = 0; i < nheavy; i++) {
       uint32_t u = 0, v = 0;
       CK(hipMemcpyAsync(&u, d_u + hq[i], sizeof(uint32_t), hipMemcpyDeviceToHost, s));
       CK(hipMemcpyAsync(&v, d_v + hq[i], sizeof(uint32_t), hipMemcpyDeviceToHost, s));
       CK(hipStreamSynchronize(s));
-      CK(dbl::launch_gbfs_start(a, c->gvis, c->vis_words, u, s));
-      uint32_t ring = 0;
-      for (;;) {
-        CK(dbl::launch_gbfs_round(a, c->gvis, u, v, ring, rules, s));
-        ring = ring == 2 ? 0 : ring + 1;
-        CKS(sync_chan(c->ctl, c->mirror, c->hs, c->seq, s));
-        if (c->hs.found || c->hs.fsize[ring] == 0) break;
-      }
-      CK(dbl::launch_gbfs_finish(a, hq[i], d_out, c->qcls, s));
+      CKS(gbfs_pair(g, c->vis_words, u, v, hq[i], rules, d_out, c->qcls, s, c->hs,
+                    [&] { return sync_chan(c->ctl, c->mirror, c->hs, c->seq, s); }));
     }
     CK(hipStreamSynchronize(s));
     c->bfs_heavy += nheavy;
@@ -1397,7 +1429,7 @@ uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
 struct ScratchLayout {
   uint32_t slots = 0, qcap = 0;
   uint64_t vis_words = 0, vis = 0, queue = 0, und = 0, heavy_q = 0, seg = 0, gvis = 0;
-  uint64_t gfq[3] = {0, 0, 0};
+  uint64_t gq[2] = {0, 0};
   uint64_t end = 0;
 };
 
@@ -1411,7 +1443,7 @@ bool scratch_layout(const dbl_index *ix, uint64_t count, ScratchLayout *L) {
                                                            : kScratchMaxQueue);
   const uint64_t blocks = (count + dbl::kQueryNT - 1) / dbl::kQueryNT;
   const uint64_t fixed = align256(blocks * dbl::kQueryNT * 4) * 2 + align256(blocks * 4) +
-                         align256(L->vis_words * 8) + 3 * align256(n * 4);
+                         align256(2 * L->vis_words * 8) + 2 * align256(n * 4);
   const uint64_t per_slot = L->vis_words * 8 + (uint64_t)L->qcap * 4;
   const uint64_t room = kScratchBytes - kScrVis;
   if (fixed + 4 * per_slot + 512 > room) return false;
@@ -1431,9 +1463,9 @@ bool scratch_layout(const dbl_index *ix, uint64_t count, ScratchLayout *L) {
   L->seg = at;
   at += align256(blocks * 4);
   L->gvis = at;
-  at += align256(L->vis_words * 8);
-  for (int i = 0; i < 3; i++) {
-    L->gfq[i] = at;
+  at += align256(2 * L->vis_words * 8);
+  for (int i = 0; i < 2; i++) {
+    L->gq[i] = at;
     at += align256(n * 4);
   }
   L->end = at;
@@ -1503,16 +1535,21 @@ dbl_status run_queries_noalloc(const dbl_index *ix, ScratchDev *sd, uint64_t cou
   }
   if (h.bfs_heavy) {
     // pairs whose pruned BFS outgrew a slot: one whole-device BFS each (rare), over the
-    // scratch's own bitmap and frontier ring
-    dbl::PropArgs a = prop_args(ix);
-    for (int i = 0; i < 3; i++) a.fq[i] = (uint32_t *)(base + L.gfq[i]);
-    a.ctl = ctl;
-    u64 *gvis = (u64 *)(base + L.gvis);
+    // scratch's own bitmaps and queues
+    uint32_t *gq[2] = {(uint32_t *)(base + L.gq[0]), (uint32_t *)(base + L.gq[1])};
+    const dbl::GbfsArgs g = gbfs_args(ix, (u64 *)(base + L.gvis), L.vis_words, gq, ctl);
     const uint32_t *heavy_q = (const uint32_t *)(base + L.heavy_q);
     uint32_t seq = 1;
+    auto sync = [&]() -> dbl_status {
+      CK(dbl::launch_publish(ctl, mirror, ++seq, s));
+      CK(hipMemcpyAsync(&h, mirror, sizeof(h), hipMemcpyDeviceToHost, s));
+      CK(hipStreamSynchronize(s));
+      return h.seq == seq ? DBL_OK : DBL_ERR_DEVICE;
+    };
+    const uint32_t nheavy = h.bfs_heavy;  // h is rewritten by every sync
     uint32_t qi[64];
-    for (uint32_t i0 = 0; i0 < h.bfs_heavy; i0 += 64) {
-      const uint32_t nb = std::min<uint32_t>(64, h.bfs_heavy - i0);
+    for (uint32_t i0 = 0; i0 < nheavy; i0 += 64) {
+      const uint32_t nb = std::min<uint32_t>(64, nheavy - i0);
       CK(hipMemcpyAsync(qi, heavy_q + i0, sizeof(uint32_t) * nb, hipMemcpyDeviceToHost, s));
       CK(hipStreamSynchronize(s));
       for (uint32_t i = 0; i < nb; i++) {
@@ -1520,18 +1557,8 @@ dbl_status run_queries_noalloc(const dbl_index *ix, ScratchDev *sd, uint64_t cou
         CK(hipMemcpyAsync(&uv[0], d_u + qi[i], sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         CK(hipMemcpyAsync(&uv[1], d_v + qi[i], sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         CK(hipStreamSynchronize(s));
-        CK(dbl::launch_gbfs_start(a, gvis, L.vis_words, uv[0], s));
-        uint32_t ring = 0;
-        for (;;) {
-          CK(dbl::launch_gbfs_round(a, gvis, uv[0], uv[1], ring, DBL_RULES_ALL, s));
-          ring = ring == 2 ? 0 : ring + 1;
-          CK(dbl::launch_publish(ctl, mirror, ++seq, s));
-          CK(hipMemcpyAsync(&h, mirror, sizeof(h), hipMemcpyDeviceToHost, s));
-          CK(hipStreamSynchronize(s));
-          if (h.seq != seq) return DBL_ERR_DEVICE;
-          if (h.found || h.fsize[ring] == 0) break;
-        }
-        CK(dbl::launch_gbfs_finish(a, qi[i], d_out, qcls, s));
+        CKS(gbfs_pair(g, L.vis_words, uv[0], uv[1], qi[i], DBL_RULES_ALL, d_out, qcls, s, h,
+                      sync));
       }
     }
     CK(hipStreamSynchronize(s));

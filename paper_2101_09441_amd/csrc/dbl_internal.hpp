@@ -318,12 +318,26 @@ hipError_t launch_query_bfs(const BfsArgs &a, uint32_t slots, Mirror *m, uint32_
 hipError_t query_node_params(LabelsView L, uint64_t count, uint32_t slots, void **label_args,
                              void **bfs_args, hipKernelNodeParams *label,
                              hipKernelNodeParams *bfs);
-// grid BFS for one query (u, v) whose slot overflowed
-hipError_t launch_gbfs_start(const PropArgs &a, unsigned long long *vis, uint64_t vis_words,
-                             uint32_t u, hipStream_t s);
-hipError_t launch_gbfs_round(const PropArgs &a, unsigned long long *vis, uint32_t u, uint32_t v,
-                             uint32_t ring, uint32_t rules, hipStream_t s);
-hipError_t launch_gbfs_finish(const PropArgs &a, uint32_t qi, uint8_t *out,
+// Whole-device BFS of one query (u, v) whose slot overflowed, searched from both ends. Side 0
+// follows out-edges from u, side 1 in-edges from v; each side has a visited bitmap and a queue
+// of n entries whose levels are consecutive segments. In the control block fsize[side] is the
+// side's queue tail, ctr[kCtrFrontEdges + side] the summed degrees of its queued vertices, and
+// found is set once a side reaches a vertex the other has visited.
+struct GbfsArgs {
+  LabelsView L;
+  Csr g[2];                         // out-edges (f) and in-edges (r)
+  unsigned long long *vis[2];
+  uint32_t *q[2];
+  Ctl *ctl;
+};
+// clear both bitmaps (vis_words each) and queue u on side 0, v on side 1
+hipError_t launch_gbfs_start(const GbfsArgs &a, uint64_t vis_words, uint32_t u, uint32_t v,
+                             hipStream_t s);
+// expand the level q[side][lo, hi)
+hipError_t launch_gbfs_round(const GbfsArgs &a, uint32_t side, uint32_t lo, uint32_t hi,
+                             uint32_t u, uint32_t v, uint32_t rules, hipStream_t s);
+// write the answer of query qi and reset the control block's search fields
+hipError_t launch_gbfs_finish(const GbfsArgs &a, uint32_t qi, uint8_t *out,
                               unsigned long long *qcls, hipStream_t s);
 
 // bucket[x] = h(x) for x in [n0, n1) (vertices added after the build; never BL sources)

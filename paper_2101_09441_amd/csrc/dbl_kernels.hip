@@ -2973,63 +2973,159 @@ hipError_t query_node_params(LabelsView L, uint64_t count, uint32_t slots, void 
 }
 
 // ---- whole-device BFS for one pair whose slot queue overflowed (rare)
+//
+// The pair is searched from both ends: side 0 follows out-edges from u, side 1 in-edges from v,
+// one side per launch (the host picks the side whose pending level has fewer edges). Each side
+// has a visited bitmap and one queue whose levels are consecutive segments. A side that reaches
+// a vertex the other side has visited has found a path. A vertex on a path from u to v passes
+// both sides' prunes (the prunes only drop vertices that cannot be on such a path while the
+// labels left the pair undecided), so every path is found, and a side whose level comes out
+// empty has shown that none exists.
 
-__global__ void k_gbfs_start(PropArgs a, u64 *vis, uint32_t u) {
+__global__ void k_gbfs_start(GbfsArgs a, uint32_t u, uint32_t v) {
   Ctl *ctl = a.ctl;
-  vis[u >> 6] |= 1ull << (u & 63u);
-  a.fq[0][0] = u;
+  a.vis[0][u >> 6] |= 1ull << (u & 63u);
+  a.vis[1][v >> 6] |= 1ull << (v & 63u);
+  a.q[0][0] = u;
+  a.q[1][0] = v;
   ctl->fsize[0] = 1;
-  ctl->fsize[1] = 0;
+  ctl->fsize[1] = 1;
   ctl->fsize[2] = 0;
-  ctl->found = 0;
+  ctl->found = u == v ? 1u : 0u;
+  ctl->ctr[kCtrFrontEdges] = min(a.g[0].deg[u], a.g[0].cap[u]);
+  ctl->ctr[kCtrFrontEdges + 1] = min(a.g[1].deg[v], a.g[1].cap[v]);
 }
 
-hipError_t launch_gbfs_start(const PropArgs &a, u64 *vis, uint64_t vis_words, uint32_t u,
+hipError_t launch_gbfs_start(const GbfsArgs &a, uint64_t vis_words, uint32_t u, uint32_t v,
                              hipStream_t s) {
-  hipError_t e = launch_fill_u64(vis, 0ull, vis_words, s);
+  hipError_t e = launch_fill_u64(a.vis[0], 0ull, vis_words, s);
+  if (e == hipSuccess) e = launch_fill_u64(a.vis[1], 0ull, vis_words, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_gbfs_start, dim3(1), dim3(1), 0, s, a, vis, u);
+  hipLaunchKernelGGL(k_gbfs_start, dim3(1), dim3(1), 0, s, a, u, v);
   return hipGetLastError();
 }
 
+// The query's words of one side's prune (a disabled label prunes nothing). Side 0 skips a target
+// x when DL_out(u) & DL_in(x) != 0 (u reaches x through a landmark, so x reaching v would have
+// decided the pair by Theorem 1), when BL_in(x) is not inside BL_in(v) or when BL_out(v) is not
+// inside BL_out(x) (x cannot reach v, Lemma 2). Side 1 mirrors it for a source y of v: DL_out(y)
+// & DL_in(v) != 0, BL_in(u) not inside BL_in(y), or BL_out(y) not inside BL_out(u) (u cannot
+// reach y).
 template <int W>
-__global__ __launch_bounds__(256) void k_gbfs_round(PropArgs a, u64 *vis, uint32_t u, uint32_t v,
-                                                    uint32_t ring, uint32_t rules) {
-  Ctl *ctl = a.ctl;
-  const uint32_t nring = ring == 2u ? 0u : ring + 1u;
-  const uint32_t fsz = ctl->fsize[ring];
-  if (blockIdx.x == 0 && threadIdx.x == 0) ctl->fsize[nring == 2u ? 0u : nring + 1u] = 0;
-  const u64 *lab = a.L.lab;
-  u64 dlo_u[W], bli_v[W], blo_v[W];
-  bfs_prune_words<W>(lab, u, v, rules, dlo_u, bli_v, blo_v);
-  for (uint32_t i0 = blockIdx.x * blockDim.x; i0 < fsz; i0 += gridDim.x * blockDim.x) {
-    const uint32_t i = i0 + threadIdx.x;
-    if (i >= fsz) continue;
-    const uint32_t w = a.fq[ring][i];
-    const uint32_t d = min(a.f.deg[w], a.f.cap[w]);
-    const u64 o = a.f.off[w];
-    for (uint32_t j = 0; j < d; j++) {
-      const uint32_t x = a.f.col[o + j];
-      if (x == v) {
-        ctl->found = 1;
-        continue;
-      }
-      if (bfs_prune<W>(lab + 4ull * W * x, dlo_u, bli_v, blo_v)) continue;
-      const u64 bit = 1ull << (x & 63u);
-      if (atomicOr(&vis[x >> 6], bit) & bit) continue;
-      const uint32_t p = atomicAdd(&ctl->fsize[nring], 1u);
-      a.fq[nring][p] = x;
+__device__ __forceinline__ void gbfs_prune_words(const u64 *lab, uint32_t u, uint32_t v,
+                                                 uint32_t side, uint32_t rules, u64 *dl, u64 *bi,
+                                                 u64 *bo) {
+  const u64 *ru = lab + 4ull * W * u, *rv = lab + 4ull * W * v;
+  const bool use_dl = rules & 1u, use_bl = rules & 2u;
+#pragma unroll
+  for (int j = 0; j < W; j++) {
+    if (side == 0) {
+      dl[j] = use_dl ? ru[2 * W + j] : 0ull;
+      bi[j] = use_bl ? rv[W + j] : ~0ull;
+      bo[j] = use_bl ? rv[3 * W + j] : 0ull;
+    } else {
+      dl[j] = use_dl ? rv[j] : 0ull;
+      bi[j] = use_bl ? ru[W + j] : 0ull;
+      bo[j] = use_bl ? ru[3 * W + j] : ~0ull;
     }
   }
 }
 
-hipError_t launch_gbfs_round(const PropArgs &a, u64 *vis, uint32_t u, uint32_t v, uint32_t ring,
-                             uint32_t rules, hipStream_t s) {
-  DBL_LAUNCH_W(a.L.words, k_gbfs_round, dim3(2048), dim3(256), s, a, vis, u, v, ring, rules);
+template <int W>
+__device__ __forceinline__ bool gbfs_prune(const u64 *rx, uint32_t side, const u64 *dl,
+                                           const u64 *bi, const u64 *bo) {
+  u64 hit = 0;
+  if (side == 0) {
+#pragma unroll
+    for (int j = 0; j < W; j++)
+      hit |= (dl[j] & rx[j]) | (rx[W + j] & ~bi[j]) | (bo[j] & ~rx[3 * W + j]);
+  } else {
+#pragma unroll
+    for (int j = 0; j < W; j++)
+      hit |= (dl[j] & rx[2 * W + j]) | (bi[j] & ~rx[W + j]) | (rx[3 * W + j] & ~bo[j]);
+  }
+  return hit != 0ull;
+}
+
+// One level of one side: the level's queue segment [lo, hi) in tiles of 256 vertices, their rows
+// laid end to end (prefix sum of the degrees in LDS) and one edge per thread, so a long row is
+// spread over the block instead of being walked by one thread. A target already visited on this
+// side is dropped on a plain load of its bitmap word before its labels are read; the atomic OR
+// that claims it comes after the prune. Every claimed vertex adds its degree to the side's
+// summed degrees (the next level's edges).
+template <int W>
+__global__ __launch_bounds__(256) void k_gbfs_round(GbfsArgs a, uint32_t side, uint32_t lo,
+                                                    uint32_t hi, uint32_t u, uint32_t v,
+                                                    uint32_t rules) {
+  __shared__ uint32_t s_start[256];
+  __shared__ u64 s_off[256];
+  __shared__ uint32_t s_wsum[4];
+  Ctl *ctl = a.ctl;
+  const uint32_t t = threadIdx.x;
+  const Csr g = a.g[side];
+  u64 *vs = a.vis[side];
+  const u64 *vo = a.vis[side ^ 1u];
+  uint32_t *qs = a.q[side];
+  const u64 *lab = a.L.lab;
+  u64 dl[W], bi[W], bo[W];
+  gbfs_prune_words<W>(lab, u, v, side, rules, dl, bi, bo);
+  bool found = false;
+  const uint32_t fsz = hi - lo;
+  for (uint32_t beg = blockIdx.x * 256u; beg < fsz; beg += gridDim.x * 256u) {
+    const uint32_t i = beg + t;
+    uint32_t d = 0;
+    if (i < fsz) {
+      const uint32_t w = qs[lo + i];
+      d = min(g.deg[w], g.cap[w]);
+      s_off[t] = g.off[w];
+    }
+    uint32_t total;
+    const uint32_t ex = block_excl_scan<256>(d, s_wsum, total);
+    s_start[t] = ex;
+    __syncthreads();
+    const uint32_t last = min(256u, fsz - beg) - 1u;
+    uint32_t r = 0;  // a thread's edges only move forward: each row search starts from the last
+    for (uint32_t e0 = 0; e0 < total; e0 += 256u) {
+      const uint32_t e = e0 + t;
+      bool keep = false;
+      uint32_t x = 0, dx = 0;
+      if (e < total) {
+        uint32_t top = last;
+        while (r < top) {
+          const uint32_t mid = (r + top + 1) >> 1;
+          if (s_start[mid] <= e) r = mid; else top = mid - 1;
+        }
+        x = g.col[s_off[r] + (e - s_start[r])];
+        const u64 bit = 1ull << (x & 63u);
+        if (vo[x >> 6] & bit) {
+          found = true;
+        } else if (!(vs[x >> 6] & bit) && !gbfs_prune<W>(lab + 4ull * W * x, side, dl, bi, bo)) {
+          keep = !(atomicOr(&vs[x >> 6], bit) & bit);
+          if (keep) dx = min(g.deg[x], g.cap[x]);
+        }
+      }
+      wave_push(qs, &ctl->fsize[side], keep, x);
+      if (__ballot(keep)) {
+        u64 sum = dx;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+        if (__lane_id() == 0) atomicAdd(&ctl->ctr[kCtrFrontEdges + side], sum);
+      }
+    }
+    __syncthreads();
+  }
+  if (__ballot(found) && __lane_id() == 0) ctl->found = 1;
+}
+
+hipError_t launch_gbfs_round(const GbfsArgs &a, uint32_t side, uint32_t lo, uint32_t hi,
+                             uint32_t u, uint32_t v, uint32_t rules, hipStream_t s) {
+  if (hi <= lo) return hipSuccess;
+  const uint32_t grid = (uint32_t)std::min<uint64_t>(2048, ((uint64_t)hi - lo + 255) / 256);
+  DBL_LAUNCH_W(a.L.words, k_gbfs_round, dim3(grid), dim3(256), s, a, side, lo, hi, u, v, rules);
   return hipGetLastError();
 }
 
-__global__ void k_gbfs_finish(PropArgs a, uint32_t qi, uint8_t *out, u64 *qcls) {
+__global__ void k_gbfs_finish(GbfsArgs a, uint32_t qi, uint8_t *out, u64 *qcls) {
   Ctl *ctl = a.ctl;
   const bool found = ctl->found != 0;
   out[qi] = found ? (uint8_t)(1u | (5u << 1)) : (uint8_t)(6u << 1);
@@ -3038,9 +3134,11 @@ __global__ void k_gbfs_finish(PropArgs a, uint32_t qi, uint8_t *out, u64 *qcls) 
   ctl->fsize[1] = 0;
   ctl->fsize[2] = 0;
   ctl->found = 0;
+  ctl->ctr[kCtrFrontEdges] = 0;
+  ctl->ctr[kCtrFrontEdges + 1] = 0;
 }
 
-hipError_t launch_gbfs_finish(const PropArgs &a, uint32_t qi, uint8_t *out, u64 *qcls,
+hipError_t launch_gbfs_finish(const GbfsArgs &a, uint32_t qi, uint8_t *out, u64 *qcls,
                               hipStream_t s) {
   hipLaunchKernelGGL(k_gbfs_finish, dim3(1), dim3(1), 0, s, a, qi, out, qcls);
   return hipGetLastError();

@@ -561,6 +561,57 @@ def test_small_bfs_slots_overflow_to_device_bfs(tiny):
     assert_queries_equal(g, o, w.q_u, w.q_v)
 
 
+@pytest.mark.parametrize("rules", [0, 2])
+def test_whole_device_bfs_from_both_ends(rules):
+    """Four landmarks, 8 BL bits and 8-entry BFS queues send many undecided pairs of a 2^15
+    R-MAT to the whole-device BFS, which searches from u and from v and expands the side with
+    fewer pending edges: hubs on either side, paths that meet anywhere, pairs with no path. With
+    no label rules nothing is pruned; with BL alone both sides' containment prunes apply.
+    Answers equal the oracle's. (With DL on, the hub landmarks stop these searches early; the
+    layered graph below covers that.)"""
+    w = dblgen.make_rmat_workload("bidir", 15, 9, draws=6 << 15, n_insert=2000,
+                                  insert_kind="rmat", n_query=3000, query_kind="mixed")
+    g = gpu_index(w.n, w.src, w.dst, num_landmarks=4, bl_bits=8, bfs_slots=4, bfs_queue_cap=8)
+    g.insert_edges(dev(w.ins_src), dev(w.ins_dst))
+    o = oracle.OracleIndex(w.n, w.src, w.dst).build(k=4, kp=8, threads=8)
+    o.insert(w.ins_src, w.ins_dst)
+    before = g.stats()["bfs_heavy"]
+    got = g.query_rules(dev(w.q_u), dev(w.q_v), rules).cpu().numpy()
+    want = o.query_rules(w.q_u, w.q_v, rules, threads=8)
+    bad = np.flatnonzero(got != want)
+    assert len(bad) == 0, f"rules {rules}: {len(bad)} answers differ, first {bad[:5]}"
+    cls = got >> 1
+    heavy = g.stats()["bfs_heavy"] - before
+    assert heavy > 0 and (cls == 5).sum() > 0 and (cls == 6).sum() > 0, (heavy, np.bincount(cls))
+
+
+
+@pytest.mark.parametrize("rules", [1, 3])
+def test_whole_device_bfs_landmark_prunes(rules):
+    """A layered DAG (48 layers of 64 vertices, three edges from each vertex into the next
+    layer) with the landmarks fixed in layer 30: a search from the first layers covers more than
+    a slot before the landmark prune (DL_out(u) & DL_in(x) forward, DL_out(y) & DL_in(v)
+    backward) cuts it off, so it runs on the whole device with both sides' DL prunes."""
+    rng = np.random.default_rng(21)
+    layers, width = 48, 64
+    n = layers * width
+    src = np.repeat(np.arange((layers - 1) * width), 3).astype(np.uint32)
+    dst = ((src // width + 1) * width + rng.integers(0, width, src.size)).astype(np.uint32)
+    lm = [30 * width + i for i in (0, 17, 40)]
+    g = gpu_index(n, src, dst, num_landmarks=3, bl_bits=1, landmarks=lm, bfs_slots=4,
+                  bfs_queue_cap=8)
+    o = oracle.OracleIndex(n, src, dst).build(k=3, kp=1, landmarks=lm)
+    u = rng.integers(0, 10 * width, 800).astype(np.uint32)
+    v = rng.integers(0, n, 800).astype(np.uint32)
+    before = g.stats()["bfs_heavy"]
+    got = g.query_rules(dev(u), dev(v), rules).cpu().numpy()
+    want = o.query_rules(u, v, rules, threads=8)
+    bad = np.flatnonzero(got != want)
+    assert len(bad) == 0, f"rules {rules}: {len(bad)} answers differ, first {bad[:5]}"
+    cls = got >> 1
+    heavy = g.stats()["bfs_heavy"] - before
+    assert heavy > 0 and (cls == 5).sum() > 0 and (cls == 6).sum() > 0, (heavy, np.bincount(cls))
+
 # ------------------------------------------------------------------ edge cases
 
 def test_out_of_range_ids_leave_index_unchanged(tiny):
