@@ -120,9 +120,11 @@ typedef struct {
   uint64_t bfs_edges;         /* adjacency entries scanned by query BFS */
   uint64_t bfs_heavy;         /* BFS that outgrew a slot and ran on the whole device */
   uint64_t pull_rounds;       /* (round, direction) pairs propagated by pulling */
-  uint64_t server_requests;   /* requests served by the request server (dbl_insert_edges_each) */
-  double server_busy_us;      /* device time it spent on them, from seeing a request to
-                                 publishing its status (device wall clock) */
+  uint64_t server_requests;   /* requests served by a resident workgroup (dbl_insert_edges_each
+                                 with insert_server 1 or 2) */
+  double server_busy_us;      /* device time it spent on them (device wall clock): from seeing a
+                                 request to publishing its status (1); the launches' whole
+                                 time (2) */
   uint64_t batch_stalls;      /* persistent insertion launches that ran out of time at a grid
                                  barrier and were finished another way (dbl_tuning) */
   uint64_t build_long_bins;   /* vertex-range bins of the last build (both directions) that held
@@ -175,12 +177,15 @@ dbl_status dbl_add_vertices(dbl_index *ix, uint32_t count, uint32_t *first, void
 /*
  * The one-request-at-a-time form of dbl_insert_edges: edge i is inserted as its own request
  * (validate, append, seed, propagate to the fixpoint, report), in order, exactly as `count`
- * calls of dbl_insert_edges with one edge each. By default a resident workgroup serves the
- * requests (dbl_tuning.insert_server): the ids are first copied to the host (the stream is
- * synchronised), and the host then hands each edge to the device with its release, after the
- * previous request was reported. h_latency_us: optional HOST array [count] that
- * receives each request's wall time in microseconds. Stops at the first failing request and
- * returns its status (earlier requests stay applied).
+ * calls of dbl_insert_edges with one edge each. By default (dbl_tuning.insert_server = 2) one
+ * resident workgroup reads the requests from d_src/d_dst and applies them in that order, with
+ * no host step per request. With insert_server = 1 the ids are first copied to the host (the
+ * stream is synchronised), and the host then hands each edge to a resident workgroup with its
+ * release, after the previous request was reported. h_latency_us: optional HOST array [count]
+ * that receives each request's time in microseconds (insert_server 2: device time from the end
+ * of the previous request, plus the host's part when the host finished the request; 1 and 0:
+ * wall time from release to report).
+ * Stops at the first failing request and returns its status (earlier requests stay applied).
  */
 dbl_status dbl_insert_edges_each(dbl_index *ix, uint64_t count, const uint32_t *d_src,
                                  const uint32_t *d_dst, float *h_latency_us, void *stream);
@@ -274,7 +279,8 @@ typedef struct {
    N+1-th, ...). Enabling clears the accumulated times. Kinds: insert_small, insert_apply, local_rounds,
    insert_server (one request-server launch), round (one grid propagation round), query_label,
    query_bfs, query_graph (one graph launch of a query batch), insert_batch (one persistent
-   launch of an insertion batch, or its graph launch). */
+   launch of an insertion batch, or its graph launch), insert_stream (one launch of the
+   device-fed request stream). */
 dbl_status dbl_time_kernels(dbl_index *ix, const char *kinds);
 
 /* Copy up to `cap` per-kind records (kinds with at least one launch) to HOST array h_out;
@@ -292,9 +298,13 @@ typedef struct {
   uint32_t local_max_edges;    /* ... and would scan at most this many edges (default 65536) */
   uint32_t round_grid;         /* blocks of a grid propagation round (1..2048; default 2048) */
   uint32_t bfs_slots;          /* BFS slots of the index's own query context (default 1024) */
-  uint32_t insert_server;      /* 1 (default): dbl_insert_edges_each keeps one workgroup resident
-                                  that takes the requests one after another from pinned host
-                                  memory; 0: one launch per request */
+  uint32_t insert_server;      /* how dbl_insert_edges_each delivers its requests. 2 (default):
+                                  one resident workgroup reads them from the device arrays and
+                                  applies them one after another (no host step per request;
+                                  latencies are device time); 1: one resident workgroup takes
+                                  them one after another from pinned host memory, the host
+                                  releasing each after the previous one was reported (a host
+                                  round trip per request); 0: one launch per request */
   uint32_t server_idle_us;     /* a server launch ends after this long without a request and is
                                   started again by the next one (0..10^7; default 200000) */
   uint32_t pull_threshold;     /* a grid propagation round pulls a direction (every vertex ORs in

@@ -88,7 +88,7 @@ struct dbl_index {
   uint32_t small_batch = dbl::kSmallBatch;
   uint32_t local_max_frontier = dbl::kLocalMaxFrontier, local_max_edges = dbl::kLocalMaxEdges;
   uint32_t round_grid = dbl::kRoundGridMax;
-  uint32_t insert_server = 1;  // dbl_insert_edges_each through the request server
+  uint32_t insert_server = 2;  // dbl_insert_edges_each: 0 launches, 1 request server, 2 stream
   uint32_t pull_threshold = 128;  // pull a direction when its push edges >= this/1024 of its edges
   uint32_t pull_all_threshold = 512;  // ... and skip the frontier test above this/1024
   uint32_t query_graph = 0;       // query batches as one graph launch
@@ -143,12 +143,13 @@ enum TimedKind : uint32_t {
   kTQueryBfs,
   kTQueryGraph,
   kTInsertBatch,
+  kTInsertStream,
   kTKinds
 };
 const char *const kKindNames[kTKinds] = {"insert_small", "insert_apply", "local_rounds",
                                          "insert_server", "round",
                                          "query_label", "query_bfs", "query_graph",
-                                         "insert_batch"};
+                                         "insert_batch", "insert_stream"};
 
 hipEvent_t take_event(dbl_index *ix) {
   if (!ix->spare.empty()) {
@@ -1373,6 +1374,72 @@ dbl_status insert_each_served(dbl_index *ix, uint32_t count, const uint32_t *d_s
   return DBL_OK;
 }
 
+// The device-fed one-request-at-a-time form (k_insert_stream): the requests stay in device
+// memory and one resident workgroup applies them in order. A request whose flags need the host
+// (a full row, a large frontier) ends the launch; the host finishes it exactly as
+// dbl_insert_edges does and starts a new launch for the rest. A request with an id out of range
+// ends the call with its status; the requests before it stay applied. Latencies are the device
+// clock's time per request, plus the host's part for a request the host finished.
+dbl_status insert_each_streamed(dbl_index *ix, uint32_t count, const uint32_t *d_src,
+                                const uint32_t *d_dst, float *h_latency_us, hipStream_t s) {
+  if (ix->ovf_cap < 2) {
+    dfree(ix->ovf);
+    CKS(dalloc(&ix->ovf, 1024));
+    ix->ovf_cap = 1024;
+  }
+  Scoped<uint32_t> ticks(s);
+  if (h_latency_us) CKS(dalloc(&ticks.p, count));
+  std::vector<float> host_us;
+  if (h_latency_us) host_us.assign(count, 0.0f);
+  dbl_status result = DBL_OK;
+  uint32_t i = 0;
+  while (i < count) {
+    const dbl::PropArgs a = prop_args(ix);
+    const uint32_t seq0 = ix->seq;
+    {
+      Timed tm(ix, kTInsertStream, s);
+      CK(dbl::launch_insert_stream(a, d_src, d_dst, i, count, ix->n, ix->ovf, ix->ovf_cap,
+                                   ix->mirror, seq0, ticks.p, s));
+    }
+    CK(hipStreamSynchronize(s));
+    const u64 w = __atomic_load_n(&ix->mirror->fast, __ATOMIC_ACQUIRE);
+    const uint32_t done = (uint32_t)w - seq0, flags = (uint32_t)(w >> 32);
+    if (done > count - i) return DBL_ERR_DEVICE;
+    ix->seq = (uint32_t)w;
+    ix->insert_calls += done;
+    i += done;
+    if (flags & dbl::kFastErr) {
+      result = DBL_ERR_VERTEX_RANGE;  // request i was refused; nothing of it applied
+      break;
+    }
+    if (flags) {
+      // request i - 1 ended the launch: finish it on the host
+      const auto t0 = std::chrono::steady_clock::now();
+      CKS(sync_ctl(ix, s));
+      uint64_t rounds = 0;
+      CKS(finish_insert(ix, s, &rounds));
+      ix->insert_rounds += rounds;
+      if (h_latency_us)
+        host_us[i - 1] = std::chrono::duration<float, std::micro>(
+                             std::chrono::steady_clock::now() - t0).count();
+    } else if (i < count) {
+      return DBL_ERR_DEVICE;  // a launch without flags serves every request
+    }
+  }
+  ix->hs.err = 0;
+  ix->hs.ovf_count = 0;
+  if (h_latency_us) {
+    std::vector<uint32_t> tk(count);
+    CK(hipMemcpyAsync(tk.data(), ticks.p, 4ull * count, hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    const double us_per_tick = 1000.0 / (double)ix->clock_khz;
+    for (uint32_t k = 0; k < count; k++)
+      h_latency_us[k] = k < i ? (float)(tk[k] * us_per_tick) + host_us[k] : 0.0f;
+  }
+  if (!ix->pending.empty()) resolve_times(ix);
+  return result;
+}
+
 // Move p to a new allocation of new_count entries, keeping the first old_count.
 template <typename T>
 dbl_status grow(T *&p, uint64_t old_count, uint64_t new_count, hipStream_t s) {
@@ -1728,6 +1795,9 @@ dbl_status dbl_insert_edges_each(dbl_index *ix, uint64_t count, const uint32_t *
     return DBL_OK;
   }
   DeviceGuard dg(ix->device);
+  if (ix->insert_server == 2)
+    return insert_each_streamed(ix, (uint32_t)count, d_src, d_dst, h_latency_us,
+                                (hipStream_t)stream);
   return insert_each_served(ix, (uint32_t)count, d_src, d_dst, h_latency_us,
                             (hipStream_t)stream);
 }
@@ -2037,7 +2107,7 @@ dbl_status dbl_get_tuning(const dbl_index *ix, dbl_tuning *out) {
 dbl_status dbl_set_tuning(dbl_index *ix, const dbl_tuning *t) {
   if (!ix || !t) return DBL_ERR_INVALID_ARG;
   if (t->small_batch > dbl::kSmallBatchMax || t->round_grid == 0 ||
-      t->round_grid > dbl::kRoundGridMax || t->bfs_slots > (1u << 16) || t->insert_server > 1 ||
+      t->round_grid > dbl::kRoundGridMax || t->bfs_slots > (1u << 16) || t->insert_server > 2 ||
       t->server_idle_us > 10000000 || t->pull_threshold > 1u << 20 ||
       t->pull_all_threshold > 1u << 20 ||
       (t->server_polls != 1 && t->server_polls != 4) || t->query_graph > 1 ||

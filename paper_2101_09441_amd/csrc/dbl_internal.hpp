@@ -253,6 +253,13 @@ hipError_t launch_insert_server(const PropArgs &a, uint32_t first, uint32_t coun
                                 Ovf *ovf, uint64_t ovf_cap, Mirror *m,
                                 const unsigned long long *door, uint32_t seq0,
                                 unsigned long long idle_ticks, uint32_t polls, hipStream_t s);
+// the device-fed one-request-at-a-time form: requests [first, count) of src/dst, one after
+// another; publishes {seq0 + requests applied, flags}; ticks (may be null): per-request device
+// clock ticks
+hipError_t launch_insert_stream(const PropArgs &a, const uint32_t *src, const uint32_t *dst,
+                                uint32_t first, uint32_t count, uint32_t n, Ovf *ovf,
+                                uint64_t ovf_cap, Mirror *m, uint32_t seq0, uint32_t *ticks,
+                                hipStream_t s);
 hipError_t launch_insert_apply(const PropArgs &a, const uint32_t *src, const uint32_t *dst,
                                uint64_t count, Ovf *ovf, uint64_t ovf_cap, hipStream_t s);
 // One insertion batch in one persistent launch (see k_insert_batch): validation, the appends and

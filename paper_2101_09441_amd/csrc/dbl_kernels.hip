@@ -2189,6 +2189,180 @@ hipError_t launch_insert_server(const PropArgs &a, uint32_t first, uint32_t coun
   return hipGetLastError();
 }
 
+// Device-fed form of the one-request-at-a-time insertion: request i is the edge (src[i],
+// dst[i]) read from device memory, and each request is applied, and propagated to its fixpoint
+// when it changed a label, before the next one takes effect (Algorithm 3 edge by edge). Wave 0
+// serves the requests in windows of up to 32: lanes 2j and 2j+1 hold request i+j's forward and
+// backward halves and issue all of the window's reads at once (the ids, the tail's label half
+// past the L1 cache, the head's label half as a pre-read, the tail row's capacity, offset and
+// degree); the requests are then applied one after another. While the launch lasts this wave is
+// the only writer of the degrees, so a row's degree is read once per window, advanced by plain
+// stores and handed on to the window's later requests on the same row. A request that changes a
+// label ends its window (the later requests' label reads may be stale): the workgroup runs the
+// propagation rounds, and the next window starts after that request. The launch returns after
+// the last request, after a request whose flags need the host (a full row, a frontier too large
+// for one workgroup), or before a request with an id out of range, publishing {seq0 + requests
+// applied, flags}. ticks (may be null): ticks[i] = device clock ticks from the end of request
+// i - 1 (or the launch's start) to the end of request i.
+constexpr uint32_t kStreamWindow = 32;
+
+template <int W>
+__global__ __launch_bounds__(kLocalThreads) void k_insert_stream(
+    PropArgs a, const uint32_t *__restrict__ src, const uint32_t *__restrict__ dst,
+    uint32_t first, uint32_t count, uint32_t n, Ovf *ovf, uint64_t ovf_cap, Mirror *m,
+    uint32_t seq0, uint32_t *ticks) {
+  __shared__ uint32_t s_cmd, s_i, s_flags;
+  Ctl *ctl = a.ctl;
+  const uint32_t t = threadIdx.x, lane = t & 63u, slot = lane >> 1, d = lane & 1u;
+  uint32_t i = first;  // next request (wave 0)
+  uint32_t flags = 0;  // wave 0
+  u64 t_prev = 0, t_start = 0;
+  if (t == 0) t_start = t_prev = wall_clock64();
+  for (;;) {
+    if (t < 64u) {
+      uint32_t cmd = kCmdExit;
+      const uint32_t ring = ld_agent32(&ctl->cur), stamp = ld_agent32(&ctl->stamp);
+      while (i < count) {
+        const uint32_t nwin = min(kStreamWindow, count - i);
+        const bool in_win = slot < nwin;
+        const uint32_t r = i + (in_win ? slot : 0u);
+        const uint32_t u = src[r], v = dst[r];
+        const u64 badm = __ballot(in_win && (u >= n || v >= n));
+        // requests up to the first one with a bad id
+        const uint32_t nok = badm ? (uint32_t)__builtin_ctzll(badm) >> 1 : nwin;
+        const bool act = slot < nok && u != v;
+        const uint32_t tail = d ? v : u, head = d ? u : v;
+        // a plain select keeps the row pointers global (stores that no wait on the LDS or
+        // scalar counters has to cover)
+        const Csr g = d ? a.r : a.f;
+        Half<W> lt, lh;
+        uint32_t cap = 0, deg = 0;
+        u64 off = 0;
+        if (act) {
+          lt = ld_half_agent<W>(half_ptr<W>(a.L.lab, tail, d));
+          lh = ld_half<W>(half_ptr<W>(a.L.lab, head, d));
+          cap = g.cap[tail];
+          off = g.off[tail];
+          deg = ld_agent32(&g.deg[tail]);  // past L1: this wave's earlier stores
+        }
+        uint32_t jj = 0;
+        bool stop = false;
+        for (; jj < nok; jj++) {
+          // The common request (it fits its row and brings its head no new label bit) only
+          // stores: its memory operations are never waited for inside the window. Label atomics,
+          // frontier pushes and overflow records sit on the rare path, which ends the window.
+          const bool mine = act && slot == jj;
+          bool newbits = false, of = false;
+          uint32_t nd = 0, pos = 0;
+          if (mine) {
+            pos = deg;
+            of = pos >= cap;
+            if (!of) g.col[off + pos] = head;
+            nd = pos + 1u;
+            g.deg[tail] = nd;
+            u64 nb = 0;
+#pragma unroll
+            for (int k = 0; k < 2 * W; k++) nb |= lt.w[k] & ~lh.w[k];
+            newbits = nb != 0ull;
+          }
+          // the later requests of the window that append to the same row start from here
+#pragma unroll
+          for (uint32_t dd = 0; dd < 2; dd++) {
+            const uint32_t row = (uint32_t)__builtin_amdgcn_readlane((int)tail, (int)(2 * jj + dd));
+            const uint32_t ndv = (uint32_t)__builtin_amdgcn_readlane((int)nd, (int)(2 * jj + dd));
+            if (ndv && d == dd && slot > jj && tail == row) deg = ndv;
+          }
+          if (__ballot(newbits || of)) {
+            bool changed = false, p = false;
+            if (mine && of) {
+              const uint32_t k = atomicAdd(&ctl->ovf_count, 1u);
+              if (k < ovf_cap) {
+                Ovf o;
+                o.x = tail | (d ? kDirBit : 0u);
+                o.pos = pos;
+                o.y = head;
+                o.pad = 0;
+                ovf[k] = o;
+              }
+            }
+            if (mine && newbits) {
+              changed = or_half<W>(half_ptr<W>(a.L.lab, head, d), lt, lh);
+              p = changed && claim(&a.inq[2ull * head + d], stamp);
+            }
+            wave_push(a.fq[ring], &ctl->fsize[ring], p, head | (d ? kDirBit : 0u));
+            if (__ballot(of)) flags |= kFastOvf;
+            if (__ballot(changed || p)) cmd = kCmdPropagate;
+            stop = (flags & kFastOvf) || cmd == kCmdPropagate;
+          }
+          if (ticks && lane == 0) {
+            const u64 now = wall_clock64();
+            ticks[i + jj] = (uint32_t)(now - t_prev);
+            t_prev = now;
+          }
+          if (stop) break;
+        }
+        if (stop) {
+          i += jj;  // the request that ended the window; done unless cmd says propagate
+          if (cmd == kCmdExit) i++;
+          break;
+        }
+        i += nok;
+        if (nok < nwin) {  // request i has an id out of range: refused, nothing of it applied
+          flags = kFastErr;
+          break;
+        }
+      }
+      if (t == 0) {
+        s_cmd = cmd;
+        s_i = i;
+        if (cmd == kCmdExit) {
+          publish_fast(m, flags, seq0 + (i - first));
+          ctl->ctr[kCtrServerTicks] += wall_clock64() - t_start;
+          ctl->ctr[kCtrServerReqs] += i - first;
+        } else {
+          st_agent32(&ctl->heavy[0], 0u);
+          st_agent32(&ctl->heavy[1], 0u);
+        }
+      }
+      // the appends and label changes so far become visible to the other waves' rounds
+      if (cmd == kCmdPropagate) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    }
+    __syncthreads();
+    if (s_cmd == kCmdExit) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    local_rounds_body<W>(a);
+    __syncthreads();
+    if (t == 0) {
+      uint32_t fl = flags;
+      if (ld_agent32(&ctl->fsize[ld_agent32(&ctl->cur)])) fl |= kFastPending;
+      s_flags = fl;
+      if (ticks) {
+        const u64 now = wall_clock64();
+        ticks[s_i] += (uint32_t)(now - t_prev);
+        t_prev = now;
+      }
+      if (fl) {
+        publish_fast(m, fl, seq0 + (s_i - first) + 1u);
+        ctl->ctr[kCtrServerTicks] += wall_clock64() - t_start;
+        ctl->ctr[kCtrServerReqs] += s_i - first + 1u;
+      }
+    }
+    __syncthreads();
+    if (s_flags) return;
+    if (t < 64u) i = s_i + 1u;
+  }
+}
+
+hipError_t launch_insert_stream(const PropArgs &a, const uint32_t *src, const uint32_t *dst,
+                                uint32_t first, uint32_t count, uint32_t n, Ovf *ovf,
+                                uint64_t ovf_cap, Mirror *m, uint32_t seq0, uint32_t *ticks,
+                                hipStream_t s) {
+  if (first >= count) return hipSuccess;
+  DBL_LAUNCH_W(a.L.words, k_insert_stream, dim3(1), dim3(kLocalThreads), s, a, src, dst, first,
+               count, n, ovf, ovf_cap, m, seq0, ticks);
+  return hipGetLastError();
+}
+
 template <int W>
 __global__ __launch_bounds__(256) void k_insert_apply(PropArgs a, const uint32_t *src,
                                                       const uint32_t *dst, uint64_t count,
