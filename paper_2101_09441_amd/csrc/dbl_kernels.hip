@@ -2206,6 +2206,33 @@ hipError_t launch_insert_server(const PropArgs &a, uint32_t first, uint32_t coun
 // i - 1 (or the launch's start) to the end of request i.
 constexpr uint32_t kStreamWindow = 32;
 
+// One direction's row arrays for each lane of the stream (lane parity = direction), as global
+// pointers chosen once per launch from scalar copies of the arguments: selecting the argument
+// fields per lane inside the loop reads the pointers back from argument memory per lane, and
+// the window then waits for those reads.
+typedef __attribute__((address_space(1))) uint32_t gu32_t;
+typedef __attribute__((address_space(1))) u64 gu64_t;
+struct LaneRows {
+  gu32_t *col, *deg, *cap;
+  gu64_t *off;
+};
+
+__device__ __forceinline__ u64 scalar_addr(const void *p) {
+  const u64 v = reinterpret_cast<u64>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return ((u64)hi << 32) | lo;
+}
+
+__device__ __forceinline__ LaneRows lane_rows(const PropArgs &a, uint32_t d) {
+  LaneRows r;
+  r.col = (gu32_t *)(d ? scalar_addr(a.r.col) : scalar_addr(a.f.col));
+  r.deg = (gu32_t *)(d ? scalar_addr(a.r.deg) : scalar_addr(a.f.deg));
+  r.cap = (gu32_t *)(d ? scalar_addr(a.r.cap) : scalar_addr(a.f.cap));
+  r.off = (gu64_t *)(d ? scalar_addr(a.r.off) : scalar_addr(a.f.off));
+  return r;
+}
+
 template <int W>
 __global__ __launch_bounds__(kLocalThreads) void k_insert_stream(
     PropArgs a, const uint32_t *__restrict__ src, const uint32_t *__restrict__ dst,
@@ -2218,10 +2245,12 @@ __global__ __launch_bounds__(kLocalThreads) void k_insert_stream(
   uint32_t flags = 0;  // wave 0
   u64 t_prev = 0, t_start = 0;
   if (t == 0) t_start = t_prev = wall_clock64();
+  const LaneRows g = lane_rows(a, d);
   for (;;) {
     if (t < 64u) {
       uint32_t cmd = kCmdExit;
       const uint32_t ring = ld_agent32(&ctl->cur), stamp = ld_agent32(&ctl->stamp);
+      const uint32_t fbase = ld_agent32(&ctl->fsize[ring]);  // the pending frontier (empty)
       while (i < count) {
         const uint32_t nwin = min(kStreamWindow, count - i);
         const bool in_win = slot < nwin;
@@ -2232,18 +2261,30 @@ __global__ __launch_bounds__(kLocalThreads) void k_insert_stream(
         const uint32_t nok = badm ? (uint32_t)__builtin_ctzll(badm) >> 1 : nwin;
         const bool act = slot < nok && u != v;
         const uint32_t tail = d ? v : u, head = d ? u : v;
-        // a plain select keeps the row pointers global (stores that no wait on the LDS or
-        // scalar counters has to cover)
-        const Csr g = d ? a.r : a.f;
-        Half<W> lt, lh;
+        Half<W> lt = {}, lh = {};
         uint32_t cap = 0, deg = 0;
         u64 off = 0;
         if (act) {
           lt = ld_half_agent<W>(half_ptr<W>(a.L.lab, tail, d));
-          lh = ld_half<W>(half_ptr<W>(a.L.lab, head, d));
+          lh = ld_half_agent<W>(half_ptr<W>(a.L.lab, head, d));
           cap = g.cap[tail];
           off = g.off[tail];
-          deg = ld_agent32(&g.deg[tail]);  // past L1: this wave's earlier stores
+          // past L1: this wave's earlier stores
+          deg = __hip_atomic_load(&g.deg[tail], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        // Every read of the window is taken here, before its first request (an empty asm that
+        // reads the registers, on every path): the wait for them then falls outside the request
+        // loop. A wait inside it would also cover the stores of the request before (vector
+        // stores count with the loads): one memory round trip per request.
+        asm volatile("" ::"v"(deg), "v"(cap), "v"(off));
+#pragma unroll
+        for (int k = 0; k < 2 * W; k++) asm volatile("" ::"v"(lt.w[k]), "v"(lh.w[k]));
+        bool lane_newbits = false;
+        if (act) {
+          u64 nb = 0;
+#pragma unroll
+          for (int k = 0; k < 2 * W; k++) nb |= lt.w[k] & ~lh.w[k];
+          lane_newbits = nb != 0ull;
         }
         uint32_t jj = 0;
         bool stop = false;
@@ -2260,10 +2301,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_insert_stream(
             if (!of) g.col[off + pos] = head;
             nd = pos + 1u;
             g.deg[tail] = nd;
-            u64 nb = 0;
-#pragma unroll
-            for (int k = 0; k < 2 * W; k++) nb |= lt.w[k] & ~lh.w[k];
-            newbits = nb != 0ull;
+            newbits = lane_newbits;
           }
           // the later requests of the window that append to the same row start from here
 #pragma unroll
@@ -2273,7 +2311,6 @@ __global__ __launch_bounds__(kLocalThreads) void k_insert_stream(
             if (ndv && d == dd && slot > jj && tail == row) deg = ndv;
           }
           if (__ballot(newbits || of)) {
-            bool changed = false, p = false;
             if (mine && of) {
               const uint32_t k = atomicAdd(&ctl->ovf_count, 1u);
               if (k < ovf_cap) {
@@ -2285,13 +2322,25 @@ __global__ __launch_bounds__(kLocalThreads) void k_insert_stream(
                 ovf[k] = o;
               }
             }
-            if (mine && newbits) {
-              changed = or_half<W>(half_ptr<W>(a.L.lab, head, d), lt, lh);
-              p = changed && claim(&a.inq[2ull * head + d], stamp);
+            // While the window runs no other wave writes labels and the head's half was read
+            // past L1, so the head changes exactly when newbits is set, and every propagation
+            // left the frontier empty and advanced the stamp (no vertex holds this one): the
+            // head's OR, its stamp and its frontier entry need no answer from memory.
+            const bool p = mine && newbits;
+            if (p) {
+              u64 *wh = half_ptr<W>(a.L.lab, head, d);
+#pragma unroll
+              for (int k = 0; k < 2 * W; k++)
+                if (lt.w[k] & ~lh.w[k]) (void)atomicOr(wh + k, lt.w[k]);
+              a.inq[2ull * head + d] = stamp;
             }
-            wave_push(a.fq[ring], &ctl->fsize[ring], p, head | (d ? kDirBit : 0u));
+            const u64 pm = __ballot(p);
+            if (pm) {
+              if (p) a.fq[ring][fbase + lanemask_lt_popc(pm)] = head | (d ? kDirBit : 0u);
+              if (lane == 0) st_agent32(&ctl->fsize[ring], fbase + (uint32_t)__popcll(pm));
+              cmd = kCmdPropagate;
+            }
             if (__ballot(of)) flags |= kFastOvf;
-            if (__ballot(changed || p)) cmd = kCmdPropagate;
             stop = (flags & kFastOvf) || cmd == kCmdPropagate;
           }
           if (ticks && lane == 0) {
