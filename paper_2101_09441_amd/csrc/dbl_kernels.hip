@@ -2249,8 +2249,13 @@ __global__ __launch_bounds__(kLocalThreads) void k_insert_stream(
   for (;;) {
     if (t < 64u) {
       uint32_t cmd = kCmdExit;
-      const uint32_t ring = ld_agent32(&ctl->cur), stamp = ld_agent32(&ctl->stamp);
-      const uint32_t fbase = ld_agent32(&ctl->fsize[ring]);  // the pending frontier (empty)
+      // values the whole wave shares are taken into scalar registers, so the compiler keeps
+      // the request loops uniform (no per-lane exit masks)
+      const uint32_t ring = __builtin_amdgcn_readfirstlane(ld_agent32(&ctl->cur));
+      const uint32_t stamp = __builtin_amdgcn_readfirstlane(ld_agent32(&ctl->stamp));
+      // the pending frontier (empty)
+      const uint32_t fbase = __builtin_amdgcn_readfirstlane(ld_agent32(&ctl->fsize[ring]));
+      i = __builtin_amdgcn_readfirstlane(i);
       while (i < count) {
         const uint32_t nwin = min(kStreamWindow, count - i);
         const bool in_win = slot < nwin;
@@ -2258,7 +2263,8 @@ __global__ __launch_bounds__(kLocalThreads) void k_insert_stream(
         const uint32_t u = src[r], v = dst[r];
         const u64 badm = __ballot(in_win && (u >= n || v >= n));
         // requests up to the first one with a bad id
-        const uint32_t nok = badm ? (uint32_t)__builtin_ctzll(badm) >> 1 : nwin;
+        const uint32_t nok =
+            __builtin_amdgcn_readfirstlane(badm ? (uint32_t)__builtin_ctzll(badm) >> 1 : nwin);
         const bool act = slot < nok && u != v;
         const uint32_t tail = d ? v : u, head = d ? u : v;
         Half<W> lt = {}, lh = {};
@@ -2287,68 +2293,75 @@ __global__ __launch_bounds__(kLocalThreads) void k_insert_stream(
           lane_newbits = nb != 0ull;
         }
         uint32_t jj = 0;
-        bool stop = false;
         for (; jj < nok; jj++) {
           // The common request (it fits its row and brings its head no new label bit) only
-          // stores: its memory operations are never waited for inside the window. Label atomics,
-          // frontier pushes and overflow records sit on the rare path, which ends the window.
+          // stores: nothing in the window waits for memory. The rare request (a full row, or
+          // new label bits for its head) leaves the loop and ends the window.
           const bool mine = act && slot == jj;
-          bool newbits = false, of = false;
-          uint32_t nd = 0, pos = 0;
+          uint32_t nd = 0;
+          bool rare = false;
           if (mine) {
-            pos = deg;
-            of = pos >= cap;
-            if (!of) g.col[off + pos] = head;
+            const uint32_t pos = deg;
+            rare = lane_newbits || pos >= cap;
+            if (pos < cap) g.col[off + pos] = head;
             nd = pos + 1u;
             g.deg[tail] = nd;
-            newbits = lane_newbits;
           }
           // the later requests of the window that append to the same row start from here
 #pragma unroll
           for (uint32_t dd = 0; dd < 2; dd++) {
-            const uint32_t row = (uint32_t)__builtin_amdgcn_readlane((int)tail, (int)(2 * jj + dd));
-            const uint32_t ndv = (uint32_t)__builtin_amdgcn_readlane((int)nd, (int)(2 * jj + dd));
+            const uint32_t src_l = 2 * jj + dd;
+            const uint32_t row = (uint32_t)__builtin_amdgcn_readlane((int)tail, (int)src_l);
+            const uint32_t ndv = (uint32_t)__builtin_amdgcn_readlane((int)nd, (int)src_l);
             if (ndv && d == dd && slot > jj && tail == row) deg = ndv;
           }
-          if (__ballot(newbits || of)) {
-            if (mine && of) {
-              const uint32_t k = atomicAdd(&ctl->ovf_count, 1u);
-              if (k < ovf_cap) {
-                Ovf o;
-                o.x = tail | (d ? kDirBit : 0u);
-                o.pos = pos;
-                o.y = head;
-                o.pad = 0;
-                ovf[k] = o;
-              }
-            }
-            // While the window runs no other wave writes labels and the head's half was read
-            // past L1, so the head changes exactly when newbits is set, and every propagation
-            // left the frontier empty and advanced the stamp (no vertex holds this one): the
-            // head's OR, its stamp and its frontier entry need no answer from memory.
-            const bool p = mine && newbits;
-            if (p) {
-              u64 *wh = half_ptr<W>(a.L.lab, head, d);
-#pragma unroll
-              for (int k = 0; k < 2 * W; k++)
-                if (lt.w[k] & ~lh.w[k]) (void)atomicOr(wh + k, lt.w[k]);
-              a.inq[2ull * head + d] = stamp;
-            }
-            const u64 pm = __ballot(p);
-            if (pm) {
-              if (p) a.fq[ring][fbase + lanemask_lt_popc(pm)] = head | (d ? kDirBit : 0u);
-              if (lane == 0) st_agent32(&ctl->fsize[ring], fbase + (uint32_t)__popcll(pm));
-              cmd = kCmdPropagate;
-            }
-            if (__ballot(of)) flags |= kFastOvf;
-            stop = (flags & kFastOvf) || cmd == kCmdPropagate;
-          }
+          if (__ballot(rare)) break;
           if (ticks && lane == 0) {
             const u64 now = wall_clock64();
             ticks[i + jj] = (uint32_t)(now - t_prev);
             t_prev = now;
           }
-          if (stop) break;
+        }
+        const bool stop = jj < nok;
+        if (stop) {
+          // request i + jj: its appends are done (the lane's own degree still holds its slot)
+          const bool mine = act && slot == jj;
+          const bool of = mine && deg >= cap;
+          if (of) {
+            const uint32_t k = atomicAdd(&ctl->ovf_count, 1u);
+            if (k < ovf_cap) {
+              Ovf o;
+              o.x = tail | (d ? kDirBit : 0u);
+              o.pos = deg;
+              o.y = head;
+              o.pad = 0;
+              ovf[k] = o;
+            }
+          }
+          // While the window runs no other wave writes labels and the head's half was read
+          // past L1, so the head changes exactly when it gets new bits, and every propagation
+          // left the frontier empty and advanced the stamp (no vertex holds this one): the
+          // head's OR, its stamp and its frontier entry need no answer from memory.
+          const bool p = mine && lane_newbits;
+          if (p) {
+            u64 *wh = half_ptr<W>(a.L.lab, head, d);
+#pragma unroll
+            for (int k = 0; k < 2 * W; k++)
+              if (lt.w[k] & ~lh.w[k]) (void)atomicOr(wh + k, lt.w[k]);
+            a.inq[2ull * head + d] = stamp;
+          }
+          const u64 pm = __ballot(p);
+          if (pm) {
+            if (p) a.fq[ring][fbase + lanemask_lt_popc(pm)] = head | (d ? kDirBit : 0u);
+            if (lane == 0) st_agent32(&ctl->fsize[ring], fbase + (uint32_t)__popcll(pm));
+            cmd = kCmdPropagate;
+          }
+          if (__ballot(of)) flags |= kFastOvf;
+          if (ticks && lane == 0) {
+            const u64 now = wall_clock64();
+            ticks[i + jj] = (uint32_t)(now - t_prev);
+            t_prev = now;
+          }
         }
         if (stop) {
           i += jj;  // the request that ended the window; done unless cmd says propagate
