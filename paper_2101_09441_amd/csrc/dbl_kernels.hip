@@ -2233,6 +2233,126 @@ __device__ __forceinline__ LaneRows lane_rows(const PropArgs &a, uint32_t d) {
   return r;
 }
 
+// Both directions' row arrays as scalar global pointers (chosen per lane by a frontier entry's
+// direction bit).
+struct BothRows {
+  LaneRows f, r;
+};
+
+__device__ __forceinline__ BothRows both_rows(const PropArgs &a) {
+  BothRows b;
+  b.f.col = (gu32_t *)scalar_addr(a.f.col);
+  b.f.deg = (gu32_t *)scalar_addr(a.f.deg);
+  b.f.cap = (gu32_t *)scalar_addr(a.f.cap);
+  b.f.off = (gu64_t *)scalar_addr(a.f.off);
+  b.r.col = (gu32_t *)scalar_addr(a.r.col);
+  b.r.deg = (gu32_t *)scalar_addr(a.r.deg);
+  b.r.cap = (gu32_t *)scalar_addr(a.r.cap);
+  b.r.off = (gu64_t *)scalar_addr(a.r.off);
+  return b;
+}
+
+// The propagation rounds of a small frontier by one wave (the stream's label-changing requests,
+// which mostly reach a vertex or two): the frontier holds at most one entry per lane (vertex |
+// direction bit where `fin` is set), all claimed with `stamp`. A round reads every entry's row
+// and label half past L1, lays the rows end to end over the lanes (one edge per lane, at most 64
+// edges), ORs the entry's label half into each target and claims a target that gained bits with
+// the next stamp; the claimed targets are the next frontier (the rounds of Algorithm 3, as the
+// workgroup's rounds run them). Returns true once a frontier is empty. A round that would scan
+// more than 64 edges is not started: its frontier goes to the pending ring (ctl->cur, fsize,
+// stamp) for the workgroup's rounds, and false is returned. Either way ctl->stamp and `stamp`
+// end at the stamp of the last frontier, and the round counters are added to the statistics.
+template <int W>
+__device__ bool stream_rounds(const PropArgs &a, const BothRows &b, uint32_t fent, bool fin,
+                              uint32_t ring, uint32_t fbase, uint32_t &stamp) {
+  Ctl *ctl = a.ctl;
+  const uint32_t lane = __lane_id();
+  u64 relaxed = 0, expanded = 0;
+  uint32_t rounds = 0;
+  bool done = false;
+  for (;;) {
+    const u64 fm = __ballot(fin);
+    if (!fm) {
+      done = true;
+      break;
+    }
+    const uint32_t x = fent & kIdMask, dir = fent >> 31;
+    uint32_t dg = 0;
+    u64 off = 0;
+    Half<W> lv = {};
+    if (fin) {
+      const LaneRows &c = dir ? b.r : b.f;
+      dg = min(c.deg[x], c.cap[x]);
+      off = c.off[x];
+      lv = ld_half_agent<W>(half_ptr<W>(a.L.lab, x, dir));
+    }
+    // exclusive prefix of the row lengths over the lanes
+    uint32_t incl = dg;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(incl, o, 64);
+      if (lane >= (uint32_t)o) incl += y;
+    }
+    const uint32_t total = __builtin_amdgcn_readlane(incl, 63);
+    if (total > 64u) {
+      // too many edges for one wave: the workgroup's rounds take this frontier
+      if (fin) a.fq[ring][fbase + lanemask_lt_popc(fm)] = fent;
+      if (lane == 0) st_agent32(&ctl->fsize[ring], fbase + (uint32_t)__popcll(fm));
+      break;
+    }
+    const uint32_t start = incl - dg;
+    // every lane below `total` takes one edge: its owner entry is found by a scalar walk over
+    // the entries that have edges (usually one or two)
+    uint32_t e_dir = 0;
+    u64 e_addr = 0;
+    Half<W> src = {};
+    bool has = false;
+    for (u64 em = __ballot(fin && dg > 0); em; em &= em - 1) {
+      const uint32_t f = (uint32_t)__builtin_ctzll(em);
+      const uint32_t sf = __builtin_amdgcn_readlane(start, f);
+      const uint32_t df = __builtin_amdgcn_readlane(dg, f);
+      if (lane >= sf && lane < sf + df) {
+        has = true;
+        e_dir = __builtin_amdgcn_readlane(dir, f);
+        const u64 of = ((u64)__builtin_amdgcn_readlane((uint32_t)(off >> 32), f) << 32) |
+                       __builtin_amdgcn_readlane((uint32_t)off, f);
+        e_addr = of + (lane - sf);
+#pragma unroll
+        for (int k = 0; k < 2 * W; k++)
+          src.w[k] = ((u64)__builtin_amdgcn_readlane((uint32_t)(lv.w[k] >> 32), f) << 32) |
+                     __builtin_amdgcn_readlane((uint32_t)lv.w[k], f);
+      }
+    }
+    const uint32_t nstamp = stamp + 1u;
+    bool push = false;
+    uint32_t y = 0;
+    if (has) {
+      y = (e_dir ? b.r.col : b.f.col)[e_addr];
+      u64 *wy = half_ptr<W>(a.L.lab, y, e_dir);
+      u64 gained = 0;
+#pragma unroll
+      for (int k = 0; k < 2 * W; k++)
+        if (src.w[k]) gained |= src.w[k] & ~atomicOr(wy + k, src.w[k]);
+      push = gained && atomicExch(&a.inq[2ull * y + e_dir], nstamp) != nstamp;
+    }
+    relaxed += total;
+    expanded += (uint32_t)__popcll(fm);
+    rounds++;
+    stamp = nstamp;
+    fin = push;
+    fent = y | (e_dir ? kDirBit : 0u);
+  }
+  if (lane == 0) {
+    st_agent32(&ctl->stamp, stamp);
+    ctl->local_rounds += rounds;
+    if (expanded) {
+      a.pcnt[2 * (kRoundGridMax + kHeavyGrid)] += expanded;
+      a.pcnt[2 * (kRoundGridMax + kHeavyGrid) + 1] += relaxed;
+    }
+  }
+  return done;
+}
+
 template <int W>
 __global__ __launch_bounds__(kLocalThreads) void k_insert_stream(
     PropArgs a, const uint32_t *__restrict__ src, const uint32_t *__restrict__ dst,
@@ -2246,13 +2366,14 @@ __global__ __launch_bounds__(kLocalThreads) void k_insert_stream(
   u64 t_prev = 0, t_start = 0;
   if (t == 0) t_start = t_prev = wall_clock64();
   const LaneRows g = lane_rows(a, d);
+  const BothRows rows = both_rows(a);
   for (;;) {
     if (t < 64u) {
       uint32_t cmd = kCmdExit;
       // values the whole wave shares are taken into scalar registers, so the compiler keeps
       // the request loops uniform (no per-lane exit masks)
       const uint32_t ring = __builtin_amdgcn_readfirstlane(ld_agent32(&ctl->cur));
-      const uint32_t stamp = __builtin_amdgcn_readfirstlane(ld_agent32(&ctl->stamp));
+      uint32_t stamp = __builtin_amdgcn_readfirstlane(ld_agent32(&ctl->stamp));
       // the pending frontier (empty)
       const uint32_t fbase = __builtin_amdgcn_readfirstlane(ld_agent32(&ctl->fsize[ring]));
       i = __builtin_amdgcn_readfirstlane(i);
@@ -2322,8 +2443,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_insert_stream(
             t_prev = now;
           }
         }
-        const bool stop = jj < nok;
-        if (stop) {
+        if (jj < nok) {
           // request i + jj: its appends are done (the lane's own degree still holds its slot)
           const bool mine = act && slot == jj;
           const bool of = mine && deg >= cap;
@@ -2350,23 +2470,25 @@ __global__ __launch_bounds__(kLocalThreads) void k_insert_stream(
               if (lt.w[k] & ~lh.w[k]) (void)atomicOr(wh + k, lt.w[k]);
             a.inq[2ull * head + d] = stamp;
           }
-          const u64 pm = __ballot(p);
-          if (pm) {
-            if (p) a.fq[ring][fbase + lanemask_lt_popc(pm)] = head | (d ? kDirBit : 0u);
-            if (lane == 0) st_agent32(&ctl->fsize[ring], fbase + (uint32_t)__popcll(pm));
+          // the head(s) that changed start the rounds: this wave alone while the frontier stays
+          // small, else the workgroup's rounds from the pending ring
+          if (__ballot(p) &&
+              !stream_rounds<W>(a, rows, head | (d ? kDirBit : 0u), p, ring, fbase, stamp))
             cmd = kCmdPropagate;
-          }
           if (__ballot(of)) flags |= kFastOvf;
           if (ticks && lane == 0) {
             const u64 now = wall_clock64();
             ticks[i + jj] = (uint32_t)(now - t_prev);
             t_prev = now;
           }
-        }
-        if (stop) {
-          i += jj;  // the request that ended the window; done unless cmd says propagate
+          // the request that ended the window: done unless the workgroup's rounds still have to
+          // finish it; a full row also ends the launch, for the host. Otherwise this wave's
+          // rounds finished it and the next window starts after it (the later requests' label
+          // reads may be stale).
+          i += jj;
           if (cmd == kCmdExit) i++;
-          break;
+          if (cmd == kCmdPropagate || (flags & kFastOvf)) break;
+          continue;
         }
         i += nok;
         if (nok < nwin) {  // request i has an id out of range: refused, nothing of it applied

@@ -529,6 +529,37 @@ def test_insert_stream_repeated_rows_and_full_rows(slack):
     assert_queries_equal(g, o, u, v)
 
 
+@pytest.mark.parametrize("server", [2, 1])
+def test_insert_each_chain_and_hub(server):
+    """Single-edge requests whose propagation is long or wide: a 20,000-vertex path closed into
+    a cycle (thousands of rounds, all small enough for one wave in the stream), then requests
+    that reach a hub of 60,000 out-edges (too many edges for one wave: the workgroup's rounds
+    take over) and lead back from its leaves. Labels after each request and the answers equal
+    the oracle's."""
+    n = 20000
+    src = np.arange(n - 1, dtype=np.uint32)
+    dst = src + 1
+    hub = np.full(60000, n, dtype=np.uint32)
+    leaves = np.arange(n + 1, n + 60001, dtype=np.uint32)
+    nn = n + 60001
+    bsrc = np.concatenate([src, hub])
+    bdst = np.concatenate([dst, leaves])
+    g = gpu_index(nn, bsrc, bdst, num_landmarks=4, bl_bits=8)
+    g.set_tuning(insert_server=server)
+    o = oracle.OracleIndex(nn, bsrc, bdst).build(k=4, kp=8, threads=8)
+    steps = [([n - 1, 5], [0, 17]),            # closes the cycle
+             ([100, 7], [n, 3]),               # the cycle now reaches the hub
+             ([n + 5, n + 70], [n + 9, 250])]  # leaves of the hub reach back into the cycle
+    for a, b in steps:
+        g.insert_edges_each(dev(a), dev(b))
+        o.insert(a, b)
+        assert_labels_equal(g, o, f"server {server} after {a}->{b}")
+    rng = np.random.default_rng(2)
+    u = rng.integers(0, nn, 4000).astype(np.uint32)
+    v = rng.integers(0, nn, 4000).astype(np.uint32)
+    assert_queries_equal(g, o, u, v)
+
+
 def test_query_graph_replays(tiny):
     """Query batches as graph launches: instantiated on the first batch, then replayed with new
     arguments. Every replay (sizes from 1 to 10,000, DL-only and BL-only rules, direct-launch
