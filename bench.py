@@ -656,7 +656,7 @@ def main():
             r["note"] = (f"one resident workgroup applies the requests in order: "
                          f"{per_request_device_us:.2f} us per request on average, "
                          f"{lat_p50_us:.2f} us at p50 (a request that changes no label is a "
-                         f"dependent chain of about 80 instructions in one wave; the few that "
+                         f"dependent chain of about 60 instructions in one wave; the few that "
                          f"change labels add their propagation rounds), so the bound is that "
                          f"chain, not HBM")
         return with_counters(r)

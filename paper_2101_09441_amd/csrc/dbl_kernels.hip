@@ -2413,28 +2413,27 @@ __global__ __launch_bounds__(kLocalThreads) void k_insert_stream(
           for (int k = 0; k < 2 * W; k++) nb |= lt.w[k] & ~lh.w[k];
           lane_newbits = nb != 0ull;
         }
+        const u64 actm = __ballot(act);  // the halves that append
         uint32_t jj = 0;
         for (; jj < nok; jj++) {
           // The common request (it fits its row and brings its head no new label bit) only
           // stores: nothing in the window waits for memory. The rare request (a full row, or
           // new label bits for its head) leaves the loop and ends the window.
           const bool mine = act && slot == jj;
-          uint32_t nd = 0;
           bool rare = false;
           if (mine) {
             const uint32_t pos = deg;
             rare = lane_newbits || pos >= cap;
             if (pos < cap) g.col[off + pos] = head;
-            nd = pos + 1u;
-            g.deg[tail] = nd;
+            g.deg[tail] = pos + 1u;
           }
-          // the later requests of the window that append to the same row start from here
+          // the later requests of the window that append to the same row start one further on
+          // (they hold the degree this request started from)
 #pragma unroll
           for (uint32_t dd = 0; dd < 2; dd++) {
             const uint32_t src_l = 2 * jj + dd;
             const uint32_t row = (uint32_t)__builtin_amdgcn_readlane((int)tail, (int)src_l);
-            const uint32_t ndv = (uint32_t)__builtin_amdgcn_readlane((int)nd, (int)src_l);
-            if (ndv && d == dd && slot > jj && tail == row) deg = ndv;
+            if (((actm >> src_l) & 1ull) && d == dd && slot > jj && tail == row) deg++;
           }
           if (__ballot(rare)) break;
           if (ticks && lane == 0) {
