@@ -2233,6 +2233,14 @@ __device__ __forceinline__ LaneRows lane_rows(const PropArgs &a, uint32_t d) {
   return r;
 }
 
+// Lane `l`'s 64-bit value (two 32-bit lane reads; each half widened as unsigned: the builtin
+// returns a signed int, which would spread bit 31 of the low half over the high half).
+__device__ __forceinline__ u64 readlane_u64(u64 x, uint32_t l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, (int)l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), (int)l);
+  return ((u64)hi << 32) | lo;
+}
+
 // Both directions' row arrays as scalar global pointers (chosen per lane by a frontier entry's
 // direction bit).
 struct BothRows {
@@ -2314,13 +2322,9 @@ __device__ bool stream_rounds(const PropArgs &a, const BothRows &b, uint32_t fen
       if (lane >= sf && lane < sf + df) {
         has = true;
         e_dir = __builtin_amdgcn_readlane(dir, f);
-        const u64 of = ((u64)__builtin_amdgcn_readlane((uint32_t)(off >> 32), f) << 32) |
-                       __builtin_amdgcn_readlane((uint32_t)off, f);
-        e_addr = of + (lane - sf);
+        e_addr = readlane_u64(off, f) + (lane - sf);
 #pragma unroll
-        for (int k = 0; k < 2 * W; k++)
-          src.w[k] = ((u64)__builtin_amdgcn_readlane((uint32_t)(lv.w[k] >> 32), f) << 32) |
-                     __builtin_amdgcn_readlane((uint32_t)lv.w[k], f);
+        for (int k = 0; k < 2 * W; k++) src.w[k] = readlane_u64(lv.w[k], f);
       }
     }
     const uint32_t nstamp = stamp + 1u;

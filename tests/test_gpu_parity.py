@@ -283,7 +283,8 @@ def test_pull_rounds_in_insertion_batches(pull_all, form):
                                         (256, 64, 4)])
 def test_multiword_labels_build_insert_query(k, kp, words):
     """k landmarks and k' buckets beyond one 64-bit word: labels word for word, answers and
-    classes byte for byte, through a build, single-workgroup batches and a grid batch."""
+    classes byte for byte, through a build, single-workgroup batches, a grid batch and
+    single-edge requests (the device-fed stream, then the request server)."""
     w = dblgen.make_rmat_workload(f"mw{k}_{kp}", 11, 4, draws=6 << 11, n_query=30000,
                                   query_kind="mixed")
     bucket = random_bucket(w.n, kp, k + kp)
@@ -300,6 +301,13 @@ def test_multiword_labels_build_insert_query(k, kp, words):
         g.insert_edges(dev(iu[lo:hi]), dev(iv[lo:hi]))
         o.insert(iu[lo:hi], iv[lo:hi])
         assert_labels_equal(g, o, f"after {hi} insertions")
+    ju = rng.integers(0, w.n, 400).astype(np.uint32)
+    jv = rng.integers(0, w.n, 400).astype(np.uint32)
+    for server, lo, hi in ((2, 0, 200), (1, 200, 400)):
+        g.set_tuning(insert_server=server)
+        g.insert_edges_each(dev(ju[lo:hi]), dev(jv[lo:hi]))
+        o.insert(ju[lo:hi], jv[lo:hi])
+        assert_labels_equal(g, o, f"after single-edge requests (form {server})")
     assert_queries_equal(g, o, w.q_u, w.q_v)
     for rules in (1, 2):
         got = g.query_rules(dev(w.q_u), dev(w.q_v), rules).cpu().numpy()
@@ -558,6 +566,27 @@ def test_insert_each_chain_and_hub(server):
     u = rng.integers(0, nn, 4000).astype(np.uint32)
     v = rng.integers(0, nn, 4000).astype(np.uint32)
     assert_queries_equal(g, o, u, v)
+
+
+@pytest.mark.parametrize("server", [2, 1])
+def test_insert_each_label_bit_31(server):
+    """Landmarks 0..63 fixed in id order, so landmark 31 is DL bit 31. Vertex 100 is reached by
+    landmark 31 alone; the request (100, 101) gives 101 exactly bit 31 and the rounds carry it
+    on to 102 and 103 (in the stream, by the single wave: a label word whose low half has bit
+    31 set must reach the targets unchanged, bits 32..63 untouched). Labels equal the
+    oracle's."""
+    n = 200
+    src = np.array([31, 101, 102, 150], dtype=np.uint32)
+    dst = np.array([100, 102, 103, 151], dtype=np.uint32)
+    lm = list(range(64))
+    g = gpu_index(n, src, dst, num_landmarks=64, bl_bits=1, landmarks=lm)
+    g.set_tuning(insert_server=server)
+    o = oracle.OracleIndex(n, src, dst).build(k=64, kp=1, landmarks=lm)
+    g.insert_edges_each(dev([100]), dev([101]))
+    o.insert([100], [101])
+    assert_labels_equal(g, o, f"form {server}")
+    dl_in = g.labels_numpy()[0].reshape(n, -1)[:, 0]
+    assert dl_in[102] == dl_in[103] == (1 << 31)
 
 
 def test_query_graph_replays(tiny):
