@@ -72,16 +72,17 @@ def kernel_source_hash():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def committed_traffic(kernel):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on the
-    kernel source as it is now (else None)."""
+def committed_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` ("lj" or "scale") from the committed
+    rocprofv3 counter summary, if it was taken on that workload and on the kernel source as it
+    is now (else None)."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return None
     try:
         with open(p) as f:
             d = json.load(f)
-        e = d.get(kernel)
+        e = d.get(workload, {}).get(kernel)
         if not e or e.get("kernel_source_sha256_16") != kernel_source_hash():
             return None
         return e.get("bytes_per_launch")
@@ -242,7 +243,7 @@ def bench_scale(args):
         kernel_rooflines[k] = with_counters({
             "bound": "hbm", "achieved": per / avg / 1e9, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": per / avg / 1e9 / HBM_PEAK_GBS,
-            "traffic": committed_traffic(k), "kernel": k,
+            "traffic": committed_traffic(k, "scale"), "kernel": k,
             "avg_launch_us": avg * 1e6, "launches": d["launches"],
             "algorithmic_bytes_per_launch": per})
     timed_kinds = [k for k in kt if kernel_rooflines.get(k)]
@@ -648,7 +649,7 @@ def main():
         avg_s = d["total_ms"] / d["launches"] / 1e3
         achieved = per_launch / avg_s / 1e9
         r = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-             "frac": achieved / HBM_PEAK_GBS, "traffic": committed_traffic(kind),
+             "frac": achieved / HBM_PEAK_GBS, "traffic": committed_traffic(kind, "lj"),
              "kernel": kind, "avg_launch_us": avg_s * 1e6, "launches": d["launches"],
              "algorithmic_bytes_per_launch": per_launch}
         if kind == "insert_stream" and per_request_device_us is not None:
