@@ -2193,13 +2193,14 @@ hipError_t launch_insert_server(const PropArgs &a, uint32_t first, uint32_t coun
 // dst[i]) read from device memory, and each request is applied, and propagated to its fixpoint
 // when it changed a label, before the next one takes effect (Algorithm 3 edge by edge). Wave 0
 // serves the requests in windows of up to 32: lanes 2j and 2j+1 hold request i+j's forward and
-// backward halves and issue all of the window's reads at once (the ids, the tail's label half
-// past the L1 cache, the head's label half as a pre-read, the tail row's capacity, offset and
-// degree); the requests are then applied one after another. While the launch lasts this wave is
-// the only writer of the degrees, so a row's degree is read once per window, advanced by plain
-// stores and handed on to the window's later requests on the same row. A request that changes a
-// label ends its window (the later requests' label reads may be stale): the workgroup runs the
-// propagation rounds, and the next window starts after that request. The launch returns after
+// backward halves and issue all of the window's reads at once (the ids, both label halves past
+// the L1 cache, the tail row's capacity, offset and degree); the requests are then applied one
+// after another. While the launch lasts this wave is the only writer of the degrees, so a row's
+// degree is read once per window, advanced by plain stores and handed on to the window's later
+// requests on the same row. A request that changes a label ends its window (the later requests'
+// label reads may be stale): this wave runs the propagation rounds while the frontier stays
+// small (stream_rounds), the workgroup's rounds take over beyond that, and the next window
+// starts after that request. The launch returns after
 // the last request, after a request whose flags need the host (a full row, a frontier too large
 // for one workgroup), or before a request with an id out of range, publishing {seq0 + requests
 // applied, flags}. ticks (may be null): ticks[i] = device clock ticks from the end of request
