@@ -22,26 +22,32 @@ def test_more_than_one_gpu_is_refused_before_any_device_work():
     assert r.stdout == ""
 
 
-def test_committed_traffic_follows_the_kernel_source(monkeypatch):
+def test_committed_traffic_follows_the_kernel_source_and_workload(monkeypatch):
     with open(os.path.join(ROOT, "profiles", "traffic.json")) as f:
         table = json.load(f)
-    assert table, "no committed counter figures"
-    for kernel, entry in table.items():
-        monkeypatch.setattr(bench, "kernel_source_hash",
-                            lambda h=entry["kernel_source_sha256_16"]: h)
-        got = bench.committed_traffic(kernel)
-        assert got == entry["bytes_per_launch"] and got > 0
-        # figures taken on another kernel source are not reported
-        monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 16)
-        assert bench.committed_traffic(kernel) is None
-    assert bench.committed_traffic("no_such_kernel") is None
+    assert table and set(table) <= {"lj", "scale"}, "no committed counter figures"
+    for workload, kinds in table.items():
+        other = "scale" if workload == "lj" else "lj"
+        for kernel, entry in kinds.items():
+            monkeypatch.setattr(bench, "kernel_source_hash",
+                                lambda h=entry["kernel_source_sha256_16"]: h)
+            got = bench.committed_traffic(kernel, workload)
+            assert got == entry["bytes_per_launch"] and got > 0
+            # one workload's counters are never reported for the other's launches
+            if kernel not in table.get(other, {}):
+                assert bench.committed_traffic(kernel, other) is None
+            # figures taken on another kernel source are not reported
+            monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 16)
+            assert bench.committed_traffic(kernel, workload) is None
+    assert bench.committed_traffic("no_such_kernel", "lj") is None
 
 
 def test_committed_profiles_describe_one_kernel_source():
     """The kernel-time summaries, the memory-counter summary and traffic.json were taken on the
     same kernel source."""
     with open(os.path.join(ROOT, "profiles", "traffic.json")) as f:
-        hashes = {e["kernel_source_sha256_16"] for e in json.load(f).values()}
+        hashes = {e["kernel_source_sha256_16"] for kinds in json.load(f).values()
+                  for e in kinds.values()}
     for name in os.listdir(os.path.join(ROOT, "profiles")):
         if name.endswith(".md"):
             with open(os.path.join(ROOT, "profiles", name)) as f:
