@@ -2196,8 +2196,9 @@ hipError_t launch_insert_server(const PropArgs &a, uint32_t first, uint32_t coun
 // backward halves and issue all of the window's reads at once (the ids, both label halves past
 // the L1 cache, the tail row's capacity, offset and degree); the requests are then applied one
 // after another. While the launch lasts this wave is the only writer of the degrees, so a row's
-// degree is read once per window, advanced by plain stores and handed on to the window's later
-// requests on the same row. A request that changes a label ends its window (the later requests'
+// degree is read once per window, and a request's slot in its row is that degree plus the
+// number of earlier requests of the window on the same row (counted once per window); each
+// request then only stores. A request that changes a label ends its window (the later requests'
 // label reads may be stale): this wave runs the propagation rounds while the frontier stays
 // small (stream_rounds), the workgroup's rounds take over beyond that, and the next window
 // starts after that request. The launch returns after
@@ -2364,6 +2365,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_insert_stream(
     uint32_t first, uint32_t count, uint32_t n, Ovf *ovf, uint64_t ovf_cap, Mirror *m,
     uint32_t seq0, uint32_t *ticks) {
   __shared__ uint32_t s_cmd, s_i, s_flags;
+  __shared__ uint32_t s_rowkey[2 * kStreamWindow];  // wave 0: each lane's row in the window
   Ctl *ctl = a.ctl;
   const uint32_t t = threadIdx.x, lane = t & 63u, slot = lane >> 1, d = lane & 1u;
   uint32_t i = first;  // next request (wave 0)
@@ -2418,7 +2420,19 @@ __global__ __launch_bounds__(kLocalThreads) void k_insert_stream(
           for (int k = 0; k < 2 * W; k++) nb |= lt.w[k] & ~lh.w[k];
           lane_newbits = nb != 0ull;
         }
-        const u64 actm = __ballot(act);  // the halves that append
+        // A lane's slot in its row: the row's degree at the window start plus the number of
+        // earlier requests of the window that append to the same row (same direction), counted
+        // once per window, so that the request loop below hands nothing between lanes. Each
+        // lane publishes its row in LDS and reads the 32 rows of its direction: reads that
+        // issue back to back, no loop over lanes.
+        s_rowkey[lane] = act ? tail : 0xFFFFFFFFu;  // no vertex id is all ones
+        uint32_t rank = 0;
+#pragma unroll
+        for (uint32_t k = 0; k < kStreamWindow; k++) {
+          const uint32_t key = s_rowkey[2 * k + d];
+          rank += (k < slot && key == tail) ? 1u : 0u;
+        }
+        if (act) deg += rank;
         uint32_t jj = 0;
         for (; jj < nok; jj++) {
           // The common request (it fits its row and brings its head no new label bit) only
@@ -2431,14 +2445,6 @@ __global__ __launch_bounds__(kLocalThreads) void k_insert_stream(
             rare = lane_newbits || pos >= cap;
             if (pos < cap) g.col[off + pos] = head;
             g.deg[tail] = pos + 1u;
-          }
-          // the later requests of the window that append to the same row start one further on
-          // (they hold the degree this request started from)
-#pragma unroll
-          for (uint32_t dd = 0; dd < 2; dd++) {
-            const uint32_t src_l = 2 * jj + dd;
-            const uint32_t row = (uint32_t)__builtin_amdgcn_readlane((int)tail, (int)src_l);
-            if (((actm >> src_l) & 1ull) && d == dd && slot > jj && tail == row) deg++;
           }
           if (__ballot(rare)) break;
           if (ticks && lane == 0) {
