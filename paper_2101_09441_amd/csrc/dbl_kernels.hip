@@ -2426,6 +2426,9 @@ __global__ __launch_bounds__(kLocalThreads) void k_insert_stream(
         // lane publishes its row in LDS and reads the 32 rows of its direction: reads that
         // issue back to back, no loop over lanes.
         s_rowkey[lane] = act ? tail : 0xFFFFFFFFu;  // no vertex id is all ones
+        // the wave's LDS operations run in order; this keeps the compiler from moving the reads
+        // of the other lanes' entries above the write
+        __builtin_amdgcn_wave_barrier();
         uint32_t rank = 0;
 #pragma unroll
         for (uint32_t k = 0; k < kStreamWindow; k++) {
