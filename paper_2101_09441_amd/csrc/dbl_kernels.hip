@@ -2429,27 +2429,32 @@ __global__ __launch_bounds__(kLocalThreads) void k_insert_stream(
         // the wave's LDS operations run in order; this keeps the compiler from moving the reads
         // of the other lanes' entries above the write
         __builtin_amdgcn_wave_barrier();
-        uint32_t rank = 0;
+        // All 32 reads are issued before the first compare (the empty asm needs every key at
+        // once); bit k of `same` is set when the window's request k appends to this lane's row,
+        // and the requests before this one are the bits below `slot`. A compare against `slot`
+        // per k instead is a lane mask the compiler keeps for the whole launch, 64 scalar
+        // registers that spill.
+        uint32_t key[kStreamWindow];
 #pragma unroll
-        for (uint32_t k = 0; k < kStreamWindow; k++) {
-          const uint32_t key = s_rowkey[2 * k + d];
-          rank += (k < slot && key == tail) ? 1u : 0u;
-        }
-        if (act) deg += rank;
+        for (uint32_t k = 0; k < kStreamWindow; k++) key[k] = s_rowkey[2 * k + d];
+#pragma unroll
+        for (uint32_t k = 0; k < kStreamWindow; k++) asm volatile("" ::"v"(key[k]));
+        uint32_t same = 0;
+#pragma unroll
+        for (uint32_t k = 0; k < kStreamWindow; k++) same |= (key[k] == tail ? 1u : 0u) << k;
+        if (act) deg += (uint32_t)__popc(same & ((1u << slot) - 1u));
+        // Whether a request is rare (a full row, or new label bits for its head) is known now:
+        // the requests before the first rare one are the common ones, which only store, so
+        // nothing in the window waits for memory. The rare request ends the window.
+        const u64 rarem = __ballot(act && (lane_newbits || deg >= cap));
+        const uint32_t stop =
+            __builtin_amdgcn_readfirstlane(rarem ? (uint32_t)__builtin_ctzll(rarem) >> 1 : nok);
         uint32_t jj = 0;
-        for (; jj < nok; jj++) {
-          // The common request (it fits its row and brings its head no new label bit) only
-          // stores: nothing in the window waits for memory. The rare request (a full row, or
-          // new label bits for its head) leaves the loop and ends the window.
-          const bool mine = act && slot == jj;
-          bool rare = false;
-          if (mine) {
-            const uint32_t pos = deg;
-            rare = lane_newbits || pos >= cap;
-            if (pos < cap) g.col[off + pos] = head;
-            g.deg[tail] = pos + 1u;
+        for (; jj < stop; jj++) {
+          if (act && slot == jj) {
+            g.col[off + deg] = head;
+            g.deg[tail] = deg + 1u;
           }
-          if (__ballot(rare)) break;
           if (ticks && lane == 0) {
             const u64 now = wall_clock64();
             ticks[i + jj] = (uint32_t)(now - t_prev);
@@ -2457,8 +2462,12 @@ __global__ __launch_bounds__(kLocalThreads) void k_insert_stream(
           }
         }
         if (jj < nok) {
-          // request i + jj: its appends are done (the lane's own degree still holds its slot)
+          // request i + jj, the rare one: its appends (the lane's own degree holds its slot)
           const bool mine = act && slot == jj;
+          if (mine) {
+            if (deg < cap) g.col[off + deg] = head;
+            g.deg[tail] = deg + 1u;
+          }
           const bool of = mine && deg >= cap;
           if (of) {
             const uint32_t k = atomicAdd(&ctl->ovf_count, 1u);
