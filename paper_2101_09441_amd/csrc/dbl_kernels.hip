@@ -2384,33 +2384,54 @@ __global__ __launch_bounds__(kLocalThreads) void k_insert_stream(
       // the pending frontier (empty)
       const uint32_t fbase = __builtin_amdgcn_readfirstlane(ld_agent32(&ctl->fsize[ring]));
       i = __builtin_amdgcn_readfirstlane(i);
-      while (i < count) {
+      // The ids are read one window ahead: a window starts with its requests' ids in registers
+      // (cu, cv: request i + slot) and reads the next window's (nu, nv: request i + 32 + slot)
+      // with its labels, so it waits for one memory round trip instead of two. Only the first
+      // window after the workgroup's rounds reads its own ids first.
+      uint32_t cu, cv;
+      {
+        const uint32_t r = min(i + slot, count - 1u);
+        cu = src[r];
+        cv = dst[r];
+        // waited for here: a read still in flight on the way into the loop would make every
+        // window wait for all memory operations before its first instruction
+        asm volatile("" ::"v"(cu), "v"(cv));
+      }
+      for (;;) {
+        // the window's first request, as a scalar (the loop stays uniform)
+        i = __builtin_amdgcn_readfirstlane(i);
+        if (i >= count) break;
         const uint32_t nwin = min(kStreamWindow, count - i);
         const bool in_win = slot < nwin;
-        const uint32_t r = i + (in_win ? slot : 0u);
-        const uint32_t u = src[r], v = dst[r];
+        const uint32_t r2 = min(i + kStreamWindow + slot, count - 1u);
+        const uint32_t nu = src[r2], nv = dst[r2];
+        const uint32_t u = cu, v = cv;
         const u64 badm = __ballot(in_win && (u >= n || v >= n));
         // requests up to the first one with a bad id
         const uint32_t nok =
             __builtin_amdgcn_readfirstlane(badm ? (uint32_t)__builtin_ctzll(badm) >> 1 : nwin);
+        if (nok == 0) {  // request i has an id out of range: refused, nothing of it applied
+          flags = kFastErr;
+          break;
+        }
         const bool act = slot < nok && u != v;
         const uint32_t tail = d ? v : u, head = d ? u : v;
-        Half<W> lt = {}, lh = {};
-        uint32_t cap = 0, deg = 0;
-        u64 off = 0;
-        if (act) {
-          lt = ld_half_agent<W>(half_ptr<W>(a.L.lab, tail, d));
-          lh = ld_half_agent<W>(half_ptr<W>(a.L.lab, head, d));
-          cap = g.cap[tail];
-          off = g.off[tail];
-          // past L1: this wave's earlier stores
-          deg = __hip_atomic_load(&g.deg[tail], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+        // Every lane reads (a lane without a request reads vertex 0's entries, which exist since
+        // request i's ids are in range, and ignores them): reads under a lane mask would first
+        // clear their registers, and the compiler holds that clear until the memory operations
+        // before it, the previous window's stores among them, are done.
+        const uint32_t rt = act ? tail : 0u, rh = act ? head : 0u;
+        Half<W> lt = ld_half_agent<W>(half_ptr<W>(a.L.lab, rt, d));
+        Half<W> lh = ld_half_agent<W>(half_ptr<W>(a.L.lab, rh, d));
+        const uint32_t cap = g.cap[rt];
+        const u64 off = g.off[rt];
+        // past L1: this wave's earlier stores
+        uint32_t deg = __hip_atomic_load(&g.deg[rt], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         // Every read of the window is taken here, before its first request (an empty asm that
         // reads the registers, on every path): the wait for them then falls outside the request
         // loop. A wait inside it would also cover the stores of the request before (vector
         // stores count with the loads): one memory round trip per request.
-        asm volatile("" ::"v"(deg), "v"(cap), "v"(off));
+        asm volatile("" ::"v"(deg), "v"(cap), "v"(off), "v"(nu), "v"(nv));
 #pragma unroll
         for (int k = 0; k < 2 * W; k++) asm volatile("" ::"v"(lt.w[k]), "v"(lh.w[k]));
         bool lane_newbits = false;
@@ -2510,6 +2531,14 @@ __global__ __launch_bounds__(kLocalThreads) void k_insert_stream(
           i += jj;
           if (cmd == kCmdExit) i++;
           if (cmd == kCmdPropagate || (flags & kFastOvf)) break;
+          // the next window starts jj + 1 requests on: its ids are the rest of this window's
+          // and the first of the next one's, moved down by jj + 1 slots
+          const uint32_t s2 = slot + jj + 1u;
+          const uint32_t from = 2u * (s2 & (kStreamWindow - 1u)) + d;
+          const uint32_t au = __shfl(u, from), av = __shfl(v, from);
+          const uint32_t bu = __shfl(nu, from), bv = __shfl(nv, from);
+          cu = s2 < kStreamWindow ? au : bu;
+          cv = s2 < kStreamWindow ? av : bv;
           continue;
         }
         i += nok;
@@ -2517,6 +2546,8 @@ __global__ __launch_bounds__(kLocalThreads) void k_insert_stream(
           flags = kFastErr;
           break;
         }
+        cu = nu;
+        cv = nv;
       }
       if (t == 0) {
         s_cmd = cmd;
