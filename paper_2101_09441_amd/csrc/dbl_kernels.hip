@@ -2296,6 +2296,12 @@ __device__ bool stream_rounds(const PropArgs &a, const BothRows &b, uint32_t fen
       off = c.off[x];
       lv = ld_half_agent<W>(half_ptr<W>(a.L.lab, x, dir));
     }
+    // all of the round's reads are waited for here (they arrive with the degrees): a read left
+    // in flight where the frontier is handed on would be waited for, with every memory
+    // operation after it, at the start of the stream's next window
+    asm volatile("" ::"v"(off));
+#pragma unroll
+    for (int k = 0; k < 2 * W; k++) asm volatile("" ::"v"(lv.w[k]));
     // exclusive prefix of the row lengths over the lanes
     uint32_t incl = dg;
 #pragma unroll
@@ -2427,11 +2433,36 @@ __global__ __launch_bounds__(kLocalThreads) void k_insert_stream(
         const u64 off = g.off[rt];
         // past L1: this wave's earlier stores
         uint32_t deg = __hip_atomic_load(&g.deg[rt], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // A lane's slot in its row: the row's degree at the window start plus the number of
+        // earlier requests of the window that append to the same row (same direction), counted
+        // once per window, so that the request loop below hands nothing between lanes. Each
+        // lane publishes its row in LDS and reads the 32 rows of its direction, all reads
+        // issued before the first compare (the empty asm needs every key at once); bit k of
+        // `same` is set when the window's request k appends to this lane's row, and the
+        // requests before this one are the bits below `slot`. A compare against `slot` per k
+        // instead is a lane mask the compiler keeps for the whole launch, 64 scalar registers
+        // that spill. The count needs only the ids, so it runs while the window's reads (and
+        // the previous window's stores) are in flight.
+        s_rowkey[lane] = act ? tail : 0xFFFFFFFFu;  // no vertex id is all ones
+        // the wave's LDS operations run in order; this keeps the compiler from moving the reads
+        // of the other lanes' entries above the write
+        __builtin_amdgcn_wave_barrier();
+        uint32_t key[kStreamWindow];
+#pragma unroll
+        for (uint32_t k = 0; k < kStreamWindow; k++) key[k] = s_rowkey[2 * k + d];
+#pragma unroll
+        for (uint32_t k = 0; k < kStreamWindow; k++) asm volatile("" ::"v"(key[k]));
+        // shifted in from the last request down (no per-bit constants held in registers)
+        uint32_t same = 0;
+#pragma unroll
+        for (int k = (int)kStreamWindow - 1; k >= 0; k--)
+          same = 2u * same + (key[k] == tail ? 1u : 0u);
+        const uint32_t rank = (uint32_t)__popc(same & ((1u << slot) - 1u));
         // Every read of the window is taken here, before its first request (an empty asm that
         // reads the registers, on every path): the wait for them then falls outside the request
         // loop. A wait inside it would also cover the stores of the request before (vector
         // stores count with the loads): one memory round trip per request.
-        asm volatile("" ::"v"(deg), "v"(cap), "v"(off), "v"(nu), "v"(nv));
+        asm volatile("" ::"v"(deg), "v"(cap), "v"(off), "v"(nu), "v"(nv), "v"(rank));
 #pragma unroll
         for (int k = 0; k < 2 * W; k++) asm volatile("" ::"v"(lt.w[k]), "v"(lh.w[k]));
         bool lane_newbits = false;
@@ -2440,30 +2471,8 @@ __global__ __launch_bounds__(kLocalThreads) void k_insert_stream(
 #pragma unroll
           for (int k = 0; k < 2 * W; k++) nb |= lt.w[k] & ~lh.w[k];
           lane_newbits = nb != 0ull;
+          deg += rank;
         }
-        // A lane's slot in its row: the row's degree at the window start plus the number of
-        // earlier requests of the window that append to the same row (same direction), counted
-        // once per window, so that the request loop below hands nothing between lanes. Each
-        // lane publishes its row in LDS and reads the 32 rows of its direction: reads that
-        // issue back to back, no loop over lanes.
-        s_rowkey[lane] = act ? tail : 0xFFFFFFFFu;  // no vertex id is all ones
-        // the wave's LDS operations run in order; this keeps the compiler from moving the reads
-        // of the other lanes' entries above the write
-        __builtin_amdgcn_wave_barrier();
-        // All 32 reads are issued before the first compare (the empty asm needs every key at
-        // once); bit k of `same` is set when the window's request k appends to this lane's row,
-        // and the requests before this one are the bits below `slot`. A compare against `slot`
-        // per k instead is a lane mask the compiler keeps for the whole launch, 64 scalar
-        // registers that spill.
-        uint32_t key[kStreamWindow];
-#pragma unroll
-        for (uint32_t k = 0; k < kStreamWindow; k++) key[k] = s_rowkey[2 * k + d];
-#pragma unroll
-        for (uint32_t k = 0; k < kStreamWindow; k++) asm volatile("" ::"v"(key[k]));
-        uint32_t same = 0;
-#pragma unroll
-        for (uint32_t k = 0; k < kStreamWindow; k++) same |= (key[k] == tail ? 1u : 0u) << k;
-        if (act) deg += (uint32_t)__popc(same & ((1u << slot) - 1u));
         // Whether a request is rare (a full row, or new label bits for its head) is known now:
         // the requests before the first rare one are the common ones, which only store, so
         // nothing in the window waits for memory. The rare request ends the window.
