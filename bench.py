@@ -658,10 +658,12 @@ def main():
             # one launch serves the whole request stream, one request after another
             r["note"] = (f"one resident workgroup applies the requests in order: "
                          f"{per_request_device_us:.2f} us per request on average, "
-                         f"{lat_p50_us:.2f} us at p50 (a request that changes no label is a "
-                         f"dependent chain of about 60 instructions in one wave; the few that "
-                         f"change labels add their propagation rounds), so the bound is that "
-                         f"chain, not HBM")
+                         f"{lat_p50_us:.2f} us at p50 (requests go in windows of 32: a window "
+                         f"waits for one memory round trip, its reads and the stores of the "
+                         f"window before, and a request that changes no label then takes a "
+                         f"dozen instructions in one wave; the few that change labels end their "
+                         f"window and add their propagation rounds), so the bound is that "
+                         f"chain of memory latencies, not HBM bandwidth")
         return with_counters(r)
 
     roofline = roofline_of(dominant) if dominant else None
