@@ -2193,9 +2193,9 @@ hipError_t launch_insert_server(const PropArgs &a, uint32_t first, uint32_t coun
 // dst[i]) read from device memory, and each request is applied, and propagated to its fixpoint
 // when it changed a label, before the next one takes effect (Algorithm 3 edge by edge). Wave 0
 // serves the requests in windows of up to 32: lanes 2j and 2j+1 hold request i+j's forward and
-// backward halves and issue all of the window's reads at once (the ids, both label halves past
-// the L1 cache, the tail row's capacity, offset and degree); the requests are then applied one
-// after another. While the launch lasts this wave is the only writer of the degrees, so a row's
+// backward halves and issue all of the window's reads at once (both label halves past the L1
+// cache, the tail row's capacity, offset and degree, and the next window's ids: a window's own
+// ids were read during the window before); the requests are then applied one after another. While the launch lasts this wave is the only writer of the degrees, so a row's
 // degree is read once per window, and a request's slot in its row is that degree plus the
 // number of earlier requests of the window on the same row (counted once per window); each
 // request then only stores. A request that changes a label ends its window (the later requests'
